@@ -1,0 +1,581 @@
+// Oracle method layer.  TEST INFRASTRUCTURE.
+//
+// What each function follows:
+//   plan_layout       : Conv-aware Encoding, Alg. (fragment-packing) steps 1-3;
+//                       block size by argmin of eq. (total-rot) under the
+//                       slot-utilisation bound eq. (opt); Theorem 1 closed form
+//                       reported beside it.
+//   element_slots     : Alg. (fragment-packing) step 3b slot map, read with
+//                       0-based floors: l = (i*m^2 + kappa)*BS_g + j, kappa =
+//                       b_i*m + b_j, batch innermost.
+//   conv2d            : eq. (multi-channel-conv) evaluated over fragment
+//                       ciphertexts: inner rotations (hoisted per input ct),
+//                       per-position masks and scalar weight codes, diagonal
+//                       outer rotations summed with a single ModDown, one
+//                       rescale; stride by discarding fragments (Evaluation
+//                       methodology, implementation paragraph).
+//   avgpool2          : average pooling as a fragment sum (S >= 2) or a
+//                       hoisted rotation sum (S = 1); the 1/4 is carried in
+//                       the scale.
+//   square_act        : x^2 polynomial activation (CMult + relinearisation).
+//   compress          : Arch-aware Ct Compression: rot-mask-add of sparse
+//                       ciphertexts into one dense ciphertext; the mask scale is
+//                       chosen so a single rescale follows (Delta1*Delta2 split).
+//   fc                : diagonal matrix-vector product with baby-step
+//                       giant-step (Evaluation methodology, implementation).
+// Pins: tests/test_oracle_method.py (optimal-S table rotation counts, Fig. 2x2
+// toy, Theorem 1 worked example, slot-map special cases S=1/BS=1 row-major and
+// S=M pixel-wise, decrypted layers against a float64 numpy CNN).
+#include "orc_method.h"
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <set>
+#include <stdexcept>
+
+namespace orc {
+
+static int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+static int posmod(long a, long b) { long r = a % b; return (int)(r < 0 ? r + b : r); }
+static double delta_of(const Context& C) { return std::ldexp(1.0, (int)C.prm.log2scale); }
+
+double rot_total_formula(double BS, double Nin, double Nout, double K, double S, double alpha) {
+  double inner = (K > S) ? (std::pow(std::ceil(K / S), 2) - 1) * Nin : 0.0;
+  double outer = std::max(alpha * S * S / BS - 1, 0.0) * Nout;
+  return BS / alpha * (inner + outer);
+}
+
+double rot_inner_formula_eq(double Nin, double K, double S, double M, double alpha) {
+  if (S >= M) return 0.0;
+  if (K > S) return Nin / alpha * (std::pow(std::ceil(K / S), 2) - 1);
+  return Nin / alpha * 4 * (S - 1) / (S * S);
+}
+
+double optimal_S_closed_form(double K, double Nin, double Nout, double alpha, double BS) {
+  return std::pow(K * K * Nin * BS / (alpha * Nout), 0.25);
+}
+
+Layout fragment_layout(const Context& C, int bs, int c, int h, int w, int S) {
+  Layout L;
+  L.kind = KIND_FRAGMENT;
+  L.bs = bs; L.c = c; L.h = h; L.w = w;
+  L.M = 1;
+  while (L.M < std::max(h, w)) L.M <<= 1;
+  if (S < 1 || L.M % S) throw std::runtime_error("fragment_layout: S must divide M");
+  L.S = S;
+  L.m = L.M / S;
+  const long m2 = (long)L.m * L.m;
+  if (m2 > C.ns) throw std::runtime_error("fragment_layout: m^2 exceeds the slot count");
+  L.bsg = (int)std::min<long>(bs, C.ns / m2);
+  L.cpc = (int)(C.ns / ((long)L.bsg * m2));
+  L.nbg = (bs + L.bsg - 1) / L.bsg;
+  L.rep = (c < L.cpc && L.cpc % c == 0) ? 1 : 0;
+  L.ncg = L.rep ? 1 : (c + L.cpc - 1) / L.cpc;
+  L.dil = 1;
+  L.level = C.L;
+  L.scale = delta_of(C);
+  return L;
+}
+
+Layout plan_layout(const Context& C, int bs, int c, int h, int w, int k_next, int cout_next,
+                   int s_override) {
+  int M = 1;
+  while (M < std::max(h, w)) M <<= 1;
+  std::vector<int> adm;
+  for (int S = 1; S <= M; S <<= 1) {
+    long m = M / S;
+    if (m * m <= C.ns) adm.push_back(S);
+  }
+  if (adm.empty()) throw std::runtime_error("plan_layout: no admissible block size");
+  int best = adm[0];
+  if (s_override > 0) {
+    if (std::find(adm.begin(), adm.end(), s_override) == adm.end())
+      throw std::runtime_error("plan_layout: block size not admissible");
+    best = s_override;
+  } else {
+    // eq. (opt): S^2 <= BS * N_in / alpha, alpha = ns / M^2  <=>  S^2 * ns <= BS * N_in * M^2
+    std::vector<int> cand;
+    for (int S : adm)
+      if ((long double)S * S * C.ns <= (long double)bs * c * M * M) cand.push_back(S);
+    if (!cand.empty()) {
+      // eq. (total-rot) scaled by ns (exact integers):
+      //   BS*M^2*I(K,S)*N_in + max(ns*S^2 - BS*M^2, 0)*N_out
+      long double bestv = -1;
+      for (int S : cand) {
+        long double I = (k_next > S) ? (long double)((k_next + S - 1) / S) * ((k_next + S - 1) / S) - 1 : 0;
+        long double outer = std::max<long double>((long double)C.ns * S * S - (long double)bs * M * M, 0);
+        long double v = (long double)bs * M * M * I * c + outer * cout_next;
+        if (bestv < 0 || v < bestv) { bestv = v; best = S; }
+      }
+    }
+  }
+  return fragment_layout(C, bs, c, h, w, best);
+}
+
+void element_slots(const Layout& L, int b, int ch, int hh, int ww,
+                   std::vector<std::pair<int, int>>& out) {
+  out.clear();
+  const int bg = b / L.bsg, jb = b % L.bsg;
+  if (L.kind == KIND_VECTOR) {
+    int f = (ch * L.h + hh) * L.w + ww;
+    out.push_back({bg, L.pos[f] * L.bsg + jb});
+    return;
+  }
+  const int gh = L.dil * hh, gw = L.dil * ww;
+  const int u = gh % L.S, bi = gh / L.S, v = gw % L.S, bj = gw / L.S;
+  auto put = [&](int cg, int q) {
+    int ct = ((bg * L.ncg + cg) * L.S + u) * L.S + v;
+    int slot = ((q * L.m + bi) * L.m + bj) * L.bsg + jb;
+    out.push_back({ct, slot});
+  };
+  if (L.rep) {
+    for (int q = ch; q < L.cpc; q += L.c) put(0, q);
+  } else {
+    put(ch / L.cpc, ch % L.cpc);
+  }
+}
+
+std::vector<RPoly> encode_fragment(Context& C, const Layout& L, const double* x) {
+  std::vector<std::vector<double>> z(L.n_ct(), std::vector<double>(C.ns, 0.0));
+  std::vector<std::pair<int, int>> sl;
+  for (int b = 0; b < L.bs; b++)
+    for (int ch = 0; ch < L.c; ch++)
+      for (int hh = 0; hh < L.h; hh++)
+        for (int ww = 0; ww < L.w; ww++) {
+          element_slots(L, b, ch, hh, ww, sl);
+          double v = x[((b * L.c + ch) * L.h + hh) * L.w + ww];
+          for (auto& p : sl) z[p.first][p.second] = v;
+        }
+  std::vector<RPoly> pts;
+  for (int t = 0; t < L.n_ct(); t++) pts.push_back(encode(C, z[t], {}, L.scale, q_basis(L.level)));
+  return pts;
+}
+
+std::vector<Ct> encrypt_batch(Context& C, const Layout& L, const std::vector<RPoly>& pts, u64 enc_seed) {
+  std::vector<Ct> out;
+  for (size_t t = 0; t < pts.size(); t++) out.push_back(encrypt(C, pts[t], L.level, L.scale, enc_seed, t));
+  return out;
+}
+
+void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, double* x) {
+  std::vector<std::vector<double>> z(cts.size());
+  for (size_t t = 0; t < cts.size(); t++) {
+    RPoly m = decrypt(C, cts[t]);
+    std::vector<double> re, im;
+    decode(C, m.c[0], C.primes[0], cts[t].scale, re, im);
+    z[t] = re;
+  }
+  std::vector<std::pair<int, int>> sl;
+  for (int b = 0; b < L.bs; b++)
+    for (int ch = 0; ch < L.c; ch++)
+      for (int hh = 0; hh < L.h; hh++)
+        for (int ww = 0; ww < L.w; ww++) {
+          element_slots(L, b, ch, hh, ww, sl);
+          x[((b * L.c + ch) * L.h + hh) * L.w + ww] = z[sl[0].first][sl[0].second];
+        }
+}
+
+i64 weight_code(double w, double scale) {
+  double v = w * scale;
+  if (std::fabs(v) >= std::ldexp(1.0, 52)) throw std::runtime_error("weight_code: out of range");
+  return (i64)std::round(v);
+}
+
+void split_scale(double T, double& dw, double& dm) {
+  int e = 0;
+  std::frexp(T, &e);   // T = f * 2^e, f in [0.5, 1)
+  int kw = (e - 1) >> 1;
+  dw = std::ldexp(1.0, kw);
+  dm = T / dw;
+}
+
+static Ct zero_ct(const Context& C, int level, double scale) {
+  Ct z;
+  z.c0 = poly_zero(C, q_basis(level));
+  z.c1 = poly_zero(C, q_basis(level));
+  z.level = level;
+  z.scale = scale;
+  return z;
+}
+
+static void add_inplace(const Context& C, Ct& a, const Ct& b) {
+  poly_add_inplace(C, a.c0, b.c0);
+  poly_add_inplace(C, a.c1, b.c1);
+}
+
+std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
+                       int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt) {
+  if (Lin.kind != KIND_FRAGMENT || Lin.dil != 1) throw std::runtime_error("conv2d: needs a dense fragment layout");
+  if (stride < 1 || Lin.S % stride) throw std::runtime_error("conv2d: stride must divide S");
+  const int cin = Lin.c;
+  if (groups < 1 || cin % groups || cout % groups) throw std::runtime_error("conv2d: bad groups");
+  const int S = Lin.S, m = Lin.m, bsg = Lin.bsg, cpc = Lin.cpc, lvl = Lin.level;
+  const int gin = cin / groups, gout = cout / groups;
+  const double Delta = delta_of(C);
+  Lout = Lin;
+  Lout.c = cout;
+  Lout.h = (Lin.h + 2 * pad - k) / stride + 1;
+  Lout.w = (Lin.w + 2 * pad - k) / stride + 1;
+  Lout.M = Lin.M / stride;
+  Lout.S = S / stride;
+  Lout.rep = 0;
+  Lout.ncg = (cout + cpc - 1) / cpc;
+  Lout.level = lvl - 1;
+  Lout.scale = Delta;
+  const int nd = Lin.rep ? cin : cpc;
+  const bool need_mask = (cpc > 1) || (pad > 0);
+  const double T = ((double)C.primes[lvl] * Delta) / Lin.scale;
+  double dw = T, dm = 1.0;
+  if (need_mask) split_scale(T, dw, dm);
+  const int npos = need_mask ? cpc : 1;
+
+  auto in_channel = [&](int gi, int q) { return Lin.rep ? q % cin : gi * cpc + q; };
+  // structural validity of the pair (input channel ch, output channel o)
+  auto pair_ok = [&](int ch, int o) {
+    if (ch >= cin || o >= cout) return false;
+    return ch / gin == o / gout;
+  };
+  auto term_active = [&](int go, int gi) {
+    for (int q = 0; q < npos; q++)
+      for (int r = 0; r < nd; r++)
+        if (pair_ok(in_channel(gi, q), go * cpc + posmod(q - r, cpc))) return true;
+    return false;
+  };
+
+  struct Term { int idx; long shift; int u, v, dbi, dbj, di, dj, gi; };
+  const int So = Lout.S, ncg_out = Lout.ncg;
+  std::vector<std::vector<Term>> terms(Lin.nbg * ncg_out * So * So);
+  std::map<int, std::set<long>> need;
+  for (int bg = 0; bg < Lin.nbg; bg++)
+    for (int go = 0; go < ncg_out; go++)
+      for (int uo = 0; uo < So; uo++)
+        for (int vo = 0; vo < So; vo++) {
+          const int oct = ((bg * ncg_out + go) * So + uo) * So + vo;
+          for (int gi = 0; gi < Lin.ncg; gi++) {
+            if (!term_active(go, gi)) continue;
+            for (int di = 0; di < k; di++)
+              for (int dj = 0; dj < k; dj++) {
+                int a = uo * stride + di - pad, b = vo * stride + dj - pad;
+                Term t;
+                t.u = posmod(a, S); t.dbi = floordiv(a, S);
+                t.v = posmod(b, S); t.dbj = floordiv(b, S);
+                t.di = di; t.dj = dj; t.gi = gi;
+                t.idx = ((bg * Lin.ncg + gi) * S + t.u) * S + t.v;
+                t.shift = posmod(((long)t.dbi * m + t.dbj) * bsg, C.ns);
+                terms[oct].push_back(t);
+                if (t.shift) need[t.idx].insert(t.shift);
+              }
+          }
+        }
+  // hoisted inner rotations: one ModUp per input ciphertext
+  std::map<std::pair<int, long>, Ct> copies;
+  for (auto& kv : need) {
+    std::vector<i64> sh(kv.second.begin(), kv.second.end());
+    std::vector<Ct> r = rotate_hoisted(C, in[kv.first], sh);
+    for (size_t i = 0; i < sh.size(); i++) copies[{kv.first, sh[i]}] = r[i];
+    cnt.inner_rot += sh.size();
+    cnt.ks += sh.size();
+    cnt.modup += 1;
+    cnt.moddown += sh.size();
+  }
+  // masks: source pixel inside the logical input, restricted to position q
+  std::map<std::vector<int>, RPoly> masks;
+  auto mask = [&](const Term& t, int q) -> const RPoly& {
+    std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q};
+    auto it = masks.find(key);
+    if (it != masks.end()) return it->second;
+    std::vector<double> z(C.ns, 0.0);
+    for (int bi = 0; bi < m; bi++)
+      for (int bj = 0; bj < m; bj++) {
+        int gh = (bi + t.dbi) * S + t.u, gw = (bj + t.dbj) * S + t.v;
+        if (gh < 0 || gh >= Lin.h || gw < 0 || gw >= Lin.w) continue;
+        for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = 1.0;
+      }
+    return masks[key] = encode(C, z, {}, dm, q_basis(lvl));
+  };
+
+  std::vector<Ct> out(terms.size());
+  for (int bg = 0; bg < Lin.nbg; bg++)
+    for (int go = 0; go < ncg_out; go++)
+      for (int uo = 0; uo < So; uo++)
+        for (int vo = 0; vo < So; vo++) {
+          const int oct = ((bg * ncg_out + go) * So + uo) * So + vo;
+          std::vector<Ct> z(nd, zero_ct(C, lvl, Lin.scale * dw * dm));
+          std::vector<bool> act(nd, false);
+          for (const Term& t : terms[oct]) {
+            const Ct& copy = t.shift ? copies.at({t.idx, t.shift}) : in[t.idx];
+            for (int q = 0; q < npos; q++) {
+              const int ch = in_channel(t.gi, q);
+              bool any = false;
+              for (int r = 0; r < nd; r++) any |= pair_ok(ch, go * cpc + posmod(q - r, cpc));
+              if (!any) continue;
+              Ct mc = need_mask ? mul_plain(C, copy, mask(t, q), dm) : copy;
+              if (need_mask) cnt.pmult++;
+              for (int r = 0; r < nd; r++) {
+                const int o = go * cpc + posmod(q - r, cpc);
+                if (!pair_ok(ch, o)) continue;
+                const int grp = o / gout;
+                double wv = w[(((long)o * gin + (ch - grp * gin)) * k + t.di) * k + t.dj];
+                i64 code = weight_code(wv, dw);
+                act[r] = true;
+                if (code == 0) continue;
+                add_inplace(C, z[r], mul_scalar(C, mc, code, dw));
+                cnt.smult++;
+              }
+            }
+          }
+          std::vector<const Ct*> zs;
+          std::vector<i64> sh;
+          for (int r = 1; r < nd; r++)
+            if (act[r]) {
+              zs.push_back(&z[r]);
+              sh.push_back((i64)r * m * m * bsg);
+            }
+          Ct y;
+          if (zs.empty()) {
+            y = z[0];
+          } else {
+            y = rotate_sum_lazy(C, act[0] ? &z[0] : nullptr, zs, sh);
+            cnt.outer_rot += zs.size();
+            cnt.ks += zs.size();
+            cnt.modup += zs.size();
+            cnt.moddown += 1;
+          }
+          y = rescale(C, y);
+          cnt.rescale++;
+          y.scale = Delta;
+          out[oct] = y;
+        }
+  return out;
+}
+
+std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
+                         Counts& cnt) {
+  if (Lin.kind != KIND_FRAGMENT) throw std::runtime_error("avgpool2: needs a fragment layout");
+  Lout = Lin;
+  Lout.h = Lin.h / 2;
+  Lout.w = Lin.w / 2;
+  Lout.scale = Lin.scale * 4.0;   // the sum of four values is their mean at four times the scale
+  std::vector<Ct> out;
+  if (Lin.S >= 2) {
+    if (Lin.dil != 1) throw std::runtime_error("avgpool2: dilated layout needs S = 1");
+    const int S = Lin.S, So = S / 2;
+    Lout.S = So;
+    Lout.M = Lin.M / 2;
+    for (int g = 0; g < Lin.nbg * Lin.ncg; g++)
+      for (int uo = 0; uo < So; uo++)
+        for (int vo = 0; vo < So; vo++) {
+          Ct y = zero_ct(C, Lin.level, Lin.scale);
+          for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) add_inplace(C, y, in[(g * S + 2 * uo + a) * S + 2 * vo + b]);
+          y.scale = Lout.scale;
+          out.push_back(y);
+        }
+  } else {
+    const long d = Lin.dil, m = Lin.m, bsg = Lin.bsg;
+    std::vector<i64> sh = {d * bsg, d * m * bsg, (d * m + d) * bsg};
+    for (const Ct& x : in) {
+      std::vector<Ct> r = rotate_hoisted(C, x, sh);
+      cnt.other_rot += 3; cnt.ks += 3; cnt.modup += 1; cnt.moddown += 3;
+      Ct y = x;
+      for (const Ct& t : r) add_inplace(C, y, t);
+      y.scale = Lout.scale;
+      out.push_back(y);
+    }
+    Lout.dil = Lin.dil * 2;
+  }
+  return out;
+}
+
+std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
+                           Counts& cnt) {
+  std::vector<Ct> out;
+  for (const Ct& x : in) {
+    Ct y = square_relin(C, x);
+    cnt.relin++; cnt.ks++; cnt.modup++; cnt.moddown++;
+    y = rescale(C, y);
+    cnt.rescale++;
+    out.push_back(y);
+  }
+  Lout = Lin;
+  Lout.level = Lin.level - 1;
+  Lout.scale = Lin.scale * Lin.scale / (double)C.primes[Lin.level];
+  for (Ct& y : out) y.scale = Lout.scale;
+  return out;
+}
+
+std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
+                         Counts& cnt) {
+  if (Lin.kind != KIND_FRAGMENT) throw std::runtime_error("compress: needs a fragment layout");
+  const int bsg = Lin.bsg, d = C.ns / bsg, lvl = Lin.level;
+  const int per_bg = Lin.ncg * Lin.S * Lin.S;
+  // positions (in units of bsg) holding valid elements, per ciphertext of batch group 0
+  std::vector<std::set<int>> P(per_bg);
+  std::vector<std::pair<int, int>> sl;
+  for (int ch = 0; ch < Lin.c; ch++)
+    for (int hh = 0; hh < Lin.h; hh++)
+      for (int ww = 0; ww < Lin.w; ww++) {
+        element_slots(Lin, 0, ch, hh, ww, sl);
+        P[sl[0].first].insert(sl[0].second / bsg);
+      }
+  // greedy first-fit placement of each ciphertext's positions at an offset phi
+  std::vector<char> occ(d, 0);
+  std::vector<int> phi(per_bg, 0);
+  for (int t = 0; t < per_bg; t++) {
+    if (P[t].empty()) continue;
+    int f = 0;
+    for (;; f++) {
+      if (*P[t].rbegin() + f >= d) throw std::runtime_error("compress: does not fit one ciphertext");
+      bool ok = true;
+      for (int p : P[t]) ok &= !occ[p + f];
+      if (ok) break;
+    }
+    phi[t] = f;
+    for (int p : P[t]) occ[p + f] = 1;
+  }
+  Lout = Layout();
+  Lout.kind = KIND_VECTOR;
+  Lout.bs = Lin.bs; Lout.c = Lin.c; Lout.h = Lin.h; Lout.w = Lin.w;
+  Lout.bsg = bsg; Lout.nbg = Lin.nbg; Lout.cpc = 1; Lout.ncg = 1; Lout.S = 1; Lout.m = 1; Lout.M = 1;
+  Lout.d = d;
+  Lout.nfeat = Lin.c * Lin.h * Lin.w;
+  Lout.pos.resize(Lout.nfeat);
+  for (int ch = 0; ch < Lin.c; ch++)
+    for (int hh = 0; hh < Lin.h; hh++)
+      for (int ww = 0; ww < Lin.w; ww++) {
+        element_slots(Lin, 0, ch, hh, ww, sl);
+        Lout.pos[(ch * Lin.h + hh) * Lin.w + ww] = sl[0].second / bsg + phi[sl[0].first];
+      }
+  Lout.level = lvl - 1;
+  Lout.scale = delta_of(C);
+  const double dm = ((double)C.primes[lvl] * delta_of(C)) / Lin.scale;
+  std::vector<RPoly> mk(per_bg);
+  for (int t = 0; t < per_bg; t++) {
+    if (P[t].empty()) continue;
+    std::vector<double> z(C.ns, 0.0);
+    for (int p : P[t])
+      for (int jb = 0; jb < bsg; jb++) z[p * bsg + jb] = 1.0;
+    mk[t] = encode(C, z, {}, dm, q_basis(lvl));
+  }
+  std::vector<Ct> out;
+  for (int bg = 0; bg < Lin.nbg; bg++) {
+    Ct z0 = zero_ct(C, lvl, Lin.scale * dm);
+    bool have0 = false;
+    std::vector<Ct> ms;
+    std::vector<i64> sh;
+    for (int t = 0; t < per_bg; t++) {
+      if (P[t].empty()) continue;
+      Ct mc = mul_plain(C, in[bg * per_bg + t], mk[t], dm);
+      cnt.pmult++;
+      if (phi[t] == 0) {
+        add_inplace(C, z0, mc);
+        have0 = true;
+      } else {
+        ms.push_back(mc);
+        sh.push_back(posmod(-(long)phi[t] * bsg, C.ns));
+      }
+    }
+    Ct y;
+    if (ms.empty()) {
+      y = z0;
+    } else {
+      std::vector<const Ct*> zs;
+      for (const Ct& c : ms) zs.push_back(&c);
+      y = rotate_sum_lazy(C, have0 ? &z0 : nullptr, zs, sh);
+      y.scale = Lin.scale * dm;
+      cnt.other_rot += zs.size(); cnt.ks += zs.size(); cnt.modup += zs.size(); cnt.moddown += 1;
+    }
+    y = rescale(C, y);
+    cnt.rescale++;
+    y.scale = Lout.scale;
+    out.push_back(y);
+  }
+  return out;
+}
+
+std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
+                   int dout, Layout& Lout, Counts& cnt) {
+  if (Lin.kind != KIND_VECTOR) throw std::runtime_error("fc: needs a vector layout");
+  const int d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level;
+  if (dout > d) throw std::runtime_error("fc: output larger than the vector");
+  int e = 0;
+  while ((1 << e) < d) e++;
+  const int n1 = 1 << ((e + 1) / 2), n2 = d / n1;
+  // padded d x d matrix, column = input position
+  std::vector<double> Wp((size_t)d * d, 0.0);
+  std::vector<char> colused(d, 0);
+  for (int f = 0; f < din; f++) colused[Lin.pos[f]] = 1;
+  for (int i = 0; i < dout; i++)
+    for (int f = 0; f < din; f++) Wp[(size_t)i * d + Lin.pos[f]] = w[(size_t)i * din + f];
+  auto diag_active = [&](int kd) {
+    for (int i = 0; i < dout; i++)
+      if (colused[(i + kd) % d]) return true;
+    return false;
+  };
+  const double dp = ((double)C.primes[lvl] * delta_of(C)) / Lin.scale;
+  std::vector<bool> baby(n1, false), giant(n2, false);
+  for (int g = 0; g < n2; g++)
+    for (int b = 0; b < n1; b++)
+      if (diag_active(g * n1 + b)) { baby[b] = true; giant[g] = true; }
+  // plaintext for (g, b): diag_{g n1 + b} rotated right by g*n1 slots-of-features
+  std::vector<std::vector<RPoly>> pt(n2, std::vector<RPoly>(n1));
+  for (int g = 0; g < n2; g++)
+    for (int b = 0; b < n1; b++) {
+      int kd = g * n1 + b;
+      if (!diag_active(kd)) continue;
+      std::vector<double> z(C.ns, 0.0);
+      for (int l = 0; l < C.ns; l++) {
+        int src = posmod((long)l - (long)g * n1 * bsg, C.ns);
+        int i = src / bsg;
+        z[l] = Wp[(size_t)i * d + (i + kd) % d];
+      }
+      pt[g][b] = encode(C, z, {}, dp, q_basis(lvl));
+    }
+  Lout = Layout();
+  Lout.kind = KIND_VECTOR;
+  Lout.bs = Lin.bs; Lout.c = dout; Lout.h = 1; Lout.w = 1;
+  Lout.bsg = bsg; Lout.nbg = Lin.nbg; Lout.cpc = 1; Lout.ncg = 1; Lout.S = 1; Lout.m = 1; Lout.M = 1;
+  Lout.d = d;
+  Lout.nfeat = dout;
+  Lout.pos.resize(dout);
+  for (int i = 0; i < dout; i++) Lout.pos[i] = i;
+  Lout.level = lvl - 1;
+  Lout.scale = delta_of(C);
+  std::vector<Ct> out;
+  for (const Ct& x : in) {
+    std::vector<i64> bsh;
+    for (int b = 1; b < n1; b++)
+      if (baby[b]) bsh.push_back((i64)b * bsg);
+    std::vector<Ct> xr;
+    if (!bsh.empty()) {
+      xr = rotate_hoisted(C, x, bsh);
+      cnt.other_rot += bsh.size(); cnt.ks += bsh.size(); cnt.modup += 1; cnt.moddown += bsh.size();
+    }
+    std::vector<const Ct*> xb(n1, nullptr);
+    xb[0] = &x;
+    for (size_t i = 0; i < bsh.size(); i++) xb[bsh[i] / bsg] = &xr[i];
+    std::vector<Ct> u(n2, zero_ct(C, lvl, Lin.scale * dp));
+    for (int g = 0; g < n2; g++)
+      for (int b = 0; b < n1; b++) {
+        if (!diag_active(g * n1 + b)) continue;
+        add_inplace(C, u[g], mul_plain(C, *xb[b], pt[g][b], dp));
+        cnt.pmult++;
+      }
+    std::vector<const Ct*> zs;
+    std::vector<i64> sh;
+    for (int g = 1; g < n2; g++)
+      if (giant[g]) { zs.push_back(&u[g]); sh.push_back((i64)g * n1 * bsg); }
+    Ct y = zs.empty() ? u[0] : rotate_sum_lazy(C, giant[0] ? &u[0] : nullptr, zs, sh);
+    if (!zs.empty()) {
+      y.scale = Lin.scale * dp;
+      cnt.other_rot += zs.size(); cnt.ks += zs.size(); cnt.modup += zs.size(); cnt.moddown += 1;
+    }
+    y = rescale(C, y);
+    cnt.rescale++;
+    y.scale = Lout.scale;
+    out.push_back(y);
+  }
+  return out;
+}
+
+}  // namespace orc

@@ -1,0 +1,61 @@
+// Oracle method layer (fragment layout, planner, HE layers).  TEST INFRASTRUCTURE.
+#pragma once
+#include "orc.h"
+
+namespace orc {
+
+enum { KIND_FRAGMENT = 0, KIND_VECTOR = 1 };
+
+struct Layout {
+  int kind = KIND_FRAGMENT;
+  int bs = 0, c = 0, h = 0, w = 0;   // logical tensor
+  int M = 0, S = 0, m = 0;           // padded side, block size, blocks per side
+  int bsg = 0, cpc = 0;              // batch per ct, channels per ct (C')
+  int nbg = 0, ncg = 0;              // batch groups, channel groups
+  int rep = 0;                       // channels replicated across positions
+  int dil = 1;                       // logical pixel (h,w) at grid (dil*h, dil*w)
+  int level = 0;
+  double scale = 1.0;
+  int d = 0, nfeat = 0;              // vector layout: positions, features
+  std::vector<int> pos;              // vector layout: feature -> position
+  int n_ct() const { return kind == KIND_FRAGMENT ? nbg * ncg * S * S : nbg; }
+};
+
+// eq. (total-rot) with the convention that reproduces the optimal-S table
+double rot_total_formula(double BS, double Nin, double Nout, double K, double S, double alpha);
+double rot_inner_formula_eq(double Nin, double K, double S, double M, double alpha);   // eq. (inner) as printed
+double optimal_S_closed_form(double K, double Nin, double Nout, double alpha, double BS);
+
+Layout plan_layout(const Context& C, int bs, int c, int h, int w, int k_next, int cout_next,
+                   int s_override);
+Layout fragment_layout(const Context& C, int bs, int c, int h, int w, int S);
+// slot positions of a logical element: returns (ct, slot) pairs (several when replicated)
+void element_slots(const Layout& L, int b, int ch, int hh, int ww,
+                   std::vector<std::pair<int, int>>& out);
+
+struct Counts {
+  long inner_rot = 0, outer_rot = 0, other_rot = 0, ks = 0, modup = 0, moddown = 0;
+  long pmult = 0, smult = 0, rescale = 0, relin = 0;
+};
+
+std::vector<RPoly> encode_fragment(Context& C, const Layout& L, const double* x);   // x[bs][c][h][w]
+std::vector<Ct> encrypt_batch(Context& C, const Layout& L, const std::vector<RPoly>& pts, u64 enc_seed);
+void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, double* x);
+
+std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
+                       int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt);
+std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
+                         Counts& cnt);
+std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
+                           Counts& cnt);
+std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
+                         Counts& cnt);
+std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
+                   int dout, Layout& Lout, Counts& cnt);
+
+// scalar weight code: round half away from zero of w * scale in binary64
+i64 weight_code(double w, double scale);
+// split T = q_l * Delta / scale_in into a power-of-two weight scale and a mask scale
+void split_scale(double T, double& dw, double& dm);
+
+}  // namespace orc

@@ -1,0 +1,202 @@
+"""Pins of the oracle's method layer (fragment layout, planner, HE layers).
+
+Expected values come from the paper's printed numbers (optimal-S table,
+Fig. 2x2 toy, Theorem 1 worked example, slot-utilisation examples) or from a
+float64 numpy CNN, never from the oracle itself.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as P
+from oracle import cnn_ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def test_optimal_s_table_rotation_counts():
+    """Every #Rot entry of the block-size table (N = 2^15, 32x32 maps, alpha = 16)."""
+    g = load_golden("optimal_s_table.json")
+    for row in g["rows"]:
+        for S, rot in zip(row["S"], row["rot"]):
+            assert P.rot_total_formula(row["BS"], row["Nin"], row["Nout"], row["K"], S, g["alpha"]) == rot
+        o = P.Oracle(15, 2, 50, 1, 50, 2, 40, 1) if row is g["rows"][0] else o
+        lay = o.plan_layout(row["BS"], row["Nin"], 32, 32, row["K"], row["Nout"])
+        best = min(zip(row["rot"], row["S"]))[1]
+        assert lay["S"] == best == row["best_S"]
+
+
+def test_fig_2x2_toy_rotation_counts():
+    """1x16x4x4 input, conv (16,16,3), BS=1, 16-slot ciphertexts: S=2 optimal."""
+    g = load_golden("fig_2x2_toy.json")
+    got = [P.rot_total_formula(1, 16, 16, 3, S, g["alpha"]) for S in g["S"]]
+    assert got == g["rot"]
+    assert g["S"][int(np.argmin(got))] == g["optimal_S"]
+    S = 2   # inner and outer balanced at the optimum
+    inner = 1 / g["alpha"] * (np.ceil(3 / S) ** 2 - 1) * 16
+    outer = 1 / g["alpha"] * (g["alpha"] * S * S / 1 - 1) * 16
+    assert inner == outer == g["inner_outer_at_optimum"]
+
+
+def test_theorem1_worked_example():
+    """Conv(128,32,9) on (8,128,32,32) at N=2^15: S* = 3.57, best block size 4."""
+    assert abs(P.optimal_S(9, 128, 32, 16, 8) - 3.57) < 0.005
+
+
+def test_slot_utilisation_example():
+    """4x4 single-channel map in 4-slot ciphertexts: S=2 gives 4 full cts, S=4 gives 16."""
+    o = P.Oracle(3, 2, 30, 1, 30, 2, 20, 1)   # N = 8 -> 4 slots
+    assert o.ns == 4
+    l2 = o.fragment_layout(1, 1, 4, 4, 2)
+    l4 = o.fragment_layout(1, 1, 4, 4, 4)
+    n = lambda L: L["nbg"] * L["ncg"] * L["S"] ** 2
+    assert n(l2) == 4 and n(l4) == 16
+    # equ. (opt): S <= sqrt(BS*N_in/alpha) = sqrt(1*1/(4/16)) = 2 -> the planner keeps S = 2
+    assert o.plan_layout(1, 1, 4, 4, 3, 1)["S"] == 2
+
+
+def all_slots(o, L):
+    seen = {}
+    for b in range(L["bs"]):
+        for c in range(L["c"]):
+            for h in range(L["h"]):
+                for w in range(L["w"]):
+                    seen[(b, c, h, w)] = o.element_slots(L, b, c, h, w)
+    return seen
+
+
+def test_slot_map_row_major_and_pixel_wise_special_cases():
+    o = P.Oracle(9, 2, 30, 1, 30, 2, 20, 1)   # 256 slots
+    # S = 1, BS = 1: row-major, channel after channel (CHET / Orion style)
+    L = o.fragment_layout(1, 4, 8, 8, 1)
+    for (b, c, h, w), sl in all_slots(o, L).items():
+        assert sl[0] == (c // L["cpc"], (c % L["cpc"]) * 64 + h * 8 + w)
+    # S = M: every ciphertext holds one pixel position of all channels and images (CryptoNets)
+    L = o.fragment_layout(4, 8, 8, 8, 8)
+    for (b, c, h, w), sl in all_slots(o, L).items():
+        ct, slot = sl[0]
+        assert ct == (c // L["cpc"]) * 64 + h * 8 + w and slot == (c % L["cpc"]) * 4 + b
+
+
+@pytest.mark.parametrize("shape,S", [((3, 5, 28, 28), 2), ((64, 1, 28, 28), 2), ((2, 16, 16, 16), 4),
+                                     ((1, 1, 28, 28), 1)])
+def test_slot_map_is_injective(shape, S):
+    o = P.Oracle(13, 2, 30, 1, 30, 2, 20, 1)
+    L = o.fragment_layout(*shape, S)
+    used = set()
+    for sl in all_slots(o, L).values():
+        for p in sl:
+            assert p not in used and 0 <= p[1] < o.ns
+            used.add(p)
+
+
+def test_planner_choices_for_the_benchmark_shapes():
+    o13 = P.Oracle(13, 4, 40, 1, 40, 4, 30, 1)
+    L = o13.plan_layout(1, 1, 28, 28, 5, 6)
+    assert (L["S"], L["cpc"], L["rep"], L["M"]) == (1, 4, 1, 32)          # replicated channel
+    o15 = P.Oracle(15, 2, 50, 1, 50, 2, 40, 1)
+    L = o15.plan_layout(64, 1, 28, 28, 5, 6)
+    assert (L["S"], L["cpc"], L["bsg"]) == (2, 1, 64)                     # 4 fragment cts
+    o16 = P.Oracle(16, 2, 50, 1, 50, 2, 40, 1)
+    L = o16.plan_layout(256, 16, 32, 32, 3, 16)
+    assert (L["S"], L["cpc"], L["bsg"]) == (4, 2, 256)
+    assert L["nbg"] * L["ncg"] * L["S"] ** 2 == 128
+
+
+# ---------------------------------------------------------------- encrypted layers
+
+def small_oracle(nq=8, logN=10):
+    return P.Oracle(logN, nq, 50, 3, 50, 3, 40, 17)   # special primes >= limbs per digit
+
+
+def rand_x(shape, seed):
+    return np.random.default_rng(seed).uniform(0, 1, shape)
+
+
+def rand_w(shape, seed):
+    return np.random.default_rng(seed).normal(0, 0.1, shape)
+
+
+@pytest.mark.parametrize("case", [
+    dict(x=(4, 1, 14, 14), w=(3, 1, 3, 3), stride=1, pad=0, groups=1, S=2),   # C'=2, replicated
+    dict(x=(2, 3, 8, 8), w=(4, 3, 3, 3), stride=1, pad=1, groups=1, S=1),     # same padding, masks
+    dict(x=(2, 4, 8, 8), w=(4, 4, 3, 3), stride=2, pad=1, groups=1, S=2),     # stride by discard
+    dict(x=(2, 4, 8, 8), w=(4, 1, 3, 3), stride=1, pad=1, groups=4, S=2),     # depthwise
+    dict(x=(16, 2, 8, 8), w=(5, 2, 5, 5), stride=1, pad=0, groups=1, S=1),    # C'=1, no masks
+])
+def test_conv2d_decrypts_to_float64_conv(case):
+    o = small_oracle()
+    x, w = rand_x(case["x"], 1), rand_w(case["w"], 2)
+    L = o.fragment_layout(*case["x"], case["S"])
+    b = o.encrypt_tensor(L, x, seed=4)
+    y, cnt = o.conv2d(b, w, case["stride"], case["pad"], case["groups"])
+    got = o.decrypt_tensor(y)
+    want = cnn_ref.conv2d(x, w, case["stride"], case["pad"], case["groups"])
+    assert got.shape == want.shape
+    assert np.max(np.abs(got - want)) < 1e-4
+
+
+def test_conv2d_rotation_counts_match_formula_when_kernel_exceeds_block():
+    """K > S with full ciphertexts: measured inner/outer rotations equal eq. (inner)/(outer-rot)."""
+    o = small_oracle(nq=3, logN=10)    # 512 slots, M = 8 -> alpha = 8
+    for (bs, cin, cout, k, S) in [(4, 8, 8, 3, 2), (1, 8, 16, 3, 1), (8, 4, 4, 5, 2)]:
+        L = o.fragment_layout(bs, cin, 8, 8, S)
+        x, w = rand_x((bs, cin, 8, 8), 3), rand_w((cout, cin, k, k), 4)
+        b = o.encrypt_tensor(L, x, seed=1)
+        _, cnt = o.conv2d(b, w, 1, k // 2, 1)
+        alpha = o.ns / 64
+        n_in = bs * cin / alpha
+        assert cnt["inner_rot"] == n_in * (np.ceil(k / S) ** 2 - 1)
+        assert cnt["outer_rot"] == max(bs * cout / alpha * (alpha * S * S / bs - 1), 0)
+        assert cnt["inner_rot"] + cnt["outer_rot"] == P.rot_total_formula(bs, cin, cout, k, S, alpha)
+
+
+def test_avgpool_square_compress_fc_decrypt_to_float64():
+    o = small_oracle()
+    x = rand_x((4, 1, 14, 14), 5)
+    w1, w2 = rand_w((3, 1, 3, 3), 6), rand_w((4, 3, 3, 3), 7)
+    f1, f2 = rand_w((8, 16), 8), rand_w((4, 8), 9)
+    L = o.fragment_layout(4, 1, 14, 14, 2)
+    b = o.encrypt_tensor(L, x, seed=2)
+    b, _ = o.conv2d(b, w1)
+    b, _ = o.square(b)
+    b, _ = o.avgpool2(b)          # fragment sum
+    ref = cnn_ref.avgpool2(cnn_ref.square(cnn_ref.conv2d(x, w1)))
+    assert np.max(np.abs(o.decrypt_tensor(b) - ref)) < 1e-4
+    b, _ = o.conv2d(b, w2)
+    b, _ = o.square(b)
+    b, cnt = o.avgpool2(b)        # S = 1: hoisted rotations
+    assert b.layout()["dil"] == 2 and cnt["other_rot"] > 0
+    ref = cnn_ref.avgpool2(cnn_ref.square(cnn_ref.conv2d(ref, w2)))
+    assert np.max(np.abs(o.decrypt_tensor(b) - ref)) < 1e-4
+    nin = len(b.layout())
+    b, cnt = o.compress(b)
+    L = b.layout()
+    assert L["kind"] == 1 and L["nbg"] == 1 and sorted(set(L["pos"])) == sorted(L["pos"])
+    assert np.max(np.abs(o.decrypt_tensor(b).reshape(ref.shape) - ref)) < 1e-4
+    b, _ = o.fc(b, f1)
+    b, cnt = o.fc(b, f2)
+    ref = cnn_ref.fc(cnn_ref.fc(ref, f1), f2)
+    assert np.max(np.abs(o.decrypt_tensor(b) - ref)) < 1e-4
+
+
+def test_compress_bottleneck_example():
+    """8 -> 2 -> 8 bottleneck: four 25%-utilised ciphertexts merge into one dense one."""
+    o = P.Oracle(6, 3, 50, 1, 50, 3, 40, 3)    # 32 slots
+    L = o.fragment_layout(1, 2, 4, 4, 2)       # 2 channels in cts of 8 channel positions
+    assert L["nbg"] * L["ncg"] * L["S"] ** 2 == 4
+    distinct = 2 * 4 * 4 / (4 * o.ns)
+    assert distinct == 0.25
+    x = rand_x((1, 2, 4, 4), 1)
+    b = o.encrypt_tensor(L, x, seed=3)
+    c, cnt = o.compress(b)
+    assert len(c.data()) == 1 and c.layout()["nfeat"] == o.ns
+    assert np.max(np.abs(o.decrypt_tensor(c).reshape(x.shape) - x)) < 1e-6
+    assert c.layout()["level"] == L["level"] - 1     # one level, like one PMult
