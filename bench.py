@@ -1,0 +1,181 @@
+"""Benchmark: encrypted LeNet-5-shaped inference on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 64 synthetic
+28x28 images, conv 1->6 5x5, x^2, avgpool, conv 6->16 5x5, x^2, avgpool,
+compression into one ciphertext, FC 256->120->84->10; RNS-CKKS N=2^15, 20 x
+50-bit primes, dnum 3, scale 2^40.  Inputs are encrypted and resident in HBM
+before timing; a step is the whole server-side circuit for the batch.
+
+Reported: images/s and key switches/s of the batched form replayed as one
+hipGraph (value), beside the per-op form (every homomorphic operation of every
+ciphertext launched separately), the roofline of the dominant kernel measured
+with HIP events, and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--per-op-steps", type=int, default=2)
+    ap.add_argument("--profile-kernel", default="kip")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=64)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the path shards by independent ciphertext "
+                                   "batches (see DESIGN.md), multi-GPU runs are not implemented"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+
+    params = W.PARAMS["lenet"]
+    fe = F.Fenc(*params)
+    x, w = W.lenet_inputs(args.batch)
+    lay = fe.plan_layout(args.batch, 1, 28, 28, 5, 6)
+    log(f"layout S={lay.S} bs_g={lay.bs_g} C'={lay.chan_per_ct} n_ct={lay.n_ct()}")
+    t0 = time.time()
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    torch.cuda.synchronize()
+    log(f"encode+encrypt {time.time() - t0:.2f}s")
+
+    def step():
+        return W.lenet_forward(fe, ct, w)
+
+    # warm-up: builds plans, keys and workspace
+    for i in range(max(1, args.warmup)):
+        t0 = time.time()
+        out_eager = step()
+        torch.cuda.synchronize()
+        log(f"warmup {i} {time.time() - t0:.2f}s")
+    fe.stats_reset()
+    step()
+    torch.cuda.synchronize()
+    st = fe.stats()
+    ks_per_step = st["keyswitch"]
+    log(f"per step: {st}")
+
+    # batched form captured once into a hipGraph, then replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out_graph = step()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    graph_bits = fe.export(out_graph)
+    eager_bits = fe.export(step())
+    identical_graph = bool(np.array_equal(graph_bits, eager_bits))
+
+    # batched eager (no graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        step()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / max(1, args.steps // 2)
+
+    # per-op form
+    fe.set_mode(F.FENC_MODE_PER_OP)
+    out_pop = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.per_op_steps):
+        out_pop = step()
+    torch.cuda.synchronize()
+    t_perop = (time.perf_counter() - t0) / args.per_op_steps
+    identical_perop = bool(np.array_equal(fe.export(out_pop), eager_bits))
+    fe.set_mode(F.FENC_MODE_BATCHED)
+
+    # dominant kernel: HIP events around each of its launches in one batched step
+    fe.profile_kernel(args.profile_kernel)
+    step()
+    torch.cuda.synchronize()
+    kms, klaunch, kbytes = fe.profile_result()
+    fe.profile_kernel(None)
+    avg_s = kms / 1e3 / max(1, klaunch)
+    achieved = (kbytes / max(1, klaunch)) / avg_s / 1e9 if klaunch else 0.0
+
+    imgs = args.batch
+    value = imgs / t_graph
+    res = {
+        "metric": "encrypted images/sec (batched hipGraph, bit-exact)",
+        "value": round(value, 3),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_graph * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic",
+        "data": "synthetic (uniform [0,1) 28x28 images, N(0,0.1) weights, seeded)",
+        "config": {"workload": "LeNet-5-shaped encrypted CNN, 64 images, RNS-CKKS N=2^15, "
+                               "20x50-bit limbs, dnum 3, scale 2^40",
+                   "batch_images": imgs, "log_n": params[0], "limbs": params[1], "dnum": params[5],
+                   "fragment_S": lay.S},
+        "keyswitches_per_s": round(ks_per_step / t_graph, 1),
+        "keyswitches_per_step": ks_per_step,
+        "per_op": {"images_per_s": round(imgs / t_perop, 3), "ms_per_step": round(t_perop * 1e3, 3),
+                   "keyswitches_per_s": round(ks_per_step / t_perop, 1)},
+        "batched_eager": {"images_per_s": round(imgs / t_eager, 3), "ms_per_step": round(t_eager * 1e3, 3)},
+        "graph_vs_per_op": round(t_perop / t_graph, 3),
+        "bit_identical": {"graph_vs_eager": identical_graph, "per_op_vs_batched": identical_perop},
+        "launches_per_step": st["launches"],
+        "roofline": {"kernel": args.profile_kernel, "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": klaunch,
+                     "bytes_per_launch": kbytes / max(1, klaunch)},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(x, w, params, lay, ks_per_step, imgs)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(x, w, params, lay, ks_per_step, imgs):
+    """The oracle (single-threaded C++ with 128-bit integers) on a bounded
+    sample: the first convolution layer of the same batch, scaled to the whole
+    network by its share of key switches."""
+    from oracle import pyoracle as P
+    t0 = time.time()
+    o = P.Oracle(*params)
+    L = o.plan_layout(lay.bs, 1, 28, 28, 5, 6)
+    b = o.encrypt_tensor(L, x, 4)
+    t1 = time.time()
+    _, cnt = o.conv2d(b, w[0])
+    t_conv = time.time() - t1
+    ks = cnt["ks"]
+    t_net = t_conv * ks_per_step / max(1, ks)
+    log(f"oracle: setup+encrypt {t1 - t0:.1f}s, conv1 {t_conv:.1f}s ({ks} key switches)")
+    return {"value": round(imgs / t_net, 6), "unit": "images/s", "cores": 1, "kind": "oracle",
+            "sample": f"first conv layer of the 64-image batch ({ks} of {ks_per_step} key switches, "
+                      f"{t_conv:.1f}s), scaled by key-switch count"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,254 @@
+/*
+ * fenc.h -- C ABI of the MI355X (gfx950) FEnc^2 hot path.
+ *
+ * FEnc^2 (arXiv 2606.16359) evaluates CNN layers on CKKS ciphertexts whose
+ * slots hold a 4-D tensor in the Conv-aware (fragment) Encoding: the padded
+ * M x M feature maps are cut into an m x m grid of S x S blocks and all
+ * elements with the same intra-block position (u, v) share ciphertexts
+ * (Conv-aware Encoding, Alg. fragment-packing).  The server side consists of
+ * homomorphic convolution (inner rotations for spatial aggregation, outer
+ * rotations for channel aggregation; Motivation section, eq.
+ * multi-channel-conv), FC layers by diagonal BSGS, polynomial activations,
+ * average pooling / stride by discarding fragments, and Arch-aware Ct
+ * Compression (rot-mask-add repacking).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: FENC_OK (0) or a negative fenc_status.  On error nothing is
+ *    launched when the error is detected during argument validation;
+ *    outputs are unspecified otherwise.  fenc_last_error() returns a
+ *    thread-local message for the last failing call of the calling thread.
+ *  - Ciphertext batches live in device memory owned by the caller, uint64
+ *    residues in [0, q_i), layout [n_ct][2][level+1][N], limb i modulo the
+ *    i-th ciphertext prime, each limb in NTT (evaluation) form stored in
+ *    bit-reversed order.  fenc_ct_bytes() gives the size.
+ *  - Sizing: calling an operation with out->data == NULL only fills out->lay
+ *    (shape, level, scale, ciphertext count) and launches nothing.
+ *  - Asynchrony: operations enqueue work on `stream` (a hipStream_t, NULL is
+ *    the default stream) and return; keep buffers alive until the stream is
+ *    synchronised.  Calls on one context are not thread-safe.
+ *  - Operations allocate their workspace from a context-owned arena that only
+ *    grows; the first call of an operation with a given shape builds and
+ *    caches its plan (encoded plaintexts, index tables) and may allocate.  A
+ *    repeated call with the same shapes and weights allocates nothing and can
+ *    be captured into a hipGraph.
+ *  - Secret material: the context holds the secret key (client role) and the
+ *    evaluation keys (server role) at once; this library is the hot path, not
+ *    a key-management system.
+ */
+#ifndef FENC_H
+#define FENC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FENC_OK = 0,
+  FENC_EINVAL = -1,        /* bad argument, shape or plan mismatch */
+  FENC_ENOMEM = -2,        /* device allocation failed */
+  FENC_ENOKEY = -3,        /* strict key mode and a rotation key is missing */
+  FENC_ELEVEL = -4,        /* not enough ciphertext levels left */
+  FENC_ESCALE = -5,        /* scale mismatch */
+  FENC_ELAYOUT = -6,       /* layout not accepted by the operation */
+  FENC_EHIP = -7,          /* HIP runtime error */
+  FENC_EUNSUPPORTED = -8   /* valid request outside what this build implements */
+} fenc_status;
+
+typedef struct fenc_ctx fenc_ctx;
+
+/* RNS-CKKS parameters.  Primes: the n_q largest primes below 2^q_bits with
+ * q = 1 mod 2N (descending), then the n_p next primes below 2^p_bits for the
+ * special modulus P.  Hybrid key switching with dnum digits of
+ * ceil(n_q/dnum) limbs; n_p must be >= the digit size and p_bits == q_bits
+ * (q_bits <= 50).  log2_scale: Delta = 2^log2_scale.  seed keys the secret
+ * and evaluation keys (SplitMix64 counter streams). */
+typedef struct {
+  uint32_t log_n, n_q, q_bits, n_p, p_bits, dnum;
+  double log2_scale;
+  uint64_t seed;
+} fenc_params;
+
+enum { FENC_LAYOUT_FRAGMENT = 0, FENC_LAYOUT_VECTOR = 1 };
+
+/* Slot layout of an encrypted tensor [bs][c][h][w].
+ * FRAGMENT (Alg. fragment-packing): M = next power of two >= max(h, w),
+ *   block size S | M, m = M/S; bs_g images share a ciphertext,
+ *   chan_per_ct = C' = (N/2)/(bs_g m^2) channel positions per ciphertext;
+ *   element (b, ch, y, x) with (dil*y, dil*x) = (bi*S+u, bj*S+v) sits in
+ *   ciphertext ((b/bs_g * n_cg + ch/C') * S + u) * S + v at slot
+ *   ((ch%C' * m + bi) * m + bj) * bs_g + b%bs_g.  With replicate != 0 the
+ *   c < C' channels are repeated in every group of c positions.
+ * VECTOR (FC input/output): one ciphertext per batch group, feature f of the
+ *   flattened [c][h][w] tensor at slot pos[f]*bs_g + b%bs_g with d = (N/2)/bs_g
+ *   positions; pos is the context-owned map map_id (0: identity). */
+typedef struct {
+  int32_t kind;
+  int32_t bs, c, h, w;
+  int32_t M, S, m;
+  int32_t bs_g, chan_per_ct;
+  int32_t n_bg, n_cg;
+  int32_t replicate, dil;
+  int32_t level;
+  int32_t d, n_feat;
+  double scale;
+  uint64_t map_id;
+} fenc_layout;
+
+typedef struct {
+  uint64_t* data;          /* device pointer, caller-owned */
+  fenc_layout lay;
+} fenc_ctbatch;
+
+/* Operation counters, mirroring the paper's per-sample count table columns
+ * (rotations, key switches, NTTs, ciphertexts, multiplications). */
+typedef struct {
+  int64_t rot_inner, rot_outer, rot_other;   /* rotations by role */
+  int64_t keyswitch;                          /* rotations + relinearisations */
+  int64_t modup, moddown;
+  int64_t ntt_limbs, intt_limbs;              /* single-limb transforms */
+  int64_t pmult, smult, rescale, relin;
+  int64_t launches;                           /* kernel launches */
+  int64_t cts_out;                            /* ciphertexts produced */
+} fenc_counters;
+
+enum { FENC_MODE_BATCHED = 0, FENC_MODE_PER_OP = 1 };
+
+/* ---- context ------------------------------------------------------------
+ * Creates a context (host tables only; device tables are built on first use
+ * on the current HIP device).  Errors: EINVAL for unsupported parameters. */
+int fenc_ctx_create(const fenc_params* p, fenc_ctx** out);
+void fenc_ctx_destroy(fenc_ctx* ctx);
+/* n_q + n_p primes of the context (host array). */
+int fenc_ctx_primes(const fenc_ctx* ctx, uint64_t* out);
+/* Execution mode: BATCHED (default) launches every key switch, product and
+ * rescale of a layer stage in one grid; PER_OP launches each homomorphic
+ * operation of each ciphertext separately.  Results are identical. */
+int fenc_set_mode(fenc_ctx* ctx, int mode);
+/* Convolution plaintext form (Arch-aware Ct Compression, scale split): when
+ * per-position weights are needed, the layer's weight diagonals are encoded as
+ * full-scale plaintexts if they fit `bytes` of device memory (default 1 GiB);
+ * otherwise 0/1 position masks at scale Delta_m are combined with integer
+ * weight codes at scale Delta_w, Delta_w * Delta_m = q_l * Delta / scale_in,
+ * so one rescale follows either way.  The choice changes the ciphertext bits,
+ * not the decrypted values beyond rounding. */
+int fenc_set_plaintext_budget(fenc_ctx* ctx, int64_t bytes);
+/* Kernel profiling: every later launch of the named kernel (e.g. "kip",
+ * "ntt_fwd_cols", "gmac") outside graph capture is bracketed by HIP events on
+ * its stream; fenc_profile_result returns the summed event time, the number
+ * of launches and their algorithmic HBM bytes (compulsory reads and writes).
+ * NULL stops profiling and drops collected events. */
+int fenc_profile_kernel(fenc_ctx* ctx, const char* name);
+int fenc_profile_result(fenc_ctx* ctx, double* total_ms, int64_t* launches, double* bytes);
+int fenc_stats(const fenc_ctx* ctx, fenc_counters* out);
+void fenc_stats_reset(fenc_ctx* ctx);
+/* Device bytes held by the context (tables, keys, plans, workspace). */
+int64_t fenc_device_bytes(const fenc_ctx* ctx);
+const char* fenc_last_error(void);
+
+/* ---- keys (Background, eq. rotation; hybrid key switching) --------------
+ * Generates rotation keys for left rotations by rot_steps[i] slots and, if
+ * relin != 0, the relinearisation key.  Keys are deterministic functions of
+ * (seed, Galois element).  strict != 0 makes later operations fail with
+ * FENC_ENOKEY instead of generating a missing key on demand. */
+int fenc_keygen(fenc_ctx* ctx, const int32_t* rot_steps, uint32_t n_steps, int relin, int strict);
+/* Host copy of a switching key in coefficient form [dnum'][2][n_q+n_p][N]
+ * (shift = slot rotation, or INT32_MIN for the relinearisation key). */
+int fenc_key_export(fenc_ctx* ctx, int32_t shift, uint64_t* out);
+
+/* ---- planning (Conv-aware Encoding: Alg. fragment-packing, eq. total-rot,
+ * eq. opt, Theorem 1) --------------------------------------------------------
+ * Layout for a fresh [bs][c][h][w] input whose next layer is a k x k
+ * convolution to cout channels: block size S minimises eq. (total-rot) over
+ * powers of two satisfying eq. (opt) (ties: smaller S); s_override > 0 forces
+ * S.  Host only. */
+int fenc_plan_layout(const fenc_ctx* ctx, uint32_t bs, uint32_t c, uint32_t h, uint32_t w,
+                     uint32_t k_next, uint32_t cout_next, int32_t s_override, fenc_layout* out);
+int fenc_layout_n_ct(const fenc_layout* lay);
+int64_t fenc_ct_bytes(const fenc_ctx* ctx, const fenc_layout* lay);
+/* First (ciphertext, slot) of element (b, ch, y, x).  Host only. */
+int fenc_layout_slot(const fenc_ctx* ctx, const fenc_layout* lay, int b, int ch, int y, int x,
+                     int32_t* ct, int32_t* slot);
+/* Feature -> position map of a VECTOR layout (n_feat entries). */
+int fenc_layout_map(const fenc_ctx* ctx, const fenc_layout* lay, int32_t* pos);
+
+/* ---- client side (problem statement: the client encodes and encrypts by the
+ * index-slot mapping and decrypts the result) ------------------------------
+ * Encodes x[bs][c][h][w] (host) into integer plaintexts pt[n_ct][level+1][N]
+ * (host, coefficient form): round(Delta * tau^{-1}(slots)), canonical
+ * embedding, half away from zero. */
+int fenc_encode_fragment(fenc_ctx* ctx, const double* x, const fenc_layout* lay, uint64_t* pt);
+/* Encodes one slot vector z[N/2] at `scale` into pt[level+1][N]. */
+int fenc_encode_slots(fenc_ctx* ctx, const double* z, int32_t level, double scale, uint64_t* pt);
+/* Secret-key encryption of host plaintexts pt[n_ct][level+1][N] (coefficient
+ * form) into out->data (device); ciphertext t draws its randomness from
+ * (enc_seed, t).  out->lay is copied from lay. */
+int fenc_encrypt(fenc_ctx* ctx, const uint64_t* pt, const fenc_layout* lay, uint64_t enc_seed,
+                 fenc_ctbatch* out, void* stream);
+/* Decrypts and decodes into x[bs][c][h][w] (host).  Synchronises the stream. */
+int fenc_decrypt(fenc_ctx* ctx, const fenc_ctbatch* in, double* x, void* stream);
+/* m = c0 + c1 s for every ciphertext and limb, coefficient form, host
+ * [n_ct][level+1][N].  Synchronises the stream. */
+int fenc_decrypt_raw(fenc_ctx* ctx, const fenc_ctbatch* in, uint64_t* m, void* stream);
+
+/* ---- ciphertext transfer --------------------------------------------------
+ * Host coefficient form [n_ct][2][level+1][N] <-> device NTT form.  Both
+ * synchronise the stream. */
+int fenc_ct_export(fenc_ctx* ctx, const fenc_ctbatch* in, uint64_t* host, void* stream);
+int fenc_ct_import(fenc_ctx* ctx, const uint64_t* host, fenc_ctbatch* out, void* stream);
+
+/* ---- server side: the hot path ---------------------------------------------
+ * Convolution (eq. multi-channel-conv) on a FRAGMENT layout with dil == 1:
+ * w[cout][c/groups][k][k] (host, float64, cross-correlation), stride | S,
+ * zero padding pad, groups | c and | cout.  Hoisted inner rotations (one
+ * ModUp per input ciphertext), masked scalar multiply-accumulate, diagonal
+ * outer rotations summed with one ModDown per output ciphertext, one rescale.
+ * Output: same m, bs_g, C'; S and M divided by the stride; level - 1;
+ * scale exactly Delta. */
+int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t cout, uint32_t k,
+                uint32_t stride, uint32_t pad, uint32_t groups, fenc_ctbatch* out, void* stream);
+/* 2x2 average pooling, stride 2 (Evaluation methodology, implementation):
+ * S >= 2 sums the four fragments of each block (no rotation); S == 1 sums
+ * three hoisted rotations and doubles dil.  The factor 1/4 is carried in the
+ * scale (x4); no level is consumed. */
+int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream);
+/* Polynomial activation coeffs[0] + coeffs[1] x + ... ; this build evaluates
+ * degree 2 with coeffs = {0, 0, 1} (x^2: tensor, relinearisation, rescale). */
+int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, uint32_t degree,
+                  fenc_ctbatch* out, void* stream);
+/* Arch-aware Ct Compression (rot-mask-add): packs a sparse FRAGMENT batch
+ * into one VECTOR ciphertext per batch group; every source ciphertext is
+ * masked and moved by one rotation, all rotations into an output share one
+ * ModDown, and the mask scale is chosen so one rescale restores Delta.
+ * target must be NULL (the library places the fragments). */
+int fenc_compress(fenc_ctx* ctx, const fenc_ctbatch* in, const fenc_layout* target,
+                  fenc_ctbatch* out, void* stream);
+/* Fully connected layer y = W x, w[dout][n_feat] (host) on a VECTOR layout:
+ * diagonal method with baby-step giant-step (hoisted baby steps, giant steps
+ * summed with one ModDown), one rescale; output features at positions 0..dout-1. */
+int fenc_fc(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t dout,
+            fenc_ctbatch* out, void* stream);
+
+/* ---- building blocks exposed for testing --------------------------------
+ * Hoisted rotations of every ciphertext of `in` by shifts[0..n) (left, in
+ * slots); out holds n_ct * n ciphertexts, ct-major. */
+int fenc_rotate(fenc_ctx* ctx, const fenc_ctbatch* in, const int32_t* shifts, uint32_t n,
+                fenc_ctbatch* out, void* stream);
+/* out = z0 + sum_i Rot(z_i, shifts[i]) with one ModDown; zs holds n
+ * ciphertexts, z0 may be NULL. */
+int fenc_rotate_sum(fenc_ctx* ctx, const fenc_ctbatch* z0, const fenc_ctbatch* zs,
+                    const int32_t* shifts, uint32_t n, fenc_ctbatch* out, void* stream);
+int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream);
+/* Forward (inverse != 0: inverse) NTT of rows[n][N] (host) modulo prime index
+ * prime[i] of row i, through the device kernels. */
+int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t n, int inverse);
+/* Sampler and codec hooks (host only). */
+uint64_t fenc_sample_word(uint64_t seed, uint64_t tag, uint64_t i);
+int fenc_sample_gauss(uint64_t seed, uint64_t tag, uint64_t i);
+int fenc_encode_int(int32_t log_n, const double* z, double scale, int64_t* m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FENC_H */

@@ -361,12 +361,12 @@ int orc_decrypt_tensor(void* c, void* bp, double* x) {
 }
 
 void* orc_conv2d(void* c, void* bp, const double* w, int cout, int k, int stride, int pad, int groups,
-                 long* counts) {
+                 long long pt_budget, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
-  out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt);
+  out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt, pt_budget);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)

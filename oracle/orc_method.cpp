@@ -204,7 +204,8 @@ static void add_inplace(const Context& C, Ct& a, const Ct& b) {
 }
 
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
-                       int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt) {
+                       int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
+                       long long pt_budget) {
   if (Lin.kind != KIND_FRAGMENT || Lin.dil != 1) throw std::runtime_error("conv2d: needs a dense fragment layout");
   if (stride < 1 || Lin.S % stride) throw std::runtime_error("conv2d: stride must divide S");
   const int cin = Lin.c;
@@ -278,6 +279,20 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
     cnt.modup += 1;
     cnt.moddown += sh.size();
   }
+  // Plaintext form: with masks, either one full-scale plaintext per (output,
+  // diagonal, term) holding the weight of every position ("materialised"),
+  // or a mask per (term class, position) times scalar weight codes.
+  long long n_pt = 0;
+  for (int oct = 0; oct < (int)terms.size(); oct++) {
+    const int go = (oct / (So * So)) % ncg_out;
+    for (const Term& t : terms[oct])
+      for (int r = 0; r < nd; r++) {
+        bool any = false;
+        for (int q = 0; q < npos; q++) any |= pair_ok(in_channel(t.gi, q), go * cpc + posmod(q - r, cpc));
+        n_pt += any;
+      }
+  }
+  const bool materialise = need_mask && n_pt * (lvl + 1) * (long long)C.N * 8 <= pt_budget;
   // masks: source pixel inside the logical input, restricted to position q
   std::map<std::vector<int>, RPoly> masks;
   auto mask = [&](const Term& t, int q) -> const RPoly& {
@@ -302,7 +317,33 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
           const int oct = ((bg * ncg_out + go) * So + uo) * So + vo;
           std::vector<Ct> z(nd, zero_ct(C, lvl, Lin.scale * dw * dm));
           std::vector<bool> act(nd, false);
-          for (const Term& t : terms[oct]) {
+          if (materialise) {
+            for (const Term& t : terms[oct]) {
+              const Ct& copy = t.shift ? copies.at({t.idx, t.shift}) : in[t.idx];
+              for (int r = 0; r < nd; r++) {
+                std::vector<double> dz(C.ns, 0.0);
+                bool any = false;
+                for (int q = 0; q < npos; q++) {
+                  const int ch = in_channel(t.gi, q), o = go * cpc + posmod(q - r, cpc);
+                  if (!pair_ok(ch, o)) continue;
+                  any = true;
+                  const int grp = o / gout;
+                  const double wv = w[(((long long)o * gin + (ch - grp * gin)) * k + t.di) * k + t.dj];
+                  for (int bi = 0; bi < m; bi++)
+                    for (int bj = 0; bj < m; bj++) {
+                      int gh = (bi + t.dbi) * S + t.u, gw = (bj + t.dbj) * S + t.v;
+                      if (gh < 0 || gh >= Lin.h || gw < 0 || gw >= Lin.w) continue;
+                      for (int jb = 0; jb < bsg; jb++) dz[((q * m + bi) * m + bj) * bsg + jb] = wv;
+                    }
+                }
+                if (!any) continue;
+                act[r] = true;
+                add_inplace(C, z[r], mul_plain(C, copy, encode(C, dz, {}, T, q_basis(lvl)), T));
+                cnt.pmult++;
+              }
+            }
+          }
+          for (const Term& t : materialise ? std::vector<Term>() : terms[oct]) {
             const Ct& copy = t.shift ? copies.at({t.idx, t.shift}) : in[t.idx];
             for (int q = 0; q < npos; q++) {
               const int ch = in_channel(t.gi, q);

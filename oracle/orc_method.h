@@ -42,8 +42,11 @@ std::vector<RPoly> encode_fragment(Context& C, const Layout& L, const double* x)
 std::vector<Ct> encrypt_batch(Context& C, const Layout& L, const std::vector<RPoly>& pts, u64 enc_seed);
 void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, double* x);
 
+// pt_budget: plaintext bytes under which per-position weights are materialised
+// as full-scale plaintext diagonals instead of mask-basis scalar codes
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
-                       int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt);
+                       int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
+                       long long pt_budget = 1LL << 30);
 std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                          Counts& cnt);
 std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,

@@ -84,7 +84,7 @@ def _declare(L):
         "orc_batch_layout": (None, [vp, C.POINTER(OrcLayout)]),
         "orc_batch_data": (i, [vp, vp, u64p]),
         "orc_decrypt_tensor": (i, [vp, vp, f64p]),
-        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.POINTER(C.c_long)]),
+        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, C.POINTER(C.c_long)]),
         "orc_avgpool2": (vp, [vp, vp, C.POINTER(C.c_long)]),
         "orc_square": (vp, [vp, vp, C.POINTER(C.c_long)]),
         "orc_compress": (vp, [vp, vp, C.POINTER(C.c_long)]),
@@ -336,9 +336,9 @@ class Oracle:
             raise OracleError(lib().orc_last_error().decode())
         return Batch(self, h), dict(zip(COUNT_FIELDS, list(cnt)))
 
-    def conv2d(self, batch, w, stride=1, pad=0, groups=1):
+    def conv2d(self, batch, w, stride=1, pad=0, groups=1, pt_budget=1 << 30):
         w = np.ascontiguousarray(w, np.float64)
-        return self._op(lib().orc_conv2d, batch.h, w, w.shape[0], w.shape[2], stride, pad, groups)
+        return self._op(lib().orc_conv2d, batch.h, w, w.shape[0], w.shape[2], stride, pad, groups, pt_budget)
 
     def avgpool2(self, batch):
         return self._op(lib().orc_avgpool2, batch.h)

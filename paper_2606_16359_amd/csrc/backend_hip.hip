@@ -1,0 +1,135 @@
+// HIP backend: kernels for gfx950 and their launchers.
+#include <hip/hip_runtime.h>
+#include <stdexcept>
+#include <string>
+
+#define FENC_HD __host__ __device__
+#include "fenc_backend.h"
+
+namespace {
+
+// Execution interface for one GPU thread (see fenc_kernels.h).
+struct GpuX {
+  int bx, by, bz, nt;
+  double* smem;
+  template <class F>
+  __device__ void phase(F f) {
+    f((int)threadIdx.x);
+    __syncthreads();
+  }
+};
+
+__device__ inline GpuX here(double* smem) {
+  GpuX x;
+  x.bx = blockIdx.x;
+  x.by = blockIdx.y;
+  x.bz = blockIdx.z;
+  x.nt = blockDim.x;
+  x.smem = smem;
+  return x;
+}
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void check_launch(const char* what) { check(hipGetLastError(), what); }
+
+}  // namespace
+
+#define FENC_KERNEL_LDS(NAME, ARGS)                                                   \
+  __global__ void __launch_bounds__(256) k_##NAME(fk::ARGS a) {                        \
+    extern __shared__ double smem[];                                                   \
+    GpuX x = here(smem);                                                               \
+    fk::NAME(x, a);                                                                    \
+  }                                                                                    \
+  void fb::NAME(Grid g, int threads, size_t lds, Stream s, const fk::ARGS& a) {        \
+    hipLaunchKernelGGL(k_##NAME, dim3(g.x, g.y, g.z), dim3(threads), lds,              \
+                       (hipStream_t)s, a);                                             \
+    check_launch(#NAME);                                                               \
+  }
+
+#define FENC_KERNEL(NAME, ARGS)                                                       \
+  __global__ void __launch_bounds__(256) k_##NAME(fk::ARGS a) {                        \
+    GpuX x = here(nullptr);                                                            \
+    fk::NAME(x, a);                                                                    \
+  }                                                                                    \
+  void fb::NAME(Grid g, int threads, Stream s, const fk::ARGS& a) {                    \
+    hipLaunchKernelGGL(k_##NAME, dim3(g.x, g.y, g.z), dim3(threads), 0,                \
+                       (hipStream_t)s, a);                                             \
+    check_launch(#NAME);                                                               \
+  }
+
+FENC_KERNEL_LDS(ntt_fwd_cols, NttArgs)
+FENC_KERNEL_LDS(ntt_fwd_rows, NttArgs)
+FENC_KERNEL_LDS(ntt_inv_rows, NttArgs)
+FENC_KERNEL_LDS(ntt_inv_cols, NttArgs)
+FENC_KERNEL(modup_fbc, ModUpArgs)
+FENC_KERNEL(kip, KipArgs)
+FENC_KERNEL(moddown_fbc, ModDownArgs)
+FENC_KERNEL(moddown_tail, TailArgs)
+FENC_KERNEL(rescale_lift, LiftArgs)
+FENC_KERNEL(rescale_tail, RescaleTailArgs)
+FENC_KERNEL(gmac, GmacArgs)
+FENC_KERNEL(tensor_square, SquareArgs)
+FENC_KERNEL(key_combine, KeyArgs)
+FENC_KERNEL(enc_combine, EncArgs)
+FENC_KERNEL(dec_combine, DecArgs)
+FENC_KERNEL(small_to_rns, SmallArgs)
+FENC_KERNEL(perm_rows, PermArgs)
+
+namespace fb {
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  check(hipMalloc(&p, bytes ? bytes : 256), "hipMalloc");
+  return p;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+void h2d(void* dst, const void* src, size_t bytes) {
+  if (bytes) check(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy H2D");
+}
+
+void d2h(void* dst, const void* src, size_t bytes) {
+  if (bytes) check(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+}
+
+void d2d_async(void* dst, const void* src, size_t bytes, Stream s) {
+  if (bytes) check(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)s), "hipMemcpyAsync D2D");
+}
+
+void sync(Stream s) { check(hipStreamSynchronize((hipStream_t)s), "hipStreamSynchronize"); }
+
+bool capturing(Stream s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing((hipStream_t)s, &st) != hipSuccess) return false;
+  return st == hipStreamCaptureStatusActive;
+}
+
+const char* backend_name() { return "hip-gfx950"; }
+
+void* event_create() {
+  hipEvent_t e;
+  check(hipEventCreate(&e), "hipEventCreate");
+  return (void*)e;
+}
+void event_record(void* e, Stream s) { check(hipEventRecord((hipEvent_t)e, (hipStream_t)s), "hipEventRecord"); }
+float event_elapsed_ms(void* a, void* b) {
+  check(hipEventSynchronize((hipEvent_t)b), "hipEventSynchronize");
+  float ms = 0;
+  check(hipEventElapsedTime(&ms, (hipEvent_t)a, (hipEvent_t)b), "hipEventElapsedTime");
+  return ms;
+}
+void event_destroy(void* e) { (void)hipEventDestroy((hipEvent_t)e); }
+
+int device_id() {
+  int d = 0;
+  check(hipGetDevice(&d), "hipGetDevice");
+  return d;
+}
+
+}  // namespace fb

@@ -1,0 +1,660 @@
+// Kernel bodies of the hot path.
+//
+// Each body is written against a small execution interface X:
+//   x.bx, x.by, x.bz   block indices
+//   x.nt               threads per block
+//   x.smem             LDS scratch (doubles)
+//   x.phase(f)         run f(tid) for the threads of the block, then barrier
+// The HIP backend instantiates X as "this thread"; the test suite also runs
+// the same bodies through a sequential emulator to check index arithmetic on
+// the CPU.  Residues are uint64 in [0, q) in HBM and exact integers in
+// binary64 inside the kernels (fenc_arith.h).
+#pragma once
+#include <cstddef>
+#include "fenc_arith.h"
+
+namespace fk {
+
+struct d2 {
+  double x, y;
+};
+
+constexpr int kMaxMap = 128;
+constexpr unsigned char kSkip = 255;
+
+// prime of row r is p[r % n]; kSkip leaves the row untouched
+struct PrimeMap {
+  int n;
+  unsigned char p[kMaxMap];
+};
+
+// ------------------------------------------------------------------ NTT
+// Negacyclic NTT over rows of N = 2^logn residues.  Forward: Cooley-Tukey
+// with merged psi twiddles, natural order in, bit-reversed order out (slot k
+// holds the evaluation at psi^(2 brev(k)+1)).  Inverse: Gentleman-Sande,
+// bit-reversed in, natural out, scaled by N^-1.  Split into a column pass
+// (stride-2^n2 butterflies, first n1 forward stages) and a row pass
+// (contiguous chunks of 2^n2, last n2 stages); both stage their tile in LDS.
+struct NttArgs {
+  const u64* src;
+  u64* dst;
+  long long src_gs, dst_gs;   // elements between row groups
+  int nrows, nl;              // rows, rows per group (row r: group r/nl, limb r%nl)
+  PrimeMap pm;
+  const d2* tw;               // [prime][N] (w, w/q)
+  const d2* pq;               // [prime] (q, 1/q)
+  const d2* ninv;             // [prime] (N^-1, N^-1/q), inverse only
+  int logn, n1, n2;
+  int cols;                   // columns per block (column pass)
+  int cpb;                    // chunks per block (row pass)
+};
+
+template <class X>
+FENC_HD void ntt_fwd_cols(X& x, const NttArgs& a) {
+  const int row = x.by;
+  const int p = a.pm.p[row % a.pm.n];
+  if (p == kSkip) return;
+  const int n1 = a.n1, n2 = a.n2, C = a.cols, R = 1 << n1, T = x.nt;
+  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn);
+  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn);
+  const int col0 = x.bx * C;
+  const double q = a.pq[p].x, qi = a.pq[p].y;
+  const d2* tw = a.tw + ((long long)p << a.logn);
+  double* s = x.smem;
+  x.phase([&](int t) {
+    for (int e = t; e < R * C; e += T) {
+      const int hi = e / C, c = e % C;
+      s[e] = u2d(src[((long long)hi << n2) + col0 + c]);
+    }
+  });
+  for (int st = 0; st < n1; st++) {
+    const int th = 1 << (n1 - 1 - st);
+    x.phase([&](int t) {
+      for (int b = t; b < (R / 2) * C; b += T) {
+        const int c = b % C, bb = b / C;
+        const int grp = bb / th, off = bb % th;
+        const int hi = grp * 2 * th + off;
+        const d2 w = tw[(1 << st) + grp];
+        const double u = s[hi * C + c];
+        const double v = mulmod_c(s[(hi + th) * C + c], w.x, w.y, q);
+        s[hi * C + c] = red(u + v, q, qi);
+        s[(hi + th) * C + c] = red(u - v, q, qi);
+      }
+    });
+  }
+  x.phase([&](int t) {
+    for (int e = t; e < R * C; e += T) {
+      const int hi = e / C, c = e % C;
+      dst[((long long)hi << n2) + col0 + c] = d2u(norm(s[e], q));
+    }
+  });
+}
+
+template <class X>
+FENC_HD void ntt_fwd_rows(X& x, const NttArgs& a) {
+  const int row = x.by;
+  const int p = a.pm.p[row % a.pm.n];
+  if (p == kSkip) return;
+  const int n1 = a.n1, n2 = a.n2, logn = a.logn, Lc = 1 << n2, T = x.nt;
+  const int E = a.cpb * Lc;
+  const long long e0 = (long long)x.bx * E;
+  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn) + e0;
+  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn) + e0;
+  const double q = a.pq[p].x, qi = a.pq[p].y;
+  const d2* tw = a.tw + ((long long)p << logn);
+  double* s = x.smem;
+  x.phase([&](int t) {
+    for (int e = t; e < E; e += T) s[e] = u2d(src[e]);
+  });
+  for (int st = n1; st < logn; st++) {
+    const int td = 1 << (logn - 1 - st);
+    x.phase([&](int t) {
+      for (int b = t; b < E / 2; b += T) {
+        const int grp = b / td, off = b % td;
+        const int lo = grp * 2 * td + off;                          // local index within the block
+        const long long gi = (e0 + lo) / (2 * td);                  // global butterfly group
+        const d2 w = tw[(1LL << st) + gi];
+        const double u = s[lo];
+        const double v = mulmod_c(s[lo + td], w.x, w.y, q);
+        s[lo] = red(u + v, q, qi);
+        s[lo + td] = red(u - v, q, qi);
+      }
+    });
+  }
+  x.phase([&](int t) {
+    for (int e = t; e < E; e += T) dst[e] = d2u(norm(s[e], q));
+  });
+}
+
+template <class X>
+FENC_HD void ntt_inv_rows(X& x, const NttArgs& a) {
+  const int row = x.by;
+  const int p = a.pm.p[row % a.pm.n];
+  if (p == kSkip) return;
+  const int n2 = a.n2, logn = a.logn, Lc = 1 << n2, T = x.nt;
+  const int E = a.cpb * Lc;
+  const long long e0 = (long long)x.bx * E;
+  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn) + e0;
+  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn) + e0;
+  const double q = a.pq[p].x, qi = a.pq[p].y;
+  const d2* tw = a.tw + ((long long)p << logn);
+  double* s = x.smem;
+  x.phase([&](int t) {
+    for (int e = t; e < E; e += T) s[e] = u2d(src[e]);
+  });
+  for (int u = 0; u < n2; u++) {
+    const int td = 1 << u;
+    const long long h = (1LL << logn) / (2 * td);
+    x.phase([&](int t) {
+      for (int b = t; b < E / 2; b += T) {
+        const int grp = b / td, off = b % td;
+        const int lo = grp * 2 * td + off;
+        const long long gi = (e0 + lo) / (2 * td);
+        const d2 w = tw[h + gi];
+        const double xv = s[lo], yv = s[lo + td];
+        s[lo] = red(xv + yv, q, qi);
+        s[lo + td] = mulmod_c(xv - yv, w.x, w.y, q);
+      }
+    });
+  }
+  x.phase([&](int t) {
+    for (int e = t; e < E; e += T) dst[e] = d2u(norm(red(s[e], q, qi), q));
+  });
+}
+
+template <class X>
+FENC_HD void ntt_inv_cols(X& x, const NttArgs& a) {
+  const int row = x.by;
+  const int p = a.pm.p[row % a.pm.n];
+  if (p == kSkip) return;
+  const int n1 = a.n1, n2 = a.n2, C = a.cols, R = 1 << n1, T = x.nt, logn = a.logn;
+  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn);
+  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn);
+  const int col0 = x.bx * C;
+  const double q = a.pq[p].x, qi = a.pq[p].y;
+  const d2* tw = a.tw + ((long long)p << logn);
+  const d2 ni = a.ninv[p];
+  double* s = x.smem;
+  x.phase([&](int t) {
+    for (int e = t; e < R * C; e += T) {
+      const int hi = e / C, c = e % C;
+      s[e] = u2d(src[((long long)hi << n2) + col0 + c]);
+    }
+  });
+  for (int u = n2; u < logn; u++) {
+    const int th = 1 << (u - n2);
+    const long long h = (1LL << logn) >> (u + 1);
+    x.phase([&](int t) {
+      for (int b = t; b < (R / 2) * C; b += T) {
+        const int c = b % C, bb = b / C;
+        const int grp = bb / th, off = bb % th;
+        const int hi = grp * 2 * th + off;
+        const d2 w = tw[h + grp];
+        const double xv = s[hi * C + c], yv = s[(hi + th) * C + c];
+        s[hi * C + c] = red(xv + yv, q, qi);
+        s[(hi + th) * C + c] = mulmod_c(xv - yv, w.x, w.y, q);
+      }
+    });
+  }
+  x.phase([&](int t) {
+    for (int e = t; e < R * C; e += T) {
+      const int hi = e / C, c = e % C;
+      dst[((long long)hi << n2) + col0 + c] = d2u(norm(mulmod_c(s[e], ni.x, ni.y, q), q));
+    }
+  });
+}
+
+// ------------------------------------------------------------------ ModUp
+// Fast base conversion of every digit of c1 (coefficient form) to the other
+// limbs of Q_l U P:  y_i = [x_i * (Qj/q_i)^-1]_{q_i},  out_t = sum_i y_i [Qj/q_i]_t.
+// The digit's own limbs are copied from the NTT-form input.
+// Table per digit j (stride tstride d2 entries): hinv[alpha], hat[le][alpha].
+struct ModUpArgs {
+  const u64* coef;        // c1 coefficient form of ct b: coef + b*coef_cs + l*N
+  const u64* ntt;         // c1 NTT form of ct b: ntt + b*ntt_cs + l*N
+  long long coef_cs, ntt_cs;
+  u64* ext;               // [B][beta][le][N]
+  int b0;                 // first ct of the launch
+  int beta, alpha, nl, le, logn;
+  const unsigned char* eprime;   // [le] prime index of extended limb
+  const d2* tab;
+  int tstride;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void modup_fbc(X& x, const ModUpArgs& a) {
+  x.phase([&](int t) {
+    const long long c = (long long)x.bx * x.nt + t;
+    const int b = a.b0 + x.by / a.beta, j = x.by % a.beta;
+    const int lo = j * a.alpha, hi = (lo + a.alpha < a.nl) ? lo + a.alpha : a.nl, ds = hi - lo;
+    const d2* tab = a.tab + (long long)j * a.tstride;
+    const long long N = 1LL << a.logn;
+    u64* out = a.ext + ((long long)b * a.beta + j) * a.le * N;
+    double y[16];
+    for (int i = 0; i < ds; i++) {
+      const int p = a.eprime[lo + i];
+      const double q = a.pq[p].x;
+      const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
+      y[i] = norm(mulmod_c(v, tab[i].x, tab[i].y, q), q);
+    }
+    for (int l = 0; l < a.le; l++) {
+      if (l >= lo && l < hi) {
+        out[l * N + c] = a.ntt[b * a.ntt_cs + l * N + c];
+        continue;
+      }
+      const int p = a.eprime[l];
+      const double q = a.pq[p].x, qi = a.pq[p].y;
+      const d2* h = tab + a.alpha + (long long)l * a.alpha;
+      double acc = 0;
+      for (int i = 0; i < ds; i++) {
+        acc += mulmod_c(y[i], h[i].x, h[i].y, q);
+        if ((i & 3) == 3) acc = red(acc, q, qi);
+      }
+      out[l * N + c] = d2u(norm(red(acc, q, qi), q));
+    }
+  });
+}
+
+// ------------------------------------------------------------------ key inner product
+// Output o sums its items: acc_o = sum_items sum_j sigma_g(ext_{ct,j}) * key_j.
+// One item per output is the hoisted rotation; several items (different cts
+// and keys) is the lazy-ModDown sum.
+struct KipItem {
+  int ct;           // index into ext
+  unsigned g;       // Galois element (1: identity)
+  const u64* key;   // [ndig][2][nprimes][N]
+};
+
+struct KipArgs {
+  const u64* ext;         // [B][beta][le][N]
+  u64* acc;               // [nout][2][le][N]
+  const KipItem* items;
+  const int* item_off;    // [nout+1]
+  int o0;                 // first output of the launch
+  int beta, le, logn, nprimes;
+  const unsigned char* eprime;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void kip(X& x, const KipArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int l = x.by, o = a.o0 + x.bz;
+    const int p = a.eprime[l];
+    const double q = a.pq[p].x, qi = a.pq[p].y;
+    double a0 = 0, a1 = 0;
+    for (int it = a.item_off[o]; it < a.item_off[o + 1]; it++) {
+      const KipItem I = a.items[it];
+      const long long src = (I.g == 1) ? c : (long long)auto_src((unsigned)c, I.g, a.logn);
+      const u64* e = a.ext + (long long)I.ct * a.beta * a.le * N + l * N + src;
+      for (int j = 0; j < a.beta; j++) {
+        const double v = u2d(e[(long long)j * a.le * N]);
+        const u64* kj = I.key + ((long long)j * 2 * a.nprimes + p) * N + c;
+        a0 += mulmod(v, u2d(kj[0]), q, qi);
+        a1 += mulmod(v, u2d(kj[(long long)a.nprimes * N]), q, qi);
+        if ((j & 3) == 3) {
+          a0 = red(a0, q, qi);
+          a1 = red(a1, q, qi);
+        }
+      }
+      a0 = red(a0, q, qi);
+      a1 = red(a1, q, qi);
+    }
+    u64* out = a.acc + (long long)o * 2 * a.le * N + l * N + c;
+    out[0] = d2u(norm(red(a0, q, qi), q));
+    out[a.le * N] = d2u(norm(red(a1, q, qi), q));
+  });
+}
+
+// ------------------------------------------------------------------ ModDown
+// conv_i = sum_k [acc_{p_k} (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}  (coefficient form)
+// Table: hinv[K], hat[nl][K].
+struct ModDownArgs {
+  const u64* acc;        // [nout][2][le][N], P limbs in coefficient form
+  u64* conv;             // [nout][2][nl][N]
+  int o0;                // first output of the launch
+  int nl, le, K, logn;
+  const unsigned char* eprime;
+  const d2* tab;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void moddown_fbc(X& x, const ModDownArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const long long op = 2LL * a.o0 + x.by;   // output * 2 + poly
+    const u64* in = a.acc + op * a.le * N + c;
+    double y[16];
+    for (int k = 0; k < a.K; k++) {
+      const int p = a.eprime[a.nl + k];
+      const double q = a.pq[p].x;
+      y[k] = norm(mulmod_c(u2d(in[(long long)(a.nl + k) * N]), a.tab[k].x, a.tab[k].y, q), q);
+    }
+    u64* out = a.conv + op * a.nl * N + c;
+    for (int i = 0; i < a.nl; i++) {
+      const int p = a.eprime[i];
+      const double q = a.pq[p].x, qi = a.pq[p].y;
+      const d2* h = a.tab + a.K + (long long)i * a.K;
+      double s = 0;
+      for (int k = 0; k < a.K; k++) {
+        s += mulmod_c(y[k], h[k].x, h[k].y, q);
+        if ((k & 3) == 3) s = red(s, q, qi);
+      }
+      out[(long long)i * N] = d2u(norm(red(s, q, qi), q));
+    }
+  });
+}
+
+// out = (acc - conv) * P^-1 + base + sum_terms sigma_g(c0 of term ct)   (terms: poly 0 only)
+// All cts are addressed as base pointer + index * ct stride; poly p of a ct
+// starts at p * poly stride.
+struct TailItem {
+  int out;           // output ct index
+  int base;          // base ct index or -1
+  int add_off, add_n;
+};
+struct AddTerm {
+  int ct;            // ct index in the add source
+  unsigned g;
+};
+struct TailArgs {
+  const u64* acc;    // [nout][2][le][N] (Q limbs NTT form)
+  const u64* conv;   // [nout][2][nl][N]
+  const TailItem* items;
+  const AddTerm* terms;
+  int o0;
+  int nl, le, logn;
+  u64* out;  long long out_cs, out_ps;
+  const u64* base;  long long base_cs, base_ps;
+  const u64* add;   long long add_cs;
+  const d2* pinv;    // [nl] (P^-1 mod q_i, /q)
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void moddown_tail(X& x, const TailArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by % a.nl, poly = x.by / a.nl, o = a.o0 + x.bz;
+    const double q = a.pq[i].x, qi = a.pq[i].y;
+    const double av = u2d(a.acc[((long long)o * 2 + poly) * a.le * N + i * N + c]);
+    const double cv = u2d(a.conv[((long long)o * 2 + poly) * a.nl * N + i * N + c]);
+    double r = mulmod_c(av - cv, a.pinv[i].x, a.pinv[i].y, q);
+    const TailItem I = a.items[o];
+    if (I.base >= 0) r += u2d(a.base[I.base * a.base_cs + poly * a.base_ps + i * N + c]);
+    if (poly == 0)
+      for (int k = 0; k < I.add_n; k++) {
+        const AddTerm T = a.terms[I.add_off + k];
+        const long long src = (T.g == 1) ? c : (long long)auto_src((unsigned)c, T.g, a.logn);
+        r += u2d(a.add[T.ct * a.add_cs + i * N + src]);
+        if ((k & 3) == 3) r = red(r, q, qi);
+      }
+    a.out[I.out * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(red(r, q, qi), q));
+  });
+}
+
+// ------------------------------------------------------------------ rescale
+// last: coefficient form of limb l (rows [B][2]); lift centred value to each q_i, i < l
+struct LiftArgs {
+  const u64* last;   // [B*2][N]
+  u64* out;          // [B*2][nl][N]
+  int nl, logn;
+  double ql;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void rescale_lift(X& x, const LiftArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int r = x.by;
+    double v = u2d(a.last[(long long)r * N + c]);
+    if (v > (a.ql - 1) * 0.5) v -= a.ql;   // centred representative
+    u64* o = a.out + (long long)r * a.nl * N + c;
+    for (int i = 0; i < a.nl; i++) {
+      const double q = a.pq[i].x, qi = a.pq[i].y;
+      o[(long long)i * N] = d2u(norm(red(v, q, qi), q));
+    }
+  });
+}
+
+struct RescaleTailArgs {
+  const u64* in;     // [B][2][nl+1][N]
+  const u64* lift;   // [B*2][nl][N] NTT form
+  u64* out;          // [B][2][nl][N]
+  int nl, logn;
+  const d2* qlinv;   // [nl]
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void rescale_tail(X& x, const RescaleTailArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by % a.nl, r = x.by / a.nl;   // r = ct*2 + poly
+    const double q = a.pq[i].x;
+    const double v = u2d(a.in[((long long)r * (a.nl + 1) + i) * N + c]);
+    const double w = u2d(a.lift[((long long)r * a.nl + i) * N + c]);
+    a.out[((long long)r * a.nl + i) * N + c] = d2u(norm(mulmod_c(v - w, a.qlinv[i].x, a.qlinv[i].y, q), q));
+  });
+}
+
+// ------------------------------------------------------------------ linear combinations
+// out[o] = sum_g mask_g (.) ( sum_{t in g} w_t * in_t )      (NTT form, both polys)
+// Input index t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.
+// Weight index < 0 means weight 1; a null mask means no plaintext product.
+struct GmacArgs {
+  const u64* in_a; long long a_cs; int na;
+  const u64* in_b; long long b_cs;
+  long long in_ps;           // poly stride of inputs
+  u64* out; long long out_cs, out_ps;
+  int o0;
+  const int* goff;           // [nout+1] groups of each output
+  const u64* const* mask;    // [ngroups] plaintext [nl][N] or null
+  const int* toff;           // [ngroups+1]
+  const int* tin;            // [nterms] input index
+  const int* tw;             // [nterms] weight index or -1
+  const d2* wt;              // [nl][nw] weight residues (w, w/q)
+  int nw, nl, logn;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void gmac(X& x, const GmacArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by % a.nl, poly = x.by / a.nl, o = a.o0 + x.bz;
+    const double q = a.pq[i].x, qi = a.pq[i].y;
+    const long long off = poly * a.in_ps + i * N + c;
+    double r = 0;
+    for (int g = a.goff[o]; g < a.goff[o + 1]; g++) {
+      double s = 0;
+      int n = 0;
+      for (int k = a.toff[g]; k < a.toff[g + 1]; k++) {
+        const int ti = a.tin[k];
+        const u64* src = ti < a.na ? a.in_a + ti * a.a_cs : a.in_b + (ti - a.na) * a.b_cs;
+        const double v = u2d(src[off]);
+        const int wi = a.tw[k];
+        if (wi < 0) {
+          s += v;
+        } else {
+          const d2 w = a.wt[(long long)i * a.nw + wi];
+          s += mulmod_c(v, w.x, w.y, q);
+        }
+        if (++n == 5) { s = red(s, q, qi); n = 0; }
+      }
+      s = red(s, q, qi);
+      if (a.mask[g]) s = mulmod(s, u2d(a.mask[g][i * N + c]), q, qi);
+      r = red(r + s, q, qi);
+    }
+    a.out[o * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(red(r, q, qi), q));
+  });
+}
+
+// ------------------------------------------------------------------ tensor / key / encryption
+// (d0, d1, d2) = (c0^2, 2 c0 c1, c1^2); d0,d1 into out (ct [2][nl][N]), d2 into d2buf [nl][N]
+struct SquareArgs {
+  const u64* in;
+  u64* out;
+  u64* d2buf;
+  int nl, logn;
+  long long ct_stride;   // elements per ct (in and out)
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void tensor_square(X& x, const SquareArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by, b = x.bz;
+    const double q = a.pq[i].x, qi = a.pq[i].y;
+    const u64* in = a.in + b * a.ct_stride + i * N + c;
+    const double c0 = u2d(in[0]), c1 = u2d(in[a.nl * N]);
+    u64* out = a.out + b * a.ct_stride + i * N + c;
+    const double m01 = mulmod(c0, c1, q, qi);
+    out[0] = d2u(norm(mulmod(c0, c0, q, qi), q));
+    out[a.nl * N] = d2u(norm(red(m01 + m01, q, qi), q));
+    a.d2buf[(long long)b * a.nl * N + i * N + c] = d2u(norm(mulmod(c1, c1, q, qi), q));
+  });
+}
+
+// b = -a*s + e + gadget * s'   (all NTT form over prime p); rows: digit*np + prime
+struct KeyArgs {
+  const u64* a;      // [ndig][np][N]
+  const u64* e;      // [ndig][np][N]
+  const u64* s;      // [np][N] secret, NTT form
+  const u64* sp;     // [np][N] target secret s' (NTT form)
+  u64* key;          // [ndig][2][np][N]
+  const d2* gadget;  // [ndig][np] (P mod q or 0, /q)
+  int np, logn;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void key_combine(X& x, const KeyArgs& A) {
+  x.phase([&](int t) {
+    const long long N = 1LL << A.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int p = x.by % A.np, j = x.by / A.np;
+    const double q = A.pq[p].x, qi = A.pq[p].y;
+    const long long o = ((long long)j * A.np + p) * N + c;
+    const double av = u2d(A.a[o]), ev = u2d(A.e[o]);
+    const double s = u2d(A.s[(long long)p * N + c]), sp = u2d(A.sp[(long long)p * N + c]);
+    const d2 g = A.gadget[(long long)j * A.np + p];
+    double b = ev - mulmod(av, s, q, qi);
+    b += mulmod_c(sp, g.x, g.y, q);
+    u64* k = A.key + ((long long)j * 2 * A.np + p) * N + c;
+    k[0] = d2u(norm(red(b, q, qi), q));
+    k[(long long)A.np * N] = A.a[o];
+  });
+}
+
+// c0 = -a*s + e + m, c1 = a   (NTT form); rows: ct*nl + limb
+struct EncArgs {
+  const u64* a;   // [B][nl][N]
+  const u64* e;   // [B][nl][N]
+  const u64* m;   // [B][nl][N]
+  const u64* s;   // [nprimes][N]
+  u64* ct;        // [B][2][nl][N]
+  int nl, logn;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void enc_combine(X& x, const EncArgs& A) {
+  x.phase([&](int t) {
+    const long long N = 1LL << A.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by % A.nl, b = x.by / A.nl;
+    const double q = A.pq[i].x, qi = A.pq[i].y;
+    const long long o = ((long long)b * A.nl + i) * N + c;
+    const double av = u2d(A.a[o]);
+    double r = u2d(A.e[o]) + u2d(A.m[o]) - mulmod(av, u2d(A.s[(long long)i * N + c]), q, qi);
+    u64* ct = A.ct + ((long long)b * 2 * A.nl + i) * N + c;
+    ct[0] = d2u(norm(red(r, q, qi), q));
+    ct[(long long)A.nl * N] = A.a[o];
+  });
+}
+
+// m = c0 + c1*s (NTT form); rows: ct*nl + limb
+struct DecArgs {
+  const u64* ct;   // [B][2][nl][N]
+  const u64* s;
+  u64* m;          // [B][nl][N]
+  int nl, logn;
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void dec_combine(X& x, const DecArgs& A) {
+  x.phase([&](int t) {
+    const long long N = 1LL << A.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by % A.nl, b = x.by / A.nl;
+    const double q = A.pq[i].x, qi = A.pq[i].y;
+    const u64* ct = A.ct + ((long long)b * 2 * A.nl + i) * N + c;
+    double r = u2d(ct[0]) + mulmod(u2d(ct[(long long)A.nl * N]), u2d(A.s[(long long)i * N + c]), q, qi);
+    A.m[((long long)b * A.nl + i) * N + c] = d2u(norm(red(r, q, qi), q));
+  });
+}
+
+// small signed integers (one polynomial, N coefficients) reduced into limbs
+struct SmallArgs {
+  const long long* v;   // [B][N]
+  u64* out;             // [B][nl][N]
+  int nl, logn;
+  const unsigned char* prime;   // [nl]
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void small_to_rns(X& x, const SmallArgs& A) {
+  x.phase([&](int t) {
+    const long long N = 1LL << A.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int l = x.by % A.nl, b = x.by / A.nl;
+    const int p = A.prime[l];
+    const double q = A.pq[p].x, qi = A.pq[p].y;
+    const double v = (double)A.v[(long long)b * N + c];
+    A.out[((long long)b * A.nl + l) * N + c] = d2u(norm(red(v, q, qi), q));
+  });
+}
+
+// out = sigma_g(in) on rows of N (NTT form), or out = in*in when g == 0
+struct PermArgs {
+  const u64* in;
+  u64* out;
+  unsigned g;
+  int logn;
+  const unsigned char* prime;   // row -> prime (for the square)
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void perm_rows(X& x, const PermArgs& A) {
+  x.phase([&](int t) {
+    const long long N = 1LL << A.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const long long r = x.by;
+    if (A.g == 0) {
+      const int p = A.prime[r];
+      const double q = A.pq[p].x, qi = A.pq[p].y;
+      const double v = u2d(A.in[r * N + c]);
+      A.out[r * N + c] = d2u(norm(mulmod(v, v, q, qi), q));
+    } else {
+      A.out[r * N + c] = A.in[r * N + auto_src((unsigned)c, A.g, A.logn)];
+    }
+  });
+}
+
+}  // namespace fk

@@ -1,0 +1,1433 @@
+// Layouts, operation plans and the C ABI.
+//
+// Conv-aware Encoding (Alg. fragment-packing) with the readings: pad() is the
+// next power of two; slot l = (i*m^2 + kappa)*BS_g + j with 0-based floors,
+// kappa = b_i*m + b_j, batch innermost; a batch larger than one ciphertext
+// is split into groups of BS_g = min(BS, (N/2)/m^2) images; C' = (N/2)/(BS_g
+// m^2) channel positions per ciphertext, channels replicated when C < C' and
+// C | C'.  Block size by argmin of eq. (total-rot) under eq. (opt).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+#include <sstream>
+#include <thread>
+
+#include "runtime.h"
+
+using namespace fr;
+using fh::mulmod;
+
+static thread_local std::string g_err;
+
+namespace fr {
+
+static int next_pow2(int x) {
+  int M = 1;
+  while (M < x) M <<= 1;
+  return M;
+}
+
+static int posmod(long long a, long long b) {
+  long long r = a % b;
+  return (int)(r < 0 ? r + b : r);
+}
+
+static int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+Layout make_fragment(int ns, int level, double scale, int bs, int c, int h, int w, int S) {
+  if (bs < 1 || c < 1 || h < 1 || w < 1) fail(FENC_EINVAL, "empty tensor");
+  Layout L;
+  L.kind = FENC_LAYOUT_FRAGMENT;
+  L.bs = bs; L.c = c; L.h = h; L.w = w;
+  L.M = next_pow2(std::max(h, w));
+  if (S < 1 || L.M % S) fail(FENC_EINVAL, "block size must divide the padded side");
+  L.S = S;
+  L.m = L.M / S;
+  const long long m2 = (long long)L.m * L.m;
+  if (m2 > ns) fail(FENC_ELAYOUT, "one fragment does not fit a ciphertext (m^2 > N/2)");
+  L.bsg = (int)std::min<long long>(bs, ns / m2);
+  L.cpc = (int)(ns / (L.bsg * m2));
+  L.nbg = (bs + L.bsg - 1) / L.bsg;
+  L.rep = (c < L.cpc && L.cpc % c == 0) ? 1 : 0;
+  L.ncg = L.rep ? 1 : (c + L.cpc - 1) / L.cpc;
+  L.dil = 1;
+  L.level = level;
+  L.scale = scale;
+  return L;
+}
+
+Layout plan_fragment(int ns, int level, double scale, int bs, int c, int h, int w, int k, int cout, int s_override) {
+  if (bs < 1 || c < 1 || h < 1 || w < 1) fail(FENC_EINVAL, "empty tensor");
+  const int M = next_pow2(std::max(h, w));
+  std::vector<int> adm;
+  for (int S = 1; S <= M; S <<= 1)
+    if ((long long)(M / S) * (M / S) <= ns) adm.push_back(S);
+  if (adm.empty()) fail(FENC_ELAYOUT, "no block size fits a ciphertext");
+  int best = adm.front();
+  if (s_override > 0) {
+    if (std::find(adm.begin(), adm.end(), s_override) == adm.end()) fail(FENC_EINVAL, "block size not admissible");
+    best = s_override;
+  } else {
+    __int128 bestcost = -1;
+    for (int S : adm) {
+      // eq. (opt): S^2 <= BS N_in / alpha with alpha = (N/2)/M^2
+      if ((__int128)S * S * ns > (__int128)bs * c * M * M) continue;
+      // eq. (total-rot) times N/2: BS M^2 I(K,S) N_in + max(ns S^2 - BS M^2, 0) N_out
+      const __int128 ck = (k + S - 1) / S;
+      const __int128 I = (k > S) ? ck * ck - 1 : 0;
+      __int128 outer = (__int128)ns * S * S - (__int128)bs * M * M;
+      if (outer < 0) outer = 0;
+      const __int128 cost = (__int128)bs * M * M * I * c + outer * cout;
+      if (bestcost < 0 || cost < bestcost) { bestcost = cost; best = S; }
+    }
+  }
+  return make_fragment(ns, level, scale, bs, c, h, w, best);
+}
+
+void layout_slots(const Layout& L, int b, int ch, int y, int x, std::vector<std::pair<int, int>>& out) {
+  out.clear();
+  const int bg = b / L.bsg, jb = b % L.bsg;
+  if (L.kind == FENC_LAYOUT_VECTOR) {
+    const int f = (ch * L.h + y) * L.w + x;
+    out.push_back({bg, L.pos[f] * L.bsg + jb});
+    return;
+  }
+  const int gy = L.dil * y, gx = L.dil * x;
+  const int u = gy % L.S, bi = gy / L.S, v = gx % L.S, bj = gx / L.S;
+  auto put = [&](int cg, int q) {
+    out.push_back({((bg * L.ncg + cg) * L.S + u) * L.S + v, ((q * L.m + bi) * L.m + bj) * L.bsg + jb});
+  };
+  if (L.rep) {
+    for (int q = ch; q < L.cpc; q += L.c) put(0, q);
+  } else {
+    put(ch / L.cpc, ch % L.cpc);
+  }
+}
+
+}  // namespace fr
+
+// ---------------------------------------------------------------- conversions
+static uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; i++) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+static Layout from_pub(const Ctx& C, const fenc_layout* p) {
+  if (!p) fail(FENC_EINVAL, "null layout");
+  Layout L;
+  L.kind = p->kind; L.bs = p->bs; L.c = p->c; L.h = p->h; L.w = p->w; L.M = p->M; L.S = p->S; L.m = p->m;
+  L.bsg = p->bs_g; L.cpc = p->chan_per_ct; L.nbg = p->n_bg; L.ncg = p->n_cg; L.rep = p->replicate; L.dil = p->dil;
+  L.level = p->level; L.d = p->d; L.nfeat = p->n_feat; L.scale = p->scale;
+  if (L.level < 0 || L.level > C.L) fail(FENC_EINVAL, "layout level out of range");
+  if (L.bsg < 1 || L.nbg < 1) fail(FENC_EINVAL, "bad layout batch fields");
+  if (L.kind == FENC_LAYOUT_VECTOR) {
+    if (L.d * L.bsg != C.ns || L.nfeat < 1 || L.nfeat > L.d) fail(FENC_EINVAL, "bad vector layout");
+    if (p->map_id == 0) {
+      L.pos.resize(L.nfeat);
+      for (int i = 0; i < L.nfeat; i++) L.pos[i] = i;
+    } else {
+      auto it = C.maps.find(p->map_id);
+      if (it == C.maps.end()) fail(FENC_EINVAL, "unknown feature map");
+      L.pos = it->second;
+    }
+  } else if (L.kind == FENC_LAYOUT_FRAGMENT) {
+    if (L.S < 1 || L.m < 1 || (long long)L.m * L.m * L.bsg * L.cpc > C.ns || L.ncg < 1) fail(FENC_EINVAL, "bad fragment layout");
+  } else {
+    fail(FENC_EINVAL, "unknown layout kind");
+  }
+  return L;
+}
+
+static fenc_layout to_pub(Ctx& C, const Layout& L) {
+  fenc_layout p{};
+  p.kind = L.kind; p.bs = L.bs; p.c = L.c; p.h = L.h; p.w = L.w; p.M = L.M; p.S = L.S; p.m = L.m;
+  p.bs_g = L.bsg; p.chan_per_ct = L.cpc; p.n_bg = L.nbg; p.n_cg = L.ncg; p.replicate = L.rep; p.dil = L.dil;
+  p.level = L.level; p.d = L.d; p.n_feat = L.nfeat; p.scale = L.scale; p.map_id = 0;
+  if (L.kind == FENC_LAYOUT_VECTOR) {
+    bool ident = true;
+    for (int i = 0; i < L.nfeat; i++) ident &= (L.pos[i] == i);
+    if (!ident) {
+      uint64_t id = fnv(L.pos.data(), L.pos.size() * sizeof(int)) | 1;
+      C.maps[id] = L.pos;
+      p.map_id = id;
+    }
+  }
+  return p;
+}
+
+static std::string layout_key(const Layout& L) {
+  std::ostringstream o;
+  o << L.kind << ',' << L.bs << ',' << L.c << ',' << L.h << ',' << L.w << ',' << L.M << ',' << L.S << ',' << L.m << ','
+    << L.bsg << ',' << L.cpc << ',' << L.nbg << ',' << L.ncg << ',' << L.rep << ',' << L.dil << ',' << L.level << ','
+    << L.d << ',' << L.nfeat << ',';
+  o.precision(17);
+  o << L.scale << ',' << (L.pos.empty() ? 0 : fnv(L.pos.data(), L.pos.size() * sizeof(int)));
+  return o.str();
+}
+
+static void check_batch(const Ctx& C, const fenc_ctbatch* b, bool need_data) {
+  if (!b) fail(FENC_EINVAL, "null ciphertext batch");
+  if (need_data && !b->data) fail(FENC_EINVAL, "null ciphertext data");
+}
+
+// ---------------------------------------------------------------- hoisted rotation stage
+// copies[c] = Rot(in[src_c], shift_c); ModUp of each source once
+struct RotStage {
+  std::vector<int> src;   // ModUp'ed input cts (sorted)
+  KsStage ks;
+  int n = 0;
+};
+
+static RotStage make_rot_stage(Ctx& C, const std::vector<std::pair<int, long long>>& copies,
+                               std::vector<void*>& owner) {
+  RotStage R;
+  R.n = (int)copies.size();
+  std::map<int, int> pos;
+  for (auto& c : copies) pos[c.first] = 0;
+  for (auto& kv : pos) {
+    kv.second = (int)R.src.size();
+    R.src.push_back(kv.first);
+  }
+  std::vector<std::vector<fk::KipItem>> items;
+  std::vector<fk::TailItem> tails;
+  std::vector<fk::AddTerm> terms;
+  for (int i = 0; i < R.n; i++) {
+    const unsigned g = (unsigned)galois(C, copies[i].second);
+    items.push_back({fk::KipItem{pos[copies[i].first], g, get_key(C, g)}});
+    tails.push_back(fk::TailItem{i, -1, (int)terms.size(), 1});
+    terms.push_back(fk::AddTerm{copies[i].first, g});
+  }
+  R.ks = make_ks(C, items, tails, terms, owner);
+  return R;
+}
+
+// ModUp of the listed cts (contiguous runs), then KIP/ModDown into out
+static void run_rot_stage(Ctx& C, int level, const RotStage& R, const u64* in, u64* out, fb::Stream s) {
+  if (R.n == 0) return;
+  const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
+  const long long ce = ct_elems(C, level), ee = (long long)beta * le * C.N;
+  Scope sc(C.arena);
+  u64* ext = (u64*)C.arena.get((size_t)R.src.size() * ee * 8, s);
+  for (size_t i = 0; i < R.src.size();) {
+    size_t j = i;
+    while (j + 1 < R.src.size() && R.src[j + 1] == R.src[j] + 1) j++;
+    modup(C, level, in + R.src[i] * ce, ce, (long long)nl * C.N, (int)(j - i + 1), ext + (long long)i * ee, s);
+    i = j + 1;
+  }
+  kip_moddown(C, level, ext, R.ks, out, ce, nullptr, 0, in, ce, s);
+}
+
+// lazy sum stage: out[o] = base[o] + sum_r Rot(z[idx], shift), one ModDown per output
+struct SumStage {
+  KsStage ks;
+  int nz = 0;
+};
+
+static SumStage make_sum_stage(Ctx& C, const std::vector<int>& out_idx, const std::vector<int>& base_idx,
+                               const std::vector<std::vector<std::pair<int, long long>>>& terms_of,
+                               std::vector<void*>& owner, int nz) {
+  SumStage S;
+  S.nz = nz;
+  std::vector<std::vector<fk::KipItem>> items;
+  std::vector<fk::TailItem> tails;
+  std::vector<fk::AddTerm> terms;
+  for (size_t o = 0; o < out_idx.size(); o++) {
+    std::vector<fk::KipItem> it;
+    const int off = (int)terms.size();
+    for (auto& t : terms_of[o]) {
+      const unsigned g = (unsigned)galois(C, t.second);
+      it.push_back(fk::KipItem{t.first, g, get_key(C, g)});
+      terms.push_back(fk::AddTerm{t.first, g});
+    }
+    items.push_back(it);
+    tails.push_back(fk::TailItem{out_idx[o], base_idx[o], off, (int)terms_of[o].size()});
+  }
+  S.ks = make_ks(C, items, tails, terms, owner);
+  return S;
+}
+
+static void run_sum_stage(Ctx& C, int level, const SumStage& S, const u64* z, u64* out, const u64* base,
+                          fb::Stream s) {
+  if (S.ks.n_out == 0) return;
+  const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
+  const long long ce = ct_elems(C, level);
+  Scope sc(C.arena);
+  u64* ext = (u64*)C.arena.get((size_t)S.nz * beta * le * C.N * 8, s);
+  modup(C, level, z, ce, (long long)nl * C.N, S.nz, ext, s);
+  kip_moddown(C, level, ext, S.ks, out, ce, base, ce, z, ce, s);
+}
+
+// ---------------------------------------------------------------- conv2d
+struct ConvPlan : Plan {
+  int level = 0, n_in = 0, n_out = 0, n_zr = 0;
+  RotStage rot;
+  GmacStage g0, gr;
+  SumStage sum;
+  long long n_terms = 0, n_masked = 0;
+};
+
+static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout, int k, int stride, int pad,
+                            int groups, bool shape_only, Layout& Lout) {
+  if (Lin.kind != FENC_LAYOUT_FRAGMENT || Lin.dil != 1) fail(FENC_ELAYOUT, "conv2d needs a dense fragment layout");
+  if (k < 1 || stride < 1 || pad < 0 || cout < 1) fail(FENC_EINVAL, "bad convolution shape");
+  if (Lin.S % stride) fail(FENC_EUNSUPPORTED, "stride must divide the block size");
+  const int cin = Lin.c;
+  if (groups < 1 || cin % groups || cout % groups) fail(FENC_EINVAL, "groups must divide both channel counts");
+  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the convolution");
+  const int S = Lin.S, m = Lin.m, bsg = Lin.bsg, cpc = Lin.cpc, lvl = Lin.level;
+  const int gin = cin / groups, gout = cout / groups;
+  Lout = Lin;
+  Lout.c = cout;
+  Lout.h = (Lin.h + 2 * pad - k) / stride + 1;
+  Lout.w = (Lin.w + 2 * pad - k) / stride + 1;
+  if (Lout.h < 1 || Lout.w < 1) fail(FENC_EINVAL, "kernel larger than the padded input");
+  Lout.M = Lin.M / stride;
+  Lout.S = S / stride;
+  Lout.rep = 0;
+  Lout.ncg = (cout + cpc - 1) / cpc;
+  Lout.level = lvl - 1;
+  Lout.scale = C.Delta;
+  if (shape_only) return nullptr;
+
+  auto P = new ConvPlan;
+  P->out = Lout;
+  P->level = lvl;
+  P->n_in = Lin.n_ct();
+  const int nd = Lin.rep ? cin : cpc;
+  const bool need_mask = (cpc > 1) || (pad > 0);
+  const double T = ((double)C.primes[lvl] * C.Delta) / Lin.scale;
+  double dw = T, dm = 1.0;
+  if (need_mask) split_scale(T, dw, dm);
+  const int npos = need_mask ? cpc : 1;
+  auto in_channel = [&](int gi, int q) { return Lin.rep ? q % cin : gi * cpc + q; };
+  auto pair_ok = [&](int ch, int o) { return ch < cin && o < cout && ch / gin == o / gout; };
+  auto term_active = [&](int go, int gi) {
+    for (int q = 0; q < npos; q++)
+      for (int r = 0; r < nd; r++)
+        if (pair_ok(in_channel(gi, q), go * cpc + posmod(q - r, cpc))) return true;
+    return false;
+  };
+  struct Term { int idx; long long shift; int u, v, dbi, dbj, di, dj, gi; };
+  const int So = Lout.S, ncg_out = Lout.ncg;
+  P->n_out = Lout.n_ct();
+  std::vector<std::vector<Term>> terms(P->n_out);
+  std::map<std::pair<int, long long>, int> copy_id;
+  for (int bg = 0; bg < Lin.nbg; bg++)
+    for (int go = 0; go < ncg_out; go++)
+      for (int uo = 0; uo < So; uo++)
+        for (int vo = 0; vo < So; vo++) {
+          const int oct = ((bg * ncg_out + go) * So + uo) * So + vo;
+          for (int gi = 0; gi < Lin.ncg; gi++) {
+            if (!term_active(go, gi)) continue;
+            for (int di = 0; di < k; di++)
+              for (int dj = 0; dj < k; dj++) {
+                const int a = uo * stride + di - pad, b = vo * stride + dj - pad;
+                Term t;
+                t.u = posmod(a, S); t.dbi = floordiv(a, S);
+                t.v = posmod(b, S); t.dbj = floordiv(b, S);
+                t.di = di; t.dj = dj; t.gi = gi;
+                t.idx = ((bg * Lin.ncg + gi) * S + t.u) * S + t.v;
+                t.shift = posmod(((long long)t.dbi * m + t.dbj) * bsg, C.ns);
+                terms[oct].push_back(t);
+                if (t.shift) copy_id[{t.idx, t.shift}] = 0;
+              }
+          }
+        }
+  std::vector<std::pair<int, long long>> copies;
+  for (auto& kv : copy_id) {
+    kv.second = (int)copies.size();
+    copies.push_back(kv.first);
+  }
+  P->rot = make_rot_stage(C, copies, P->owned);
+
+  // Plaintext form: with masks, either one full-scale plaintext per (output,
+  // diagonal, term) holding the weight of every position ("materialised"),
+  // or a mask per (term class, position) times scalar weight codes.
+  long long n_pt = 0;
+  for (int oct = 0; oct < P->n_out; oct++) {
+    const int go = (oct / (So * So)) % ncg_out;
+    for (const Term& t : terms[oct])
+      for (int r = 0; r < nd; r++) {
+        bool any = false;
+        for (int q = 0; q < npos; q++) any = any || pair_ok(in_channel(t.gi, q), go * cpc + posmod(q - r, cpc));
+        n_pt += any;
+      }
+  }
+  const bool materialise = need_mask && n_pt * (lvl + 1) * (long long)C.N * 8 <= C.pt_budget;
+  auto valid_src = [&](const Term& t, int bi, int bj) {
+    const int gy = (bi + t.dbi) * S + t.u, gx = (bj + t.dbj) * S + t.v;
+    return gy >= 0 && gy < Lin.h && gx >= 0 && gx < Lin.w;
+  };
+  // masks: source pixel inside the logical input, at channel position q
+  std::map<std::vector<int>, int> mask_id;
+  std::vector<std::vector<double>> mask_slots;
+  auto mask_of = [&](const Term& t, int q) {
+    std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q};
+    auto it = mask_id.find(key);
+    if (it != mask_id.end()) return it->second;
+    std::vector<double> z(C.ns, 0.0);
+    for (int bi = 0; bi < m; bi++)
+      for (int bj = 0; bj < m; bj++) {
+        if (!valid_src(t, bi, bj)) continue;
+        for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = 1.0;
+      }
+    mask_slots.push_back(z);
+    return mask_id[key] = (int)mask_slots.size() - 1;
+  };
+  std::map<int64_t, int> wid;
+  std::vector<int64_t> codes;
+  auto weight_id = [&](int64_t code) {
+    auto it = wid.find(code);
+    if (it != wid.end()) return it->second;
+    codes.push_back(code);
+    return wid[code] = (int)codes.size() - 1;
+  };
+  auto wval = [&](int o, int ch, const Term& t) {
+    const int grp = o / gout;
+    return w[(((long long)o * gin + (ch - grp * gin)) * k + t.di) * k + t.dj];
+  };
+  // groups[o][r]: plaintext id -> terms (input id, weight id); plaintext ids index
+  // mask_slots (mask-basis) or diag_slots (materialised, one term per group)
+  typedef std::map<int, std::vector<std::pair<int, int>>> Groups;
+  std::vector<std::vector<Groups>> G(P->n_out, std::vector<Groups>(nd));
+  std::vector<std::vector<char>> act(P->n_out, std::vector<char>(nd, 0));
+  std::vector<std::vector<double>> diag_slots;
+  for (int oct = 0; oct < P->n_out; oct++) {
+    const int go = (oct / (So * So)) % ncg_out;
+    for (const Term& t : terms[oct]) {
+      const int in_id = t.shift ? P->n_in + copy_id[{t.idx, t.shift}] : t.idx;
+      if (materialise) {
+        for (int r = 0; r < nd; r++) {
+          std::vector<double> z;
+          for (int q = 0; q < npos; q++) {
+            const int ch = in_channel(t.gi, q), o = go * cpc + posmod(q - r, cpc);
+            if (!pair_ok(ch, o)) continue;
+            if (z.empty()) z.assign(C.ns, 0.0);
+            const double wv = wval(o, ch, t);
+            for (int bi = 0; bi < m; bi++)
+              for (int bj = 0; bj < m; bj++) {
+                if (!valid_src(t, bi, bj)) continue;
+                for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = wv;
+              }
+          }
+          if (z.empty()) continue;
+          act[oct][r] = 1;
+          G[oct][r][(int)diag_slots.size()].push_back({in_id, -1});
+          diag_slots.push_back(std::move(z));
+          P->n_terms++;
+        }
+        continue;
+      }
+      for (int q = 0; q < npos; q++) {
+        const int ch = in_channel(t.gi, q);
+        for (int r = 0; r < nd; r++) {
+          const int o = go * cpc + posmod(q - r, cpc);
+          if (!pair_ok(ch, o)) continue;
+          act[oct][r] = 1;
+          const int64_t code = weight_code(wval(o, ch, t), dw);
+          if (code == 0) continue;
+          const int mid = need_mask ? mask_of(t, q) : -1;
+          G[oct][r][mid].push_back({in_id, weight_id(code)});
+          P->n_terms++;
+        }
+      }
+    }
+  }
+  const u64* masks = materialise ? (diag_slots.empty() ? nullptr : encode_plaintexts(C, diag_slots, T, lvl, P->owned))
+                                 : (mask_slots.empty() ? nullptr : encode_plaintexts(C, mask_slots, dm, lvl, P->owned));
+  const long long pe = (long long)(lvl + 1) * C.N;
+  GmacBuild b0, br;
+  std::vector<int> sum_out, sum_base;
+  std::vector<std::vector<std::pair<int, long long>>> sum_terms;
+  auto emit = [&](GmacBuild& gb, const Groups& gr) {
+    for (auto& kv : gr) {
+      gb.add_group(kv.first < 0 ? nullptr : masks + kv.first * pe);
+      if (kv.first >= 0) P->n_masked++;
+      for (auto& t : kv.second) gb.add_term(t.first, t.second);
+      gb.end_group();
+    }
+    gb.end_output();
+  };
+  for (int o = 0; o < P->n_out; o++) {
+    emit(b0, G[o][0]);
+    std::vector<std::pair<int, long long>> tl;
+    for (int r = 1; r < nd; r++)
+      if (act[o][r]) {
+        emit(br, G[o][r]);
+        tl.push_back({P->n_zr++, (long long)r * m * m * bsg});
+      }
+    if (!tl.empty()) {
+      sum_out.push_back(o);
+      sum_base.push_back(o);
+      sum_terms.push_back(tl);
+    }
+  }
+  P->g0 = make_gmac(C, b0, codes, lvl, P->owned);
+  P->gr = make_gmac(C, br, codes, lvl, P->owned);
+  P->sum = make_sum_stage(C, sum_out, sum_base, sum_terms, P->owned, P->n_zr);
+  return P;
+}
+
+static void run_conv(Ctx& C, const ConvPlan& P, const u64* in, u64* out, fb::Stream s) {
+  const int lvl = P.level, nl = lvl + 1;
+  const long long ce = ct_elems(C, lvl), ps = (long long)nl * C.N;
+  Scope sc(C.arena);
+  u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
+  u64* y = (u64*)C.arena.get((size_t)P.n_out * ce * 8, s);
+  u64* zr = (u64*)C.arena.get((size_t)std::max(1, P.n_zr) * ce * 8, s);
+  run_rot_stage(C, lvl, P.rot, in, copies, s);
+  run_gmac(C, nl, P.g0, in, ce, P.n_in, copies, ce, ps, y, ce, ps, s);
+  run_gmac(C, nl, P.gr, in, ce, P.n_in, copies, ce, ps, zr, ce, ps, s);
+  run_sum_stage(C, lvl, P.sum, zr, y, y, s);
+  rescale(C, lvl, y, P.n_out, out, s);
+  C.cnt.rot_inner += P.rot.n;
+  C.cnt.rot_outer += P.n_zr;
+  C.cnt.keyswitch += P.rot.n + P.n_zr;
+  C.cnt.smult += P.n_terms;
+  C.cnt.pmult += P.n_masked;
+  C.cnt.cts_out += P.n_out;
+}
+
+// ---------------------------------------------------------------- avgpool
+struct PoolPlan : Plan {
+  int level = 0, n_in = 0, n_out = 0;
+  RotStage rot;
+  GmacStage g;
+};
+
+static PoolPlan* build_pool(Ctx& C, const Layout& Lin, bool shape_only, Layout& Lout) {
+  if (Lin.kind != FENC_LAYOUT_FRAGMENT) fail(FENC_ELAYOUT, "avgpool needs a fragment layout");
+  Lout = Lin;
+  Lout.h = Lin.h / 2;
+  Lout.w = Lin.w / 2;
+  if (Lout.h < 1 || Lout.w < 1) fail(FENC_EINVAL, "input too small to pool");
+  Lout.scale = Lin.scale * 4.0;
+  if (Lin.S >= 2) {
+    if (Lin.dil != 1) fail(FENC_ELAYOUT, "dilated layouts pool at S = 1 only");
+    Lout.S = Lin.S / 2;
+    Lout.M = Lin.M / 2;
+  } else {
+    Lout.dil = Lin.dil * 2;
+  }
+  if (shape_only) return nullptr;
+  auto P = new PoolPlan;
+  P->out = Lout;
+  P->level = Lin.level;
+  P->n_in = Lin.n_ct();
+  P->n_out = Lout.n_ct();
+  GmacBuild gb;
+  if (Lin.S >= 2) {
+    const int S = Lin.S, So = S / 2;
+    for (int g = 0; g < Lin.nbg * Lin.ncg; g++)
+      for (int uo = 0; uo < So; uo++)
+        for (int vo = 0; vo < So; vo++) {
+          gb.add_group(nullptr);
+          for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) gb.add_term((g * S + 2 * uo + a) * S + 2 * vo + b, -1);
+          gb.end_group();
+          gb.end_output();
+        }
+  } else {
+    const long long d = Lin.dil, m = Lin.m, bsg = Lin.bsg;
+    const long long sh[3] = {d * bsg, d * m * bsg, (d * m + d) * bsg};
+    std::vector<std::pair<int, long long>> copies;
+    for (int t = 0; t < P->n_in; t++)
+      for (int i = 0; i < 3; i++) copies.push_back({t, sh[i] % C.ns});
+    P->rot = make_rot_stage(C, copies, P->owned);
+    for (int t = 0; t < P->n_in; t++) {
+      gb.add_group(nullptr);
+      gb.add_term(t, -1);
+      for (int i = 0; i < 3; i++) gb.add_term(P->n_in + 3 * t + i, -1);
+      gb.end_group();
+      gb.end_output();
+    }
+  }
+  P->g = make_gmac(C, gb, {}, Lin.level, P->owned);
+  return P;
+}
+
+static void run_pool(Ctx& C, const PoolPlan& P, const u64* in, u64* out, fb::Stream s) {
+  const int nl = P.level + 1;
+  const long long ce = ct_elems(C, P.level), ps = (long long)nl * C.N;
+  Scope sc(C.arena);
+  u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
+  run_rot_stage(C, P.level, P.rot, in, copies, s);
+  run_gmac(C, nl, P.g, in, ce, P.n_in, copies, ce, ps, out, ce, ps, s);
+  C.cnt.rot_other += P.rot.n;
+  C.cnt.keyswitch += P.rot.n;
+  C.cnt.cts_out += P.n_out;
+}
+
+// ---------------------------------------------------------------- x^2 activation
+struct SquarePlan : Plan {
+  int level = 0, n = 0;
+  KsStage ks;
+};
+
+static void run_square(Ctx& C, const SquarePlan& P, const u64* in, u64* out, fb::Stream s) {
+  const int lvl = P.level, nl = lvl + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
+  const long long ce = ct_elems(C, lvl);
+  Scope sc(C.arena);
+  u64* t = (u64*)C.arena.get((size_t)P.n * ce * 8, s);
+  u64* d2b = (u64*)C.arena.get((size_t)P.n * nl * C.N * 8, s);
+  u64* ext = (u64*)C.arena.get((size_t)P.n * beta * le * C.N * 8, s);
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  for (int b0 = 0; b0 < P.n; b0 += per_op ? 1 : P.n) {
+    const int nb = per_op ? 1 : P.n;
+    fk::SquareArgs a{in + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, C.pq};
+    timed(C, "tensor_square", 5.0 * nb * nl * C.N * 8, s, [&] {
+      fb::tensor_square({(unsigned)std::max(1, C.N / 256), (unsigned)nl, (unsigned)nb}, std::min(256, C.N), s, a);
+    });
+    C.cnt.launches++;
+  }
+  modup(C, lvl, d2b, (long long)nl * C.N, 0, P.n, ext, s);
+  kip_moddown(C, lvl, ext, P.ks, t, ce, t, ce, nullptr, 0, s);
+  rescale(C, lvl, t, P.n, out, s);
+  C.cnt.relin += P.n;
+  C.cnt.keyswitch += P.n;
+  C.cnt.cts_out += P.n;
+}
+
+// ---------------------------------------------------------------- compress (AAC)
+struct CompressPlan : Plan {
+  int level = 0, n_in = 0, n_out = 0, n_zr = 0;
+  GmacStage g0, gr;
+  SumStage sum;
+};
+
+static CompressPlan* build_compress(Ctx& C, const Layout& Lin, bool shape_only, Layout& Lout) {
+  if (Lin.kind != FENC_LAYOUT_FRAGMENT) fail(FENC_ELAYOUT, "compress packs fragment layouts");
+  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the compression mask");
+  const int bsg = Lin.bsg, d = C.ns / bsg, per_bg = Lin.ncg * Lin.S * Lin.S;
+  std::vector<std::set<int>> Pset(per_bg);
+  std::vector<std::pair<int, int>> sl;
+  for (int ch = 0; ch < Lin.c; ch++)
+    for (int y = 0; y < Lin.h; y++)
+      for (int x = 0; x < Lin.w; x++) {
+        layout_slots(Lin, 0, ch, y, x, sl);
+        Pset[sl[0].first].insert(sl[0].second / bsg);
+      }
+  std::vector<char> occ(d, 0);
+  std::vector<int> phi(per_bg, 0);
+  for (int t = 0; t < per_bg; t++) {
+    if (Pset[t].empty()) continue;
+    int f = 0;
+    for (;; f++) {
+      if (*Pset[t].rbegin() + f >= d) fail(FENC_EUNSUPPORTED, "compressed tensor does not fit one ciphertext");
+      bool ok = true;
+      for (int p : Pset[t]) ok = ok && !occ[p + f];
+      if (ok) break;
+    }
+    phi[t] = f;
+    for (int p : Pset[t]) occ[p + f] = 1;
+  }
+  Lout = Layout();
+  Lout.kind = FENC_LAYOUT_VECTOR;
+  Lout.bs = Lin.bs; Lout.c = Lin.c; Lout.h = Lin.h; Lout.w = Lin.w;
+  Lout.bsg = bsg; Lout.nbg = Lin.nbg; Lout.cpc = 1; Lout.ncg = 1; Lout.S = 1; Lout.m = 1; Lout.M = 1;
+  Lout.d = d;
+  Lout.nfeat = Lin.c * Lin.h * Lin.w;
+  Lout.pos.resize(Lout.nfeat);
+  for (int ch = 0; ch < Lin.c; ch++)
+    for (int y = 0; y < Lin.h; y++)
+      for (int x = 0; x < Lin.w; x++) {
+        layout_slots(Lin, 0, ch, y, x, sl);
+        Lout.pos[(ch * Lin.h + y) * Lin.w + x] = sl[0].second / bsg + phi[sl[0].first];
+      }
+  Lout.level = Lin.level - 1;
+  Lout.scale = C.Delta;
+  if (shape_only) return nullptr;
+  auto P = new CompressPlan;
+  P->out = Lout;
+  P->level = Lin.level;
+  P->n_in = Lin.n_ct();
+  P->n_out = Lout.n_ct();
+  const double dm = ((double)C.primes[Lin.level] * C.Delta) / Lin.scale;
+  std::vector<std::vector<double>> ms;
+  std::vector<int> mid(per_bg, -1);
+  for (int t = 0; t < per_bg; t++) {
+    if (Pset[t].empty()) continue;
+    std::vector<double> z(C.ns, 0.0);
+    for (int p : Pset[t])
+      for (int jb = 0; jb < bsg; jb++) z[p * bsg + jb] = 1.0;
+    mid[t] = (int)ms.size();
+    ms.push_back(z);
+  }
+  const u64* masks = encode_plaintexts(C, ms, dm, Lin.level, P->owned);
+  const long long pe = (long long)(Lin.level + 1) * C.N;
+  GmacBuild b0, br;
+  std::vector<int> so, sb;
+  std::vector<std::vector<std::pair<int, long long>>> st;
+  for (int bg = 0; bg < Lin.nbg; bg++) {
+    std::vector<std::pair<int, long long>> tl;
+    for (int t = 0; t < per_bg; t++) {
+      if (mid[t] < 0 || phi[t] != 0) continue;
+      b0.add_group(masks + mid[t] * pe);
+      b0.add_term(bg * per_bg + t, -1);
+      b0.end_group();
+    }
+    b0.end_output();
+    for (int t = 0; t < per_bg; t++) {
+      if (mid[t] < 0 || phi[t] == 0) continue;
+      br.add_group(masks + mid[t] * pe);
+      br.add_term(bg * per_bg + t, -1);
+      br.end_group();
+      br.end_output();
+      tl.push_back({P->n_zr++, posmod(-(long long)phi[t] * bsg, C.ns)});
+    }
+    if (!tl.empty()) {
+      so.push_back(bg);
+      sb.push_back(bg);
+      st.push_back(tl);
+    }
+  }
+  P->g0 = make_gmac(C, b0, {}, Lin.level, P->owned);
+  P->gr = make_gmac(C, br, {}, Lin.level, P->owned);
+  P->sum = make_sum_stage(C, so, sb, st, P->owned, P->n_zr);
+  return P;
+}
+
+static void run_compress(Ctx& C, const CompressPlan& P, const u64* in, u64* out, fb::Stream s) {
+  const int lvl = P.level, nl = lvl + 1;
+  const long long ce = ct_elems(C, lvl), ps = (long long)nl * C.N;
+  Scope sc(C.arena);
+  u64* y = (u64*)C.arena.get((size_t)P.n_out * ce * 8, s);
+  u64* zr = (u64*)C.arena.get((size_t)std::max(1, P.n_zr) * ce * 8, s);
+  run_gmac(C, nl, P.g0, in, ce, P.n_in, nullptr, 0, ps, y, ce, ps, s);
+  run_gmac(C, nl, P.gr, in, ce, P.n_in, nullptr, 0, ps, zr, ce, ps, s);
+  run_sum_stage(C, lvl, P.sum, zr, y, y, s);
+  rescale(C, lvl, y, P.n_out, out, s);
+  C.cnt.rot_other += P.n_zr;
+  C.cnt.keyswitch += P.n_zr;
+  C.cnt.pmult += P.n_in;
+  C.cnt.cts_out += P.n_out;
+}
+
+// ---------------------------------------------------------------- fc (diagonal BSGS)
+struct FcPlan : Plan {
+  int level = 0, n_in = 0, n_out = 0, n_zr = 0;
+  RotStage rot;
+  GmacStage g0, gr;
+  SumStage sum;
+};
+
+static FcPlan* build_fc(Ctx& C, const Layout& Lin, const double* W, int dout, bool shape_only, Layout& Lout) {
+  if (Lin.kind != FENC_LAYOUT_VECTOR) fail(FENC_ELAYOUT, "fc needs a vector layout");
+  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the fc layer");
+  const int d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level;
+  if (dout < 1 || dout > d) fail(FENC_EINVAL, "fc output larger than the vector");
+  Lout = Layout();
+  Lout.kind = FENC_LAYOUT_VECTOR;
+  Lout.bs = Lin.bs; Lout.c = dout; Lout.h = 1; Lout.w = 1;
+  Lout.bsg = bsg; Lout.nbg = Lin.nbg; Lout.cpc = 1; Lout.ncg = 1; Lout.S = 1; Lout.m = 1; Lout.M = 1;
+  Lout.d = d;
+  Lout.nfeat = dout;
+  Lout.pos.resize(dout);
+  for (int i = 0; i < dout; i++) Lout.pos[i] = i;
+  Lout.level = lvl - 1;
+  Lout.scale = C.Delta;
+  if (shape_only) return nullptr;
+  int e = 0;
+  while ((1 << e) < d) e++;
+  const int n1 = 1 << ((e + 1) / 2), n2 = d / n1;
+  std::vector<double> Wp((size_t)d * d, 0.0);
+  std::vector<char> colused(d, 0);
+  for (int f = 0; f < din; f++) colused[Lin.pos[f]] = 1;
+  for (int i = 0; i < dout; i++)
+    for (int f = 0; f < din; f++) Wp[(size_t)i * d + Lin.pos[f]] = W[(size_t)i * din + f];
+  auto diag_active = [&](int kd) {
+    for (int i = 0; i < dout; i++)
+      if (colused[(i + kd) % d]) return true;
+    return false;
+  };
+  auto P = new FcPlan;
+  P->out = Lout;
+  P->level = lvl;
+  P->n_in = Lin.n_ct();
+  P->n_out = Lout.n_ct();
+  std::vector<char> baby(n1, 0), giant(n2, 0);
+  for (int g = 0; g < n2; g++)
+    for (int b = 0; b < n1; b++)
+      if (diag_active(g * n1 + b)) baby[b] = giant[g] = 1;
+  const double dp = ((double)C.primes[lvl] * C.Delta) / Lin.scale;
+  std::vector<std::vector<double>> slots;
+  std::vector<int> pid((size_t)n1 * n2, -1);
+  for (int g = 0; g < n2; g++)
+    for (int b = 0; b < n1; b++) {
+      const int kd = g * n1 + b;
+      if (!diag_active(kd)) continue;
+      std::vector<double> z(C.ns);
+      for (int l = 0; l < C.ns; l++) {
+        const int i = posmod((long long)l - (long long)g * n1 * bsg, C.ns) / bsg;
+        z[l] = Wp[(size_t)i * d + (i + kd) % d];
+      }
+      pid[(size_t)g * n1 + b] = (int)slots.size();
+      slots.push_back(std::move(z));
+    }
+  const u64* pts = encode_plaintexts(C, slots, dp, lvl, P->owned);
+  const long long pe = (long long)(lvl + 1) * C.N;
+  std::vector<std::pair<int, long long>> copies;
+  std::vector<int> bidx(n1, -1);
+  int nb = 0;
+  for (int b = 1; b < n1; b++)
+    if (baby[b]) bidx[b] = nb++;
+  for (int t = 0; t < P->n_in; t++)
+    for (int b = 1; b < n1; b++)
+      if (baby[b]) copies.push_back({t, (long long)b * bsg});
+  P->rot = make_rot_stage(C, copies, P->owned);
+  GmacBuild b0, br;
+  std::vector<int> so, sb;
+  std::vector<std::vector<std::pair<int, long long>>> st;
+  for (int t = 0; t < P->n_in; t++) {
+    auto in_id = [&](int b) { return b == 0 ? t : P->n_in + t * nb + bidx[b]; };
+    std::vector<std::pair<int, long long>> tl;
+    for (int g = 0; g < n2; g++) {
+      if (g > 0 && !giant[g]) continue;
+      GmacBuild& gb = g == 0 ? b0 : br;
+      for (int b = 0; b < n1; b++) {
+        const int id = pid[(size_t)g * n1 + b];
+        if (id < 0) continue;
+        gb.add_group(pts + id * pe);
+        gb.add_term(in_id(b), -1);
+        gb.end_group();
+      }
+      gb.end_output();
+      if (g > 0) tl.push_back({P->n_zr++, (long long)g * n1 * bsg});
+    }
+    if (!tl.empty()) {
+      so.push_back(t);
+      sb.push_back(t);
+      st.push_back(tl);
+    }
+  }
+  P->g0 = make_gmac(C, b0, {}, lvl, P->owned);
+  P->gr = make_gmac(C, br, {}, lvl, P->owned);
+  P->sum = make_sum_stage(C, so, sb, st, P->owned, P->n_zr);
+  return P;
+}
+
+static void run_fc(Ctx& C, const FcPlan& P, const u64* in, u64* out, fb::Stream s) {
+  const int lvl = P.level, nl = lvl + 1;
+  const long long ce = ct_elems(C, lvl), ps = (long long)nl * C.N;
+  Scope sc(C.arena);
+  u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
+  u64* y = (u64*)C.arena.get((size_t)P.n_out * ce * 8, s);
+  u64* zr = (u64*)C.arena.get((size_t)std::max(1, P.n_zr) * ce * 8, s);
+  run_rot_stage(C, lvl, P.rot, in, copies, s);
+  run_gmac(C, nl, P.g0, in, ce, P.n_in, copies, ce, ps, y, ce, ps, s);
+  run_gmac(C, nl, P.gr, in, ce, P.n_in, copies, ce, ps, zr, ce, ps, s);
+  run_sum_stage(C, lvl, P.sum, zr, y, y, s);
+  rescale(C, lvl, y, P.n_out, out, s);
+  C.cnt.rot_other += P.rot.n + P.n_zr;
+  C.cnt.keyswitch += P.rot.n + P.n_zr;
+  C.cnt.cts_out += P.n_out;
+}
+
+// ---------------------------------------------------------------- plan cache
+template <class T, class F>
+static T& cached(Ctx& C, const std::string& key, F build) {
+  auto it = C.plans.find(key);
+  if (it != C.plans.end()) return *(T*)it->second.get();
+  T* p = build();
+  C.plans[key].reset(p);
+  return *p;
+}
+
+// ================================================================ C ABI
+#define API_BEGIN try {
+#define API_END                                                  \
+  }                                                              \
+  catch (const fr::Error& e) {                                   \
+    g_err = e.what();                                            \
+    return e.code;                                               \
+  }                                                              \
+  catch (const std::exception& e) {                              \
+    g_err = e.what();                                            \
+    return strstr(e.what(), "out of memory") ? FENC_ENOMEM : FENC_EHIP; \
+  }                                                              \
+  return FENC_OK;
+
+extern "C" {
+
+const char* fenc_last_error(void) { return g_err.c_str(); }
+
+int fenc_ctx_create(const fenc_params* p, fenc_ctx** out) {
+  API_BEGIN
+  if (!p || !out) fail(FENC_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->log_n < 3 || p->log_n > 17) fail(FENC_EINVAL, "log_n must be in [3, 17]");
+  if (p->n_q < 2 || p->n_p < 1 || p->dnum < 1 || p->dnum > p->n_q) fail(FENC_EINVAL, "bad prime counts");
+  if (p->q_bits > 50 || p->q_bits < 20 || p->p_bits != p->q_bits) fail(FENC_EINVAL, "primes must share one bit size <= 50");
+  const int alpha = (p->n_q + p->dnum - 1) / p->dnum;
+  if ((int)p->n_p < alpha) fail(FENC_EINVAL, "need at least one special prime per digit limb");
+  if (alpha > 16 || p->n_p > 16) fail(FENC_EUNSUPPORTED, "digit or special-prime count above 16");
+  if (p->n_q + p->n_p > 100) fail(FENC_EUNSUPPORTED, "too many primes");
+  if (p->log2_scale < 1 || p->log2_scale >= p->q_bits) fail(FENC_EINVAL, "scale must be below the primes");
+  std::unique_ptr<fenc_ctx> C(new fenc_ctx);
+  C->prm = *p;
+  C->logn = p->log_n;
+  C->N = 1 << p->log_n;
+  C->ns = C->N / 2;
+  C->L = p->n_q - 1;
+  C->K = p->n_p;
+  C->alpha = alpha;
+  C->ndig = (p->n_q + alpha - 1) / alpha;
+  C->np = p->n_q + p->n_p;
+  C->Delta = std::ldexp(1.0, (int)p->log2_scale);
+  C->primes = fh::ntt_primes(p->q_bits, p->log_n, p->n_q, {});
+  auto ps = fh::ntt_primes(p->p_bits, p->log_n, p->n_p, C->primes);
+  C->primes.insert(C->primes.end(), ps.begin(), ps.end());
+  for (uint64_t q : C->primes) C->psi.push_back(fh::root_2n(q, p->log_n));
+  C->s.resize(C->N);
+  for (int i = 0; i < C->N; i++) C->s[i] = fh::draw_ternary(p->seed, fh::tag::secret, i);
+  *out = C.release();
+  API_END
+}
+
+void fenc_ctx_destroy(fenc_ctx* ctx) {
+  try {
+    delete ctx;
+  } catch (...) {
+  }
+}
+
+int fenc_ctx_primes(const fenc_ctx* ctx, uint64_t* out) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  for (size_t i = 0; i < ctx->primes.size(); i++) out[i] = ctx->primes[i];
+  API_END
+}
+
+int fenc_set_mode(fenc_ctx* ctx, int mode) {
+  API_BEGIN
+  if (!ctx || (mode != FENC_MODE_BATCHED && mode != FENC_MODE_PER_OP)) fail(FENC_EINVAL, "bad mode");
+  ctx->mode = mode;
+  API_END
+}
+
+int fenc_set_plaintext_budget(fenc_ctx* ctx, int64_t bytes) {
+  API_BEGIN
+  if (!ctx || bytes < 0) fail(FENC_EINVAL, "bad budget");
+  ctx->pt_budget = bytes;
+  API_END
+}
+
+int fenc_profile_kernel(fenc_ctx* ctx, const char* name) {
+  API_BEGIN
+  if (!ctx) fail(FENC_EINVAL, "null argument");
+  for (auto& r : ctx->prof) {
+    fb::event_destroy(r.a);
+    fb::event_destroy(r.b);
+  }
+  ctx->prof.clear();
+  ctx->prof_kernel = name ? name : "";
+  API_END
+}
+
+int fenc_profile_result(fenc_ctx* ctx, double* total_ms, int64_t* launches, double* bytes) {
+  API_BEGIN
+  if (!ctx || !total_ms || !launches || !bytes) fail(FENC_EINVAL, "null argument");
+  double ms = 0, b = 0;
+  for (auto& r : ctx->prof) {
+    ms += fb::event_elapsed_ms(r.a, r.b);
+    b += r.bytes;
+  }
+  *total_ms = ms;
+  *launches = (int64_t)ctx->prof.size();
+  *bytes = b;
+  API_END
+}
+
+int fenc_stats(const fenc_ctx* ctx, fenc_counters* out) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  *out = ctx->cnt;
+  API_END
+}
+
+void fenc_stats_reset(fenc_ctx* ctx) {
+  if (ctx) ctx->cnt = fenc_counters{};
+}
+
+int64_t fenc_device_bytes(const fenc_ctx* ctx) { return ctx ? ctx->dev_bytes + (int64_t)ctx->arena.bytes() : 0; }
+
+int fenc_keygen(fenc_ctx* ctx, const int32_t* rot_steps, uint32_t n_steps, int relin, int strict) {
+  API_BEGIN
+  if (!ctx || (n_steps && !rot_steps)) fail(FENC_EINVAL, "null argument");
+  ctx->strict = false;
+  ensure_device(*ctx);
+  for (uint32_t i = 0; i < n_steps; i++) {
+    const uint64_t g = galois(*ctx, rot_steps[i]);
+    if (g != 1) get_key(*ctx, g);
+  }
+  if (relin) get_key(*ctx, 0);
+  ctx->strict = strict != 0;
+  API_END
+}
+
+int fenc_key_export(fenc_ctx* ctx, int32_t shift, uint64_t* out) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  ensure_device(*ctx);
+  const uint64_t g = shift == INT32_MIN ? 0 : galois(*ctx, shift);
+  const uint64_t* key = get_key(*ctx, g);
+  const int np = ctx->np, nd = ctx->ndig, N = ctx->N;
+  std::vector<void*> tmp;
+  uint64_t* t = (uint64_t*)dalloc(*ctx, (size_t)nd * 2 * np * N * 8, tmp);
+  ntt(*ctx, true, key, t, (long long)np * N, (long long)np * N, nd * 2 * np, np, identity_map(np), nullptr);
+  fb::sync(nullptr);
+  fb::d2h(out, t, (size_t)nd * 2 * np * N * 8);
+  for (void* p : tmp) fb::dev_free(p);
+  API_END
+}
+
+int fenc_plan_layout(const fenc_ctx* ctx, uint32_t bs, uint32_t c, uint32_t h, uint32_t w, uint32_t k_next,
+                     uint32_t cout_next, int32_t s_override, fenc_layout* out) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  Layout L = plan_fragment(ctx->ns, ctx->L, ctx->Delta, bs, c, h, w, k_next, cout_next, s_override);
+  *out = to_pub(*(fenc_ctx*)ctx, L);
+  API_END
+}
+
+int fenc_layout_n_ct(const fenc_layout* lay) {
+  if (!lay) return FENC_EINVAL;
+  return lay->kind == FENC_LAYOUT_FRAGMENT ? lay->n_bg * lay->n_cg * lay->S * lay->S : lay->n_bg;
+}
+
+int64_t fenc_ct_bytes(const fenc_ctx* ctx, const fenc_layout* lay) {
+  if (!ctx || !lay) return FENC_EINVAL;
+  return (int64_t)fenc_layout_n_ct(lay) * 2 * (lay->level + 1) * ctx->N * 8;
+}
+
+int fenc_layout_slot(const fenc_ctx* ctx, const fenc_layout* lay, int b, int ch, int y, int x, int32_t* ct,
+                     int32_t* slot) {
+  API_BEGIN
+  if (!ctx || !ct || !slot) fail(FENC_EINVAL, "null argument");
+  Layout L = from_pub(*ctx, lay);
+  if (b < 0 || b >= L.bs || ch < 0 || ch >= L.c || y < 0 || y >= L.h || x < 0 || x >= L.w) fail(FENC_EINVAL, "element out of range");
+  std::vector<std::pair<int, int>> sl;
+  layout_slots(L, b, ch, y, x, sl);
+  *ct = sl[0].first;
+  *slot = sl[0].second;
+  API_END
+}
+
+int fenc_layout_map(const fenc_ctx* ctx, const fenc_layout* lay, int32_t* pos) {
+  API_BEGIN
+  if (!ctx || !pos) fail(FENC_EINVAL, "null argument");
+  Layout L = from_pub(*ctx, lay);
+  if (L.kind != FENC_LAYOUT_VECTOR) fail(FENC_ELAYOUT, "not a vector layout");
+  for (int i = 0; i < L.nfeat; i++) pos[i] = L.pos[i];
+  API_END
+}
+
+int fenc_encode_int(int32_t log_n, const double* z, double scale, int64_t* m) {
+  API_BEGIN
+  if (!z || !m || log_n < 2 || log_n > 17) fail(FENC_EINVAL, "bad argument");
+  fh::encode_real(log_n, z, scale, m);
+  API_END
+}
+
+uint64_t fenc_sample_word(uint64_t seed, uint64_t tag, uint64_t i) { return fh::stream_word(seed, tag, i); }
+int fenc_sample_gauss(uint64_t seed, uint64_t tag, uint64_t i) { return fh::draw_gauss(seed, tag, i); }
+
+int fenc_encode_slots(fenc_ctx* ctx, const double* z, int32_t level, double scale, uint64_t* pt) {
+  API_BEGIN
+  if (!ctx || !z || !pt || level < 0 || level > ctx->L) fail(FENC_EINVAL, "bad argument");
+  std::vector<int64_t> m(ctx->N);
+  fh::encode_real(ctx->logn, z, scale, m.data());
+  for (int i = 0; i <= level; i++) {
+    const int64_t q = (int64_t)ctx->primes[i];
+    for (int c = 0; c < ctx->N; c++) {
+      int64_t v = m[c] % q;
+      pt[(size_t)i * ctx->N + c] = (uint64_t)(v < 0 ? v + q : v);
+    }
+  }
+  API_END
+}
+
+int fenc_encode_fragment(fenc_ctx* ctx, const double* x, const fenc_layout* lay, uint64_t* pt) {
+  API_BEGIN
+  if (!ctx || !x || !pt) fail(FENC_EINVAL, "null argument");
+  Layout L = from_pub(*ctx, lay);
+  const int n = L.n_ct(), N = ctx->N;
+  std::vector<std::vector<double>> z(n, std::vector<double>(ctx->ns, 0.0));
+  std::vector<std::pair<int, int>> sl;
+  for (int b = 0; b < L.bs; b++)
+    for (int ch = 0; ch < L.c; ch++)
+      for (int y = 0; y < L.h; y++)
+        for (int xx = 0; xx < L.w; xx++) {
+          layout_slots(L, b, ch, y, xx, sl);
+          const double v = x[(((size_t)b * L.c + ch) * L.h + y) * L.w + xx];
+          for (auto& p : sl) z[p.first][p.second] = v;
+        }
+  const int nl = L.level + 1;
+  const int nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int wk = 0; wk < nthr; wk++)
+    th.emplace_back([&, wk] {
+      std::vector<int64_t> m(N);
+      for (int t = wk; t < n; t += nthr) {
+        fh::encode_real(ctx->logn, z[t].data(), L.scale, m.data());
+        for (int i = 0; i < nl; i++) {
+          const int64_t q = (int64_t)ctx->primes[i];
+          for (int c = 0; c < N; c++) {
+            int64_t v = m[c] % q;
+            pt[((size_t)t * nl + i) * N + c] = (uint64_t)(v < 0 ? v + q : v);
+          }
+        }
+      }
+    });
+  for (auto& t : th) t.join();
+  API_END
+}
+
+int fenc_encrypt(fenc_ctx* ctx, const uint64_t* pt, const fenc_layout* lay, uint64_t enc_seed, fenc_ctbatch* out,
+                 void* stream) {
+  API_BEGIN
+  if (!ctx || !pt || !out) fail(FENC_EINVAL, "null argument");
+  Layout L = from_pub(*ctx, lay);
+  out->lay = *lay;
+  if (!out->data) return FENC_OK;
+  fenc_ctx& C = *ctx;
+  ensure_device(C);
+  const int n = L.n_ct(), nl = L.level + 1, N = C.N;
+  std::vector<uint64_t> a((size_t)n * nl * N);
+  std::vector<long long> e((size_t)n * N);
+  const int nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int wk = 0; wk < nthr; wk++)
+    th.emplace_back([&, wk] {
+      for (int r = wk; r < n * nl; r += nthr) {
+        const int t = r / nl, i = r % nl;
+        for (int c = 0; c < N; c++) a[(size_t)r * N + c] = fh::draw_uniform(enc_seed, fh::tag::enc_a(t, i), c, C.primes[i]);
+      }
+      for (int t = wk; t < n; t += nthr)
+        for (int c = 0; c < N; c++) e[(size_t)t * N + c] = fh::draw_gauss(enc_seed, fh::tag::enc_e(t), c);
+    });
+  for (auto& t : th) t.join();
+  fb::Stream s = (fb::Stream)stream;
+  fb::sync(s);
+  std::vector<void*> tmp;
+  uint64_t* da = upload(C, a, tmp);
+  std::vector<uint64_t> ptv(pt, pt + (size_t)n * nl * N);
+  uint64_t* dm = upload(C, ptv, tmp);
+  long long* de = upload(C, e, tmp);
+  std::vector<unsigned char> pr(nl);
+  for (int i = 0; i < nl; i++) pr[i] = (unsigned char)i;
+  unsigned char* dp = upload(C, pr, tmp);
+  uint64_t* dE = (uint64_t*)dalloc(C, (size_t)n * nl * N * 8, tmp);
+  ntt(C, false, da, da, (long long)nl * N, (long long)nl * N, n * nl, nl, identity_map(nl), nullptr);
+  ntt(C, false, dm, dm, (long long)nl * N, (long long)nl * N, n * nl, nl, identity_map(nl), nullptr);
+  fk::SmallArgs sa{de, dE, nl, C.logn, dp, C.pq};
+  fb::small_to_rns({(unsigned)std::max(1, N / 256), (unsigned)(n * nl), 1}, std::min(256, N), nullptr, sa);
+  ntt(C, false, dE, dE, (long long)nl * N, (long long)nl * N, n * nl, nl, identity_map(nl), nullptr);
+  fk::EncArgs ea{da, dE, dm, C.s_ntt, out->data, nl, C.logn, C.pq};
+  fb::enc_combine({(unsigned)std::max(1, N / 256), (unsigned)(n * nl), 1}, std::min(256, N), nullptr, ea);
+  fb::sync(nullptr);
+  for (void* p : tmp) fb::dev_free(p);
+  API_END
+}
+
+static void decrypt_limbs(fenc_ctx& C, const fenc_ctbatch* in, std::vector<uint64_t>& m, int limbs, fb::Stream s) {
+  Layout L = from_pub(C, &in->lay);
+  ensure_device(C);
+  const int n = L.n_ct(), nl = L.level + 1, N = C.N;
+  fb::sync(s);
+  std::vector<void*> tmp;
+  uint64_t* dm = (uint64_t*)dalloc(C, (size_t)n * nl * N * 8, tmp);
+  fk::DecArgs da{in->data, C.s_ntt, dm, nl, C.logn, C.pq};
+  fb::dec_combine({(unsigned)std::max(1, N / 256), (unsigned)(n * nl), 1}, std::min(256, N), nullptr, da);
+  fk::PrimeMap pm = identity_map(nl);
+  for (int i = limbs; i < nl; i++) pm.p[i] = fk::kSkip;
+  ntt(C, true, dm, dm, (long long)nl * N, (long long)nl * N, n * nl, nl, pm, nullptr);
+  fb::sync(nullptr);
+  m.resize((size_t)n * nl * N);
+  fb::d2h(m.data(), dm, m.size() * 8);
+  for (void* p : tmp) fb::dev_free(p);
+}
+
+int fenc_decrypt_raw(fenc_ctx* ctx, const fenc_ctbatch* in, uint64_t* m, void* stream) {
+  API_BEGIN
+  if (!ctx || !m) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, true);
+  std::vector<uint64_t> v;
+  decrypt_limbs(*ctx, in, v, in->lay.level + 1, (fb::Stream)stream);
+  std::memcpy(m, v.data(), v.size() * 8);
+  API_END
+}
+
+int fenc_decrypt(fenc_ctx* ctx, const fenc_ctbatch* in, double* x, void* stream) {
+  API_BEGIN
+  if (!ctx || !x) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, true);
+  fenc_ctx& C = *ctx;
+  Layout L = from_pub(C, &in->lay);
+  std::vector<uint64_t> m;
+  decrypt_limbs(C, in, m, 1, (fb::Stream)stream);
+  const int n = L.n_ct(), nl = L.level + 1, N = C.N;
+  const uint64_t q0 = C.primes[0];
+  std::vector<std::vector<double>> z(n, std::vector<double>(C.ns));
+  std::vector<int64_t> mi(N);
+  for (int t = 0; t < n; t++) {
+    const uint64_t* r = &m[(size_t)t * nl * N];
+    for (int c = 0; c < N; c++) mi[c] = r[c] > (q0 - 1) / 2 ? (int64_t)r[c] - (int64_t)q0 : (int64_t)r[c];
+    fh::decode_real(C.logn, mi.data(), L.scale, z[t].data());
+  }
+  std::vector<std::pair<int, int>> sl;
+  for (int b = 0; b < L.bs; b++)
+    for (int ch = 0; ch < L.c; ch++)
+      for (int y = 0; y < L.h; y++)
+        for (int xx = 0; xx < L.w; xx++) {
+          layout_slots(L, b, ch, y, xx, sl);
+          x[(((size_t)b * L.c + ch) * L.h + y) * L.w + xx] = z[sl[0].first][sl[0].second];
+        }
+  API_END
+}
+
+int fenc_ct_export(fenc_ctx* ctx, const fenc_ctbatch* in, uint64_t* host, void* stream) {
+  API_BEGIN
+  if (!ctx || !host) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, true);
+  fenc_ctx& C = *ctx;
+  ensure_device(C);
+  Layout L = from_pub(C, &in->lay);
+  const int n = L.n_ct(), nl = L.level + 1, N = C.N;
+  fb::sync((fb::Stream)stream);
+  std::vector<void*> tmp;
+  uint64_t* t = (uint64_t*)dalloc(C, (size_t)n * 2 * nl * N * 8, tmp);
+  ntt(C, true, in->data, t, (long long)nl * N, (long long)nl * N, n * 2 * nl, nl, identity_map(nl), nullptr);
+  fb::sync(nullptr);
+  fb::d2h(host, t, (size_t)n * 2 * nl * N * 8);
+  for (void* p : tmp) fb::dev_free(p);
+  API_END
+}
+
+int fenc_ct_import(fenc_ctx* ctx, const uint64_t* host, fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !host) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, out, true);
+  fenc_ctx& C = *ctx;
+  ensure_device(C);
+  Layout L = from_pub(C, &out->lay);
+  const int n = L.n_ct(), nl = L.level + 1, N = C.N;
+  fb::sync((fb::Stream)stream);
+  fb::h2d(out->data, host, (size_t)n * 2 * nl * N * 8);
+  ntt(C, false, out->data, out->data, (long long)nl * N, (long long)nl * N, n * 2 * nl, nl, identity_map(nl), nullptr);
+  fb::sync(nullptr);
+  API_END
+}
+
+int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t cout, uint32_t k, uint32_t stride,
+                uint32_t pad, uint32_t groups, fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !w || !out) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, false);
+  fenc_ctx& C = *ctx;
+  Layout Lin = from_pub(C, &in->lay), Lout;
+  build_conv(C, Lin, w, cout, k, stride, pad, groups, true, Lout);
+  out->lay = to_pub(C, Lout);
+  if (!out->data) return FENC_OK;
+  check_batch(C, in, true);
+  ensure_device(C);
+  const size_t nw = (size_t)cout * (Lin.c / groups) * k * k;
+  std::ostringstream key;
+  key << "conv|" << layout_key(Lin) << '|' << cout << ',' << k << ',' << stride << ',' << pad << ',' << groups << ','
+      << fnv(w, nw * sizeof(double)) << ',' << C.pt_budget;
+  ConvPlan& P = cached<ConvPlan>(C, key.str(), [&] { return build_conv(C, Lin, w, cout, k, stride, pad, groups, false, Lout); });
+  run_conv(C, P, in->data, out->data, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, false);
+  fenc_ctx& C = *ctx;
+  Layout Lin = from_pub(C, &in->lay), Lout;
+  build_pool(C, Lin, true, Lout);
+  out->lay = to_pub(C, Lout);
+  if (!out->data) return FENC_OK;
+  check_batch(C, in, true);
+  ensure_device(C);
+  PoolPlan& P = cached<PoolPlan>(C, "pool|" + layout_key(Lin), [&] { return build_pool(C, Lin, false, Lout); });
+  run_pool(C, P, in->data, out->data, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, uint32_t degree, fenc_ctbatch* out,
+                  void* stream) {
+  API_BEGIN
+  if (!ctx || !coeffs || !out) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, false);
+  if (!(degree == 2 && coeffs[0] == 0.0 && coeffs[1] == 0.0 && coeffs[2] == 1.0))
+    fail(FENC_EUNSUPPORTED, "this build evaluates the x^2 activation only");
+  fenc_ctx& C = *ctx;
+  Layout Lin = from_pub(C, &in->lay);
+  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the activation");
+  Layout Lout = Lin;
+  Lout.level = Lin.level - 1;
+  Lout.scale = Lin.scale * Lin.scale / (double)C.primes[Lin.level];
+  out->lay = to_pub(C, Lout);
+  if (!out->data) return FENC_OK;
+  check_batch(C, in, true);
+  ensure_device(C);
+  SquarePlan& P = cached<SquarePlan>(C, "sq|" + layout_key(Lin), [&] {
+    auto p = new SquarePlan;
+    p->out = Lout;
+    p->level = Lin.level;
+    p->n = Lin.n_ct();
+    std::vector<std::vector<fk::KipItem>> items;
+    std::vector<fk::TailItem> tails;
+    const uint64_t* rk = get_key(C, 0);
+    for (int b = 0; b < p->n; b++) {
+      items.push_back({fk::KipItem{b, 1u, rk}});
+      tails.push_back(fk::TailItem{b, b, 0, 0});
+    }
+    p->ks = make_ks(C, items, tails, {}, p->owned);
+    return p;
+  });
+  run_square(C, P, in->data, out->data, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_compress(fenc_ctx* ctx, const fenc_ctbatch* in, const fenc_layout* target, fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  if (target) fail(FENC_EUNSUPPORTED, "explicit compression targets are not supported");
+  check_batch(*ctx, in, false);
+  fenc_ctx& C = *ctx;
+  Layout Lin = from_pub(C, &in->lay), Lout;
+  build_compress(C, Lin, true, Lout);
+  out->lay = to_pub(C, Lout);
+  if (!out->data) return FENC_OK;
+  check_batch(C, in, true);
+  ensure_device(C);
+  CompressPlan& P = cached<CompressPlan>(C, "aac|" + layout_key(Lin), [&] { return build_compress(C, Lin, false, Lout); });
+  run_compress(C, P, in->data, out->data, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_fc(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t dout, fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !w || !out) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, false);
+  fenc_ctx& C = *ctx;
+  Layout Lin = from_pub(C, &in->lay), Lout;
+  build_fc(C, Lin, w, dout, true, Lout);
+  out->lay = to_pub(C, Lout);
+  if (!out->data) return FENC_OK;
+  check_batch(C, in, true);
+  ensure_device(C);
+  std::ostringstream key;
+  key << "fc|" << layout_key(Lin) << '|' << dout << ',' << fnv(w, (size_t)dout * Lin.nfeat * sizeof(double));
+  FcPlan& P = cached<FcPlan>(C, key.str(), [&] { return build_fc(C, Lin, w, dout, false, Lout); });
+  run_fc(C, P, in->data, out->data, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_rotate(fenc_ctx* ctx, const fenc_ctbatch* in, const int32_t* shifts, uint32_t n, fenc_ctbatch* out,
+                void* stream) {
+  API_BEGIN
+  if (!ctx || !shifts || !out || n == 0) fail(FENC_EINVAL, "bad argument");
+  check_batch(*ctx, in, true);
+  fenc_ctx& C = *ctx;
+  Layout L = from_pub(C, &in->lay);
+  check_batch(C, out, true);
+  ensure_device(C);
+  const int nct = L.n_ct();
+  std::ostringstream key;
+  key << "rot|" << L.level << ',' << nct;
+  for (uint32_t i = 0; i < n; i++) {
+    if (galois(C, shifts[i]) == 1) fail(FENC_EINVAL, "zero rotation");
+    key << ',' << shifts[i];
+  }
+  struct RotPlan : Plan {
+    RotStage r;
+  };
+  RotPlan& P = cached<RotPlan>(C, key.str(), [&] {
+    auto p = new RotPlan;
+    std::vector<std::pair<int, long long>> copies;
+    for (int t = 0; t < nct; t++)
+      for (uint32_t i = 0; i < n; i++) copies.push_back({t, shifts[i]});
+    p->r = make_rot_stage(C, copies, p->owned);
+    return p;
+  });
+  run_rot_stage(C, L.level, P.r, in->data, out->data, (fb::Stream)stream);
+  C.cnt.rot_other += P.r.n;
+  C.cnt.keyswitch += P.r.n;
+  API_END
+}
+
+int fenc_rotate_sum(fenc_ctx* ctx, const fenc_ctbatch* z0, const fenc_ctbatch* zs, const int32_t* shifts, uint32_t n,
+                    fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !shifts || !out || n == 0) fail(FENC_EINVAL, "bad argument");
+  check_batch(*ctx, zs, true);
+  check_batch(*ctx, out, true);
+  fenc_ctx& C = *ctx;
+  Layout L = from_pub(C, &zs->lay);
+  if (z0) check_batch(C, z0, true);
+  ensure_device(C);
+  std::ostringstream key;
+  key << "rsum|" << L.level << ',' << (z0 ? 1 : 0);
+  for (uint32_t i = 0; i < n; i++) key << ',' << shifts[i];
+  struct SumPlan : Plan {
+    SumStage s;
+  };
+  SumPlan& P = cached<SumPlan>(C, key.str(), [&] {
+    auto p = new SumPlan;
+    std::vector<std::pair<int, long long>> t;
+    for (uint32_t i = 0; i < n; i++) t.push_back({(int)i, shifts[i]});
+    p->s = make_sum_stage(C, {0}, {z0 ? 0 : -1}, {t}, p->owned, (int)n);
+    return p;
+  });
+  run_sum_stage(C, L.level, P.s, zs->data, out->data, z0 ? z0->data : nullptr, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, false);
+  fenc_ctx& C = *ctx;
+  Layout L = from_pub(C, &in->lay);
+  if (L.level < 1) fail(FENC_ELEVEL, "no level left to rescale");
+  Layout Lo = L;
+  Lo.level = L.level - 1;
+  Lo.scale = L.scale / (double)C.primes[L.level];
+  out->lay = to_pub(C, Lo);
+  if (!out->data) return FENC_OK;
+  check_batch(C, in, true);
+  ensure_device(C);
+  rescale(C, L.level, in->data, L.n_ct(), out->data, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t n, int inverse) {
+  API_BEGIN
+  if (!ctx || !rows || !prime || n == 0 || n > (uint32_t)fk::kMaxMap) fail(FENC_EINVAL, "bad argument");
+  fenc_ctx& C = *ctx;
+  ensure_device(C);
+  fk::PrimeMap pm;
+  pm.n = (int)n;
+  for (uint32_t i = 0; i < n; i++) {
+    if (prime[i] < 0 || prime[i] >= C.np) fail(FENC_EINVAL, "prime index out of range");
+    pm.p[i] = (unsigned char)prime[i];
+  }
+  std::vector<void*> tmp;
+  std::vector<uint64_t> h(rows, rows + (size_t)n * C.N);
+  uint64_t* d = upload(C, h, tmp);
+  ntt(C, inverse != 0, d, d, C.N, C.N, (int)n, 1, pm, nullptr);
+  fb::sync(nullptr);
+  fb::d2h(rows, d, (size_t)n * C.N * 8);
+  for (void* p : tmp) fb::dev_free(p);
+  API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,543 @@
+// Host runtime: device tables, keys, workspace, key-switching pipelines.
+//
+// Hybrid key switching (the rotation formula of the Background section read
+// as Han-Ki hybrid switching with dnum digits):
+//   ModUp    iNTT(c1) -> fast base conversion of each digit -> NTT of the new limbs
+//   KIP      acc = sum_j sigma_g(ext_j) * key_j        (automorphism fused as a gather)
+//   ModDown  iNTT(P limbs) -> base conversion P -> Q -> NTT -> (acc - conv) * P^-1
+// Hoisted rotations share one ModUp per input ciphertext; lazy sums share one
+// ModDown per output ciphertext.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+namespace fr {
+
+using fh::invmod;
+using fh::mulmod;
+
+// ---------------------------------------------------------------- arena
+Arena::~Arena() {
+  for (auto& c : chunks_) fb::dev_free(c.p);
+}
+
+void* Arena::get(size_t bytes, fb::Stream s) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  while (cur_ < chunks_.size()) {
+    if (off_ + bytes <= chunks_[cur_].cap) {
+      void* p = chunks_[cur_].p + off_;
+      off_ += bytes;
+      return p;
+    }
+    cur_++;
+    off_ = 0;
+  }
+  if (fb::capturing(s)) fail(FENC_ENOMEM, "workspace must grow during stream capture; run the operation once before capturing");
+  size_t cap = std::max<size_t>(bytes, chunks_.empty() ? (size_t)64 << 20 : chunks_.back().cap * 2);
+  chunks_.push_back({(char*)fb::dev_alloc(cap), cap});
+  cur_ = chunks_.size() - 1;
+  off_ = bytes;
+  return chunks_[cur_].p;
+}
+
+size_t Arena::bytes() const {
+  size_t b = 0;
+  for (auto& c : chunks_) b += c.cap;
+  return b;
+}
+
+// ---------------------------------------------------------------- helpers
+d2 cpair(uint64_t w, uint64_t q) { return {(double)w, (double)w / (double)q}; }
+
+void* dalloc(Ctx& C, size_t bytes, std::vector<void*>& owner) {
+  void* p = fb::dev_alloc(bytes);
+  owner.push_back(p);
+  C.dev_bytes += (int64_t)bytes;
+  return p;
+}
+
+fk::PrimeMap identity_map(int n) {
+  fk::PrimeMap pm;
+  pm.n = n;
+  for (int i = 0; i < n; i++) pm.p[i] = (unsigned char)i;
+  return pm;
+}
+
+uint64_t galois(const Ctx& C, long long shift) {
+  long long r = shift % C.ns;
+  if (r < 0) r += C.ns;
+  return fh::powmod(5, (uint64_t)r, 2ull * C.N);
+}
+
+static unsigned grid_x(const Ctx& C) { return (unsigned)std::max(1, C.N / 256); }
+static int block_threads(const Ctx& C) { return std::min(256, C.N); }
+
+// ---------------------------------------------------------------- device set-up
+void ensure_device(Ctx& C) {
+  if (C.dev) return;
+  C.device = fb::device_id();
+  const int N = C.N, np = C.np;
+  std::vector<d2> pq(np), twf((size_t)np * N), twi((size_t)np * N), ni(np);
+  for (int p = 0; p < np; p++) {
+    const uint64_t q = C.primes[p], psi = C.psi[p], psi_inv = invmod(psi, q);
+    pq[p] = {(double)q, 1.0 / (double)q};
+    for (int k = 0; k < N; k++) {
+      const unsigned e = fh::bitrev((unsigned)k, C.logn);
+      twf[(size_t)p * N + k] = cpair(fh::powmod(psi, e, q), q);
+      twi[(size_t)p * N + k] = cpair(fh::powmod(psi_inv, e, q), q);
+    }
+    ni[p] = cpair(invmod((uint64_t)N, q), q);
+  }
+  C.pq = upload(C, pq, C.owned);
+  C.tw_fwd = upload(C, twf, C.owned);
+  C.tw_inv = upload(C, twi, C.owned);
+  C.ninv = upload(C, ni, C.owned);
+  // ModDown tables (level independent): hinv[k] mod p_k, hat[i][k] = (P/p_k) mod q_i, P^-1 mod q_i
+  const int K = C.K, L1 = C.L + 1;
+  std::vector<d2> md((size_t)K + (size_t)L1 * K), pinv(L1);
+  for (int k = 0; k < K; k++) {
+    const uint64_t pk = C.primes[L1 + k];
+    uint64_t hat = 1;
+    for (int k2 = 0; k2 < K; k2++)
+      if (k2 != k) hat = mulmod(hat, C.primes[L1 + k2] % pk, pk);
+    md[k] = cpair(invmod(hat, pk), pk);
+  }
+  for (int i = 0; i < L1; i++) {
+    const uint64_t qi = C.primes[i];
+    uint64_t P = 1;
+    for (int k = 0; k < K; k++) {
+      uint64_t hat = 1;
+      for (int k2 = 0; k2 < K; k2++)
+        if (k2 != k) hat = mulmod(hat, C.primes[L1 + k2] % qi, qi);
+      md[K + (size_t)i * K + k] = cpair(hat, qi);
+      P = mulmod(P, C.primes[L1 + k] % qi, qi);
+    }
+    pinv[i] = cpair(invmod(P, qi), qi);
+  }
+  C.md_tab = upload(C, md, C.owned);
+  C.pinv = upload(C, pinv, C.owned);
+  C.dev = true;
+  // secret key in NTT form over every prime
+  std::vector<long long> sv(C.s.begin(), C.s.end());
+  long long* ds = upload(C, sv, C.owned);
+  std::vector<unsigned char> allp(np);
+  for (int p = 0; p < np; p++) allp[p] = (unsigned char)p;
+  unsigned char* dp = upload(C, allp, C.owned);
+  C.s_ntt = (uint64_t*)dalloc(C, (size_t)np * N * 8, C.owned);
+  fk::SmallArgs a{ds, C.s_ntt, np, C.logn, dp, C.pq};
+  fb::small_to_rns({grid_x(C), (unsigned)np, 1}, block_threads(C), nullptr, a);
+  ntt(C, false, C.s_ntt, C.s_ntt, 0, 0, np, np, identity_map(np), nullptr);
+  fb::sync(nullptr);
+}
+
+const LevelTabs& level_tabs(Ctx& C, int level) {
+  auto it = C.lvl.find(level);
+  if (it != C.lvl.end()) return it->second;
+  LevelTabs T;
+  const int nl = level + 1, le = nl + C.K, alpha = C.alpha, beta = (nl + alpha - 1) / alpha;
+  T.h_eprime.resize(le);
+  for (int l = 0; l < le; l++) T.h_eprime[l] = (unsigned char)(l < nl ? l : C.L + 1 + (l - nl));
+  T.eprime = upload(C, T.h_eprime, C.owned);
+  T.tstride = alpha + le * alpha;
+  std::vector<d2> tab((size_t)beta * T.tstride, d2{0, 0});
+  for (int j = 0; j < beta; j++) {
+    const int lo = j * alpha, hi = std::min(lo + alpha, nl);
+    d2* t = &tab[(size_t)j * T.tstride];
+    for (int i = lo; i < hi; i++) {
+      const uint64_t qi = C.primes[i];
+      uint64_t hat = 1;
+      for (int i2 = lo; i2 < hi; i2++)
+        if (i2 != i) hat = mulmod(hat, C.primes[i2] % qi, qi);
+      t[i - lo] = cpair(invmod(hat, qi), qi);
+    }
+    for (int l = 0; l < le; l++) {
+      if (l >= lo && l < hi) continue;
+      const uint64_t qt = C.primes[T.h_eprime[l]];
+      for (int i = lo; i < hi; i++) {
+        uint64_t hat = 1;
+        for (int i2 = lo; i2 < hi; i2++)
+          if (i2 != i) hat = mulmod(hat, C.primes[i2] % qt, qt);
+        t[alpha + (size_t)l * alpha + (i - lo)] = cpair(hat, qt);
+      }
+    }
+  }
+  T.modup = upload(C, tab, C.owned);
+  std::vector<d2> ql(std::max(1, level));
+  for (int i = 0; i < level; i++) ql[i] = cpair(invmod(C.primes[level] % C.primes[i], C.primes[i]), C.primes[i]);
+  T.qlinv = upload(C, ql, C.owned);
+  return C.lvl[level] = T;
+}
+
+// ---------------------------------------------------------------- NTT
+void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long long dst_gs, int nrows, int nl,
+         const fk::PrimeMap& pm, fb::Stream s) {
+  if (nrows <= 0) return;
+  fk::NttArgs a;
+  a.src = src;
+  a.dst = dst;
+  a.src_gs = src_gs;
+  a.dst_gs = dst_gs;
+  a.nrows = nrows;
+  a.nl = nl;
+  a.pm = pm;
+  a.tw = inverse ? C.tw_inv : C.tw_fwd;
+  a.pq = C.pq;
+  a.ninv = C.ninv;
+  a.logn = C.logn;
+  a.n2 = (C.logn + 1) / 2;
+  a.n1 = C.logn - a.n2;
+  a.cols = std::min(16, 1 << a.n2);
+  a.cpb = std::min(std::max(1, 2048 >> a.n2), 1 << a.n1);
+  const unsigned colblocks = (unsigned)((1 << a.n2) / a.cols), rowblocks = (unsigned)((1 << a.n1) / a.cpb);
+  const size_t lds_c = (size_t)(1 << a.n1) * a.cols * 8, lds_r = (size_t)a.cpb * (1 << a.n2) * 8;
+  const int T = 256;
+  int active = 0;
+  for (int r = 0; r < std::min(nrows, pm.n); r++) active += (pm.p[r] != fk::kSkip);
+  active = (int)((long long)active * nrows / std::max(1, std::min(nrows, pm.n)));
+  const double pass_bytes = 16.0 * active * C.N;   // read + write of every active row
+  if (!inverse) {
+    timed(C, "ntt_fwd_cols", pass_bytes, s, [&] { fb::ntt_fwd_cols({colblocks, (unsigned)nrows, 1}, T, lds_c, s, a); });
+    a.src = dst;
+    a.src_gs = dst_gs;
+    timed(C, "ntt_fwd_rows", pass_bytes, s, [&] { fb::ntt_fwd_rows({rowblocks, (unsigned)nrows, 1}, T, lds_r, s, a); });
+    C.cnt.ntt_limbs += active;
+  } else {
+    timed(C, "ntt_inv_rows", pass_bytes, s, [&] { fb::ntt_inv_rows({rowblocks, (unsigned)nrows, 1}, T, lds_r, s, a); });
+    a.src = dst;
+    a.src_gs = dst_gs;
+    timed(C, "ntt_inv_cols", pass_bytes, s, [&] { fb::ntt_inv_cols({colblocks, (unsigned)nrows, 1}, T, lds_c, s, a); });
+    C.cnt.intt_limbs += active;
+  }
+  C.cnt.launches += 2;
+}
+
+// ---------------------------------------------------------------- keys
+const uint64_t* get_key(Ctx& C, uint64_t g) {
+  auto it = C.keys.find(g);
+  if (it != C.keys.end()) return it->second;
+  if (C.strict) fail(FENC_ENOKEY, "missing switching key for Galois element " + std::to_string(g));
+  ensure_device(C);
+  const int N = C.N, np = C.np, nd = C.ndig, L1 = C.L + 1;
+  const uint64_t seed = C.prm.seed;
+  // host sampling of the uniform a_j and the errors e_j
+  std::vector<uint64_t> a((size_t)nd * np * N);
+  std::vector<long long> e((size_t)nd * N);
+  const int nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int w = 0; w < nthr; w++)
+    th.emplace_back([&, w] {
+      for (int r = w; r < nd * np; r += nthr) {
+        const int j = r / np, p = r % np;
+        const uint64_t q = C.primes[p], tg = fh::tag::key_a(g, j, p);
+        uint64_t* dst = &a[(size_t)r * N];
+        for (int i = 0; i < N; i++) dst[i] = fh::draw_uniform(seed, tg, i, q);
+      }
+      for (int j = w; j < nd; j += nthr)
+        for (int i = 0; i < N; i++) e[(size_t)j * N + i] = fh::draw_gauss(seed, fh::tag::key_e(g, j), i);
+    });
+  for (auto& t : th) t.join();
+  std::vector<void*> tmp;
+  uint64_t* da = upload(C, a, tmp);
+  long long* de = upload(C, e, tmp);
+  std::vector<unsigned char> allp(np);
+  for (int p = 0; p < np; p++) allp[p] = (unsigned char)p;
+  unsigned char* dp = upload(C, allp, tmp);
+  uint64_t* dE = (uint64_t*)dalloc(C, (size_t)nd * np * N * 8, tmp);
+  uint64_t* dS = (uint64_t*)dalloc(C, (size_t)np * N * 8, tmp);
+  ntt(C, false, da, da, (long long)np * N, (long long)np * N, nd * np, np, identity_map(np), nullptr);
+  fk::SmallArgs sa{de, dE, np, C.logn, dp, C.pq};
+  fb::small_to_rns({grid_x(C), (unsigned)(nd * np), 1}, block_threads(C), nullptr, sa);
+  ntt(C, false, dE, dE, (long long)np * N, (long long)np * N, nd * np, np, identity_map(np), nullptr);
+  fk::PermArgs pa{C.s_ntt, dS, (unsigned)g, C.logn, dp, C.pq};   // g == 0: s^2, else sigma_g(s)
+  fb::perm_rows({grid_x(C), (unsigned)np, 1}, block_threads(C), nullptr, pa);
+  std::vector<d2> gad((size_t)nd * np, d2{0, 0});
+  for (int j = 0; j < nd; j++)
+    for (int p = j * C.alpha; p < std::min((j + 1) * C.alpha, L1); p++) {
+      uint64_t P = 1;
+      for (int k = 0; k < C.K; k++) P = mulmod(P, C.primes[L1 + k] % C.primes[p], C.primes[p]);
+      gad[(size_t)j * np + p] = cpair(P, C.primes[p]);
+    }
+  d2* dg = upload(C, gad, tmp);
+  uint64_t* key = (uint64_t*)dalloc(C, (size_t)nd * 2 * np * N * 8, C.owned);
+  fk::KeyArgs ka{da, dE, C.s_ntt, dS, key, dg, np, C.logn, C.pq};
+  fb::key_combine({grid_x(C), (unsigned)(nd * np), 1}, block_threads(C), nullptr, ka);
+  fb::sync(nullptr);
+  for (void* p : tmp) {
+    fb::dev_free(p);
+  }
+  C.keys[g] = key;
+  return key;
+}
+
+// ---------------------------------------------------------------- key switching
+void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s) {
+  if (B <= 0) return;
+  const LevelTabs& T = level_tabs(C, level);
+  const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha, N = C.N;
+  if (beta * le > fk::kMaxMap) fail(FENC_EUNSUPPORTED, "too many extended limbs");
+  Scope sc(C.arena);
+  u64* coef = (u64*)C.arena.get((size_t)B * nl * N * 8, s);
+  fk::PrimeMap pmd;
+  pmd.n = beta * le;
+  for (int j = 0; j < beta; j++)
+    for (int l = 0; l < le; l++) {
+      const bool own = l >= j * C.alpha && l < std::min((j + 1) * C.alpha, nl);
+      pmd.p[j * le + l] = own ? fk::kSkip : T.h_eprime[l];
+    }
+  fk::ModUpArgs a;
+  a.coef = coef;
+  a.ntt = in + ps;
+  a.coef_cs = (long long)nl * N;
+  a.ntt_cs = cs;
+  a.ext = ext;
+  a.beta = beta;
+  a.alpha = C.alpha;
+  a.nl = nl;
+  a.le = le;
+  a.logn = C.logn;
+  a.eprime = T.eprime;
+  a.tab = T.modup;
+  a.tstride = T.tstride;
+  a.pq = C.pq;
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  for (int b0 = 0; b0 < B; b0 += per_op ? 1 : B) {
+    const int nb = per_op ? 1 : B;
+    ntt(C, true, in + ps + b0 * cs, coef + (long long)b0 * nl * N, cs, (long long)nl * N, nb * nl, nl,
+        identity_map(nl), s);
+    a.b0 = b0;
+    double mb = 0;
+    for (int j = 0; j < beta; j++) mb += (2.0 * (std::min((j + 1) * C.alpha, nl) - j * C.alpha) + le) * N * 8.0;
+    timed(C, "modup_fbc", mb * nb, s,
+          [&] { fb::modup_fbc({(unsigned)(N / block_threads(C)), (unsigned)(nb * beta), 1}, block_threads(C), s, a); });
+    ntt(C, false, ext + (long long)b0 * beta * le * N, ext + (long long)b0 * beta * le * N, (long long)le * N,
+        (long long)le * N, nb * beta * le, le, pmd, s);
+    C.cnt.launches += 1;
+    C.cnt.modup += nb;
+  }
+}
+
+void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
+                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s) {
+  if (st.n_out <= 0) return;
+  const LevelTabs& T = level_tabs(C, level);
+  const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha, N = C.N;
+  Scope sc(C.arena);
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  const int chunk = per_op ? 1 : st.n_out;
+  u64* acc = (u64*)C.arena.get((size_t)st.n_out * 2 * le * N * 8, s);
+  u64* conv = (u64*)C.arena.get((size_t)st.n_out * 2 * nl * N * 8, s);
+  fk::PrimeMap pmP;
+  pmP.n = le;
+  for (int l = 0; l < le; l++) pmP.p[l] = l < nl ? fk::kSkip : T.h_eprime[l];
+  for (int o0 = 0; o0 < st.n_out; o0 += chunk) {
+    const int no = std::min(chunk, st.n_out - o0);
+    fk::KipArgs k{ext, acc, st.items, st.d_item_off, o0, beta, le, C.logn, C.np, T.eprime, C.pq};
+    const int nit = st.item_off[o0 + no] - st.item_off[o0];
+    const int nkeys = per_op ? nit : st.n_keys;
+    const double kb = ((double)nit * beta * le + (double)nkeys * 2 * beta * le + 2.0 * no * le) * N * 8;
+    timed(C, "kip", kb, s,
+          [&] { fb::kip({(unsigned)(N / block_threads(C)), (unsigned)le, (unsigned)no}, block_threads(C), s, k); });
+    u64* acc0 = acc + (long long)o0 * 2 * le * N;
+    ntt(C, true, acc0, acc0, (long long)le * N, (long long)le * N, no * 2 * le, le, pmP, s);
+    fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.eprime, C.md_tab, C.pq};
+    timed(C, "moddown_fbc", 2.0 * no * (C.K + nl) * N * 8, s, [&] {
+      fb::moddown_fbc({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, m);
+    });
+    u64* conv0 = conv + (long long)o0 * 2 * nl * N;
+    ntt(C, false, conv0, conv0, (long long)nl * N, (long long)nl * N, no * 2 * nl, nl, identity_map(nl), s);
+    fk::TailArgs t;
+    t.acc = acc;
+    t.conv = conv;
+    t.items = st.tails;
+    t.terms = st.terms;
+    t.o0 = o0;
+    t.nl = nl;
+    t.le = le;
+    t.logn = C.logn;
+    t.out = out;
+    t.out_cs = out_cs;
+    t.out_ps = (long long)nl * N;
+    t.base = base;
+    t.base_cs = base_cs;
+    t.base_ps = (long long)nl * N;
+    t.add = add;
+    t.add_cs = add_cs;
+    t.pinv = C.pinv;
+    t.pq = C.pq;
+    const double frac = (double)no / st.n_out;
+    const double tb = (6.0 * no + 2.0 * st.n_base * frac + st.n_adds * frac) * nl * N * 8;
+    timed(C, "moddown_tail", tb, s, [&] {
+      fb::moddown_tail({(unsigned)(N / block_threads(C)), (unsigned)(2 * nl), (unsigned)no}, block_threads(C), s, t);
+    });
+    C.cnt.launches += 3;
+    C.cnt.moddown += no;
+  }
+}
+
+void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
+  if (B <= 0) return;
+  if (level < 1) fail(FENC_ELEVEL, "no level left to rescale");
+  const LevelTabs& T = level_tabs(C, level);
+  const int nl = level, N = C.N;   // output limbs
+  Scope sc(C.arena);
+  u64* last = (u64*)C.arena.get((size_t)B * 2 * N * 8, s);
+  u64* lift = (u64*)C.arena.get((size_t)B * 2 * nl * N * 8, s);
+  fk::PrimeMap pl;
+  pl.n = 1;
+  pl.p[0] = (unsigned char)level;
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  for (int b0 = 0; b0 < B; b0 += per_op ? 1 : B) {
+    const int nb = per_op ? 1 : B;
+    const long long in_cs = 2LL * (level + 1) * N, out_cs = 2LL * nl * N;
+    ntt(C, true, in + b0 * in_cs + (long long)level * N, last + (long long)b0 * 2 * N, (long long)(level + 1) * N,
+        N, nb * 2, 1, pl, s);
+    fk::LiftArgs la{last + (long long)b0 * 2 * N, lift + (long long)b0 * 2 * nl * N, nl, C.logn,
+                    (double)C.primes[level], C.pq};
+    timed(C, "rescale_lift", 2.0 * nb * (1 + nl) * N * 8, s,
+          [&] { fb::rescale_lift({(unsigned)(N / block_threads(C)), (unsigned)(nb * 2), 1}, block_threads(C), s, la); });
+    u64* l0 = lift + (long long)b0 * 2 * nl * N;
+    ntt(C, false, l0, l0, (long long)nl * N, (long long)nl * N, nb * 2 * nl, nl, identity_map(nl), s);
+    fk::RescaleTailArgs ra{in + b0 * in_cs, l0, out + b0 * out_cs, nl, C.logn, T.qlinv, C.pq};
+    timed(C, "rescale_tail", 6.0 * nb * nl * N * 8, s, [&] {
+      fb::rescale_tail({(unsigned)(N / block_threads(C)), (unsigned)(nb * 2 * nl), 1}, block_threads(C), s, ra);
+    });
+    C.cnt.launches += 2;
+    C.cnt.rescale += nb;
+  }
+}
+
+void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, int na, const u64* in_b,
+              long long b_cs, long long in_ps, u64* out, long long out_cs, long long out_ps, fb::Stream s) {
+  if (g.n_out <= 0) return;
+  fk::GmacArgs a;
+  a.in_a = in_a;
+  a.a_cs = a_cs;
+  a.na = na;
+  a.in_b = in_b;
+  a.b_cs = b_cs;
+  a.in_ps = in_ps;
+  a.out = out;
+  a.out_cs = out_cs;
+  a.out_ps = out_ps;
+  a.goff = g.goff;
+  a.mask = g.mask;
+  a.toff = g.toff;
+  a.tin = g.tin;
+  a.tw = g.tw;
+  a.wt = g.wt;
+  a.nw = g.nw;
+  a.nl = nl;
+  a.logn = C.logn;
+  a.pq = C.pq;
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  for (int o0 = 0; o0 < g.n_out; o0 += per_op ? 1 : g.n_out) {
+    a.o0 = o0;
+    const int no = per_op ? 1 : g.n_out;
+    const double frac = (double)no / g.n_out;
+    const double gb = (2.0 * g.n_terms * frac + 1.0 * g.n_masked * frac + 2.0 * no) * nl * C.N * 8;
+    timed(C, "gmac", gb, s, [&] {
+      fb::gmac({(unsigned)(C.N / block_threads(C)), (unsigned)(2 * nl), (unsigned)no}, block_threads(C), s, a);
+    });
+    C.cnt.launches += 1;
+  }
+}
+
+KsStage make_ks(Ctx& C, const std::vector<std::vector<fk::KipItem>>& items, const std::vector<fk::TailItem>& tails,
+                const std::vector<fk::AddTerm>& terms, std::vector<void*>& owner) {
+  KsStage st;
+  st.n_out = (int)items.size();
+  std::vector<fk::KipItem> flat;
+  st.item_off.push_back(0);
+  for (auto& v : items) {
+    flat.insert(flat.end(), v.begin(), v.end());
+    st.item_off.push_back((int)flat.size());
+  }
+  std::map<const u64*, int> uk;
+  for (auto& it : flat) uk[it.key] = 1;
+  st.n_keys = (int)uk.size();
+  for (auto& t : tails) {
+    st.n_base += t.base >= 0;
+    st.n_adds += t.add_n;
+  }
+  st.items = upload(C, flat, owner);
+  st.d_item_off = upload(C, st.item_off, owner);
+  st.tails = upload(C, tails, owner);
+  st.terms = upload(C, terms, owner);
+  return st;
+}
+
+GmacStage make_gmac(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int level,
+                    std::vector<void*>& owner) {
+  GmacStage g;
+  g.n_out = (int)b.goff.size() - 1;
+  g.nw = (int)wcodes.size();
+  g.n_terms = (long long)b.tin.size();
+  for (auto* m : b.mask) g.n_masked += m != nullptr;
+  g.goff = upload(C, b.goff, owner);
+  g.mask = (const u64**)upload(C, b.mask, owner);
+  g.toff = upload(C, b.toff, owner);
+  g.tin = upload(C, b.tin, owner);
+  g.tw = upload(C, b.tw, owner);
+  const int nl = level + 1;
+  std::vector<d2> wt((size_t)nl * std::max<size_t>(1, wcodes.size()));
+  for (int i = 0; i < nl; i++) {
+    const uint64_t q = C.primes[i];
+    for (size_t w = 0; w < wcodes.size(); w++) {
+      const int64_t v = wcodes[w] % (int64_t)q;
+      wt[(size_t)i * wcodes.size() + w] = cpair((uint64_t)(v < 0 ? v + (int64_t)q : v), q);
+    }
+  }
+  g.wt = upload(C, wt, owner);
+  return g;
+}
+
+u64* encode_plaintexts(Ctx& C, const std::vector<std::vector<double>>& slots, double scale, int level,
+                       std::vector<void*>& owner) {
+  const int N = C.N, nl = level + 1, n = (int)slots.size();
+  std::vector<uint64_t> h((size_t)n * nl * N);
+  const int nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int w = 0; w < nthr; w++)
+    th.emplace_back([&, w] {
+      std::vector<int64_t> m(N);
+      for (int t = w; t < n; t += nthr) {
+        fh::encode_real(C.logn, slots[t].data(), scale, m.data());
+        for (int i = 0; i < nl; i++) {
+          const int64_t q = (int64_t)C.primes[i];
+          uint64_t* dst = &h[((size_t)t * nl + i) * N];
+          for (int c = 0; c < N; c++) {
+            int64_t v = m[c] % q;
+            dst[c] = (uint64_t)(v < 0 ? v + q : v);
+          }
+        }
+      }
+    });
+  for (auto& t : th) t.join();
+  u64* d = upload(C, h, owner);
+  ntt(C, false, d, d, (long long)nl * N, (long long)nl * N, n * nl, nl, identity_map(nl), nullptr);
+  fb::sync(nullptr);
+  return d;
+}
+
+int64_t weight_code(double w, double scale) {
+  const double v = w * scale;
+  if (!(std::fabs(v) < 4503599627370496.0)) fail(FENC_EINVAL, "weight too large for its scale");
+  return (int64_t)std::round(v);
+}
+
+void split_scale(double T, double& dw, double& dm) {
+  int e = 0;
+  std::frexp(T, &e);
+  dw = std::ldexp(1.0, (e - 1) >> 1);
+  dm = T / dw;
+}
+
+}  // namespace fr
+
+fenc_ctx::~fenc_ctx() {
+  plans.clear();
+  for (void* p : owned) fb::dev_free(p);
+}

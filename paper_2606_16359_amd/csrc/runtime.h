@@ -1,0 +1,214 @@
+// Host runtime of the library: context, device tables, keys, workspace arena,
+// key-switching pipelines and cached operation plans.  Contains no device
+// code; every kernel is reached through fenc_backend.h.
+#pragma once
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fenc.h"
+#include "fenc_backend.h"
+#include "host_math.h"
+
+namespace fr {
+
+typedef uint64_t u64;
+using fk::d2;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] inline void fail(int code, const std::string& m) { throw Error(code, m); }
+
+// ---------------------------------------------------------------- layout
+struct Layout {
+  int kind = FENC_LAYOUT_FRAGMENT;
+  int bs = 0, c = 0, h = 0, w = 0, M = 0, S = 0, m = 0, bsg = 0, cpc = 0, nbg = 0, ncg = 0;
+  int rep = 0, dil = 1, level = 0, d = 0, nfeat = 0;
+  double scale = 1.0;
+  std::vector<int> pos;   // VECTOR layouts
+  int n_ct() const { return kind == FENC_LAYOUT_FRAGMENT ? nbg * ncg * S * S : nbg; }
+};
+
+Layout make_fragment(int ns, int level, double scale, int bs, int c, int h, int w, int S);
+Layout plan_fragment(int ns, int level, double scale, int bs, int c, int h, int w, int k, int cout, int s_override);
+// first (ct, slot) of an element, plus every replica when `all`
+void layout_slots(const Layout& L, int b, int ch, int y, int x, std::vector<std::pair<int, int>>& out);
+
+// ---------------------------------------------------------------- arena
+// Grow-only chunked workspace.  Allocation order is deterministic, so a
+// repeated operation gets the same addresses (required for graph replay).
+class Arena {
+ public:
+  struct Mark {
+    size_t chunk, off;
+  };
+  ~Arena();
+  void* get(size_t bytes, fb::Stream s);
+  Mark mark() const { return {cur_, off_}; }
+  void release(Mark m) { cur_ = m.chunk; off_ = m.off; }
+  size_t bytes() const;
+ private:
+  struct Chunk {
+    char* p;
+    size_t cap;
+  };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, off_ = 0;
+};
+
+struct Scope {   // releases arena allocations of one operation
+  Arena& a;
+  Arena::Mark m;
+  explicit Scope(Arena& ar) : a(ar), m(ar.mark()) {}
+  ~Scope() { a.release(m); }
+};
+
+// ---------------------------------------------------------------- device tables of a KS stage
+struct KsStage {
+  int n_out = 0;
+  std::vector<int> item_off;           // host copy
+  std::vector<int> key_groups;         // host: distinct keys among items [o0, o0+n) when launched whole
+  int n_keys = 0, n_base = 0, n_adds = 0;
+  fk::KipItem* items = nullptr;        // device
+  int* d_item_off = nullptr;
+  fk::TailItem* tails = nullptr;
+  fk::AddTerm* terms = nullptr;
+};
+
+struct GmacStage {
+  int n_out = 0, nw = 0;
+  long long n_terms = 0, n_masked = 0;   // host counts (traffic accounting)
+  int* goff = nullptr;
+  const u64** mask = nullptr;
+  int* toff = nullptr;
+  int* tin = nullptr;
+  int* tw = nullptr;
+  d2* wt = nullptr;
+};
+
+struct Plan {
+  virtual ~Plan() {
+    for (void* p : owned) fb::dev_free(p);
+  }
+  std::vector<void*> owned;   // device allocations of the plan
+  Layout out;
+};
+
+struct LevelTabs {
+  d2* modup = nullptr;   // [beta][alpha + le*alpha]
+  int tstride = 0;
+  d2* qlinv = nullptr;   // [level]
+  unsigned char* eprime = nullptr;
+  std::vector<unsigned char> h_eprime;
+};
+
+}  // namespace fr
+
+struct fenc_ctx {
+  fenc_params prm{};
+  int logn = 0, N = 0, ns = 0, L = 0, K = 0, alpha = 0, ndig = 0, np = 0;
+  double Delta = 1.0;
+  std::vector<uint64_t> primes, psi;
+  std::vector<int64_t> s;            // secret key coefficients
+  int mode = FENC_MODE_BATCHED;
+  bool strict = false;
+  int64_t pt_budget = 1LL << 30;     // bytes of materialised conv plaintexts
+  fenc_counters cnt{};
+
+  // device state (built on first use)
+  bool dev = false;
+  int device = -1;
+  fk::d2 *pq = nullptr, *tw_fwd = nullptr, *tw_inv = nullptr, *ninv = nullptr;
+  fk::d2 *md_tab = nullptr, *pinv = nullptr;   // ModDown: hinv[K], hat[L+1][K]; P^-1 mod q_i
+  uint64_t* s_ntt = nullptr;                   // [np][N]
+  std::map<int, fr::LevelTabs> lvl;
+  std::map<uint64_t, uint64_t*> keys;          // Galois element (0: relinearisation) -> key
+  std::map<std::string, std::unique_ptr<fr::Plan>> plans;
+  std::map<uint64_t, std::vector<int>> maps;
+  std::vector<void*> owned;
+  fr::Arena arena;
+  int64_t dev_bytes = 0;
+  // single-kernel profiling: events around every launch of `prof_kernel`
+  std::string prof_kernel;
+  struct ProfRec {
+    void *a, *b;
+    double bytes;
+  };
+  std::vector<ProfRec> prof;
+  ~fenc_ctx();
+};
+
+namespace fr {
+
+typedef fenc_ctx Ctx;
+
+void ensure_device(Ctx& C);
+void* dalloc(Ctx& C, size_t bytes, std::vector<void*>& owner);
+template <class T>
+T* upload(Ctx& C, const std::vector<T>& v, std::vector<void*>& owner) {
+  T* p = (T*)dalloc(C, v.size() * sizeof(T) + 8, owner);
+  if (!v.empty()) fb::h2d(p, v.data(), v.size() * sizeof(T));
+  return p;
+}
+const LevelTabs& level_tabs(Ctx& C, int level);
+uint64_t galois(const Ctx& C, long long shift);
+const uint64_t* get_key(Ctx& C, uint64_t g);
+d2 cpair(uint64_t w, uint64_t q);   // (w, w/q)
+
+// NTT of rows: row r reads src + (r/nl)*src_gs + (r%nl)*N, prime pm.p[r % pm.n]
+void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long long dst_gs, int nrows, int nl,
+         const fk::PrimeMap& pm, fb::Stream s);
+fk::PrimeMap identity_map(int n);
+
+// key switching pieces
+void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s);
+void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
+                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s);
+void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s);
+void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, int na, const u64* in_b,
+              long long b_cs, long long in_ps, u64* out, long long out_cs, long long out_ps, fb::Stream s);
+
+KsStage make_ks(Ctx& C, const std::vector<std::vector<fk::KipItem>>& items, const std::vector<fk::TailItem>& tails,
+                const std::vector<fk::AddTerm>& terms, std::vector<void*>& owner);
+struct GmacBuild {
+  std::vector<int> goff{0}, toff{0}, tin, tw;
+  std::vector<const u64*> mask;
+  void add_group(const u64* m) { mask.push_back(m); }
+  void add_term(int in, int w) { tin.push_back(in); tw.push_back(w); }
+  void end_group() { toff.push_back((int)tin.size()); }
+  void end_output() { goff.push_back((int)mask.size()); }
+};
+GmacStage make_gmac(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int level,
+                    std::vector<void*>& owner);
+
+// plaintexts: encode real slots at `scale`, reduce, NTT on device ([level+1][N])
+u64* encode_plaintexts(Ctx& C, const std::vector<std::vector<double>>& slots, double scale, int level,
+                       std::vector<void*>& owner);
+
+int64_t weight_code(double w, double scale);
+void split_scale(double T, double& dw, double& dm);
+
+inline long long ct_elems(const Ctx& C, int level) { return 2LL * (level + 1) * C.N; }
+
+// Times the launch(es) issued by `launch` when `name` is the profiled kernel;
+// `bytes` is the algorithmic HBM traffic of those launches.
+template <class F>
+void timed(Ctx& C, const char* name, double bytes, fb::Stream s, F launch) {
+  if (C.prof_kernel.empty() || C.prof_kernel != name || fb::capturing(s)) {
+    launch();
+    return;
+  }
+  void* a = fb::event_create();
+  void* b = fb::event_create();
+  fb::event_record(a, s);
+  launch();
+  fb::event_record(b, s);
+  C.prof.push_back({a, b, bytes});
+}
+
+}  // namespace fr

@@ -1,0 +1,191 @@
+"""Element-by-element parity of the library's kernels with the oracle.
+
+Every test runs twice: through the CPU emulator of the kernel bodies (CPU
+suite) and on the MI355X (marked gpu).  Ciphertext limbs must be bit-exact in
+coefficient form; decrypted values are compared with float64 references.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn_ref
+from oracle import pyoracle as P
+
+from fenc_backends import BACKENDS, make, rng
+from paper_2606_16359_amd import fenc as F
+
+# toy parameters: N = 2^10, 8 x 50-bit primes, 3 special primes, dnum 3 (3 limbs per digit)
+SMALL = (10, 8, 50, 3, 50, 3, 40, 17)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return P.Oracle(*SMALL)
+
+
+def cmp(lib_ct, orc_batch, fenc):
+    a = fenc.export(lib_ct)
+    b = orc_batch if isinstance(orc_batch, np.ndarray) else orc_batch.data()
+    assert a.shape == b.shape
+    bad = np.argwhere(a != b)
+    assert bad.size == 0, f"{len(bad)} limbs words differ, first at {bad[0]}"
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("logn", [10, 13])
+def test_ntt_roundtrip_and_product(backend, logn):
+    o = P.Oracle(logn, 4, 50, 2, 50, 2, 40, 3)
+    f = make(backend, logn, 4, 50, 2, 50, 2, 40, 3)
+    r = rng(logn)
+    primes = o.primes()
+    rows = np.array([r.integers(0, primes[i % 6], o.N, dtype=np.uint64) for i in range(7)])   # 7 rows: ragged
+    pidx = [i % 6 for i in range(7)]
+    A = f.ntt_rows(rows, pidx)
+    assert np.array_equal(f.ntt_rows(A, pidx, inverse=True), rows)
+    for i in range(0, 6, 2):
+        q = primes[pidx[i]]
+        prod = (A[i].astype(object) * A[i + 1].astype(object) % q).astype(np.uint64)
+        got = f.ntt_rows(prod[None], [pidx[i]], inverse=True)[0]
+        assert np.array_equal(got, o.polymul(pidx[i], rows[i], rows[i + 1])) if pidx[i] == pidx[i + 1] else True
+    # evaluation order: slot k holds a(psi^(2 brev(k) + 1))
+    psi, q = o.psi()[0], primes[0]
+    a = rows[0]
+    for k in [0, 1, 5, o.N - 1]:
+        e = 2 * int(format(k, f"0{logn}b")[::-1], 2) + 1
+        assert int(A[0][k]) == sum(int(a[i]) * pow(psi, e * i, q) for i in range(o.N)) % q
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_encrypt_keys_and_keyswitch_building_blocks(backend, orc):
+    o, f = orc, make(backend, *SMALL)
+    assert f.primes() == o.primes()
+    z = rng(1).uniform(-1, 1, o.ns)
+    pt = o.encode(z, None, 2.0 ** 40)
+    assert np.array_equal(f.encode_slots(z, o.L, 2.0 ** 40), pt)
+    lay = f.plan_layout(1, 1, 16, 16, 3, 1)
+    ct = f.encrypt(pt[None], lay, 7)
+    oc = o.encrypt(pt, o.L, 2.0 ** 40, 7, 0)
+    cmp(ct, oc[None], f)
+    for shift in (1, 37):
+        assert np.array_equal(f.key_export(shift), o.switch_key(o.galois(shift)))
+    assert np.array_equal(f.key_export(F.RELIN), o.switch_key(0))
+    shifts = [1, 37, o.ns - 5]
+    cmp(f.rotate(ct, shifts), o.rotate(oc, shifts), f)
+    r = f.rotate(ct, [3, 9])
+    orr = o.rotate(oc, [3, 9])
+    cmp(f.rotate_sum(ct, r, [1, 2]), o.rotate_sum(oc, orr, [1, 2])[None], f)
+    cmp(f.rotate_sum(None, r, [1, 2]), o.rotate_sum(None, orr, [1, 2])[None], f)
+    cmp(f.rescale(ct), o.rescale(oc)[None], f)
+    assert np.array_equal(f.decrypt_raw(ct)[0], o.decrypt(oc))
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("mode,budget", [(F.FENC_MODE_BATCHED, 1 << 30), (F.FENC_MODE_PER_OP, 1 << 30),
+                                         (F.FENC_MODE_BATCHED, 0)])
+def test_mini_lenet_layers_bit_exact(backend, mode, budget, orc):
+    """Two conv/x^2/pool blocks, compression and two FC layers at N = 2^10."""
+    o, f = orc, make(backend, *SMALL)
+    f.set_mode(mode)
+    f.set_plaintext_budget(budget)
+    r = rng(2)
+    x = r.uniform(0, 1, (4, 1, 14, 14))
+    w1, w2 = r.normal(0, 0.1, (3, 1, 3, 3)), r.normal(0, 0.1, (4, 3, 3, 3))
+    f1, f2 = r.normal(0, 0.1, (8, 16)), r.normal(0, 0.1, (4, 8))
+    Lo = o.fragment_layout(4, 1, 14, 14, 2)
+    lay = f.plan_layout(4, 1, 14, 14, 3, 3, 2)
+    pt = f.encode_fragment(x, lay)
+    assert np.array_equal(pt, o.encode_tensor(Lo, x))
+    ob, fb = o.encrypt_tensor(Lo, x, 3), f.encrypt(pt, lay, 3)
+    cmp(fb, ob, f)
+    steps = [("conv", lambda c: f.conv2d(c, w1), lambda b: o.conv2d(b, w1, pt_budget=budget)[0]),
+             ("square", f.poly_act, lambda b: o.square(b)[0]),
+             ("pool-fragments", f.avgpool2, lambda b: o.avgpool2(b)[0]),
+             ("conv", lambda c: f.conv2d(c, w2), lambda b: o.conv2d(b, w2, pt_budget=budget)[0]),
+             ("square", f.poly_act, lambda b: o.square(b)[0]),
+             ("pool-rotations", f.avgpool2, lambda b: o.avgpool2(b)[0]),
+             ("compress", f.compress, lambda b: o.compress(b)[0]),
+             ("fc", lambda c: f.fc(c, f1), lambda b: o.fc(b, f1)[0]),
+             ("fc", lambda c: f.fc(c, f2), lambda b: o.fc(b, f2)[0])]
+    for name, fl, ol in steps:
+        fb, ob = fl(fb), ol(ob)
+        cmp(fb, ob, f)
+    ref = cnn_ref.fc(cnn_ref.fc(cnn_ref.avgpool2(cnn_ref.square(cnn_ref.conv2d(
+        cnn_ref.avgpool2(cnn_ref.square(cnn_ref.conv2d(x, w1))), w2))), f1), f2)
+    assert np.max(np.abs(f.decrypt(fb) - ref)) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("budget", [1 << 30, 0])
+@pytest.mark.parametrize("case", [
+    dict(x=(2, 4, 8, 8), w=(4, 4, 3, 3), stride=2, pad=1, groups=1, S=2),    # stride by discarding, masks
+    dict(x=(2, 4, 8, 8), w=(4, 1, 3, 3), stride=1, pad=1, groups=4, S=2),    # depthwise
+    dict(x=(2, 3, 8, 8), w=(5, 3, 3, 3), stride=1, pad=1, groups=1, S=1),    # outer rotations, ragged channels
+    dict(x=(16, 2, 8, 8), w=(5, 2, 5, 5), stride=1, pad=0, groups=1, S=1),   # C' = 1: scalar MAC only
+    dict(x=(1, 1, 12, 12), w=(6, 1, 5, 5), stride=1, pad=0, groups=1, S=1),  # replicated single channel
+])
+def test_conv_variants_bit_exact(backend, budget, case, orc):
+    o, f = orc, make(backend, *SMALL)
+    f.set_plaintext_budget(budget)
+    r = rng(3)
+    x, w = r.uniform(0, 1, case["x"]), r.normal(0, 0.1, case["w"])
+    Lo = o.fragment_layout(*case["x"], case["S"])
+    lay = f.plan_layout(*case["x"], case["w"][2], case["w"][0], case["S"])
+    ob, fb = o.encrypt_tensor(Lo, x, 5), f.encrypt(f.encode_fragment(x, lay), lay, 5)
+    yo, cnt = o.conv2d(ob, w, case["stride"], case["pad"], case["groups"], pt_budget=budget)
+    f.stats_reset()
+    yf = f.conv2d(fb, w, case["stride"], case["pad"], case["groups"])
+    cmp(yf, yo, f)
+    st = f.stats()
+    assert (st["rot_inner"], st["rot_outer"]) == (cnt["inner_rot"], cnt["outer_rot"])
+    want = cnn_ref.conv2d(x, w, case["stride"], case["pad"], case["groups"])
+    assert np.max(np.abs(f.decrypt(yf) - want)) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_single_conv_layer_benchmark_small_config(backend):
+    """1x28x28 image, conv 1->6 5x5 valid, N=2^13, 4 x 40-bit primes + 1 special, scale 2^30."""
+    params = (13, 4, 40, 1, 40, 4, 30, 1)
+    o, f = P.Oracle(*params), make(backend, *params)
+    r = rng(4)
+    x, w = r.uniform(0, 1, (1, 1, 28, 28)), r.normal(0, 0.1, (6, 1, 5, 5))
+    Lo = o.plan_layout(1, 1, 28, 28, 5, 6)
+    lay = f.plan_layout(1, 1, 28, 28, 5, 6)
+    assert (lay.S, lay.chan_per_ct, lay.replicate) == (Lo["S"], Lo["cpc"], Lo["rep"]) == (1, 4, 1)
+    ob, fb = o.encrypt_tensor(Lo, x, 9), f.encrypt(f.encode_fragment(x, lay), lay, 9)
+    cmp(fb, ob, f)
+    yo, cnt = o.conv2d(ob, w)
+    yf = f.conv2d(fb, w)
+    cmp(yf, yo, f)
+    assert cnt["inner_rot"] == 24 and cnt["outer_rot"] == 0 and yf.n_ct == 2
+    # At Delta = 2^30 with one 40-bit special prime each key switch adds slot
+    # noise of std ~ 3.2 * sqrt(4 N) * sqrt(N) / 2^30 ~ 5e-5; 24 rotations
+    # weighted by |w| ~ 0.1 keep the maximum error below 5e-4.
+    assert np.max(np.abs(f.decrypt(yf) - cnn_ref.conv2d(x, w))) < 5e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_errors_are_reported_not_launched(backend, orc):
+    f = make(backend, *SMALL)
+    with pytest.raises(F.FencError) as e:
+        F.Fenc(10, 8, 50, 1, 50, 3, 40, 1, lib_path=f.lib._name if backend == "emu" else None)
+    assert e.value.code == -1          # fewer special primes than digit limbs
+    lay = f.plan_layout(2, 4, 8, 8, 3, 4, 2)
+    ct = f.encrypt(f.encode_fragment(np.zeros((2, 4, 8, 8)), lay), lay, 1)
+    with pytest.raises(F.FencError) as e:
+        f.conv2d(ct, np.zeros((4, 4, 3, 3)), stride=4)       # stride must divide S
+    assert e.value.code == -8
+    with pytest.raises(F.FencError) as e:
+        f.poly_act(ct, (0.5, 0.0, 1.0))
+    assert e.value.code == -8
+    with pytest.raises(F.FencError) as e:
+        f.fc(ct, np.zeros((4, 4)))                            # fc needs a vector layout
+    assert e.value.code == -6
+    lay0 = lay.copy()
+    lay0.level = 0
+    c0 = f.encrypt(f.encode_fragment(np.zeros((2, 4, 8, 8)), lay0)[:, :1], lay0, 1)
+    with pytest.raises(F.FencError) as e:
+        f.conv2d(c0, np.zeros((4, 4, 3, 3)), pad=1)
+    assert e.value.code == -4
+    f.keygen([1], relin=False, strict=True)
+    with pytest.raises(F.FencError) as e:
+        f.rotate(ct, [2])
+    assert e.value.code == -3
