@@ -157,7 +157,8 @@ Ct rescale(const Context& C, const Ct& x);
 Ct add(const Context& C, const Ct& a, const Ct& b);
 Ct mul_plain(const Context& C, const Ct& a, const RPoly& pt, double pt_scale);
 Ct mul_scalar(const Context& C, const Ct& a, i64 s, double s_scale);
-Ct square_relin(Context& C, const Ct& a);   // tensor, relinearise, no rescale
+// k * a^2: tensor product scaled by the integer k, relinearised, no rescale
+Ct square_relin(Context& C, const Ct& a, i64 k = 1);
 
 // ---------------------------------------------------------------- encoding
 // m = round(scale * tau^{-1}(z)), complex slots z (ns entries), reduced mod primes

@@ -266,7 +266,7 @@ int orc_rescale(void* c, const uint64_t* ct, int level, uint64_t* out) {
 int orc_square_relin(void* c, const uint64_t* ct, int level, uint64_t* out) {
   GUARD_BEGIN
   Context* C = (Context*)c;
-  ct_to(*C, square_relin(*C, ct_from(*C, ct, level, 1.0)), out);
+  ct_to(*C, square_relin(*C, ct_from(*C, ct, level, 1.0), 1), out);
   return 0;
   GUARD_END(-1)
 }

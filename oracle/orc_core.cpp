@@ -408,14 +408,17 @@ std::vector<RPoly> mod_up(const Context& C, const RPoly& d, int level) {
   std::vector<RPoly> out;
   for (int j = 0; j < beta; j++) {
     const int lo = j * C.alpha, hi = std::min((j + 1) * C.alpha, level + 1);
-    // y_i = [d_i * (Qj/q_i)^{-1}]_{q_i}
-    std::vector<Vec> y(hi - lo, Vec(C.N));
+    // y_i = [d_i * (Qj/q_i)^{-1}]_{q_i}, centred in (-q_i/2, q_i/2]
+    std::vector<std::vector<i64>> y(hi - lo, std::vector<i64>(C.N));
     for (int i = lo; i < hi; i++) {
       u64 qi = C.primes[i], hat = 1;
       for (int i2 = lo; i2 < hi; i2++)
         if (i2 != i) hat = mulm(hat, C.primes[i2] % qi, qi);
       u64 hinv = invm(hat, qi);
-      for (int c = 0; c < C.N; c++) y[i - lo][c] = mulm(d.c[i][c], hinv, qi);
+      for (int c = 0; c < C.N; c++) {
+        u64 v = mulm(d.c[i][c], hinv, qi);
+        y[i - lo][c] = v <= (qi - 1) / 2 ? (i64)v : (i64)v - (i64)qi;
+      }
     }
     RPoly r = poly_zero(C, ext);
     for (size_t l = 0; l < ext.size(); l++) {
@@ -429,7 +432,7 @@ std::vector<RPoly> mod_up(const Context& C, const RPoly& d, int level) {
         u64 hat = 1;   // [Qj / q_i]_t
         for (int i2 = lo; i2 < hi; i2++)
           if (i2 != i) hat = mulm(hat, C.primes[i2] % qt, qt);
-        for (int c = 0; c < C.N; c++) r.c[l][c] = addm(r.c[l][c], mulm(y[i - lo][c] % qt, hat, qt), qt);
+        for (int c = 0; c < C.N; c++) r.c[l][c] = addm(r.c[l][c], mulm(from_i64(y[i - lo][c], qt), hat, qt), qt);
       }
     }
     out.push_back(r);
@@ -440,13 +443,17 @@ std::vector<RPoly> mod_up(const Context& C, const RPoly& d, int level) {
 RPoly mod_down(const Context& C, const RPoly& a, int level) {
   RPoly r = poly_zero(C, q_basis(level));
   const int off = level + 1;   // P limbs follow the level+1 Q limbs in qp_basis
-  std::vector<Vec> y(C.K, Vec(C.N));
+  // y_k = [a_{p_k} (P/p_k)^{-1}]_{p_k}, centred in (-p_k/2, p_k/2]
+  std::vector<std::vector<i64>> y(C.K, std::vector<i64>(C.N));
   for (int k = 0; k < C.K; k++) {
     u64 pk = C.primes[C.L + 1 + k], hat = 1;
     for (int k2 = 0; k2 < C.K; k2++)
       if (k2 != k) hat = mulm(hat, C.primes[C.L + 1 + k2] % pk, pk);
     u64 hinv = invm(hat, pk);
-    for (int c = 0; c < C.N; c++) y[k][c] = mulm(a.c[off + k][c], hinv, pk);
+    for (int c = 0; c < C.N; c++) {
+      u64 v = mulm(a.c[off + k][c], hinv, pk);
+      y[k][c] = v <= (pk - 1) / 2 ? (i64)v : (i64)v - (i64)pk;
+    }
   }
   for (int i = 0; i <= level; i++) {
     u64 qi = C.primes[i];
@@ -459,7 +466,7 @@ RPoly mod_down(const Context& C, const RPoly& a, int level) {
     }
     for (int c = 0; c < C.N; c++) {
       u64 conv = 0;
-      for (int k = 0; k < C.K; k++) conv = addm(conv, mulm(y[k][c] % qi, hat[k], qi), qi);
+      for (int k = 0; k < C.K; k++) conv = addm(conv, mulm(from_i64(y[k][c], qi), hat[k], qi), qi);
       r.c[i][c] = mulm(subm(a.c[i][c], conv, qi), Pinv, qi);
     }
   }
@@ -589,10 +596,10 @@ Ct mul_scalar(const Context& C, const Ct& a, i64 s, double s_scale) {
   return y;
 }
 
-Ct square_relin(Context& C, const Ct& a) {
-  RPoly d0 = poly_mul(C, a.c0, a.c0);
-  RPoly d1 = poly_scalar(C, poly_mul(C, a.c0, a.c1), 2);
-  RPoly d2 = poly_mul(C, a.c1, a.c1);
+Ct square_relin(Context& C, const Ct& a, i64 k) {
+  RPoly d0 = poly_scalar(C, poly_mul(C, a.c0, a.c0), k);
+  RPoly d1 = poly_scalar(C, poly_mul(C, a.c0, a.c1), 2 * k);
+  RPoly d2 = poly_scalar(C, poly_mul(C, a.c1, a.c1), k);
   std::vector<RPoly> up = mod_up(C, d2, a.level);
   RPoly a0, a1;
   key_inner_product(C, up, 0, a.level, a0, a1);
@@ -602,7 +609,7 @@ Ct square_relin(Context& C, const Ct& a) {
   y.c1 = d1;
   poly_add_inplace(C, y.c1, mod_down(C, a1, a.level));
   y.level = a.level;
-  y.scale = a.scale * a.scale;
+  y.scale = ((double)k * a.scale) * a.scale;
   return y;
 }
 

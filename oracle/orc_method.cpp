@@ -175,9 +175,11 @@ void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, dou
         }
 }
 
+// code = round half away from zero of the binary64 product w * scale (exact
+// integer conversion; above 2^53 the product is already an integer)
 i64 weight_code(double w, double scale) {
   double v = w * scale;
-  if (std::fabs(v) >= std::ldexp(1.0, 52)) throw std::runtime_error("weight_code: out of range");
+  if (!(std::fabs(v) < std::ldexp(1.0, 62))) throw std::runtime_error("weight_code: out of range");
   return (i64)std::round(v);
 }
 
@@ -428,11 +430,16 @@ std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& i
   return out;
 }
 
+// x^2 keeping the scale near Delta: the tensor product is multiplied by the
+// integer k = round((Delta * q_l) / s^2), so (k s^2) / q_l after the rescale
 std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                            Counts& cnt) {
+  const double s = Lin.scale, ql = (double)C.primes[Lin.level];
+  i64 k = (i64)std::round((delta_of(C) * ql) / (s * s));
+  if (k < 1) k = 1;
   std::vector<Ct> out;
   for (const Ct& x : in) {
-    Ct y = square_relin(C, x);
+    Ct y = square_relin(C, x, k);
     cnt.relin++; cnt.ks++; cnt.modup++; cnt.moddown++;
     y = rescale(C, y);
     cnt.rescale++;
@@ -440,7 +447,7 @@ std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>&
   }
   Lout = Lin;
   Lout.level = Lin.level - 1;
-  Lout.scale = Lin.scale * Lin.scale / (double)C.primes[Lin.level];
+  Lout.scale = (((double)k * s) * s) / ql;
   for (Ct& y : out) y.scale = Lout.scale;
   return out;
 }

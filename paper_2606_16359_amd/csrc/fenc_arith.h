@@ -58,6 +58,11 @@ FENC_HD inline double red(double x, double q, double qinv) {
 
 // representative in [0, q) of x in (-q, q)
 FENC_HD inline double norm(double x, double q) { return x < 0 ? x + q : x; }
+// centred representative in [-(q-1)/2, (q-1)/2] of x in (-q, q)
+FENC_HD inline double centre(double x, double q) {
+  const double t = x < 0 ? x + q : x;
+  return t > (q - 1) * 0.5 ? t - q : t;
+}
 // representative in [0, q) of any |x| < 2^52
 FENC_HD inline double full_norm(double x, double q, double qinv) {
   double r = red(x, q, qinv);

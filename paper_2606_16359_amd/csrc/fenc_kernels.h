@@ -206,7 +206,8 @@ FENC_HD void ntt_inv_cols(X& x, const NttArgs& a) {
 
 // ------------------------------------------------------------------ ModUp
 // Fast base conversion of every digit of c1 (coefficient form) to the other
-// limbs of Q_l U P:  y_i = [x_i * (Qj/q_i)^-1]_{q_i},  out_t = sum_i y_i [Qj/q_i]_t.
+// limbs of Q_l U P:  y_i = [x_i * (Qj/q_i)^-1]_{q_i} (centred),
+// out_t = sum_i y_i [Qj/q_i]_t.
 // The digit's own limbs are copied from the NTT-form input.
 // Table per digit j (stride tstride d2 entries): hinv[alpha], hat[le][alpha].
 struct ModUpArgs {
@@ -236,7 +237,7 @@ FENC_HD void modup_fbc(X& x, const ModUpArgs& a) {
       const int p = a.eprime[lo + i];
       const double q = a.pq[p].x;
       const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
-      y[i] = norm(mulmod_c(v, tab[i].x, tab[i].y, q), q);
+      y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);
     }
     for (int l = 0; l < a.le; l++) {
       if (l >= lo && l < hi) {
@@ -310,7 +311,8 @@ FENC_HD void kip(X& x, const KipArgs& a) {
 }
 
 // ------------------------------------------------------------------ ModDown
-// conv_i = sum_k [acc_{p_k} (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}  (coefficient form)
+// conv_i = sum_k [acc_{p_k} (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}  (coefficient form,
+// the bracket centred)
 // Table: hinv[K], hat[nl][K].
 struct ModDownArgs {
   const u64* acc;        // [nout][2][le][N], P limbs in coefficient form
@@ -333,7 +335,7 @@ FENC_HD void moddown_fbc(X& x, const ModDownArgs& a) {
     for (int k = 0; k < a.K; k++) {
       const int p = a.eprime[a.nl + k];
       const double q = a.pq[p].x;
-      y[k] = norm(mulmod_c(u2d(in[(long long)(a.nl + k) * N]), a.tab[k].x, a.tab[k].y, q), q);
+      y[k] = centre(mulmod_c(u2d(in[(long long)(a.nl + k) * N]), a.tab[k].x, a.tab[k].y, q), q);
     }
     u64* out = a.conv + op * a.nl * N + c;
     for (int i = 0; i < a.nl; i++) {
@@ -501,13 +503,14 @@ FENC_HD void gmac(X& x, const GmacArgs& a) {
 }
 
 // ------------------------------------------------------------------ tensor / key / encryption
-// (d0, d1, d2) = (c0^2, 2 c0 c1, c1^2); d0,d1 into out (ct [2][nl][N]), d2 into d2buf [nl][N]
+// (d0, d1, d2) = k (c0^2, 2 c0 c1, c1^2); d0,d1 into out (ct [2][nl][N]), d2 into d2buf [nl][N]
 struct SquareArgs {
   const u64* in;
   u64* out;
   u64* d2buf;
   int nl, logn;
   long long ct_stride;   // elements per ct (in and out)
+  const d2* k;           // [nl] (k mod q_i, /q)
   const d2* pq;
 };
 
@@ -521,10 +524,11 @@ FENC_HD void tensor_square(X& x, const SquareArgs& a) {
     const u64* in = a.in + b * a.ct_stride + i * N + c;
     const double c0 = u2d(in[0]), c1 = u2d(in[a.nl * N]);
     u64* out = a.out + b * a.ct_stride + i * N + c;
-    const double m01 = mulmod(c0, c1, q, qi);
-    out[0] = d2u(norm(mulmod(c0, c0, q, qi), q));
+    const d2 k = a.k[i];
+    const double m01 = mulmod_c(mulmod(c0, c1, q, qi), k.x, k.y, q);
+    out[0] = d2u(norm(mulmod_c(mulmod(c0, c0, q, qi), k.x, k.y, q), q));
     out[a.nl * N] = d2u(norm(red(m01 + m01, q, qi), q));
-    a.d2buf[(long long)b * a.nl * N + i * N + c] = d2u(norm(mulmod(c1, c1, q, qi), q));
+    a.d2buf[(long long)b * a.nl * N + i * N + c] = d2u(norm(mulmod_c(mulmod(c1, c1, q, qi), k.x, k.y, q), q));
   });
 }
 

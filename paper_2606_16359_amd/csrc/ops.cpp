@@ -566,6 +566,7 @@ static void run_pool(Ctx& C, const PoolPlan& P, const u64* in, u64* out, fb::Str
 struct SquarePlan : Plan {
   int level = 0, n = 0;
   KsStage ks;
+  d2* kf = nullptr;   // [nl] scale-restoring integer k mod q_i
 };
 
 static void run_square(Ctx& C, const SquarePlan& P, const u64* in, u64* out, fb::Stream s) {
@@ -578,7 +579,7 @@ static void run_square(Ctx& C, const SquarePlan& P, const u64* in, u64* out, fb:
   const bool per_op = C.mode == FENC_MODE_PER_OP;
   for (int b0 = 0; b0 < P.n; b0 += per_op ? 1 : P.n) {
     const int nb = per_op ? 1 : P.n;
-    fk::SquareArgs a{in + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, C.pq};
+    fk::SquareArgs a{in + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, P.kf, C.pq};
     timed(C, "tensor_square", 5.0 * nb * nl * C.N * 8, s, [&] {
       fb::tensor_square({(unsigned)std::max(1, C.N / 256), (unsigned)nl, (unsigned)nb}, std::min(256, C.N), s, a);
     });
@@ -1270,9 +1271,14 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
   fenc_ctx& C = *ctx;
   Layout Lin = from_pub(C, &in->lay);
   if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the activation");
+  // x^2 with the tensor product multiplied by the integer k = round(Delta q_l / s^2):
+  // the output scale k s^2 / q_l stays within 2^-11 of Delta without a level
+  const double s0 = Lin.scale, ql = (double)C.primes[Lin.level];
+  int64_t kk = (int64_t)std::round((C.Delta * ql) / (s0 * s0));
+  if (kk < 1) kk = 1;
   Layout Lout = Lin;
   Lout.level = Lin.level - 1;
-  Lout.scale = Lin.scale * Lin.scale / (double)C.primes[Lin.level];
+  Lout.scale = (((double)kk * s0) * s0) / ql;
   out->lay = to_pub(C, Lout);
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
@@ -1290,6 +1296,9 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
       tails.push_back(fk::TailItem{b, b, 0, 0});
     }
     p->ks = make_ks(C, items, tails, {}, p->owned);
+    std::vector<d2> kf(Lin.level + 1);
+    for (int i = 0; i <= Lin.level; i++) kf[i] = cpair((uint64_t)kk % C.primes[i], C.primes[i]);
+    p->kf = upload(C, kf, p->owned);
     return p;
   });
   run_square(C, P, in->data, out->data, (fb::Stream)stream);

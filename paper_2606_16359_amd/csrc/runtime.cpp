@@ -522,9 +522,11 @@ u64* encode_plaintexts(Ctx& C, const std::vector<std::vector<double>>& slots, do
   return d;
 }
 
+// Integer weight code: the binary64 product w * scale rounded half away from
+// zero (above 2^53 the product is already an integer), |code| < 2^62.
 int64_t weight_code(double w, double scale) {
   const double v = w * scale;
-  if (!(std::fabs(v) < 4503599627370496.0)) fail(FENC_EINVAL, "weight too large for its scale");
+  if (!(std::fabs(v) < 4611686018427387904.0)) fail(FENC_EINVAL, "weight too large for its scale");
   return (int64_t)std::round(v);
 }
 

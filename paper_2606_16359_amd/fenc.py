@@ -62,11 +62,18 @@ _LIBS = {}
 
 def load(path=None):
     """Load the library (default: the in-tree HIP build)."""
+    hip = path is None
     path = path or _build.LIB
     if path in _LIBS:
         return _LIBS[path]
     if not os.path.exists(path):
         raise RuntimeError(f"FEnc HIP library not built: {path} (run __graft_entry__.build())")
+    if hip:
+        # PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading it
+        # first makes the dynamic loader bind this library to the same runtime,
+        # so there is one HIP runtime per process and library launches on torch
+        # streams can be captured into torch's hipGraphs.
+        import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, i32, u32, d, u64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_double, C.c_uint64
     P, L, B = C.POINTER(Params), C.POINTER(Layout), C.POINTER(CtBatch)

@@ -212,7 +212,7 @@ def crt(residues, primes):
     return x % Q, Q
 
 
-def test_mod_up_is_digit_lift_plus_small_multiple(orc_small):
+def test_mod_up_is_centred_digit_lift_plus_small_multiple(orc_small):
     o = orc_small
     qs = o.primes()
     level = o.L
@@ -224,16 +224,18 @@ def test_mod_up_is_digit_lift_plus_small_multiple(orc_small):
         dig = list(range(j * o.alpha, min((j + 1) * o.alpha, level + 1)))
         for c in range(0, o.N, 7):
             a, Qj = crt([d[i][c] for i in dig], [qs[i] for i in dig])
+            if a > Qj // 2:
+                a -= Qj        # centred representative of the digit
             us = set()
             for li, t in enumerate(basis):
                 diff = (int(ext[j][li][c]) - a) % qs[t]
                 if t in dig:          # the digit's own limbs are copied unchanged
                     assert diff == 0
                     continue
-                found = [u for u in range(len(dig)) if (u * Qj) % qs[t] == diff]
+                found = [u for u in range(-len(dig), len(dig) + 1) if (u * Qj) % qs[t] == diff]
                 assert found, (j, c, t)
                 us.add(found[0])
-            assert len(us) == 1     # one integer a + u*Qj, 0 <= u < |D_j|, in every prime
+            assert len(us) == 1     # one integer a + u*Qj, |u| <= |D_j|, in every prime
 
 
 def test_mod_down_divides_by_P(orc_small):
@@ -254,8 +256,8 @@ def test_mod_down_divides_by_P(orc_small):
                           np.array([[xi % qs[i] for xi in x] for i in range(level + 1)], dtype=np.uint64))
     for i in range(level + 1):
         for c in range(o.N):
-            # y < P so its P-part converts to y + v P with 0 <= v < K, i.e. result x - v
-            cands = [(x[c] - v) % qs[i] for v in range(o.np)]
+            # y < P/2 so its P-part converts to y + v P with |v| <= K, i.e. result x - v
+            cands = [(x[c] - v) % qs[i] for v in range(-o.np, o.np + 1)]
             assert int(got[i][c]) in cands
 
 
@@ -305,7 +307,7 @@ def test_square_relin_decrypts_to_square():
     rng = np.random.default_rng(9)
     z = rng.uniform(-1, 1, o.ns)
     ct = o.encrypt(o.encode(z, None, 2.0 ** 30), o.L, 2.0 ** 30, seed=6)
-    sq = o.rescale(o.square_relin(ct))
+    sq = o.rescale(o.square_relin(ct))     # k = 1 through the C entry point
     got = o.decode(o.decrypt(sq)[0], 2.0 ** 60 / o.primes()[o.L]).real
     assert np.max(np.abs(got - z * z)) < 1e-4
 

@@ -189,3 +189,21 @@ def test_errors_are_reported_not_launched(backend, orc):
     with pytest.raises(F.FencError) as e:
         f.rotate(ct, [2])
     assert e.value.code == -3
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_scalar_weights_after_activation_scale_drop(backend, orc):
+    """x^2 leaves scale Delta^2/q (about 2^30 here); the next C'=1 convolution
+    restores Delta with weight codes near 2^58."""
+    o, f = orc, make(backend, *SMALL)
+    r = rng(5)
+    x = r.uniform(0, 1, (16, 2, 8, 8))
+    w1, w2 = r.normal(0, 0.1, (2, 2, 3, 3)), r.normal(0, 0.1, (3, 2, 3, 3))
+    Lo = o.fragment_layout(16, 2, 8, 8, 1)
+    lay = f.plan_layout(16, 2, 8, 8, 3, 2, 1)
+    ob, fb = o.encrypt_tensor(Lo, x, 6), f.encrypt(f.encode_fragment(x, lay), lay, 6)
+    ob = o.conv2d(o.square(o.conv2d(ob, w1)[0])[0], w2)[0]
+    fb = f.conv2d(f.poly_act(f.conv2d(fb, w1)), w2)
+    cmp(fb, ob, f)
+    want = cnn_ref.conv2d(cnn_ref.square(cnn_ref.conv2d(x, w1)), w2)
+    assert np.max(np.abs(f.decrypt(fb) - want)) < 1e-4
