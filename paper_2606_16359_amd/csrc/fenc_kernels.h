@@ -45,121 +45,94 @@ struct NttArgs {
   const d2* pq;               // [prime] (q, 1/q)
   const d2* ninv;             // [prime] (N^-1, N^-1/q), inverse only
   int logn, n1, n2;
-  int cols;                   // columns per block (column pass)
-  int cpb;                    // chunks per block (row pass)
+  int lcols;                  // log2 of the columns per block (column pass)
+  int lcpb;                   // log2 of the chunks per block (row pass)
 };
 
+constexpr int kRadixBits = 3;   // butterfly stages per register round
+
+// Stage index of member f (< 2^k) of the butterfly group whose other stage
+// bits are `rest`, with the k-bit field at bit `lo`.
+FENC_HD inline int member(int rest, int f, int lo, int k) {
+  return ((((rest >> lo) << k) | f) << lo) | (rest & ((1 << lo) - 1));
+}
+
+// One register round of forward (Cooley-Tukey) stages s0..s0+k-1 of a pass
+// with P stage bits: local stage s pairs stage-index bit P-1-s.  tw_of(s, a)
+// is the twiddle of the butterfly whose upper element has stage index a.
+// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2] (k <= 3 keeps
+// every product operand below 3q and every sum below 4q < 2^52).
+template <class LD, class ST, class TW>
+FENC_HD inline void fwd_round(int rest, int s0, int k, int P, double q, double qi, LD ld, ST st, TW tw_of) {
+  double v[1 << kRadixBits];
+  const int lo = P - s0 - k;
+  for (int f = 0; f < (1 << k); f++) v[f] = ld(member(rest, f, lo, k));
+  for (int s = 0; s < k; s++) {
+    const int half = 1 << (k - 1 - s);
+    for (int f = 0; f < (1 << k); f++) {
+      if (f & half) continue;
+      const d2 w = tw_of(s0 + s, member(rest, f, lo, k));
+      const double u = v[f], t = mulmod_c(v[f | half], w.x, w.y, q);
+      v[f] = u + t;
+      v[f | half] = u - t;
+    }
+  }
+  for (int f = 0; f < (1 << k); f++) st(member(rest, f, lo, k), red(v[f], q, qi));
+}
+
+// One register round of inverse (Gentleman-Sande) stages s0..s0+k-1: local
+// stage s pairs stage-index bit s.  Inputs and outputs have magnitude < q.
+template <class LD, class ST, class TW>
+FENC_HD inline void inv_round(int rest, int s0, int k, double q, double qi, LD ld, ST st, TW tw_of) {
+  double v[1 << kRadixBits];
+  const int lo = s0;
+  for (int f = 0; f < (1 << k); f++) v[f] = ld(member(rest, f, lo, k));
+  for (int s = 0; s < k; s++) {
+    const int half = 1 << s;
+    for (int f = 0; f < (1 << k); f++) {
+      if (f & half) continue;
+      const d2 w = tw_of(s0 + s, member(rest, f, lo, k));
+      const double xv = v[f], yv = v[f | half];
+      v[f] = red(xv + yv, q, qi);
+      v[f | half] = mulmod_c(xv - yv, w.x, w.y, q);
+    }
+  }
+  for (int f = 0; f < (1 << k); f++) st(member(rest, f, lo, k), v[f]);
+}
+
+// Column pass: stages acting on 2^n1 elements at stride 2^n2 ("columns").  A
+// block stages 2^lcols adjacent columns; the column index is the low part of
+// the thread's group index so neighbouring threads touch neighbouring words.
+// Forward: the first n1 stages; inverse: the last n1 stages, then * N^-1.
 template <class X>
 FENC_HD void ntt_fwd_cols(X& x, const NttArgs& a) {
   const int row = x.by;
   const int p = a.pm.p[row % a.pm.n];
   if (p == kSkip) return;
-  const int n1 = a.n1, n2 = a.n2, C = a.cols, R = 1 << n1, T = x.nt;
+  const int n1 = a.n1, n2 = a.n2, sb = a.lcols, T = x.nt, bm = (1 << sb) - 1;
   const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn);
   u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn);
-  const int col0 = x.bx * C;
+  const long long col0 = (long long)x.bx << sb;
   const double q = a.pq[p].x, qi = a.pq[p].y;
   const d2* tw = a.tw + ((long long)p << a.logn);
-  double* s = x.smem;
-  x.phase([&](int t) {
-    for (int e = t; e < R * C; e += T) {
-      const int hi = e / C, c = e % C;
-      s[e] = u2d(src[((long long)hi << n2) + col0 + c]);
-    }
-  });
-  for (int st = 0; st < n1; st++) {
-    const int th = 1 << (n1 - 1 - st);
+  double* sm = x.smem;
+  for (int s0 = 0; s0 < n1; s0 += kRadixBits) {
+    const int k = n1 - s0 < kRadixBits ? n1 - s0 : kRadixBits;
+    const bool first = s0 == 0, last = s0 + k == n1;
     x.phase([&](int t) {
-      for (int b = t; b < (R / 2) * C; b += T) {
-        const int c = b % C, bb = b / C;
-        const int grp = bb / th, off = bb % th;
-        const int hi = grp * 2 * th + off;
-        const d2 w = tw[(1 << st) + grp];
-        const double u = s[hi * C + c];
-        const double v = mulmod_c(s[(hi + th) * C + c], w.x, w.y, q);
-        s[hi * C + c] = red(u + v, q, qi);
-        s[(hi + th) * C + c] = red(u - v, q, qi);
+      for (int g = t; g < (1 << (n1 + sb - k)); g += T) {
+        const int c = g & bm, rest = g >> sb;
+        fwd_round(
+            rest, s0, k, n1, q, qi,
+            [&](int hi) { return first ? u2d(src[((long long)hi << n2) + col0 + c]) : sm[(hi << sb) | c]; },
+            [&](int hi, double v) {
+              if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(v, q));
+              else sm[(hi << sb) | c] = v;
+            },
+            [&](int st, int hi) { return tw[(1 << st) + (hi >> (n1 - st))]; });
       }
     });
   }
-  x.phase([&](int t) {
-    for (int e = t; e < R * C; e += T) {
-      const int hi = e / C, c = e % C;
-      dst[((long long)hi << n2) + col0 + c] = d2u(norm(s[e], q));
-    }
-  });
-}
-
-template <class X>
-FENC_HD void ntt_fwd_rows(X& x, const NttArgs& a) {
-  const int row = x.by;
-  const int p = a.pm.p[row % a.pm.n];
-  if (p == kSkip) return;
-  const int n1 = a.n1, n2 = a.n2, logn = a.logn, Lc = 1 << n2, T = x.nt;
-  const int E = a.cpb * Lc;
-  const long long e0 = (long long)x.bx * E;
-  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn) + e0;
-  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn) + e0;
-  const double q = a.pq[p].x, qi = a.pq[p].y;
-  const d2* tw = a.tw + ((long long)p << logn);
-  double* s = x.smem;
-  x.phase([&](int t) {
-    for (int e = t; e < E; e += T) s[e] = u2d(src[e]);
-  });
-  for (int st = n1; st < logn; st++) {
-    const int td = 1 << (logn - 1 - st);
-    x.phase([&](int t) {
-      for (int b = t; b < E / 2; b += T) {
-        const int grp = b / td, off = b % td;
-        const int lo = grp * 2 * td + off;                          // local index within the block
-        const long long gi = (e0 + lo) / (2 * td);                  // global butterfly group
-        const d2 w = tw[(1LL << st) + gi];
-        const double u = s[lo];
-        const double v = mulmod_c(s[lo + td], w.x, w.y, q);
-        s[lo] = red(u + v, q, qi);
-        s[lo + td] = red(u - v, q, qi);
-      }
-    });
-  }
-  x.phase([&](int t) {
-    for (int e = t; e < E; e += T) dst[e] = d2u(norm(s[e], q));
-  });
-}
-
-template <class X>
-FENC_HD void ntt_inv_rows(X& x, const NttArgs& a) {
-  const int row = x.by;
-  const int p = a.pm.p[row % a.pm.n];
-  if (p == kSkip) return;
-  const int n2 = a.n2, logn = a.logn, Lc = 1 << n2, T = x.nt;
-  const int E = a.cpb * Lc;
-  const long long e0 = (long long)x.bx * E;
-  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn) + e0;
-  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn) + e0;
-  const double q = a.pq[p].x, qi = a.pq[p].y;
-  const d2* tw = a.tw + ((long long)p << logn);
-  double* s = x.smem;
-  x.phase([&](int t) {
-    for (int e = t; e < E; e += T) s[e] = u2d(src[e]);
-  });
-  for (int u = 0; u < n2; u++) {
-    const int td = 1 << u;
-    const long long h = (1LL << logn) / (2 * td);
-    x.phase([&](int t) {
-      for (int b = t; b < E / 2; b += T) {
-        const int grp = b / td, off = b % td;
-        const int lo = grp * 2 * td + off;
-        const long long gi = (e0 + lo) / (2 * td);
-        const d2 w = tw[h + gi];
-        const double xv = s[lo], yv = s[lo + td];
-        s[lo] = red(xv + yv, q, qi);
-        s[lo + td] = mulmod_c(xv - yv, w.x, w.y, q);
-      }
-    });
-  }
-  x.phase([&](int t) {
-    for (int e = t; e < E; e += T) dst[e] = d2u(norm(red(s[e], q, qi), q));
-  });
 }
 
 template <class X>
@@ -167,41 +140,106 @@ FENC_HD void ntt_inv_cols(X& x, const NttArgs& a) {
   const int row = x.by;
   const int p = a.pm.p[row % a.pm.n];
   if (p == kSkip) return;
-  const int n1 = a.n1, n2 = a.n2, C = a.cols, R = 1 << n1, T = x.nt, logn = a.logn;
-  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn);
-  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn);
-  const int col0 = x.bx * C;
+  const int n1 = a.n1, n2 = a.n2, sb = a.lcols, T = x.nt, bm = (1 << sb) - 1;
+  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn);
+  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn);
+  const long long col0 = (long long)x.bx << sb;
   const double q = a.pq[p].x, qi = a.pq[p].y;
-  const d2* tw = a.tw + ((long long)p << logn);
+  const d2* tw = a.tw + ((long long)p << a.logn);
   const d2 ni = a.ninv[p];
-  double* s = x.smem;
-  x.phase([&](int t) {
-    for (int e = t; e < R * C; e += T) {
-      const int hi = e / C, c = e % C;
-      s[e] = u2d(src[((long long)hi << n2) + col0 + c]);
-    }
-  });
-  for (int u = n2; u < logn; u++) {
-    const int th = 1 << (u - n2);
-    const long long h = (1LL << logn) >> (u + 1);
+  double* sm = x.smem;
+  for (int s0 = 0; s0 < n1; s0 += kRadixBits) {
+    const int k = n1 - s0 < kRadixBits ? n1 - s0 : kRadixBits;
+    const bool first = s0 == 0, last = s0 + k == n1;
     x.phase([&](int t) {
-      for (int b = t; b < (R / 2) * C; b += T) {
-        const int c = b % C, bb = b / C;
-        const int grp = bb / th, off = bb % th;
-        const int hi = grp * 2 * th + off;
-        const d2 w = tw[h + grp];
-        const double xv = s[hi * C + c], yv = s[(hi + th) * C + c];
-        s[hi * C + c] = red(xv + yv, q, qi);
-        s[(hi + th) * C + c] = mulmod_c(xv - yv, w.x, w.y, q);
+      for (int g = t; g < (1 << (n1 + sb - k)); g += T) {
+        const int c = g & bm, rest = g >> sb;
+        inv_round(
+            rest, s0, k, q, qi,
+            [&](int hi) { return first ? u2d(src[((long long)hi << n2) + col0 + c]) : sm[(hi << sb) | c]; },
+            [&](int hi, double v) {
+              if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(mulmod_c(v, ni.x, ni.y, q), q));
+              else sm[(hi << sb) | c] = v;
+            },
+            // global stage u = n2 + st: h = N >> (u+1), group = hi >> (st+1)
+            [&](int st, int hi) { return tw[(1LL << (n1 - st - 1)) + (hi >> (st + 1))]; });
       }
     });
   }
-  x.phase([&](int t) {
-    for (int e = t; e < R * C; e += T) {
-      const int hi = e / C, c = e % C;
-      dst[((long long)hi << n2) + col0 + c] = d2u(norm(mulmod_c(s[e], ni.x, ni.y, q), q));
-    }
-  });
+}
+
+// Row pass: stages acting inside contiguous chunks of 2^n2 elements; a block
+// stages 2^lcpb chunks.  The chunk is the high part of the thread's group
+// index so neighbouring threads touch neighbouring words.  Forward: the last
+// n2 stages; inverse: the first n2 stages.
+template <class X>
+FENC_HD void ntt_fwd_rows(X& x, const NttArgs& a) {
+  const int row = x.by;
+  const int p = a.pm.p[row % a.pm.n];
+  if (p == kSkip) return;
+  const int n1 = a.n1, n2 = a.n2, cb = a.lcpb, T = x.nt;
+  const long long e0 = (long long)x.bx << (n2 + cb);
+  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn) + e0;
+  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn) + e0;
+  const long long chunk0 = (long long)x.bx << cb;
+  const double q = a.pq[p].x, qi = a.pq[p].y;
+  const d2* tw = a.tw + ((long long)p << a.logn);
+  double* sm = x.smem;
+  for (int s0 = 0; s0 < n2; s0 += kRadixBits) {
+    const int k = n2 - s0 < kRadixBits ? n2 - s0 : kRadixBits;
+    const bool first = s0 == 0, last = s0 + k == n2;
+    x.phase([&](int t) {
+      for (int g = t; g < (1 << (n2 + cb - k)); g += T) {
+        const int rest = g & ((1 << (n2 - k)) - 1), ch = g >> (n2 - k);
+        const int base = ch << n2;
+        fwd_round(
+            rest, s0, k, n2, q, qi,
+            [&](int lo) { return first ? u2d(src[base + lo]) : sm[base + lo]; },
+            [&](int lo, double v) {
+              if (last) dst[base + lo] = d2u(norm(v, q));
+              else sm[base + lo] = v;
+            },
+            // global stage S = n1 + st: group = (chunk << st) + (lo >> (n2 - st))
+            [&](int st, int lo) { return tw[(1LL << (n1 + st)) + ((chunk0 + ch) << st) + (lo >> (n2 - st))]; });
+      }
+    });
+  }
+}
+
+template <class X>
+FENC_HD void ntt_inv_rows(X& x, const NttArgs& a) {
+  const int row = x.by;
+  const int p = a.pm.p[row % a.pm.n];
+  if (p == kSkip) return;
+  const int n2 = a.n2, cb = a.lcpb, T = x.nt, logn = a.logn;
+  const long long e0 = (long long)x.bx << (n2 + cb);
+  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn) + e0;
+  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn) + e0;
+  const long long chunk0 = (long long)x.bx << cb;
+  const double q = a.pq[p].x, qi = a.pq[p].y;
+  const d2* tw = a.tw + ((long long)p << logn);
+  double* sm = x.smem;
+  for (int s0 = 0; s0 < n2; s0 += kRadixBits) {
+    const int k = n2 - s0 < kRadixBits ? n2 - s0 : kRadixBits;
+    const bool first = s0 == 0, last = s0 + k == n2;
+    x.phase([&](int t) {
+      for (int g = t; g < (1 << (n2 + cb - k)); g += T) {
+        const int rest = g & ((1 << (n2 - k)) - 1), ch = g >> (n2 - k);
+        const int base = ch << n2;
+        inv_round(
+            rest, s0, k, q, qi,
+            [&](int lo) { return first ? u2d(src[base + lo]) : sm[base + lo]; },
+            [&](int lo, double v) {
+              if (last) dst[base + lo] = d2u(norm(v, q));
+              else sm[base + lo] = v;
+            },
+            // stage u = st: h = N >> (u+1), group = (chunk << (n2-st-1)) + (lo >> (st+1))
+            [&](int st, int lo) {
+              return tw[(1LL << (logn - st - 1)) + ((chunk0 + ch) << (n2 - st - 1)) + (lo >> (st + 1))];
+            });
+      }
+    });
+  }
 }
 
 // ------------------------------------------------------------------ ModUp
@@ -258,21 +296,30 @@ FENC_HD void modup_fbc(X& x, const ModUpArgs& a) {
 }
 
 // ------------------------------------------------------------------ key inner product
-// Output o sums its items: acc_o = sum_items sum_j sigma_g(ext_{ct,j}) * key_j.
-// One item per output is the hoisted rotation; several items (different cts
-// and keys) is the lazy-ModDown sum.
-struct KipItem {
-  int ct;           // index into ext
-  unsigned g;       // Galois element (1: identity)
-  const u64* key;   // [ndig][2][nprimes][N]
+// A group holds up to kKipOut outputs and the keys they use.  For every key
+// the thread loads key_j once and applies it to each output that has an item
+// for that key:  acc_o += sum_j sigma_g(ext_{ct,j}) * key_j.  One key shared
+// by several outputs is the hoisted rotation of several ciphertexts by the
+// same shift; several keys per output is the lazy-ModDown sum.
+constexpr int kKipOut = 8;
+
+struct KipKey {
+  unsigned g;        // Galois element (1: identity)
+  const u64* key;    // [ndig][2][nprimes][N]
+  int item0;         // items[item0 + o]: ext ct index for output o of the group, or -1
+};
+struct KipGroup {
+  int out0, nout;    // outputs out0 .. out0+nout-1
+  int key0, nkey;    // keys key0 .. key0+nkey-1
 };
 
 struct KipArgs {
   const u64* ext;         // [B][beta][le][N]
   u64* acc;               // [nout][2][le][N]
-  const KipItem* items;
-  const int* item_off;    // [nout+1]
-  int o0;                 // first output of the launch
+  const KipGroup* groups;
+  const KipKey* keys;
+  const int* items;
+  int g0;                 // first group of the launch
   int beta, le, logn, nprimes;
   const unsigned char* eprime;
   const d2* pq;
@@ -283,30 +330,34 @@ FENC_HD void kip(X& x, const KipArgs& a) {
   x.phase([&](int t) {
     const long long N = 1LL << a.logn;
     const long long c = (long long)x.bx * x.nt + t;
-    const int l = x.by, o = a.o0 + x.bz;
+    const int l = x.by;
+    const KipGroup G = a.groups[a.g0 + x.bz];
     const int p = a.eprime[l];
     const double q = a.pq[p].x, qi = a.pq[p].y;
-    double a0 = 0, a1 = 0;
-    for (int it = a.item_off[o]; it < a.item_off[o + 1]; it++) {
-      const KipItem I = a.items[it];
-      const long long src = (I.g == 1) ? c : (long long)auto_src((unsigned)c, I.g, a.logn);
-      const u64* e = a.ext + (long long)I.ct * a.beta * a.le * N + l * N + src;
+    double a0[kKipOut], a1[kKipOut];
+    for (int o = 0; o < kKipOut; o++) a0[o] = a1[o] = 0;
+    for (int kk = 0; kk < G.nkey; kk++) {
+      const KipKey K = a.keys[G.key0 + kk];
+      const long long src = (K.g == 1) ? c : (long long)auto_src((unsigned)c, K.g, a.logn);
       for (int j = 0; j < a.beta; j++) {
-        const double v = u2d(e[(long long)j * a.le * N]);
-        const u64* kj = I.key + ((long long)j * 2 * a.nprimes + p) * N + c;
-        a0 += mulmod(v, u2d(kj[0]), q, qi);
-        a1 += mulmod(v, u2d(kj[(long long)a.nprimes * N]), q, qi);
-        if ((j & 3) == 3) {
-          a0 = red(a0, q, qi);
-          a1 = red(a1, q, qi);
+        const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
+        const double k0 = u2d(kj[0]), k1 = u2d(kj[(long long)a.nprimes * N]);
+        for (int o = 0; o < kKipOut; o++) {
+          if (o >= G.nout) break;
+          const int ct = a.items[K.item0 + o];
+          if (ct < 0) continue;
+          const double v = u2d(a.ext[(((long long)ct * a.beta + j) * a.le + l) * N + src]);
+          a0[o] = red(a0[o] + mulmod(v, k0, q, qi), q, qi);
+          a1[o] = red(a1[o] + mulmod(v, k1, q, qi), q, qi);
         }
       }
-      a0 = red(a0, q, qi);
-      a1 = red(a1, q, qi);
     }
-    u64* out = a.acc + (long long)o * 2 * a.le * N + l * N + c;
-    out[0] = d2u(norm(red(a0, q, qi), q));
-    out[a.le * N] = d2u(norm(red(a1, q, qi), q));
+    for (int o = 0; o < kKipOut; o++) {
+      if (o >= G.nout) break;
+      u64* out = a.acc + (long long)(G.out0 + o) * 2 * a.le * N + l * N + c;
+      out[0] = d2u(norm(a0[o], q));
+      out[a.le * N] = d2u(norm(a1[o], q));
+    }
   });
 }
 
@@ -450,20 +501,34 @@ FENC_HD void rescale_tail(X& x, const RescaleTailArgs& a) {
 }
 
 // ------------------------------------------------------------------ linear combinations
-// out[o] = sum_g mask_g (.) ( sum_{t in g} w_t * in_t )      (NTT form, both polys)
-// Input index t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.
-// Weight index < 0 means weight 1; a null mask means no plaintext product.
+// A class is a set of up to kMacOut outputs with the same input terms, each
+// output with its own integer weights and its own plaintext per group (a small
+// modular GEMM followed by a plaintext product):
+//   out_o = sum_g pt_{g,o} (.) ( sum_{t in g} w_{t,o} * in_t )   (NTT form, both polys)
+// Each input word is loaded once for all outputs of the class.  Input index
+// t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.  Weight index
+// < 0 means weight 1; a null plaintext means no product.
+constexpr int kMacOut = 16;
+
+struct MacClass {
+  int g0, ng;        // groups g0 .. g0+ng-1 (terms shared by the outputs)
+  int o0, nout;      // cls_out[o0 .. o0+nout-1]: output ct indices
+  int w0;            // weights: wi[w0 + term_rank * nout + o]
+  int m0;            // plaintexts: mask[m0 + group_rank * nout + o]
+};
+
 struct GmacArgs {
   const u64* in_a; long long a_cs; int na;
   const u64* in_b; long long b_cs;
   long long in_ps;           // poly stride of inputs
   u64* out; long long out_cs, out_ps;
-  int o0;
-  const int* goff;           // [nout+1] groups of each output
-  const u64* const* mask;    // [ngroups] plaintext [nl][N] or null
+  int c0;                    // first class of the launch
+  const MacClass* cls;
+  const int* cls_out;
+  const u64* const* mask;    // per (class, group, output) plaintext [nl][N] or null
   const int* toff;           // [ngroups+1]
   const int* tin;            // [nterms] input index
-  const int* tw;             // [nterms] weight index or -1
+  const int* wi;             // weight indices
   const d2* wt;              // [nl][nw] weight residues (w, w/q)
   int nw, nl, logn;
   const d2* pq;
@@ -474,31 +539,53 @@ FENC_HD void gmac(X& x, const GmacArgs& a) {
   x.phase([&](int t) {
     const long long N = 1LL << a.logn;
     const long long c = (long long)x.bx * x.nt + t;
-    const int i = x.by % a.nl, poly = x.by / a.nl, o = a.o0 + x.bz;
+    const int i = x.by % a.nl, poly = x.by / a.nl;
+    const MacClass K = a.cls[a.c0 + x.bz];
     const double q = a.pq[i].x, qi = a.pq[i].y;
     const long long off = poly * a.in_ps + i * N + c;
-    double r = 0;
-    for (int g = a.goff[o]; g < a.goff[o + 1]; g++) {
-      double s = 0;
+    const d2* wt = a.wt + (long long)i * a.nw;
+    double r[kMacOut], sg[kMacOut];
+    for (int o = 0; o < kMacOut; o++) r[o] = 0;
+    int rank = 0;
+    for (int g = K.g0; g < K.g0 + K.ng; g++) {
+      for (int o = 0; o < kMacOut; o++) sg[o] = 0;
       int n = 0;
-      for (int k = a.toff[g]; k < a.toff[g + 1]; k++) {
+      for (int k = a.toff[g]; k < a.toff[g + 1]; k++, rank++) {
         const int ti = a.tin[k];
         const u64* src = ti < a.na ? a.in_a + ti * a.a_cs : a.in_b + (ti - a.na) * a.b_cs;
         const double v = u2d(src[off]);
-        const int wi = a.tw[k];
-        if (wi < 0) {
-          s += v;
-        } else {
-          const d2 w = a.wt[(long long)i * a.nw + wi];
-          s += mulmod_c(v, w.x, w.y, q);
+        const int* w = a.wi + K.w0 + (long long)rank * K.nout;
+        for (int o = 0; o < kMacOut; o++) {
+          if (o >= K.nout) break;
+          const int wi = w[o];
+          sg[o] += wi < 0 ? v : mulmod_c(v, wt[wi].x, wt[wi].y, q);
         }
-        if (++n == 5) { s = red(s, q, qi); n = 0; }
+        if (++n == 5) {
+          for (int o = 0; o < kMacOut; o++) sg[o] = red(sg[o], q, qi);
+          n = 0;
+        }
       }
-      s = red(s, q, qi);
-      if (a.mask[g]) s = mulmod(s, u2d(a.mask[g][i * N + c]), q, qi);
-      r = red(r + s, q, qi);
+      const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * K.nout;
+      const u64* mprev = nullptr;
+      double mv = 0;
+      for (int o = 0; o < kMacOut; o++) {
+        if (o >= K.nout) break;
+        const u64* m = mg[o];
+        double s = red(sg[o], q, qi);
+        if (m) {
+          if (m != mprev) {
+            mv = u2d(m[i * N + c]);
+            mprev = m;
+          }
+          s = mulmod(s, mv, q, qi);
+        }
+        r[o] = red(r[o] + s, q, qi);
+      }
     }
-    a.out[o * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(red(r, q, qi), q));
+    for (int o = 0; o < kMacOut; o++) {
+      if (o >= K.nout) break;
+      a.out[a.cls_out[K.o0 + o] * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(r[o], q));
+    }
   });
 }
 

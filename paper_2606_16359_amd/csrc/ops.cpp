@@ -192,12 +192,12 @@ static RotStage make_rot_stage(Ctx& C, const std::vector<std::pair<int, long lon
     kv.second = (int)R.src.size();
     R.src.push_back(kv.first);
   }
-  std::vector<std::vector<fk::KipItem>> items;
+  std::vector<std::vector<KsItem>> items;
   std::vector<fk::TailItem> tails;
   std::vector<fk::AddTerm> terms;
   for (int i = 0; i < R.n; i++) {
     const unsigned g = (unsigned)galois(C, copies[i].second);
-    items.push_back({fk::KipItem{pos[copies[i].first], g, get_key(C, g)}});
+    items.push_back({KsItem{pos[copies[i].first], g, get_key(C, g)}});
     tails.push_back(fk::TailItem{i, -1, (int)terms.size(), 1});
     terms.push_back(fk::AddTerm{copies[i].first, g});
   }
@@ -232,15 +232,15 @@ static SumStage make_sum_stage(Ctx& C, const std::vector<int>& out_idx, const st
                                std::vector<void*>& owner, int nz) {
   SumStage S;
   S.nz = nz;
-  std::vector<std::vector<fk::KipItem>> items;
+  std::vector<std::vector<KsItem>> items;
   std::vector<fk::TailItem> tails;
   std::vector<fk::AddTerm> terms;
   for (size_t o = 0; o < out_idx.size(); o++) {
-    std::vector<fk::KipItem> it;
+    std::vector<KsItem> it;
     const int off = (int)terms.size();
     for (auto& t : terms_of[o]) {
       const unsigned g = (unsigned)galois(C, t.second);
-      it.push_back(fk::KipItem{t.first, g, get_key(C, g)});
+      it.push_back(KsItem{t.first, g, get_key(C, g)});
       terms.push_back(fk::AddTerm{t.first, g});
     }
     items.push_back(it);
@@ -337,10 +337,16 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
               }
           }
         }
+  // copies ordered by shift, so rotations that share a key are adjacent
   std::vector<std::pair<int, long long>> copies;
-  for (auto& kv : copy_id) {
-    kv.second = (int)copies.size();
-    copies.push_back(kv.first);
+  {
+    std::vector<std::pair<long long, int>> bykey;
+    for (auto& kv : copy_id) bykey.push_back({kv.first.second, kv.first.first});
+    std::sort(bykey.begin(), bykey.end());
+    for (auto& kv : bykey) {
+      copy_id[{kv.second, kv.first}] = (int)copies.size();
+      copies.push_back({kv.second, kv.first});
+    }
   }
   P->rot = make_rot_stage(C, copies, P->owned);
 
@@ -428,8 +434,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
           const int o = go * cpc + posmod(q - r, cpc);
           if (!pair_ok(ch, o)) continue;
           act[oct][r] = 1;
-          const int64_t code = weight_code(wval(o, ch, t), dw);
-          if (code == 0) continue;
+          const int64_t code = weight_code(wval(o, ch, t), dw);   // zero codes kept: shared structure
           const int mid = need_mask ? mask_of(t, q) : -1;
           G[oct][r][mid].push_back({in_id, weight_id(code)});
           P->n_terms++;
@@ -1288,11 +1293,11 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
     p->out = Lout;
     p->level = Lin.level;
     p->n = Lin.n_ct();
-    std::vector<std::vector<fk::KipItem>> items;
+    std::vector<std::vector<KsItem>> items;
     std::vector<fk::TailItem> tails;
     const uint64_t* rk = get_key(C, 0);
     for (int b = 0; b < p->n; b++) {
-      items.push_back({fk::KipItem{b, 1u, rk}});
+      items.push_back({KsItem{b, 1u, rk}});
       tails.push_back(fk::TailItem{b, b, 0, 0});
     }
     p->ks = make_ks(C, items, tails, {}, p->owned);

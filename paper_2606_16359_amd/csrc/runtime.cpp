@@ -189,10 +189,10 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
   a.logn = C.logn;
   a.n2 = (C.logn + 1) / 2;
   a.n1 = C.logn - a.n2;
-  a.cols = std::min(16, 1 << a.n2);
-  a.cpb = std::min(std::max(1, 2048 >> a.n2), 1 << a.n1);
-  const unsigned colblocks = (unsigned)((1 << a.n2) / a.cols), rowblocks = (unsigned)((1 << a.n1) / a.cpb);
-  const size_t lds_c = (size_t)(1 << a.n1) * a.cols * 8, lds_r = (size_t)a.cpb * (1 << a.n2) * 8;
+  a.lcols = std::min(4, a.n2);                                   // 16 columns per block
+  a.lcpb = std::min(std::max(0, 11 - a.n2), a.n1);              // ~2048 elements per block
+  const unsigned colblocks = 1u << (a.n2 - a.lcols), rowblocks = 1u << (a.n1 - a.lcpb);
+  const size_t lds_c = (size_t)8 << (a.n1 + a.lcols), lds_r = (size_t)8 << (a.n2 + a.lcpb);
   const int T = 256;
   int active = 0;
   for (int r = 0; r < std::min(nrows, pm.n); r++) active += (pm.p[r] != fk::kSkip);
@@ -326,20 +326,23 @@ void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out,
   const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha, N = C.N;
   Scope sc(C.arena);
   const bool per_op = C.mode == FENC_MODE_PER_OP;
-  const int chunk = per_op ? 1 : st.n_out;
+  const KipTables& KT = per_op ? st.single : st.batched;
   u64* acc = (u64*)C.arena.get((size_t)st.n_out * 2 * le * N * 8, s);
   u64* conv = (u64*)C.arena.get((size_t)st.n_out * 2 * nl * N * 8, s);
   fk::PrimeMap pmP;
   pmP.n = le;
   for (int l = 0; l < le; l++) pmP.p[l] = l < nl ? fk::kSkip : T.h_eprime[l];
-  for (int o0 = 0; o0 < st.n_out; o0 += chunk) {
-    const int no = std::min(chunk, st.n_out - o0);
-    fk::KipArgs k{ext, acc, st.items, st.d_item_off, o0, beta, le, C.logn, C.np, T.eprime, C.pq};
-    const int nit = st.item_off[o0 + no] - st.item_off[o0];
-    const int nkeys = per_op ? nit : st.n_keys;
-    const double kb = ((double)nit * beta * le + (double)nkeys * 2 * beta * le + 2.0 * no * le) * N * 8;
+  // per-op: one launch sequence per output; batched: every output at once
+  const int steps = per_op ? st.n_out : 1;
+  for (int it = 0; it < steps; it++) {
+    const int g0 = per_op ? it : 0, ng = per_op ? 1 : KT.n;
+    const int o0 = per_op ? it : 0, no = per_op ? 1 : st.n_out;
+    fk::KipArgs k{ext, acc, KT.groups, KT.keys, KT.items, g0, beta, le, C.logn, C.np, T.eprime, C.pq};
+    double kb = 0;
+    for (int g = g0; g < g0 + ng; g++) kb += KT.rd[g] * beta + KT.wr[g];
+    kb *= (double)le * N * 8;
     timed(C, "kip", kb, s,
-          [&] { fb::kip({(unsigned)(N / block_threads(C)), (unsigned)le, (unsigned)no}, block_threads(C), s, k); });
+          [&] { fb::kip({(unsigned)(N / block_threads(C)), (unsigned)le, (unsigned)ng}, block_threads(C), s, k); });
     u64* acc0 = acc + (long long)o0 * 2 * le * N;
     ntt(C, true, acc0, acc0, (long long)le * N, (long long)le * N, no * 2 * le, le, pmP, s);
     fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.eprime, C.md_tab, C.pq};
@@ -412,6 +415,8 @@ void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
 void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, int na, const u64* in_b,
               long long b_cs, long long in_ps, u64* out, long long out_cs, long long out_ps, fb::Stream s) {
   if (g.n_out <= 0) return;
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  const MacTables& M = per_op ? g.single : g.batched;
   fk::GmacArgs a;
   a.in_a = in_a;
   a.a_cs = a_cs;
@@ -422,51 +427,152 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
   a.out = out;
   a.out_cs = out_cs;
   a.out_ps = out_ps;
-  a.goff = g.goff;
-  a.mask = g.mask;
-  a.toff = g.toff;
-  a.tin = g.tin;
-  a.tw = g.tw;
+  a.cls = M.cls;
+  a.cls_out = M.cls_out;
+  a.mask = M.mask;
+  a.toff = M.toff;
+  a.tin = M.tin;
+  a.wi = M.wi;
   a.wt = g.wt;
   a.nw = g.nw;
   a.nl = nl;
   a.logn = C.logn;
   a.pq = C.pq;
-  const bool per_op = C.mode == FENC_MODE_PER_OP;
-  for (int o0 = 0; o0 < g.n_out; o0 += per_op ? 1 : g.n_out) {
-    a.o0 = o0;
-    const int no = per_op ? 1 : g.n_out;
-    const double frac = (double)no / g.n_out;
-    const double gb = (2.0 * g.n_terms * frac + 1.0 * g.n_masked * frac + 2.0 * no) * nl * C.N * 8;
+  const int steps = per_op ? M.n : 1;
+  for (int it = 0; it < steps; it++) {
+    a.c0 = per_op ? it : 0;
+    const int nc = per_op ? 1 : M.n;
+    const double frac = (double)nc / M.n;
+    const double gb = ((double)M.loads * frac * 2 + (double)M.masked * frac + 2.0 * (per_op ? 1 : g.n_out)) * nl * C.N * 8;
     timed(C, "gmac", gb, s, [&] {
-      fb::gmac({(unsigned)(C.N / block_threads(C)), (unsigned)(2 * nl), (unsigned)no}, block_threads(C), s, a);
+      fb::gmac({(unsigned)(C.N / block_threads(C)), (unsigned)(2 * nl), (unsigned)nc}, block_threads(C), s, a);
     });
     C.cnt.launches += 1;
   }
 }
 
-KsStage make_ks(Ctx& C, const std::vector<std::vector<fk::KipItem>>& items, const std::vector<fk::TailItem>& tails,
+static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>& items, bool single,
+                                 std::vector<void*>& owner) {
+  // batched: consecutive outputs with the same ordered key list share a group
+  std::vector<fk::KipGroup> groups;
+  std::vector<fk::KipKey> keys;
+  std::vector<int> it;
+  std::vector<double> bytes, wbytes;
+  const int n = (int)items.size();
+  int o = 0;
+  while (o < n) {
+    int e = o + 1;
+    if (!single)
+      while (e < n && e - o < fk::kKipOut && items[e].size() == items[o].size()) {
+        bool same = true;
+        for (size_t k = 0; k < items[o].size(); k++) same = same && items[e][k].g == items[o][k].g;
+        if (!same) break;
+        e++;
+      }
+    fk::KipGroup G{o, e - o, (int)keys.size(), (int)items[o].size()};
+    for (size_t k = 0; k < items[o].size(); k++) {
+      keys.push_back(fk::KipKey{items[o][k].g, items[o][k].key, (int)it.size()});
+      for (int oo = o; oo < e; oo++) it.push_back(items[oo][k].ct);
+    }
+    // words per (limb, coefficient): per digit, nkey keys (2 words) and one ext word per item
+    bytes.push_back((double)items[o].size() * ((e - o) + 2));
+    wbytes.push_back(2.0 * (e - o));
+    groups.push_back(G);
+    o = e;
+  }
+  KipTables T;
+  T.n = (int)groups.size();
+  T.groups = upload(C, groups, owner);
+  T.keys = upload(C, keys, owner);
+  T.items = upload(C, it, owner);
+  T.rd = bytes;
+  T.wr = wbytes;
+  return T;
+}
+
+KsStage make_ks(Ctx& C, const std::vector<std::vector<KsItem>>& items, const std::vector<fk::TailItem>& tails,
                 const std::vector<fk::AddTerm>& terms, std::vector<void*>& owner) {
   KsStage st;
   st.n_out = (int)items.size();
-  std::vector<fk::KipItem> flat;
-  st.item_off.push_back(0);
-  for (auto& v : items) {
-    flat.insert(flat.end(), v.begin(), v.end());
-    st.item_off.push_back((int)flat.size());
-  }
-  std::map<const u64*, int> uk;
-  for (auto& it : flat) uk[it.key] = 1;
-  st.n_keys = (int)uk.size();
+  st.batched = make_kip_tables(C, items, false, owner);
+  st.single = make_kip_tables(C, items, true, owner);
   for (auto& t : tails) {
     st.n_base += t.base >= 0;
     st.n_adds += t.add_n;
   }
-  st.items = upload(C, flat, owner);
-  st.d_item_off = upload(C, st.item_off, owner);
   st.tails = upload(C, tails, owner);
   st.terms = upload(C, terms, owner);
   return st;
+}
+
+static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, bool single, std::vector<void*>& owner) {
+  const int nout = (int)b.goff.size() - 1;
+  // signature of an output: per group, whether it has a plaintext, and its inputs
+  std::map<std::vector<int>, int> open;   // signature -> last class with it
+  std::vector<std::vector<int>> members;
+  for (int o = 0; o < nout; o++) {
+    std::vector<int> sig;
+    for (int g = b.goff[o]; g < b.goff[o + 1]; g++) {
+      sig.push_back(b.mask[g] ? -2 : -1);
+      for (int k = b.toff[g]; k < b.toff[g + 1]; k++) sig.push_back(b.tin[k]);
+    }
+    int c = -1;
+    if (!single) {
+      auto it = open.find(sig);
+      if (it != open.end() && (int)members[it->second].size() < fk::kMacOut) c = it->second;
+    }
+    if (c < 0) {
+      c = (int)members.size();
+      members.push_back({});
+      if (!single) open[sig] = c;
+    }
+    members[c].push_back(o);
+  }
+  std::vector<fk::MacClass> cls;
+  std::vector<int> cls_out, toff{0}, tin, wi;
+  std::vector<const uint64_t*> mask;
+  MacTables T;
+  int ngroups = 0;
+  for (auto& mem : members) {
+    const int rep = mem[0], no = (int)mem.size();
+    fk::MacClass K;
+    K.g0 = ngroups;
+    K.ng = b.goff[rep + 1] - b.goff[rep];
+    K.o0 = (int)cls_out.size();
+    K.nout = no;
+    K.w0 = (int)wi.size();
+    K.m0 = (int)mask.size();
+    for (int o : mem) cls_out.push_back(o);
+    for (int gr = 0; gr < K.ng; gr++) {
+      const int g = b.goff[rep] + gr;
+      for (int k = b.toff[g]; k < b.toff[g + 1]; k++) {
+        tin.push_back(b.tin[k]);
+        T.loads++;
+      }
+      toff.push_back((int)tin.size());
+      ngroups++;
+      const uint64_t* prev = nullptr;
+      for (int o : mem) {
+        const uint64_t* m = b.mask[b.goff[o] + gr];
+        mask.push_back(m);
+        if (m && m != prev) T.masked++;
+        prev = m;
+      }
+    }
+    // weights term-major, output-minor
+    const int nterm = b.toff[b.goff[rep + 1]] - b.toff[b.goff[rep]];
+    for (int r = 0; r < nterm; r++)
+      for (int o : mem) wi.push_back(b.tw[b.toff[b.goff[o]] + r]);
+    cls.push_back(K);
+  }
+  T.n = (int)cls.size();
+  T.cls = upload(C, cls, owner);
+  T.cls_out = upload(C, cls_out, owner);
+  T.mask = (const uint64_t**)upload(C, mask, owner);
+  T.toff = upload(C, toff, owner);
+  T.tin = upload(C, tin, owner);
+  T.wi = upload(C, wi, owner);
+  return T;
 }
 
 GmacStage make_gmac(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int level,
@@ -476,11 +582,10 @@ GmacStage make_gmac(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcod
   g.nw = (int)wcodes.size();
   g.n_terms = (long long)b.tin.size();
   for (auto* m : b.mask) g.n_masked += m != nullptr;
-  g.goff = upload(C, b.goff, owner);
-  g.mask = (const u64**)upload(C, b.mask, owner);
-  g.toff = upload(C, b.toff, owner);
-  g.tin = upload(C, b.tin, owner);
-  g.tw = upload(C, b.tw, owner);
+  if (g.n_out > 0) {
+    g.batched = make_mac_tables(C, b, false, owner);
+    g.single = make_mac_tables(C, b, true, owner);
+  }
   const int nl = level + 1;
   std::vector<d2> wt((size_t)nl * std::max<size_t>(1, wcodes.size()));
   for (int i = 0; i < nl; i++) {

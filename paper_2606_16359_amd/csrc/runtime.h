@@ -69,25 +69,47 @@ struct Scope {   // releases arena allocations of one operation
 };
 
 // ---------------------------------------------------------------- device tables of a KS stage
+// One item of a key-switch stage: ext ct `ct` rotated by Galois element g.
+struct KsItem {
+  int ct;
+  unsigned g;
+  const uint64_t* key;
+};
+
+// Device tables of a KIP + ModDown stage.  Outputs are grouped twice: in
+// batched groups (up to kKipOut outputs sharing their keys) and one output per
+// group for the per-op mode.
+struct KipTables {
+  int n = 0;                       // groups
+  fk::KipGroup* groups = nullptr;
+  fk::KipKey* keys = nullptr;
+  int* items = nullptr;
+  std::vector<double> rd, wr;      // host: words per (limb, coefficient) read per digit / written
+};
 struct KsStage {
   int n_out = 0;
-  std::vector<int> item_off;           // host copy
-  std::vector<int> key_groups;         // host: distinct keys among items [o0, o0+n) when launched whole
-  int n_keys = 0, n_base = 0, n_adds = 0;
-  fk::KipItem* items = nullptr;        // device
-  int* d_item_off = nullptr;
+  KipTables batched, single;
+  int n_base = 0, n_adds = 0;
   fk::TailItem* tails = nullptr;
   fk::AddTerm* terms = nullptr;
 };
 
-struct GmacStage {
-  int n_out = 0, nw = 0;
-  long long n_terms = 0, n_masked = 0;   // host counts (traffic accounting)
-  int* goff = nullptr;
-  const u64** mask = nullptr;
+// Device tables of a linear-combination stage (classes of outputs with the
+// same terms), batched and one output per class.
+struct MacTables {
+  int n = 0;                       // classes
+  fk::MacClass* cls = nullptr;
+  int* cls_out = nullptr;
+  const uint64_t** mask = nullptr;
   int* toff = nullptr;
   int* tin = nullptr;
-  int* tw = nullptr;
+  int* wi = nullptr;
+  long long loads = 0, masked = 0; // host: input words and mask words per coefficient-limb
+};
+struct GmacStage {
+  int n_out = 0, nw = 0;
+  long long n_terms = 0, n_masked = 0;
+  MacTables batched, single;
   d2* wt = nullptr;
 };
 
@@ -173,7 +195,7 @@ void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s);
 void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, int na, const u64* in_b,
               long long b_cs, long long in_ps, u64* out, long long out_cs, long long out_ps, fb::Stream s);
 
-KsStage make_ks(Ctx& C, const std::vector<std::vector<fk::KipItem>>& items, const std::vector<fk::TailItem>& tails,
+KsStage make_ks(Ctx& C, const std::vector<std::vector<KsItem>>& items, const std::vector<fk::TailItem>& tails,
                 const std::vector<fk::AddTerm>& terms, std::vector<void*>& owner);
 struct GmacBuild {
   std::vector<int> goff{0}, toff{0}, tin, tw;
