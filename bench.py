@@ -23,6 +23,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNELS = ["gmac", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "moddown_tail",
+           "moddown_fbc", "modup_fbc", "rescale_tail", "rescale_lift", "tensor_square"]
+# HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
+# a copy kernel of known size), per kernel; only kernels unchanged since the
+# counters were taken are listed
+TRAFFIC = {}
 
 
 def log(*a):
@@ -35,7 +41,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--per-op-steps", type=int, default=2)
-    ap.add_argument("--profile-kernel", default="kip")
+    ap.add_argument("--profile-kernel", default="auto",
+                    help="kernel for the roofline object; auto = the one with the most time per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64)
     args = ap.parse_args()
@@ -111,14 +118,27 @@ def main():
     identical_perop = bool(np.array_equal(fe.export(out_pop), eager_bits))
     fe.set_mode(F.FENC_MODE_BATCHED)
 
-    # dominant kernel: HIP events around each of its launches in one batched step
-    fe.profile_kernel(args.profile_kernel)
-    step()
-    torch.cuda.synchronize()
-    kms, klaunch, kbytes = fe.profile_result()
+    # per-kernel time and algorithmic bytes: HIP events around each launch of
+    # one kernel over one batched step, one kernel at a time
+    kernels = {}
+    for name in KERNELS:
+        fe.profile_kernel(name)
+        step()
+        torch.cuda.synchronize()
+        kms, klaunch, kbytes = fe.profile_result()
+        if klaunch:
+            avg_s = kms / 1e3 / klaunch
+            gbs = kbytes / klaunch / avg_s / 1e9
+            kernels[name] = {"launches": klaunch, "ms_per_step": round(kms, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+                             "bytes_per_launch": round(kbytes / klaunch), "achieved_GBs": round(gbs, 1),
+                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     fe.profile_kernel(None)
-    avg_s = kms / 1e3 / max(1, klaunch)
-    achieved = (kbytes / max(1, klaunch)) / avg_s / 1e9 if klaunch else 0.0
+    log("kernels: " + json.dumps(kernels))
+    dom = args.profile_kernel
+    if dom == "auto":
+        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    achieved = kd["achieved_GBs"]
 
     imgs = args.batch
     value = imgs / t_graph
@@ -147,10 +167,11 @@ def main():
         "graph_vs_per_op": round(t_perop / t_graph, 3),
         "bit_identical": {"graph_vs_eager": identical_graph, "per_op_vs_batched": identical_perop},
         "launches_per_step": st["launches"],
-        "roofline": {"kernel": args.profile_kernel, "bound": "hbm", "achieved": round(achieved, 1),
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2), "launches": klaunch,
-                     "bytes_per_launch": kbytes / max(1, klaunch)},
+                     "traffic": TRAFFIC.get(dom), "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],
+                     "bytes_per_launch": kd["bytes_per_launch"]},
+        "kernels": kernels,
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(x, w, params, lay, ks_per_step, imgs)

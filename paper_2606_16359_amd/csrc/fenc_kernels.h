@@ -11,6 +11,7 @@
 // binary64 inside the kernels (fenc_arith.h).
 #pragma once
 #include <cstddef>
+#include <type_traits>
 #include "fenc_arith.h"
 
 namespace fk {
@@ -57,189 +58,209 @@ FENC_HD inline int member(int rest, int f, int lo, int k) {
   return ((((rest >> lo) << k) | f) << lo) | (rest & ((1 << lo) - 1));
 }
 
-// One register round of forward (Cooley-Tukey) stages s0..s0+k-1 of a pass
+// One register round of forward (Cooley-Tukey) stages s0..s0+K-1 of a pass
 // with P stage bits: local stage s pairs stage-index bit P-1-s.  tw_of(s, a)
 // is the twiddle of the butterfly whose upper element has stage index a.
-// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2] (k <= 3 keeps
-// every product operand below 3q and every sum below 4q < 2^52).
-template <class LD, class ST, class TW>
-FENC_HD inline void fwd_round(int rest, int s0, int k, int P, double q, double qi, LD ld, ST st, TW tw_of) {
-  double v[1 << kRadixBits];
-  const int lo = P - s0 - k;
-  for (int f = 0; f < (1 << k); f++) v[f] = ld(member(rest, f, lo, k));
-  for (int s = 0; s < k; s++) {
-    const int half = 1 << (k - 1 - s);
-    for (int f = 0; f < (1 << k); f++) {
+// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2] (K <= 3 keeps
+// every product operand below 3q and every sum below 4q < 2^52).  K is a
+// compile-time constant so the group lives in registers.
+template <int K, class LD, class ST, class TW>
+FENC_HD inline void fwd_round(int rest, int s0, int P, double q, double qi, LD ld, ST st, TW tw_of) {
+  double v[1 << K];
+  const int lo = P - s0 - K;
+#pragma unroll
+  for (int f = 0; f < (1 << K); f++) v[f] = ld(member(rest, f, lo, K));
+#pragma unroll
+  for (int s = 0; s < K; s++) {
+    const int half = 1 << (K - 1 - s);
+#pragma unroll
+    for (int f = 0; f < (1 << K); f++) {
       if (f & half) continue;
-      const d2 w = tw_of(s0 + s, member(rest, f, lo, k));
+      const d2 w = tw_of(s0 + s, member(rest, f, lo, K));
       const double u = v[f], t = mulmod_c(v[f | half], w.x, w.y, q);
       v[f] = u + t;
       v[f | half] = u - t;
     }
   }
-  for (int f = 0; f < (1 << k); f++) st(member(rest, f, lo, k), red(v[f], q, qi));
+#pragma unroll
+  for (int f = 0; f < (1 << K); f++) st(member(rest, f, lo, K), red(v[f], q, qi));
 }
 
-// One register round of inverse (Gentleman-Sande) stages s0..s0+k-1: local
+// One register round of inverse (Gentleman-Sande) stages s0..s0+K-1: local
 // stage s pairs stage-index bit s.  Inputs and outputs have magnitude < q.
-template <class LD, class ST, class TW>
-FENC_HD inline void inv_round(int rest, int s0, int k, double q, double qi, LD ld, ST st, TW tw_of) {
-  double v[1 << kRadixBits];
+template <int K, class LD, class ST, class TW>
+FENC_HD inline void inv_round(int rest, int s0, double q, double qi, LD ld, ST st, TW tw_of) {
+  double v[1 << K];
   const int lo = s0;
-  for (int f = 0; f < (1 << k); f++) v[f] = ld(member(rest, f, lo, k));
-  for (int s = 0; s < k; s++) {
+#pragma unroll
+  for (int f = 0; f < (1 << K); f++) v[f] = ld(member(rest, f, lo, K));
+#pragma unroll
+  for (int s = 0; s < K; s++) {
     const int half = 1 << s;
-    for (int f = 0; f < (1 << k); f++) {
+#pragma unroll
+    for (int f = 0; f < (1 << K); f++) {
       if (f & half) continue;
-      const d2 w = tw_of(s0 + s, member(rest, f, lo, k));
+      const d2 w = tw_of(s0 + s, member(rest, f, lo, K));
       const double xv = v[f], yv = v[f | half];
       v[f] = red(xv + yv, q, qi);
       v[f | half] = mulmod_c(xv - yv, w.x, w.y, q);
     }
   }
-  for (int f = 0; f < (1 << k); f++) st(member(rest, f, lo, k), v[f]);
+#pragma unroll
+  for (int f = 0; f < (1 << K); f++) st(member(rest, f, lo, K), v[f]);
+}
+
+// Round schedule of a pass with P stage bits: ceil(P/3) register rounds of
+// nearly equal size (larger rounds first).
+FENC_HD constexpr int n_rounds(int P) { return (P + kRadixBits - 1) / kRadixBits; }
+FENC_HD constexpr int round_size(int P, int r) {
+  return P / n_rounds(P) + (r < P % n_rounds(P) ? 1 : 0);
+}
+FENC_HD constexpr int round_start(int P, int r) { return r == 0 ? 0 : round_start(P, r - 1) + round_size(P, r - 1); }
+
+template <int R, int NR>
+struct RoundLoop {
+  template <class B>
+  FENC_HD static void run(B body) {
+    body(std::integral_constant<int, R>());
+    RoundLoop<R + 1, NR>::run(body);
+  }
+};
+template <int NR>
+struct RoundLoop<NR, NR> {
+  template <class B>
+  FENC_HD static void run(B) {}
+};
+
+// Calls body(integral_constant<P>) for the pass size p in 1..8.
+template <class B>
+FENC_HD inline void with_pass(int p, B body) {
+  switch (p) {
+    case 1: body(std::integral_constant<int, 1>()); break;
+    case 2: body(std::integral_constant<int, 2>()); break;
+    case 3: body(std::integral_constant<int, 3>()); break;
+    case 4: body(std::integral_constant<int, 4>()); break;
+    case 5: body(std::integral_constant<int, 5>()); break;
+    case 6: body(std::integral_constant<int, 6>()); break;
+    case 7: body(std::integral_constant<int, 7>()); break;
+    default: body(std::integral_constant<int, 8>()); break;
+  }
 }
 
 // Column pass: stages acting on 2^n1 elements at stride 2^n2 ("columns").  A
 // block stages 2^lcols adjacent columns; the column index is the low part of
 // the thread's group index so neighbouring threads touch neighbouring words.
 // Forward: the first n1 stages; inverse: the last n1 stages, then * N^-1.
-template <class X>
-FENC_HD void ntt_fwd_cols(X& x, const NttArgs& a) {
+// The first round reads HBM, the last writes HBM, the others use LDS.
+template <bool INV, int P, class X>
+FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
+  const int n2 = a.n2, sb = a.lcols, T = x.nt, bm = (1 << sb) - 1;
   const int row = x.by;
-  const int p = a.pm.p[row % a.pm.n];
-  if (p == kSkip) return;
-  const int n1 = a.n1, n2 = a.n2, sb = a.lcols, T = x.nt, bm = (1 << sb) - 1;
   const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn);
   u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn);
   const long long col0 = (long long)x.bx << sb;
   const double q = a.pq[p].x, qi = a.pq[p].y;
   const d2* tw = a.tw + ((long long)p << a.logn);
   double* sm = x.smem;
-  for (int s0 = 0; s0 < n1; s0 += kRadixBits) {
-    const int k = n1 - s0 < kRadixBits ? n1 - s0 : kRadixBits;
-    const bool first = s0 == 0, last = s0 + k == n1;
+  const d2 ni = INV ? a.ninv[p] : d2{0, 0};
+  RoundLoop<0, n_rounds(P)>::run([&](auto R) {
+    constexpr int r = decltype(R)::value;
+    constexpr int K = round_size(P, r), s0 = round_start(P, r);
+    constexpr bool first = r == 0, last = r == n_rounds(P) - 1;
     x.phase([&](int t) {
-      for (int g = t; g < (1 << (n1 + sb - k)); g += T) {
+      for (int g = t; g < (1 << (P + sb - K)); g += T) {
         const int c = g & bm, rest = g >> sb;
-        fwd_round(
-            rest, s0, k, n1, q, qi,
-            [&](int hi) { return first ? u2d(src[((long long)hi << n2) + col0 + c]) : sm[(hi << sb) | c]; },
-            [&](int hi, double v) {
-              if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(v, q));
-              else sm[(hi << sb) | c] = v;
-            },
-            [&](int st, int hi) { return tw[(1 << st) + (hi >> (n1 - st))]; });
+        auto ld = [&](int hi) { return first ? u2d(src[((long long)hi << n2) + col0 + c]) : sm[(hi << sb) | c]; };
+        if constexpr (!INV) {
+          fwd_round<K>(
+              rest, s0, P, q, qi, ld,
+              [&](int hi, double v) {
+                if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(v, q));
+                else sm[(hi << sb) | c] = v;
+              },
+              [&](int st, int hi) { return tw[(1 << st) + (hi >> (P - st))]; });
+        } else {
+          inv_round<K>(
+              rest, s0, q, qi, ld,
+              [&](int hi, double v) {
+                if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(mulmod_c(v, ni.x, ni.y, q), q));
+                else sm[(hi << sb) | c] = v;
+              },
+              // global stage u = n2 + st: h = N >> (u+1), group = hi >> (st+1)
+              [&](int st, int hi) { return tw[(1LL << (P - st - 1)) + (hi >> (st + 1))]; });
+        }
       }
     });
-  }
-}
-
-template <class X>
-FENC_HD void ntt_inv_cols(X& x, const NttArgs& a) {
-  const int row = x.by;
-  const int p = a.pm.p[row % a.pm.n];
-  if (p == kSkip) return;
-  const int n1 = a.n1, n2 = a.n2, sb = a.lcols, T = x.nt, bm = (1 << sb) - 1;
-  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn);
-  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn);
-  const long long col0 = (long long)x.bx << sb;
-  const double q = a.pq[p].x, qi = a.pq[p].y;
-  const d2* tw = a.tw + ((long long)p << a.logn);
-  const d2 ni = a.ninv[p];
-  double* sm = x.smem;
-  for (int s0 = 0; s0 < n1; s0 += kRadixBits) {
-    const int k = n1 - s0 < kRadixBits ? n1 - s0 : kRadixBits;
-    const bool first = s0 == 0, last = s0 + k == n1;
-    x.phase([&](int t) {
-      for (int g = t; g < (1 << (n1 + sb - k)); g += T) {
-        const int c = g & bm, rest = g >> sb;
-        inv_round(
-            rest, s0, k, q, qi,
-            [&](int hi) { return first ? u2d(src[((long long)hi << n2) + col0 + c]) : sm[(hi << sb) | c]; },
-            [&](int hi, double v) {
-              if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(mulmod_c(v, ni.x, ni.y, q), q));
-              else sm[(hi << sb) | c] = v;
-            },
-            // global stage u = n2 + st: h = N >> (u+1), group = hi >> (st+1)
-            [&](int st, int hi) { return tw[(1LL << (n1 - st - 1)) + (hi >> (st + 1))]; });
-      }
-    });
-  }
+  });
 }
 
 // Row pass: stages acting inside contiguous chunks of 2^n2 elements; a block
 // stages 2^lcpb chunks.  The chunk is the high part of the thread's group
 // index so neighbouring threads touch neighbouring words.  Forward: the last
 // n2 stages; inverse: the first n2 stages.
-template <class X>
-FENC_HD void ntt_fwd_rows(X& x, const NttArgs& a) {
+template <bool INV, int P, class X>
+FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
+  const int n1 = a.n1, cb = a.lcpb, T = x.nt, logn = a.logn;
   const int row = x.by;
-  const int p = a.pm.p[row % a.pm.n];
-  if (p == kSkip) return;
-  const int n1 = a.n1, n2 = a.n2, cb = a.lcpb, T = x.nt;
-  const long long e0 = (long long)x.bx << (n2 + cb);
-  const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn) + e0;
-  u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn) + e0;
-  const long long chunk0 = (long long)x.bx << cb;
-  const double q = a.pq[p].x, qi = a.pq[p].y;
-  const d2* tw = a.tw + ((long long)p << a.logn);
-  double* sm = x.smem;
-  for (int s0 = 0; s0 < n2; s0 += kRadixBits) {
-    const int k = n2 - s0 < kRadixBits ? n2 - s0 : kRadixBits;
-    const bool first = s0 == 0, last = s0 + k == n2;
-    x.phase([&](int t) {
-      for (int g = t; g < (1 << (n2 + cb - k)); g += T) {
-        const int rest = g & ((1 << (n2 - k)) - 1), ch = g >> (n2 - k);
-        const int base = ch << n2;
-        fwd_round(
-            rest, s0, k, n2, q, qi,
-            [&](int lo) { return first ? u2d(src[base + lo]) : sm[base + lo]; },
-            [&](int lo, double v) {
-              if (last) dst[base + lo] = d2u(norm(v, q));
-              else sm[base + lo] = v;
-            },
-            // global stage S = n1 + st: group = (chunk << st) + (lo >> (n2 - st))
-            [&](int st, int lo) { return tw[(1LL << (n1 + st)) + ((chunk0 + ch) << st) + (lo >> (n2 - st))]; });
-      }
-    });
-  }
-}
-
-template <class X>
-FENC_HD void ntt_inv_rows(X& x, const NttArgs& a) {
-  const int row = x.by;
-  const int p = a.pm.p[row % a.pm.n];
-  if (p == kSkip) return;
-  const int n2 = a.n2, cb = a.lcpb, T = x.nt, logn = a.logn;
-  const long long e0 = (long long)x.bx << (n2 + cb);
+  const long long e0 = (long long)x.bx << (P + cb);
   const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << logn) + e0;
   u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn) + e0;
   const long long chunk0 = (long long)x.bx << cb;
   const double q = a.pq[p].x, qi = a.pq[p].y;
   const d2* tw = a.tw + ((long long)p << logn);
   double* sm = x.smem;
-  for (int s0 = 0; s0 < n2; s0 += kRadixBits) {
-    const int k = n2 - s0 < kRadixBits ? n2 - s0 : kRadixBits;
-    const bool first = s0 == 0, last = s0 + k == n2;
+  RoundLoop<0, n_rounds(P)>::run([&](auto R) {
+    constexpr int r = decltype(R)::value;
+    constexpr int K = round_size(P, r), s0 = round_start(P, r);
+    constexpr bool first = r == 0, last = r == n_rounds(P) - 1;
     x.phase([&](int t) {
-      for (int g = t; g < (1 << (n2 + cb - k)); g += T) {
-        const int rest = g & ((1 << (n2 - k)) - 1), ch = g >> (n2 - k);
-        const int base = ch << n2;
-        inv_round(
-            rest, s0, k, q, qi,
-            [&](int lo) { return first ? u2d(src[base + lo]) : sm[base + lo]; },
-            [&](int lo, double v) {
-              if (last) dst[base + lo] = d2u(norm(v, q));
-              else sm[base + lo] = v;
-            },
-            // stage u = st: h = N >> (u+1), group = (chunk << (n2-st-1)) + (lo >> (st+1))
-            [&](int st, int lo) {
-              return tw[(1LL << (logn - st - 1)) + ((chunk0 + ch) << (n2 - st - 1)) + (lo >> (st + 1))];
-            });
+      for (int g = t; g < (1 << (P + cb - K)); g += T) {
+        const int rest = g & ((1 << (P - K)) - 1), ch = g >> (P - K);
+        const int base = ch << P;
+        auto ld = [&](int lo) { return first ? u2d(src[base + lo]) : sm[base + lo]; };
+        auto st = [&](int lo, double v) {
+          if (last) dst[base + lo] = d2u(norm(v, q));
+          else sm[base + lo] = v;
+        };
+        if constexpr (!INV) {
+          fwd_round<K>(rest, s0, P, q, qi, ld, st,
+                       // global stage n1 + st: group = (chunk << st) + (lo >> (n2 - st))
+                       [&](int s, int lo) { return tw[(1LL << (n1 + s)) + ((chunk0 + ch) << s) + (lo >> (P - s))]; });
+        } else {
+          inv_round<K>(rest, s0, q, qi, ld, st,
+                       // stage s: h = N >> (s+1), group = (chunk << (n2-s-1)) + (lo >> (s+1))
+                       [&](int s, int lo) {
+                         return tw[(1LL << (logn - s - 1)) + ((chunk0 + ch) << (P - s - 1)) + (lo >> (s + 1))];
+                       });
+        }
       }
     });
-  }
+  });
+}
+
+template <class X>
+FENC_HD void ntt_fwd_cols(X& x, const NttArgs& a) {
+  const int p = a.pm.p[x.by % a.pm.n];
+  if (p == kSkip) return;
+  with_pass(a.n1, [&](auto P) { ntt_cols_pass<false, decltype(P)::value>(x, a, p); });
+}
+template <class X>
+FENC_HD void ntt_inv_cols(X& x, const NttArgs& a) {
+  const int p = a.pm.p[x.by % a.pm.n];
+  if (p == kSkip) return;
+  with_pass(a.n1, [&](auto P) { ntt_cols_pass<true, decltype(P)::value>(x, a, p); });
+}
+template <class X>
+FENC_HD void ntt_fwd_rows(X& x, const NttArgs& a) {
+  const int p = a.pm.p[x.by % a.pm.n];
+  if (p == kSkip) return;
+  with_pass(a.n2, [&](auto P) { ntt_rows_pass<false, decltype(P)::value>(x, a, p); });
+}
+template <class X>
+FENC_HD void ntt_inv_rows(X& x, const NttArgs& a) {
+  const int p = a.pm.p[x.by % a.pm.n];
+  if (p == kSkip) return;
+  with_pass(a.n2, [&](auto P) { ntt_rows_pass<true, decltype(P)::value>(x, a, p); });
 }
 
 // ------------------------------------------------------------------ ModUp
@@ -306,7 +327,7 @@ constexpr int kKipOut = 8;
 struct KipKey {
   unsigned g;        // Galois element (1: identity)
   const u64* key;    // [ndig][2][nprimes][N]
-  int item0;         // items[item0 + o]: ext ct index for output o of the group, or -1
+  int item0;         // items[item0 + o], o < kKipOut: ext ct of output o of the group, or -1
 };
 struct KipGroup {
   int out0, nout;    // outputs out0 .. out0+nout-1
@@ -335,25 +356,34 @@ FENC_HD void kip(X& x, const KipArgs& a) {
     const int p = a.eprime[l];
     const double q = a.pq[p].x, qi = a.pq[p].y;
     double a0[kKipOut], a1[kKipOut];
+#pragma unroll
     for (int o = 0; o < kKipOut; o++) a0[o] = a1[o] = 0;
     for (int kk = 0; kk < G.nkey; kk++) {
       const KipKey K = a.keys[G.key0 + kk];
       const long long src = (K.g == 1) ? c : (long long)auto_src((unsigned)c, K.g, a.logn);
+      // item lists are padded to kKipOut entries; -1 marks no item
+      int ct[kKipOut];
+#pragma unroll
+      for (int o = 0; o < kKipOut; o++) ct[o] = a.items[K.item0 + o];
       for (int j = 0; j < a.beta; j++) {
         const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
+        const u64* ej = a.ext + ((long long)j * a.le + l) * N + src;
+        const long long es = (long long)a.beta * a.le * N;
+        double v[kKipOut];
+#pragma unroll
+        for (int o = 0; o < kKipOut; o++) v[o] = ct[o] >= 0 ? u2d(ej[ct[o] * es]) : 0.0;
         const double k0 = u2d(kj[0]), k1 = u2d(kj[(long long)a.nprimes * N]);
+#pragma unroll
         for (int o = 0; o < kKipOut; o++) {
-          if (o >= G.nout) break;
-          const int ct = a.items[K.item0 + o];
-          if (ct < 0) continue;
-          const double v = u2d(a.ext[(((long long)ct * a.beta + j) * a.le + l) * N + src]);
-          a0[o] = red(a0[o] + mulmod(v, k0, q, qi), q, qi);
-          a1[o] = red(a1[o] + mulmod(v, k1, q, qi), q, qi);
+          if (ct[o] < 0) continue;
+          a0[o] = red(a0[o] + mulmod(v[o], k0, q, qi), q, qi);
+          a1[o] = red(a1[o] + mulmod(v[o], k1, q, qi), q, qi);
         }
       }
     }
+#pragma unroll
     for (int o = 0; o < kKipOut; o++) {
-      if (o >= G.nout) break;
+      if (o >= G.nout) continue;
       u64* out = a.acc + (long long)(G.out0 + o) * 2 * a.le * N + l * N + c;
       out[0] = d2u(norm(a0[o], q));
       out[a.le * N] = d2u(norm(a1[o], q));
@@ -506,15 +536,15 @@ FENC_HD void rescale_tail(X& x, const RescaleTailArgs& a) {
 // modular GEMM followed by a plaintext product):
 //   out_o = sum_g pt_{g,o} (.) ( sum_{t in g} w_{t,o} * in_t )   (NTT form, both polys)
 // Each input word is loaded once for all outputs of the class.  Input index
-// t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.  Weight index
-// < 0 means weight 1; a null plaintext means no product.
+// t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.  A null
+// plaintext means no product.
 constexpr int kMacOut = 16;
 
 struct MacClass {
   int g0, ng;        // groups g0 .. g0+ng-1 (terms shared by the outputs)
   int o0, nout;      // cls_out[o0 .. o0+nout-1]: output ct indices
-  int w0;            // weights: wi[w0 + term_rank * nout + o]
-  int m0;            // plaintexts: mask[m0 + group_rank * nout + o]
+  int w0;            // weights: ew[limb][w0 + term_rank * width + o]
+  int m0;            // plaintexts: mask[m0 + group_rank * width + o]
 };
 
 struct GmacArgs {
@@ -523,19 +553,20 @@ struct GmacArgs {
   long long in_ps;           // poly stride of inputs
   u64* out; long long out_cs, out_ps;
   int c0;                    // first class of the launch
+  int width;                 // 1, 2, 4, 8 or 16: outputs per class row (nout <= width; rows zero-padded)
   const MacClass* cls;
   const int* cls_out;
   const u64* const* mask;    // per (class, group, output) plaintext [nl][N] or null
-  const int* toff;           // [ngroups+1]
+  const int* toff;           // [ngroups+1] term ranges
   const int* tin;            // [nterms] input index
-  const int* wi;             // weight indices
-  const d2* wt;              // [nl][nw] weight residues (w, w/q)
-  int nw, nl, logn;
+  const d2* ew;              // [nl][ews] weight residues (w mod q, fl(w/q))
+  long long ews;
+  int nl, logn;
   const d2* pq;
 };
 
-template <class X>
-FENC_HD void gmac(X& x, const GmacArgs& a) {
+template <int W, class X>
+FENC_HD void gmac_w(X& x, const GmacArgs& a) {
   x.phase([&](int t) {
     const long long N = 1LL << a.logn;
     const long long c = (long long)x.bx * x.nt + t;
@@ -543,33 +574,39 @@ FENC_HD void gmac(X& x, const GmacArgs& a) {
     const MacClass K = a.cls[a.c0 + x.bz];
     const double q = a.pq[i].x, qi = a.pq[i].y;
     const long long off = poly * a.in_ps + i * N + c;
-    const d2* wt = a.wt + (long long)i * a.nw;
-    double r[kMacOut], sg[kMacOut];
-    for (int o = 0; o < kMacOut; o++) r[o] = 0;
-    int rank = 0;
+    const d2* ew = a.ew + (long long)i * a.ews + K.w0;
+    auto load_in = [&](int k) {
+      const int ti = a.tin[k];
+      const u64* src = ti < a.na ? a.in_a + ti * a.a_cs : a.in_b + (ti - a.na) * a.b_cs;
+      return u2d(src[off]);
+    };
+    double r[W], sg[W];
+#pragma unroll
+    for (int o = 0; o < W; o++) r[o] = 0;
+    const int k0 = a.toff[K.g0], kend = a.toff[K.g0 + K.ng];
+    int k = k0;
+    double vn = k < kend ? load_in(k) : 0.0;
     for (int g = K.g0; g < K.g0 + K.ng; g++) {
-      for (int o = 0; o < kMacOut; o++) sg[o] = 0;
+#pragma unroll
+      for (int o = 0; o < W; o++) sg[o] = 0;
       int n = 0;
-      for (int k = a.toff[g]; k < a.toff[g + 1]; k++, rank++) {
-        const int ti = a.tin[k];
-        const u64* src = ti < a.na ? a.in_a + ti * a.a_cs : a.in_b + (ti - a.na) * a.b_cs;
-        const double v = u2d(src[off]);
-        const int* w = a.wi + K.w0 + (long long)rank * K.nout;
-        for (int o = 0; o < kMacOut; o++) {
-          if (o >= K.nout) break;
-          const int wi = w[o];
-          sg[o] += wi < 0 ? v : mulmod_c(v, wt[wi].x, wt[wi].y, q);
-        }
+      for (const int ge = a.toff[g + 1]; k < ge; k++) {
+        const double v = vn;
+        if (k + 1 < kend) vn = load_in(k + 1);   // next term's word in flight during this one
+        const d2* w = ew + (long long)(k - k0) * W;
+#pragma unroll
+        for (int o = 0; o < W; o++) sg[o] += mulmod_c(v, w[o].x, w[o].y, q);
         if (++n == 5) {
-          for (int o = 0; o < kMacOut; o++) sg[o] = red(sg[o], q, qi);
+#pragma unroll
+          for (int o = 0; o < W; o++) sg[o] = red(sg[o], q, qi);
           n = 0;
         }
       }
-      const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * K.nout;
+      const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
       const u64* mprev = nullptr;
       double mv = 0;
-      for (int o = 0; o < kMacOut; o++) {
-        if (o >= K.nout) break;
+#pragma unroll
+      for (int o = 0; o < W; o++) {
         const u64* m = mg[o];
         double s = red(sg[o], q, qi);
         if (m) {
@@ -582,11 +619,23 @@ FENC_HD void gmac(X& x, const GmacArgs& a) {
         r[o] = red(r[o] + s, q, qi);
       }
     }
-    for (int o = 0; o < kMacOut; o++) {
-      if (o >= K.nout) break;
+#pragma unroll
+    for (int o = 0; o < W; o++) {
+      if (o >= K.nout) continue;
       a.out[a.cls_out[K.o0 + o] * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(r[o], q));
     }
   });
+}
+
+template <class X>
+FENC_HD void gmac(X& x, const GmacArgs& a) {
+  switch (a.width) {
+    case 1: gmac_w<1>(x, a); break;
+    case 2: gmac_w<2>(x, a); break;
+    case 4: gmac_w<4>(x, a); break;
+    case 8: gmac_w<8>(x, a); break;
+    default: gmac_w<kMacOut>(x, a); break;
+  }
 }
 
 // ------------------------------------------------------------------ tensor / key / encryption

@@ -432,22 +432,24 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
   a.mask = M.mask;
   a.toff = M.toff;
   a.tin = M.tin;
-  a.wi = M.wi;
-  a.wt = g.wt;
-  a.nw = g.nw;
+  a.ew = M.ew;
+  a.ews = M.ews;
   a.nl = nl;
   a.logn = C.logn;
   a.pq = C.pq;
-  const int steps = per_op ? M.n : 1;
-  for (int it = 0; it < steps; it++) {
-    a.c0 = per_op ? it : 0;
-    const int nc = per_op ? 1 : M.n;
-    const double frac = (double)nc / M.n;
-    const double gb = ((double)M.loads * frac * 2 + (double)M.masked * frac + 2.0 * (per_op ? 1 : g.n_out)) * nl * C.N * 8;
-    timed(C, "gmac", gb, s, [&] {
-      fb::gmac({(unsigned)(C.N / block_threads(C)), (unsigned)(2 * nl), (unsigned)nc}, block_threads(C), s, a);
-    });
-    C.cnt.launches += 1;
+  // batched: one launch per class width; per-op: one launch per class (width 1)
+  for (const MacSeg& sg : M.seg) {
+    const int steps = per_op ? sg.n : 1;
+    for (int it = 0; it < steps; it++) {
+      a.c0 = sg.c0 + (per_op ? it : 0);
+      a.width = sg.width;
+      const int nc = per_op ? 1 : sg.n;
+      const double gb = sg.words / sg.n * nc * nl * C.N * 8;
+      timed(C, "gmac", gb, s, [&] {
+        fb::gmac({(unsigned)(C.N / block_threads(C)), (unsigned)(2 * nl), (unsigned)nc}, block_threads(C), s, a);
+      });
+      C.cnt.launches += 1;
+    }
   }
 }
 
@@ -472,7 +474,7 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
     fk::KipGroup G{o, e - o, (int)keys.size(), (int)items[o].size()};
     for (size_t k = 0; k < items[o].size(); k++) {
       keys.push_back(fk::KipKey{items[o][k].g, items[o][k].key, (int)it.size()});
-      for (int oo = o; oo < e; oo++) it.push_back(items[oo][k].ct);
+      for (int oo = o; oo < o + fk::kKipOut; oo++) it.push_back(oo < e ? items[oo][k].ct : -1);
     }
     // words per (limb, coefficient): per digit, nkey keys (2 words) and one ext word per item
     bytes.push_back((double)items[o].size() * ((e - o) + 2));
@@ -505,7 +507,8 @@ KsStage make_ks(Ctx& C, const std::vector<std::vector<KsItem>>& items, const std
   return st;
 }
 
-static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, bool single, std::vector<void*>& owner) {
+static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int nl, bool single,
+                                 std::vector<void*>& owner) {
   const int nout = (int)b.goff.size() - 1;
   // signature of an output: per group, whether it has a plaintext, and its inputs
   std::map<std::vector<int>, int> open;   // signature -> last class with it
@@ -528,13 +531,27 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, bool single, std::v
     }
     members[c].push_back(o);
   }
+  // classes ordered by row width (next power of two of the output count), one
+  // launch per width
+  auto width_of = [](int n) {
+    int w = 1;
+    while (w < n) w <<= 1;
+    return w;
+  };
+  std::stable_sort(members.begin(), members.end(), [&](const std::vector<int>& x, const std::vector<int>& y) {
+    return width_of((int)x.size()) < width_of((int)y.size());
+  });
+  constexpr int kZero = INT32_MIN;   // padding weight 0
   std::vector<fk::MacClass> cls;
-  std::vector<int> cls_out, toff{0}, tin, wi;
+  std::vector<int> cls_out, toff{0}, tin, wi;   // wi: weight index per (class term, row slot), -1: weight 1
   std::vector<const uint64_t*> mask;
   MacTables T;
   int ngroups = 0;
   for (auto& mem : members) {
-    const int rep = mem[0], no = (int)mem.size();
+    const int rep = mem[0], no = (int)mem.size(), W = width_of(no);
+    if (T.seg.empty() || T.seg.back().width != W) T.seg.push_back(MacSeg{(int)cls.size(), 0, W, 0.0});
+    MacSeg& sg = T.seg.back();
+    sg.n++;
     fk::MacClass K;
     K.g0 = ngroups;
     K.ng = b.goff[rep + 1] - b.goff[rep];
@@ -543,26 +560,27 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, bool single, std::v
     K.w0 = (int)wi.size();
     K.m0 = (int)mask.size();
     for (int o : mem) cls_out.push_back(o);
+    sg.words += 2.0 * no;   // outputs written
     for (int gr = 0; gr < K.ng; gr++) {
       const int g = b.goff[rep] + gr;
       for (int k = b.toff[g]; k < b.toff[g + 1]; k++) {
         tin.push_back(b.tin[k]);
-        T.loads++;
+        sg.words += 2.0;   // input read (both polys)
       }
       toff.push_back((int)tin.size());
       ngroups++;
       const uint64_t* prev = nullptr;
-      for (int o : mem) {
-        const uint64_t* m = b.mask[b.goff[o] + gr];
+      for (int o = 0; o < W; o++) {
+        const uint64_t* m = o < no ? b.mask[b.goff[mem[o]] + gr] : nullptr;
         mask.push_back(m);
-        if (m && m != prev) T.masked++;
-        prev = m;
+        if (m && m != prev) sg.words += 1.0;   // plaintext read (one poly)
+        if (m) prev = m;
       }
     }
-    // weights term-major, output-minor
+    // weights term-major, row-slot-minor
     const int nterm = b.toff[b.goff[rep + 1]] - b.toff[b.goff[rep]];
     for (int r = 0; r < nterm; r++)
-      for (int o : mem) wi.push_back(b.tw[b.toff[b.goff[o]] + r]);
+      for (int o = 0; o < W; o++) wi.push_back(o < no ? b.tw[b.toff[b.goff[mem[o]]] + r] : kZero);
     cls.push_back(K);
   }
   T.n = (int)cls.size();
@@ -571,7 +589,16 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, bool single, std::v
   T.mask = (const uint64_t**)upload(C, mask, owner);
   T.toff = upload(C, toff, owner);
   T.tin = upload(C, tin, owner);
-  T.wi = upload(C, wi, owner);
+  T.ews = std::max<long long>(1, (long long)wi.size());
+  std::vector<d2> ew((size_t)nl * T.ews, d2{0, 0});
+  for (int l = 0; l < nl; l++) {
+    const uint64_t q = C.primes[l];
+    for (size_t k = 0; k < wi.size(); k++) {
+      const int64_t v = wi[k] == kZero ? 0 : wi[k] < 0 ? 1 : wcodes[wi[k]] % (int64_t)q;
+      ew[(size_t)l * T.ews + k] = cpair((uint64_t)(v < 0 ? v + (int64_t)q : v), q);
+    }
+  }
+  T.ew = upload(C, ew, owner);
   return T;
 }
 
@@ -579,23 +606,12 @@ GmacStage make_gmac(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcod
                     std::vector<void*>& owner) {
   GmacStage g;
   g.n_out = (int)b.goff.size() - 1;
-  g.nw = (int)wcodes.size();
   g.n_terms = (long long)b.tin.size();
   for (auto* m : b.mask) g.n_masked += m != nullptr;
   if (g.n_out > 0) {
-    g.batched = make_mac_tables(C, b, false, owner);
-    g.single = make_mac_tables(C, b, true, owner);
+    g.batched = make_mac_tables(C, b, wcodes, level + 1, false, owner);
+    g.single = make_mac_tables(C, b, wcodes, level + 1, true, owner);
   }
-  const int nl = level + 1;
-  std::vector<d2> wt((size_t)nl * std::max<size_t>(1, wcodes.size()));
-  for (int i = 0; i < nl; i++) {
-    const uint64_t q = C.primes[i];
-    for (size_t w = 0; w < wcodes.size(); w++) {
-      const int64_t v = wcodes[w] % (int64_t)q;
-      wt[(size_t)i * wcodes.size() + w] = cpair((uint64_t)(v < 0 ? v + (int64_t)q : v), q);
-    }
-  }
-  g.wt = upload(C, wt, owner);
   return g;
 }
 

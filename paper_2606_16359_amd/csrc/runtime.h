@@ -95,22 +95,27 @@ struct KsStage {
 };
 
 // Device tables of a linear-combination stage (classes of outputs with the
-// same terms), batched and one output per class.
+// same terms), batched and one output per class.  Classes are ordered by row
+// width; a segment is the classes of one width.
+struct MacSeg {
+  int c0, n, width;
+  double words;                    // words per (coefficient, limb) moved by the segment's classes
+};
 struct MacTables {
   int n = 0;                       // classes
+  std::vector<MacSeg> seg;
   fk::MacClass* cls = nullptr;
   int* cls_out = nullptr;
   const uint64_t** mask = nullptr;
   int* toff = nullptr;
   int* tin = nullptr;
-  int* wi = nullptr;
-  long long loads = 0, masked = 0; // host: input words and mask words per coefficient-limb
+  d2* ew = nullptr;                // [nl][ews] weight residues
+  long long ews = 0;
 };
 struct GmacStage {
-  int n_out = 0, nw = 0;
+  int n_out = 0;
   long long n_terms = 0, n_masked = 0;
   MacTables batched, single;
-  d2* wt = nullptr;
 };
 
 struct Plan {
