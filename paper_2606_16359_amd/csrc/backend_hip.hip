@@ -49,6 +49,20 @@ void check_launch(const char* what) { check(hipGetLastError(), what); }
     check_launch(#NAME);                                                               \
   }
 
+// Kernels launched in the XCD-aware block order (1-D grid, coordinates decoded
+// by xcd_coords).
+#define FENC_KERNEL_XCD(NAME, ARGS)                                                   \
+  __global__ void __launch_bounds__(256) k_##NAME(fk::ARGS a, unsigned gx, unsigned gy, unsigned gz) { \
+    GpuX x = here(nullptr);                                                            \
+    fk::xcd_coords(blockIdx.x, gx, gy, gz, x.bx, x.by, x.bz);                          \
+    fk::NAME(x, a);                                                                    \
+  }                                                                                    \
+  void fb::NAME(Grid g, int threads, Stream s, const fk::ARGS& a) {                    \
+    hipLaunchKernelGGL(k_##NAME, dim3(g.x * g.y * g.z), dim3(threads), 0,              \
+                       (hipStream_t)s, a, g.x, g.y, g.z);                              \
+    check_launch(#NAME);                                                               \
+  }
+
 #define FENC_KERNEL(NAME, ARGS)                                                       \
   __global__ void __launch_bounds__(256) k_##NAME(fk::ARGS a) {                        \
     GpuX x = here(nullptr);                                                            \
@@ -65,12 +79,13 @@ FENC_KERNEL_LDS(ntt_fwd_rows, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_rows, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_cols, NttArgs)
 FENC_KERNEL(modup_fbc, ModUpArgs)
-FENC_KERNEL(kip, KipArgs)
+FENC_KERNEL_XCD(kip, KipArgs)
 FENC_KERNEL(moddown_fbc, ModDownArgs)
 FENC_KERNEL(moddown_tail, TailArgs)
 FENC_KERNEL(rescale_lift, LiftArgs)
 FENC_KERNEL(rescale_tail, RescaleTailArgs)
-FENC_KERNEL(gmac, GmacArgs)
+FENC_KERNEL_XCD(gmac, GmacArgs)
+FENC_KERNEL_XCD(gmac_pt, GmacArgs)
 FENC_KERNEL(tensor_square, SquareArgs)
 FENC_KERNEL(key_combine, KeyArgs)
 FENC_KERNEL(enc_combine, EncArgs)

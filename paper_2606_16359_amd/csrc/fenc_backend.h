@@ -40,6 +40,7 @@ void moddown_tail(Grid g, int threads, Stream s, const fk::TailArgs& a);
 void rescale_lift(Grid g, int threads, Stream s, const fk::LiftArgs& a);
 void rescale_tail(Grid g, int threads, Stream s, const fk::RescaleTailArgs& a);
 void gmac(Grid g, int threads, Stream s, const fk::GmacArgs& a);
+void gmac_pt(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void tensor_square(Grid g, int threads, Stream s, const fk::SquareArgs& a);
 void key_combine(Grid g, int threads, Stream s, const fk::KeyArgs& a);
 void enc_combine(Grid g, int threads, Stream s, const fk::EncArgs& a);

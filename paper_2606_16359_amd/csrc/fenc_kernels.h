@@ -29,6 +29,23 @@ struct PrimeMap {
   unsigned char p[kMaxMap];
 };
 
+// ------------------------------------------------------------------ XCD-aware block order
+// The chip dispatches the blocks of a launch round-robin over its 8 XCDs
+// (block p runs on XCD p % 8), and each XCD has its own L2.  A launch made
+// with this order runs as a 1-D grid of gx*gy*gz blocks; every XCD receives a
+// contiguous range of the logical order in which z varies fastest, so blocks
+// that differ only in z (and read the same tile of a shared operand) run on
+// one XCD, close in time.
+constexpr unsigned kXcds = 8;
+FENC_HD inline void xcd_coords(unsigned p, unsigned gx, unsigned gy, unsigned gz, int& bx, int& by, int& bz) {
+  const unsigned nb = gx * gy * gz, q = nb / kXcds, rem = nb % kXcds, r = p % kXcds;
+  const unsigned L = r * q + (r < rem ? r : rem) + p / kXcds;
+  bz = (int)(L % gz);
+  const unsigned rest = L / gz;
+  bx = (int)(rest % gx);
+  by = (int)(rest / gx);
+}
+
 // ------------------------------------------------------------------ NTT
 // Negacyclic NTT over rows of N = 2^logn residues.  Forward: Cooley-Tukey
 // with merged psi twiddles, natural order in, bit-reversed order out (slot k
@@ -144,6 +161,23 @@ FENC_HD inline void with_pass(int p, B body) {
     case 6: body(std::integral_constant<int, 6>()); break;
     case 7: body(std::integral_constant<int, 7>()); break;
     default: body(std::integral_constant<int, 8>()); break;
+  }
+}
+
+// Calls body(integral_constant<n>) for a small count n in 1..8, else with 16
+// (the body then guards with the runtime count).
+template <class B>
+FENC_HD inline void with_count(int n, B body) {
+  switch (n) {
+    case 1: body(std::integral_constant<int, 1>()); break;
+    case 2: body(std::integral_constant<int, 2>()); break;
+    case 3: body(std::integral_constant<int, 3>()); break;
+    case 4: body(std::integral_constant<int, 4>()); break;
+    case 5: body(std::integral_constant<int, 5>()); break;
+    case 6: body(std::integral_constant<int, 6>()); break;
+    case 7: body(std::integral_constant<int, 7>()); break;
+    case 8: body(std::integral_constant<int, 8>()); break;
+    default: body(std::integral_constant<int, 16>()); break;
   }
 }
 
@@ -282,8 +316,8 @@ struct ModUpArgs {
   const d2* pq;
 };
 
-template <class X>
-FENC_HD void modup_fbc(X& x, const ModUpArgs& a) {
+template <int A, class X>
+FENC_HD void modup_fbc_a(X& x, const ModUpArgs& a) {
   x.phase([&](int t) {
     const long long c = (long long)x.bx * x.nt + t;
     const int b = a.b0 + x.by / a.beta, j = x.by % a.beta;
@@ -291,12 +325,16 @@ FENC_HD void modup_fbc(X& x, const ModUpArgs& a) {
     const d2* tab = a.tab + (long long)j * a.tstride;
     const long long N = 1LL << a.logn;
     u64* out = a.ext + ((long long)b * a.beta + j) * a.le * N;
-    double y[16];
-    for (int i = 0; i < ds; i++) {
-      const int p = a.eprime[lo + i];
-      const double q = a.pq[p].x;
-      const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
-      y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);
+    double y[A];
+#pragma unroll
+    for (int i = 0; i < A; i++) {
+      y[i] = 0;
+      if (i < ds) {
+        const int p = a.eprime[lo + i];
+        const double q = a.pq[p].x;
+        const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
+        y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);
+      }
     }
     for (int l = 0; l < a.le; l++) {
       if (l >= lo && l < hi) {
@@ -307,13 +345,19 @@ FENC_HD void modup_fbc(X& x, const ModUpArgs& a) {
       const double q = a.pq[p].x, qi = a.pq[p].y;
       const d2* h = tab + a.alpha + (long long)l * a.alpha;
       double acc = 0;
-      for (int i = 0; i < ds; i++) {
-        acc += mulmod_c(y[i], h[i].x, h[i].y, q);
+#pragma unroll
+      for (int i = 0; i < A; i++) {
+        if (i < ds) acc += mulmod_c(y[i], h[i].x, h[i].y, q);
         if ((i & 3) == 3) acc = red(acc, q, qi);
       }
       out[l * N + c] = d2u(norm(red(acc, q, qi), q));
     }
   });
+}
+
+template <class X>
+FENC_HD void modup_fbc(X& x, const ModUpArgs& a) {
+  with_count(a.alpha, [&](auto A) { modup_fbc_a<decltype(A)::value>(x, a); });
 }
 
 // ------------------------------------------------------------------ key inner product
@@ -346,6 +390,8 @@ struct KipArgs {
   const d2* pq;
 };
 
+constexpr int kKipDigits = 4;   // digits whose words are in flight together
+
 template <class X>
 FENC_HD void kip(X& x, const KipArgs& a) {
   x.phase([&](int t) {
@@ -355,6 +401,7 @@ FENC_HD void kip(X& x, const KipArgs& a) {
     const KipGroup G = a.groups[a.g0 + x.bz];
     const int p = a.eprime[l];
     const double q = a.pq[p].x, qi = a.pq[p].y;
+    const long long es = (long long)a.beta * a.le * N;   // ext ct stride
     double a0[kKipOut], a1[kKipOut];
 #pragma unroll
     for (int o = 0; o < kKipOut; o++) a0[o] = a1[o] = 0;
@@ -365,19 +412,29 @@ FENC_HD void kip(X& x, const KipArgs& a) {
       int ct[kKipOut];
 #pragma unroll
       for (int o = 0; o < kKipOut; o++) ct[o] = a.items[K.item0 + o];
-      for (int j = 0; j < a.beta; j++) {
-        const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
-        const u64* ej = a.ext + ((long long)j * a.le + l) * N + src;
-        const long long es = (long long)a.beta * a.le * N;
-        double v[kKipOut];
+      for (int j0 = 0; j0 < a.beta; j0 += kKipDigits) {
+        // every word of kKipDigits digits is requested before any is used
+        double v[kKipDigits][kKipOut], k0[kKipDigits], k1[kKipDigits];
 #pragma unroll
-        for (int o = 0; o < kKipOut; o++) v[o] = ct[o] >= 0 ? u2d(ej[ct[o] * es]) : 0.0;
-        const double k0 = u2d(kj[0]), k1 = u2d(kj[(long long)a.nprimes * N]);
+        for (int jj = 0; jj < kKipDigits; jj++) {
+          const int j = j0 + jj;
+          const bool dj = j < a.beta;
+          const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
+          k0[jj] = dj ? u2d(kj[0]) : 0.0;
+          k1[jj] = dj ? u2d(kj[(long long)a.nprimes * N]) : 0.0;
+          const u64* ej = a.ext + ((long long)j * a.le + l) * N + src;
 #pragma unroll
-        for (int o = 0; o < kKipOut; o++) {
-          if (ct[o] < 0) continue;
-          a0[o] = red(a0[o] + mulmod(v[o], k0, q, qi), q, qi);
-          a1[o] = red(a1[o] + mulmod(v[o], k1, q, qi), q, qi);
+          for (int o = 0; o < kKipOut; o++) v[jj][o] = (dj && ct[o] >= 0) ? u2d(ej[ct[o] * es]) : 0.0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < kKipDigits; jj++) {
+          if (j0 + jj >= a.beta) continue;
+#pragma unroll
+          for (int o = 0; o < kKipOut; o++) {
+            if (ct[o] < 0) continue;
+            a0[o] = red(a0[o] + mulmod(v[jj][o], k0[jj], q, qi), q, qi);
+            a1[o] = red(a1[o] + mulmod(v[jj][o], k1[jj], q, qi), q, qi);
+          }
         }
       }
     }
@@ -405,18 +462,22 @@ struct ModDownArgs {
   const d2* pq;
 };
 
-template <class X>
-FENC_HD void moddown_fbc(X& x, const ModDownArgs& a) {
+template <int KP, class X>
+FENC_HD void moddown_fbc_k(X& x, const ModDownArgs& a) {
   x.phase([&](int t) {
     const long long N = 1LL << a.logn;
     const long long c = (long long)x.bx * x.nt + t;
     const long long op = 2LL * a.o0 + x.by;   // output * 2 + poly
     const u64* in = a.acc + op * a.le * N + c;
-    double y[16];
-    for (int k = 0; k < a.K; k++) {
-      const int p = a.eprime[a.nl + k];
-      const double q = a.pq[p].x;
-      y[k] = centre(mulmod_c(u2d(in[(long long)(a.nl + k) * N]), a.tab[k].x, a.tab[k].y, q), q);
+    double y[KP];
+#pragma unroll
+    for (int k = 0; k < KP; k++) {
+      y[k] = 0;
+      if (k < a.K) {
+        const int p = a.eprime[a.nl + k];
+        const double q = a.pq[p].x;
+        y[k] = centre(mulmod_c(u2d(in[(long long)(a.nl + k) * N]), a.tab[k].x, a.tab[k].y, q), q);
+      }
     }
     u64* out = a.conv + op * a.nl * N + c;
     for (int i = 0; i < a.nl; i++) {
@@ -424,13 +485,19 @@ FENC_HD void moddown_fbc(X& x, const ModDownArgs& a) {
       const double q = a.pq[p].x, qi = a.pq[p].y;
       const d2* h = a.tab + a.K + (long long)i * a.K;
       double s = 0;
-      for (int k = 0; k < a.K; k++) {
-        s += mulmod_c(y[k], h[k].x, h[k].y, q);
+#pragma unroll
+      for (int k = 0; k < KP; k++) {
+        if (k < a.K) s += mulmod_c(y[k], h[k].x, h[k].y, q);
         if ((k & 3) == 3) s = red(s, q, qi);
       }
       out[(long long)i * N] = d2u(norm(red(s, q, qi), q));
     }
   });
+}
+
+template <class X>
+FENC_HD void moddown_fbc(X& x, const ModDownArgs& a) {
+  with_count(a.K, [&](auto KP) { moddown_fbc_k<decltype(KP)::value>(x, a); });
 }
 
 // out = (acc - conv) * P^-1 + base + sum_terms sigma_g(c0 of term ct)   (terms: poly 0 only)
@@ -565,13 +632,17 @@ struct GmacArgs {
   const d2* pq;
 };
 
-template <int W, class X>
+// Grid (N/256, nl, 2 * classes): z = class * 2 + poly, launched in the
+// XCD-aware order so both polys and neighbouring classes of one tile share an
+// L2 (plaintexts and shared inputs are fetched once).  PT: the class has
+// plaintext products.
+template <int W, bool PT, class X>
 FENC_HD void gmac_w(X& x, const GmacArgs& a) {
   x.phase([&](int t) {
     const long long N = 1LL << a.logn;
     const long long c = (long long)x.bx * x.nt + t;
-    const int i = x.by % a.nl, poly = x.by / a.nl;
-    const MacClass K = a.cls[a.c0 + x.bz];
+    const int i = x.by, poly = x.bz & 1;
+    const MacClass K = a.cls[a.c0 + (x.bz >> 1)];
     const double q = a.pq[i].x, qi = a.pq[i].y;
     const long long off = poly * a.in_ps + i * N + c;
     const d2* ew = a.ew + (long long)i * a.ews + K.w0;
@@ -602,21 +673,21 @@ FENC_HD void gmac_w(X& x, const GmacArgs& a) {
           n = 0;
         }
       }
-      const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
-      const u64* mprev = nullptr;
-      double mv = 0;
+      if constexpr (PT) {
+        // every plaintext word of the group is requested before any is used
+        const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
+        double mv[W];
 #pragma unroll
-      for (int o = 0; o < W; o++) {
-        const u64* m = mg[o];
-        double s = red(sg[o], q, qi);
-        if (m) {
-          if (m != mprev) {
-            mv = u2d(m[i * N + c]);
-            mprev = m;
-          }
-          s = mulmod(s, mv, q, qi);
+        for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
+#pragma unroll
+        for (int o = 0; o < W; o++) {
+          double s = red(sg[o], q, qi);
+          if (mg[o]) s = mulmod(s, mv[o], q, qi);
+          r[o] = red(r[o] + s, q, qi);
         }
-        r[o] = red(r[o] + s, q, qi);
+      } else {
+#pragma unroll
+        for (int o = 0; o < W; o++) r[o] = red(r[o] + red(sg[o], q, qi), q, qi);
       }
     }
 #pragma unroll
@@ -627,16 +698,22 @@ FENC_HD void gmac_w(X& x, const GmacArgs& a) {
   });
 }
 
-template <class X>
-FENC_HD void gmac(X& x, const GmacArgs& a) {
+template <bool PT, class X>
+FENC_HD void gmac_any(X& x, const GmacArgs& a) {
   switch (a.width) {
-    case 1: gmac_w<1>(x, a); break;
-    case 2: gmac_w<2>(x, a); break;
-    case 4: gmac_w<4>(x, a); break;
-    case 8: gmac_w<8>(x, a); break;
-    default: gmac_w<kMacOut>(x, a); break;
+    case 1: gmac_w<1, PT>(x, a); break;
+    case 2: gmac_w<2, PT>(x, a); break;
+    case 4: gmac_w<4, PT>(x, a); break;
+    case 8: gmac_w<8, PT>(x, a); break;
+    default: gmac_w<kMacOut, PT>(x, a); break;
   }
 }
+// classes without plaintext products
+template <class X>
+FENC_HD void gmac(X& x, const GmacArgs& a) { gmac_any<false>(x, a); }
+// classes with plaintext products (null entries allowed)
+template <class X>
+FENC_HD void gmac_pt(X& x, const GmacArgs& a) { gmac_any<true>(x, a); }
 
 // ------------------------------------------------------------------ tensor / key / encryption
 // (d0, d1, d2) = k (c0^2, 2 c0 c1, c1^2); d0,d1 into out (ct [2][nl][N]), d2 into d2buf [nl][N]

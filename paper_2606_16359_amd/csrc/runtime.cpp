@@ -445,8 +445,10 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
       a.width = sg.width;
       const int nc = per_op ? 1 : sg.n;
       const double gb = sg.words / sg.n * nc * nl * C.N * 8;
+      const fb::Grid grid{(unsigned)(C.N / block_threads(C)), (unsigned)nl, (unsigned)(2 * nc)};
       timed(C, "gmac", gb, s, [&] {
-        fb::gmac({(unsigned)(C.N / block_threads(C)), (unsigned)(2 * nl), (unsigned)nc}, block_threads(C), s, a);
+        if (sg.pt) fb::gmac_pt(grid, block_threads(C), s, a);
+        else fb::gmac(grid, block_threads(C), s, a);
       });
       C.cnt.launches += 1;
     }
@@ -538,8 +540,15 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
     while (w < n) w <<= 1;
     return w;
   };
+  auto has_pt = [&](const std::vector<int>& mem) {
+    for (int o : mem)
+      for (int g = b.goff[o]; g < b.goff[o + 1]; g++)
+        if (b.mask[g]) return true;
+    return false;
+  };
   std::stable_sort(members.begin(), members.end(), [&](const std::vector<int>& x, const std::vector<int>& y) {
-    return width_of((int)x.size()) < width_of((int)y.size());
+    const int wx = width_of((int)x.size()), wy = width_of((int)y.size());
+    return wx != wy ? wx < wy : (int)has_pt(x) < (int)has_pt(y);
   });
   constexpr int kZero = INT32_MIN;   // padding weight 0
   std::vector<fk::MacClass> cls;
@@ -549,7 +558,9 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
   int ngroups = 0;
   for (auto& mem : members) {
     const int rep = mem[0], no = (int)mem.size(), W = width_of(no);
-    if (T.seg.empty() || T.seg.back().width != W) T.seg.push_back(MacSeg{(int)cls.size(), 0, W, 0.0});
+    const bool pt = has_pt(mem);
+    if (T.seg.empty() || T.seg.back().width != W || T.seg.back().pt != pt)
+      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, pt, 0.0});
     MacSeg& sg = T.seg.back();
     sg.n++;
     fk::MacClass K;

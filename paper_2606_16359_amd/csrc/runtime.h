@@ -99,6 +99,7 @@ struct KsStage {
 // width; a segment is the classes of one width.
 struct MacSeg {
   int c0, n, width;
+  bool pt;                         // classes with plaintext products
   double words;                    // words per (coefficient, limb) moved by the segment's classes
 };
 struct MacTables {

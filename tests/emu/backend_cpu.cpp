@@ -24,7 +24,7 @@ struct CpuX {
 };
 
 template <class F>
-void run(fb::Grid g, int threads, size_t lds, F body) {
+void run(fb::Grid g, int threads, size_t lds, F body, bool xcd = false) {
   const long long nb = (long long)g.x * g.y * g.z;
 #pragma omp parallel
   {
@@ -32,9 +32,13 @@ void run(fb::Grid g, int threads, size_t lds, F body) {
 #pragma omp for schedule(dynamic, 4)
     for (long long i = 0; i < nb; i++) {
       CpuX x;
-      x.bx = (int)(i % g.x);
-      x.by = (int)((i / g.x) % g.y);
-      x.bz = (int)(i / ((long long)g.x * g.y));
+      if (xcd) {
+        fk::xcd_coords((unsigned)i, g.x, g.y, g.z, x.bx, x.by, x.bz);
+      } else {
+        x.bx = (int)(i % g.x);
+        x.by = (int)((i / g.x) % g.y);
+        x.bz = (int)(i / ((long long)g.x * g.y));
+      }
       x.nt = threads;
       x.smem = sm.data();
       body(x);
@@ -48,6 +52,10 @@ void run(fb::Grid g, int threads, size_t lds, F body) {
   void fb::NAME(Grid g, int threads, size_t lds, Stream, const fk::ARGS& a) {         \
     run(g, threads, lds, [&](CpuX& x) { fk::NAME(x, a); });                           \
   }
+#define EMU_XCD(NAME, ARGS)                                                          \
+  void fb::NAME(Grid g, int threads, Stream, const fk::ARGS& a) {                     \
+    run(g, threads, 0, [&](CpuX& x) { fk::NAME(x, a); }, true);                       \
+  }
 #define EMU(NAME, ARGS)                                                              \
   void fb::NAME(Grid g, int threads, Stream, const fk::ARGS& a) {                     \
     run(g, threads, 0, [&](CpuX& x) { fk::NAME(x, a); });                             \
@@ -58,12 +66,13 @@ EMU_LDS(ntt_fwd_rows, NttArgs)
 EMU_LDS(ntt_inv_rows, NttArgs)
 EMU_LDS(ntt_inv_cols, NttArgs)
 EMU(modup_fbc, ModUpArgs)
-EMU(kip, KipArgs)
+EMU_XCD(kip, KipArgs)
 EMU(moddown_fbc, ModDownArgs)
 EMU(moddown_tail, TailArgs)
 EMU(rescale_lift, LiftArgs)
 EMU(rescale_tail, RescaleTailArgs)
-EMU(gmac, GmacArgs)
+EMU_XCD(gmac, GmacArgs)
+EMU_XCD(gmac_pt, GmacArgs)
 EMU(tensor_square, SquareArgs)
 EMU(key_combine, KeyArgs)
 EMU(enc_combine, EncArgs)
