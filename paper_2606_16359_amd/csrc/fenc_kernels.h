@@ -390,8 +390,6 @@ struct KipArgs {
   const d2* pq;
 };
 
-constexpr int kKipDigits = 4;   // digits whose words are in flight together
-
 template <class X>
 FENC_HD void kip(X& x, const KipArgs& a) {
   x.phase([&](int t) {
@@ -412,29 +410,19 @@ FENC_HD void kip(X& x, const KipArgs& a) {
       int ct[kKipOut];
 #pragma unroll
       for (int o = 0; o < kKipOut; o++) ct[o] = a.items[K.item0 + o];
-      for (int j0 = 0; j0 < a.beta; j0 += kKipDigits) {
-        // every word of kKipDigits digits is requested before any is used
-        double v[kKipDigits][kKipOut], k0[kKipDigits], k1[kKipDigits];
+      for (int j = 0; j < a.beta; j++) {
+        const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
+        const u64* ej = a.ext + ((long long)j * a.le + l) * N + src;
+        // every output's word for this digit is requested before any is used
+        double v[kKipOut];
 #pragma unroll
-        for (int jj = 0; jj < kKipDigits; jj++) {
-          const int j = j0 + jj;
-          const bool dj = j < a.beta;
-          const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
-          k0[jj] = dj ? u2d(kj[0]) : 0.0;
-          k1[jj] = dj ? u2d(kj[(long long)a.nprimes * N]) : 0.0;
-          const u64* ej = a.ext + ((long long)j * a.le + l) * N + src;
+        for (int o = 0; o < kKipOut; o++) v[o] = ct[o] >= 0 ? u2d(ej[ct[o] * es]) : 0.0;
+        const double k0 = u2d(kj[0]), k1 = u2d(kj[(long long)a.nprimes * N]);
 #pragma unroll
-          for (int o = 0; o < kKipOut; o++) v[jj][o] = (dj && ct[o] >= 0) ? u2d(ej[ct[o] * es]) : 0.0;
-        }
-#pragma unroll
-        for (int jj = 0; jj < kKipDigits; jj++) {
-          if (j0 + jj >= a.beta) continue;
-#pragma unroll
-          for (int o = 0; o < kKipOut; o++) {
-            if (ct[o] < 0) continue;
-            a0[o] = red(a0[o] + mulmod(v[jj][o], k0[jj], q, qi), q, qi);
-            a1[o] = red(a1[o] + mulmod(v[jj][o], k1[jj], q, qi), q, qi);
-          }
+        for (int o = 0; o < kKipOut; o++) {
+          if (ct[o] < 0) continue;
+          a0[o] = red(a0[o] + mulmod(v[o], k0, q, qi), q, qi);
+          a1[o] = red(a1[o] + mulmod(v[o], k1, q, qi), q, qi);
         }
       }
     }

@@ -446,7 +446,7 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
       const int nc = per_op ? 1 : sg.n;
       const double gb = sg.words / sg.n * nc * nl * C.N * 8;
       const fb::Grid grid{(unsigned)(C.N / block_threads(C)), (unsigned)nl, (unsigned)(2 * nc)};
-      timed(C, "gmac", gb, s, [&] {
+      timed(C, sg.pt ? "gmac_pt" : "gmac", gb, s, [&] {
         if (sg.pt) fb::gmac_pt(grid, block_threads(C), s, a);
         else fb::gmac(grid, block_threads(C), s, a);
       });
