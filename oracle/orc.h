@@ -159,6 +159,12 @@ Ct mul_plain(const Context& C, const Ct& a, const RPoly& pt, double pt_scale);
 Ct mul_scalar(const Context& C, const Ct& a, i64 s, double s_scale);
 // k * a^2: tensor product scaled by the integer k, relinearised, no rescale
 Ct square_relin(Context& C, const Ct& a, i64 k = 1);
+// a * b: tensor product of two ciphertexts at one level, relinearised, no rescale
+Ct mul_relin(Context& C, const Ct& a, const Ct& b);
+// the same ciphertext at one level less (the last limb dropped)
+Ct drop_last_limb(const Ct& a);
+// base + k1 * x + k0 (k0 added to the constant coefficient of c0); base may be null
+Ct lin_comb(const Context& C, const Ct* base, const Ct& x, i128 k1, i128 k0);
 
 // ---------------------------------------------------------------- encoding
 // m = round(scale * tau^{-1}(z)), complex slots z (ns entries), reduced mod primes

@@ -394,6 +394,17 @@ void* orc_square(void* c, void* bp, long* counts) {
   GUARD_END(nullptr)
 }
 
+void* orc_poly_act(void* c, void* bp, const double* coeffs, int n, long* counts) {
+  GUARD_BEGIN
+  Batch* in = (Batch*)bp;
+  Batch* out = new Batch;
+  Counts cnt;
+  out->cts = poly_act(*(Context*)c, in->L, in->cts, std::vector<double>(coeffs, coeffs + n), out->L, cnt);
+  counts_to(cnt, counts);
+  return out;
+  GUARD_END(nullptr)
+}
+
 void* orc_compress(void* c, void* bp, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;

@@ -613,4 +613,55 @@ Ct square_relin(Context& C, const Ct& a, i64 k) {
   return y;
 }
 
+Ct mul_relin(Context& C, const Ct& a, const Ct& b) {
+  if (a.level != b.level) throw std::runtime_error("mul_relin: level mismatch");
+  RPoly d0 = poly_mul(C, a.c0, b.c0);
+  RPoly d1 = poly_mul(C, a.c0, b.c1);
+  poly_add_inplace(C, d1, poly_mul(C, a.c1, b.c0));
+  RPoly d2 = poly_mul(C, a.c1, b.c1);
+  std::vector<RPoly> up = mod_up(C, d2, a.level);
+  RPoly a0, a1;
+  key_inner_product(C, up, 0, a.level, a0, a1);
+  Ct y;
+  y.c0 = d0;
+  poly_add_inplace(C, y.c0, mod_down(C, a0, a.level));
+  y.c1 = d1;
+  poly_add_inplace(C, y.c1, mod_down(C, a1, a.level));
+  y.level = a.level;
+  y.scale = a.scale * b.scale;
+  return y;
+}
+
+Ct drop_last_limb(const Ct& a) {
+  if (a.level < 1) throw std::runtime_error("drop_last_limb: level 0");
+  Ct y = a;
+  y.c0.pidx.pop_back();
+  y.c0.c.pop_back();
+  y.c1.pidx.pop_back();
+  y.c1.c.pop_back();
+  y.level = a.level - 1;
+  return y;
+}
+
+Ct lin_comb(const Context& C, const Ct* base, const Ct& x, i128 k1, i128 k0) {
+  Ct y;
+  y.level = x.level;
+  y.scale = x.scale;
+  y.c0 = poly_zero(C, x.c0.pidx);
+  y.c1 = poly_zero(C, x.c1.pidx);
+  for (size_t l = 0; l < x.c0.pidx.size(); l++) {
+    const u64 q = C.primes[x.c0.pidx[l]], m = from_i128(k1, q);
+    for (int i = 0; i < C.N; i++) {
+      y.c0.c[l][i] = mulm(x.c0.c[l][i], m, q);
+      y.c1.c[l][i] = mulm(x.c1.c[l][i], m, q);
+    }
+    y.c0.c[l][0] = addm(y.c0.c[l][0], from_i128(k0, q), q);
+  }
+  if (base) {
+    poly_add_inplace(C, y.c0, base->c0);
+    poly_add_inplace(C, y.c1, base->c1);
+  }
+  return y;
+}
+
 }  // namespace orc

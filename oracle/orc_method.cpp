@@ -18,6 +18,8 @@
 //                       hoisted rotation sum (S = 1); the 1/4 is carried in
 //                       the scale.
 //   square_act        : x^2 polynomial activation (CMult + relinearisation).
+//   poly_act          : polynomial activation of degree <= 3 (Evaluation
+//                       methodology: ReLU replaced by a low-degree polynomial).
 //   compress          : Arch-aware Ct Compression: rot-mask-add of sparse
 //                       ciphertexts into one dense ciphertext; the mask scale is
 //                       chosen so a single rescale follows (Delta1*Delta2 split).
@@ -432,6 +434,84 @@ std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& i
 
 // x^2 keeping the scale near Delta: the tensor product is multiplied by the
 // integer k = round((Delta * q_l) / s^2), so (k s^2) / q_l after the rescale
+i128 big_code(double v) {
+  if (!(std::fabs(v) < std::ldexp(1.0, 120))) throw std::runtime_error("polynomial code too large for its scale");
+  return (i128)std::round(v);   // exact: |v| < 2^120 and round() returns an integral binary64
+}
+
+// Polynomial activation (Evaluation Methodology: ReLU replaced by a polynomial
+// a x^2 + b x + c; the CIFAR-shaped stack uses degree 3).  Every term of one
+// rescale is brought to one scale S by integer codes; the leading coefficient
+// is carried by the scale itself (S = k s^2 / c) so that it is exact while the
+// output scale stays within a small factor of Delta:
+//   d <= 1: y = rescale(k1 x + k0),                S = Delta q_l
+//   d  = 2: y = rescale(k2 x*x + k1 x + k0),       k2 = round(c2 Delta q_l / s^2), S = k2 s^2 / c2
+//   d  = 3: X2 = rescale(k x*x) as for x^2;  u = k3 x' + k2' at S_u = k3 s / c3,
+//           k3 = round(c3 q_{l-1} / s);  y = rescale(X2 * u + k1 x' + k0)  at S = s2 S_u
+// (x' = x with its last limb dropped; k1 = round(c1 S / s), k0 = round(c0 S)).
+std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& in,
+                         const std::vector<double>& coeffs, Layout& Lout, Counts& cnt) {
+  int d = (int)coeffs.size() - 1;
+  while (d > 0 && coeffs[d] == 0.0) d--;
+  if (d > 3) throw std::runtime_error("poly_act: degree above 3");
+  const double s = Lin.scale, Delta = delta_of(C);
+  const double c0 = coeffs.size() > 0 ? coeffs[0] : 0.0, c1 = coeffs.size() > 1 ? coeffs[1] : 0.0;
+  const double c2 = coeffs.size() > 2 ? coeffs[2] : 0.0, c3 = coeffs.size() > 3 ? coeffs[3] : 0.0;
+  std::vector<Ct> out;
+  Lout = Lin;
+  if (d <= 2) {
+    if (Lin.level < 1) throw std::runtime_error("poly_act: no level left");
+    const double ql = (double)C.primes[Lin.level];
+    double S = Delta * ql;
+    i64 k2 = 0;
+    if (d == 2) {
+      k2 = (i64)std::round((c2 * (Delta * ql)) / (s * s));
+      if (k2 == 0) k2 = c2 > 0 ? 1 : -1;
+      S = (((double)k2 * s) * s) / c2;
+    }
+    const i128 k1 = big_code(c1 * S / s), k0 = big_code(c0 * S);
+    for (const Ct& x : in) {
+      Ct y;
+      if (d == 2) {
+        Ct t = square_relin(C, x, k2);
+        cnt.relin++; cnt.ks++; cnt.modup++; cnt.moddown++;
+        y = lin_comb(C, &t, x, k1, k0);
+      } else {
+        y = lin_comb(C, nullptr, x, k1, k0);
+      }
+      y = rescale(C, y);
+      cnt.rescale++;
+      out.push_back(y);
+    }
+    Lout.level = Lin.level - 1;
+    Lout.scale = S / ql;
+  } else {
+    if (Lin.level < 2) throw std::runtime_error("poly_act: degree 3 needs two levels");
+    const double ql = (double)C.primes[Lin.level], q1 = (double)C.primes[Lin.level - 1];
+    i64 k = (i64)std::round((Delta * ql) / (s * s));
+    if (k < 1) k = 1;
+    const double s2 = (((double)k * s) * s) / ql;
+    i64 k3 = (i64)std::round((c3 * q1) / s);
+    if (k3 == 0) k3 = c3 > 0 ? 1 : -1;
+    const double Su = ((double)k3 * s) / c3, S = s2 * Su;
+    const i128 k2c = big_code(c2 * Su), k1 = big_code(c1 * S / s), k0 = big_code(c0 * S);
+    for (const Ct& x : in) {
+      Ct X2 = rescale(C, square_relin(C, x, k));
+      const Ct xd = drop_last_limb(x);
+      const Ct u = lin_comb(C, nullptr, xd, k3, k2c);
+      Ct P = mul_relin(C, X2, u);
+      cnt.relin += 2; cnt.ks += 2; cnt.modup += 2; cnt.moddown += 2;
+      Ct y = rescale(C, lin_comb(C, &P, xd, k1, k0));
+      cnt.rescale += 2;
+      out.push_back(y);
+    }
+    Lout.level = Lin.level - 2;
+    Lout.scale = S / q1;
+  }
+  for (Ct& y : out) y.scale = Lout.scale;
+  return out;
+}
+
 std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                            Counts& cnt) {
   const double s = Lin.scale, ql = (double)C.primes[Lin.level];

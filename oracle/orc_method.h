@@ -51,6 +51,12 @@ std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& i
                          Counts& cnt);
 std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                            Counts& cnt);
+// p(x) = coeffs[0] + coeffs[1] x + ... + coeffs[d] x^d, d <= 3, one rescale per
+// multiplicative level (d <= 2: one level, d = 3: two levels)
+std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& in,
+                         const std::vector<double>& coeffs, Layout& Lout, Counts& cnt);
+// integer nearest to v (half away from zero) for |v| < 2^120, as a 128-bit integer
+i128 big_code(double v);
 std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                          Counts& cnt);
 std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,

@@ -87,6 +87,7 @@ def _declare(L):
         "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, C.POINTER(C.c_long)]),
         "orc_avgpool2": (vp, [vp, vp, C.POINTER(C.c_long)]),
         "orc_square": (vp, [vp, vp, C.POINTER(C.c_long)]),
+        "orc_poly_act": (vp, [vp, vp, f64p, i, C.POINTER(C.c_long)]),
         "orc_compress": (vp, [vp, vp, C.POINTER(C.c_long)]),
         "orc_fc": (vp, [vp, vp, f64p, i, C.POINTER(C.c_long)]),
         "orc_weight_code": (C.c_int64, [d, d]),
@@ -345,6 +346,10 @@ class Oracle:
 
     def square(self, batch):
         return self._op(lib().orc_square, batch.h)
+
+    def poly_act(self, batch, coeffs):
+        c = np.ascontiguousarray(coeffs, np.float64)
+        return self._op(lib().orc_poly_act, batch.h, c, len(c))
 
     def compress(self, batch):
         return self._op(lib().orc_compress, batch.h)

@@ -200,3 +200,37 @@ def test_compress_bottleneck_example():
     assert len(c.data()) == 1 and c.layout()["nfeat"] == o.ns
     assert np.max(np.abs(o.decrypt_tensor(c).reshape(x.shape) - x)) < 1e-6
     assert c.layout()["level"] == L["level"] - 1     # one level, like one PMult
+
+
+def test_poly_act_quadratic_with_unit_leading_coefficient_is_the_square():
+    """p(x) = x^2 takes exactly the x^2 path (same integer k, same residues)."""
+    o = small_oracle()
+    x = rand_x((4, 2, 8, 8), 11) - 0.5
+    L = o.fragment_layout(4, 2, 8, 8, 2)
+    b = o.encrypt_tensor(L, x, seed=5)
+    sq, _ = o.square(b)
+    pa, cnt = o.poly_act(b, [0.0, 0.0, 1.0])
+    assert np.array_equal(sq.data(), pa.data())
+    assert sq.layout()["scale"] == pa.layout()["scale"] and cnt["relin"] == len(b.data())
+
+
+@pytest.mark.parametrize("coeffs", [
+    [0.25, -1.5],                            # affine
+    [0.1471, 0.5, 0.1196],                   # a x^2 + b x + c, ReLU-shaped
+    [-0.3, 0.0, -2.0],                       # negative leading coefficient
+    [0.02, 0.5, 0.2, -0.04],                 # cubic
+    [0.0, 0.0, 0.0, 1.0],                    # x^3 alone
+])
+def test_poly_act_decrypts_to_the_polynomial(coeffs):
+    o = small_oracle()
+    x = 2.0 * rand_x((4, 2, 8, 8), 12) - 1.0
+    L = o.fragment_layout(4, 2, 8, 8, 2)
+    b = o.encrypt_tensor(L, x, seed=6)
+    y, cnt = o.poly_act(b, coeffs)
+    deg = len(coeffs) - 1
+    Ly = y.layout()
+    assert Ly["level"] == L["level"] - (2 if deg == 3 else 1)
+    assert abs(np.log2(Ly["scale"]) - np.log2(2.0 ** 40)) < 0.02      # within 1.4% of Delta
+    assert cnt["relin"] == len(b.data()) * {1: 0, 2: 1, 3: 2}[deg]
+    ref = np.polynomial.polynomial.polyval(x, coeffs)
+    assert np.max(np.abs(o.decrypt_tensor(y) - ref)) < 1e-5
