@@ -213,8 +213,18 @@ int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t
  * three hoisted rotations and doubles dil.  The factor 1/4 is carried in the
  * scale (x4); no level is consumed. */
 int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream);
-/* Polynomial activation coeffs[0] + coeffs[1] x + ... ; this build evaluates
- * degree 2 with coeffs = {0, 0, 1} (x^2: tensor, relinearisation, rescale). */
+/* Polynomial activation p(x) = coeffs[0] + coeffs[1] x + ... + coeffs[degree] x^degree,
+ * degree <= 3 (Evaluation Methodology: ReLU replaced by a low-degree polynomial;
+ * coeffs is a host array of degree+1 doubles).  Leading zero coefficients lower
+ * the degree.  All terms of one rescale share one scale reached by integer
+ * codes, and the leading coefficient is carried by that scale, so the output
+ * scale is within a small factor of Delta (exact value in out->lay.scale):
+ *   degree <= 2: one tensor product (x*x times an integer), relinearisation,
+ *                c1 x + c0 added, one rescale (one level);
+ *   degree 3:    x^2 as above and rescaled, times u = c3 x + c2, relinearised,
+ *                c1 x + c0 added, rescaled (two levels).
+ * Errors: EUNSUPPORTED for degree > 3, ELEVEL without the levels, EINVAL for
+ * non-finite coefficients, ESCALE when a code exceeds 2^120. */
 int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, uint32_t degree,
                   fenc_ctbatch* out, void* stream);
 /* Arch-aware Ct Compression (rot-mask-add): packs a sparse FRAGMENT batch

@@ -87,6 +87,7 @@ FENC_KERNEL(rescale_tail, RescaleTailArgs)
 FENC_KERNEL_XCD(gmac, GmacArgs)
 FENC_KERNEL_XCD(gmac_pt, GmacArgs)
 FENC_KERNEL(tensor_square, SquareArgs)
+FENC_KERNEL(lin_comb, LinArgs)
 FENC_KERNEL(key_combine, KeyArgs)
 FENC_KERNEL(enc_combine, EncArgs)
 FENC_KERNEL(dec_combine, DecArgs)

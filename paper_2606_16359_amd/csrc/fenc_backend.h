@@ -42,6 +42,7 @@ void rescale_tail(Grid g, int threads, Stream s, const fk::RescaleTailArgs& a);
 void gmac(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_pt(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void tensor_square(Grid g, int threads, Stream s, const fk::SquareArgs& a);
+void lin_comb(Grid g, int threads, Stream s, const fk::LinArgs& a);
 void key_combine(Grid g, int threads, Stream s, const fk::KeyArgs& a);
 void enc_combine(Grid g, int threads, Stream s, const fk::EncArgs& a);
 void dec_combine(Grid g, int threads, Stream s, const fk::DecArgs& a);

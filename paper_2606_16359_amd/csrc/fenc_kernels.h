@@ -704,13 +704,16 @@ template <class X>
 FENC_HD void gmac_pt(X& x, const GmacArgs& a) { gmac_any<true>(x, a); }
 
 // ------------------------------------------------------------------ tensor / key / encryption
-// (d0, d1, d2) = k (c0^2, 2 c0 c1, c1^2); d0,d1 into out (ct [2][nl][N]), d2 into d2buf [nl][N]
+// Tensor product of ciphertexts a and b (b == a for a square), times the
+// integer k: (d0, d1, d2) = k (a0 b0, a0 b1 + a1 b0, a1 b1); d0, d1 into out
+// (ct [2][nl][N]), d2 into d2buf [nl][N].
 struct SquareArgs {
   const u64* in;
+  const u64* in_b;
   u64* out;
   u64* d2buf;
   int nl, logn;
-  long long ct_stride;   // elements per ct (in and out)
+  long long ct_stride;   // elements per ct (inputs and out)
   const d2* k;           // [nl] (k mod q_i, /q)
   const d2* pq;
 };
@@ -722,14 +725,43 @@ FENC_HD void tensor_square(X& x, const SquareArgs& a) {
     const long long c = (long long)x.bx * x.nt + t;
     const int i = x.by, b = x.bz;
     const double q = a.pq[i].x, qi = a.pq[i].y;
-    const u64* in = a.in + b * a.ct_stride + i * N + c;
-    const double c0 = u2d(in[0]), c1 = u2d(in[a.nl * N]);
+    const u64* pa = a.in + b * a.ct_stride + i * N + c;
+    const u64* pb = a.in_b + b * a.ct_stride + i * N + c;
+    const double a0 = u2d(pa[0]), a1 = u2d(pa[a.nl * N]);
+    const double b0 = u2d(pb[0]), b1 = u2d(pb[a.nl * N]);
     u64* out = a.out + b * a.ct_stride + i * N + c;
     const d2 k = a.k[i];
-    const double m01 = mulmod_c(mulmod(c0, c1, q, qi), k.x, k.y, q);
-    out[0] = d2u(norm(mulmod_c(mulmod(c0, c0, q, qi), k.x, k.y, q), q));
-    out[a.nl * N] = d2u(norm(red(m01 + m01, q, qi), q));
-    a.d2buf[(long long)b * a.nl * N + i * N + c] = d2u(norm(mulmod_c(mulmod(c1, c1, q, qi), k.x, k.y, q), q));
+    const double m01 = mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);
+    out[0] = d2u(norm(mulmod_c(mulmod(a0, b0, q, qi), k.x, k.y, q), q));
+    out[a.nl * N] = d2u(norm(mulmod_c(m01, k.x, k.y, q), q));
+    a.d2buf[(long long)b * a.nl * N + i * N + c] = d2u(norm(mulmod_c(mulmod(a1, b1, q, qi), k.x, k.y, q), q));
+  });
+}
+
+// out = base + k1 * x + k0 (k0 on poly 0 only: the constant polynomial k0 in
+// NTT form); base may be null; x may have more limbs than out (limb drop).
+struct LinArgs {
+  const u64* x;  long long x_cs, x_ps;
+  const u64* base;  long long b_cs, b_ps;
+  u64* out;  long long o_cs, o_ps;
+  int nl, logn;
+  const d2* k1;          // [nl]
+  const d2* k0;          // [nl]
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void lin_comb(X& x, const LinArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by % a.nl, poly = x.by / a.nl, b = x.bz;
+    const double q = a.pq[i].x, qi = a.pq[i].y;
+    const double xv = u2d(a.x[b * a.x_cs + poly * a.x_ps + i * N + c]);
+    double r = mulmod_c(xv, a.k1[i].x, a.k1[i].y, q);
+    if (a.base) r += u2d(a.base[b * a.b_cs + poly * a.b_ps + i * N + c]);
+    if (poly == 0) r += a.k0[i].x;
+    a.out[b * a.o_cs + poly * a.o_ps + i * N + c] = d2u(norm(red(r, q, qi), q));
   });
 }
 

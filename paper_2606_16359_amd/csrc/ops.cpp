@@ -567,35 +567,115 @@ static void run_pool(Ctx& C, const PoolPlan& P, const u64* in, u64* out, fb::Str
   C.cnt.cts_out += P.n_out;
 }
 
-// ---------------------------------------------------------------- x^2 activation
-struct SquarePlan : Plan {
-  int level = 0, n = 0;
-  KsStage ks;
-  d2* kf = nullptr;   // [nl] scale-restoring integer k mod q_i
+// ---------------------------------------------------------------- polynomial activation
+// p(x) = c0 + c1 x + c2 x^2 + c3 x^3 (Evaluation methodology: ReLU replaced by a
+// low-degree polynomial).  All terms of one rescale share one scale S reached
+// with integer codes; the leading coefficient is carried by S itself:
+//   d <= 1: rescale(k1 x + k0),                   S = Delta q_l
+//   d  = 2: rescale(k2 x*x + k1 x + k0),          k2 = round(c2 Delta q_l / s^2), S = k2 s^2 / c2
+//   d  = 3: X2 = rescale(k x*x) (x^2 path);  u = k3 x' + k2' at S_u = k3 s / c3 with
+//           k3 = round(c3 q_{l-1} / s);  rescale(X2 * u + k1 x' + k0) at S = s2 S_u
+// where x' is x without its last limb, k1 = round(c1 S / s), k0 = round(c0 S).
+struct PolyPlan : Plan {
+  int level = 0, n = 0, d = 0;
+  KsStage ks_a, ks_b;            // relinearisation at level l and l-1
+  d2 *kf = nullptr, *one = nullptr, *k1 = nullptr, *k0 = nullptr, *k3 = nullptr, *k2c = nullptr;
 };
 
-static void run_square(Ctx& C, const SquarePlan& P, const u64* in, u64* out, fb::Stream s) {
-  const int lvl = P.level, nl = lvl + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
+// residues of the integer nearest to v (half away from zero), |v| < 2^120
+static std::vector<d2> code_residues(const Ctx& C, double v, int nl) {
+  if (!(std::fabs(v) < std::ldexp(1.0, 120))) fail(FENC_ESCALE, "polynomial coefficient too large for its scale");
+  const double r = std::fabs(std::round(v));
+  int e = 0;
+  const double f = std::frexp(r, &e);   // r = f 2^e, f in [0.5, 1)
+  std::vector<d2> out(nl);
+  for (int i = 0; i < nl; i++) {
+    const uint64_t q = C.primes[i];
+    uint64_t m;
+    if (e <= 63) {
+      m = (uint64_t)r % q;
+    } else {   // r = mant 2^(e-53) with a 53-bit integer mantissa
+      const uint64_t mant = (uint64_t)std::ldexp(f, 53);
+      m = fh::mulmod(mant % q, fh::powmod(2, (uint64_t)(e - 53), q), q);
+    }
+    if (v < 0 && m) m = q - m;
+    out[i] = cpair(m, q);
+  }
+  return out;
+}
+
+static void run_tensor(Ctx& C, int lvl, int n, const u64* a, const u64* b, const d2* k, u64* t, u64* d2b,
+                       fb::Stream s) {
+  const int nl = lvl + 1;
   const long long ce = ct_elems(C, lvl);
-  Scope sc(C.arena);
-  u64* t = (u64*)C.arena.get((size_t)P.n * ce * 8, s);
-  u64* d2b = (u64*)C.arena.get((size_t)P.n * nl * C.N * 8, s);
-  u64* ext = (u64*)C.arena.get((size_t)P.n * beta * le * C.N * 8, s);
   const bool per_op = C.mode == FENC_MODE_PER_OP;
-  for (int b0 = 0; b0 < P.n; b0 += per_op ? 1 : P.n) {
-    const int nb = per_op ? 1 : P.n;
-    fk::SquareArgs a{in + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, P.kf, C.pq};
-    timed(C, "tensor_square", 5.0 * nb * nl * C.N * 8, s, [&] {
-      fb::tensor_square({(unsigned)std::max(1, C.N / 256), (unsigned)nl, (unsigned)nb}, std::min(256, C.N), s, a);
+  for (int b0 = 0; b0 < n; b0 += per_op ? 1 : n) {
+    const int nb = per_op ? 1 : n;
+    fk::SquareArgs sa{a + b0 * ce, b + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, k, C.pq};
+    timed(C, "tensor_square", (a == b ? 5.0 : 7.0) * nb * nl * C.N * 8, s, [&] {
+      fb::tensor_square({(unsigned)std::max(1, C.N / 256), (unsigned)nl, (unsigned)nb}, std::min(256, C.N), s, sa);
     });
     C.cnt.launches++;
   }
-  modup(C, lvl, d2b, (long long)nl * C.N, 0, P.n, ext, s);
-  kip_moddown(C, lvl, ext, P.ks, t, ce, t, ce, nullptr, 0, s);
-  rescale(C, lvl, t, P.n, out, s);
-  C.cnt.relin += P.n;
-  C.cnt.keyswitch += P.n;
-  C.cnt.cts_out += P.n;
+}
+
+// out[b] = base[b] + k1 x[b] + k0 over nl limbs; x has its own ct / poly strides
+static void run_lin(Ctx& C, int nl, int n, const u64* x, long long x_cs, long long x_ps, const u64* base, u64* out,
+                    const d2* k1, const d2* k0, fb::Stream s) {
+  const long long cs = 2LL * nl * C.N, ps = (long long)nl * C.N;
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  for (int b0 = 0; b0 < n; b0 += per_op ? 1 : n) {
+    const int nb = per_op ? 1 : n;
+    fk::LinArgs la{x + b0 * x_cs, x_cs, x_ps, base ? base + b0 * cs : nullptr, cs, ps, out + b0 * cs, cs, ps,
+                   nl, C.logn, k1, k0, C.pq};
+    timed(C, "lin_comb", (base ? 6.0 : 4.0) * nb * nl * C.N * 8, s, [&] {
+      fb::lin_comb({(unsigned)std::max(1, C.N / 256), (unsigned)(2 * nl), (unsigned)nb}, std::min(256, C.N), s, la);
+    });
+    C.cnt.launches++;
+  }
+}
+
+// relinearise in place: t (d0, d1) += KS(d2b) at level lvl
+static void relin(Ctx& C, int lvl, int n, const KsStage& ks, u64* t, const u64* d2b, fb::Stream s) {
+  const int nl = lvl + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
+  const long long ce = ct_elems(C, lvl);
+  Scope sc(C.arena);
+  u64* ext = (u64*)C.arena.get((size_t)n * beta * le * C.N * 8, s);
+  modup(C, lvl, d2b, (long long)nl * C.N, 0, n, ext, s);
+  kip_moddown(C, lvl, ext, ks, t, ce, t, ce, nullptr, 0, s);
+  C.cnt.relin += n;
+  C.cnt.keyswitch += n;
+}
+
+static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Stream s) {
+  const int l = P.level, n = P.n;
+  const long long ce = ct_elems(C, l);
+  Scope sc(C.arena);
+  u64* t = (u64*)C.arena.get((size_t)n * ce * 8, s);
+  if (P.d <= 1) {
+    run_lin(C, l + 1, n, in, ce, (long long)(l + 1) * C.N, nullptr, t, P.k1, P.k0, s);
+    rescale(C, l, t, n, out, s);
+  } else {
+    u64* d2b = (u64*)C.arena.get((size_t)n * (l + 1) * C.N * 8, s);
+    run_tensor(C, l, n, in, in, P.kf, t, d2b, s);
+    relin(C, l, n, P.ks_a, t, d2b, s);
+    if (P.d == 2) {
+      run_lin(C, l + 1, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
+      rescale(C, l, t, n, out, s);
+    } else {
+      const long long c1e = ct_elems(C, l - 1);
+      u64* x2 = (u64*)C.arena.get((size_t)n * c1e * 8, s);
+      u64* u = (u64*)C.arena.get((size_t)n * c1e * 8, s);
+      rescale(C, l, t, n, x2, s);
+      // x' = x without its last limb: the same words read with level-l strides
+      run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, nullptr, u, P.k3, P.k2c, s);
+      run_tensor(C, l - 1, n, x2, u, P.one, t, d2b, s);
+      relin(C, l - 1, n, P.ks_b, t, d2b, s);
+      run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
+      rescale(C, l - 1, t, n, out, s);
+    }
+  }
+  C.cnt.cts_out += n;
 }
 
 // ---------------------------------------------------------------- compress (AAC)
@@ -1271,42 +1351,82 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
   API_BEGIN
   if (!ctx || !coeffs || !out) fail(FENC_EINVAL, "null argument");
   check_batch(*ctx, in, false);
-  if (!(degree == 2 && coeffs[0] == 0.0 && coeffs[1] == 0.0 && coeffs[2] == 1.0))
-    fail(FENC_EUNSUPPORTED, "this build evaluates the x^2 activation only");
+  if (degree > 3) fail(FENC_EUNSUPPORTED, "polynomial degree above 3");
   fenc_ctx& C = *ctx;
+  double c[4] = {0, 0, 0, 0};
+  for (uint32_t i = 0; i <= degree; i++) {
+    if (!std::isfinite(coeffs[i])) fail(FENC_EINVAL, "non-finite coefficient");
+    c[i] = coeffs[i];
+  }
+  int d = (int)degree;
+  while (d > 0 && c[d] == 0.0) d--;
   Layout Lin = from_pub(C, &in->lay);
-  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the activation");
-  // x^2 with the tensor product multiplied by the integer k = round(Delta q_l / s^2):
-  // the output scale k s^2 / q_l stays within 2^-11 of Delta without a level
+  if (Lin.level < (d == 3 ? 2 : 1)) fail(FENC_ELEVEL, "no level left for the activation");
   const double s0 = Lin.scale, ql = (double)C.primes[Lin.level];
-  int64_t kk = (int64_t)std::round((C.Delta * ql) / (s0 * s0));
-  if (kk < 1) kk = 1;
   Layout Lout = Lin;
-  Lout.level = Lin.level - 1;
-  Lout.scale = (((double)kk * s0) * s0) / ql;
+  double S = C.Delta * ql, kk = 0, k3 = 0, Su = 0;
+  if (d == 2) {
+    kk = std::round((c[2] * (C.Delta * ql)) / (s0 * s0));
+    if (kk == 0) kk = c[2] > 0 ? 1 : -1;
+    S = ((kk * s0) * s0) / c[2];
+    Lout.level = Lin.level - 1;
+    Lout.scale = S / ql;
+  } else if (d == 3) {
+    const double q1 = (double)C.primes[Lin.level - 1];
+    kk = std::round((C.Delta * ql) / (s0 * s0));
+    if (kk < 1) kk = 1;
+    const double s2 = ((kk * s0) * s0) / ql;
+    k3 = std::round((c[3] * q1) / s0);
+    if (k3 == 0) k3 = c[3] > 0 ? 1 : -1;
+    Su = (k3 * s0) / c[3];
+    S = s2 * Su;
+    Lout.level = Lin.level - 2;
+    Lout.scale = S / q1;
+  } else {
+    Lout.level = Lin.level - 1;
+    Lout.scale = S / ql;
+  }
+  if (std::fabs(kk) >= 9007199254740992.0 || std::fabs(k3) >= 9007199254740992.0)
+    fail(FENC_ESCALE, "activation scale factor out of range");
   out->lay = to_pub(C, Lout);
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
-  SquarePlan& P = cached<SquarePlan>(C, "sq|" + layout_key(Lin), [&] {
-    auto p = new SquarePlan;
+  std::ostringstream key;
+  key << "poly|" << layout_key(Lin) << '|' << fnv(c, sizeof(c));
+  PolyPlan& P = cached<PolyPlan>(C, key.str(), [&] {
+    auto p = new PolyPlan;
     p->out = Lout;
     p->level = Lin.level;
     p->n = Lin.n_ct();
-    std::vector<std::vector<KsItem>> items;
-    std::vector<fk::TailItem> tails;
-    const uint64_t* rk = get_key(C, 0);
-    for (int b = 0; b < p->n; b++) {
-      items.push_back({KsItem{b, 1u, rk}});
-      tails.push_back(fk::TailItem{b, b, 0, 0});
+    p->d = d;
+    const int l = Lin.level;
+    auto up = [&](const std::vector<d2>& v) { return upload(C, v, p->owned); };
+    if (d >= 2) {
+      std::vector<std::vector<KsItem>> items;
+      std::vector<fk::TailItem> tails;
+      const uint64_t* rk = get_key(C, 0);
+      for (int b = 0; b < p->n; b++) {
+        items.push_back({KsItem{b, 1u, rk}});
+        tails.push_back(fk::TailItem{b, b, 0, 0});
+      }
+      p->ks_a = make_ks(C, items, tails, {}, p->owned);
+      if (d == 3) p->ks_b = make_ks(C, items, tails, {}, p->owned);
+      p->kf = up(code_residues(C, kk, l + 1));
     }
-    p->ks = make_ks(C, items, tails, {}, p->owned);
-    std::vector<d2> kf(Lin.level + 1);
-    for (int i = 0; i <= Lin.level; i++) kf[i] = cpair((uint64_t)kk % C.primes[i], C.primes[i]);
-    p->kf = upload(C, kf, p->owned);
+    if (d == 3) {
+      p->one = up(code_residues(C, 1.0, l));
+      p->k3 = up(code_residues(C, k3, l));
+      p->k2c = up(code_residues(C, c[2] * Su, l));
+      p->k1 = up(code_residues(C, c[1] * S / s0, l));
+      p->k0 = up(code_residues(C, c[0] * S, l));
+    } else {
+      p->k1 = up(code_residues(C, c[1] * S / s0, l + 1));
+      p->k0 = up(code_residues(C, c[0] * S, l + 1));
+    }
     return p;
   });
-  run_square(C, P, in->data, out->data, (fb::Stream)stream);
+  run_poly(C, P, in->data, out->data, (fb::Stream)stream);
   API_END
 }
 

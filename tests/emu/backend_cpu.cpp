@@ -74,6 +74,7 @@ EMU(rescale_tail, RescaleTailArgs)
 EMU_XCD(gmac, GmacArgs)
 EMU_XCD(gmac_pt, GmacArgs)
 EMU(tensor_square, SquareArgs)
+EMU(lin_comb, LinArgs)
 EMU(key_combine, KeyArgs)
 EMU(enc_combine, EncArgs)
 EMU(dec_combine, DecArgs)

@@ -174,7 +174,7 @@ def test_errors_are_reported_not_launched(backend, orc):
         f.conv2d(ct, np.zeros((4, 4, 3, 3)), stride=4)       # stride must divide S
     assert e.value.code == -8
     with pytest.raises(F.FencError) as e:
-        f.poly_act(ct, (0.5, 0.0, 1.0))
+        f.poly_act(ct, (0.5, 0.0, 1.0, 0.0, 1.0))                 # degree 4
     assert e.value.code == -8
     with pytest.raises(F.FencError) as e:
         f.fc(ct, np.zeros((4, 4)))                            # fc needs a vector layout
@@ -207,3 +207,30 @@ def test_scalar_weights_after_activation_scale_drop(backend, orc):
     cmp(fb, ob, f)
     want = cnn_ref.conv2d(cnn_ref.square(cnn_ref.conv2d(x, w1)), w2)
     assert np.max(np.abs(f.decrypt(fb) - want)) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("coeffs", [
+    (0.25, -1.5),                          # affine
+    (0.1471, 0.5, 0.1196),                 # a x^2 + b x + c, ReLU-shaped
+    (-0.3, 0.0, -2.0),                     # negative leading coefficient
+    (0.02, 0.5, 0.2, -0.04),               # cubic
+    (0.0, 0.0, 0.0, 1.0),                  # x^3 alone
+])
+def test_poly_act_bit_exact(backend, orc, coeffs):
+    """Polynomial activations of degree 1-3 on a 3-ct fragment batch, batched and per-op."""
+    o, f = orc, make(backend, *SMALL)
+    x = 2.0 * rng(21).uniform(0, 1, (4, 3, 8, 8)) - 1.0
+    Lo = o.fragment_layout(4, 3, 8, 8, 2)
+    lay = f.plan_layout(4, 3, 8, 8, 3, 3, 2)
+    ob, fb = o.encrypt_tensor(Lo, x, 3), f.encrypt(f.encode_fragment(x, lay), lay, 3)
+    yo, cnt = o.poly_act(ob, list(coeffs))
+    for mode in (F.FENC_MODE_BATCHED, F.FENC_MODE_PER_OP):
+        f.set_mode(mode)
+        yf = f.poly_act(fb, coeffs)
+        Ly = yo.layout()
+        assert (yf.lay.level, yf.lay.scale) == (Ly["level"], Ly["scale"])
+        cmp(yf, yo, f)
+    f.set_mode(F.FENC_MODE_BATCHED)
+    ref = np.polynomial.polynomial.polyval(x, coeffs)
+    assert np.max(np.abs(f.decrypt(yf) - ref)) < 1e-5
