@@ -47,3 +47,23 @@ def lenet_forward(fenc, ct, w):
     y = fenc.fc(y, w[2])
     y = fenc.fc(y, w[3])
     return fenc.fc(y, w[4])
+
+
+# CIFAR-shaped stack: 3 x (3x3 conv 16->16, same), 3x3 conv 16->32 stride 2,
+# 3x3 conv 32->32 (same), a degree-3 polynomial activation after each conv
+CIFAR_SHAPES = [(16, 16, 3, 3)] * 3 + [(32, 16, 3, 3), (32, 32, 3, 3)]
+CIFAR_STRIDES = [1, 1, 1, 2, 1]
+# a cubic of the ReLU-approximation kind (coefficients c0..c3)
+CUBIC = (0.1, 0.5, 0.25, -0.02)
+
+
+def cifar_inputs(batch=256, channels=16, side=32, shapes=None):
+    """x[batch][channels][side][side] and the conv weights of the CIFAR-shaped stack."""
+    return images((batch, channels, side, side)), weights(shapes or CIFAR_SHAPES)
+
+
+def cifar_forward(fenc, ct, w, strides=None, coeffs=CUBIC):
+    y = ct
+    for wi, s in zip(w, strides or CIFAR_STRIDES):
+        y = fenc.poly_act(fenc.conv2d(y, wi, stride=s, pad=wi.shape[2] // 2), coeffs)
+    return y

@@ -62,3 +62,34 @@ def test_lenet_first_layer_matches_oracle_at_full_size(lenet):
     y = fe.conv2d(ct, w[0])
     assert cnt["ks"] == 32
     assert np.array_equal(fe.export(y), yo.data())
+
+
+def test_cifar_stack_full_size_decrypts_to_float64():
+    """CIFAR-shaped stack at its full size: 256 images 16x32x32, N = 2^16, 24 limbs,
+    dnum 4; three 3x3 convs 16->16, a stride-2 conv 16->32, a conv 32->32, each
+    followed by the cubic activation (two levels each)."""
+    import time
+    import torch
+    from oracle import cnn_ref
+    from oracle import pyoracle as P
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["cifar"])
+    x, w = W.cifar_inputs(256)
+    lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
+    ol = P.Oracle(*W.PARAMS["cifar"]).plan_layout(256, 16, 32, 32, 3, 16)
+    assert (lay.S, lay.n_ct()) == (ol["S"], ol["nbg"] * ol["ncg"] * ol["S"] ** 2) == (4, 128)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    t0 = time.time()
+    out = W.cifar_forward(fe, ct, w)
+    torch.cuda.synchronize()
+    print(f"cifar stack first pass (plans, keys) {time.time() - t0:.2f}s", flush=True)
+    t0 = time.time()
+    out = W.cifar_forward(fe, ct, w)
+    torch.cuda.synchronize()
+    print(f"cifar stack {time.time() - t0:.3f}s for 256 images, {fe.stats()}", flush=True)
+    ref = x
+    for wi, s in zip(w, W.CIFAR_STRIDES):
+        ref = np.polynomial.polynomial.polyval(cnn_ref.conv2d(ref, wi, s, 1), W.CUBIC)
+    assert out.lay.level == 23 - 15
+    assert np.max(np.abs(fe.decrypt(out) - ref)) < 1e-4

@@ -234,3 +234,25 @@ def test_poly_act_bit_exact(backend, orc, coeffs):
     f.set_mode(F.FENC_MODE_BATCHED)
     ref = np.polynomial.polynomial.polyval(x, coeffs)
     assert np.max(np.abs(f.decrypt(yf) - ref)) < 1e-5
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_cifar_shaped_stack_small_bit_exact(backend):
+    """The CIFAR-shaped stack scaled down: 3x3 convs with padding, a stride-2 conv
+    (fragments discarded) and a cubic activation after each conv; N = 2^11."""
+    from paper_2606_16359_amd import workloads as W
+    params = (11, 12, 50, 4, 50, 3, 40, 17)
+    o, f = P.Oracle(*params), make(backend, *params)
+    shapes, strides = [(4, 4, 3, 3), (8, 4, 3, 3), (8, 8, 3, 3)], [1, 2, 1]
+    x, w = W.cifar_inputs(2, 4, 8, shapes)
+    Lo = o.fragment_layout(2, 4, 8, 8, 2)
+    lay = f.plan_layout(2, 4, 8, 8, 3, 4, 2)
+    ob, fb = o.encrypt_tensor(Lo, x, 7), f.encrypt(f.encode_fragment(x, lay), lay, 7)
+    ref = x
+    for wi, s in zip(w, strides):
+        ob = o.poly_act(o.conv2d(ob, wi, s, 1)[0], list(W.CUBIC))[0]
+        ref = np.polynomial.polynomial.polyval(cnn_ref.conv2d(ref, wi, s, 1), W.CUBIC)
+    fb = W.cifar_forward(f, fb, w, strides)
+    cmp(fb, ob, f)
+    assert fb.lay.level == 11 - 9
+    assert np.max(np.abs(f.decrypt(fb) - ref)) < 1e-4
