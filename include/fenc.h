@@ -254,6 +254,16 @@ int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void*
  * prime[i] of row i, through the device kernels. */
 int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t n, int inverse);
 /* Sampler and codec hooks (host only). */
+/* NTT pass shapes, 8 ints: for [forward columns, forward rows, inverse rows,
+ * inverse columns] the radix bits of a register round (3: radix 8, 4: radix
+ * 16) and the log2 of the columns (column pass) or chunks (row pass) a block
+ * stages, -1 for the default.  The shapes change speed, never results.  The
+ * first device use times the candidates on the current GPU and keeps the
+ * fastest (not on the CPU emulator, not during stream capture); setting a
+ * shape turns that off.  Errors: EINVAL for radix bits other than 3/4 or a
+ * tile beyond the pass or above 64 KiB of LDS. */
+int fenc_ntt_config(fenc_ctx* ctx, int32_t* out);
+int fenc_set_ntt_config(fenc_ctx* ctx, const int32_t* cfg);
 uint64_t fenc_sample_word(uint64_t seed, uint64_t tag, uint64_t i);
 int fenc_sample_gauss(uint64_t seed, uint64_t tag, uint64_t i);
 int fenc_encode_int(int32_t log_n, const double* z, double scale, int64_t* m);

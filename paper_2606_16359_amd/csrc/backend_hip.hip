@@ -78,6 +78,10 @@ FENC_KERNEL_LDS(ntt_fwd_cols, NttArgs)
 FENC_KERNEL_LDS(ntt_fwd_rows, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_rows, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_cols, NttArgs)
+FENC_KERNEL_LDS(ntt_fwd_cols16, NttArgs)
+FENC_KERNEL_LDS(ntt_fwd_rows16, NttArgs)
+FENC_KERNEL_LDS(ntt_inv_rows16, NttArgs)
+FENC_KERNEL_LDS(ntt_inv_cols16, NttArgs)
 FENC_KERNEL(modup_fbc, ModUpArgs)
 FENC_KERNEL_XCD(kip, KipArgs)
 FENC_KERNEL(moddown_fbc, ModDownArgs)

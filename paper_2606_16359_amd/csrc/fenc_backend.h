@@ -33,6 +33,11 @@ void ntt_fwd_cols(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs&
 void ntt_fwd_rows(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void ntt_inv_rows(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void ntt_inv_cols(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
+// the same passes with radix-16 register rounds
+void ntt_fwd_cols16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
+void ntt_fwd_rows16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
+void ntt_inv_rows16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
+void ntt_inv_cols16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void modup_fbc(Grid g, int threads, Stream s, const fk::ModUpArgs& a);
 void kip(Grid g, int threads, Stream s, const fk::KipArgs& a);
 void moddown_fbc(Grid g, int threads, Stream s, const fk::ModDownArgs& a);

@@ -67,7 +67,6 @@ struct NttArgs {
   int lcpb;                   // log2 of the chunks per block (row pass)
 };
 
-constexpr int kRadixBits = 3;   // butterfly stages per register round
 
 // Stage index of member f (< 2^k) of the butterfly group whose other stage
 // bits are `rest`, with the k-bit field at bit `lo`.
@@ -78,9 +77,10 @@ FENC_HD inline int member(int rest, int f, int lo, int k) {
 // One register round of forward (Cooley-Tukey) stages s0..s0+K-1 of a pass
 // with P stage bits: local stage s pairs stage-index bit P-1-s.  tw_of(s, a)
 // is the twiddle of the butterfly whose upper element has stage index a.
-// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2] (K <= 3 keeps
-// every product operand below 3q and every sum below 4q < 2^52).  K is a
-// compile-time constant so the group lives in registers.
+// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2].  Three
+// stages keep every product operand below 3q and every sum below 4q < 2^52;
+// a fourth stage (K = 4) follows a reduction.  K is a compile-time constant
+// so the group lives in registers.
 template <int K, class LD, class ST, class TW>
 FENC_HD inline void fwd_round(int rest, int s0, int P, double q, double qi, LD ld, ST st, TW tw_of) {
   double v[1 << K];
@@ -89,6 +89,10 @@ FENC_HD inline void fwd_round(int rest, int s0, int P, double q, double qi, LD l
   for (int f = 0; f < (1 << K); f++) v[f] = ld(member(rest, f, lo, K));
 #pragma unroll
   for (int s = 0; s < K; s++) {
+    if (s == 3) {   // K = 4: bring the values back below q/2 before the fourth stage
+#pragma unroll
+      for (int f = 0; f < (1 << K); f++) v[f] = red(v[f], q, qi);
+    }
     const int half = 1 << (K - 1 - s);
 #pragma unroll
     for (int f = 0; f < (1 << K); f++) {
@@ -127,13 +131,15 @@ FENC_HD inline void inv_round(int rest, int s0, double q, double qi, LD ld, ST s
   for (int f = 0; f < (1 << K); f++) st(member(rest, f, lo, K), v[f]);
 }
 
-// Round schedule of a pass with P stage bits: ceil(P/3) register rounds of
-// nearly equal size (larger rounds first).
-FENC_HD constexpr int n_rounds(int P) { return (P + kRadixBits - 1) / kRadixBits; }
-FENC_HD constexpr int round_size(int P, int r) {
-  return P / n_rounds(P) + (r < P % n_rounds(P) ? 1 : 0);
+// Round schedule of a pass with P stage bits and rounds of at most RB stages:
+// ceil(P/RB) register rounds of nearly equal size (larger rounds first).
+FENC_HD constexpr int n_rounds(int P, int RB) { return (P + RB - 1) / RB; }
+FENC_HD constexpr int round_size(int P, int RB, int r) {
+  return P / n_rounds(P, RB) + (r < P % n_rounds(P, RB) ? 1 : 0);
 }
-FENC_HD constexpr int round_start(int P, int r) { return r == 0 ? 0 : round_start(P, r - 1) + round_size(P, r - 1); }
+FENC_HD constexpr int round_start(int P, int RB, int r) {
+  return r == 0 ? 0 : round_start(P, RB, r - 1) + round_size(P, RB, r - 1);
+}
 
 template <int R, int NR>
 struct RoundLoop {
@@ -186,7 +192,7 @@ FENC_HD inline void with_count(int n, B body) {
 // the thread's group index so neighbouring threads touch neighbouring words.
 // Forward: the first n1 stages; inverse: the last n1 stages, then * N^-1.
 // The first round reads HBM, the last writes HBM, the others use LDS.
-template <bool INV, int P, class X>
+template <bool INV, int P, int RB, class X>
 FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
   const int n2 = a.n2, sb = a.lcols, T = x.nt, bm = (1 << sb) - 1;
   const int row = x.by;
@@ -197,10 +203,10 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
   const d2* tw = a.tw + ((long long)p << a.logn);
   double* sm = x.smem;
   const d2 ni = INV ? a.ninv[p] : d2{0, 0};
-  RoundLoop<0, n_rounds(P)>::run([&](auto R) {
+  RoundLoop<0, n_rounds(P, RB)>::run([&](auto R) {
     constexpr int r = decltype(R)::value;
-    constexpr int K = round_size(P, r), s0 = round_start(P, r);
-    constexpr bool first = r == 0, last = r == n_rounds(P) - 1;
+    constexpr int K = round_size(P, RB, r), s0 = round_start(P, RB, r);
+    constexpr bool first = r == 0, last = r == n_rounds(P, RB) - 1;
     x.phase([&](int t) {
       for (int g = t; g < (1 << (P + sb - K)); g += T) {
         const int c = g & bm, rest = g >> sb;
@@ -232,7 +238,7 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
 // stages 2^lcpb chunks.  The chunk is the high part of the thread's group
 // index so neighbouring threads touch neighbouring words.  Forward: the last
 // n2 stages; inverse: the first n2 stages.
-template <bool INV, int P, class X>
+template <bool INV, int P, int RB, class X>
 FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
   const int n1 = a.n1, cb = a.lcpb, T = x.nt, logn = a.logn;
   const int row = x.by;
@@ -243,10 +249,10 @@ FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
   const double q = a.pq[p].x, qi = a.pq[p].y;
   const d2* tw = a.tw + ((long long)p << logn);
   double* sm = x.smem;
-  RoundLoop<0, n_rounds(P)>::run([&](auto R) {
+  RoundLoop<0, n_rounds(P, RB)>::run([&](auto R) {
     constexpr int r = decltype(R)::value;
-    constexpr int K = round_size(P, r), s0 = round_start(P, r);
-    constexpr bool first = r == 0, last = r == n_rounds(P) - 1;
+    constexpr int K = round_size(P, RB, r), s0 = round_start(P, RB, r);
+    constexpr bool first = r == 0, last = r == n_rounds(P, RB) - 1;
     x.phase([&](int t) {
       for (int g = t; g < (1 << (P + cb - K)); g += T) {
         const int rest = g & ((1 << (P - K)) - 1), ch = g >> (P - K);
@@ -272,30 +278,39 @@ FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
   });
 }
 
-template <class X>
-FENC_HD void ntt_fwd_cols(X& x, const NttArgs& a) {
+// Kernel entries: radix-8 rounds (RB = 3) and radix-16 rounds (RB = 4).
+template <int RB, class X>
+FENC_HD void ntt_fwd_cols_rb(X& x, const NttArgs& a) {
   const int p = a.pm.p[x.by % a.pm.n];
   if (p == kSkip) return;
-  with_pass(a.n1, [&](auto P) { ntt_cols_pass<false, decltype(P)::value>(x, a, p); });
+  with_pass(a.n1, [&](auto P) { ntt_cols_pass<false, decltype(P)::value, RB>(x, a, p); });
 }
-template <class X>
-FENC_HD void ntt_inv_cols(X& x, const NttArgs& a) {
+template <int RB, class X>
+FENC_HD void ntt_inv_cols_rb(X& x, const NttArgs& a) {
   const int p = a.pm.p[x.by % a.pm.n];
   if (p == kSkip) return;
-  with_pass(a.n1, [&](auto P) { ntt_cols_pass<true, decltype(P)::value>(x, a, p); });
+  with_pass(a.n1, [&](auto P) { ntt_cols_pass<true, decltype(P)::value, RB>(x, a, p); });
 }
-template <class X>
-FENC_HD void ntt_fwd_rows(X& x, const NttArgs& a) {
+template <int RB, class X>
+FENC_HD void ntt_fwd_rows_rb(X& x, const NttArgs& a) {
   const int p = a.pm.p[x.by % a.pm.n];
   if (p == kSkip) return;
-  with_pass(a.n2, [&](auto P) { ntt_rows_pass<false, decltype(P)::value>(x, a, p); });
+  with_pass(a.n2, [&](auto P) { ntt_rows_pass<false, decltype(P)::value, RB>(x, a, p); });
 }
-template <class X>
-FENC_HD void ntt_inv_rows(X& x, const NttArgs& a) {
+template <int RB, class X>
+FENC_HD void ntt_inv_rows_rb(X& x, const NttArgs& a) {
   const int p = a.pm.p[x.by % a.pm.n];
   if (p == kSkip) return;
-  with_pass(a.n2, [&](auto P) { ntt_rows_pass<true, decltype(P)::value>(x, a, p); });
+  with_pass(a.n2, [&](auto P) { ntt_rows_pass<true, decltype(P)::value, RB>(x, a, p); });
 }
+template <class X> FENC_HD void ntt_fwd_cols(X& x, const NttArgs& a) { ntt_fwd_cols_rb<3>(x, a); }
+template <class X> FENC_HD void ntt_inv_cols(X& x, const NttArgs& a) { ntt_inv_cols_rb<3>(x, a); }
+template <class X> FENC_HD void ntt_fwd_rows(X& x, const NttArgs& a) { ntt_fwd_rows_rb<3>(x, a); }
+template <class X> FENC_HD void ntt_inv_rows(X& x, const NttArgs& a) { ntt_inv_rows_rb<3>(x, a); }
+template <class X> FENC_HD void ntt_fwd_cols16(X& x, const NttArgs& a) { ntt_fwd_cols_rb<4>(x, a); }
+template <class X> FENC_HD void ntt_inv_cols16(X& x, const NttArgs& a) { ntt_inv_cols_rb<4>(x, a); }
+template <class X> FENC_HD void ntt_fwd_rows16(X& x, const NttArgs& a) { ntt_fwd_rows_rb<4>(x, a); }
+template <class X> FENC_HD void ntt_inv_rows16(X& x, const NttArgs& a) { ntt_inv_rows_rb<4>(x, a); }
 
 // ------------------------------------------------------------------ ModUp
 // Fast base conversion of every digit of c1 (coefficient form) to the other

@@ -1543,6 +1543,34 @@ int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void*
   API_END
 }
 
+int fenc_ntt_config(fenc_ctx* ctx, int32_t* out) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  for (int k = 0; k < 4; k++) {
+    out[2 * k] = ctx->ntt_cfg[k][0];
+    out[2 * k + 1] = ctx->ntt_cfg[k][1];
+  }
+  API_END
+}
+
+int fenc_set_ntt_config(fenc_ctx* ctx, const int32_t* cfg) {
+  API_BEGIN
+  if (!ctx || !cfg) fail(FENC_EINVAL, "null argument");
+  const int n2 = (ctx->logn + 1) / 2, n1 = ctx->logn - n2;
+  for (int k = 0; k < 4; k++) {
+    const int rb = cfg[2 * k], t = cfg[2 * k + 1];
+    const int P = (k == 0 || k == 3) ? n1 : n2, other = (k == 0 || k == 3) ? n2 : n1;
+    if (rb != 3 && rb != 4) fail(FENC_EINVAL, "NTT radix bits must be 3 or 4");
+    if (t < -1 || t > other || (t >= 0 && (8LL << (P + t)) > (64 << 10))) fail(FENC_EINVAL, "NTT tile out of range");
+  }
+  for (int k = 0; k < 4; k++) {
+    ctx->ntt_cfg[k][0] = cfg[2 * k];
+    ctx->ntt_cfg[k][1] = cfg[2 * k + 1];
+  }
+  ctx->ntt_tuned = true;   // an explicit shape is not re-tuned
+  API_END
+}
+
 int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t n, int inverse) {
   API_BEGIN
   if (!ctx || !rows || !prime || n == 0 || n > (uint32_t)fk::kMaxMap) fail(FENC_EINVAL, "bad argument");

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <thread>
 
 namespace fr {
@@ -131,6 +132,7 @@ void ensure_device(Ctx& C) {
   fb::small_to_rns({grid_x(C), (unsigned)np, 1}, block_threads(C), nullptr, a);
   ntt(C, false, C.s_ntt, C.s_ntt, 0, 0, np, np, identity_map(np), nullptr);
   fb::sync(nullptr);
+  autotune_ntt(C);
 }
 
 const LevelTabs& level_tabs(Ctx& C, int level) {
@@ -189,29 +191,110 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
   a.logn = C.logn;
   a.n2 = (C.logn + 1) / 2;
   a.n1 = C.logn - a.n2;
-  a.lcols = std::min(4, a.n2);                                   // 16 columns per block
-  a.lcpb = std::min(std::max(0, 11 - a.n2), a.n1);              // ~2048 elements per block
+  // pass shape: radix bits and tile (defaults: radix 8, 16 columns / ~2048 elements per block)
+  auto shape = [&](int k, int P, int other, int def) {
+    const int rb = C.ntt_cfg[k][0];
+    const int t = C.ntt_cfg[k][1] >= 0 ? std::min(C.ntt_cfg[k][1], other) : def;
+    const int nr = (P + rb - 1) / rb, kmax = P / nr + (P % nr ? 1 : 0);   // size of the first (largest) round
+    const int T = (int)std::min<long long>(256, std::max<long long>(64, 1LL << std::max(0, P + t - kmax)));
+    return std::array<int, 3>{rb, t, T};
+  };
+  const auto fc = shape(inverse ? 3 : 0, a.n1, a.n2, std::min(4, a.n2));
+  const auto fr = shape(inverse ? 2 : 1, a.n2, a.n1, std::min(std::max(0, 11 - a.n2), a.n1));
+  a.lcols = fc[1];
+  a.lcpb = fr[1];
   const unsigned colblocks = 1u << (a.n2 - a.lcols), rowblocks = 1u << (a.n1 - a.lcpb);
   const size_t lds_c = (size_t)8 << (a.n1 + a.lcols), lds_r = (size_t)8 << (a.n2 + a.lcpb);
-  const int T = 256;
   int active = 0;
   for (int r = 0; r < std::min(nrows, pm.n); r++) active += (pm.p[r] != fk::kSkip);
   active = (int)((long long)active * nrows / std::max(1, std::min(nrows, pm.n)));
   const double pass_bytes = 16.0 * active * C.N;   // read + write of every active row
+  const fb::Grid gc{colblocks, (unsigned)nrows, 1}, gr{rowblocks, (unsigned)nrows, 1};
   if (!inverse) {
-    timed(C, "ntt_fwd_cols", pass_bytes, s, [&] { fb::ntt_fwd_cols({colblocks, (unsigned)nrows, 1}, T, lds_c, s, a); });
+    timed(C, "ntt_fwd_cols", pass_bytes, s, [&] {
+      if (fc[0] == 4) fb::ntt_fwd_cols16(gc, fc[2], lds_c, s, a);
+      else fb::ntt_fwd_cols(gc, fc[2], lds_c, s, a);
+    });
     a.src = dst;
     a.src_gs = dst_gs;
-    timed(C, "ntt_fwd_rows", pass_bytes, s, [&] { fb::ntt_fwd_rows({rowblocks, (unsigned)nrows, 1}, T, lds_r, s, a); });
+    timed(C, "ntt_fwd_rows", pass_bytes, s, [&] {
+      if (fr[0] == 4) fb::ntt_fwd_rows16(gr, fr[2], lds_r, s, a);
+      else fb::ntt_fwd_rows(gr, fr[2], lds_r, s, a);
+    });
     C.cnt.ntt_limbs += active;
   } else {
-    timed(C, "ntt_inv_rows", pass_bytes, s, [&] { fb::ntt_inv_rows({rowblocks, (unsigned)nrows, 1}, T, lds_r, s, a); });
+    timed(C, "ntt_inv_rows", pass_bytes, s, [&] {
+      if (fr[0] == 4) fb::ntt_inv_rows16(gr, fr[2], lds_r, s, a);
+      else fb::ntt_inv_rows(gr, fr[2], lds_r, s, a);
+    });
     a.src = dst;
     a.src_gs = dst_gs;
-    timed(C, "ntt_inv_cols", pass_bytes, s, [&] { fb::ntt_inv_cols({colblocks, (unsigned)nrows, 1}, T, lds_c, s, a); });
+    timed(C, "ntt_inv_cols", pass_bytes, s, [&] {
+      if (fc[0] == 4) fb::ntt_inv_cols16(gc, fc[2], lds_c, s, a);
+      else fb::ntt_inv_cols(gc, fc[2], lds_c, s, a);
+    });
     C.cnt.intt_limbs += active;
   }
   C.cnt.launches += 2;
+}
+
+// ---------------------------------------------------------------- NTT autotuning
+// Every candidate pass shape computes the same residues; only speed differs.
+// Each pass is timed on a batch of rows with HIP events and the fastest shape
+// is kept.  Skipped on the CPU emulator and while a stream is being captured.
+void autotune_ntt(Ctx& C) {
+  if (C.ntt_tuned) return;
+  C.ntt_tuned = true;
+  if (std::string(fb::backend_name()) != "hip-gfx950" || C.logn < 10 || fb::capturing(nullptr)) return;
+  const int rows = std::max(8, std::min(256, (int)((64LL << 20) / ((long long)C.N * 8))));
+  std::vector<void*> tmp;
+  u64* buf = (u64*)dalloc(C, (size_t)rows * C.N * 8, tmp);
+  std::vector<u64> zero((size_t)C.N, 0);
+  for (int r = 0; r < rows; r++) fb::h2d(buf + (size_t)r * C.N, zero.data(), (size_t)C.N * 8);
+  fk::PrimeMap pm;
+  pm.n = std::min(C.np, fk::kMaxMap);
+  for (int i = 0; i < pm.n; i++) pm.p[i] = (unsigned char)i;
+  const int n2 = (C.logn + 1) / 2, n1 = C.logn - n2;
+  void* e0 = fb::event_create();
+  void* e1 = fb::event_create();
+  auto time_dir = [&](bool inverse) {
+    float best = 0;
+    fb::sync(nullptr);
+    for (int rep = 0; rep < 4; rep++) {
+      fb::event_record(e0, nullptr);
+      ntt(C, inverse, buf, buf, (long long)pm.n * C.N, (long long)pm.n * C.N, rows, pm.n, pm, nullptr);
+      fb::event_record(e1, nullptr);
+      const float ms = fb::event_elapsed_ms(e0, e1);
+      if (rep > 0 && (best == 0 || ms < best)) best = ms;
+    }
+    return best;
+  };
+  // tune one pass at a time, the other pass at its current shape
+  for (int k = 0; k < 4; k++) {
+    const bool inverse = k >= 2, cols = (k == 0 || k == 3);
+    const int P = cols ? n1 : n2, other = cols ? n2 : n1;
+    int best_rb = C.ntt_cfg[k][0], best_t = C.ntt_cfg[k][1];
+    float best = time_dir(inverse);
+    for (int rb = 3; rb <= 4; rb++)
+      for (int t = 0; t <= std::min(other, 5); t++) {
+        if ((8LL << (P + t)) > (64 << 10)) continue;   // LDS tile at most 64 KiB
+        if ((1LL << (P + t)) < 512) continue;         // at least 512 elements per block
+        C.ntt_cfg[k][0] = rb;
+        C.ntt_cfg[k][1] = t;
+        const float ms = time_dir(inverse);
+        if (ms < best) {
+          best = ms;
+          best_rb = rb;
+          best_t = t;
+        }
+      }
+    C.ntt_cfg[k][0] = best_rb;
+    C.ntt_cfg[k][1] = best_t;
+  }
+  fb::sync(nullptr);
+  fb::event_destroy(e0);
+  fb::event_destroy(e1);
+  for (void* p : tmp) fb::dev_free(p);
 }
 
 // ---------------------------------------------------------------- keys

@@ -161,6 +161,10 @@ struct fenc_ctx {
   std::vector<void*> owned;
   fr::Arena arena;
   int64_t dev_bytes = 0;
+  // NTT pass shapes: [fwd cols, fwd rows, inv rows, inv cols] = {radix bits (3 or 4),
+  // log2 of columns (cols pass) or chunks (rows pass) per block}; results do not depend on them
+  int ntt_cfg[4][2] = {{3, -1}, {3, -1}, {3, -1}, {3, -1}};
+  bool ntt_tuned = false;
   // single-kernel profiling: events around every launch of `prof_kernel`
   std::string prof_kernel;
   struct ProfRec {
@@ -176,6 +180,8 @@ namespace fr {
 typedef fenc_ctx Ctx;
 
 void ensure_device(Ctx& C);
+// times the candidate NTT pass shapes on this device and keeps the fastest
+void autotune_ntt(Ctx& C);
 void* dalloc(Ctx& C, size_t bytes, std::vector<void*>& owner);
 template <class T>
 T* upload(Ctx& C, const std::vector<T>& v, std::vector<void*>& owner) {

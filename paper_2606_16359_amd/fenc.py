@@ -112,6 +112,8 @@ def load(path=None):
         "fenc_rotate_sum": (C.c_int, [vp, B, B, vp, u32, B, vp]),
         "fenc_rescale": (C.c_int, [vp, B, B, vp]),
         "fenc_ntt_rows": (C.c_int, [vp, vp, vp, u32, C.c_int]),
+        "fenc_ntt_config": (C.c_int, [vp, vp]),
+        "fenc_set_ntt_config": (C.c_int, [vp, vp]),
         "fenc_sample_word": (u64, [u64, u64, u64]),
         "fenc_sample_gauss": (C.c_int, [u64, u64, u64]),
         "fenc_encode_int": (C.c_int, [i32, vp, d, vp]),
@@ -197,6 +199,15 @@ class Fenc:
 
     def set_mode(self, mode):
         self._check(self.lib.fenc_set_mode(self.h, mode))
+
+    def ntt_config(self):
+        out = np.zeros(8, np.int32)
+        self._check(self.lib.fenc_ntt_config(self.h, out.ctypes.data))
+        return [tuple(int(v) for v in out[2 * k:2 * k + 2]) for k in range(4)]
+
+    def set_ntt_config(self, cfg):
+        arr = np.array([v for pair in cfg for v in pair], np.int32)
+        self._check(self.lib.fenc_set_ntt_config(self.h, arr.ctypes.data))
 
     def set_plaintext_budget(self, nbytes):
         self._check(self.lib.fenc_set_plaintext_budget(self.h, nbytes))

@@ -65,6 +65,10 @@ EMU_LDS(ntt_fwd_cols, NttArgs)
 EMU_LDS(ntt_fwd_rows, NttArgs)
 EMU_LDS(ntt_inv_rows, NttArgs)
 EMU_LDS(ntt_inv_cols, NttArgs)
+EMU_LDS(ntt_fwd_cols16, NttArgs)
+EMU_LDS(ntt_fwd_rows16, NttArgs)
+EMU_LDS(ntt_inv_rows16, NttArgs)
+EMU_LDS(ntt_inv_cols16, NttArgs)
 EMU(modup_fbc, ModUpArgs)
 EMU_XCD(kip, KipArgs)
 EMU(moddown_fbc, ModDownArgs)

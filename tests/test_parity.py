@@ -55,6 +55,40 @@ def test_ntt_roundtrip_and_product(backend, logn):
 
 
 @pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("logn", [11, 15])
+def test_ntt_pass_shapes_give_identical_residues(backend, logn):
+    """Radix-8 and radix-16 rounds and every tile size compute the same NTT."""
+    f = make(backend, logn, 3, 50, 1, 50, 3, 40, 3)
+    o = P.Oracle(logn, 3, 50, 1, 50, 3, 40, 3)
+    r = rng(logn + 1)
+    primes = o.primes()
+    pidx = [0, 1, 2, 3, 1]                       # 5 rows: ragged against any batch shape
+    rows = np.array([r.integers(0, primes[p], o.N, dtype=np.uint64) for p in pidx])
+    n2 = (logn + 1) // 2
+    n1 = logn - n2
+    shapes = [[(3, -1)] * 4, [(4, -1)] * 4, [(4, 0), (4, 0), (3, 0), (3, 0)],
+              [(3, min(5, n2)), (4, min(3, n1)), (4, min(2, n1)), (3, 2)]]
+    shapes = [[(rb, t if t < 0 or 8 << ((n1 if k in (0, 3) else n2) + t) <= 65536 else 0)
+               for k, (rb, t) in enumerate(sh)] for sh in shapes]
+    want_f = want_i = None
+    for sh in shapes:
+        f.set_ntt_config(sh)
+        assert f.ntt_config() == [tuple(x) for x in sh]
+        A = f.ntt_rows(rows, pidx)
+        B = f.ntt_rows(A, pidx, inverse=True)
+        assert np.array_equal(B, rows)
+        if want_f is None:
+            want_f = A
+            # a spot check against the oracle's NTT (natural order there, bit-reversed here)
+            nat = o.ntt(pidx[0], rows[0])
+            br = [int(format(k, f"0{logn}b")[::-1], 2) for k in range(o.N)]
+            assert np.array_equal(A[0], nat[br])
+        assert np.array_equal(A, want_f)
+    with pytest.raises(F.FencError):
+        f.set_ntt_config([(5, -1)] * 4)
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
 def test_encrypt_keys_and_keyswitch_building_blocks(backend, orc):
     o, f = orc, make(backend, *SMALL)
     assert f.primes() == o.primes()
