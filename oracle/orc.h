@@ -150,6 +150,13 @@ void key_inner_product(Context& C, const std::vector<RPoly>& ext, u64 keyid, int
 // rotations (left by `shift` slots), hoisted form: ModUp(c1) once, automorphism
 // applied to the extended digits, one ModDown per output
 std::vector<Ct> rotate_hoisted(Context& C, const Ct& x, const std::vector<i64>& shifts);
+// hoisted rotations left in the extended basis Q_l U P (no ModDown):
+// (KIP_0 + P sigma_g(c0), KIP_1); ModDown of the result is the rotated ciphertext
+std::vector<Ct> rotate_hoisted_pq(Context& C, const Ct& x, const std::vector<i64>& shifts);
+// (P x0, P x1) over Q_l U P (zero on the special primes); ModDown gives x back
+Ct lift_pq(const Context& C, const Ct& x);
+// ModDown of both polys of an extended-basis ciphertext
+Ct mod_down_ct(const Context& C, const Ct& y);
 // lazy form: y = z0 + sum_r Rot(z_r, shift_r) with a single ModDown
 Ct rotate_sum_lazy(Context& C, const Ct* z0, const std::vector<const Ct*>& zs,
                    const std::vector<i64>& shifts);

@@ -239,6 +239,23 @@ int orc_rotate(void* c, const uint64_t* ct, int level, const int64_t* shifts, in
   GUARD_END(-1)
 }
 
+// the extended-basis forms moved down: mode 0 rotations (ModDown of
+// rotate_hoisted_pq), mode 1 the lift P x (ModDown of lift_pq, shifts unused)
+int orc_pq_roundtrip(void* c, const uint64_t* ct, int level, const int64_t* shifts, int n, int mode, uint64_t* out) {
+  GUARD_BEGIN
+  Context* C = (Context*)c;
+  const Ct x = ct_from(*C, ct, level, 1.0);
+  const size_t per = 2 * (size_t)(level + 1) * C->N;
+  if (mode == 1) {
+    ct_to(*C, mod_down_ct(*C, lift_pq(*C, x)), out);
+    return 0;
+  }
+  std::vector<Ct> r = rotate_hoisted_pq(*C, x, std::vector<i64>(shifts, shifts + n));
+  for (int i = 0; i < n; i++) ct_to(*C, mod_down_ct(*C, r[i]), out + i * per);
+  return 0;
+  GUARD_END(-1)
+}
+
 int orc_rotate_sum(void* c, const uint64_t* z0, const uint64_t* zs, const int64_t* shifts, int n,
                    int level, uint64_t* out) {
   GUARD_BEGIN
@@ -361,23 +378,23 @@ int orc_decrypt_tensor(void* c, void* bp, double* x) {
 }
 
 void* orc_conv2d(void* c, void* bp, const double* w, int cout, int k, int stride, int pad, int groups,
-                 long long pt_budget, long* counts) {
+                 long long pt_budget, int hoist, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
-  out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt, pt_budget);
+  out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt, pt_budget, hoist);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)
 }
 
-void* orc_avgpool2(void* c, void* bp, long* counts) {
+void* orc_avgpool2(void* c, void* bp, int hoist, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
-  out->cts = avgpool2(*(Context*)c, in->L, in->cts, out->L, cnt);
+  out->cts = avgpool2(*(Context*)c, in->L, in->cts, out->L, cnt, hoist);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)

@@ -519,6 +519,72 @@ std::vector<Ct> rotate_hoisted(Context& C, const Ct& x, const std::vector<i64>& 
   return out;
 }
 
+// P mod q for every prime index of pidx (zero on the special primes)
+static std::vector<u64> p_mod(const Context& C, const std::vector<int>& pidx) {
+  std::vector<u64> r;
+  for (int i : pidx) {
+    const u64 q = C.primes[i];
+    u64 v = 1;
+    for (int k = 0; k < C.K; k++) v = mulm(v, C.primes[C.L + 1 + k] % q, q);
+    r.push_back(v);
+  }
+  return r;
+}
+
+std::vector<Ct> rotate_hoisted_pq(Context& C, const Ct& x, const std::vector<i64>& shifts) {
+  std::vector<RPoly> ext = mod_up(C, x.c1, x.level);
+  const std::vector<int> qp = qp_basis(C, x.level);
+  const std::vector<u64> pm = p_mod(C, qp);
+  std::vector<Ct> out;
+  for (i64 r : shifts) {
+    u64 g = C.galois(r);
+    if (g == 1) throw std::runtime_error("rotate_hoisted_pq: zero shift");
+    std::vector<RPoly> eg;
+    for (const RPoly& e : ext) eg.push_back(automorph(C, e, g));
+    RPoly a0, a1;
+    key_inner_product(C, eg, g, x.level, a0, a1);
+    const RPoly c0g = automorph(C, x.c0, g);
+    for (int l = 0; l <= x.level; l++) {   // + P sigma_g(c0) on the Q limbs (P = 0 mod p_k)
+      const u64 q = C.primes[qp[l]];
+      for (int i = 0; i < C.N; i++) a0.c[l][i] = addm(a0.c[l][i], mulm(c0g.c[l][i], pm[l], q), q);
+    }
+    Ct y;
+    y.c0 = a0;
+    y.c1 = a1;
+    y.level = x.level;
+    y.scale = x.scale;
+    out.push_back(y);
+  }
+  return out;
+}
+
+Ct lift_pq(const Context& C, const Ct& x) {
+  const std::vector<int> qp = qp_basis(C, x.level);
+  const std::vector<u64> pm = p_mod(C, qp);
+  Ct y;
+  y.c0 = poly_zero(C, qp);
+  y.c1 = poly_zero(C, qp);
+  for (int l = 0; l <= x.level; l++) {
+    const u64 q = C.primes[qp[l]];
+    for (int i = 0; i < C.N; i++) {
+      y.c0.c[l][i] = mulm(x.c0.c[l][i], pm[l], q);
+      y.c1.c[l][i] = mulm(x.c1.c[l][i], pm[l], q);
+    }
+  }
+  y.level = x.level;
+  y.scale = x.scale;
+  return y;
+}
+
+Ct mod_down_ct(const Context& C, const Ct& y) {
+  Ct r;
+  r.c0 = mod_down(C, y.c0, y.level);
+  r.c1 = mod_down(C, y.c1, y.level);
+  r.level = y.level;
+  r.scale = y.scale;
+  return r;
+}
+
 Ct rotate_sum_lazy(Context& C, const Ct* z0, const std::vector<const Ct*>& zs,
                    const std::vector<i64>& shifts) {
   assert(!zs.empty() && zs.size() == shifts.size());

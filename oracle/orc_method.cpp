@@ -209,7 +209,7 @@ static void add_inplace(const Context& C, Ct& a, const Ct& b) {
 
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
-                       long long pt_budget) {
+                       long long pt_budget, int hoist) {
   if (Lin.kind != KIND_FRAGMENT || Lin.dil != 1) throw std::runtime_error("conv2d: needs a dense fragment layout");
   if (stride < 1 || Lin.S % stride) throw std::runtime_error("conv2d: stride must divide S");
   const int cin = Lin.c;
@@ -272,17 +272,29 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
               }
           }
         }
-  // hoisted inner rotations: one ModUp per input ciphertext
+  // hoisted inner rotations: one ModUp per input ciphertext.  hoist = 1 keeps
+  // the rotated copies in the extended basis Q_l U P, takes the linear
+  // combination there (unrotated inputs enter as P x) and moves each combined
+  // ciphertext down once; hoist = 0 moves every copy down.
+  const std::vector<int> basis = hoist ? qp_basis(C, lvl) : q_basis(lvl);
   std::map<std::pair<int, long>, Ct> copies;
   for (auto& kv : need) {
     std::vector<i64> sh(kv.second.begin(), kv.second.end());
-    std::vector<Ct> r = rotate_hoisted(C, in[kv.first], sh);
+    std::vector<Ct> r = hoist ? rotate_hoisted_pq(C, in[kv.first], sh) : rotate_hoisted(C, in[kv.first], sh);
     for (size_t i = 0; i < sh.size(); i++) copies[{kv.first, sh[i]}] = r[i];
     cnt.inner_rot += sh.size();
     cnt.ks += sh.size();
     cnt.modup += 1;
-    cnt.moddown += sh.size();
+    if (!hoist) cnt.moddown += sh.size();
   }
+  std::map<int, Ct> lifted;   // P x of the unrotated inputs (hoist = 1)
+  auto source = [&](int idx, long shift) -> const Ct& {
+    if (shift) return copies.at({idx, shift});
+    if (!hoist) return in[idx];
+    auto it = lifted.find(idx);
+    if (it == lifted.end()) it = lifted.emplace(idx, lift_pq(C, in[idx])).first;
+    return it->second;
+  };
   // Plaintext form: with masks, either one full-scale plaintext per (output,
   // diagonal, term) holding the weight of every position ("materialised"),
   // or a mask per (term class, position) times scalar weight codes.
@@ -310,7 +322,7 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
         if (gh < 0 || gh >= Lin.h || gw < 0 || gw >= Lin.w) continue;
         for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = 1.0;
       }
-    return masks[key] = encode(C, z, {}, dm, q_basis(lvl));
+    return masks[key] = encode(C, z, {}, dm, basis);
   };
 
   std::vector<Ct> out(terms.size());
@@ -320,10 +332,15 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
         for (int vo = 0; vo < So; vo++) {
           const int oct = ((bg * ncg_out + go) * So + uo) * So + vo;
           std::vector<Ct> z(nd, zero_ct(C, lvl, Lin.scale * dw * dm));
+          if (hoist)
+            for (Ct& zr : z) {
+              zr.c0 = poly_zero(C, basis);
+              zr.c1 = poly_zero(C, basis);
+            }
           std::vector<bool> act(nd, false);
           if (materialise) {
             for (const Term& t : terms[oct]) {
-              const Ct& copy = t.shift ? copies.at({t.idx, t.shift}) : in[t.idx];
+              const Ct& copy = source(t.idx, t.shift);
               for (int r = 0; r < nd; r++) {
                 std::vector<double> dz(C.ns, 0.0);
                 bool any = false;
@@ -342,13 +359,13 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
                 }
                 if (!any) continue;
                 act[r] = true;
-                add_inplace(C, z[r], mul_plain(C, copy, encode(C, dz, {}, T, q_basis(lvl)), T));
+                add_inplace(C, z[r], mul_plain(C, copy, encode(C, dz, {}, T, basis), T));
                 cnt.pmult++;
               }
             }
           }
           for (const Term& t : materialise ? std::vector<Term>() : terms[oct]) {
-            const Ct& copy = t.shift ? copies.at({t.idx, t.shift}) : in[t.idx];
+            const Ct& copy = source(t.idx, t.shift);
             for (int q = 0; q < npos; q++) {
               const int ch = in_channel(t.gi, q);
               bool any = false;
@@ -369,6 +386,12 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
               }
             }
           }
+          if (hoist)
+            for (int r = 0; r < nd; r++)
+              if (act[r]) {
+                z[r] = mod_down_ct(C, z[r]);
+                cnt.moddown++;
+              }
           std::vector<const Ct*> zs;
           std::vector<i64> sh;
           for (int r = 1; r < nd; r++)
@@ -395,7 +418,7 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
 }
 
 std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
-                         Counts& cnt) {
+                         Counts& cnt, int hoist) {
   if (Lin.kind != KIND_FRAGMENT) throw std::runtime_error("avgpool2: needs a fragment layout");
   Lout = Lin;
   Lout.h = Lin.h / 2;
@@ -420,10 +443,20 @@ std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& i
     const long d = Lin.dil, m = Lin.m, bsg = Lin.bsg;
     std::vector<i64> sh = {d * bsg, d * m * bsg, (d * m + d) * bsg};
     for (const Ct& x : in) {
-      std::vector<Ct> r = rotate_hoisted(C, x, sh);
-      cnt.other_rot += 3; cnt.ks += 3; cnt.modup += 1; cnt.moddown += 3;
-      Ct y = x;
-      for (const Ct& t : r) add_inplace(C, y, t);
+      Ct y;
+      if (hoist) {   // sum in the extended basis, one ModDown
+        std::vector<Ct> r = rotate_hoisted_pq(C, x, sh);
+        y = lift_pq(C, x);
+        for (const Ct& t : r) add_inplace(C, y, t);
+        y = mod_down_ct(C, y);
+        cnt.moddown += 1;
+      } else {
+        std::vector<Ct> r = rotate_hoisted(C, x, sh);
+        y = x;
+        for (const Ct& t : r) add_inplace(C, y, t);
+        cnt.moddown += 3;
+      }
+      cnt.other_rot += 3; cnt.ks += 3; cnt.modup += 1;
       y.scale = Lout.scale;
       out.push_back(y);
     }
@@ -432,8 +465,6 @@ std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& i
   return out;
 }
 
-// x^2 keeping the scale near Delta: the tensor product is multiplied by the
-// integer k = round((Delta * q_l) / s^2), so (k s^2) / q_l after the rescale
 i128 big_code(double v) {
   if (!(std::fabs(v) < std::ldexp(1.0, 120))) throw std::runtime_error("polynomial code too large for its scale");
   return (i128)std::round(v);   // exact: |v| < 2^120 and round() returns an integral binary64
@@ -512,6 +543,8 @@ std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& i
   return out;
 }
 
+// x^2 keeping the scale near Delta: the tensor product is multiplied by the
+// integer k = round((Delta * q_l) / s^2), so (k s^2) / q_l after the rescale
 std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                            Counts& cnt) {
   const double s = Lin.scale, ql = (double)C.primes[Lin.level];

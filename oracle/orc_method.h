@@ -46,9 +46,11 @@ void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, dou
 // as full-scale plaintext diagonals instead of mask-basis scalar codes
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
-                       long long pt_budget = 1LL << 30);
+                       long long pt_budget = 1LL << 30, int hoist = 0);
+// hoist = 1: rotated copies stay in the extended basis and each combined
+// ciphertext is moved down once (see conv2d)
 std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
-                         Counts& cnt);
+                         Counts& cnt, int hoist = 0);
 std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                            Counts& cnt);
 // p(x) = coeffs[0] + coeffs[1] x + ... + coeffs[d] x^d, d <= 3, one rescale per

@@ -84,8 +84,9 @@ def _declare(L):
         "orc_batch_layout": (None, [vp, C.POINTER(OrcLayout)]),
         "orc_batch_data": (i, [vp, vp, u64p]),
         "orc_decrypt_tensor": (i, [vp, vp, f64p]),
-        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, C.POINTER(C.c_long)]),
-        "orc_avgpool2": (vp, [vp, vp, C.POINTER(C.c_long)]),
+        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, i, C.POINTER(C.c_long)]),
+        "orc_avgpool2": (vp, [vp, vp, i, C.POINTER(C.c_long)]),
+        "orc_pq_roundtrip": (i, [vp, u64p, i, vp, i, i, u64p]),
         "orc_square": (vp, [vp, vp, C.POINTER(C.c_long)]),
         "orc_poly_act": (vp, [vp, vp, f64p, i, C.POINTER(C.c_long)]),
         "orc_compress": (vp, [vp, vp, C.POINTER(C.c_long)]),
@@ -267,6 +268,15 @@ class Oracle:
                                 np.array(shifts, np.int64), len(shifts), out))
         return out
 
+    def pq_roundtrip(self, ct, shifts=(), lift=False):
+        """ModDown of the extended-basis rotations (or of the lift P x)."""
+        level = ct.shape[1] - 1
+        out = np.zeros((max(1, len(shifts)), 2, level + 1, self.N), np.uint64)
+        sh = np.array(list(shifts) or [0], np.int64)
+        _check(lib().orc_pq_roundtrip(self.h, np.ascontiguousarray(ct, np.uint64), level, sh.ctypes.data,
+                                      len(shifts), int(lift), out))
+        return out[0] if lift else out
+
     def rotate_sum(self, z0, zs, shifts):
         level = zs.shape[2] - 1
         out = np.zeros((2, level + 1, self.N), np.uint64)
@@ -337,12 +347,15 @@ class Oracle:
             raise OracleError(lib().orc_last_error().decode())
         return Batch(self, h), dict(zip(COUNT_FIELDS, list(cnt)))
 
-    def conv2d(self, batch, w, stride=1, pad=0, groups=1, pt_budget=1 << 30):
+    def conv2d(self, batch, w, stride=1, pad=0, groups=1, pt_budget=1 << 30, hoist=0):
+        """hoist=1: the linear combination is taken in the extended basis Q_l U P
+        and each combined ciphertext is moved down once."""
         w = np.ascontiguousarray(w, np.float64)
-        return self._op(lib().orc_conv2d, batch.h, w, w.shape[0], w.shape[2], stride, pad, groups, pt_budget)
+        return self._op(lib().orc_conv2d, batch.h, w, w.shape[0], w.shape[2], stride, pad, groups, pt_budget,
+                        hoist)
 
-    def avgpool2(self, batch):
-        return self._op(lib().orc_avgpool2, batch.h)
+    def avgpool2(self, batch, hoist=0):
+        return self._op(lib().orc_avgpool2, batch.h, hoist)
 
     def square(self, batch):
         return self._op(lib().orc_square, batch.h)

@@ -332,3 +332,17 @@ def test_switch_key_structure(orc_small):
             indicator = 1 if (t < o.nq and j * o.alpha <= t < (j + 1) * o.alpha) else 0
             rhs = [(ei + indicator * (P_ % q) * int(sv)) % q for ei, sv in zip(e, sg)]
             assert lhs == rhs
+
+
+def test_extended_basis_rotation_moves_down_to_the_rotation():
+    """ModDown(KIP + P sigma(c0), KIP) is the rotated ciphertext word for word, and
+    ModDown(P x) = x: the identity that lets a linear combination of rotated
+    copies be taken before the single ModDown."""
+    o = P.Oracle(10, 6, 50, 2, 50, 3, 40, 5)
+    r = np.random.default_rng(3)
+    z = r.uniform(-1, 1, o.ns)
+    level = 5
+    ct = o.encrypt(o.encode(z, None, 2.0 ** 40, level), level, 2.0 ** 40, 7)
+    shifts = [1, 5, 200]
+    assert np.array_equal(o.pq_roundtrip(ct, shifts), o.rotate(ct, shifts))
+    assert np.array_equal(o.pq_roundtrip(ct, lift=True), ct)

@@ -131,16 +131,24 @@ def rand_w(shape, seed):
     dict(x=(2, 4, 8, 8), w=(4, 1, 3, 3), stride=1, pad=1, groups=4, S=2),     # depthwise
     dict(x=(16, 2, 8, 8), w=(5, 2, 5, 5), stride=1, pad=0, groups=1, S=1),    # C'=1, no masks
 ])
-def test_conv2d_decrypts_to_float64_conv(case):
+@pytest.mark.parametrize("budget", [1 << 30, 0])
+@pytest.mark.parametrize("hoist", [0, 1])
+def test_conv2d_decrypts_to_float64_conv(case, hoist, budget):
     o = small_oracle()
     x, w = rand_x(case["x"], 1), rand_w(case["w"], 2)
     L = o.fragment_layout(*case["x"], case["S"])
     b = o.encrypt_tensor(L, x, seed=4)
-    y, cnt = o.conv2d(b, w, case["stride"], case["pad"], case["groups"])
+    y, cnt = o.conv2d(b, w, case["stride"], case["pad"], case["groups"], pt_budget=budget, hoist=hoist)
     got = o.decrypt_tensor(y)
     want = cnn_ref.conv2d(x, w, case["stride"], case["pad"], case["groups"])
     assert got.shape == want.shape
     assert np.max(np.abs(got - want)) < 1e-4
+    if hoist:
+        # the same rotations; each combined diagonal ciphertext moves down once instead of every copy
+        _, c0 = o.conv2d(b, w, case["stride"], case["pad"], case["groups"], pt_budget=budget, hoist=0)
+        assert (cnt["inner_rot"], cnt["outer_rot"], cnt["ks"]) == (c0["inner_rot"], c0["outer_rot"], c0["ks"])
+        n_diag = L["c"] if L["rep"] else L["cpc"]    # diagonals per output ciphertext
+        assert cnt["moddown"] <= c0["moddown"] - c0["inner_rot"] + len(y.data()) * n_diag
 
 
 def test_conv2d_rotation_counts_match_formula_when_kernel_exceeds_block():
@@ -234,3 +242,18 @@ def test_poly_act_decrypts_to_the_polynomial(coeffs):
     assert cnt["relin"] == len(b.data()) * {1: 0, 2: 1, 3: 2}[deg]
     ref = np.polynomial.polynomial.polyval(x, coeffs)
     assert np.max(np.abs(o.decrypt_tensor(y) - ref)) < 1e-5
+
+
+def test_avgpool_rotation_sum_in_the_extended_basis():
+    """S = 1 average pooling: the three rotations summed before one ModDown decrypt
+    to the same mean as the per-rotation form, with one ModDown per ciphertext."""
+    o = small_oracle()
+    x = rand_x((4, 2, 8, 8), 13)
+    L = o.fragment_layout(4, 2, 8, 8, 1)
+    b = o.encrypt_tensor(L, x, seed=8)
+    y0, c0 = o.avgpool2(b, hoist=0)
+    y1, c1 = o.avgpool2(b, hoist=1)
+    want = cnn_ref.avgpool2(x)
+    for y in (y0, y1):
+        assert np.max(np.abs(o.decrypt_tensor(y) - want)) < 1e-6
+    assert (c0["moddown"], c1["moddown"]) == (3 * len(b.data()), len(b.data()))
