@@ -254,6 +254,16 @@ int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void*
  * prime[i] of row i, through the device kernels. */
 int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t n, int inverse);
 /* Sampler and codec hooks (host only). */
+/* Hoisting schedule of convolutions and S = 1 average pooling (Motivation,
+ * inner rotations; the paper leaves the placement of ModDown open).  Mode 1
+ * (default): the hoisted rotated copies stay in the extended basis Q_l U P
+ * as (KIP_0 + P sigma(c0), KIP_1), the linear combination (scalar weights,
+ * masks or diagonals encoded over Q_l U P) is taken there, unrotated inputs
+ * enter as P x, and each combined ciphertext is moved down once.  Mode 0:
+ * every rotated copy is moved down.  The two modes round differently, so the
+ * residues differ; each matches the oracle's schedule of the same number.
+ * Errors: EINVAL for other modes. */
+int fenc_set_hoisting(fenc_ctx* ctx, int mode);
 /* NTT pass shapes, 8 ints: for [forward columns, forward rows, inverse rows,
  * inverse columns] the radix bits of a register round (3: radix 8, 4: radix
  * 16) and the log2 of the columns (column pass) or chunks (row pass) a block

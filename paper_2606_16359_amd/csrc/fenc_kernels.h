@@ -403,6 +403,13 @@ struct KipArgs {
   int beta, le, logn, nprimes;
   const unsigned char* eprime;
   const d2* pq;
+  // optional: acc_0 += P sigma_g(c0 of ct c0ct[item]) on the nl Q limbs, so
+  // that ModDown of acc is the whole rotated ciphertext
+  const int* c0ct;        // parallel to items, -1: none
+  const u64* c0;          // c0 of input ct t at c0 + t * c0_cs
+  long long c0_cs;
+  const d2* pmod;         // [nl] P mod q_i
+  int nl;
 };
 
 template <class X>
@@ -439,6 +446,17 @@ FENC_HD void kip(X& x, const KipArgs& a) {
           a0[o] = red(a0[o] + mulmod(v[o], k0, q, qi), q, qi);
           a1[o] = red(a1[o] + mulmod(v[o], k1, q, qi), q, qi);
         }
+      }
+      if (a.c0 && l < a.nl) {
+        int t0[kKipOut];
+        double cv[kKipOut];
+#pragma unroll
+        for (int o = 0; o < kKipOut; o++) t0[o] = a.c0ct[K.item0 + o];
+#pragma unroll
+        for (int o = 0; o < kKipOut; o++) cv[o] = t0[o] >= 0 ? u2d(a.c0[t0[o] * a.c0_cs + l * N + src]) : 0.0;
+#pragma unroll
+        for (int o = 0; o < kKipOut; o++)
+          if (t0[o] >= 0) a0[o] = red(a0[o] + mulmod_c(cv[o], a.pmod[l].x, a.pmod[l].y, q), q, qi);
       }
     }
 #pragma unroll
@@ -618,9 +636,9 @@ struct MacClass {
 };
 
 struct GmacArgs {
-  const u64* in_a; long long a_cs; int na;
-  const u64* in_b; long long b_cs;
-  long long in_ps;           // poly stride of inputs
+  const u64* in_a; long long a_cs, a_ps; int na;
+  const u64* in_b; long long b_cs, b_ps;
+  int nl_a;                  // limbs of the A inputs: A terms read nothing at limbs >= nl_a
   u64* out; long long out_cs, out_ps;
   int c0;                    // first class of the launch
   int width;                 // 1, 2, 4, 8 or 16: outputs per class row (nout <= width; rows zero-padded)
@@ -632,6 +650,7 @@ struct GmacArgs {
   const d2* ew;              // [nl][ews] weight residues (w mod q, fl(w/q))
   long long ews;
   int nl, logn;
+  const unsigned char* eprime;   // prime index of limb i (null: i)
   const d2* pq;
 };
 
@@ -646,13 +665,15 @@ FENC_HD void gmac_w(X& x, const GmacArgs& a) {
     const long long c = (long long)x.bx * x.nt + t;
     const int i = x.by, poly = x.bz & 1;
     const MacClass K = a.cls[a.c0 + (x.bz >> 1)];
-    const double q = a.pq[i].x, qi = a.pq[i].y;
-    const long long off = poly * a.in_ps + i * N + c;
+    const int pi = a.eprime ? a.eprime[i] : i;
+    const double q = a.pq[pi].x, qi = a.pq[pi].y;
+    const long long off_a = poly * a.a_ps + i * N + c, off_b = poly * a.b_ps + i * N + c;
+    const bool a_here = i < a.nl_a;
     const d2* ew = a.ew + (long long)i * a.ews + K.w0;
     auto load_in = [&](int k) {
       const int ti = a.tin[k];
-      const u64* src = ti < a.na ? a.in_a + ti * a.a_cs : a.in_b + (ti - a.na) * a.b_cs;
-      return u2d(src[off]);
+      if (ti < a.na) return a_here ? u2d(a.in_a[ti * a.a_cs + off_a]) : 0.0;
+      return u2d(a.in_b[(ti - a.na) * a.b_cs + off_b]);
     };
     double r[W], sg[W];
 #pragma unroll

@@ -183,7 +183,7 @@ struct RotStage {
 };
 
 static RotStage make_rot_stage(Ctx& C, const std::vector<std::pair<int, long long>>& copies,
-                               std::vector<void*>& owner) {
+                               std::vector<void*>& owner, bool pq = false) {
   RotStage R;
   R.n = (int)copies.size();
   std::map<int, int> pos;
@@ -197,7 +197,7 @@ static RotStage make_rot_stage(Ctx& C, const std::vector<std::pair<int, long lon
   std::vector<fk::AddTerm> terms;
   for (int i = 0; i < R.n; i++) {
     const unsigned g = (unsigned)galois(C, copies[i].second);
-    items.push_back({KsItem{pos[copies[i].first], g, get_key(C, g)}});
+    items.push_back({KsItem{pos[copies[i].first], g, get_key(C, g), pq ? copies[i].first : -1}});
     tails.push_back(fk::TailItem{i, -1, (int)terms.size(), 1});
     terms.push_back(fk::AddTerm{copies[i].first, g});
   }
@@ -205,8 +205,10 @@ static RotStage make_rot_stage(Ctx& C, const std::vector<std::pair<int, long lon
   return R;
 }
 
-// ModUp of the listed cts (contiguous runs), then KIP/ModDown into out
-static void run_rot_stage(Ctx& C, int level, const RotStage& R, const u64* in, u64* out, fb::Stream s) {
+// ModUp of the listed cts (contiguous runs), then KIP/ModDown into out; with
+// pq, KIP only: out[i] = (KIP_0 + P sigma(c0), KIP_1) over Q_l U P ([2][le][N])
+static void run_rot_stage(Ctx& C, int level, const RotStage& R, const u64* in, u64* out, fb::Stream s,
+                          bool pq = false) {
   if (R.n == 0) return;
   const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
   const long long ce = ct_elems(C, level), ee = (long long)beta * le * C.N;
@@ -218,7 +220,8 @@ static void run_rot_stage(Ctx& C, int level, const RotStage& R, const u64* in, u
     modup(C, level, in + R.src[i] * ce, ce, (long long)nl * C.N, (int)(j - i + 1), ext + (long long)i * ee, s);
     i = j + 1;
   }
-  kip_moddown(C, level, ext, R.ks, out, ce, nullptr, 0, in, ce, s);
+  if (pq) kip_only(C, level, ext, R.ks, out, in, ce, s);
+  else kip_moddown(C, level, ext, R.ks, out, ce, nullptr, 0, in, ce, s);
 }
 
 // lazy sum stage: out[o] = base[o] + sum_r Rot(z[idx], shift), one ModDown per output
@@ -264,8 +267,10 @@ static void run_sum_stage(Ctx& C, int level, const SumStage& S, const u64* z, u6
 // ---------------------------------------------------------------- conv2d
 struct ConvPlan : Plan {
   int level = 0, n_in = 0, n_out = 0, n_zr = 0;
+  bool pq = false;   // linear combinations in the extended basis, one ModDown per combined ciphertext
   RotStage rot;
   GmacStage g0, gr;
+  KsStage md;        // pq: ModDown of the n_out + n_zr combined ciphertexts
   SumStage sum;
   long long n_terms = 0, n_masked = 0;
 };
@@ -297,6 +302,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   P->out = Lout;
   P->level = lvl;
   P->n_in = Lin.n_ct();
+  P->pq = C.hoist != 0;
   const int nd = Lin.rep ? cin : cpc;
   const bool need_mask = (cpc > 1) || (pad > 0);
   const double T = ((double)C.primes[lvl] * C.Delta) / Lin.scale;
@@ -348,7 +354,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
       copies.push_back({kv.second, kv.first});
     }
   }
-  P->rot = make_rot_stage(C, copies, P->owned);
+  P->rot = make_rot_stage(C, copies, P->owned, P->pq);
 
   // Plaintext form: with masks, either one full-scale plaintext per (output,
   // diagonal, term) holding the weight of every position ("materialised"),
@@ -442,9 +448,10 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
       }
     }
   }
-  const u64* masks = materialise ? (diag_slots.empty() ? nullptr : encode_plaintexts(C, diag_slots, T, lvl, P->owned))
-                                 : (mask_slots.empty() ? nullptr : encode_plaintexts(C, mask_slots, dm, lvl, P->owned));
-  const long long pe = (long long)(lvl + 1) * C.N;
+  const u64* masks =
+      materialise ? (diag_slots.empty() ? nullptr : encode_plaintexts(C, diag_slots, T, lvl, P->owned, P->pq))
+                  : (mask_slots.empty() ? nullptr : encode_plaintexts(C, mask_slots, dm, lvl, P->owned, P->pq));
+  const long long pe = (long long)(lvl + 1 + (P->pq ? C.K : 0)) * C.N;
   GmacBuild b0, br;
   std::vector<int> sum_out, sum_base;
   std::vector<std::vector<std::pair<int, long long>>> sum_terms;
@@ -471,22 +478,35 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
       sum_terms.push_back(tl);
     }
   }
-  P->g0 = make_gmac(C, b0, codes, lvl, P->owned);
-  P->gr = make_gmac(C, br, codes, lvl, P->owned);
+  P->g0 = make_gmac(C, b0, codes, lvl, P->owned, P->pq, P->n_in);
+  P->gr = make_gmac(C, br, codes, lvl, P->owned, P->pq, P->n_in);
+  if (P->pq) P->md = make_md(C, P->n_out + P->n_zr, P->owned);
   P->sum = make_sum_stage(C, sum_out, sum_base, sum_terms, P->owned, P->n_zr);
   return P;
 }
 
 static void run_conv(Ctx& C, const ConvPlan& P, const u64* in, u64* out, fb::Stream s) {
-  const int lvl = P.level, nl = lvl + 1;
+  const int lvl = P.level, nl = lvl + 1, le = nl + C.K;
   const long long ce = ct_elems(C, lvl), ps = (long long)nl * C.N;
   Scope sc(C.arena);
-  u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
-  u64* y = (u64*)C.arena.get((size_t)P.n_out * ce * 8, s);
-  u64* zr = (u64*)C.arena.get((size_t)std::max(1, P.n_zr) * ce * 8, s);
-  run_rot_stage(C, lvl, P.rot, in, copies, s);
-  run_gmac(C, nl, P.g0, in, ce, P.n_in, copies, ce, ps, y, ce, ps, s);
-  run_gmac(C, nl, P.gr, in, ce, P.n_in, copies, ce, ps, zr, ce, ps, s);
+  // y and the diagonals z_r share one buffer: y = yz[0, n_out), z_r = yz[n_out, ...)
+  u64* yz = (u64*)C.arena.get((size_t)(P.n_out + P.n_zr) * ce * 8, s);
+  u64* y = yz;
+  u64* zr = yz + (long long)P.n_out * ce;
+  if (P.pq) {
+    const long long ee = 2LL * le * C.N, pe = (long long)le * C.N;
+    u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ee * 8, s);
+    u64* yzp = (u64*)C.arena.get((size_t)(P.n_out + P.n_zr) * ee * 8, s);
+    run_rot_stage(C, lvl, P.rot, in, copies, s, true);
+    run_gmac(C, nl, P.g0, in, ce, ps, P.n_in, copies, ee, pe, yzp, ee, pe, s);
+    run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, copies, ee, pe, yzp + (long long)P.n_out * ee, ee, pe, s);
+    moddown_only(C, lvl, yzp, P.md, yz, ce, s);
+  } else {
+    u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
+    run_rot_stage(C, lvl, P.rot, in, copies, s);
+    run_gmac(C, nl, P.g0, in, ce, ps, P.n_in, copies, ce, ps, y, ce, ps, s);
+    run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, copies, ce, ps, zr, ce, ps, s);
+  }
   run_sum_stage(C, lvl, P.sum, zr, y, y, s);
   rescale(C, lvl, y, P.n_out, out, s);
   C.cnt.rot_inner += P.rot.n;
@@ -500,8 +520,10 @@ static void run_conv(Ctx& C, const ConvPlan& P, const u64* in, u64* out, fb::Str
 // ---------------------------------------------------------------- avgpool
 struct PoolPlan : Plan {
   int level = 0, n_in = 0, n_out = 0;
+  bool pq = false;   // S = 1: rotations summed in the extended basis, one ModDown per output
   RotStage rot;
   GmacStage g;
+  KsStage md;
 };
 
 static PoolPlan* build_pool(Ctx& C, const Layout& Lin, bool shape_only, Layout& Lout) {
@@ -539,29 +561,41 @@ static PoolPlan* build_pool(Ctx& C, const Layout& Lin, bool shape_only, Layout& 
   } else {
     const long long d = Lin.dil, m = Lin.m, bsg = Lin.bsg;
     const long long sh[3] = {d * bsg, d * m * bsg, (d * m + d) * bsg};
+    // copies ordered by shift (rotations sharing a key are adjacent): copy i * n_in + t
     std::vector<std::pair<int, long long>> copies;
-    for (int t = 0; t < P->n_in; t++)
-      for (int i = 0; i < 3; i++) copies.push_back({t, sh[i] % C.ns});
-    P->rot = make_rot_stage(C, copies, P->owned);
+    for (int i = 0; i < 3; i++)
+      for (int t = 0; t < P->n_in; t++) copies.push_back({t, sh[i] % C.ns});
+    P->pq = C.hoist != 0;
+    P->rot = make_rot_stage(C, copies, P->owned, P->pq);
     for (int t = 0; t < P->n_in; t++) {
       gb.add_group(nullptr);
       gb.add_term(t, -1);
-      for (int i = 0; i < 3; i++) gb.add_term(P->n_in + 3 * t + i, -1);
+      for (int i = 0; i < 3; i++) gb.add_term(P->n_in + i * P->n_in + t, -1);
       gb.end_group();
       gb.end_output();
     }
+    if (P->pq) P->md = make_md(C, P->n_out, P->owned);
   }
-  P->g = make_gmac(C, gb, {}, Lin.level, P->owned);
+  P->g = make_gmac(C, gb, {}, Lin.level, P->owned, P->pq, P->n_in);
   return P;
 }
 
 static void run_pool(Ctx& C, const PoolPlan& P, const u64* in, u64* out, fb::Stream s) {
-  const int nl = P.level + 1;
+  const int nl = P.level + 1, le = nl + C.K;
   const long long ce = ct_elems(C, P.level), ps = (long long)nl * C.N;
   Scope sc(C.arena);
-  u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
-  run_rot_stage(C, P.level, P.rot, in, copies, s);
-  run_gmac(C, nl, P.g, in, ce, P.n_in, copies, ce, ps, out, ce, ps, s);
+  if (P.pq) {
+    const long long ee = 2LL * le * C.N, pe = (long long)le * C.N;
+    u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ee * 8, s);
+    u64* zp = (u64*)C.arena.get((size_t)P.n_out * ee * 8, s);
+    run_rot_stage(C, P.level, P.rot, in, copies, s, true);
+    run_gmac(C, nl, P.g, in, ce, ps, P.n_in, copies, ee, pe, zp, ee, pe, s);
+    moddown_only(C, P.level, zp, P.md, out, ce, s);
+  } else {
+    u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
+    run_rot_stage(C, P.level, P.rot, in, copies, s);
+    run_gmac(C, nl, P.g, in, ce, ps, P.n_in, copies, ce, ps, out, ce, ps, s);
+  }
   C.cnt.rot_other += P.rot.n;
   C.cnt.keyswitch += P.rot.n;
   C.cnt.cts_out += P.n_out;
@@ -783,8 +817,8 @@ static void run_compress(Ctx& C, const CompressPlan& P, const u64* in, u64* out,
   Scope sc(C.arena);
   u64* y = (u64*)C.arena.get((size_t)P.n_out * ce * 8, s);
   u64* zr = (u64*)C.arena.get((size_t)std::max(1, P.n_zr) * ce * 8, s);
-  run_gmac(C, nl, P.g0, in, ce, P.n_in, nullptr, 0, ps, y, ce, ps, s);
-  run_gmac(C, nl, P.gr, in, ce, P.n_in, nullptr, 0, ps, zr, ce, ps, s);
+  run_gmac(C, nl, P.g0, in, ce, ps, P.n_in, nullptr, 0, ps, y, ce, ps, s);
+  run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, nullptr, 0, ps, zr, ce, ps, s);
   run_sum_stage(C, lvl, P.sum, zr, y, y, s);
   rescale(C, lvl, y, P.n_out, out, s);
   C.cnt.rot_other += P.n_zr;
@@ -904,8 +938,8 @@ static void run_fc(Ctx& C, const FcPlan& P, const u64* in, u64* out, fb::Stream 
   u64* y = (u64*)C.arena.get((size_t)P.n_out * ce * 8, s);
   u64* zr = (u64*)C.arena.get((size_t)std::max(1, P.n_zr) * ce * 8, s);
   run_rot_stage(C, lvl, P.rot, in, copies, s);
-  run_gmac(C, nl, P.g0, in, ce, P.n_in, copies, ce, ps, y, ce, ps, s);
-  run_gmac(C, nl, P.gr, in, ce, P.n_in, copies, ce, ps, zr, ce, ps, s);
+  run_gmac(C, nl, P.g0, in, ce, ps, P.n_in, copies, ce, ps, y, ce, ps, s);
+  run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, copies, ce, ps, zr, ce, ps, s);
   run_sum_stage(C, lvl, P.sum, zr, y, y, s);
   rescale(C, lvl, y, P.n_out, out, s);
   C.cnt.rot_other += P.rot.n + P.n_zr;
@@ -1324,7 +1358,7 @@ int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t
   const size_t nw = (size_t)cout * (Lin.c / groups) * k * k;
   std::ostringstream key;
   key << "conv|" << layout_key(Lin) << '|' << cout << ',' << k << ',' << stride << ',' << pad << ',' << groups << ','
-      << fnv(w, nw * sizeof(double)) << ',' << C.pt_budget;
+      << fnv(w, nw * sizeof(double)) << ',' << C.pt_budget << ',' << C.hoist;
   ConvPlan& P = cached<ConvPlan>(C, key.str(), [&] { return build_conv(C, Lin, w, cout, k, stride, pad, groups, false, Lout); });
   run_conv(C, P, in->data, out->data, (fb::Stream)stream);
   API_END
@@ -1341,7 +1375,8 @@ int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
-  PoolPlan& P = cached<PoolPlan>(C, "pool|" + layout_key(Lin), [&] { return build_pool(C, Lin, false, Lout); });
+  PoolPlan& P = cached<PoolPlan>(C, "pool|" + layout_key(Lin) + (C.hoist ? "|h" : ""),
+                                 [&] { return build_pool(C, Lin, false, Lout); });
   run_pool(C, P, in->data, out->data, (fb::Stream)stream);
   API_END
 }
@@ -1540,6 +1575,13 @@ int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void*
   check_batch(C, in, true);
   ensure_device(C);
   rescale(C, L.level, in->data, L.n_ct(), out->data, (fb::Stream)stream);
+  API_END
+}
+
+int fenc_set_hoisting(fenc_ctx* ctx, int mode) {
+  API_BEGIN
+  if (!ctx || (mode != 0 && mode != 1)) fail(FENC_EINVAL, "hoisting mode must be 0 or 1");
+  ctx->hoist = mode;
   API_END
 }
 

@@ -170,6 +170,15 @@ const LevelTabs& level_tabs(Ctx& C, int level) {
   std::vector<d2> ql(std::max(1, level));
   for (int i = 0; i < level; i++) ql[i] = cpair(invmod(C.primes[level] % C.primes[i], C.primes[i]), C.primes[i]);
   T.qlinv = upload(C, ql, C.owned);
+  std::vector<d2> pm(nl);
+  T.h_pmod.resize(nl);
+  for (int i = 0; i < nl; i++) {
+    uint64_t P = 1;
+    for (int k = 0; k < C.K; k++) P = mulmod(P, C.primes[C.L + 1 + k] % C.primes[i], C.primes[i]);
+    T.h_pmod[i] = P;
+    pm[i] = cpair(P, C.primes[i]);
+  }
+  T.pmod = upload(C, pm, C.owned);
   return C.lvl[level] = T;
 }
 
@@ -402,65 +411,119 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
   }
 }
 
-void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
-                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s) {
-  if (st.n_out <= 0) return;
+// ModDown of outputs o0 .. o0+no-1 of acc ([n][2][le][N], NTT form; its P
+// limbs are transformed in place), then the tail into out
+static void moddown_part(Ctx& C, int level, u64* acc, u64* conv, const KsStage& st, int o0, int no, u64* out,
+                         long long out_cs, const u64* base, long long base_cs, const u64* add, long long add_cs,
+                         fb::Stream s) {
   const LevelTabs& T = level_tabs(C, level);
-  const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha, N = C.N;
-  Scope sc(C.arena);
-  const bool per_op = C.mode == FENC_MODE_PER_OP;
-  const KipTables& KT = per_op ? st.single : st.batched;
-  u64* acc = (u64*)C.arena.get((size_t)st.n_out * 2 * le * N * 8, s);
-  u64* conv = (u64*)C.arena.get((size_t)st.n_out * 2 * nl * N * 8, s);
+  const int nl = level + 1, le = nl + C.K, N = C.N;
   fk::PrimeMap pmP;
   pmP.n = le;
   for (int l = 0; l < le; l++) pmP.p[l] = l < nl ? fk::kSkip : T.h_eprime[l];
+  u64* acc0 = acc + (long long)o0 * 2 * le * N;
+  ntt(C, true, acc0, acc0, (long long)le * N, (long long)le * N, no * 2 * le, le, pmP, s);
+  fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.eprime, C.md_tab, C.pq};
+  timed(C, "moddown_fbc", 2.0 * no * (C.K + nl) * N * 8, s, [&] {
+    fb::moddown_fbc({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, m);
+  });
+  u64* conv0 = conv + (long long)o0 * 2 * nl * N;
+  ntt(C, false, conv0, conv0, (long long)nl * N, (long long)nl * N, no * 2 * nl, nl, identity_map(nl), s);
+  fk::TailArgs t;
+  t.acc = acc;
+  t.conv = conv;
+  t.items = st.tails;
+  t.terms = st.terms;
+  t.o0 = o0;
+  t.nl = nl;
+  t.le = le;
+  t.logn = C.logn;
+  t.out = out;
+  t.out_cs = out_cs;
+  t.out_ps = (long long)nl * N;
+  t.base = base;
+  t.base_cs = base_cs;
+  t.base_ps = (long long)nl * N;
+  t.add = add;
+  t.add_cs = add_cs;
+  t.pinv = C.pinv;
+  t.pq = C.pq;
+  const double frac = (double)no / st.n_out;
+  const double tb = (6.0 * no + 2.0 * st.n_base * frac + st.n_adds * frac) * nl * N * 8;
+  timed(C, "moddown_tail", tb, s, [&] {
+    fb::moddown_tail({(unsigned)(N / block_threads(C)), (unsigned)(2 * nl), (unsigned)no}, block_threads(C), s, t);
+  });
+  C.cnt.launches += 2;
+  C.cnt.moddown += no;
+}
+
+static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int it, u64* acc, const u64* c0,
+                       long long c0_cs, fb::Stream s) {
+  const LevelTabs& T = level_tabs(C, level);
+  const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha, N = C.N;
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  const KipTables& KT = per_op ? st.single : st.batched;
+  const int g0 = per_op ? it : 0, ng = per_op ? 1 : KT.n;
+  fk::KipArgs k{ext, acc, KT.groups, KT.keys, KT.items, g0, beta, le, C.logn, C.np, T.eprime, C.pq,
+                nullptr, nullptr, 0, nullptr, nl};
+  if (c0 && KT.c0items) {
+    k.c0ct = KT.c0items;
+    k.c0 = c0;
+    k.c0_cs = c0_cs;
+    k.pmod = T.pmod;
+  }
+  double kb = 0;
+  for (int g = g0; g < g0 + ng; g++) kb += KT.rd[g] * beta + KT.wr[g];
+  kb *= (double)le * N * 8;
+  timed(C, "kip", kb, s,
+        [&] { fb::kip({(unsigned)(N / block_threads(C)), (unsigned)le, (unsigned)ng}, block_threads(C), s, k); });
+  C.cnt.launches += 1;
+}
+
+void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
+                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s) {
+  if (st.n_out <= 0) return;
+  const int nl = level + 1, le = nl + C.K, N = C.N;
+  Scope sc(C.arena);
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  u64* acc = (u64*)C.arena.get((size_t)st.n_out * 2 * le * N * 8, s);
+  u64* conv = (u64*)C.arena.get((size_t)st.n_out * 2 * nl * N * 8, s);
   // per-op: one launch sequence per output; batched: every output at once
   const int steps = per_op ? st.n_out : 1;
   for (int it = 0; it < steps; it++) {
-    const int g0 = per_op ? it : 0, ng = per_op ? 1 : KT.n;
-    const int o0 = per_op ? it : 0, no = per_op ? 1 : st.n_out;
-    fk::KipArgs k{ext, acc, KT.groups, KT.keys, KT.items, g0, beta, le, C.logn, C.np, T.eprime, C.pq};
-    double kb = 0;
-    for (int g = g0; g < g0 + ng; g++) kb += KT.rd[g] * beta + KT.wr[g];
-    kb *= (double)le * N * 8;
-    timed(C, "kip", kb, s,
-          [&] { fb::kip({(unsigned)(N / block_threads(C)), (unsigned)le, (unsigned)ng}, block_threads(C), s, k); });
-    u64* acc0 = acc + (long long)o0 * 2 * le * N;
-    ntt(C, true, acc0, acc0, (long long)le * N, (long long)le * N, no * 2 * le, le, pmP, s);
-    fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.eprime, C.md_tab, C.pq};
-    timed(C, "moddown_fbc", 2.0 * no * (C.K + nl) * N * 8, s, [&] {
-      fb::moddown_fbc({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, m);
-    });
-    u64* conv0 = conv + (long long)o0 * 2 * nl * N;
-    ntt(C, false, conv0, conv0, (long long)nl * N, (long long)nl * N, no * 2 * nl, nl, identity_map(nl), s);
-    fk::TailArgs t;
-    t.acc = acc;
-    t.conv = conv;
-    t.items = st.tails;
-    t.terms = st.terms;
-    t.o0 = o0;
-    t.nl = nl;
-    t.le = le;
-    t.logn = C.logn;
-    t.out = out;
-    t.out_cs = out_cs;
-    t.out_ps = (long long)nl * N;
-    t.base = base;
-    t.base_cs = base_cs;
-    t.base_ps = (long long)nl * N;
-    t.add = add;
-    t.add_cs = add_cs;
-    t.pinv = C.pinv;
-    t.pq = C.pq;
-    const double frac = (double)no / st.n_out;
-    const double tb = (6.0 * no + 2.0 * st.n_base * frac + st.n_adds * frac) * nl * N * 8;
-    timed(C, "moddown_tail", tb, s, [&] {
-      fb::moddown_tail({(unsigned)(N / block_threads(C)), (unsigned)(2 * nl), (unsigned)no}, block_threads(C), s, t);
-    });
-    C.cnt.launches += 3;
-    C.cnt.moddown += no;
+    kip_launch(C, level, ext, st, it, acc, nullptr, 0, s);
+    moddown_part(C, level, acc, conv, st, per_op ? it : 0, per_op ? 1 : st.n_out, out, out_cs, base, base_cs, add,
+                 add_cs, s);
   }
+}
+
+void kip_only(Ctx& C, int level, const u64* ext, const KsStage& st, u64* acc, const u64* c0, long long c0_cs,
+              fb::Stream s) {
+  if (st.n_out <= 0) return;
+  const int steps = C.mode == FENC_MODE_PER_OP ? st.n_out : 1;
+  for (int it = 0; it < steps; it++) kip_launch(C, level, ext, st, it, acc, c0, c0_cs, s);
+}
+
+void moddown_only(Ctx& C, int level, const u64* acc, const KsStage& md, u64* out, long long out_cs, fb::Stream s) {
+  if (md.n_out <= 0) return;
+  const int nl = level + 1;
+  Scope sc(C.arena);
+  u64* conv = (u64*)C.arena.get((size_t)md.n_out * 2 * nl * C.N * 8, s);
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  const int steps = per_op ? md.n_out : 1;
+  for (int it = 0; it < steps; it++)
+    moddown_part(C, level, (u64*)acc, conv, md, per_op ? it : 0, per_op ? 1 : md.n_out, out, out_cs, nullptr, 0,
+                 nullptr, 0, s);
+}
+
+KsStage make_md(Ctx& C, int n, std::vector<void*>& owner) {
+  std::vector<fk::TailItem> tails;
+  for (int o = 0; o < n; o++) tails.push_back(fk::TailItem{o, -1, 0, 0});
+  KsStage st;
+  st.n_out = n;
+  st.tails = upload(C, tails, owner);
+  st.terms = nullptr;
+  return st;
 }
 
 void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
@@ -495,18 +558,23 @@ void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
   }
 }
 
-void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, int na, const u64* in_b,
-              long long b_cs, long long in_ps, u64* out, long long out_cs, long long out_ps, fb::Stream s) {
+void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, long long a_ps, int na,
+              const u64* in_b, long long b_cs, long long b_ps, u64* out, long long out_cs, long long out_ps,
+              fb::Stream s) {
   if (g.n_out <= 0) return;
   const bool per_op = C.mode == FENC_MODE_PER_OP;
   const MacTables& M = per_op ? g.single : g.batched;
+  // extended basis: nl Q limbs of the A inputs, nl + K limbs processed
+  const int nlimbs = g.pq ? nl + C.K : nl;
   fk::GmacArgs a;
   a.in_a = in_a;
   a.a_cs = a_cs;
+  a.a_ps = a_ps;
   a.na = na;
   a.in_b = in_b;
   a.b_cs = b_cs;
-  a.in_ps = in_ps;
+  a.b_ps = b_ps;
+  a.nl_a = nl;
   a.out = out;
   a.out_cs = out_cs;
   a.out_ps = out_ps;
@@ -517,9 +585,11 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
   a.tin = M.tin;
   a.ew = M.ew;
   a.ews = M.ews;
-  a.nl = nl;
+  a.nl = nlimbs;
   a.logn = C.logn;
+  a.eprime = g.pq ? g.eprime : nullptr;
   a.pq = C.pq;
+  nl = nlimbs;
   // batched: one launch per class width; per-op: one launch per class (width 1)
   for (const MacSeg& sg : M.seg) {
     const int steps = per_op ? sg.n : 1;
@@ -543,7 +613,8 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
   // batched: consecutive outputs with the same ordered key list share a group
   std::vector<fk::KipGroup> groups;
   std::vector<fk::KipKey> keys;
-  std::vector<int> it;
+  std::vector<int> it, c0it;
+  bool any_c0 = false;
   std::vector<double> bytes, wbytes;
   const int n = (int)items.size();
   int o = 0;
@@ -559,7 +630,11 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
     fk::KipGroup G{o, e - o, (int)keys.size(), (int)items[o].size()};
     for (size_t k = 0; k < items[o].size(); k++) {
       keys.push_back(fk::KipKey{items[o][k].g, items[o][k].key, (int)it.size()});
-      for (int oo = o; oo < o + fk::kKipOut; oo++) it.push_back(oo < e ? items[oo][k].ct : -1);
+      for (int oo = o; oo < o + fk::kKipOut; oo++) {
+        it.push_back(oo < e ? items[oo][k].ct : -1);
+        c0it.push_back(oo < e ? items[oo][k].c0ct : -1);
+        any_c0 = any_c0 || (oo < e && items[oo][k].c0ct >= 0);
+      }
     }
     // words per (limb, coefficient): per digit, nkey keys (2 words) and one ext word per item
     bytes.push_back((double)items[o].size() * ((e - o) + 2));
@@ -572,6 +647,7 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
   T.groups = upload(C, groups, owner);
   T.keys = upload(C, keys, owner);
   T.items = upload(C, it, owner);
+  if (any_c0) T.c0items = upload(C, c0it, owner);
   T.rd = bytes;
   T.wr = wbytes;
   return T;
@@ -592,8 +668,8 @@ KsStage make_ks(Ctx& C, const std::vector<std::vector<KsItem>>& items, const std
   return st;
 }
 
-static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int nl, bool single,
-                                 std::vector<void*>& owner) {
+static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int level,
+                                 bool single, bool pq, int na, std::vector<void*>& owner) {
   const int nout = (int)b.goff.size() - 1;
   // signature of an output: per group, whether it has a plaintext, and its inputs
   std::map<std::vector<int>, int> open;   // signature -> last class with it
@@ -636,6 +712,7 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
   constexpr int kZero = INT32_MIN;   // padding weight 0
   std::vector<fk::MacClass> cls;
   std::vector<int> cls_out, toff{0}, tin, wi;   // wi: weight index per (class term, row slot), -1: weight 1
+  std::vector<char> wa;                         // the term reads an A input
   std::vector<const uint64_t*> mask;
   MacTables T;
   int ngroups = 0;
@@ -674,7 +751,10 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
     // weights term-major, row-slot-minor
     const int nterm = b.toff[b.goff[rep + 1]] - b.toff[b.goff[rep]];
     for (int r = 0; r < nterm; r++)
-      for (int o = 0; o < W; o++) wi.push_back(o < no ? b.tw[b.toff[b.goff[mem[o]]] + r] : kZero);
+      for (int o = 0; o < W; o++) {
+        wi.push_back(o < no ? b.tw[b.toff[b.goff[mem[o]]] + r] : kZero);
+        wa.push_back(b.tin[b.toff[b.goff[rep]] + r] < na);
+      }
     cls.push_back(K);
   }
   T.n = (int)cls.size();
@@ -683,13 +763,19 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
   T.mask = (const uint64_t**)upload(C, mask, owner);
   T.toff = upload(C, toff, owner);
   T.tin = upload(C, tin, owner);
+  // weight residues per limb; in the extended basis the A inputs (Q only)
+  // enter as P x: weight * P on the Q limbs, zero on the P limbs
+  const int nq = level + 1, nlimbs = pq ? nq + C.K : nq;
+  const LevelTabs& LT = level_tabs(C, level);
   T.ews = std::max<long long>(1, (long long)wi.size());
-  std::vector<d2> ew((size_t)nl * T.ews, d2{0, 0});
-  for (int l = 0; l < nl; l++) {
-    const uint64_t q = C.primes[l];
+  std::vector<d2> ew((size_t)nlimbs * T.ews, d2{0, 0});
+  for (int l = 0; l < nlimbs; l++) {
+    const uint64_t q = C.primes[pq ? LT.h_eprime[l] : l];
     for (size_t k = 0; k < wi.size(); k++) {
       const int64_t v = wi[k] == kZero ? 0 : wi[k] < 0 ? 1 : wcodes[wi[k]] % (int64_t)q;
-      ew[(size_t)l * T.ews + k] = cpair((uint64_t)(v < 0 ? v + (int64_t)q : v), q);
+      uint64_t r = (uint64_t)(v < 0 ? v + (int64_t)q : v);
+      if (pq && wa[k]) r = l < nq ? mulmod(r, LT.h_pmod[l], q) : 0;
+      ew[(size_t)l * T.ews + k] = cpair(r, q);
     }
   }
   T.ew = upload(C, ew, owner);
@@ -697,21 +783,24 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
 }
 
 GmacStage make_gmac(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int level,
-                    std::vector<void*>& owner) {
+                    std::vector<void*>& owner, bool pq, int na) {
   GmacStage g;
   g.n_out = (int)b.goff.size() - 1;
   g.n_terms = (long long)b.tin.size();
+  g.pq = pq;
+  if (pq) g.eprime = level_tabs(C, level).eprime;
   for (auto* m : b.mask) g.n_masked += m != nullptr;
   if (g.n_out > 0) {
-    g.batched = make_mac_tables(C, b, wcodes, level + 1, false, owner);
-    g.single = make_mac_tables(C, b, wcodes, level + 1, true, owner);
+    g.batched = make_mac_tables(C, b, wcodes, level, false, pq, na, owner);
+    g.single = make_mac_tables(C, b, wcodes, level, true, pq, na, owner);
   }
   return g;
 }
 
 u64* encode_plaintexts(Ctx& C, const std::vector<std::vector<double>>& slots, double scale, int level,
-                       std::vector<void*>& owner) {
-  const int N = C.N, nl = level + 1, n = (int)slots.size();
+                       std::vector<void*>& owner, bool ext) {
+  const LevelTabs& LT = level_tabs(C, level);
+  const int N = C.N, nl = ext ? level + 1 + C.K : level + 1, n = (int)slots.size();
   std::vector<uint64_t> h((size_t)n * nl * N);
   const int nthr = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::thread> th;
@@ -721,7 +810,7 @@ u64* encode_plaintexts(Ctx& C, const std::vector<std::vector<double>>& slots, do
       for (int t = w; t < n; t += nthr) {
         fh::encode_real(C.logn, slots[t].data(), scale, m.data());
         for (int i = 0; i < nl; i++) {
-          const int64_t q = (int64_t)C.primes[i];
+          const int64_t q = (int64_t)C.primes[ext ? LT.h_eprime[i] : i];
           uint64_t* dst = &h[((size_t)t * nl + i) * N];
           for (int c = 0; c < N; c++) {
             int64_t v = m[c] % q;
@@ -732,7 +821,10 @@ u64* encode_plaintexts(Ctx& C, const std::vector<std::vector<double>>& slots, do
     });
   for (auto& t : th) t.join();
   u64* d = upload(C, h, owner);
-  ntt(C, false, d, d, (long long)nl * N, (long long)nl * N, n * nl, nl, identity_map(nl), nullptr);
+  fk::PrimeMap pm = identity_map(nl);
+  if (ext)
+    for (int i = 0; i < nl; i++) pm.p[i] = LT.h_eprime[i];
+  ntt(C, false, d, d, (long long)nl * N, (long long)nl * N, n * nl, nl, pm, nullptr);
   fb::sync(nullptr);
   return d;
 }

@@ -74,6 +74,7 @@ struct KsItem {
   int ct;
   unsigned g;
   const uint64_t* key;
+  int c0ct = -1;   // input ct whose sigma_g(c0), times P, is folded into the accumulator (-1: none)
 };
 
 // Device tables of a KIP + ModDown stage.  Outputs are grouped twice: in
@@ -84,6 +85,7 @@ struct KipTables {
   fk::KipGroup* groups = nullptr;
   fk::KipKey* keys = nullptr;
   int* items = nullptr;
+  int* c0items = nullptr;          // parallel to items: folded c0 source, -1 none (null: no folding)
   std::vector<double> rd, wr;      // host: words per (limb, coefficient) read per digit / written
 };
 struct KsStage {
@@ -117,6 +119,10 @@ struct GmacStage {
   int n_out = 0;
   long long n_terms = 0, n_masked = 0;
   MacTables batched, single;
+  // extended basis: limbs Q_l U P (prime indices eprime), A inputs (Q only)
+  // weighted by P on the Q limbs and absent on the P limbs
+  bool pq = false;
+  const unsigned char* eprime = nullptr;
 };
 
 struct Plan {
@@ -133,6 +139,8 @@ struct LevelTabs {
   d2* qlinv = nullptr;   // [level]
   unsigned char* eprime = nullptr;
   std::vector<unsigned char> h_eprime;
+  d2* pmod = nullptr;    // [level+1] P mod q_i
+  std::vector<uint64_t> h_pmod;
 };
 
 }  // namespace fr
@@ -165,6 +173,10 @@ struct fenc_ctx {
   // log2 of columns (cols pass) or chunks (rows pass) per block}; results do not depend on them
   int ntt_cfg[4][2] = {{3, -1}, {3, -1}, {3, -1}, {3, -1}};
   bool ntt_tuned = false;
+  // hoisting schedule of convolutions and S = 1 pooling: 1 = linear
+  // combinations of rotated copies in the extended basis with one ModDown per
+  // combined ciphertext, 0 = one ModDown per rotated copy
+  int hoist = 1;
   // single-kernel profiling: events around every launch of `prof_kernel`
   std::string prof_kernel;
   struct ProfRec {
@@ -204,8 +216,16 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
 void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
                  const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s);
 void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s);
-void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, int na, const u64* in_b,
-              long long b_cs, long long in_ps, u64* out, long long out_cs, long long out_ps, fb::Stream s);
+void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, long long a_ps, int na,
+              const u64* in_b, long long b_cs, long long b_ps, u64* out, long long out_cs, long long out_ps,
+              fb::Stream s);
+// KIP only (no ModDown): acc[o] over Q_l U P in NTT form, with P sigma(c0) folded in
+void kip_only(Ctx& C, int level, const u64* ext, const KsStage& st, u64* acc, const u64* c0, long long c0_cs,
+              fb::Stream s);
+// ModDown only of n extended-basis ciphertexts acc[o] ([2][le][N], NTT form) into out[o]
+void moddown_only(Ctx& C, int level, const u64* acc, const KsStage& md, u64* out, long long out_cs, fb::Stream s);
+// a ModDown-only stage for n outputs (tails only)
+KsStage make_md(Ctx& C, int n, std::vector<void*>& owner);
 
 KsStage make_ks(Ctx& C, const std::vector<std::vector<KsItem>>& items, const std::vector<fk::TailItem>& tails,
                 const std::vector<fk::AddTerm>& terms, std::vector<void*>& owner);
@@ -218,11 +238,11 @@ struct GmacBuild {
   void end_output() { goff.push_back((int)mask.size()); }
 };
 GmacStage make_gmac(Ctx& C, const GmacBuild& b, const std::vector<int64_t>& wcodes, int level,
-                    std::vector<void*>& owner);
+                    std::vector<void*>& owner, bool pq = false, int na = 0);
 
 // plaintexts: encode real slots at `scale`, reduce, NTT on device ([level+1][N])
 u64* encode_plaintexts(Ctx& C, const std::vector<std::vector<double>>& slots, double scale, int level,
-                       std::vector<void*>& owner);
+                       std::vector<void*>& owner, bool ext = false);   // ext: over Q_l U P ([le][N])
 
 int64_t weight_code(double w, double scale);
 void split_scale(double T, double& dw, double& dm);

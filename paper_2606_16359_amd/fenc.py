@@ -113,6 +113,7 @@ def load(path=None):
         "fenc_rescale": (C.c_int, [vp, B, B, vp]),
         "fenc_ntt_rows": (C.c_int, [vp, vp, vp, u32, C.c_int]),
         "fenc_ntt_config": (C.c_int, [vp, vp]),
+        "fenc_set_hoisting": (C.c_int, [vp, C.c_int]),
         "fenc_set_ntt_config": (C.c_int, [vp, vp]),
         "fenc_sample_word": (u64, [u64, u64, u64]),
         "fenc_sample_gauss": (C.c_int, [u64, u64, u64]),
@@ -164,6 +165,7 @@ class Fenc:
         self.N, self.ns, self.L = 1 << log_n, 1 << (log_n - 1), n_q - 1
         self.n_q, self.n_p, self.dnum = n_q, n_p, dnum
         self.alpha = (n_q + dnum - 1) // dnum
+        self.hoist = 1
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -199,6 +201,12 @@ class Fenc:
 
     def set_mode(self, mode):
         self._check(self.lib.fenc_set_mode(self.h, mode))
+
+    def set_hoisting(self, mode):
+        """1: linear combinations of rotated copies in the extended basis (one
+        ModDown per combined ciphertext); 0: one ModDown per rotated copy."""
+        self._check(self.lib.fenc_set_hoisting(self.h, mode))
+        self.hoist = mode
 
     def ntt_config(self):
         out = np.zeros(8, np.int32)

@@ -58,7 +58,7 @@ def test_lenet_first_layer_matches_oracle_at_full_size(lenet):
     Lo = o.plan_layout(64, 1, 28, 28, 5, 6)
     ob = o.encrypt_tensor(Lo, x, W.SEED_ENC)
     assert np.array_equal(fe.export(ct), ob.data())
-    yo, cnt = o.conv2d(ob, w[0])
+    yo, cnt = o.conv2d(ob, w[0], hoist=fe.hoist)
     y = fe.conv2d(ct, w[0])
     assert cnt["ks"] == 32
     assert np.array_equal(fe.export(y), yo.data())

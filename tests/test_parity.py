@@ -113,13 +113,16 @@ def test_encrypt_keys_and_keyswitch_building_blocks(backend, orc):
 
 
 @pytest.mark.parametrize("backend", BACKENDS)
-@pytest.mark.parametrize("mode,budget", [(F.FENC_MODE_BATCHED, 1 << 30), (F.FENC_MODE_PER_OP, 1 << 30),
-                                         (F.FENC_MODE_BATCHED, 0)])
-def test_mini_lenet_layers_bit_exact(backend, mode, budget, orc):
-    """Two conv/x^2/pool blocks, compression and two FC layers at N = 2^10."""
+@pytest.mark.parametrize("mode,budget,hoist", [(F.FENC_MODE_BATCHED, 1 << 30, 1), (F.FENC_MODE_PER_OP, 1 << 30, 1),
+                                               (F.FENC_MODE_BATCHED, 0, 1), (F.FENC_MODE_BATCHED, 1 << 30, 0),
+                                               (F.FENC_MODE_PER_OP, 0, 0)])
+def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
+    """Two conv/x^2/pool blocks, compression and two FC layers at N = 2^10, in
+    both hoisting schedules."""
     o, f = orc, make(backend, *SMALL)
     f.set_mode(mode)
     f.set_plaintext_budget(budget)
+    f.set_hoisting(hoist)
     r = rng(2)
     x = r.uniform(0, 1, (4, 1, 14, 14))
     w1, w2 = r.normal(0, 0.1, (3, 1, 3, 3)), r.normal(0, 0.1, (4, 3, 3, 3))
@@ -130,12 +133,12 @@ def test_mini_lenet_layers_bit_exact(backend, mode, budget, orc):
     assert np.array_equal(pt, o.encode_tensor(Lo, x))
     ob, fb = o.encrypt_tensor(Lo, x, 3), f.encrypt(pt, lay, 3)
     cmp(fb, ob, f)
-    steps = [("conv", lambda c: f.conv2d(c, w1), lambda b: o.conv2d(b, w1, pt_budget=budget)[0]),
+    steps = [("conv", lambda c: f.conv2d(c, w1), lambda b: o.conv2d(b, w1, pt_budget=budget, hoist=hoist)[0]),
              ("square", f.poly_act, lambda b: o.square(b)[0]),
-             ("pool-fragments", f.avgpool2, lambda b: o.avgpool2(b)[0]),
-             ("conv", lambda c: f.conv2d(c, w2), lambda b: o.conv2d(b, w2, pt_budget=budget)[0]),
+             ("pool-fragments", f.avgpool2, lambda b: o.avgpool2(b, hoist)[0]),
+             ("conv", lambda c: f.conv2d(c, w2), lambda b: o.conv2d(b, w2, pt_budget=budget, hoist=hoist)[0]),
              ("square", f.poly_act, lambda b: o.square(b)[0]),
-             ("pool-rotations", f.avgpool2, lambda b: o.avgpool2(b)[0]),
+             ("pool-rotations", f.avgpool2, lambda b: o.avgpool2(b, hoist)[0]),
              ("compress", f.compress, lambda b: o.compress(b)[0]),
              ("fc", lambda c: f.fc(c, f1), lambda b: o.fc(b, f1)[0]),
              ("fc", lambda c: f.fc(c, f2), lambda b: o.fc(b, f2)[0])]
@@ -156,20 +159,22 @@ def test_mini_lenet_layers_bit_exact(backend, mode, budget, orc):
     dict(x=(16, 2, 8, 8), w=(5, 2, 5, 5), stride=1, pad=0, groups=1, S=1),   # C' = 1: scalar MAC only
     dict(x=(1, 1, 12, 12), w=(6, 1, 5, 5), stride=1, pad=0, groups=1, S=1),  # replicated single channel
 ])
-def test_conv_variants_bit_exact(backend, budget, case, orc):
+@pytest.mark.parametrize("hoist", [1, 0])
+def test_conv_variants_bit_exact(backend, budget, case, hoist, orc):
     o, f = orc, make(backend, *SMALL)
     f.set_plaintext_budget(budget)
+    f.set_hoisting(hoist)
     r = rng(3)
     x, w = r.uniform(0, 1, case["x"]), r.normal(0, 0.1, case["w"])
     Lo = o.fragment_layout(*case["x"], case["S"])
     lay = f.plan_layout(*case["x"], case["w"][2], case["w"][0], case["S"])
     ob, fb = o.encrypt_tensor(Lo, x, 5), f.encrypt(f.encode_fragment(x, lay), lay, 5)
-    yo, cnt = o.conv2d(ob, w, case["stride"], case["pad"], case["groups"], pt_budget=budget)
+    yo, cnt = o.conv2d(ob, w, case["stride"], case["pad"], case["groups"], pt_budget=budget, hoist=hoist)
     f.stats_reset()
     yf = f.conv2d(fb, w, case["stride"], case["pad"], case["groups"])
     cmp(yf, yo, f)
     st = f.stats()
-    assert (st["rot_inner"], st["rot_outer"]) == (cnt["inner_rot"], cnt["outer_rot"])
+    assert (st["rot_inner"], st["rot_outer"], st["moddown"]) == (cnt["inner_rot"], cnt["outer_rot"], cnt["moddown"])
     want = cnn_ref.conv2d(x, w, case["stride"], case["pad"], case["groups"])
     assert np.max(np.abs(f.decrypt(yf) - want)) < 1e-4
 
@@ -186,7 +191,7 @@ def test_single_conv_layer_benchmark_small_config(backend):
     assert (lay.S, lay.chan_per_ct, lay.replicate) == (Lo["S"], Lo["cpc"], Lo["rep"]) == (1, 4, 1)
     ob, fb = o.encrypt_tensor(Lo, x, 9), f.encrypt(f.encode_fragment(x, lay), lay, 9)
     cmp(fb, ob, f)
-    yo, cnt = o.conv2d(ob, w)
+    yo, cnt = o.conv2d(ob, w, hoist=f.hoist)
     yf = f.conv2d(fb, w)
     cmp(yf, yo, f)
     assert cnt["inner_rot"] == 24 and cnt["outer_rot"] == 0 and yf.n_ct == 2
@@ -236,7 +241,7 @@ def test_scalar_weights_after_activation_scale_drop(backend, orc):
     Lo = o.fragment_layout(16, 2, 8, 8, 1)
     lay = f.plan_layout(16, 2, 8, 8, 3, 2, 1)
     ob, fb = o.encrypt_tensor(Lo, x, 6), f.encrypt(f.encode_fragment(x, lay), lay, 6)
-    ob = o.conv2d(o.square(o.conv2d(ob, w1)[0])[0], w2)[0]
+    ob = o.conv2d(o.square(o.conv2d(ob, w1, hoist=f.hoist)[0])[0], w2, hoist=f.hoist)[0]
     fb = f.conv2d(f.poly_act(f.conv2d(fb, w1)), w2)
     cmp(fb, ob, f)
     want = cnn_ref.conv2d(cnn_ref.square(cnn_ref.conv2d(x, w1)), w2)
@@ -284,7 +289,7 @@ def test_cifar_shaped_stack_small_bit_exact(backend):
     ob, fb = o.encrypt_tensor(Lo, x, 7), f.encrypt(f.encode_fragment(x, lay), lay, 7)
     ref = x
     for wi, s in zip(w, strides):
-        ob = o.poly_act(o.conv2d(ob, wi, s, 1)[0], list(W.CUBIC))[0]
+        ob = o.poly_act(o.conv2d(ob, wi, s, 1, hoist=f.hoist)[0], list(W.CUBIC))[0]
         ref = np.polynomial.polynomial.polyval(cnn_ref.conv2d(ref, wi, s, 1), W.CUBIC)
     fb = W.cifar_forward(f, fb, w, strides)
     cmp(fb, ob, f)
