@@ -25,11 +25,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
 KERNELS = ["gmac", "gmac_pt", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "moddown_tail",
-           "moddown_fbc", "modup_fbc", "rescale_tail", "rescale_lift", "tensor_square"]
+           "moddown_fbc", "modup_fbc", "rescale_tail", "rescale_lift", "tensor_square", "lin_comb"]
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"moddown_tail": 837662041, "kip": 846503449, "ntt_fwd_rows": 352841969, "ntt_fwd_cols": 323150844, "gmac_pt": 355602609, "gmac": 788688914, "ntt_inv_rows": 112046506, "ntt_inv_cols": 106633050, "rescale_tail": 289028177, "moddown_fbc": 332516596, "modup_fbc": 256674868, "tensor_square": 477122721, "rescale_lift": 101864473}
+TRAFFIC = {"kip": 856221778, "ntt_fwd_rows": 250346734, "ntt_fwd_cols": 225821822, "gmac": 1045898940, "moddown_tail": 371033652, "gmac_pt": 355610380, "rescale_tail": 289028580, "ntt_inv_cols": 68112833, "modup_fbc": 256665540, "lin_comb": 572520554, "moddown_fbc": 151115059, "tensor_square": 477122546, "rescale_lift": 101859921}
 
 
 def log(*a):
@@ -184,6 +184,8 @@ def main():
         "graph_vs_per_op": round(t_perop / t_graph, 3),
         "bit_identical": {"graph_vs_eager": identical_graph, "per_op_vs_batched": identical_perop},
         "launches_per_step": st["launches"],
+        "step_counters": st,
+        "ntt_config": fe.ntt_config(),
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": TRAFFIC.get(dom), "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],

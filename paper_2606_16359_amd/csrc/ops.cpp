@@ -612,6 +612,7 @@ static void run_pool(Ctx& C, const PoolPlan& P, const u64* in, u64* out, fb::Str
 // where x' is x without its last limb, k1 = round(c1 S / s), k0 = round(c0 S).
 struct PolyPlan : Plan {
   int level = 0, n = 0, d = 0;
+  bool lin = true;               // the c1 x + c0 terms are present
   KsStage ks_a, ks_b;            // relinearisation at level l and l-1
   d2 *kf = nullptr, *one = nullptr, *k1 = nullptr, *k0 = nullptr, *k3 = nullptr, *k2c = nullptr;
 };
@@ -694,7 +695,7 @@ static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Str
     run_tensor(C, l, n, in, in, P.kf, t, d2b, s);
     relin(C, l, n, P.ks_a, t, d2b, s);
     if (P.d == 2) {
-      run_lin(C, l + 1, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
+      if (P.lin) run_lin(C, l + 1, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
       rescale(C, l, t, n, out, s);
     } else {
       const long long c1e = ct_elems(C, l - 1);
@@ -705,7 +706,7 @@ static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Str
       run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, nullptr, u, P.k3, P.k2c, s);
       run_tensor(C, l - 1, n, x2, u, P.one, t, d2b, s);
       relin(C, l - 1, n, P.ks_b, t, d2b, s);
-      run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
+      if (P.lin) run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
       rescale(C, l - 1, t, n, out, s);
     }
   }
@@ -1435,6 +1436,7 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
     p->level = Lin.level;
     p->n = Lin.n_ct();
     p->d = d;
+    p->lin = d <= 1 || c[0] != 0.0 || c[1] != 0.0;   // adding zero codes changes nothing
     const int l = Lin.level;
     auto up = [&](const std::vector<d2>& v) { return upload(C, v, p->owned); };
     if (d >= 2) {
