@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_ro
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 856221778, "ntt_fwd_rows": 250346734, "ntt_fwd_cols": 225821822, "gmac": 1045898940, "moddown_tail": 371033652, "gmac_pt": 355610380, "rescale_tail": 289028580, "ntt_inv_cols": 68112833, "modup_fbc": 256665540, "lin_comb": 572520554, "moddown_fbc": 151115059, "tensor_square": 477122546, "rescale_lift": 101859921}
+TRAFFIC = {"kip": 856221501, "ntt_fwd_rows": 250323477, "gmac": 1045899996, "moddown_tail": 371042899, "gmac_pt": 355610431, "rescale_tail": 289028692, "ntt_inv_rows": 73469240, "ntt_inv_cols": 68093148, "modup_fbc": 256666639, "moddown_fbc": 151115177, "tensor_square": 477121650, "rescale_lift": 101859889}
 
 
 def log(*a):
