@@ -24,12 +24,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
-KERNELS = ["gmac", "gmac_pt", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "moddown_tail",
-           "moddown_fbc", "modup_fbc", "rescale_tail", "rescale_lift", "tensor_square", "lin_comb"]
+KERNELS = ["gmac", "gmac_pt", "gmac_fast", "gmac_pt_fast", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "moddown_tail",
+           "moddown_fbc", "modup_fbc", "rescale_tail", "rescale_lift", "tensor_square", "lin_comb", "lift_pq"]
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 856221501, "ntt_fwd_rows": 250323477, "gmac": 1045899996, "moddown_tail": 371042899, "gmac_pt": 355610431, "rescale_tail": 289028692, "ntt_inv_rows": 73469240, "ntt_inv_cols": 68093148, "modup_fbc": 256666639, "moddown_fbc": 151115177, "tensor_square": 477121650, "rescale_lift": 101859889}
+TRAFFIC = {"kip": 856221501, "ntt_fwd_rows": 250323477, "moddown_tail": 371042899, "rescale_tail": 289028692, "ntt_inv_rows": 73469240, "ntt_inv_cols": 68093148, "modup_fbc": 256666639, "moddown_fbc": 151115177, "tensor_square": 477121650, "rescale_lift": 101859889}
 
 
 def log(*a):

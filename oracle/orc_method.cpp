@@ -228,10 +228,15 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
   Lout.level = lvl - 1;
   Lout.scale = Delta;
   const int nd = Lin.rep ? cin : cpc;
+  // Per-position masks are needed when a ciphertext holds several channel
+  // positions or the kernel reads padding.  Either way T = q_l Delta / s_in is
+  // split into a weight scale dw and a plaintext scale dm (Delta1 Delta2 split),
+  // so weight codes stay below 2^25; without masks the plaintext is the
+  // all-ones vector at dm.
   const bool need_mask = (cpc > 1) || (pad > 0);
   const double T = ((double)C.primes[lvl] * Delta) / Lin.scale;
   double dw = T, dm = 1.0;
-  if (need_mask) split_scale(T, dw, dm);
+  split_scale(T, dw, dm);
   const int npos = need_mask ? cpc : 1;
 
   auto in_channel = [&](int gi, int q) { return Lin.rep ? q % cin : gi * cpc + q; };
@@ -324,6 +329,12 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
       }
     return masks[key] = encode(C, z, {}, dm, basis);
   };
+  auto ones = [&]() -> const RPoly& {
+    const std::vector<int> key = {-1};
+    auto it = masks.find(key);
+    if (it != masks.end()) return it->second;
+    return masks[key] = encode(C, std::vector<double>(C.ns, 1.0), {}, dm, basis);
+  };
 
   std::vector<Ct> out(terms.size());
   for (int bg = 0; bg < Lin.nbg; bg++)
@@ -371,8 +382,8 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
               bool any = false;
               for (int r = 0; r < nd; r++) any |= pair_ok(ch, go * cpc + posmod(q - r, cpc));
               if (!any) continue;
-              Ct mc = need_mask ? mul_plain(C, copy, mask(t, q), dm) : copy;
-              if (need_mask) cnt.pmult++;
+              Ct mc = mul_plain(C, copy, need_mask ? mask(t, q) : ones(), dm);
+              cnt.pmult++;
               for (int r = 0; r < nd; r++) {
                 const int o = go * cpc + posmod(q - r, cpc);
                 if (!pair_ok(ch, o)) continue;

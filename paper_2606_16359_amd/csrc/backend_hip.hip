@@ -90,7 +90,10 @@ FENC_KERNEL(rescale_lift, LiftArgs)
 FENC_KERNEL(rescale_tail, RescaleTailArgs)
 FENC_KERNEL_XCD(gmac, GmacArgs)
 FENC_KERNEL_XCD(gmac_pt, GmacArgs)
+FENC_KERNEL_XCD(gmac_fast, GmacArgs)
+FENC_KERNEL_XCD(gmac_pt_fast, GmacArgs)
 FENC_KERNEL(tensor_square, SquareArgs)
+FENC_KERNEL(lift_pq, LiftPqArgs)
 FENC_KERNEL(lin_comb, LinArgs)
 FENC_KERNEL(key_combine, KeyArgs)
 FENC_KERNEL(enc_combine, EncArgs)

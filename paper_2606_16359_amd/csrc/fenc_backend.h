@@ -46,7 +46,10 @@ void rescale_lift(Grid g, int threads, Stream s, const fk::LiftArgs& a);
 void rescale_tail(Grid g, int threads, Stream s, const fk::RescaleTailArgs& a);
 void gmac(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_pt(Grid g, int threads, Stream s, const fk::GmacArgs& a);
+void gmac_fast(Grid g, int threads, Stream s, const fk::GmacArgs& a);
+void gmac_pt_fast(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void tensor_square(Grid g, int threads, Stream s, const fk::SquareArgs& a);
+void lift_pq(Grid g, int threads, Stream s, const fk::LiftPqArgs& a);
 void lin_comb(Grid g, int threads, Stream s, const fk::LinArgs& a);
 void key_combine(Grid g, int threads, Stream s, const fk::KeyArgs& a);
 void enc_combine(Grid g, int threads, Stream s, const fk::EncArgs& a);

@@ -618,6 +618,35 @@ FENC_HD void rescale_tail(X& x, const RescaleTailArgs& a) {
   });
 }
 
+// ------------------------------------------------------------------ lift to the extended basis
+// out[t] = P x_t on the nl Q limbs and 0 on the K special limbs ([2][le][N],
+// NTT form): ModDown of it gives x_t back, so unrotated inputs join linear
+// combinations taken in Q_l U P.
+struct LiftPqArgs {
+  const u64* in;  long long in_cs;   // [n][2][nl][N]
+  u64* out;  long long out_cs;       // [n][2][le][N]
+  int nl, le, logn;
+  const d2* pmod;                    // [nl] P mod q_i
+  const d2* pq;
+};
+
+template <class X>
+FENC_HD void lift_pq(X& x, const LiftPqArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int l = x.by % a.le, poly = x.by / a.le, b = x.bz;
+    u64* o = a.out + b * a.out_cs + ((long long)poly * a.le + l) * N + c;
+    if (l >= a.nl) {
+      *o = 0;
+      return;
+    }
+    const double q = a.pq[l].x;
+    const double v = u2d(a.in[b * a.in_cs + ((long long)poly * a.nl + l) * N + c]);
+    *o = d2u(norm(mulmod_c(v, a.pmod[l].x, a.pmod[l].y, q), q));
+  });
+}
+
 // ------------------------------------------------------------------ linear combinations
 // A class is a set of up to kMacOut outputs with the same input terms, each
 // output with its own integer weights and its own plaintext per group (a small
@@ -658,6 +687,87 @@ struct GmacArgs {
 // XCD-aware order so both polys and neighbouring classes of one tile share an
 // L2 (plaintexts and shared inputs are fetched once).  PT: the class has
 // plaintext products.
+// Classes whose weight codes are all below 2^23 in magnitude (split-scale
+// weights) take exact products without a modular reduction per term: the
+// input word is split into 25-bit halves, hi * w and lo * w are exact binary64
+// integers below 2^48, and 16 of them are summed before one reduction.  The
+// weight table then holds the signed code itself (y unused).
+constexpr int kFastWBits = 23;
+
+template <int W, bool PT, class X>
+FENC_HD void gmac_fast_w(X& x, const GmacArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int i = x.by, poly = x.bz & 1;
+    const MacClass K = a.cls[a.c0 + (x.bz >> 1)];
+    const int pi = a.eprime ? a.eprime[i] : i;
+    const double q = a.pq[pi].x, qi = a.pq[pi].y;
+    const double t25 = 33554432.0, t25q = t25 * qi;   // 2^25 < q
+    const long long off_a = poly * a.a_ps + i * N + c, off_b = poly * a.b_ps + i * N + c;
+    const bool a_here = i < a.nl_a;
+    const d2* ew = a.ew + (long long)i * a.ews + K.w0;
+    auto load_in = [&](int k) -> u64 {
+      const int ti = a.tin[k];
+      if (ti < a.na) return a_here ? a.in_a[ti * a.a_cs + off_a] : 0;
+      return a.in_b[(ti - a.na) * a.b_cs + off_b];
+    };
+    double r[W], sh[W], sl[W];
+#pragma unroll
+    for (int o = 0; o < W; o++) r[o] = 0;
+    const int k0 = a.toff[K.g0], kend = a.toff[K.g0 + K.ng];
+    int k = k0;
+    u64 vn = k < kend ? load_in(k) : 0;
+    for (int g = K.g0; g < K.g0 + K.ng; g++) {
+#pragma unroll
+      for (int o = 0; o < W; o++) sh[o] = sl[o] = 0;
+      int n = 0;
+      for (const int ge = a.toff[g + 1]; k < ge; k++) {
+        const u64 v = vn;
+        if (k + 1 < kend) vn = load_in(k + 1);
+        const double vh = u2d(v >> 25), vl = u2d(v & 0x1FFFFFFull);
+        const d2* w = ew + (long long)(k - k0) * W;
+#pragma unroll
+        for (int o = 0; o < W; o++) {
+          sh[o] = fma(vh, w[o].x, sh[o]);
+          sl[o] = fma(vl, w[o].x, sl[o]);
+        }
+        if (++n == 16) {
+#pragma unroll
+          for (int o = 0; o < W; o++) {
+            sh[o] = red(sh[o], q, qi);
+            sl[o] = red(sl[o], q, qi);
+          }
+          n = 0;
+        }
+      }
+      double sg[W];
+#pragma unroll
+      for (int o = 0; o < W; o++) sg[o] = red(mulmod_c(red(sh[o], q, qi), t25, t25q, q) + red(sl[o], q, qi), q, qi);
+      if constexpr (PT) {
+        const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
+        double mv[W];
+#pragma unroll
+        for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
+#pragma unroll
+        for (int o = 0; o < W; o++) {
+          double s = sg[o];
+          if (mg[o]) s = mulmod(s, mv[o], q, qi);
+          r[o] = red(r[o] + s, q, qi);
+        }
+      } else {
+#pragma unroll
+        for (int o = 0; o < W; o++) r[o] = red(r[o] + sg[o], q, qi);
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < W; o++) {
+      if (o >= K.nout) continue;
+      a.out[a.cls_out[K.o0 + o] * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(r[o], q));
+    }
+  });
+}
+
 template <int W, bool PT, class X>
 FENC_HD void gmac_w(X& x, const GmacArgs& a) {
   x.phase([&](int t) {
@@ -722,22 +832,27 @@ FENC_HD void gmac_w(X& x, const GmacArgs& a) {
   });
 }
 
-template <bool PT, class X>
+template <bool PT, bool FAST, class X>
 FENC_HD void gmac_any(X& x, const GmacArgs& a) {
   switch (a.width) {
-    case 1: gmac_w<1, PT>(x, a); break;
-    case 2: gmac_w<2, PT>(x, a); break;
-    case 4: gmac_w<4, PT>(x, a); break;
-    case 8: gmac_w<8, PT>(x, a); break;
-    default: gmac_w<kMacOut, PT>(x, a); break;
+    case 1: FAST ? gmac_fast_w<1, PT>(x, a) : gmac_w<1, PT>(x, a); break;
+    case 2: FAST ? gmac_fast_w<2, PT>(x, a) : gmac_w<2, PT>(x, a); break;
+    case 4: FAST ? gmac_fast_w<4, PT>(x, a) : gmac_w<4, PT>(x, a); break;
+    case 8: FAST ? gmac_fast_w<8, PT>(x, a) : gmac_w<8, PT>(x, a); break;
+    default: FAST ? gmac_fast_w<kMacOut, PT>(x, a) : gmac_w<kMacOut, PT>(x, a); break;
   }
 }
 // classes without plaintext products
 template <class X>
-FENC_HD void gmac(X& x, const GmacArgs& a) { gmac_any<false>(x, a); }
+FENC_HD void gmac(X& x, const GmacArgs& a) { gmac_any<false, false>(x, a); }
 // classes with plaintext products (null entries allowed)
 template <class X>
-FENC_HD void gmac_pt(X& x, const GmacArgs& a) { gmac_any<true>(x, a); }
+FENC_HD void gmac_pt(X& x, const GmacArgs& a) { gmac_any<true, false>(x, a); }
+// the same with small weight codes (|code| < 2^23)
+template <class X>
+FENC_HD void gmac_fast(X& x, const GmacArgs& a) { gmac_any<false, true>(x, a); }
+template <class X>
+FENC_HD void gmac_pt_fast(X& x, const GmacArgs& a) { gmac_any<true, true>(x, a); }
 
 // ------------------------------------------------------------------ tensor / key / encryption
 // Tensor product of ciphertexts a and b (b == a for a square), times the

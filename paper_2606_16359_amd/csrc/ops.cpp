@@ -304,10 +304,14 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   P->n_in = Lin.n_ct();
   P->pq = C.hoist != 0;
   const int nd = Lin.rep ? cin : cpc;
+  // masks per channel position when a ciphertext holds several positions or the
+  // kernel reads padding; T is always split into a weight scale dw and a
+  // plaintext scale dm, so weight codes stay small (the all-ones plaintext at
+  // dm when no mask is needed)
   const bool need_mask = (cpc > 1) || (pad > 0);
   const double T = ((double)C.primes[lvl] * C.Delta) / Lin.scale;
   double dw = T, dm = 1.0;
-  if (need_mask) split_scale(T, dw, dm);
+  split_scale(T, dw, dm);
   const int npos = need_mask ? cpc : 1;
   auto in_channel = [&](int gi, int q) { return Lin.rep ? q % cin : gi * cpc + q; };
   auto pair_ok = [&](int ch, int o) { return ch < cin && o < cout && ch / gin == o / gout; };
@@ -390,6 +394,13 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
     mask_slots.push_back(z);
     return mask_id[key] = (int)mask_slots.size() - 1;
   };
+  auto ones_id = [&]() {
+    const std::vector<int> key = {-1};
+    auto it = mask_id.find(key);
+    if (it != mask_id.end()) return it->second;
+    mask_slots.push_back(std::vector<double>(C.ns, 1.0));
+    return mask_id[key] = (int)mask_slots.size() - 1;
+  };
   std::map<int64_t, int> wid;
   std::vector<int64_t> codes;
   auto weight_id = [&](int64_t code) {
@@ -411,7 +422,9 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   for (int oct = 0; oct < P->n_out; oct++) {
     const int go = (oct / (So * So)) % ncg_out;
     for (const Term& t : terms[oct]) {
-      const int in_id = t.shift ? P->n_in + copy_id[{t.idx, t.shift}] : t.idx;
+      // pq: unrotated inputs enter lifted (P x) after the copies in the B buffer
+      const int in_id = t.shift ? P->n_in + copy_id[{t.idx, t.shift}]
+                                : (P->pq ? P->n_in + (int)copies.size() + t.idx : t.idx);
       if (materialise) {
         for (int r = 0; r < nd; r++) {
           std::vector<double> z;
@@ -441,7 +454,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
           if (!pair_ok(ch, o)) continue;
           act[oct][r] = 1;
           const int64_t code = weight_code(wval(o, ch, t), dw);   // zero codes kept: shared structure
-          const int mid = need_mask ? mask_of(t, q) : -1;
+          const int mid = need_mask ? mask_of(t, q) : ones_id();
           G[oct][r][mid].push_back({in_id, weight_id(code)});
           P->n_terms++;
         }
@@ -495,9 +508,10 @@ static void run_conv(Ctx& C, const ConvPlan& P, const u64* in, u64* out, fb::Str
   u64* zr = yz + (long long)P.n_out * ce;
   if (P.pq) {
     const long long ee = 2LL * le * C.N, pe = (long long)le * C.N;
-    u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ee * 8, s);
+    u64* copies = (u64*)C.arena.get((size_t)(P.rot.n + P.n_in) * ee * 8, s);   // copies, then lifted inputs
     u64* yzp = (u64*)C.arena.get((size_t)(P.n_out + P.n_zr) * ee * 8, s);
     run_rot_stage(C, lvl, P.rot, in, copies, s, true);
+    lift_to_pq(C, lvl, in, P.n_in, copies + (long long)P.rot.n * ee, s);
     run_gmac(C, nl, P.g0, in, ce, ps, P.n_in, copies, ee, pe, yzp, ee, pe, s);
     run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, copies, ee, pe, yzp + (long long)P.n_out * ee, ee, pe, s);
     moddown_only(C, lvl, yzp, P.md, yz, ce, s);
@@ -569,7 +583,7 @@ static PoolPlan* build_pool(Ctx& C, const Layout& Lin, bool shape_only, Layout& 
     P->rot = make_rot_stage(C, copies, P->owned, P->pq);
     for (int t = 0; t < P->n_in; t++) {
       gb.add_group(nullptr);
-      gb.add_term(t, -1);
+      gb.add_term(P->pq ? P->n_in + 3 * P->n_in + t : t, -1);   // pq: the lifted input after the copies
       for (int i = 0; i < 3; i++) gb.add_term(P->n_in + i * P->n_in + t, -1);
       gb.end_group();
       gb.end_output();
@@ -586,9 +600,10 @@ static void run_pool(Ctx& C, const PoolPlan& P, const u64* in, u64* out, fb::Str
   Scope sc(C.arena);
   if (P.pq) {
     const long long ee = 2LL * le * C.N, pe = (long long)le * C.N;
-    u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ee * 8, s);
+    u64* copies = (u64*)C.arena.get((size_t)(P.rot.n + P.n_in) * ee * 8, s);   // copies, then lifted inputs
     u64* zp = (u64*)C.arena.get((size_t)P.n_out * ee * 8, s);
     run_rot_stage(C, P.level, P.rot, in, copies, s, true);
+    lift_to_pq(C, P.level, in, P.n_in, copies + (long long)P.rot.n * ee, s);
     run_gmac(C, nl, P.g, in, ce, ps, P.n_in, copies, ee, pe, zp, ee, pe, s);
     moddown_only(C, P.level, zp, P.md, out, ce, s);
   } else {

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <array>
+#include <tuple>
 #include <thread>
 
 namespace fr {
@@ -516,6 +517,22 @@ void moddown_only(Ctx& C, int level, const u64* acc, const KsStage& md, u64* out
                  nullptr, 0, s);
 }
 
+void lift_to_pq(Ctx& C, int level, const u64* in, int n, u64* out, fb::Stream s) {
+  if (n <= 0) return;
+  const LevelTabs& T = level_tabs(C, level);
+  const int nl = level + 1, le = nl + C.K;
+  const bool per_op = C.mode == FENC_MODE_PER_OP;
+  for (int b0 = 0; b0 < n; b0 += per_op ? 1 : n) {
+    const int nb = per_op ? 1 : n;
+    fk::LiftPqArgs a{in + (long long)b0 * 2 * nl * C.N, 2LL * nl * C.N, out + (long long)b0 * 2 * le * C.N,
+                     2LL * le * C.N, nl, le, C.logn, T.pmod, C.pq};
+    timed(C, "lift_pq", 2.0 * nb * (nl + le) * C.N * 8, s, [&] {
+      fb::lift_pq({(unsigned)(C.N / block_threads(C)), (unsigned)(2 * le), (unsigned)nb}, block_threads(C), s, a);
+    });
+    C.cnt.launches++;
+  }
+}
+
 KsStage make_md(Ctx& C, int n, std::vector<void*>& owner) {
   std::vector<fk::TailItem> tails;
   for (int o = 0; o < n; o++) tails.push_back(fk::TailItem{o, -1, 0, 0});
@@ -599,9 +616,15 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
       const int nc = per_op ? 1 : sg.n;
       const double gb = sg.words / sg.n * nc * nl * C.N * 8;
       const fb::Grid grid{(unsigned)(C.N / block_threads(C)), (unsigned)nl, (unsigned)(2 * nc)};
-      timed(C, sg.pt ? "gmac_pt" : "gmac", gb, s, [&] {
-        if (sg.pt) fb::gmac_pt(grid, block_threads(C), s, a);
-        else fb::gmac(grid, block_threads(C), s, a);
+      timed(C, sg.fast ? (sg.pt ? "gmac_pt_fast" : "gmac_fast") : (sg.pt ? "gmac_pt" : "gmac"), gb, s, [&] {
+        if (sg.fast) {
+          if (sg.pt) fb::gmac_pt_fast(grid, block_threads(C), s, a);
+          else fb::gmac_fast(grid, block_threads(C), s, a);
+        } else if (sg.pt) {
+          fb::gmac_pt(grid, block_threads(C), s, a);
+        } else {
+          fb::gmac(grid, block_threads(C), s, a);
+        }
       });
       C.cnt.launches += 1;
     }
@@ -705,22 +728,37 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
         if (b.mask[g]) return true;
     return false;
   };
+  const int64_t fast_lim = 1LL << fk::kFastWBits;
+  auto is_fast = [&](const std::vector<int>& mem) {
+    for (int o : mem)
+      for (int k = b.toff[b.goff[o]]; k < b.toff[b.goff[o + 1]]; k++) {
+        if (pq && b.tin[k] < na) return false;   // A terms carry the factor P
+        const int w = b.tw[k];
+        if (w >= 0 && !(wcodes[w] > -fast_lim && wcodes[w] < fast_lim)) return false;
+      }
+    return true;
+  };
+  auto seg_key = [&](const std::vector<int>& m) {
+    return std::make_tuple(width_of((int)m.size()), (int)has_pt(m), (int)is_fast(m));
+  };
   std::stable_sort(members.begin(), members.end(), [&](const std::vector<int>& x, const std::vector<int>& y) {
-    const int wx = width_of((int)x.size()), wy = width_of((int)y.size());
-    return wx != wy ? wx < wy : (int)has_pt(x) < (int)has_pt(y);
+    return seg_key(x) < seg_key(y);
   });
   constexpr int kZero = INT32_MIN;   // padding weight 0
   std::vector<fk::MacClass> cls;
   std::vector<int> cls_out, toff{0}, tin, wi;   // wi: weight index per (class term, row slot), -1: weight 1
   std::vector<char> wa;                         // the term reads an A input
+  std::vector<char> wfast;                      // the entry belongs to a fast class (signed code stored)
   std::vector<const uint64_t*> mask;
   MacTables T;
   int ngroups = 0;
   for (auto& mem : members) {
     const int rep = mem[0], no = (int)mem.size(), W = width_of(no);
-    const bool pt = has_pt(mem);
-    if (T.seg.empty() || T.seg.back().width != W || T.seg.back().pt != pt)
-      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, pt, 0.0});
+    const bool pt = has_pt(mem), fast = is_fast(mem);
+    if (T.seg.empty() || T.seg.back().width != W || T.seg.back().pt != pt || T.seg.back().fast != fast)
+      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, pt, fast, 0.0});
+    for (int r = 0; r < b.toff[b.goff[rep + 1]] - b.toff[b.goff[rep]]; r++)
+      for (int o = 0; o < W; o++) wfast.push_back(fast);
     MacSeg& sg = T.seg.back();
     sg.n++;
     fk::MacClass K;
@@ -772,6 +810,11 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
   for (int l = 0; l < nlimbs; l++) {
     const uint64_t q = C.primes[pq ? LT.h_eprime[l] : l];
     for (size_t k = 0; k < wi.size(); k++) {
+      if (wfast[k]) {   // the signed code itself
+        const int64_t code = wi[k] == kZero ? 0 : wi[k] < 0 ? 1 : wcodes[wi[k]];
+        ew[(size_t)l * T.ews + k] = d2{(double)code, 0.0};
+        continue;
+      }
       const int64_t v = wi[k] == kZero ? 0 : wi[k] < 0 ? 1 : wcodes[wi[k]] % (int64_t)q;
       uint64_t r = (uint64_t)(v < 0 ? v + (int64_t)q : v);
       if (pq && wa[k]) r = l < nq ? mulmod(r, LT.h_pmod[l], q) : 0;

@@ -102,6 +102,7 @@ struct KsStage {
 struct MacSeg {
   int c0, n, width;
   bool pt;                         // classes with plaintext products
+  bool fast;                       // every weight code below 2^23 in magnitude
   double words;                    // words per (coefficient, limb) moved by the segment's classes
 };
 struct MacTables {
@@ -224,6 +225,8 @@ void kip_only(Ctx& C, int level, const u64* ext, const KsStage& st, u64* acc, co
               fb::Stream s);
 // ModDown only of n extended-basis ciphertexts acc[o] ([2][le][N], NTT form) into out[o]
 void moddown_only(Ctx& C, int level, const u64* acc, const KsStage& md, u64* out, long long out_cs, fb::Stream s);
+// out[t] = (P x_t, 0) over Q_l U P for n cts at level (NTT form)
+void lift_to_pq(Ctx& C, int level, const u64* in, int n, u64* out, fb::Stream s);
 // a ModDown-only stage for n outputs (tails only)
 KsStage make_md(Ctx& C, int n, std::vector<void*>& owner);
 

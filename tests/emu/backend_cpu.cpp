@@ -77,7 +77,10 @@ EMU(rescale_lift, LiftArgs)
 EMU(rescale_tail, RescaleTailArgs)
 EMU_XCD(gmac, GmacArgs)
 EMU_XCD(gmac_pt, GmacArgs)
+EMU_XCD(gmac_fast, GmacArgs)
+EMU_XCD(gmac_pt_fast, GmacArgs)
 EMU(tensor_square, SquareArgs)
+EMU(lift_pq, LiftPqArgs)
 EMU(lin_comb, LinArgs)
 EMU(key_combine, KeyArgs)
 EMU(enc_combine, EncArgs)

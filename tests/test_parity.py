@@ -232,8 +232,8 @@ def test_errors_are_reported_not_launched(backend, orc):
 
 @pytest.mark.parametrize("backend", BACKENDS)
 def test_scalar_weights_after_activation_scale_drop(backend, orc):
-    """x^2 leaves scale Delta^2/q (about 2^30 here); the next C'=1 convolution
-    restores Delta with weight codes near 2^58."""
+    """x^2 leaves the scale near Delta; after a second conv the activation's scale
+    drift is absorbed by the next convolution's T = q_l Delta / s_in split."""
     o, f = orc, make(backend, *SMALL)
     r = rng(5)
     x = r.uniform(0, 1, (16, 2, 8, 8))
