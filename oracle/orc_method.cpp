@@ -329,11 +329,15 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
       }
     return masks[key] = encode(C, z, {}, dm, basis);
   };
-  auto ones = [&]() -> const RPoly& {
-    const std::vector<int> key = {-1};
-    auto it = masks.find(key);
-    if (it != masks.end()) return it->second;
-    return masks[key] = encode(C, std::vector<double>(C.ns, 1.0), {}, dm, basis);
+  // the all-ones plaintext at dm: its integer polynomial is checked to be the
+  // constant round(dm) (every other coefficient zero) and that constant is used
+  i64 ones_c = 0;
+  auto ones_const = [&]() -> i64 {
+    if (ones_c) return ones_c;
+    const std::vector<i64> m = encode_int(C, std::vector<double>(C.ns, 1.0), {}, dm);
+    for (size_t i = 1; i < m.size(); i++)
+      if (m[i] != 0) throw std::runtime_error("conv2d: all-ones plaintext is not constant");
+    return ones_c = m[0];
   };
 
   std::vector<Ct> out(terms.size());
@@ -382,7 +386,9 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
               bool any = false;
               for (int r = 0; r < nd; r++) any |= pair_ok(ch, go * cpc + posmod(q - r, cpc));
               if (!any) continue;
-              Ct mc = mul_plain(C, copy, need_mask ? mask(t, q) : ones(), dm);
+              // the all-ones vector encodes to the constant polynomial round(dm):
+              // multiplying by it is multiplying by that integer
+              Ct mc = need_mask ? mul_plain(C, copy, mask(t, q), dm) : mul_scalar(C, copy, ones_const(), dm);
               cnt.pmult++;
               for (int r = 0; r < nd; r++) {
                 const int o = go * cpc + posmod(q - r, cpc);

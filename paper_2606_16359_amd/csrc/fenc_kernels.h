@@ -694,6 +694,42 @@ struct GmacArgs {
 // weight table then holds the signed code itself (y unused).
 constexpr int kFastWBits = 23;
 
+constexpr int kMacChunk = 8;   // input words requested together
+
+// Term stream of a class: the input words of kMacChunk consecutive terms are
+// requested before any is used; body(k, word) runs per term in order and
+// end_group(g) after the last term of each group.
+template <class LD, class B, class E>
+FENC_HD inline void mac_stream(const GmacArgs& a, const MacClass& K, LD load_in, B body, E end_group) {
+  const int k0 = a.toff[K.g0], kend = a.toff[K.g0 + K.ng];
+  int g = K.g0, ge = a.toff[g + 1];
+  while (g < K.g0 + K.ng && ge == a.toff[g]) {   // empty leading groups
+    end_group(g);
+    g++;
+    ge = g < K.g0 + K.ng ? a.toff[g + 1] : kend;
+  }
+  for (int kb = k0; kb < kend; kb += kMacChunk) {
+    u64 v[kMacChunk];
+#pragma unroll
+    for (int j = 0; j < kMacChunk; j++) v[j] = kb + j < kend ? load_in(kb + j) : 0;
+#pragma unroll
+    for (int j = 0; j < kMacChunk; j++) {
+      const int k = kb + j;
+      if (k >= kend) break;
+      body(k, v[j]);
+      while (k + 1 == ge && g < K.g0 + K.ng) {   // group g ends here (and any empty ones after it)
+        end_group(g);
+        g++;
+        ge = g < K.g0 + K.ng ? a.toff[g + 1] : kend + 1;
+      }
+    }
+  }
+  while (g < K.g0 + K.ng) {   // trailing empty groups
+    end_group(g);
+    g++;
+  }
+}
+
 template <int W, bool PT, class X>
 FENC_HD void gmac_fast_w(X& x, const GmacArgs& a) {
   x.phase([&](int t) {
@@ -706,6 +742,7 @@ FENC_HD void gmac_fast_w(X& x, const GmacArgs& a) {
     const double t25 = 33554432.0, t25q = t25 * qi;   // 2^25 < q
     const long long off_a = poly * a.a_ps + i * N + c, off_b = poly * a.b_ps + i * N + c;
     const bool a_here = i < a.nl_a;
+    const int k0 = a.toff[K.g0];
     const d2* ew = a.ew + (long long)i * a.ews + K.w0;
     auto load_in = [&](int k) -> u64 {
       const int ti = a.tin[k];
@@ -714,52 +751,51 @@ FENC_HD void gmac_fast_w(X& x, const GmacArgs& a) {
     };
     double r[W], sh[W], sl[W];
 #pragma unroll
-    for (int o = 0; o < W; o++) r[o] = 0;
-    const int k0 = a.toff[K.g0], kend = a.toff[K.g0 + K.ng];
-    int k = k0;
-    u64 vn = k < kend ? load_in(k) : 0;
-    for (int g = K.g0; g < K.g0 + K.ng; g++) {
-#pragma unroll
-      for (int o = 0; o < W; o++) sh[o] = sl[o] = 0;
-      int n = 0;
-      for (const int ge = a.toff[g + 1]; k < ge; k++) {
-        const u64 v = vn;
-        if (k + 1 < kend) vn = load_in(k + 1);
-        const double vh = u2d(v >> 25), vl = u2d(v & 0x1FFFFFFull);
-        const d2* w = ew + (long long)(k - k0) * W;
-#pragma unroll
-        for (int o = 0; o < W; o++) {
-          sh[o] = fma(vh, w[o].x, sh[o]);
-          sl[o] = fma(vl, w[o].x, sl[o]);
-        }
-        if (++n == 16) {
+    for (int o = 0; o < W; o++) r[o] = sh[o] = sl[o] = 0;
+    int n = 0;
+    mac_stream(
+        a, K, load_in,
+        [&](int k, u64 v) {
+          const double vh = u2d(v >> 25), vl = u2d(v & 0x1FFFFFFull);
+          const d2* w = ew + (long long)(k - k0) * W;
 #pragma unroll
           for (int o = 0; o < W; o++) {
-            sh[o] = red(sh[o], q, qi);
-            sl[o] = red(sl[o], q, qi);
+            sh[o] = fma(vh, w[o].x, sh[o]);
+            sl[o] = fma(vl, w[o].x, sl[o]);
+          }
+          if (++n == 16) {
+#pragma unroll
+            for (int o = 0; o < W; o++) {
+              sh[o] = red(sh[o], q, qi);
+              sl[o] = red(sl[o], q, qi);
+            }
+            n = 0;
+          }
+        },
+        [&](int g) {
+          double sg[W];
+#pragma unroll
+          for (int o = 0; o < W; o++) {
+            sg[o] = red(mulmod_c(red(sh[o], q, qi), t25, t25q, q) + red(sl[o], q, qi), q, qi);
+            sh[o] = sl[o] = 0;
           }
           n = 0;
-        }
-      }
-      double sg[W];
+          if constexpr (PT) {
+            const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
+            double mv[W];
 #pragma unroll
-      for (int o = 0; o < W; o++) sg[o] = red(mulmod_c(red(sh[o], q, qi), t25, t25q, q) + red(sl[o], q, qi), q, qi);
-      if constexpr (PT) {
-        const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
-        double mv[W];
+            for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
 #pragma unroll
-        for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
+            for (int o = 0; o < W; o++) {
+              double s = sg[o];
+              if (mg[o]) s = mulmod(s, mv[o], q, qi);
+              r[o] = red(r[o] + s, q, qi);
+            }
+          } else {
 #pragma unroll
-        for (int o = 0; o < W; o++) {
-          double s = sg[o];
-          if (mg[o]) s = mulmod(s, mv[o], q, qi);
-          r[o] = red(r[o] + s, q, qi);
-        }
-      } else {
-#pragma unroll
-        for (int o = 0; o < W; o++) r[o] = red(r[o] + sg[o], q, qi);
-      }
-    }
+            for (int o = 0; o < W; o++) r[o] = red(r[o] + sg[o], q, qi);
+          }
+        });
 #pragma unroll
     for (int o = 0; o < W; o++) {
       if (o >= K.nout) continue;
@@ -779,51 +815,53 @@ FENC_HD void gmac_w(X& x, const GmacArgs& a) {
     const double q = a.pq[pi].x, qi = a.pq[pi].y;
     const long long off_a = poly * a.a_ps + i * N + c, off_b = poly * a.b_ps + i * N + c;
     const bool a_here = i < a.nl_a;
+    const int k0 = a.toff[K.g0];
     const d2* ew = a.ew + (long long)i * a.ews + K.w0;
-    auto load_in = [&](int k) {
+    auto load_in = [&](int k) -> u64 {
       const int ti = a.tin[k];
-      if (ti < a.na) return a_here ? u2d(a.in_a[ti * a.a_cs + off_a]) : 0.0;
-      return u2d(a.in_b[(ti - a.na) * a.b_cs + off_b]);
+      if (ti < a.na) return a_here ? a.in_a[ti * a.a_cs + off_a] : 0;
+      return a.in_b[(ti - a.na) * a.b_cs + off_b];
     };
     double r[W], sg[W];
 #pragma unroll
-    for (int o = 0; o < W; o++) r[o] = 0;
-    const int k0 = a.toff[K.g0], kend = a.toff[K.g0 + K.ng];
-    int k = k0;
-    double vn = k < kend ? load_in(k) : 0.0;
-    for (int g = K.g0; g < K.g0 + K.ng; g++) {
+    for (int o = 0; o < W; o++) r[o] = sg[o] = 0;
+    int n = 0;
+    mac_stream(
+        a, K, load_in,
+        [&](int k, u64 word) {
+          const double v = u2d(word);
+          const d2* w = ew + (long long)(k - k0) * W;
 #pragma unroll
-      for (int o = 0; o < W; o++) sg[o] = 0;
-      int n = 0;
-      for (const int ge = a.toff[g + 1]; k < ge; k++) {
-        const double v = vn;
-        if (k + 1 < kend) vn = load_in(k + 1);   // next term's word in flight during this one
-        const d2* w = ew + (long long)(k - k0) * W;
+          for (int o = 0; o < W; o++) sg[o] += mulmod_c(v, w[o].x, w[o].y, q);
+          if (++n == 5) {
 #pragma unroll
-        for (int o = 0; o < W; o++) sg[o] += mulmod_c(v, w[o].x, w[o].y, q);
-        if (++n == 5) {
-#pragma unroll
-          for (int o = 0; o < W; o++) sg[o] = red(sg[o], q, qi);
+            for (int o = 0; o < W; o++) sg[o] = red(sg[o], q, qi);
+            n = 0;
+          }
+        },
+        [&](int g) {
           n = 0;
-        }
-      }
-      if constexpr (PT) {
-        // every plaintext word of the group is requested before any is used
-        const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
-        double mv[W];
+          if constexpr (PT) {
+            // every plaintext word of the group is requested before any is used
+            const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
+            double mv[W];
 #pragma unroll
-        for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
+            for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
 #pragma unroll
-        for (int o = 0; o < W; o++) {
-          double s = red(sg[o], q, qi);
-          if (mg[o]) s = mulmod(s, mv[o], q, qi);
-          r[o] = red(r[o] + s, q, qi);
-        }
-      } else {
+            for (int o = 0; o < W; o++) {
+              double s = red(sg[o], q, qi);
+              if (mg[o]) s = mulmod(s, mv[o], q, qi);
+              r[o] = red(r[o] + s, q, qi);
+              sg[o] = 0;
+            }
+          } else {
 #pragma unroll
-        for (int o = 0; o < W; o++) r[o] = red(r[o] + red(sg[o], q, qi), q, qi);
-      }
-    }
+            for (int o = 0; o < W; o++) {
+              r[o] = red(r[o] + red(sg[o], q, qi), q, qi);
+              sg[o] = 0;
+            }
+          }
+        });
 #pragma unroll
     for (int o = 0; o < W; o++) {
       if (o >= K.nout) continue;
