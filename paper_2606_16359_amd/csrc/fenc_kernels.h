@@ -696,106 +696,115 @@ constexpr int kFastWBits = 23;
 
 constexpr int kMacChunk = 8;   // input words requested together
 
-// Term stream of a class: the input words of kMacChunk consecutive terms are
-// requested before any is used; body(k, word) runs per term in order and
-// end_group(g) after the last term of each group.
-template <class LD, class B, class E>
-FENC_HD inline void mac_stream(const GmacArgs& a, const MacClass& K, LD load_in, B body, E end_group) {
-  const int k0 = a.toff[K.g0], kend = a.toff[K.g0 + K.ng];
-  int g = K.g0, ge = a.toff[g + 1];
-  while (g < K.g0 + K.ng && ge == a.toff[g]) {   // empty leading groups
-    end_group(g);
-    g++;
-    ge = g < K.g0 + K.ng ? a.toff[g + 1] : kend;
-  }
-  for (int kb = k0; kb < kend; kb += kMacChunk) {
-    u64 v[kMacChunk];
+#ifndef FENC_AI
+#define FENC_AI __attribute__((always_inline)) inline
+#endif
+
+// End of group g: fold its sums into r (through the plaintext product for PT).
+// FAST: acc/acc2 hold the sums of hi*w and lo*w; otherwise acc holds the sum.
+template <int W, bool PT, bool FAST>
+FENC_HD FENC_AI void mac_end_group(const GmacArgs& a, const MacClass& K, int g, int i, long long N, long long c,
+                                   double q, double qi, double (&acc)[W], double (&acc2)[W], double (&r)[W]) {
+  const double t25 = 33554432.0, t25q = t25 * qi;   // 2^25 < q
+  const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
 #pragma unroll
-    for (int j = 0; j < kMacChunk; j++) v[j] = kb + j < kend ? load_in(kb + j) : 0;
+  for (int o0 = 0; o0 < W; o0 += 4) {   // plaintext words requested four at a time
+    double mv[4];
 #pragma unroll
-    for (int j = 0; j < kMacChunk; j++) {
-      const int k = kb + j;
-      if (k >= kend) break;
-      body(k, v[j]);
-      while (k + 1 == ge && g < K.g0 + K.ng) {   // group g ends here (and any empty ones after it)
-        end_group(g);
-        g++;
-        ge = g < K.g0 + K.ng ? a.toff[g + 1] : kend + 1;
+    for (int j = 0; j < 4; j++) {
+      const int o = o0 + j;
+      mv[j] = 0.0;
+      if constexpr (PT) {
+        if (o < W && mg[o]) mv[j] = u2d(mg[o][i * N + c]);
       }
     }
-  }
-  while (g < K.g0 + K.ng) {   // trailing empty groups
-    end_group(g);
-    g++;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int o = o0 + j;
+      if (o >= W) break;
+      double sv;
+      if constexpr (FAST) sv = red(mulmod_c(red(acc[o], q, qi), t25, t25q, q) + red(acc2[o], q, qi), q, qi);
+      else sv = red(acc[o], q, qi);
+      if constexpr (PT) {
+        if (mg[o]) sv = mulmod(sv, mv[j], q, qi);
+      }
+      r[o] = red(r[o] + sv, q, qi);
+      acc[o] = 0;
+      acc2[o] = 0;
+    }
   }
 }
 
-template <int W, bool PT, class X>
-FENC_HD void gmac_fast_w(X& x, const GmacArgs& a) {
-  x.phase([&](int t) {
+// One MAC kernel body for every form: W outputs per class row, PT plaintext
+// products, FAST small signed codes (see kFastWBits).  The terms of each group
+// are walked in chunks of up to kMacChunk whose input words are requested
+// together.
+template <int W, bool PT, bool FAST, class X>
+FENC_HD FENC_AI void gmac_body(X& x, const GmacArgs& a) {
+  x.phase([&](int t) __attribute__((always_inline)) {
     const long long N = 1LL << a.logn;
     const long long c = (long long)x.bx * x.nt + t;
     const int i = x.by, poly = x.bz & 1;
     const MacClass K = a.cls[a.c0 + (x.bz >> 1)];
     const int pi = a.eprime ? a.eprime[i] : i;
     const double q = a.pq[pi].x, qi = a.pq[pi].y;
-    const double t25 = 33554432.0, t25q = t25 * qi;   // 2^25 < q
     const long long off_a = poly * a.a_ps + i * N + c, off_b = poly * a.b_ps + i * N + c;
     const bool a_here = i < a.nl_a;
-    const int k0 = a.toff[K.g0];
+    const int k0 = a.toff[K.g0], gend = K.g0 + K.ng;
     const d2* ew = a.ew + (long long)i * a.ews + K.w0;
-    auto load_in = [&](int k) -> u64 {
-      const int ti = a.tin[k];
-      if (ti < a.na) return a_here ? a.in_a[ti * a.a_cs + off_a] : 0;
-      return a.in_b[(ti - a.na) * a.b_cs + off_b];
-    };
-    double r[W], sh[W], sl[W];
+    double r[W], acc[W], acc2[W];
 #pragma unroll
-    for (int o = 0; o < W; o++) r[o] = sh[o] = sl[o] = 0;
-    int n = 0;
-    mac_stream(
-        a, K, load_in,
-        [&](int k, u64 v) {
-          const double vh = u2d(v >> 25), vl = u2d(v & 0x1FFFFFFull);
-          const d2* w = ew + (long long)(k - k0) * W;
+    for (int o = 0; o < W; o++) r[o] = acc[o] = acc2[o] = 0;
+    int k = k0;
+    for (int g = K.g0; g < gend; g++) {
+      const int ge = a.toff[g + 1];
+      int n = 0;
+      while (k < ge) {
+        const int cnt = ge - k < kMacChunk ? ge - k : kMacChunk;
+        u64 v[kMacChunk];
 #pragma unroll
-          for (int o = 0; o < W; o++) {
-            sh[o] = fma(vh, w[o].x, sh[o]);
-            sl[o] = fma(vl, w[o].x, sl[o]);
+        for (int j = 0; j < kMacChunk; j++) {
+          v[j] = 0;
+          if (j < cnt) {
+            const int ti = a.tin[k + j];
+            if (ti < a.na) v[j] = a_here ? a.in_a[ti * a.a_cs + off_a] : 0;
+            else v[j] = a.in_b[(ti - a.na) * a.b_cs + off_b];
           }
-          if (++n == 16) {
+        }
+#pragma unroll
+        for (int j = 0; j < kMacChunk; j++) {
+          if (j >= cnt) break;
+          const d2* w = ew + (long long)(k + j - k0) * W;
+          if constexpr (FAST) {
+            const double vh = u2d(v[j] >> 25), vl = u2d(v[j] & 0x1FFFFFFull);
 #pragma unroll
             for (int o = 0; o < W; o++) {
-              sh[o] = red(sh[o], q, qi);
-              sl[o] = red(sl[o], q, qi);
+              acc[o] = fma(vh, w[o].x, acc[o]);
+              acc2[o] = fma(vl, w[o].x, acc2[o]);
             }
-            n = 0;
-          }
-        },
-        [&](int g) {
-          double sg[W];
+            if (++n == 16) {
 #pragma unroll
-          for (int o = 0; o < W; o++) {
-            sg[o] = red(mulmod_c(red(sh[o], q, qi), t25, t25q, q) + red(sl[o], q, qi), q, qi);
-            sh[o] = sl[o] = 0;
-          }
-          n = 0;
-          if constexpr (PT) {
-            const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
-            double mv[W];
-#pragma unroll
-            for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
-#pragma unroll
-            for (int o = 0; o < W; o++) {
-              double s = sg[o];
-              if (mg[o]) s = mulmod(s, mv[o], q, qi);
-              r[o] = red(r[o] + s, q, qi);
+              for (int o = 0; o < W; o++) {
+                acc[o] = red(acc[o], q, qi);
+                acc2[o] = red(acc2[o], q, qi);
+              }
+              n = 0;
             }
           } else {
+            const double vv = u2d(v[j]);
 #pragma unroll
-            for (int o = 0; o < W; o++) r[o] = red(r[o] + sg[o], q, qi);
+            for (int o = 0; o < W; o++) acc[o] += mulmod_c(vv, w[o].x, w[o].y, q);
+            if (++n == 5) {
+#pragma unroll
+              for (int o = 0; o < W; o++) acc[o] = red(acc[o], q, qi);
+              n = 0;
+            }
           }
-        });
+        }
+        k += cnt;
+      }
+      mac_end_group<W, PT, FAST>(a, K, g, i, N, c, q, qi, acc, acc2, r);
+    }
 #pragma unroll
     for (int o = 0; o < W; o++) {
       if (o >= K.nout) continue;
@@ -805,70 +814,9 @@ FENC_HD void gmac_fast_w(X& x, const GmacArgs& a) {
 }
 
 template <int W, bool PT, class X>
-FENC_HD void gmac_w(X& x, const GmacArgs& a) {
-  x.phase([&](int t) {
-    const long long N = 1LL << a.logn;
-    const long long c = (long long)x.bx * x.nt + t;
-    const int i = x.by, poly = x.bz & 1;
-    const MacClass K = a.cls[a.c0 + (x.bz >> 1)];
-    const int pi = a.eprime ? a.eprime[i] : i;
-    const double q = a.pq[pi].x, qi = a.pq[pi].y;
-    const long long off_a = poly * a.a_ps + i * N + c, off_b = poly * a.b_ps + i * N + c;
-    const bool a_here = i < a.nl_a;
-    const int k0 = a.toff[K.g0];
-    const d2* ew = a.ew + (long long)i * a.ews + K.w0;
-    auto load_in = [&](int k) -> u64 {
-      const int ti = a.tin[k];
-      if (ti < a.na) return a_here ? a.in_a[ti * a.a_cs + off_a] : 0;
-      return a.in_b[(ti - a.na) * a.b_cs + off_b];
-    };
-    double r[W], sg[W];
-#pragma unroll
-    for (int o = 0; o < W; o++) r[o] = sg[o] = 0;
-    int n = 0;
-    mac_stream(
-        a, K, load_in,
-        [&](int k, u64 word) {
-          const double v = u2d(word);
-          const d2* w = ew + (long long)(k - k0) * W;
-#pragma unroll
-          for (int o = 0; o < W; o++) sg[o] += mulmod_c(v, w[o].x, w[o].y, q);
-          if (++n == 5) {
-#pragma unroll
-            for (int o = 0; o < W; o++) sg[o] = red(sg[o], q, qi);
-            n = 0;
-          }
-        },
-        [&](int g) {
-          n = 0;
-          if constexpr (PT) {
-            // every plaintext word of the group is requested before any is used
-            const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
-            double mv[W];
-#pragma unroll
-            for (int o = 0; o < W; o++) mv[o] = mg[o] ? u2d(mg[o][i * N + c]) : 0.0;
-#pragma unroll
-            for (int o = 0; o < W; o++) {
-              double s = red(sg[o], q, qi);
-              if (mg[o]) s = mulmod(s, mv[o], q, qi);
-              r[o] = red(r[o] + s, q, qi);
-              sg[o] = 0;
-            }
-          } else {
-#pragma unroll
-            for (int o = 0; o < W; o++) {
-              r[o] = red(r[o] + red(sg[o], q, qi), q, qi);
-              sg[o] = 0;
-            }
-          }
-        });
-#pragma unroll
-    for (int o = 0; o < W; o++) {
-      if (o >= K.nout) continue;
-      a.out[a.cls_out[K.o0 + o] * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(r[o], q));
-    }
-  });
-}
+FENC_HD FENC_AI void gmac_fast_w(X& x, const GmacArgs& a) { gmac_body<W, PT, true>(x, a); }
+template <int W, bool PT, class X>
+FENC_HD FENC_AI void gmac_w(X& x, const GmacArgs& a) { gmac_body<W, PT, false>(x, a); }
 
 template <bool PT, bool FAST, class X>
 FENC_HD void gmac_any(X& x, const GmacArgs& a) {
