@@ -83,7 +83,7 @@ FENC_KERNEL_LDS(ntt_fwd_rows16, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_rows16, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_cols16, NttArgs)
 FENC_KERNEL(modup_fbc, ModUpArgs)
-FENC_KERNEL_XCD(kip, KipArgs)
+FENC_KERNEL(kip, KipArgs)
 FENC_KERNEL(moddown_fbc, ModDownArgs)
 FENC_KERNEL(moddown_tail, TailArgs)
 FENC_KERNEL(rescale_lift, LiftArgs)

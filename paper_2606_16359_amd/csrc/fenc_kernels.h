@@ -655,7 +655,7 @@ FENC_HD void lift_pq(X& x, const LiftPqArgs& a) {
 // Each input word is loaded once for all outputs of the class.  Input index
 // t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.  A null
 // plaintext means no product.
-constexpr int kMacOut = 16;
+constexpr int kMacOut = 8;
 
 struct MacClass {
   int g0, ng;        // groups g0 .. g0+ng-1 (terms shared by the outputs)
@@ -700,38 +700,23 @@ constexpr int kMacChunk = 8;   // input words requested together
 #define FENC_AI __attribute__((always_inline)) inline
 #endif
 
-// End of group g: fold its sums into r (through the plaintext product for PT).
-// FAST: acc/acc2 hold the sums of hi*w and lo*w; otherwise acc holds the sum.
+// End of group g: fold its sums into r (through the plaintext words mv for
+// PT).  FAST: acc/acc2 hold the sums of hi*w and lo*w; otherwise acc holds the sum.
 template <int W, bool PT, bool FAST>
-FENC_HD FENC_AI void mac_end_group(const GmacArgs& a, const MacClass& K, int g, int i, long long N, long long c,
-                                   double q, double qi, double (&acc)[W], double (&acc2)[W], double (&r)[W]) {
+FENC_HD FENC_AI void mac_end_group(const u64* const* mg, double q, double qi, const double (&mv)[W],
+                                   double (&acc)[W], double (&acc2)[W], double (&r)[W]) {
   const double t25 = 33554432.0, t25q = t25 * qi;   // 2^25 < q
-  const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
 #pragma unroll
-  for (int o0 = 0; o0 < W; o0 += 4) {   // plaintext words requested four at a time
-    double mv[4];
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int o = o0 + j;
-      mv[j] = 0.0;
-      if constexpr (PT) {
-        if (o < W && mg[o]) mv[j] = u2d(mg[o][i * N + c]);
-      }
+  for (int o = 0; o < W; o++) {
+    double sv;
+    if constexpr (FAST) sv = red(mulmod_c(red(acc[o], q, qi), t25, t25q, q) + red(acc2[o], q, qi), q, qi);
+    else sv = red(acc[o], q, qi);
+    if constexpr (PT) {
+      if (mg[o]) sv = mulmod(sv, mv[o], q, qi);
     }
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const int o = o0 + j;
-      if (o >= W) break;
-      double sv;
-      if constexpr (FAST) sv = red(mulmod_c(red(acc[o], q, qi), t25, t25q, q) + red(acc2[o], q, qi), q, qi);
-      else sv = red(acc[o], q, qi);
-      if constexpr (PT) {
-        if (mg[o]) sv = mulmod(sv, mv[j], q, qi);
-      }
-      r[o] = red(r[o] + sv, q, qi);
-      acc[o] = 0;
-      acc2[o] = 0;
-    }
+    r[o] = red(r[o] + sv, q, qi);
+    acc[o] = 0;
+    acc2[o] = 0;
   }
 }
 
@@ -759,6 +744,16 @@ FENC_HD FENC_AI void gmac_body(X& x, const GmacArgs& a) {
     for (int g = K.g0; g < gend; g++) {
       const int ge = a.toff[g + 1];
       int n = 0;
+      // the group's plaintext words are requested with its first input words
+      const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
+      double mv[W];
+#pragma unroll
+      for (int o = 0; o < W; o++) {
+        mv[o] = 0.0;
+        if constexpr (PT) {
+          if (mg[o]) mv[o] = u2d(mg[o][i * N + c]);
+        }
+      }
       while (k < ge) {
         const int cnt = ge - k < kMacChunk ? ge - k : kMacChunk;
         u64 v[kMacChunk];
@@ -803,7 +798,7 @@ FENC_HD FENC_AI void gmac_body(X& x, const GmacArgs& a) {
         }
         k += cnt;
       }
-      mac_end_group<W, PT, FAST>(a, K, g, i, N, c, q, qi, acc, acc2, r);
+      mac_end_group<W, PT, FAST>(mg, q, qi, mv, acc, acc2, r);
     }
 #pragma unroll
     for (int o = 0; o < W; o++) {

@@ -70,7 +70,7 @@ EMU_LDS(ntt_fwd_rows16, NttArgs)
 EMU_LDS(ntt_inv_rows16, NttArgs)
 EMU_LDS(ntt_inv_cols16, NttArgs)
 EMU(modup_fbc, ModUpArgs)
-EMU_XCD(kip, KipArgs)
+EMU(kip, KipArgs)
 EMU(moddown_fbc, ModDownArgs)
 EMU(moddown_tail, TailArgs)
 EMU(rescale_lift, LiftArgs)
