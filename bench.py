@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_fast", "gmac_pt_fast", "ntt_fwd_rows", "ntt_
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 856221501, "ntt_fwd_rows": 250323477, "moddown_tail": 371042899, "rescale_tail": 289028692, "ntt_inv_rows": 73469240, "ntt_inv_cols": 68093148, "modup_fbc": 256666639, "moddown_fbc": 151115177, "tensor_square": 477121650, "rescale_lift": 101859889}
+TRAFFIC = {"kip": 1319951745, "gmac_pt_fast": 543766284, "ntt_fwd_rows": 297354468, "ntt_fwd_cols16": 225668201, "moddown_tail": 371000460, "rescale_tail": 289029347, "ntt_inv_rows": 73507977, "ntt_inv_cols": 68093063, "modup_fbc": 256664117, "gmac_fast": 624035721, "moddown_fbc": 151105523, "tensor_square": 477119927, "lift_pq": 187012293, "rescale_lift": 101864016}
 
 
 def log(*a):
