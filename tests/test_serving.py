@@ -1,0 +1,108 @@
+"""Serving loop: requests of several tenants, continuously batched, give the
+same ciphertexts as each request run alone (batch groups never share a
+ciphertext), and decrypt to the float64 network."""
+import numpy as np
+import pytest
+
+from oracle import cnn_ref
+from paper_2606_16359_amd import serve as S
+from paper_2606_16359_amd import workloads as W
+
+from fenc_backends import BACKENDS, lib_path
+
+SMALL_NET = dict(params=(11, 12, 50, 4, 50, 3, 0, 0), shapes=[(4, 4, 3, 3), (8, 4, 3, 3), (8, 8, 3, 3)],
+                 strides=[1, 2, 1], in_shape=(4, 8, 8))
+
+
+def small_tenant(name, seed, backend, max_batch=2):
+    prm = list(SMALL_NET["params"])
+    prm[6] = 40
+    return S.Tenant(name, "cifar", seed, 2, max_batch, lib_path=lib_path(backend), params=prm,
+                    shapes=SMALL_NET["shapes"], strides=SMALL_NET["strides"], in_shape=SMALL_NET["in_shape"],
+                    block_size=2)
+
+
+def reference(t, x):
+    y = x
+    for wi, s in zip(t.w, t.strides):
+        y = np.polynomial.polynomial.polyval(cnn_ref.conv2d(y, wi, s, 1), W.CUBIC)
+    return y.reshape(x.shape[0], -1)
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_requests_batched_across_arrivals_match_each_alone(backend):
+    tenants = [small_tenant("a", 21, backend), small_tenant("b", 22, backend)]
+    srv = S.Server(tenants)
+    trace = [(0.0, "a", 1), (0.0, "b", 2), (0.0, "a", 2), (0.0, "a", 1), (0.0, "b", 1)]
+    reqs, xs = [], []
+    for i, (off, name, n) in enumerate(trace):
+        t = srv.tenants[name]
+        x = W.images((n,) + t.in_shape, seed=300 + i)
+        xs.append(x)
+        reqs.append((off, S.Request(i, name, n, t.encrypt_request(x, 900 + i))))
+    srv.serve(reqs)
+    assert len(srv.done) == len(trace)
+    assert max(b[1] for b in srv.batches) == 2            # at least one batch merged two requests
+    for (off, r), x in zip(reqs, xs):
+        t = srv.tenants[r.tenant]
+        mixed = t.fe.export(r.out)
+        alone = S.Request(r.rid, r.tenant, r.n_images, r.ct)
+        srv._run(t, [alone])
+        assert np.array_equal(t.fe.export(alone.out), mixed)
+        got = t.decrypt_request(r)
+        assert np.max(np.abs(got - reference(t, x))) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_admission_respects_the_memory_budget(backend):
+    t = small_tenant("a", 23, backend, max_batch=4)
+    x = W.images((1,) + t.in_shape, seed=5)
+    reqs = [S.Request(i, "a", 1, t.encrypt_request(x, 40 + i)) for i in range(4)]
+    fp = t.footprint(reqs[0].ct)
+    srv = S.Server([t], hbm_budget=2 * fp)                 # two requests fit at once
+    for r in reqs:
+        srv.submit(r)
+    first = srv._take(t)
+    assert len(first) == 2 and srv.in_flight == 2 * fp
+    assert srv._take(t) == []                               # nothing more fits until they finish
+    srv.in_flight = 0
+    assert len(srv._take(t)) == 2
+
+
+def test_poisson_trace_is_seeded_and_mixed():
+    a = S.poisson_trace(200, 1.0, {"x": 0.6, "y": 0.4}, {"x": (1, 64), "y": (1, 8)}, seed=3)
+    b = S.poisson_trace(200, 1.0, {"x": 0.6, "y": 0.4}, {"x": (1, 64), "y": (1, 8)}, seed=3)
+    assert a == b and 150 < len(a) < 250
+    assert all(0 < t <= 1.0 for t, _, _ in a) and all(a[i][0] < a[i + 1][0] for i in range(len(a) - 1))
+    assert {n for _, n, _ in a} == {"x", "y"} and all(1 <= k <= 8 for _, n, k in a if n == "y")
+
+
+@pytest.mark.gpu
+def test_lenet_tenants_served_in_batches_match_alone_at_full_size():
+    """Two LeNet-shaped tenants (N = 2^15, 64-image batch groups): ten requests
+    arriving together are served in merged batches; sampled requests are
+    bit-identical to their runs alone and decrypt to the float64 network."""
+    import torch
+    ts = [S.Tenant("l0", "lenet", 11, 64, 4), S.Tenant("l1", "lenet", 12, 64, 4)]
+    srv = S.Server(ts)
+    reqs, xs = [], []
+    for i in range(10):
+        t = ts[i % 2]
+        n = 1 + (7 * i) % 64
+        x = W.images((n, 1, 28, 28), seed=500 + i)
+        xs.append(x)
+        reqs.append((0.0, S.Request(i, t.name, n, t.encrypt_request(x, 700 + i))))
+    torch.cuda.synchronize()
+    srv.serve(reqs)
+    assert len(srv.done) == 10 and max(b[1] for b in srv.batches) > 1
+    for k in (0, 3, 8):
+        r, x = reqs[k][1], xs[k]
+        t = srv.tenants[r.tenant]
+        mixed = t.fe.export(r.out)
+        alone = S.Request(r.rid, r.tenant, r.n_images, r.ct)
+        srv._run(t, [alone])
+        assert np.array_equal(t.fe.export(alone.out), mixed)
+        want = cnn_ref.lenet(x, *t.w).reshape(r.n_images, -1)
+        assert np.max(np.abs(t.decrypt_request(r)[:, :want.shape[1]] - want)) < 1e-4
+    s = S.latency_summary(srv.done)
+    assert s["requests"] == 10 and s["p99_ms"] >= s["p50_ms"] > 0
