@@ -67,3 +67,29 @@ def cifar_forward(fenc, ct, w, strides=None, coeffs=CUBIC):
     for wi, s in zip(w, strides or CIFAR_STRIDES):
         y = fenc.poly_act(fenc.conv2d(y, wi, stride=s, pad=wi.shape[2] // 2), coeffs)
     return y
+
+
+# MobileNet-V1-shaped early blocks at ImageNet shape, each from a fresh encryption:
+#   A: 3x3 conv 3->32 stride 2;  B: depthwise 3x3 (32) + pointwise 32->64;
+#   C: depthwise 3x3 stride 2 (64) + pointwise 64->128;  a quadratic after each conv
+MOBILENET_BLOCKS = [
+    [dict(w=(32, 3, 3, 3), stride=2, pad=1, groups=1)],
+    [dict(w=(32, 1, 3, 3), stride=1, pad=1, groups=32), dict(w=(64, 32, 1, 1), stride=1, pad=0, groups=1)],
+    [dict(w=(64, 1, 3, 3), stride=2, pad=1, groups=64), dict(w=(128, 64, 1, 1), stride=1, pad=0, groups=1)],
+]
+# the input shape and the block size each block's fresh encryption uses
+MOBILENET_INPUTS = [((3, 224, 224), 2), ((32, 112, 112), 1), ((64, 112, 112), 2)]
+QUADRATIC = (0.1471, 0.5, 0.1196)   # a x^2 + b x + c of the ReLU-approximation kind
+
+
+def mobilenet_weights(seed=SEED_WEIGHTS):
+    return [weights([layer["w"] for layer in blk], seed=seed + i) for i, blk in enumerate(MOBILENET_BLOCKS)]
+
+
+def mobilenet_block(fenc, ct, blk, w, coeffs=QUADRATIC):
+    """One block on an encrypted batch: each conv followed by the quadratic."""
+    y = ct
+    for layer, wi in zip(blk, w):
+        y = fenc.poly_act(fenc.conv2d(y, wi, stride=layer["stride"], pad=layer["pad"], groups=layer["groups"]),
+                          coeffs)
+    return y

@@ -93,3 +93,32 @@ def test_cifar_stack_full_size_decrypts_to_float64():
         ref = np.polynomial.polynomial.polyval(cnn_ref.conv2d(ref, wi, s, 1), W.CUBIC)
     assert out.lay.level == 23 - 15
     assert np.max(np.abs(fe.decrypt(out) - ref)) < 1e-4
+
+
+def test_mobilenet_blocks_at_imagenet_shape_decrypt_to_float64():
+    """MobileNet-V1-shaped early blocks at 224x224 (N = 2^16, 24 limbs), each from
+    a fresh encryption of the float64 output of the previous block, 2 images."""
+    import time
+    import torch
+    from oracle import cnn_ref
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["cifar"])
+    ws = W.mobilenet_weights()
+    x = W.images((2, 3, 224, 224))
+    for b, (blk, w, ((c, h, wd), S)) in enumerate(zip(W.MOBILENET_BLOCKS, ws, W.MOBILENET_INPUTS)):
+        assert x.shape[1:] == (c, h, wd)
+        lay = fe.plan_layout(2, c, h, wd, blk[0]["w"][2], blk[0]["w"][0], S)
+        ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC + b)
+        t0 = time.time()
+        y = W.mobilenet_block(fe, ct, blk, w)
+        torch.cuda.synchronize()
+        print(f"block {b}: {lay.n_ct()} input cts, S={lay.S}, {time.time() - t0:.2f}s (first run)", flush=True)
+        ref = x
+        for layer, wi in zip(blk, w):
+            ref = np.polynomial.polynomial.polyval(
+                cnn_ref.conv2d(ref, wi, layer["stride"], layer["pad"], layer["groups"]), W.QUADRATIC)
+        got = fe.decrypt(y)
+        assert got.shape == ref.shape
+        assert np.max(np.abs(got - ref)) < 1e-4, (b, np.max(np.abs(got - ref)))
+        x = ref

@@ -158,6 +158,8 @@ def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
     dict(x=(2, 3, 8, 8), w=(5, 3, 3, 3), stride=1, pad=1, groups=1, S=1),    # outer rotations, ragged channels
     dict(x=(16, 2, 8, 8), w=(5, 2, 5, 5), stride=1, pad=0, groups=1, S=1),   # C' = 1: scalar MAC only
     dict(x=(1, 1, 12, 12), w=(6, 1, 5, 5), stride=1, pad=0, groups=1, S=1),  # replicated single channel
+    dict(x=(2, 4, 8, 8), w=(6, 4, 1, 1), stride=1, pad=0, groups=1, S=1),    # pointwise: outer rotations only
+    dict(x=(2, 4, 8, 8), w=(4, 1, 3, 3), stride=2, pad=1, groups=4, S=2),    # depthwise with stride
 ])
 @pytest.mark.parametrize("hoist", [1, 0])
 def test_conv_variants_bit_exact(backend, budget, case, hoist, orc):
