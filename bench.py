@@ -24,12 +24,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
-KERNELS = ["gmac", "gmac_pt", "gmac_fast", "gmac_pt_fast", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "moddown_tail",
+KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv_fast", "gmac_diag", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "moddown_tail",
            "moddown_fbc", "modup_fbc", "rescale_tail", "rescale_lift", "tensor_square", "lin_comb", "lift_pq"]
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1319951745, "gmac_pt_fast": 543766284, "ntt_fwd_rows": 297354468, "ntt_fwd_cols16": 225668201, "moddown_tail": 371000460, "rescale_tail": 289029347, "ntt_inv_rows": 73507977, "ntt_inv_cols": 68093063, "modup_fbc": 256664117, "gmac_fast": 624035721, "moddown_fbc": 151105523, "tensor_square": 477119927, "lift_pq": 187012293, "rescale_lift": 101864016}
+TRAFFIC = {"kip": 1319951745, "ntt_fwd_rows": 297354468, "ntt_fwd_cols16": 225668201, "moddown_tail": 371000460, "rescale_tail": 289029347, "ntt_inv_rows": 73507977, "ntt_inv_cols": 68093063, "modup_fbc": 256664117, "moddown_fbc": 151105523, "tensor_square": 477119927, "lift_pq": 187012293, "rescale_lift": 101864016}
 
 
 def log(*a):

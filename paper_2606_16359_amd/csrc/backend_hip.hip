@@ -4,6 +4,10 @@
 #include <string>
 
 #define FENC_HD __host__ __device__
+// device pass: table-held pointers are global memory (no generic/flat access)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FENC_GLOBAL __attribute__((address_space(1)))
+#endif
 #include "fenc_backend.h"
 
 namespace {
@@ -92,6 +96,9 @@ FENC_KERNEL_XCD(gmac, GmacArgs)
 FENC_KERNEL_XCD(gmac_pt, GmacArgs)
 FENC_KERNEL_XCD(gmac_fast, GmacArgs)
 FENC_KERNEL_XCD(gmac_pt_fast, GmacArgs)
+FENC_KERNEL_XCD(gmac_ptv, GmacArgs)
+FENC_KERNEL_XCD(gmac_ptv_fast, GmacArgs)
+FENC_KERNEL_XCD(gmac_diag, GmacArgs)
 FENC_KERNEL(tensor_square, SquareArgs)
 FENC_KERNEL(lift_pq, LiftPqArgs)
 FENC_KERNEL(lin_comb, LinArgs)

@@ -678,6 +678,8 @@ struct GmacArgs {
   const int* tin;            // [nterms] input index
   const d2* ew;              // [nl][ews] weight residues (w mod q, fl(w/q))
   long long ews;
+  const double* wc;          // [ews] signed weight codes of the small-code classes (any limb)
+  int chunk;                 // terms per chunk: kMacChunk or 4
   int nl, logn;
   const unsigned char* eprime;   // prime index of limb i (null: i)
   const d2* pq;
@@ -685,8 +687,7 @@ struct GmacArgs {
 
 // Grid (N/256, nl, 2 * classes): z = class * 2 + poly, launched in the
 // XCD-aware order so both polys and neighbouring classes of one tile share an
-// L2 (plaintexts and shared inputs are fetched once).  PT: the class has
-// plaintext products.
+// L2 (plaintexts and shared inputs are fetched once).
 // Classes whose weight codes are all below 2^23 in magnitude (split-scale
 // weights) take exact products without a modular reduction per term: the
 // input word is split into 25-bit halves, hi * w and lo * w are exact binary64
@@ -694,25 +695,114 @@ struct GmacArgs {
 // weight table then holds the signed code itself (y unused).
 constexpr int kFastWBits = 23;
 
-constexpr int kMacChunk = 8;   // input words requested together
+constexpr int kMacChunk = 8;   // input words requested together (classes with small groups: 4)
+
+// Plaintext products of a class: none, one plaintext per group shared by every
+// output of the class, or one per (group, output).
+enum { kPtNone = 0, kPtShared = 1, kPtEach = 2 };
 
 #ifndef FENC_AI
 #define FENC_AI __attribute__((always_inline)) inline
 #endif
 
-// End of group g: fold its sums into r (through the plaintext words mv for
-// PT).  FAST: acc/acc2 hold the sums of hi*w and lo*w; otherwise acc holds the sum.
-template <int W, bool PT, bool FAST>
-FENC_HD FENC_AI void mac_end_group(const u64* const* mg, double q, double qi, const double (&mv)[W],
+#ifndef FENC_GLOBAL
+#define FENC_GLOBAL
+#endif
+// Load through a device pointer known to address global memory.
+FENC_HD FENC_AI u64 ldg(const u64* p) { return *(const FENC_GLOBAL u64*)p; }
+
+// Requests the input words of terms k .. k+cnt-1 (cnt <= CH <= kMacChunk).  The term
+// table carries kMacChunk spare entries, so a whole chunk of indices is read
+// at once; every slot of the chunk issues one load (slots past cnt read the
+// word of input ts, which exists), so the loads in flight are counted exactly.
+// A inputs have no words at limbs >= nl_a: off_a then addresses limb 0, and
+// the weights of A terms are zero at those limbs.
+template <int CH>
+FENC_HD FENC_AI void mac_fetch(const GmacArgs& a, int k, int cnt, int ts, long long off_a, long long off_b,
+                               u64 (&v)[CH]) {
+  int ti[CH];
+#pragma unroll
+  for (int j = 0; j < CH; j++) ti[j] = a.tin[k + j];
+#pragma unroll
+  for (int j = 0; j < CH; j++) {
+    const int tj = j < cnt ? ti[j] : ts;
+    const u64* p = tj < a.na ? a.in_a + tj * a.a_cs + off_a : a.in_b + (tj - a.na) * a.b_cs + off_b;
+    v[j] = ldg(p);
+  }
+}
+
+// Requests the plaintext word(s) of one group (mg: its W plaintext pointers);
+// for a null plaintext the word at `safe` is read and never used.
+template <int W, int PTM>
+FENC_HD FENC_AI void mac_fetch_pt(const u64* const* mg, bool use, long long off, const u64* safe,
+                                  u64 (&m)[PTM == kPtEach ? W : 1]) {
+  constexpr int NM = PTM == kPtEach ? W : 1;
+#pragma unroll
+  for (int o = 0; o < NM; o++) {
+    const u64* p = use ? mg[o] : nullptr;
+    m[o] = ldg(p ? p + off : safe);
+  }
+}
+
+// Adds the cnt terms of one chunk (weights w[j * W + o]) into the group sums.
+// FAST: acc/acc2 hold the sums of hi*w and lo*w, reduced once more than
+// 16 - CH terms are in them (at most 16 unreduced products of < 2^48);
+// otherwise acc holds a sum of modular products reduced every 5 terms.
+template <int W, bool FAST, int CH>
+FENC_HD FENC_AI void mac_terms(const u64 (&v)[CH], int cnt, const d2* w, const double* wc, double q,
+                               double qi, int& n, double (&acc)[W], double (&acc2)[W]) {
+#pragma unroll
+  for (int j = 0; j < CH; j++) {
+    if (j >= cnt) break;
+    if constexpr (FAST) {
+      const double* cj = wc + j * W;
+      const double vh = u2d(v[j] >> 25), vl = u2d(v[j] & 0x1FFFFFFull);
+#pragma unroll
+      for (int o = 0; o < W; o++) {
+        acc[o] = fma(vh, cj[o], acc[o]);
+        acc2[o] = fma(vl, cj[o], acc2[o]);
+      }
+    } else {
+      const d2* wj = w + j * W;
+      const double vv = u2d(v[j]);
+#pragma unroll
+      for (int o = 0; o < W; o++) acc[o] += mulmod_c(vv, wj[o].x, wj[o].y, q);
+      if (++n == 5) {
+#pragma unroll
+        for (int o = 0; o < W; o++) acc[o] = red(acc[o], q, qi);
+        n = 0;
+      }
+    }
+  }
+  if constexpr (FAST) {
+    n += cnt;
+    if (n > 16 - CH) {
+#pragma unroll
+      for (int o = 0; o < W; o++) {
+        acc[o] = red(acc[o], q, qi);
+        acc2[o] = red(acc2[o], q, qi);
+      }
+      n = 0;
+    }
+  }
+}
+
+// End of a group: fold its sums into r, through its plaintext word(s) m.
+template <int W, int PTM, bool FAST>
+FENC_HD FENC_AI void mac_end_group(const u64* const* mg, double q, double qi, const u64 (&m)[PTM == kPtEach ? W : 1],
                                    double (&acc)[W], double (&acc2)[W], double (&r)[W]) {
   const double t25 = 33554432.0, t25q = t25 * qi;   // 2^25 < q
+  double ms = 0;
+  if constexpr (PTM == kPtShared) ms = u2d(m[0]);
 #pragma unroll
   for (int o = 0; o < W; o++) {
     double sv;
     if constexpr (FAST) sv = red(mulmod_c(red(acc[o], q, qi), t25, t25q, q) + red(acc2[o], q, qi), q, qi);
     else sv = red(acc[o], q, qi);
-    if constexpr (PT) {
-      if (mg[o]) sv = mulmod(sv, mv[o], q, qi);
+    if constexpr (PTM == kPtShared) {
+      if (mg[0]) sv = mulmod(sv, ms, q, qi);
+    } else if constexpr (PTM == kPtEach) {
+      if (mg[o]) sv = mulmod(sv, u2d(m[o]), q, qi);
     }
     r[o] = red(r[o] + sv, q, qi);
     acc[o] = 0;
@@ -720,120 +810,245 @@ FENC_HD FENC_AI void mac_end_group(const u64* const* mg, double q, double qi, co
   }
 }
 
-// One MAC kernel body for every form: W outputs per class row, PT plaintext
-// products, FAST small signed codes (see kFastWBits).  The terms of each group
-// are walked in chunks of up to kMacChunk whose input words are requested
-// together.
-template <int W, bool PT, bool FAST, class X>
+// Common set-up of a MAC thread: its coefficient, limb, poly and class.
+struct MacThread {
+  long long N, c, off_a, off_b, off_pt;
+  int i, poly, k0, gend, nterm;
+  int ts;              // first term's input: the spare loads read its word
+  const u64* safe;     // address of that word
+  bool a_here;
+  double q, qi;
+  MacClass K;
+};
+
+template <class X>
+FENC_HD FENC_AI MacThread mac_thread(X& x, int t, const GmacArgs& a) {
+  MacThread m;
+  m.N = 1LL << a.logn;
+  m.c = (long long)x.bx * x.nt + t;
+  m.i = x.by;
+  m.poly = x.bz & 1;
+  m.K = a.cls[a.c0 + (x.bz >> 1)];
+  const int pi = a.eprime ? a.eprime[m.i] : m.i;
+  m.q = a.pq[pi].x;
+  m.qi = a.pq[pi].y;
+  m.a_here = m.i < a.nl_a;
+  m.off_a = m.poly * a.a_ps + (m.a_here ? m.i * m.N : 0) + m.c;
+  m.off_b = m.poly * a.b_ps + m.i * m.N + m.c;
+  m.off_pt = m.i * m.N + m.c;
+  m.gend = m.K.g0 + m.K.ng;
+  m.k0 = m.K.ng > 0 ? a.toff[m.K.g0] : 0;
+  m.nterm = m.K.ng > 0 ? a.toff[m.gend] - m.k0 : 0;
+  m.ts = a.tin[m.k0];
+  m.safe = m.ts < a.na ? a.in_a + m.ts * a.a_cs + m.off_a : a.in_b + (m.ts - a.na) * a.b_cs + m.off_b;
+  return m;
+}
+
+template <int W, class X>
+FENC_HD FENC_AI void mac_store(const GmacArgs& a, const MacThread& m, const double (&r)[W]) {
+#pragma unroll
+  for (int o = 0; o < W; o++) {
+    if (o >= m.K.nout) continue;
+    a.out[a.cls_out[m.K.o0 + o] * a.out_cs + m.poly * a.out_ps + m.i * m.N + m.c] = d2u(norm(r[o], m.q));
+  }
+}
+
+// One MAC kernel body for the general forms: W outputs per class row, PTM
+// plaintext products, FAST small signed codes (see kFastWBits).  The terms of
+// each group are walked in chunks of up to CH, in two alternating
+// buffers: the words of the next chunk (with its group's plaintext words when
+// it ends its group) are requested before the current chunk is used.
+template <int W, int PTM, int CH>
+struct MacBuf {
+  u64 v[CH];
+  u64 m[PTM == kPtEach ? W : 1];
+};
+
+// Walk state of one MAC thread: the chunk (g, k) of group g ending at ge, the
+// unreduced term count n and the sums.
+template <int W>
+struct MacState {
+  MacThread T;
+  const d2* ew;
+  const double* wc;
+  const u64* const* mk;
+  int g, k, ge, n;
+  bool done;
+  double r[W], acc[W], acc2[W];
+};
+
+// Requests chunk (g, k) of group g ending at ge (with the group's plaintext
+// words when the chunk ends the group).
+template <int W, int PTM, int CH>
+FENC_HD FENC_AI void mac_chunk_fetch(const GmacArgs& a, const MacState<W>& S, MacBuf<W, PTM, CH>& b, int g, int k,
+                                     int ge) {
+  const int cnt = ge - k < CH ? ge - k : CH;
+  mac_fetch(a, k, cnt, S.T.ts, S.T.off_a, S.T.off_b, b.v);
+  if constexpr (PTM != kPtNone)
+    mac_fetch_pt<W, PTM>(S.mk + (long long)(g - S.T.K.g0) * W, k + cnt >= ge, S.T.off_pt, S.T.safe, b.m);
+}
+
+// Requests the next chunk into nxt (past the class end, the first chunk again,
+// never used), then adds the current chunk cur and closes its group if it ends.
+template <int W, int PTM, bool FAST, int CH>
+FENC_HD FENC_AI void mac_step(const GmacArgs& a, MacState<W>& S, const MacBuf<W, PTM, CH>& cur,
+                              MacBuf<W, PTM, CH>& nxt) {
+  const int cnt = S.ge - S.k < CH ? S.ge - S.k : CH;
+  const bool last = S.k + cnt >= S.ge;
+  int kn = S.k + cnt, gn = S.g, gen = S.ge;
+  if (last) {
+    gn = S.g + 1;
+    if (gn < S.T.gend) gen = a.toff[gn + 1];
+  }
+  const bool more = gn < S.T.gend;
+  if (more) mac_chunk_fetch(a, S, nxt, gn, kn, gen);
+  else mac_chunk_fetch(a, S, nxt, S.T.K.g0, S.T.k0, S.T.k0);
+  const long long w = (long long)(S.k - S.T.k0) * W;
+  mac_terms<W, FAST, CH>(cur.v, cnt, S.ew + w, S.wc + w, S.T.q, S.T.qi, S.n, S.acc, S.acc2);
+  if (last) {
+    mac_end_group<W, PTM, FAST>(S.mk + (long long)(S.g - S.T.K.g0) * W, S.T.q, S.T.qi, cur.m, S.acc, S.acc2, S.r);
+    S.n = 0;
+  }
+  S.k = kn;
+  S.g = gn;
+  S.ge = gen;
+  S.done = !more;
+}
+
+template <int W, int PTM, bool FAST, int CH, class X>
 FENC_HD FENC_AI void gmac_body(X& x, const GmacArgs& a) {
   x.phase([&](int t) __attribute__((always_inline)) {
-    const long long N = 1LL << a.logn;
-    const long long c = (long long)x.bx * x.nt + t;
-    const int i = x.by, poly = x.bz & 1;
-    const MacClass K = a.cls[a.c0 + (x.bz >> 1)];
-    const int pi = a.eprime ? a.eprime[i] : i;
-    const double q = a.pq[pi].x, qi = a.pq[pi].y;
-    const long long off_a = poly * a.a_ps + i * N + c, off_b = poly * a.b_ps + i * N + c;
-    const bool a_here = i < a.nl_a;
-    const int k0 = a.toff[K.g0], gend = K.g0 + K.ng;
-    const d2* ew = a.ew + (long long)i * a.ews + K.w0;
-    double r[W], acc[W], acc2[W];
+    MacState<W> S;
+    S.T = mac_thread(x, t, a);
+    S.ew = a.ew + (long long)S.T.i * a.ews + S.T.K.w0;
+    S.wc = a.wc + S.T.K.w0;
+    S.mk = a.mask + S.T.K.m0;
 #pragma unroll
-    for (int o = 0; o < W; o++) r[o] = acc[o] = acc2[o] = 0;
-    int k = k0;
-    for (int g = K.g0; g < gend; g++) {
-      const int ge = a.toff[g + 1];
-      int n = 0;
-      // the group's plaintext words are requested with its first input words
-      const u64* const* mg = a.mask + K.m0 + (long long)(g - K.g0) * W;
-      double mv[W];
-#pragma unroll
-      for (int o = 0; o < W; o++) {
-        mv[o] = 0.0;
-        if constexpr (PT) {
-          if (mg[o]) mv[o] = u2d(mg[o][i * N + c]);
-        }
+    for (int o = 0; o < W; o++) S.r[o] = S.acc[o] = S.acc2[o] = 0;
+    if (S.T.nterm > 0) {
+      S.g = S.T.K.g0;
+      S.k = S.T.k0;
+      S.ge = a.toff[S.g + 1];
+      S.n = 0;
+      S.done = false;
+      MacBuf<W, PTM, CH> A, B;
+      mac_chunk_fetch(a, S, A, S.g, S.k, S.ge);
+      for (;;) {
+        mac_step<W, PTM, FAST, CH>(a, S, A, B);
+        if (S.done) break;
+        mac_step<W, PTM, FAST, CH>(a, S, B, A);
+        if (S.done) break;
       }
-      while (k < ge) {
-        const int cnt = ge - k < kMacChunk ? ge - k : kMacChunk;
-        u64 v[kMacChunk];
-#pragma unroll
-        for (int j = 0; j < kMacChunk; j++) {
-          v[j] = 0;
-          if (j < cnt) {
-            const int ti = a.tin[k + j];
-            if (ti < a.na) v[j] = a_here ? a.in_a[ti * a.a_cs + off_a] : 0;
-            else v[j] = a.in_b[(ti - a.na) * a.b_cs + off_b];
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < kMacChunk; j++) {
-          if (j >= cnt) break;
-          const d2* w = ew + (long long)(k + j - k0) * W;
-          if constexpr (FAST) {
-            const double vh = u2d(v[j] >> 25), vl = u2d(v[j] & 0x1FFFFFFull);
-#pragma unroll
-            for (int o = 0; o < W; o++) {
-              acc[o] = fma(vh, w[o].x, acc[o]);
-              acc2[o] = fma(vl, w[o].x, acc2[o]);
-            }
-            if (++n == 16) {
-#pragma unroll
-              for (int o = 0; o < W; o++) {
-                acc[o] = red(acc[o], q, qi);
-                acc2[o] = red(acc2[o], q, qi);
-              }
-              n = 0;
-            }
-          } else {
-            const double vv = u2d(v[j]);
-#pragma unroll
-            for (int o = 0; o < W; o++) acc[o] += mulmod_c(vv, w[o].x, w[o].y, q);
-            if (++n == 5) {
-#pragma unroll
-              for (int o = 0; o < W; o++) acc[o] = red(acc[o], q, qi);
-              n = 0;
-            }
-          }
-        }
-        k += cnt;
-      }
-      mac_end_group<W, PT, FAST>(mg, q, qi, mv, acc, acc2, r);
     }
-#pragma unroll
-    for (int o = 0; o < W; o++) {
-      if (o >= K.nout) continue;
-      a.out[a.cls_out[K.o0 + o] * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(r[o], q));
-    }
+    mac_store<W, X>(a, S.T, S.r);
   });
 }
 
-template <int W, bool PT, class X>
-FENC_HD FENC_AI void gmac_fast_w(X& x, const GmacArgs& a) { gmac_body<W, PT, true>(x, a); }
-template <int W, bool PT, class X>
-FENC_HD FENC_AI void gmac_w(X& x, const GmacArgs& a) { gmac_body<W, PT, false>(x, a); }
+// Diagonal form: every group is one term of weight 1 with its own plaintext
+// per output (materialised diagonals, FC diagonals, compress masks):
+//   out_o = sum_g pt_{g,o} (.) in_g
+// Groups alternate between two buffers: the next group's input and plaintext
+// words are requested before the current group's products.  The sums are
+// reduced every 4 groups (|r| < q/2 + 4q).
+template <int W>
+struct DiagBuf {
+  u64 v[1];
+  u64 m[W];
+};
 
-template <bool PT, bool FAST, class X>
-FENC_HD void gmac_any(X& x, const GmacArgs& a) {
-  switch (a.width) {
-    case 1: FAST ? gmac_fast_w<1, PT>(x, a) : gmac_w<1, PT>(x, a); break;
-    case 2: FAST ? gmac_fast_w<2, PT>(x, a) : gmac_w<2, PT>(x, a); break;
-    case 4: FAST ? gmac_fast_w<4, PT>(x, a) : gmac_w<4, PT>(x, a); break;
-    case 8: FAST ? gmac_fast_w<8, PT>(x, a) : gmac_w<8, PT>(x, a); break;
-    default: FAST ? gmac_fast_w<kMacOut, PT>(x, a) : gmac_w<kMacOut, PT>(x, a); break;
+template <int W>
+FENC_HD FENC_AI void diag_fetch(const GmacArgs& a, const MacThread& T, const u64* const* mk, int g, DiagBuf<W>& b) {
+  mac_fetch(a, a.toff[g], 1, T.ts, T.off_a, T.off_b, b.v);
+  mac_fetch_pt<W, kPtEach>(mk + (long long)(g - T.K.g0) * W, true, T.off_pt, T.safe, b.m);
+}
+
+// Adds group g from cur after requesting group g + 1 (past the class end, the
+// first group again, never used) into nxt.
+template <int W>
+FENC_HD FENC_AI bool diag_step(const GmacArgs& a, const MacThread& T, const u64* const* mk, int& g, int& n,
+                               const DiagBuf<W>& cur, DiagBuf<W>& nxt, double (&r)[W]) {
+  const bool more = g + 1 < T.gend;
+  diag_fetch(a, T, mk, more ? g + 1 : T.K.g0, nxt);
+  const double vv = u2d(cur.v[0]);
+#pragma unroll
+  for (int o = 0; o < W; o++) r[o] += mulmod(vv, u2d(cur.m[o]), T.q, T.qi);
+  if (++n == 4) {
+#pragma unroll
+    for (int o = 0; o < W; o++) r[o] = red(r[o], T.q, T.qi);
+    n = 0;
   }
+  g++;
+  return more;
+}
+
+template <int W, class X>
+FENC_HD FENC_AI void gmac_diag_body(X& x, const GmacArgs& a) {
+  x.phase([&](int t) __attribute__((always_inline)) {
+    const MacThread T = mac_thread(x, t, a);
+    const u64* const* mk = a.mask + T.K.m0;
+    double r[W];
+#pragma unroll
+    for (int o = 0; o < W; o++) r[o] = 0;
+    if (T.nterm > 0) {
+      DiagBuf<W> A, B;
+      int g = T.K.g0, n = 0;
+      diag_fetch(a, T, mk, g, A);
+      for (;;) {
+        if (!diag_step(a, T, mk, g, n, A, B, r)) break;
+        if (!diag_step(a, T, mk, g, n, B, A, r)) break;
+      }
+#pragma unroll
+      for (int o = 0; o < W; o++) r[o] = red(r[o], T.q, T.qi);
+    }
+    mac_store<W, X>(a, T, r);
+  });
+}
+
+// Classes with one plaintext per (group, output) hold at most kMacOutEach
+// outputs (their plaintext words take registers per output).
+constexpr int kMacOutEach = 4;
+
+template <int PTM, bool FAST, int CH, class X>
+FENC_HD FENC_AI void gmac_width(X& x, const GmacArgs& a) {
+  constexpr int WMAX = PTM == kPtEach ? kMacOutEach : kMacOut;
+  switch (a.width) {
+    case 1: gmac_body<1, PTM, FAST, CH>(x, a); break;
+    case 2: gmac_body<2, PTM, FAST, CH>(x, a); break;
+    case 4: gmac_body<4, PTM, FAST, CH>(x, a); break;
+    default: gmac_body<WMAX, PTM, FAST, CH>(x, a); break;
+  }
+}
+template <int PTM, bool FAST, class X>
+FENC_HD void gmac_any(X& x, const GmacArgs& a) {
+  if (a.chunk == kMacChunk) gmac_width<PTM, FAST, kMacChunk>(x, a);
+  else gmac_width<PTM, FAST, 4>(x, a);
 }
 // classes without plaintext products
 template <class X>
-FENC_HD void gmac(X& x, const GmacArgs& a) { gmac_any<false, false>(x, a); }
-// classes with plaintext products (null entries allowed)
+FENC_HD void gmac(X& x, const GmacArgs& a) { gmac_any<kPtNone, false>(x, a); }
+// one plaintext per group for the whole class
 template <class X>
-FENC_HD void gmac_pt(X& x, const GmacArgs& a) { gmac_any<true, false>(x, a); }
-// the same with small weight codes (|code| < 2^23)
+FENC_HD void gmac_pt(X& x, const GmacArgs& a) { gmac_any<kPtShared, false>(x, a); }
+// one plaintext per (group, output)
 template <class X>
-FENC_HD void gmac_fast(X& x, const GmacArgs& a) { gmac_any<false, true>(x, a); }
+FENC_HD void gmac_ptv(X& x, const GmacArgs& a) { gmac_any<kPtEach, false>(x, a); }
+// the same three with small weight codes (|code| < 2^23)
 template <class X>
-FENC_HD void gmac_pt_fast(X& x, const GmacArgs& a) { gmac_any<true, true>(x, a); }
+FENC_HD void gmac_fast(X& x, const GmacArgs& a) { gmac_any<kPtNone, true>(x, a); }
+template <class X>
+FENC_HD void gmac_pt_fast(X& x, const GmacArgs& a) { gmac_any<kPtShared, true>(x, a); }
+template <class X>
+FENC_HD void gmac_ptv_fast(X& x, const GmacArgs& a) { gmac_any<kPtEach, true>(x, a); }
+// diagonal classes
+template <class X>
+FENC_HD void gmac_diag(X& x, const GmacArgs& a) {
+  switch (a.width) {
+    case 1: gmac_diag_body<1>(x, a); break;
+    case 2: gmac_diag_body<2>(x, a); break;
+    case 4: gmac_diag_body<4>(x, a); break;
+    default: gmac_diag_body<kMacOut>(x, a); break;
+  }
+}
 
 // ------------------------------------------------------------------ tensor / key / encryption
 // Tensor product of ciphertexts a and b (b == a for a square), times the

@@ -602,6 +602,7 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
   a.tin = M.tin;
   a.ew = M.ew;
   a.ews = M.ews;
+  a.wc = M.wc;
   a.nl = nlimbs;
   a.logn = C.logn;
   a.eprime = g.pq ? g.eprime : nullptr;
@@ -613,19 +614,18 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
     for (int it = 0; it < steps; it++) {
       a.c0 = sg.c0 + (per_op ? it : 0);
       a.width = sg.width;
+      a.chunk = sg.chunk;
       const int nc = per_op ? 1 : sg.n;
       const double gb = sg.words / sg.n * nc * nl * C.N * 8;
       const fb::Grid grid{(unsigned)(C.N / block_threads(C)), (unsigned)nl, (unsigned)(2 * nc)};
-      timed(C, sg.fast ? (sg.pt ? "gmac_pt_fast" : "gmac_fast") : (sg.pt ? "gmac_pt" : "gmac"), gb, s, [&] {
-        if (sg.fast) {
-          if (sg.pt) fb::gmac_pt_fast(grid, block_threads(C), s, a);
-          else fb::gmac_fast(grid, block_threads(C), s, a);
-        } else if (sg.pt) {
-          fb::gmac_pt(grid, block_threads(C), s, a);
-        } else {
-          fb::gmac(grid, block_threads(C), s, a);
-        }
-      });
+      static const char* const names[2][3] = {{"gmac", "gmac_pt", "gmac_ptv"},
+                                                {"gmac_fast", "gmac_pt_fast", "gmac_ptv_fast"}};
+      typedef void (*Launch)(fb::Grid, int, fb::Stream, const fk::GmacArgs&);
+      static const Launch launch[2][3] = {{fb::gmac, fb::gmac_pt, fb::gmac_ptv},
+                                          {fb::gmac_fast, fb::gmac_pt_fast, fb::gmac_ptv_fast}};
+      const char* name = sg.diag ? "gmac_diag" : names[sg.fast][sg.ptm];
+      const Launch fn = sg.diag ? fb::gmac_diag : launch[sg.fast][sg.ptm];
+      timed(C, name, gb, s, [&] { fn(grid, block_threads(C), s, a); });
       C.cnt.launches += 1;
     }
   }
@@ -722,11 +722,27 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
     while (w < n) w <<= 1;
     return w;
   };
-  auto has_pt = [&](const std::vector<int>& mem) {
+  // plaintext form of a class: none, the same plaintext for every member in
+  // each group, or one per (group, member)
+  auto ptm_of = [&](const std::vector<int>& mem) {
+    bool any = false, shared = true;
+    for (int gr = 0; gr < b.goff[mem[0] + 1] - b.goff[mem[0]]; gr++)
+      for (int o : mem) {
+        any = any || b.mask[b.goff[o] + gr];
+        shared = shared && b.mask[b.goff[o] + gr] == b.mask[b.goff[mem[0]] + gr];
+      }
+    return !any ? (int)fk::kPtNone : shared ? (int)fk::kPtShared : (int)fk::kPtEach;
+  };
+  // diagonal class: every group one term of weight 1 and a plaintext for every member
+  auto is_diag = [&](const std::vector<int>& mem) {
     for (int o : mem)
-      for (int g = b.goff[o]; g < b.goff[o + 1]; g++)
-        if (b.mask[g]) return true;
-    return false;
+      for (int g = b.goff[o]; g < b.goff[o + 1]; g++) {
+        if (!b.mask[g] || b.toff[g + 1] - b.toff[g] != 1) return false;
+        const int k = b.toff[g];
+        if (pq && b.tin[k] < na) return false;   // A terms carry the factor P
+        if (b.tw[k] >= 0 && wcodes[b.tw[k]] != 1) return false;
+      }
+    return true;
   };
   const int64_t fast_lim = 1LL << fk::kFastWBits;
   auto is_fast = [&](const std::vector<int>& mem) {
@@ -738,9 +754,28 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
       }
     return true;
   };
-  auto seg_key = [&](const std::vector<int>& m) {
-    return std::make_tuple(width_of((int)m.size()), (int)has_pt(m), (int)is_fast(m));
+  auto chunk_of = [&](const std::vector<int>& m) {
+    const int ng = b.goff[m[0] + 1] - b.goff[m[0]];
+    const int nt = b.toff[b.goff[m[0] + 1]] - b.toff[b.goff[m[0]]];
+    return nt >= 6 * ng ? fk::kMacChunk : 4;
   };
+  auto seg_key = [&](const std::vector<int>& m) {
+    const bool dg = is_diag(m);
+    return std::make_tuple(width_of((int)m.size()), dg ? (int)fk::kPtEach : ptm_of(m), (int)dg,
+                           (int)(!dg && is_fast(m)), chunk_of(m));
+  };
+  {   // classes with a plaintext per (group, output) hold at most kMacOutEach outputs
+    std::vector<std::vector<int>> split;
+    for (auto& mem : members) {
+      if ((int)mem.size() <= fk::kMacOutEach || is_diag(mem) || ptm_of(mem) != fk::kPtEach) {
+        split.push_back(mem);
+        continue;
+      }
+      for (size_t o = 0; o < mem.size(); o += fk::kMacOutEach)
+        split.push_back(std::vector<int>(mem.begin() + o, mem.begin() + std::min(mem.size(), o + fk::kMacOutEach)));
+    }
+    members.swap(split);
+  }
   std::stable_sort(members.begin(), members.end(), [&](const std::vector<int>& x, const std::vector<int>& y) {
     return seg_key(x) < seg_key(y);
   });
@@ -754,9 +789,11 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
   int ngroups = 0;
   for (auto& mem : members) {
     const int rep = mem[0], no = (int)mem.size(), W = width_of(no);
-    const bool pt = has_pt(mem), fast = is_fast(mem);
-    if (T.seg.empty() || T.seg.back().width != W || T.seg.back().pt != pt || T.seg.back().fast != fast)
-      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, pt, fast, 0.0});
+    const bool diag = is_diag(mem), fast = !diag && is_fast(mem);
+    const int ptm = diag ? (int)fk::kPtEach : ptm_of(mem), chunk = chunk_of(mem);
+    if (T.seg.empty() || T.seg.back().width != W || T.seg.back().ptm != ptm || T.seg.back().diag != diag ||
+        T.seg.back().fast != fast || T.seg.back().chunk != chunk)
+      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, ptm, diag, fast, chunk, 0.0});
     for (int r = 0; r < b.toff[b.goff[rep + 1]] - b.toff[b.goff[rep]]; r++)
       for (int o = 0; o < W; o++) wfast.push_back(fast);
     MacSeg& sg = T.seg.back();
@@ -796,6 +833,7 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
     cls.push_back(K);
   }
   T.n = (int)cls.size();
+  tin.resize(tin.size() + fk::kMacChunk, 0);   // whole chunks of indices are read at once
   T.cls = upload(C, cls, owner);
   T.cls_out = upload(C, cls_out, owner);
   T.mask = (const uint64_t**)upload(C, mask, owner);
@@ -822,6 +860,10 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
     }
   }
   T.ew = upload(C, ew, owner);
+  std::vector<double> wc(T.ews, 0.0);
+  for (size_t k = 0; k < wi.size(); k++)
+    if (wfast[k]) wc[k] = (double)(wi[k] == kZero ? 0 : wi[k] < 0 ? 1 : wcodes[wi[k]]);
+  T.wc = upload(C, wc, owner);
   return T;
 }
 

@@ -101,8 +101,10 @@ struct KsStage {
 // width; a segment is the classes of one width.
 struct MacSeg {
   int c0, n, width;
-  bool pt;                         // classes with plaintext products
+  int ptm;                         // plaintext products: none, one per group, one per (group, output)
+  bool diag;                       // every group one term of weight 1 with its own plaintexts
   bool fast;                       // every weight code below 2^23 in magnitude
+  int chunk;                       // terms per chunk: 8, or 4 for groups of under 6 terms on average
   double words;                    // words per (coefficient, limb) moved by the segment's classes
 };
 struct MacTables {
@@ -115,6 +117,7 @@ struct MacTables {
   int* tin = nullptr;
   d2* ew = nullptr;                // [nl][ews] weight residues
   long long ews = 0;
+  double* wc = nullptr;            // [ews] signed codes of the small-code classes
 };
 struct GmacStage {
   int n_out = 0;

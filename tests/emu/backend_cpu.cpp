@@ -79,6 +79,9 @@ EMU_XCD(gmac, GmacArgs)
 EMU_XCD(gmac_pt, GmacArgs)
 EMU_XCD(gmac_fast, GmacArgs)
 EMU_XCD(gmac_pt_fast, GmacArgs)
+EMU_XCD(gmac_ptv, GmacArgs)
+EMU_XCD(gmac_ptv_fast, GmacArgs)
+EMU_XCD(gmac_diag, GmacArgs)
 EMU(tensor_square, SquareArgs)
 EMU(lift_pq, LiftPqArgs)
 EMU(lin_comb, LinArgs)

@@ -182,6 +182,31 @@ def test_conv_variants_bit_exact(backend, budget, case, hoist, orc):
 
 
 @pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("case", [
+    dict(x=(2, 4, 8, 8), w=(4, 4, 3, 3), stride=1, pad=1, groups=1, S=2),    # one mask per group and class
+    dict(x=(2, 4, 8, 8), w=(4, 1, 3, 3), stride=2, pad=1, groups=4, S=2),    # masks differing per output
+])
+@pytest.mark.parametrize("hoist", [1, 0])
+def test_conv_large_weight_codes_bit_exact(backend, case, hoist, orc):
+    """Weights of magnitude ~10 give codes above 2^23 after the scale split,
+    so the MAC takes a modular product per term instead of the small-code
+    path; the mask-basis form (plaintext budget 0) is forced."""
+    o, f = orc, make(backend, *SMALL)
+    f.set_plaintext_budget(0)
+    f.set_hoisting(hoist)
+    r = rng(4)
+    x, w = r.uniform(0, 1, case["x"]), r.normal(0, 10.0, case["w"])
+    Lo = o.fragment_layout(*case["x"], case["S"])
+    lay = f.plan_layout(*case["x"], case["w"][2], case["w"][0], case["S"])
+    ob, fb = o.encrypt_tensor(Lo, x, 5), f.encrypt(f.encode_fragment(x, lay), lay, 5)
+    yo, _ = o.conv2d(ob, w, case["stride"], case["pad"], case["groups"], pt_budget=0, hoist=hoist)
+    yf = f.conv2d(fb, w, case["stride"], case["pad"], case["groups"])
+    cmp(yf, yo, f)
+    want = cnn_ref.conv2d(x, w, case["stride"], case["pad"], case["groups"])
+    assert np.max(np.abs(f.decrypt(yf) - want)) < 1e-4 * max(1.0, np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
 def test_single_conv_layer_benchmark_small_config(backend):
     """1x28x28 image, conv 1->6 5x5 valid, N=2^13, 4 x 40-bit primes + 1 special, scale 2^30."""
     params = (13, 4, 40, 1, 40, 4, 30, 1)
