@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1319951745, "ntt_fwd_rows": 297354468, "ntt_fwd_cols16": 225668201, "moddown_tail": 371000460, "rescale_tail": 289029347, "ntt_inv_rows": 73507977, "ntt_inv_cols": 68093063, "modup_fbc": 256664117, "moddown_fbc": 151105523, "tensor_square": 477119927, "lift_pq": 187012293, "rescale_lift": 101864016}
+TRAFFIC = {"kip": 1319468353, "ntt_fwd_rows": 252631363, "gmac_diag": 352230757, "moddown_tail": 371042977, "gmac_pt_fast": 1520354662, "rescale_tail": 289029254, "ntt_inv_rows": 73439239, "ntt_inv_cols": 68107059, "modup_fbc": 256664207, "gmac_fast": 623982234, "moddown_fbc": 151115943, "tensor_square": 477122887, "lift_pq": 187026312, "rescale_lift": 101859929}
 
 
 def log(*a):
