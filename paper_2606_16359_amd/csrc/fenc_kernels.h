@@ -59,7 +59,7 @@ struct NttArgs {
   long long src_gs, dst_gs;   // elements between row groups
   int nrows, nl;              // rows, rows per group (row r: group r/nl, limb r%nl)
   PrimeMap pm;
-  const d2* tw;               // [prime][N] (w, w/q)
+  const double* tw;           // [prime][N] twiddles w; the quotient estimate w/q is formed as w * (1/q)
   const d2* pq;               // [prime] (q, 1/q)
   const d2* ninv;             // [prime] (N^-1, N^-1/q), inverse only
   int logn, n1, n2;
@@ -67,6 +67,13 @@ struct NttArgs {
   int lcpb;                   // log2 of the chunks per block (row pass)
 };
 
+
+// Twiddle pair (w, w/q) for mulmod_c from w alone; the twiddle table holds 8
+// bytes per entry.  The estimate fl(w * fl(1/q)) has relative error below
+// 2^-52, so for q < 2^50 the rounded quotient of a*w/q is off by at most
+// 1/2 + |a|/(4q) and mulmod_c returns the exact a*w - e*q with magnitude at
+// most (1/2 + |a|/(4q)) q.
+FENC_HD inline d2 twiddle(double w, double qi) { return d2{w, w * qi}; }
 
 // Stage index of member f (< 2^k) of the butterfly group whose other stage
 // bits are `rest`, with the k-bit field at bit `lo`.
@@ -77,10 +84,10 @@ FENC_HD inline int member(int rest, int f, int lo, int k) {
 // One register round of forward (Cooley-Tukey) stages s0..s0+K-1 of a pass
 // with P stage bits: local stage s pairs stage-index bit P-1-s.  tw_of(s, a)
 // is the twiddle of the butterfly whose upper element has stage index a.
-// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2].  Three
-// stages keep every product operand below 3q and every sum below 4q < 2^52;
-// a fourth stage (K = 4) follows a reduction.  K is a compile-time constant
-// so the group lives in registers.
+// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2].  With the
+// product bound of twiddle(), three stages keep the sums below 1.75q, 2.69q
+// and 3.86q (< 2^52, exact); a fourth stage (K = 4) follows a reduction.  K
+// is a compile-time constant so the group lives in registers.
 template <int K, class LD, class ST, class TW>
 FENC_HD inline void fwd_round(int rest, int s0, int P, double q, double qi, LD ld, ST st, TW tw_of) {
   double v[1 << K];
@@ -200,7 +207,7 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
   u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << a.logn);
   const long long col0 = (long long)x.bx << sb;
   const double q = a.pq[p].x, qi = a.pq[p].y;
-  const d2* tw = a.tw + ((long long)p << a.logn);
+  const double* tw = a.tw + ((long long)p << a.logn);
   double* sm = x.smem;
   const d2 ni = INV ? a.ninv[p] : d2{0, 0};
   RoundLoop<0, n_rounds(P, RB)>::run([&](auto R) {
@@ -218,7 +225,7 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
                 if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(v, q));
                 else sm[(hi << sb) | c] = v;
               },
-              [&](int st, int hi) { return tw[(1 << st) + (hi >> (P - st))]; });
+              [&](int st, int hi) { return twiddle(tw[(1 << st) + (hi >> (P - st))], qi); });
         } else {
           inv_round<K>(
               rest, s0, q, qi, ld,
@@ -227,7 +234,7 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
                 else sm[(hi << sb) | c] = v;
               },
               // global stage u = n2 + st: h = N >> (u+1), group = hi >> (st+1)
-              [&](int st, int hi) { return tw[(1LL << (P - st - 1)) + (hi >> (st + 1))]; });
+              [&](int st, int hi) { return twiddle(tw[(1LL << (P - st - 1)) + (hi >> (st + 1))], qi); });
         }
       }
     });
@@ -247,7 +254,7 @@ FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
   u64* dst = a.dst + (long long)(row / a.nl) * a.dst_gs + ((long long)(row % a.nl) << logn) + e0;
   const long long chunk0 = (long long)x.bx << cb;
   const double q = a.pq[p].x, qi = a.pq[p].y;
-  const d2* tw = a.tw + ((long long)p << logn);
+  const double* tw = a.tw + ((long long)p << logn);
   double* sm = x.smem;
   RoundLoop<0, n_rounds(P, RB)>::run([&](auto R) {
     constexpr int r = decltype(R)::value;
@@ -265,12 +272,14 @@ FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
         if constexpr (!INV) {
           fwd_round<K>(rest, s0, P, q, qi, ld, st,
                        // global stage n1 + st: group = (chunk << st) + (lo >> (n2 - st))
-                       [&](int s, int lo) { return tw[(1LL << (n1 + s)) + ((chunk0 + ch) << s) + (lo >> (P - s))]; });
+                       [&](int s, int lo) {
+                         return twiddle(tw[(1LL << (n1 + s)) + ((chunk0 + ch) << s) + (lo >> (P - s))], qi);
+                       });
         } else {
           inv_round<K>(rest, s0, q, qi, ld, st,
                        // stage s: h = N >> (s+1), group = (chunk << (n2-s-1)) + (lo >> (s+1))
                        [&](int s, int lo) {
-                         return tw[(1LL << (logn - s - 1)) + ((chunk0 + ch) << (P - s - 1)) + (lo >> (s + 1))];
+                         return twiddle(tw[(1LL << (logn - s - 1)) + ((chunk0 + ch) << (P - s - 1)) + (lo >> (s + 1))], qi);
                        });
         }
       }

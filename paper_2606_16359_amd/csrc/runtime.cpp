@@ -82,14 +82,15 @@ void ensure_device(Ctx& C) {
   if (C.dev) return;
   C.device = fb::device_id();
   const int N = C.N, np = C.np;
-  std::vector<d2> pq(np), twf((size_t)np * N), twi((size_t)np * N), ni(np);
+  std::vector<d2> pq(np), ni(np);
+  std::vector<double> twf((size_t)np * N), twi((size_t)np * N);   // twiddles w (the kernels form w/q)
   for (int p = 0; p < np; p++) {
     const uint64_t q = C.primes[p], psi = C.psi[p], psi_inv = invmod(psi, q);
     pq[p] = {(double)q, 1.0 / (double)q};
     for (int k = 0; k < N; k++) {
       const unsigned e = fh::bitrev((unsigned)k, C.logn);
-      twf[(size_t)p * N + k] = cpair(fh::powmod(psi, e, q), q);
-      twi[(size_t)p * N + k] = cpair(fh::powmod(psi_inv, e, q), q);
+      twf[(size_t)p * N + k] = (double)fh::powmod(psi, e, q);
+      twi[(size_t)p * N + k] = (double)fh::powmod(psi_inv, e, q);
     }
     ni[p] = cpair(invmod((uint64_t)N, q), q);
   }

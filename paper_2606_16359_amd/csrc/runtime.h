@@ -163,7 +163,8 @@ struct fenc_ctx {
   // device state (built on first use)
   bool dev = false;
   int device = -1;
-  fk::d2 *pq = nullptr, *tw_fwd = nullptr, *tw_inv = nullptr, *ninv = nullptr;
+  fk::d2 *pq = nullptr, *ninv = nullptr;
+  double *tw_fwd = nullptr, *tw_inv = nullptr;
   fk::d2 *md_tab = nullptr, *pinv = nullptr;   // ModDown: hinv[K], hat[L+1][K]; P^-1 mod q_i
   uint64_t* s_ntt = nullptr;                   // [np][N]
   std::map<int, fr::LevelTabs> lvl;
