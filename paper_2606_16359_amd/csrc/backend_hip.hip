@@ -120,6 +120,8 @@ void dev_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
+void device_sync() { check(hipDeviceSynchronize(), "hipDeviceSynchronize"); }
+
 void h2d(void* dst, const void* src, size_t bytes) {
   if (bytes) check(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy H2D");
 }

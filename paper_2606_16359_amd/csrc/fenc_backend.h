@@ -15,6 +15,7 @@ struct Grid {
 
 void* dev_alloc(size_t bytes);                       // throws std::runtime_error
 void dev_free(void* p);
+void device_sync();                                  // waits for all work on the device
 void h2d(void* dst, const void* src, size_t bytes);  // synchronous
 void d2h(void* dst, const void* src, size_t bytes);  // synchronous (device-wide)
 void d2d_async(void* dst, const void* src, size_t bytes, Stream s);

@@ -28,18 +28,39 @@ Arena::~Arena() {
 
 void* Arena::get(size_t bytes, fb::Stream s) {
   bytes = (bytes + 255) & ~(size_t)255;
-  while (cur_ < chunks_.size()) {
-    if (off_ + bytes <= chunks_[cur_].cap) {
-      void* p = chunks_[cur_].p + off_;
-      off_ += bytes;
-      return p;
-    }
-    cur_++;
-    off_ = 0;
+  const bool cap_now = fb::capturing(s);
+  if (!chunks_.empty() && off_ + bytes <= chunks_[cur_].cap) {
+    void* p = chunks_[cur_].p + off_;
+    off_ += bytes;
+    chunks_[cur_].pinned = chunks_[cur_].pinned || cap_now;
+    return p;
   }
-  if (fb::capturing(s)) fail(FENC_ENOMEM, "workspace must grow during stream capture; run the operation once before capturing");
-  size_t cap = std::max<size_t>(bytes, chunks_.empty() ? (size_t)64 << 20 : chunks_.back().cap * 2);
-  chunks_.push_back({(char*)fb::dev_alloc(cap), cap});
+  // the chunks after the current one are free: the first that is large enough
+  const size_t from = chunks_.empty() ? 0 : cur_ + 1;
+  for (size_t n = from; n < chunks_.size(); n++)
+    if (chunks_[n].cap >= bytes) {
+      cur_ = n;
+      off_ = bytes;
+      chunks_[n].pinned = chunks_[n].pinned || cap_now;
+      return chunks_[n].p;
+    }
+  if (cap_now) fail(FENC_ENOMEM, "workspace must grow during stream capture; run the operation once before capturing");
+  // return the free chunks that are too small (earlier launches may still use
+  // them: wait for the device first), then add one that fits; chunks grow
+  // from 64 MiB up to 1 GiB, larger requests get a chunk of their own size
+  bool dropped = false;
+  for (size_t n = chunks_.size(); n-- > from;)
+    if (!chunks_[n].pinned) {
+      if (!dropped) fb::device_sync();
+      dropped = true;
+      fb::dev_free(chunks_[n].p);
+      chunks_.erase(chunks_.begin() + n);
+    }
+  size_t biggest = 0;
+  for (auto& c : chunks_) biggest = std::max(biggest, c.cap);
+  const size_t grow = chunks_.empty() ? (size_t)64 << 20 : std::min<size_t>(biggest * 2, (size_t)1 << 30);
+  const size_t cap = std::max<size_t>(bytes, grow);
+  chunks_.push_back({(char*)fb::dev_alloc(cap), cap, false});
   cur_ = chunks_.size() - 1;
   off_ = bytes;
   return chunks_[cur_].p;

@@ -40,8 +40,13 @@ Layout plan_fragment(int ns, int level, double scale, int bs, int c, int h, int 
 void layout_slots(const Layout& L, int b, int ch, int y, int x, std::vector<std::pair<int, int>>& out);
 
 // ---------------------------------------------------------------- arena
-// Grow-only chunked workspace.  Allocation order is deterministic, so a
-// repeated operation gets the same addresses (required for graph replay).
+// Chunked stack workspace.  Allocation order is deterministic, so a repeated
+// operation gets the same addresses (required for graph replay).  Everything
+// past the current position is free; when a request fits no chunk, the free
+// chunks that are too small are returned to the device (after a device-wide
+// synchronisation) before a larger one is allocated, so the capacity follows
+// the largest operation instead of accumulating.  Chunks used during a stream
+// capture are kept: a captured graph holds their addresses.
 class Arena {
  public:
   struct Mark {
@@ -56,6 +61,7 @@ class Arena {
   struct Chunk {
     char* p;
     size_t cap;
+    bool pinned;   // used during a stream capture
   };
   std::vector<Chunk> chunks_;
   size_t cur_ = 0, off_ = 0;

@@ -4,8 +4,8 @@ launches.
 
 Each tenant owns a context (its own keys, resident in HBM), a network and a
 serving layout whose batch group holds `capacity` images.  A request is one
-client's batch of 1..capacity images, encrypted by the client into one batch
-group.  A tenant's executor takes every request queued when it becomes idle
+client's batch of images, encrypted by the client into up to `max_groups`
+whole batch groups.  A tenant's executor takes every request queued when it becomes idle
 (up to its batch-size limit and the memory budget), concatenates their batch
 groups into one ciphertext batch and runs the network once for all of them:
 every stage launch covers the requests together.  Batch groups never mix
@@ -16,6 +16,7 @@ batches overlap on the device.
 This module holds scheduling and bookkeeping only; all arithmetic runs in the
 library.  Arrival traces are seeded and synthetic.
 """
+import sys
 import threading
 import time
 from collections import deque
@@ -38,30 +39,37 @@ class Request:
 class Tenant:
     """A network served for one key owner.
 
-    net: "lenet" (LeNet-5-shaped, N = 2^15) or "cifar" (CIFAR-shaped stack,
-    N = 2^16).  capacity: images per batch group (the slots of one request).
+    net: "lenet" (LeNet-5-shaped, N = 2^15), "cifar" (CIFAR-shaped stack,
+    N = 2^16) or "mobilenet" (the first MobileNet-V1-shaped block at
+    224x224: conv 3->32 stride 2 and the quadratic activation, N = 2^16).
+    capacity: images per batch group; max_groups: batch groups per request;
     max_batch: requests merged into one run."""
 
     NETS = {
-        "lenet": dict(params="lenet", in_shape=(1, 28, 28), k=5, cout=6),
-        "cifar": dict(params="cifar", in_shape=(16, 32, 32), k=3, cout=16),
+        "lenet": dict(params="lenet", in_shape=(1, 28, 28), block_size=0),
+        "cifar": dict(params="cifar", in_shape=(16, 32, 32), block_size=0),
+        "mobilenet": dict(params="cifar", in_shape=W.MOBILENET_INPUTS[0][0], block_size=W.MOBILENET_INPUTS[0][1]),
     }
 
     def __init__(self, name, net, seed, capacity, max_batch=4, lib_path=None, params=None, shapes=None,
-                 strides=None, in_shape=None, block_size=0):
+                 strides=None, in_shape=None, block_size=None, max_groups=1):
         spec = self.NETS[net]
         self.name, self.net, self.capacity, self.max_batch = name, net, capacity, max_batch
+        self.max_groups = max_groups
         prm = list(params or W.PARAMS[spec["params"]])
         prm[-1] = seed
         self.fe = F.Fenc(*prm, lib_path=lib_path)
         c, h, w = in_shape or spec["in_shape"]
         self.in_shape = (c, h, w)
-        self.w = W.weights(shapes or (W.LENET_SHAPES if net == "lenet" else W.CIFAR_SHAPES), seed=seed + 100)
+        if net == "mobilenet":
+            self.w = W.mobilenet_weights(seed=seed + 100)[0]
+        else:
+            self.w = W.weights(shapes or (W.LENET_SHAPES if net == "lenet" else W.CIFAR_SHAPES), seed=seed + 100)
         self.strides = strides or W.CIFAR_STRIDES
-        k0 = self.w[0].shape[2] if net == "cifar" else spec["k"]
-        self.lay = self.fe.plan_layout(capacity, c, h, w, k0, self.w[0].shape[0], block_size)
-        if self.lay.n_bg != 1:
-            raise ValueError("a request's images must fit one batch group")
+        self.k0 = self.w[0].shape[2]
+        self.block_size = spec["block_size"] if block_size is None else block_size
+        self.layouts = {}
+        self.lay = self.layout(1)
         self.stream = None
         if not self.fe.emulated:
             import torch
@@ -69,40 +77,72 @@ class Tenant:
         self.queue = deque()
         self.lock = threading.Lock()
 
+    def layout(self, groups):
+        """Serving layout of `groups` whole batch groups of `capacity` images."""
+        if groups not in self.layouts:
+            c, h, w = self.in_shape
+            lay = self.fe.plan_layout(groups * self.capacity, c, h, w, self.k0, self.w[0].shape[0], self.block_size)
+            if lay.n_bg != groups or lay.bs != groups * self.capacity:
+                raise ValueError("capacity must be the layout's images per batch group")
+            self.layouts[groups] = lay
+        return self.layouts[groups]
+
+    def groups_of(self, n_images):
+        g = -(-n_images // self.capacity)
+        if n_images < 1 or g > self.max_groups:
+            raise ValueError("request size out of range")
+        return g
+
     # ---- client side
     def encrypt_request(self, x, seed):
-        """Encode and encrypt up to `capacity` images (x[n][c][h][w]) into one batch group."""
-        n = x.shape[0]
-        if n < 1 or n > self.capacity:
-            raise ValueError("request size out of range")
-        full = np.zeros((self.capacity,) + self.in_shape)
-        full[:n] = x
-        return self.fe.encrypt(self.fe.encode_fragment(full, self.lay), self.lay, seed)
+        """Encode and encrypt images x[n][c][h][w] into whole batch groups."""
+        g = self.groups_of(x.shape[0])
+        full = np.zeros((g * self.capacity,) + self.in_shape)
+        full[:x.shape[0]] = x
+        lay = self.layout(g)
+        return self.fe.encrypt(self.fe.encode_fragment(full, lay), lay, seed)
+
+    def leading_groups(self, ct, g):
+        """The first g batch groups of an encrypted request (ciphertexts are
+        batch-group major, so this is a prefix of the buffer, shared)."""
+        if g == ct.lay.n_bg:
+            return ct
+        lay = ct.lay.copy()
+        lay.n_bg, lay.bs = g, g * self.capacity
+        return F.Ciphertexts(self.fe, lay, ct.buf[:g * (ct.n_ct // ct.lay.n_bg) * 2 * (lay.level + 1) * self.fe.N])
 
     def decrypt_request(self, req):
         y = self.fe.decrypt(req.out)
-        return y.reshape(self.capacity, -1)[:req.n_images]
+        return y.reshape(y.shape[0], -1)[:req.n_images]
 
     # ---- server side
     def forward(self, ct):
         if self.net == "lenet":
             return W.lenet_forward(self.fe, ct, self.w)
+        if self.net == "mobilenet":
+            return W.mobilenet_block(self.fe, ct, W.MOBILENET_BLOCKS[0], self.w)
         return W.cifar_forward(self.fe, ct, self.w, self.strides)
 
+    # HBM held while a request runs, in units of its input ciphertext bytes
+    # (rotated copies, extended digits and outputs).  The MobileNet-shaped
+    # block writes 32 output ciphertexts per 12 input ones and relinearises
+    # them all at once: extended digits of ~2.5 ciphertexts each.
+    WORKING_SET = {"lenet": 5, "cifar": 5, "mobilenet": 16}
+
     def footprint(self, ct):
-        """HBM bytes a request holds while in flight: its input ciphertexts and a
-        working set of four times that (rotated copies, extended digits, outputs)."""
-        return 5 * ct.n_ct * 2 * (ct.lay.level + 1) * self.fe.N * 8
+        """HBM bytes a request holds while in flight."""
+        return self.WORKING_SET[self.net] * ct.n_ct * 2 * (ct.lay.level + 1) * self.fe.N * 8
 
     def run_batch(self, reqs):
         """Concatenate the requests' batch groups, run the network once, split."""
-        R = len(reqs)
-        if R == 1:
+        groups = [r.ct.lay.n_bg for r in reqs]
+        G = sum(groups)
+        if len(reqs) == 1:
             ct = reqs[0].ct
         else:
             lay = reqs[0].ct.lay.copy()
-            lay.n_bg = R
-            lay.bs = R * reqs[0].ct.lay.bs
+            lay.n_bg = G
+            lay.bs = G * self.capacity
             bufs = [r.ct.buf for r in reqs]
             if self.fe.emulated:
                 buf = np.concatenate(bufs)
@@ -111,35 +151,44 @@ class Tenant:
                 buf = torch.cat(bufs)
             ct = F.Ciphertexts(self.fe, lay, buf)
         out = self.forward(ct)
-        per = out.n_ct // R
-        elems = 2 * (out.lay.level + 1) * self.fe.N
-        for i, r in enumerate(reqs):
+        per = out.n_ct // G * 2 * (out.lay.level + 1) * self.fe.N   # elements per batch group
+        g0 = 0
+        for r, g in zip(reqs, groups):
             lay = out.lay.copy()
-            lay.n_bg = 1
-            lay.bs = out.lay.bs // R
-            r.out = F.Ciphertexts(self.fe, lay, out.buf[i * per * elems:(i + 1) * per * elems])
+            lay.n_bg = g
+            lay.bs = out.lay.bs // G * g
+            r.out = F.Ciphertexts(self.fe, lay, out.buf[g0 * per:(g0 + g) * per])
+            g0 += g
         return out
 
 
 class Server:
     """Continuous batching over tenants with HBM-footprint admission."""
 
-    def __init__(self, tenants, hbm_budget=200 << 30):
+    def __init__(self, tenants, hbm_budget=200 << 30, keep_outputs=True):
+        """keep_outputs=False drops each request's output ciphertexts once it
+        is done (a benchmark without clients to hand them to)."""
         self.tenants = {t.name: t for t in tenants}
         self.budget = hbm_budget
+        self.keep_outputs = keep_outputs
         self.in_flight = 0
         self.mem = threading.Lock()
         self.done = []
         self.done_lock = threading.Lock()
         self.batches = []
 
-    def warmup(self, seed=1):
-        """Build every tenant's plans for each batch size it may run (not timed)."""
+    def warmup(self, seed=1, group_counts=None, progress=None):
+        """Build a tenant's plans for the batch-group counts it may run (all
+        counts up to max_batch * max_groups unless given; not timed).
+        progress(tenant name, group count) is called after each run."""
         for t in self.tenants.values():
-            x = np.zeros((1,) + t.in_shape)
-            for R in range(1, t.max_batch + 1):
-                reqs = [Request(-1, t.name, 1, t.encrypt_request(x, seed + i)) for i in range(R)]
+            x = np.zeros((t.capacity,) + t.in_shape)
+            ct = t.encrypt_request(x, seed)
+            for G in (group_counts or {}).get(t.name, range(1, t.max_batch * t.max_groups + 1)):
+                reqs = [Request(-1, t.name, t.capacity, ct) for _ in range(G)]
                 self._run(t, reqs)
+                if progress:
+                    progress(t.name, G)
 
     @staticmethod
     def _run(t, reqs):
@@ -189,6 +238,8 @@ class Server:
         with self.done_lock:
             for r in reqs:
                 r.t_done = t1
+                if not self.keep_outputs:
+                    r.out = None
                 self.done.append(r)
             self.batches.append((t.name, len(reqs), sum(r.n_images for r in reqs), t0, t1))
         return len(reqs)
@@ -265,8 +316,9 @@ def latency_summary(done):
 
 
 def main():
-    """Serving benchmark: Poisson arrivals over LeNet-shaped and CIFAR-shaped
-    tenants; prints one JSON line with latency percentiles and throughput."""
+    """Serving benchmark: Poisson arrivals over LeNet-shaped, CIFAR-shaped and
+    MobileNet-block tenants; prints one JSON line with latency percentiles and
+    throughput."""
     import argparse
     import json
     ap = argparse.ArgumentParser()
@@ -274,6 +326,9 @@ def main():
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--lenet-tenants", type=int, default=2)
     ap.add_argument("--cifar-tenants", type=int, default=1)
+    ap.add_argument("--mobilenet-tenants", type=int, default=1)
+    ap.add_argument("--mobilenet-max-images", type=int, default=16,
+                    help="largest MobileNet request (two 224x224 images per batch group)")
     ap.add_argument("--max-batch", type=int, default=4)
     ap.add_argument("--cifar-capacity", type=int, default=64)
     ap.add_argument("--pool", type=int, default=4, help="distinct pre-encrypted requests per tenant")
@@ -282,23 +337,40 @@ def main():
     import torch
     tenants = [Tenant(f"lenet{i}", "lenet", 11 + i, 64, args.max_batch) for i in range(args.lenet_tenants)]
     tenants += [Tenant(f"cifar{i}", "cifar", 31 + i, args.cifar_capacity, 2) for i in range(args.cifar_tenants)]
-    srv = Server(tenants)
+    tenants += [Tenant(f"mobilenet{i}", "mobilenet", 41 + i, 2, 1, max_groups=-(-args.mobilenet_max_images // 2))
+                for i in range(args.mobilenet_tenants)]
+    srv = Server(tenants, keep_outputs=False)
+    share = {"lenet": 0.6, "cifar": 0.3, "mobilenet": 0.1}
+    count = {net: sum(t.net == net for t in tenants) for net in share}
+    mix = {t.name: share[t.net] / count[t.net] for t in tenants}
+    sizes = {t.name: (1, min(64, t.capacity * t.max_groups)) for t in tenants}
+    trace = poisson_trace(args.rate, args.duration, mix, sizes, args.seed)
+    # plans for every batch-group count a run can reach
     t0 = time.perf_counter()
-    srv.warmup()
+    srv.warmup(progress=lambda n, G: print(
+        f"warm-up {n}: {G} batch groups, {time.perf_counter() - t0:.1f}s, library GiB "
+        f"{srv.tenants[n].fe.device_bytes() / 2**30:.1f}, torch GiB {torch.cuda.memory_reserved() / 2**30:.1f}",
+        file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
-    mix = {t.name: (0.6 / max(1, args.lenet_tenants) if t.net == "lenet" else 0.3 / max(1, args.cifar_tenants))
-           for t in tenants}
-    sizes = {t.name: (1, 64) for t in tenants}
-    trace = poisson_trace(args.rate, args.duration, mix, sizes, args.seed)
+    held = {t.name: round(t.fe.device_bytes() / 2**30, 2) for t in tenants}
+    print(f"warm-up {t_warm:.1f}s; device GiB held per tenant {held}", file=sys.stderr, flush=True)
     # clients encrypt before sending (outside the served latency); each tenant
-    # has a pool of distinct encrypted full-capacity batches that arrivals reuse
-    # read-only (the network never writes its input), counting the trace's
-    # image count as the images served
-    pool = {t.name: [t.encrypt_request(W.images((t.capacity,) + t.in_shape, seed=1000 + j), 5000 + j)
-                     for j in range(args.pool)] for t in tenants}
-    arrivals = [(off, Request(i, name, min(n, srv.tenants[name].capacity), pool[name][i % args.pool]))
-                for i, (off, name, n) in enumerate(trace)]
+    # has a pool of distinct encrypted requests of its largest size, and an
+    # arrival of n images takes the leading batch groups it needs (read-only:
+    # the network never writes its input)
+    pool = {t.name: [t.encrypt_request(W.images((t.capacity * t.max_groups,) + t.in_shape, seed=1000 + j),
+                                       5000 + j) for j in range(args.pool)] for t in tenants}
+    arrivals = []
+    for i, (off, name, n) in enumerate(trace):
+        t = srv.tenants[name]
+        ct = t.leading_groups(pool[name][i % args.pool], t.groups_of(n))
+        arrivals.append((off, Request(i, name, n, ct)))
+    # the tenants' workspaces were sized in the warm-up; admission budgets what
+    # is left for the ciphertexts that runs allocate between layers
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    srv.budget = int(0.8 * torch.cuda.mem_get_info()[0])
     torch.cuda.synchronize()
     wall = srv.serve(arrivals)
     res = latency_summary(srv.done)
@@ -307,8 +379,9 @@ def main():
                 "rate_req_per_s": args.rate, "batches": len(srv.batches),
                 "mean_batch": round(float(np.mean([b[1] for b in srv.batches])), 2),
                 "tenants": {t.name: t.net for t in tenants}, "warmup_s": round(t_warm, 1),
+                "device_GiB_after_warmup": held, "admission_budget_GiB": round(srv.budget / 2**30, 1),
                 "per_net": {}})
-    for net in ("lenet", "cifar"):
+    for net in ("lenet", "cifar", "mobilenet"):
         d = [r for r in srv.done if srv.tenants[r.tenant].net == net]
         if d:
             res["per_net"][net] = latency_summary(d)

@@ -99,6 +99,7 @@ void* dev_alloc(size_t bytes) {
   return p;
 }
 void dev_free(void* p) { std::free(p); }
+void device_sync() {}
 void h2d(void* dst, const void* src, size_t bytes) { std::memcpy(dst, src, bytes); }
 void d2h(void* dst, const void* src, size_t bytes) { std::memcpy(dst, src, bytes); }
 void d2d_async(void* dst, const void* src, size_t bytes, Stream) { std::memcpy(dst, src, bytes); }

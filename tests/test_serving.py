@@ -1,6 +1,8 @@
 """Serving loop: requests of several tenants, continuously batched, give the
 same ciphertexts as each request run alone (batch groups never share a
 ciphertext), and decrypt to the float64 network."""
+import time
+
 import numpy as np
 import pytest
 
@@ -69,6 +71,40 @@ def test_admission_respects_the_memory_budget(backend):
     assert len(srv._take(t)) == 2
 
 
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_requests_of_several_batch_groups(backend):
+    """A tenant whose batch group holds 16 images takes requests of up to two
+    groups; merged runs cover up to four groups and each request's output is
+    bit-identical to its run alone."""
+    prm = list(SMALL_NET["params"])
+    prm[6] = 40
+    t = S.Tenant("m", "cifar", 24, 16, 2, lib_path=lib_path(backend), params=prm, shapes=SMALL_NET["shapes"],
+                 strides=[1, 1, 1], in_shape=SMALL_NET["in_shape"], block_size=1, max_groups=2)
+    assert t.layout(2).n_bg == 2 and t.groups_of(17) == 2 and t.groups_of(16) == 1
+    with pytest.raises(ValueError):
+        t.groups_of(33)
+    srv = S.Server([t])
+    reqs, xs = [], []
+    for i, n in enumerate((20, 5, 32, 16)):
+        x = W.images((n,) + t.in_shape, seed=310 + i)
+        xs.append(x)
+        reqs.append((0.0, S.Request(i, "m", n, t.encrypt_request(x, 910 + i))))
+        srv.submit(reqs[-1][1])
+    # two requests per run: groups 2 + 1, then 2 + 1
+    assert srv.step(t, time.perf_counter) == 2 and srv.step(t, time.perf_counter) == 2
+    assert [b[2] for b in srv.batches] == [25, 48]
+    for (off, r), x in zip(reqs, xs):
+        mixed = t.fe.export(r.out)
+        alone = S.Request(r.rid, r.tenant, r.n_images, r.ct)
+        srv._run(t, [alone])
+        assert np.array_equal(t.fe.export(alone.out), mixed)
+        assert np.max(np.abs(t.decrypt_request(r) - reference(t, x))) < 1e-4
+    # the leading groups of a request are a view of its buffer
+    c = reqs[2][1].ct
+    one = t.leading_groups(c, 1)
+    assert one.lay.n_bg == 1 and one.n_ct == c.n_ct // 2
+
+
 def test_poisson_trace_is_seeded_and_mixed():
     a = S.poisson_trace(200, 1.0, {"x": 0.6, "y": 0.4}, {"x": (1, 64), "y": (1, 8)}, seed=3)
     b = S.poisson_trace(200, 1.0, {"x": 0.6, "y": 0.4}, {"x": (1, 64), "y": (1, 8)}, seed=3)
@@ -106,3 +142,30 @@ def test_lenet_tenants_served_in_batches_match_alone_at_full_size():
         assert np.max(np.abs(t.decrypt_request(r)[:, :want.shape[1]] - want)) < 1e-4
     s = S.latency_summary(srv.done)
     assert s["requests"] == 10 and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+@pytest.mark.gpu
+def test_mobilenet_tenant_requests_of_several_groups_at_full_size():
+    """The first MobileNet-V1-shaped block at 224x224 (N = 2^16, two images per
+    batch group): a three-image and a two-image request are merged into one
+    three-group run; each matches its run alone and the float64 block."""
+    import torch
+    t = S.Tenant("mb", "mobilenet", 41, 2, 2, max_groups=2)
+    srv = S.Server([t])
+    reqs, xs = [], []
+    for i, n in enumerate((3, 2)):
+        x = W.images((n,) + t.in_shape, seed=520 + i)
+        xs.append(x)
+        reqs.append((0.0, S.Request(i, t.name, n, t.encrypt_request(x, 720 + i))))
+        srv.submit(reqs[-1][1])
+    torch.cuda.synchronize()
+    assert srv.step(t, time.perf_counter) == 2 and len(srv.done) == 2
+    for (off, r), x in zip(reqs, xs):
+        mixed = t.fe.export(r.out)
+        alone = S.Request(r.rid, r.tenant, r.n_images, r.ct)
+        srv._run(t, [alone])
+        assert np.array_equal(t.fe.export(alone.out), mixed)
+        layer = W.MOBILENET_BLOCKS[0][0]
+        want = np.polynomial.polynomial.polyval(
+            cnn_ref.conv2d(x, t.w[0], layer["stride"], layer["pad"], layer["groups"]), W.QUADRATIC)
+        assert np.max(np.abs(t.decrypt_request(r) - want.reshape(x.shape[0], -1))) < 1e-4
