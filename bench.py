@@ -24,12 +24,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
-KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv_fast", "gmac_diag", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "moddown_tail",
-           "moddown_fbc", "modup_fbc", "rescale_tail", "rescale_lift", "tensor_square", "lin_comb", "lift_pq"]
+KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv_fast", "gmac_diag", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "ntt_fwd_rows_md", "ntt_fwd_rows_rs",
+           "moddown_fbc", "modup_fbc", "rescale_lift", "tensor_square", "lin_comb", "lift_pq"]
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1319468353, "ntt_fwd_rows": 252631363, "gmac_diag": 352230757, "moddown_tail": 371042977, "gmac_pt_fast": 1520354662, "rescale_tail": 289029254, "ntt_inv_rows": 73439239, "ntt_inv_cols": 68107059, "modup_fbc": 256664207, "gmac_fast": 623982234, "moddown_fbc": 151115943, "tensor_square": 477122887, "lift_pq": 187026312, "rescale_lift": 101859929}
+TRAFFIC = {"kip": 1319468353, "ntt_fwd_rows": 252631363, "gmac_diag": 352230757, "gmac_pt_fast": 1520354662, "ntt_inv_rows": 73439239, "ntt_inv_cols": 68107059, "modup_fbc": 256664207, "gmac_fast": 623982234, "moddown_fbc": 151115943, "tensor_square": 477122887, "lift_pq": 187026312, "rescale_lift": 101859929}
 
 
 def log(*a):

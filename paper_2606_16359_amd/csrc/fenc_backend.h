@@ -37,14 +37,16 @@ void ntt_inv_cols(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs&
 // the same passes with radix-16 register rounds
 void ntt_fwd_cols16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void ntt_fwd_rows16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
+void ntt_fwd_rows_md(Grid g, int threads, size_t smem, Stream s, const fk::NttMdArgs& a);
+void ntt_fwd_rows16_md(Grid g, int threads, size_t smem, Stream s, const fk::NttMdArgs& a);
+void ntt_fwd_rows_rs(Grid g, int threads, size_t smem, Stream s, const fk::NttRsArgs& a);
+void ntt_fwd_rows16_rs(Grid g, int threads, size_t smem, Stream s, const fk::NttRsArgs& a);
 void ntt_inv_rows16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void ntt_inv_cols16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void modup_fbc(Grid g, int threads, Stream s, const fk::ModUpArgs& a);
 void kip(Grid g, int threads, Stream s, const fk::KipArgs& a);
 void moddown_fbc(Grid g, int threads, Stream s, const fk::ModDownArgs& a);
-void moddown_tail(Grid g, int threads, Stream s, const fk::TailArgs& a);
 void rescale_lift(Grid g, int threads, Stream s, const fk::LiftArgs& a);
-void rescale_tail(Grid g, int threads, Stream s, const fk::RescaleTailArgs& a);
 void gmac(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_pt(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_fast(Grid g, int threads, Stream s, const fk::GmacArgs& a);

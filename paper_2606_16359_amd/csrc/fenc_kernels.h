@@ -245,8 +245,18 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
 // stages 2^lcpb chunks.  The chunk is the high part of the thread's group
 // index so neighbouring threads touch neighbouring words.  Forward: the last
 // n2 stages; inverse: the first n2 stages.
-template <bool INV, int P, int RB, class X>
-FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
+// The last forward round writes its groups at a stride of 2^K words; it
+// writes the LDS tile instead, and the block's words, which are contiguous,
+// go to HBM in a separate coalesced phase.  (Staging the strided first round
+// of the inverse pass the same way was measured slower.)  With an epilogue
+// (EPI other than NoEpi) that phase hands each value (row, element, v in
+// [-q/2, q/2]) to epi_store instead of writing dst.
+struct NoEpi {};
+
+template <bool INV, int P, int RB, class EPI = NoEpi, class X>
+FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p, const EPI* epi = nullptr) {
+  constexpr bool plain = std::is_same<EPI, NoEpi>::value;
+  constexpr bool stage_out = !INV;
   const int n1 = a.n1, cb = a.lcpb, T = x.nt, logn = a.logn;
   const int row = x.by;
   const long long e0 = (long long)x.bx << (P + cb);
@@ -266,7 +276,7 @@ FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
         const int base = ch << P;
         auto ld = [&](int lo) { return first ? u2d(src[base + lo]) : sm[base + lo]; };
         auto st = [&](int lo, double v) {
-          if (last) dst[base + lo] = d2u(norm(v, q));
+          if (last && !stage_out) dst[base + lo] = d2u(norm(v, q));
           else sm[base + lo] = v;
         };
         if constexpr (!INV) {
@@ -285,6 +295,14 @@ FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p) {
       }
     });
   });
+  if constexpr (stage_out) {
+    x.phase([&](int t) {
+      for (int g = t; g < (1 << (P + cb)); g += T) {
+        if constexpr (plain) dst[g] = d2u(norm(sm[g], q));
+        else epi_store(*epi, row, e0 + g, sm[g], q, qi);
+      }
+    });
+  }
 }
 
 // Kernel entries: radix-8 rounds (RB = 3) and radix-16 rounds (RB = 4).
@@ -544,7 +562,7 @@ struct AddTerm {
 };
 struct TailArgs {
   const u64* acc;    // [nout][2][le][N] (Q limbs NTT form)
-  const u64* conv;   // [nout][2][nl][N]
+  const u64* conv;   // [nout][2][nl][N] converted values (input of the NTT that applies the tail)
   const TailItem* items;
   const AddTerm* terms;
   int o0;
@@ -556,28 +574,44 @@ struct TailArgs {
   const d2* pq;
 };
 
-template <class X>
-FENC_HD void moddown_tail(X& x, const TailArgs& a) {
-  x.phase([&](int t) {
-    const long long N = 1LL << a.logn;
-    const long long c = (long long)x.bx * x.nt + t;
-    const int i = x.by % a.nl, poly = x.by / a.nl, o = a.o0 + x.bz;
-    const double q = a.pq[i].x, qi = a.pq[i].y;
-    const double av = u2d(a.acc[((long long)o * 2 + poly) * a.le * N + i * N + c]);
-    const double cv = u2d(a.conv[((long long)o * 2 + poly) * a.nl * N + i * N + c]);
-    double r = mulmod_c(av - cv, a.pinv[i].x, a.pinv[i].y, q);
-    const TailItem I = a.items[o];
-    if (I.base >= 0) r += u2d(a.base[I.base * a.base_cs + poly * a.base_ps + i * N + c]);
-    if (poly == 0)
-      for (int k = 0; k < I.add_n; k++) {
-        const AddTerm T = a.terms[I.add_off + k];
-        const long long src = (T.g == 1) ? c : (long long)auto_src((unsigned)c, T.g, a.logn);
-        r += u2d(a.add[T.ct * a.add_cs + i * N + src]);
-        if ((k & 3) == 3) r = red(r, q, qi);
-      }
-    a.out[I.out * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(red(r, q, qi), q));
-  });
+// Output word (o, poly, limb i, coefficient c) from the converted value cv
+// (|cv| < q; |acc - cv| < 2q).
+FENC_HD inline void tail_value(const TailArgs& a, int o, int poly, int i, long long c, double cv, double q, double qi) {
+  const long long N = 1LL << a.logn;
+  const double av = u2d(a.acc[((long long)o * 2 + poly) * a.le * N + i * N + c]);
+  double r = mulmod_c(av - cv, a.pinv[i].x, a.pinv[i].y, q);
+  const TailItem I = a.items[o];
+  if (I.base >= 0) r += u2d(a.base[I.base * a.base_cs + poly * a.base_ps + i * N + c]);
+  if (poly == 0)
+    for (int k = 0; k < I.add_n; k++) {
+      const AddTerm T = a.terms[I.add_off + k];
+      const long long src = (T.g == 1) ? c : (long long)auto_src((unsigned)c, T.g, a.logn);
+      r += u2d(a.add[T.ct * a.add_cs + i * N + src]);
+      if ((k & 3) == 3) r = red(r, q, qi);
+    }
+  a.out[I.out * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(red(r, q, qi), q));
 }
+
+// The tail is the epilogue of the forward row pass that finishes the NTT of
+// the converted values (rows: [output][poly][limb], limb = prime index), so
+// the converted values never return to memory.
+FENC_HD inline void epi_store(const TailArgs& a, int row, long long c, double v, double q, double qi) {
+  const int i = row % a.nl, grp = row / a.nl;
+  tail_value(a, a.o0 + (grp >> 1), grp & 1, i, c, v, q, qi);
+}
+
+struct NttMdArgs {
+  NttArgs n;
+  TailArgs t;
+};
+template <int RB, class X>
+FENC_HD void ntt_fwd_rows_md_rb(X& x, const NttMdArgs& a) {
+  const int p = a.n.pm.p[x.by % a.n.pm.n];
+  if (p == kSkip) return;
+  with_pass(a.n.n2, [&](auto P) { ntt_rows_pass<false, decltype(P)::value, RB>(x, a.n, p, &a.t); });
+}
+template <class X> FENC_HD void ntt_fwd_rows_md(X& x, const NttMdArgs& a) { ntt_fwd_rows_md_rb<3>(x, a); }
+template <class X> FENC_HD void ntt_fwd_rows16_md(X& x, const NttMdArgs& a) { ntt_fwd_rows_md_rb<4>(x, a); }
 
 // ------------------------------------------------------------------ rescale
 // last: coefficient form of limb l (rows [B][2]); lift centred value to each q_i, i < l
@@ -607,25 +641,34 @@ FENC_HD void rescale_lift(X& x, const LiftArgs& a) {
 
 struct RescaleTailArgs {
   const u64* in;     // [B][2][nl+1][N]
-  const u64* lift;   // [B*2][nl][N] NTT form
+  const u64* lift;   // [B*2][nl][N] lifted last limb (input of the NTT that applies the tail)
   u64* out;          // [B][2][nl][N]
   int nl, logn;
   const d2* qlinv;   // [nl]
   const d2* pq;
 };
 
-template <class X>
-FENC_HD void rescale_tail(X& x, const RescaleTailArgs& a) {
-  x.phase([&](int t) {
-    const long long N = 1LL << a.logn;
-    const long long c = (long long)x.bx * x.nt + t;
-    const int i = x.by % a.nl, r = x.by / a.nl;   // r = ct*2 + poly
-    const double q = a.pq[i].x;
-    const double v = u2d(a.in[((long long)r * (a.nl + 1) + i) * N + c]);
-    const double w = u2d(a.lift[((long long)r * a.nl + i) * N + c]);
-    a.out[((long long)r * a.nl + i) * N + c] = d2u(norm(mulmod_c(v - w, a.qlinv[i].x, a.qlinv[i].y, q), q));
-  });
+// The rescale tail as the epilogue of the forward row pass that finishes the
+// NTT of the lifted last limb (rows: [ct * 2 + poly][limb]); w in [-q/2, q/2].
+FENC_HD inline void epi_store(const RescaleTailArgs& a, int row, long long c, double w, double q, double) {
+  const long long N = 1LL << a.logn;
+  const int i = row % a.nl, r = row / a.nl;   // r = ct*2 + poly
+  const double v = u2d(a.in[((long long)r * (a.nl + 1) + i) * N + c]);
+  a.out[((long long)r * a.nl + i) * N + c] = d2u(norm(mulmod_c(v - w, a.qlinv[i].x, a.qlinv[i].y, q), q));
 }
+
+struct NttRsArgs {
+  NttArgs n;
+  RescaleTailArgs t;
+};
+template <int RB, class X>
+FENC_HD void ntt_fwd_rows_rs_rb(X& x, const NttRsArgs& a) {
+  const int p = a.n.pm.p[x.by % a.n.pm.n];
+  if (p == kSkip) return;
+  with_pass(a.n.n2, [&](auto P) { ntt_rows_pass<false, decltype(P)::value, RB>(x, a.n, p, &a.t); });
+}
+template <class X> FENC_HD void ntt_fwd_rows_rs(X& x, const NttRsArgs& a) { ntt_fwd_rows_rs_rb<3>(x, a); }
+template <class X> FENC_HD void ntt_fwd_rows16_rs(X& x, const NttRsArgs& a) { ntt_fwd_rows_rs_rb<4>(x, a); }
 
 // ------------------------------------------------------------------ lift to the extended basis
 // out[t] = P x_t on the nl Q limbs and 0 on the K special limbs ([2][le][N],

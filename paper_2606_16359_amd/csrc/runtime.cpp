@@ -207,7 +207,8 @@ const LevelTabs& level_tabs(Ctx& C, int level) {
 
 // ---------------------------------------------------------------- NTT
 void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long long dst_gs, int nrows, int nl,
-         const fk::PrimeMap& pm, fb::Stream s) {
+         const fk::PrimeMap& pm, fb::Stream s, const fk::TailArgs* md, double md_bytes,
+         const fk::RescaleTailArgs* rs) {
   if (nrows <= 0) return;
   fk::NttArgs a;
   a.src = src;
@@ -249,10 +250,24 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
     });
     a.src = dst;
     a.src_gs = dst_gs;
-    timed(C, "ntt_fwd_rows", pass_bytes, s, [&] {
-      if (fr[0] == 4) fb::ntt_fwd_rows16(gr, fr[2], lds_r, s, a);
-      else fb::ntt_fwd_rows(gr, fr[2], lds_r, s, a);
-    });
+    if (md) {   // the row pass ends in the ModDown tail
+      const fk::NttMdArgs m{a, *md};
+      timed(C, "ntt_fwd_rows_md", md_bytes, s, [&] {
+        if (fr[0] == 4) fb::ntt_fwd_rows16_md(gr, fr[2], lds_r, s, m);
+        else fb::ntt_fwd_rows_md(gr, fr[2], lds_r, s, m);
+      });
+    } else if (rs) {   // the row pass ends in the rescale tail
+      const fk::NttRsArgs m{a, *rs};
+      timed(C, "ntt_fwd_rows_rs", md_bytes, s, [&] {
+        if (fr[0] == 4) fb::ntt_fwd_rows16_rs(gr, fr[2], lds_r, s, m);
+        else fb::ntt_fwd_rows_rs(gr, fr[2], lds_r, s, m);
+      });
+    } else {
+      timed(C, "ntt_fwd_rows", pass_bytes, s, [&] {
+        if (fr[0] == 4) fb::ntt_fwd_rows16(gr, fr[2], lds_r, s, a);
+        else fb::ntt_fwd_rows(gr, fr[2], lds_r, s, a);
+      });
+    }
     C.cnt.ntt_limbs += active;
   } else {
     timed(C, "ntt_inv_rows", pass_bytes, s, [&] {
@@ -451,7 +466,6 @@ static void moddown_part(Ctx& C, int level, u64* acc, u64* conv, const KsStage& 
     fb::moddown_fbc({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, m);
   });
   u64* conv0 = conv + (long long)o0 * 2 * nl * N;
-  ntt(C, false, conv0, conv0, (long long)nl * N, (long long)nl * N, no * 2 * nl, nl, identity_map(nl), s);
   fk::TailArgs t;
   t.acc = acc;
   t.conv = conv;
@@ -471,12 +485,12 @@ static void moddown_part(Ctx& C, int level, u64* acc, u64* conv, const KsStage& 
   t.add_cs = add_cs;
   t.pinv = C.pinv;
   t.pq = C.pq;
+  // NTT of the converted values; its row pass applies the tail: reads the
+  // converted words and acc, writes the output (plus base and added words)
   const double frac = (double)no / st.n_out;
   const double tb = (6.0 * no + 2.0 * st.n_base * frac + st.n_adds * frac) * nl * N * 8;
-  timed(C, "moddown_tail", tb, s, [&] {
-    fb::moddown_tail({(unsigned)(N / block_threads(C)), (unsigned)(2 * nl), (unsigned)no}, block_threads(C), s, t);
-  });
-  C.cnt.launches += 2;
+  ntt(C, false, conv0, conv0, (long long)nl * N, (long long)nl * N, no * 2 * nl, nl, identity_map(nl), s, &t, tb);
+  C.cnt.launches += 1;
   C.cnt.moddown += no;
 }
 
@@ -586,13 +600,13 @@ void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
                     (double)C.primes[level], C.pq};
     timed(C, "rescale_lift", 2.0 * nb * (1 + nl) * N * 8, s,
           [&] { fb::rescale_lift({(unsigned)(N / block_threads(C)), (unsigned)(nb * 2), 1}, block_threads(C), s, la); });
+    // NTT of the lifted limb; its row pass applies the tail (reads the lifted
+    // words and the input, writes the output)
     u64* l0 = lift + (long long)b0 * 2 * nl * N;
-    ntt(C, false, l0, l0, (long long)nl * N, (long long)nl * N, nb * 2 * nl, nl, identity_map(nl), s);
     fk::RescaleTailArgs ra{in + b0 * in_cs, l0, out + b0 * out_cs, nl, C.logn, T.qlinv, C.pq};
-    timed(C, "rescale_tail", 6.0 * nb * nl * N * 8, s, [&] {
-      fb::rescale_tail({(unsigned)(N / block_threads(C)), (unsigned)(nb * 2 * nl), 1}, block_threads(C), s, ra);
-    });
-    C.cnt.launches += 2;
+    ntt(C, false, l0, l0, (long long)nl * N, (long long)nl * N, nb * 2 * nl, nl, identity_map(nl), s, nullptr,
+        6.0 * nb * nl * N * 8, &ra);
+    C.cnt.launches += 1;
     C.cnt.rescale += nb;
   }
 }
