@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1319468353, "ntt_fwd_rows": 252631363, "gmac_diag": 352230757, "gmac_pt_fast": 1520354662, "ntt_inv_rows": 73439239, "ntt_inv_cols": 68107059, "modup_fbc": 256664207, "gmac_fast": 623982234, "moddown_fbc": 151115943, "tensor_square": 477122887, "lift_pq": 187026312, "rescale_lift": 101859929}
+TRAFFIC = {"kip": 1319771547, "ntt_fwd_cols16": 225520616, "gmac_diag": 352318694, "ntt_fwd_rows_md": 388243176, "gmac_pt_fast": 1520827676, "ntt_fwd_rows": 278895876, "ntt_fwd_rows_rs": 300173953, "ntt_inv_cols": 68029794, "modup_fbc": 256651584, "gmac_fast": 623961896, "moddown_fbc": 151130439, "tensor_square": 477120949, "lift_pq": 187025540, "rescale_lift": 101871133}
 
 
 def log(*a):
