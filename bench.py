@@ -25,11 +25,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
 KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv_fast", "gmac_diag", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "ntt_fwd_rows_md", "ntt_fwd_rows_rs",
-           "moddown_fbc", "modup_fbc", "rescale_lift", "tensor_square", "lin_comb", "lift_pq"]
+           "moddown_fbc", "modup_fbc", "ntt_fwd_cols_lift", "tensor_square", "lin_comb", "lift_pq"]
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1319771547, "ntt_fwd_cols16": 225520616, "gmac_diag": 352318694, "ntt_fwd_rows_md": 388243176, "gmac_pt_fast": 1520827676, "ntt_fwd_rows": 278895876, "ntt_fwd_rows_rs": 300173953, "ntt_inv_cols": 68029794, "modup_fbc": 256651584, "gmac_fast": 623961896, "moddown_fbc": 151130439, "tensor_square": 477120949, "lift_pq": 187025540, "rescale_lift": 101871133}
+TRAFFIC = {"kip": 1319771547, "ntt_fwd_cols16": 225520616, "gmac_diag": 352318694, "ntt_fwd_rows_md": 388243176, "gmac_pt_fast": 1520827676, "ntt_fwd_rows": 278895876, "ntt_fwd_rows_rs": 300173953, "ntt_inv_cols": 68029794, "modup_fbc": 256651584, "gmac_fast": 623961896, "moddown_fbc": 151130439, "tensor_square": 477120949, "lift_pq": 187025540}
 
 
 def log(*a):

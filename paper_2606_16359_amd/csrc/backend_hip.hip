@@ -88,12 +88,13 @@ FENC_KERNEL_LDS(ntt_fwd_rows_md, NttMdArgs)
 FENC_KERNEL_LDS(ntt_fwd_rows16_md, NttMdArgs)
 FENC_KERNEL_LDS(ntt_fwd_rows_rs, NttRsArgs)
 FENC_KERNEL_LDS(ntt_fwd_rows16_rs, NttRsArgs)
+FENC_KERNEL_LDS(ntt_fwd_cols_lift, NttLiftArgs)
+FENC_KERNEL_LDS(ntt_fwd_cols16_lift, NttLiftArgs)
 FENC_KERNEL_LDS(ntt_inv_rows16, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_cols16, NttArgs)
 FENC_KERNEL(modup_fbc, ModUpArgs)
 FENC_KERNEL(kip, KipArgs)
 FENC_KERNEL(moddown_fbc, ModDownArgs)
-FENC_KERNEL(rescale_lift, LiftArgs)
 FENC_KERNEL_XCD(gmac, GmacArgs)
 FENC_KERNEL_XCD(gmac_pt, GmacArgs)
 FENC_KERNEL_XCD(gmac_fast, GmacArgs)

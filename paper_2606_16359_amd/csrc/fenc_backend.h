@@ -40,13 +40,14 @@ void ntt_fwd_rows16(Grid g, int threads, size_t smem, Stream s, const fk::NttArg
 void ntt_fwd_rows_md(Grid g, int threads, size_t smem, Stream s, const fk::NttMdArgs& a);
 void ntt_fwd_rows16_md(Grid g, int threads, size_t smem, Stream s, const fk::NttMdArgs& a);
 void ntt_fwd_rows_rs(Grid g, int threads, size_t smem, Stream s, const fk::NttRsArgs& a);
+void ntt_fwd_cols_lift(Grid g, int threads, size_t smem, Stream s, const fk::NttLiftArgs& a);
+void ntt_fwd_cols16_lift(Grid g, int threads, size_t smem, Stream s, const fk::NttLiftArgs& a);
 void ntt_fwd_rows16_rs(Grid g, int threads, size_t smem, Stream s, const fk::NttRsArgs& a);
 void ntt_inv_rows16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void ntt_inv_cols16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void modup_fbc(Grid g, int threads, Stream s, const fk::ModUpArgs& a);
 void kip(Grid g, int threads, Stream s, const fk::KipArgs& a);
 void moddown_fbc(Grid g, int threads, Stream s, const fk::ModDownArgs& a);
-void rescale_lift(Grid g, int threads, Stream s, const fk::LiftArgs& a);
 void gmac(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_pt(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_fast(Grid g, int threads, Stream s, const fk::GmacArgs& a);

@@ -194,13 +194,17 @@ FENC_HD inline void with_count(int n, B body) {
   }
 }
 
+struct NoPro {};
+
 // Column pass: stages acting on 2^n1 elements at stride 2^n2 ("columns").  A
 // block stages 2^lcols adjacent columns; the column index is the low part of
 // the thread's group index so neighbouring threads touch neighbouring words.
 // Forward: the first n1 stages; inverse: the last n1 stages, then * N^-1.
 // The first round reads HBM, the last writes HBM, the others use LDS.
-template <bool INV, int P, int RB, class X>
-FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
+// With a prologue (PRO other than NoPro) the first round takes each input
+// value from pro_load(row, element) (magnitude < q) instead of reading src.
+template <bool INV, int P, int RB, class PRO = NoPro, class X>
+FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p, const PRO* pro = nullptr) {
   const int n2 = a.n2, sb = a.lcols, T = x.nt, bm = (1 << sb) - 1;
   const int row = x.by;
   const u64* src = a.src + (long long)(row / a.nl) * a.src_gs + ((long long)(row % a.nl) << a.logn);
@@ -217,7 +221,14 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p) {
     x.phase([&](int t) {
       for (int g = t; g < (1 << (P + sb - K)); g += T) {
         const int c = g & bm, rest = g >> sb;
-        auto ld = [&](int hi) { return first ? u2d(src[((long long)hi << n2) + col0 + c]) : sm[(hi << sb) | c]; };
+        auto ld = [&](int hi) {
+          if constexpr (!std::is_same<PRO, NoPro>::value) {
+            if (first) return pro_load(*pro, row, ((long long)hi << n2) + col0 + c, q, qi);
+          } else {
+            if (first) return u2d(src[((long long)hi << n2) + col0 + c]);
+          }
+          return sm[(hi << sb) | c];
+        };
         if constexpr (!INV) {
           fwd_round<K>(
               rest, s0, P, q, qi, ld,
@@ -617,27 +628,34 @@ template <class X> FENC_HD void ntt_fwd_rows16_md(X& x, const NttMdArgs& a) { nt
 // last: coefficient form of limb l (rows [B][2]); lift centred value to each q_i, i < l
 struct LiftArgs {
   const u64* last;   // [B*2][N]
-  u64* out;          // [B*2][nl][N]
+  u64* out;          // [B*2][nl][N] (unused: the lifted values feed the NTT directly)
   int nl, logn;
   double ql;
   const d2* pq;
 };
 
-template <class X>
-FENC_HD void rescale_lift(X& x, const LiftArgs& a) {
-  x.phase([&](int t) {
-    const long long N = 1LL << a.logn;
-    const long long c = (long long)x.bx * x.nt + t;
-    const int r = x.by;
-    double v = u2d(a.last[(long long)r * N + c]);
-    if (v > (a.ql - 1) * 0.5) v -= a.ql;   // centred representative
-    u64* o = a.out + (long long)r * a.nl * N + c;
-    for (int i = 0; i < a.nl; i++) {
-      const double q = a.pq[i].x, qi = a.pq[i].y;
-      o[(long long)i * N] = d2u(norm(red(v, q, qi), q));
-    }
-  });
+// The lift as the prologue of the forward column pass over the lifted rows
+// ([ct * 2 + poly][limb]): the rows of one ct and poly share the last limb's
+// words, so the lifted values are never written.
+FENC_HD inline double pro_load(const LiftArgs& a, int row, long long c, double q, double qi) {
+  const long long N = 1LL << a.logn;
+  double v = u2d(a.last[(long long)(row / a.nl) * N + c]);
+  if (v > (a.ql - 1) * 0.5) v -= a.ql;   // centred representative
+  return red(v, q, qi);
 }
+
+struct NttLiftArgs {
+  NttArgs n;
+  LiftArgs l;
+};
+template <int RB, class X>
+FENC_HD void ntt_fwd_cols_lift_rb(X& x, const NttLiftArgs& a) {
+  const int p = a.n.pm.p[x.by % a.n.pm.n];
+  if (p == kSkip) return;
+  with_pass(a.n.n1, [&](auto P) { ntt_cols_pass<false, decltype(P)::value, RB>(x, a.n, p, &a.l); });
+}
+template <class X> FENC_HD void ntt_fwd_cols_lift(X& x, const NttLiftArgs& a) { ntt_fwd_cols_lift_rb<3>(x, a); }
+template <class X> FENC_HD void ntt_fwd_cols16_lift(X& x, const NttLiftArgs& a) { ntt_fwd_cols_lift_rb<4>(x, a); }
 
 struct RescaleTailArgs {
   const u64* in;     // [B][2][nl+1][N]

@@ -208,7 +208,7 @@ const LevelTabs& level_tabs(Ctx& C, int level) {
 // ---------------------------------------------------------------- NTT
 void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long long dst_gs, int nrows, int nl,
          const fk::PrimeMap& pm, fb::Stream s, const fk::TailArgs* md, double md_bytes,
-         const fk::RescaleTailArgs* rs) {
+         const fk::RescaleTailArgs* rs, const fk::LiftArgs* lift, double lift_bytes) {
   if (nrows <= 0) return;
   fk::NttArgs a;
   a.src = src;
@@ -244,10 +244,18 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
   const double pass_bytes = 16.0 * active * C.N;   // read + write of every active row
   const fb::Grid gc{colblocks, (unsigned)nrows, 1}, gr{rowblocks, (unsigned)nrows, 1};
   if (!inverse) {
-    timed(C, "ntt_fwd_cols", pass_bytes, s, [&] {
-      if (fc[0] == 4) fb::ntt_fwd_cols16(gc, fc[2], lds_c, s, a);
-      else fb::ntt_fwd_cols(gc, fc[2], lds_c, s, a);
-    });
+    if (lift) {   // the column pass starts from the rescale lift
+      const fk::NttLiftArgs m{a, *lift};
+      timed(C, "ntt_fwd_cols_lift", lift_bytes, s, [&] {
+        if (fc[0] == 4) fb::ntt_fwd_cols16_lift(gc, fc[2], lds_c, s, m);
+        else fb::ntt_fwd_cols_lift(gc, fc[2], lds_c, s, m);
+      });
+    } else {
+      timed(C, "ntt_fwd_cols", pass_bytes, s, [&] {
+        if (fc[0] == 4) fb::ntt_fwd_cols16(gc, fc[2], lds_c, s, a);
+        else fb::ntt_fwd_cols(gc, fc[2], lds_c, s, a);
+      });
+    }
     a.src = dst;
     a.src_gs = dst_gs;
     if (md) {   // the row pass ends in the ModDown tail
@@ -596,17 +604,14 @@ void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
     const long long in_cs = 2LL * (level + 1) * N, out_cs = 2LL * nl * N;
     ntt(C, true, in + b0 * in_cs + (long long)level * N, last + (long long)b0 * 2 * N, (long long)(level + 1) * N,
         N, nb * 2, 1, pl, s);
-    fk::LiftArgs la{last + (long long)b0 * 2 * N, lift + (long long)b0 * 2 * nl * N, nl, C.logn,
-                    (double)C.primes[level], C.pq};
-    timed(C, "rescale_lift", 2.0 * nb * (1 + nl) * N * 8, s,
-          [&] { fb::rescale_lift({(unsigned)(N / block_threads(C)), (unsigned)(nb * 2), 1}, block_threads(C), s, la); });
-    // NTT of the lifted limb; its row pass applies the tail (reads the lifted
-    // words and the input, writes the output)
+    // NTT of the last limb lifted to every other limb: the column pass lifts
+    // as it loads (reads the last limb, writes the lifted rows' first pass),
+    // the row pass applies the tail (reads them and the input, writes the output)
     u64* l0 = lift + (long long)b0 * 2 * nl * N;
+    fk::LiftArgs la{last + (long long)b0 * 2 * N, l0, nl, C.logn, (double)C.primes[level], C.pq};
     fk::RescaleTailArgs ra{in + b0 * in_cs, l0, out + b0 * out_cs, nl, C.logn, T.qlinv, C.pq};
     ntt(C, false, l0, l0, (long long)nl * N, (long long)nl * N, nb * 2 * nl, nl, identity_map(nl), s, nullptr,
-        6.0 * nb * nl * N * 8, &ra);
-    C.cnt.launches += 1;
+        6.0 * nb * nl * N * 8, &ra, &la, (2.0 * nb + 8.0 * nb * nl) * N * 8);
     C.cnt.rescale += nb;
   }
 }

@@ -219,10 +219,12 @@ d2 cpair(uint64_t w, uint64_t q);   // (w, w/q)
 
 // NTT of rows: row r reads src + (r/nl)*src_gs + (r%nl)*N, prime pm.p[r % pm.n]
 // md or rs (forward only): the row pass ends in that ModDown or rescale tail
-// instead of writing dst (md_bytes: the fused row pass's algorithmic bytes)
+// instead of writing dst (md_bytes: the fused row pass's algorithmic bytes);
+// lift: the column pass takes its input from that rescale lift instead of src
+// (lift_bytes: its algorithmic bytes)
 void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long long dst_gs, int nrows, int nl,
          const fk::PrimeMap& pm, fb::Stream s, const fk::TailArgs* md = nullptr, double md_bytes = 0,
-         const fk::RescaleTailArgs* rs = nullptr);
+         const fk::RescaleTailArgs* rs = nullptr, const fk::LiftArgs* lift = nullptr, double lift_bytes = 0);
 fk::PrimeMap identity_map(int n);
 
 // key switching pieces

@@ -71,12 +71,13 @@ EMU_LDS(ntt_fwd_rows_md, NttMdArgs)
 EMU_LDS(ntt_fwd_rows16_md, NttMdArgs)
 EMU_LDS(ntt_fwd_rows_rs, NttRsArgs)
 EMU_LDS(ntt_fwd_rows16_rs, NttRsArgs)
+EMU_LDS(ntt_fwd_cols_lift, NttLiftArgs)
+EMU_LDS(ntt_fwd_cols16_lift, NttLiftArgs)
 EMU_LDS(ntt_inv_rows16, NttArgs)
 EMU_LDS(ntt_inv_cols16, NttArgs)
 EMU(modup_fbc, ModUpArgs)
 EMU(kip, KipArgs)
 EMU(moddown_fbc, ModDownArgs)
-EMU(rescale_lift, LiftArgs)
 EMU_XCD(gmac, GmacArgs)
 EMU_XCD(gmac_pt, GmacArgs)
 EMU_XCD(gmac_fast, GmacArgs)
