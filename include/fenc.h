@@ -26,11 +26,13 @@
  *  - Asynchrony: operations enqueue work on `stream` (a hipStream_t, NULL is
  *    the default stream) and return; keep buffers alive until the stream is
  *    synchronised.  Calls on one context are not thread-safe.
- *  - Operations allocate their workspace from a context-owned arena that only
- *    grows; the first call of an operation with a given shape builds and
- *    caches its plan (encoded plaintexts, index tables) and may allocate.  A
- *    repeated call with the same shapes and weights allocates nothing and can
- *    be captured into a hipGraph.
+ *  - Operations allocate their workspace from a context-owned arena; it grows
+ *    to the largest operation run so far (returning smaller free chunks to
+ *    the device first, after a device-wide synchronisation) and keeps every
+ *    chunk used during a stream capture.  The first call of an operation with
+ *    a given shape builds and caches its plan (encoded plaintexts, index
+ *    tables) and may allocate.  A repeated call with the same shapes and
+ *    weights allocates nothing and can be captured into a hipGraph.
  *  - Secret material: the context holds the secret key (client role) and the
  *    evaluation keys (server role) at once; this library is the hot path, not
  *    a key-management system.
