@@ -20,6 +20,24 @@ struct d2 {
   double x, y;
 };
 
+#ifndef FENC_AI
+#define FENC_AI __attribute__((always_inline)) inline
+#endif
+#ifndef FENC_GLOBAL
+#define FENC_GLOBAL
+#endif
+// Loads and stores through device pointers known to address global memory;
+// w2: two adjacent words, 16-byte aligned.
+typedef u64 w2 __attribute__((vector_size(16)));
+FENC_HD FENC_AI u64 ldg(const u64* p) { return *(const FENC_GLOBAL u64*)p; }
+FENC_HD FENC_AI w2 ldg2(const u64* p) { return *(const FENC_GLOBAL w2*)p; }
+FENC_HD FENC_AI void stg2(u64* p, u64 x, u64 y) {
+  w2 v;
+  v[0] = x;
+  v[1] = y;
+  *(FENC_GLOBAL w2*)p = v;
+}
+
 constexpr int kMaxMap = 128;
 constexpr unsigned char kSkip = 255;
 
@@ -448,63 +466,99 @@ struct KipArgs {
   long long c0_cs;
   const d2* pmod;         // [nl] P mod q_i
   int nl;
+  int width;              // outputs per group slot row: 1, 2, 4 or kKipOut (>= every group's nout)
 };
 
-template <class X>
-FENC_HD void kip(X& x, const KipArgs& a) {
-  x.phase([&](int t) {
+// A thread handles the coefficient pair (c, c+1), c even, with 16-byte
+// accesses: sigma_g maps the evaluation points of a pair, w and -w, to w^g and
+// -w^g, which are again a pair (m, m+1) in the bit-reversed order, swapped
+// when auto_src(c) is odd.  W (1, 2, 4 or 8) is the launch's largest group
+// padded to a power of two; padded slots read ct 0's words, which exist, and
+// are computed but never stored, so every load is used and the loads in
+// flight are counted exactly.
+template <int W, class X>
+FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
+  x.phase([&](int t) __attribute__((always_inline)) {
     const long long N = 1LL << a.logn;
-    const long long c = (long long)x.bx * x.nt + t;
+    const long long c = 2 * ((long long)x.bx * x.nt + t);
     const int l = x.by;
     const KipGroup G = a.groups[a.g0 + x.bz];
     const int p = a.eprime[l];
     const double q = a.pq[p].x, qi = a.pq[p].y;
     const long long es = (long long)a.beta * a.le * N;   // ext ct stride
-    double a0[kKipOut], a1[kKipOut];
+    double a0[W][2], a1[W][2];
 #pragma unroll
-    for (int o = 0; o < kKipOut; o++) a0[o] = a1[o] = 0;
+    for (int o = 0; o < W; o++) a0[o][0] = a0[o][1] = a1[o][0] = a1[o][1] = 0;
     for (int kk = 0; kk < G.nkey; kk++) {
       const KipKey K = a.keys[G.key0 + kk];
       const long long src = (K.g == 1) ? c : (long long)auto_src((unsigned)c, K.g, a.logn);
+      const long long m = src & ~1LL;
+      const bool sw = (src & 1) != 0;
       // item lists are padded to kKipOut entries; -1 marks no item
-      int ct[kKipOut];
+      int ct[W];
 #pragma unroll
-      for (int o = 0; o < kKipOut; o++) ct[o] = a.items[K.item0 + o];
+      for (int o = 0; o < W; o++) {
+        ct[o] = a.items[K.item0 + o];
+        ct[o] = ct[o] >= 0 ? ct[o] : 0;
+      }
       for (int j = 0; j < a.beta; j++) {
         const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
-        const u64* ej = a.ext + ((long long)j * a.le + l) * N + src;
-        // every output's word for this digit is requested before any is used
-        double v[kKipOut];
+        const u64* ej = a.ext + ((long long)j * a.le + l) * N + m;
+        // every output's words for this digit are requested before any is used
+        w2 v[W];
 #pragma unroll
-        for (int o = 0; o < kKipOut; o++) v[o] = ct[o] >= 0 ? u2d(ej[ct[o] * es]) : 0.0;
-        const double k0 = u2d(kj[0]), k1 = u2d(kj[(long long)a.nprimes * N]);
+        for (int o = 0; o < W; o++) v[o] = ldg2(ej + (long long)ct[o] * es);
+        const w2 k0 = ldg2(kj), k1 = ldg2(kj + (long long)a.nprimes * N);
+        const double k00 = u2d(k0[0]), k01 = u2d(k0[1]), k10 = u2d(k1[0]), k11 = u2d(k1[1]);
 #pragma unroll
-        for (int o = 0; o < kKipOut; o++) {
-          if (ct[o] < 0) continue;
-          a0[o] = red(a0[o] + mulmod(v[o], k0, q, qi), q, qi);
-          a1[o] = red(a1[o] + mulmod(v[o], k1, q, qi), q, qi);
+        for (int o = 0; o < W; o++) {
+          const double e0 = u2d(sw ? v[o][1] : v[o][0]), e1 = u2d(sw ? v[o][0] : v[o][1]);
+          a0[o][0] = red(a0[o][0] + mulmod(e0, k00, q, qi), q, qi);
+          a0[o][1] = red(a0[o][1] + mulmod(e1, k01, q, qi), q, qi);
+          a1[o][0] = red(a1[o][0] + mulmod(e0, k10, q, qi), q, qi);
+          a1[o][1] = red(a1[o][1] + mulmod(e1, k11, q, qi), q, qi);
         }
       }
       if (a.c0 && l < a.nl) {
-        int t0[kKipOut];
-        double cv[kKipOut];
+        int t0[W];
+        bool use[W];
+        w2 cv[W];
 #pragma unroll
-        for (int o = 0; o < kKipOut; o++) t0[o] = a.c0ct[K.item0 + o];
+        for (int o = 0; o < W; o++) {
+          t0[o] = a.c0ct[K.item0 + o];
+          use[o] = t0[o] >= 0;
+          t0[o] = use[o] ? t0[o] : 0;
+        }
 #pragma unroll
-        for (int o = 0; o < kKipOut; o++) cv[o] = t0[o] >= 0 ? u2d(a.c0[t0[o] * a.c0_cs + l * N + src]) : 0.0;
+        for (int o = 0; o < W; o++) cv[o] = ldg2(a.c0 + (long long)t0[o] * a.c0_cs + (long long)l * N + m);
+        // items without a folded c0 take the factor 0 (their words are still used)
 #pragma unroll
-        for (int o = 0; o < kKipOut; o++)
-          if (t0[o] >= 0) a0[o] = red(a0[o] + mulmod_c(cv[o], a.pmod[l].x, a.pmod[l].y, q), q, qi);
+        for (int o = 0; o < W; o++) {
+          const double pw = use[o] ? a.pmod[l].x : 0.0, pwq = use[o] ? a.pmod[l].y : 0.0;
+          const double e0 = u2d(sw ? cv[o][1] : cv[o][0]), e1 = u2d(sw ? cv[o][0] : cv[o][1]);
+          a0[o][0] = red(a0[o][0] + mulmod_c(e0, pw, pwq, q), q, qi);
+          a0[o][1] = red(a0[o][1] + mulmod_c(e1, pw, pwq, q), q, qi);
+        }
       }
     }
 #pragma unroll
-    for (int o = 0; o < kKipOut; o++) {
+    for (int o = 0; o < W; o++) {
       if (o >= G.nout) continue;
-      u64* out = a.acc + (long long)(G.out0 + o) * 2 * a.le * N + l * N + c;
-      out[0] = d2u(norm(a0[o], q));
-      out[a.le * N] = d2u(norm(a1[o], q));
+      u64* out = a.acc + (long long)(G.out0 + o) * 2 * a.le * N + (long long)l * N + c;
+      stg2(out, d2u(norm(a0[o][0], q)), d2u(norm(a0[o][1], q)));
+      stg2(out + (long long)a.le * N, d2u(norm(a1[o][0], q)), d2u(norm(a1[o][1], q)));
     }
   });
+}
+
+template <class X>
+FENC_HD void kip(X& x, const KipArgs& a) {
+  switch (a.width) {
+    case 1: kip_w<1>(x, a); break;
+    case 2: kip_w<2>(x, a); break;
+    case 4: kip_w<4>(x, a); break;
+    default: kip_w<kKipOut>(x, a); break;
+  }
 }
 
 // ------------------------------------------------------------------ ModDown
@@ -770,16 +824,6 @@ constexpr int kMacChunk = 8;   // input words requested together (classes with s
 // Plaintext products of a class: none, one plaintext per group shared by every
 // output of the class, or one per (group, output).
 enum { kPtNone = 0, kPtShared = 1, kPtEach = 2 };
-
-#ifndef FENC_AI
-#define FENC_AI __attribute__((always_inline)) inline
-#endif
-
-#ifndef FENC_GLOBAL
-#define FENC_GLOBAL
-#endif
-// Load through a device pointer known to address global memory.
-FENC_HD FENC_AI u64 ldg(const u64* p) { return *(const FENC_GLOBAL u64*)p; }
 
 // Requests the input words of terms k .. k+cnt-1 (cnt <= CH <= kMacChunk).  The term
 // table carries kMacChunk spare entries, so a whole chunk of indices is read

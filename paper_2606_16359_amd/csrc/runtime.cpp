@@ -510,7 +510,7 @@ static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int
   const KipTables& KT = per_op ? st.single : st.batched;
   const int g0 = per_op ? it : 0, ng = per_op ? 1 : KT.n;
   fk::KipArgs k{ext, acc, KT.groups, KT.keys, KT.items, g0, beta, le, C.logn, C.np, T.eprime, C.pq,
-                nullptr, nullptr, 0, nullptr, nl};
+                nullptr, nullptr, 0, nullptr, nl, per_op ? 1 : KT.width};
   if (c0 && KT.c0items) {
     k.c0ct = KT.c0items;
     k.c0 = c0;
@@ -521,7 +521,10 @@ static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int
   for (int g = g0; g < g0 + ng; g++) kb += KT.rd[g] * beta + KT.wr[g];
   kb *= (double)le * N * 8;
   timed(C, "kip", kb, s,
-        [&] { fb::kip({(unsigned)(N / block_threads(C)), (unsigned)le, (unsigned)ng}, block_threads(C), s, k); });
+        [&] {   // a thread per coefficient pair
+          const int kt = std::min(256, N / 2);
+          fb::kip({(unsigned)(N / 2 / kt), (unsigned)le, (unsigned)ng}, kt, s, k);
+        });
   C.cnt.launches += 1;
 }
 
@@ -708,6 +711,8 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
   }
   KipTables T;
   T.n = (int)groups.size();
+  for (auto& g : groups)
+    while (T.width < g.nout) T.width *= 2;
   T.groups = upload(C, groups, owner);
   T.keys = upload(C, keys, owner);
   T.items = upload(C, it, owner);

@@ -92,6 +92,7 @@ struct KipTables {
   fk::KipKey* keys = nullptr;
   int* items = nullptr;
   int* c0items = nullptr;          // parallel to items: folded c0 source, -1 none (null: no folding)
+  int width = 1;                   // largest group's output count, as a power of two
   std::vector<double> rd, wr;      // host: words per (limb, coefficient) read per digit / written
 };
 struct KsStage {
