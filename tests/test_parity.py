@@ -112,6 +112,29 @@ def test_encrypt_keys_and_keyswitch_building_blocks(backend, orc):
     assert np.array_equal(f.decrypt_raw(ct)[0], o.decrypt(oc))
 
 
+WIDE = (10, 10, 40, 10, 40, 1, 30, 19)   # one digit of 10 limbs, 10 special primes
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_keyswitch_with_digits_and_special_primes_above_eight(backend):
+    """A digit of 10 limbs and 10 special primes: the base conversions run in
+    their wide form (more than 8 limbs)."""
+    from oracle import pyoracle as P
+    o, f = P.Oracle(*WIDE), make(backend, *WIDE)
+    assert f.primes() == o.primes()
+    z = rng(2).uniform(-1, 1, o.ns)
+    pt = o.encode(z, None, 2.0 ** 30)
+    lay = f.plan_layout(1, 1, 16, 16, 3, 1)
+    ct = f.encrypt(pt[None], lay, 7)
+    oc = o.encrypt(pt, o.L, 2.0 ** 30, 7, 0)
+    cmp(ct, oc[None], f)
+    shifts = [1, 37, o.ns - 5]
+    cmp(f.rotate(ct, shifts), o.rotate(oc, shifts), f)
+    r = f.rotate(ct, [3, 9])
+    cmp(f.rotate_sum(ct, r, [1, 2]), o.rotate_sum(oc, o.rotate(oc, [3, 9]), [1, 2])[None], f)
+    cmp(f.rescale(ct), o.rescale(oc)[None], f)
+
+
 @pytest.mark.parametrize("backend", BACKENDS)
 @pytest.mark.parametrize("mode,budget,hoist", [(F.FENC_MODE_BATCHED, 1 << 30, 1), (F.FENC_MODE_PER_OP, 1 << 30, 1),
                                                (F.FENC_MODE_BATCHED, 0, 1), (F.FENC_MODE_BATCHED, 1 << 30, 0),
