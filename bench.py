@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1319771547, "ntt_fwd_cols16": 225520616, "gmac_diag": 352318694, "ntt_fwd_rows_md": 388243176, "gmac_pt_fast": 1520827676, "ntt_fwd_rows": 278895876, "ntt_fwd_rows_rs": 300173953, "ntt_inv_cols": 68029794, "modup_fbc": 256651584, "gmac_fast": 623961896, "moddown_fbc": 151130439, "tensor_square": 477120949, "lift_pq": 187025540}
+TRAFFIC = {"kip": 1320077117, "gmac_diag": 352011814, "ntt_fwd_rows_md": 384909285, "ntt_fwd_cols": 236304294, "gmac_pt_fast": 1520332574, "ntt_fwd_rows": 271767985, "ntt_fwd_rows_rs": 298085224, "ntt_inv_cols": 68046088, "modup_fbc": 256656138, "gmac_fast": 623962344, "moddown_fbc": 151120990, "tensor_square": 477121141, "lift_pq": 187016667, "ntt_fwd_cols_lift": 102182532}
 
 
 def log(*a):
