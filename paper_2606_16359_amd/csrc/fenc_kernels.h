@@ -780,6 +780,7 @@ FENC_HD void lift_pq(X& x, const LiftPqArgs& a) {
 // t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.  A null
 // plaintext means no product.
 constexpr int kMacOut = 8;
+static_assert(kMacOut == 8 || kMacOut == 16, "class rows are 1, 2, 4, 8 or 16 wide");
 
 struct MacClass {
   int g0, ng;        // groups g0 .. g0+ng-1 (terms shared by the outputs)
@@ -1129,6 +1130,7 @@ FENC_HD FENC_AI void gmac_width(X& x, const GmacArgs& a) {
     case 1: gmac_body<1, PTM, FAST, CH>(x, a); break;
     case 2: gmac_body<2, PTM, FAST, CH>(x, a); break;
     case 4: gmac_body<4, PTM, FAST, CH>(x, a); break;
+    case 8: gmac_body<(WMAX < 8 ? WMAX : 8), PTM, FAST, CH>(x, a); break;
     default: gmac_body<WMAX, PTM, FAST, CH>(x, a); break;
   }
 }
@@ -1160,6 +1162,7 @@ FENC_HD void gmac_diag(X& x, const GmacArgs& a) {
     case 1: gmac_diag_body<1>(x, a); break;
     case 2: gmac_diag_body<2>(x, a); break;
     case 4: gmac_diag_body<4>(x, a); break;
+    case 8: gmac_diag_body<8>(x, a); break;
     default: gmac_diag_body<kMacOut>(x, a); break;
   }
 }
