@@ -232,6 +232,12 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p, const PRO* pro = nullp
   const double* tw = a.tw + ((long long)p << a.logn);
   double* sm = x.smem;
   const d2 ni = INV ? a.ninv[p] : d2{0, 0};
+  // the pass uses the 2^P twiddles tw[0, 2^P) of every column: staged once in
+  // LDS after the tile, so the rounds read them there
+  double* twl = sm + (1 << (P + sb));
+  x.phase([&](int t) {
+    for (int i = t; i < (1 << P); i += T) twl[i] = tw[i];
+  });
   RoundLoop<0, n_rounds(P, RB)>::run([&](auto R) {
     constexpr int r = decltype(R)::value;
     constexpr int K = round_size(P, RB, r), s0 = round_start(P, RB, r);
@@ -254,7 +260,7 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p, const PRO* pro = nullp
                 if (last) dst[((long long)hi << n2) + col0 + c] = d2u(norm(v, q));
                 else sm[(hi << sb) | c] = v;
               },
-              [&](int st, int hi) { return twiddle(tw[(1 << st) + (hi >> (P - st))], qi); });
+              [&](int st, int hi) { return twiddle(twl[(1 << st) + (hi >> (P - st))], qi); });
         } else {
           inv_round<K>(
               rest, s0, q, qi, ld,
@@ -263,7 +269,7 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p, const PRO* pro = nullp
                 else sm[(hi << sb) | c] = v;
               },
               // global stage u = n2 + st: h = N >> (u+1), group = hi >> (st+1)
-              [&](int st, int hi) { return twiddle(tw[(1LL << (P - st - 1)) + (hi >> (st + 1))], qi); });
+              [&](int st, int hi) { return twiddle(twl[(1 << (P - st - 1)) + (hi >> (st + 1))], qi); });
         }
       }
     });
@@ -780,7 +786,8 @@ FENC_HD void lift_pq(X& x, const LiftPqArgs& a) {
 // t < na addresses in_a + t*a_cs, otherwise in_b + (t-na)*b_cs.  A null
 // plaintext means no product.
 constexpr int kMacOut = 8;
-static_assert(kMacOut == 8 || kMacOut == 16, "class rows are 1, 2, 4, 8 or 16 wide");
+// the kernels' width dispatch (1, 2, 4, default) takes the default for 8
+static_assert(kMacOut == 8, "class rows are 1, 2, 4 or 8 wide");
 
 struct MacClass {
   int g0, ng;        // groups g0 .. g0+ng-1 (terms shared by the outputs)
@@ -1130,8 +1137,7 @@ FENC_HD FENC_AI void gmac_width(X& x, const GmacArgs& a) {
     case 1: gmac_body<1, PTM, FAST, CH>(x, a); break;
     case 2: gmac_body<2, PTM, FAST, CH>(x, a); break;
     case 4: gmac_body<4, PTM, FAST, CH>(x, a); break;
-    case 8: gmac_body<(WMAX < 8 ? WMAX : 8), PTM, FAST, CH>(x, a); break;
-    default: gmac_body<WMAX, PTM, FAST, CH>(x, a); break;
+    default: gmac_body<WMAX, PTM, FAST, CH>(x, a); break;   // width 8 (kMacOut)
   }
 }
 template <int PTM, bool FAST, class X>
@@ -1162,8 +1168,7 @@ FENC_HD void gmac_diag(X& x, const GmacArgs& a) {
     case 1: gmac_diag_body<1>(x, a); break;
     case 2: gmac_diag_body<2>(x, a); break;
     case 4: gmac_diag_body<4>(x, a); break;
-    case 8: gmac_diag_body<8>(x, a); break;
-    default: gmac_diag_body<kMacOut>(x, a); break;
+    default: gmac_diag_body<kMacOut>(x, a); break;   // width 8 (kMacOut)
   }
 }
 

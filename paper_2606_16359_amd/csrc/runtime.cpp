@@ -237,7 +237,9 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
   a.lcols = fc[1];
   a.lcpb = fr[1];
   const unsigned colblocks = 1u << (a.n2 - a.lcols), rowblocks = 1u << (a.n1 - a.lcpb);
-  const size_t lds_c = (size_t)8 << (a.n1 + a.lcols), lds_r = (size_t)8 << (a.n2 + a.lcpb);
+  // LDS: the tile (column pass: then its 2^n1 twiddles)
+  const size_t lds_c = ((size_t)8 << (a.n1 + a.lcols)) + ((size_t)8 << a.n1);
+  const size_t lds_r = (size_t)8 << (a.n2 + a.lcpb);
   int active = 0;
   for (int r = 0; r < std::min(nrows, pm.n); r++) active += (pm.p[r] != fk::kSkip);
   active = (int)((long long)active * nrows / std::max(1, std::min(nrows, pm.n)));
@@ -332,7 +334,7 @@ void autotune_ntt(Ctx& C) {
     float best = time_dir(inverse);
     for (int rb = 3; rb <= 4; rb++)
       for (int t = 0; t <= std::min(other, 5); t++) {
-        if ((8LL << (P + t)) > (64 << 10)) continue;   // LDS tile at most 64 KiB
+        if ((8LL << (P + t)) > (64 << 10)) continue;   // LDS tile (without twiddles) at most 64 KiB
         if ((1LL << (P + t)) < 512) continue;         // at least 512 elements per block
         C.ntt_cfg[k][0] = rb;
         C.ntt_cfg[k][1] = t;
