@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1320077117, "gmac_diag": 352011814, "ntt_fwd_rows_md": 384909285, "ntt_fwd_cols": 236304294, "gmac_pt_fast": 1520332574, "ntt_fwd_rows": 271767985, "ntt_fwd_rows_rs": 298085224, "ntt_inv_cols": 68046088, "modup_fbc": 256656138, "gmac_fast": 623962344, "moddown_fbc": 151120990, "tensor_square": 477121141, "lift_pq": 187016667, "ntt_fwd_cols_lift": 102182532}
+TRAFFIC = {"kip": 1320067870, "gmac_diag": 351985185, "ntt_fwd_rows_md": 388370364, "ntt_fwd_cols": 236386668, "gmac_pt_fast": 1520241787, "ntt_fwd_rows": 279084448, "ntt_fwd_rows_rs": 300343692, "modup_fbc": 256657095, "gmac_fast": 623964309, "moddown_fbc": 151104861, "tensor_square": 477120180, "lift_pq": 187012723, "ntt_fwd_cols_lift": 102165854}
 
 
 def log(*a):
