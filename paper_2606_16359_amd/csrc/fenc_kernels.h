@@ -688,8 +688,7 @@ template <class X> FENC_HD void ntt_fwd_rows16_md(X& x, const NttMdArgs& a) { nt
 // last: coefficient form of limb l (rows [B][2]); lift centred value to each q_i, i < l
 struct LiftArgs {
   const u64* last;   // [B*2][N]
-  u64* out;          // [B*2][nl][N] (unused: the lifted values feed the NTT directly)
-  int nl, logn;
+  int nl, logn;      // nl: limbs the value is lifted to (rows per ct and poly of the NTT it feeds)
   double ql;
   const d2* pq;
 };

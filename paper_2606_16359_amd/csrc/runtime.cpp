@@ -613,7 +613,7 @@ void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
     // as it loads (reads the last limb, writes the lifted rows' first pass),
     // the row pass applies the tail (reads them and the input, writes the output)
     u64* l0 = lift + (long long)b0 * 2 * nl * N;
-    fk::LiftArgs la{last + (long long)b0 * 2 * N, l0, nl, C.logn, (double)C.primes[level], C.pq};
+    fk::LiftArgs la{last + (long long)b0 * 2 * N, nl, C.logn, (double)C.primes[level], C.pq};
     fk::RescaleTailArgs ra{in + b0 * in_cs, l0, out + b0 * out_cs, nl, C.logn, T.qlinv, C.pq};
     ntt(C, false, l0, l0, (long long)nl * N, (long long)nl * N, nb * 2 * nl, nl, identity_map(nl), s, nullptr,
         6.0 * nb * nl * N * 8, &ra, &la, (2.0 * nb + 8.0 * nb * nl) * N * 8);
