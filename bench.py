@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1320067870, "gmac_diag": 351985185, "ntt_fwd_rows_md": 388370364, "ntt_fwd_cols": 236386668, "gmac_pt_fast": 1520241787, "ntt_fwd_rows": 279084448, "ntt_fwd_rows_rs": 300343692, "modup_fbc": 256657095, "gmac_fast": 623964309, "moddown_fbc": 151104861, "tensor_square": 477120180, "lift_pq": 187012723, "ntt_fwd_cols_lift": 102165854}
+TRAFFIC = {"kip": 1320086570, "gmac_diag": 351818622, "ntt_fwd_rows_md": 385106384, "ntt_fwd_cols": 236292587, "gmac_pt_fast": 1520082010, "ntt_fwd_rows": 272869353, "ntt_fwd_rows_rs": 298019991, "ntt_inv_rows": 70466984, "modup_fbc": 256656348, "gmac_fast": 623969798, "moddown_fbc": 151104785, "tensor_square": 477121801, "lift_pq": 187013576, "ntt_fwd_cols_lift": 102167640}
 
 
 def log(*a):
