@@ -48,6 +48,35 @@ def test_lenet_modes_and_graph_replays_are_bit_identical(lenet):
         assert np.array_equal(fe.export(W.lenet_forward(fe, ct, w)), ref)
 
 
+def test_graph_replay_survives_workspace_growth():
+    """A captured rescale keeps its workspace when a much larger operation in
+    the same context later grows the arena: chunks used during a capture are
+    never returned, so replays after the growth still give the eager result."""
+    import torch
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["lenet"])
+    x, w = W.lenet_inputs(64)
+    lay = fe.plan_layout(64, 1, 28, 28, 5, 6)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    ref = fe.export(fe.rescale(ct))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = fe.rescale(ct)
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(fe.export(out), ref)
+    before = fe.device_bytes()
+    y = W.lenet_forward(fe, ct, w)          # hundreds of MB of workspace
+    torch.cuda.synchronize()
+    assert fe.device_bytes() > before
+    for _ in range(2):
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(fe.export(out), ref)
+    assert fe.export(y).shape[0] == y.n_ct
+
+
 def test_lenet_first_layer_matches_oracle_at_full_size(lenet):
     """Encryption and the whole first convolution (4 -> 24 ciphertexts, 32
     hoisted key switches) at N = 2^15, 20 limbs, element by element."""
