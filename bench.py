@@ -46,6 +46,8 @@ def main():
                     help="kernel for the roofline object; auto = the one with the most time per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--workload", choices=["lenet", "cifar", "mobilenet"], default="lenet",
+                    help="lenet: the headline benchmark; cifar / mobilenet: secondary full-size measurements")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes: one warm-up step, a 256 MiB device copy "
                          "(calibration of the byte counters), one batched step; no timing")
@@ -54,6 +56,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; the path shards by independent ciphertext "
                                    "batches (see DESIGN.md), multi-GPU runs are not implemented"}))
         sys.exit(2)
+
+    if args.workload != "lenet":
+        other_workload(args)
+        return
 
     import torch
     from paper_2606_16359_amd import fenc as F
@@ -135,22 +141,7 @@ def main():
     identical_perop = bool(np.array_equal(fe.export(out_pop), eager_bits))
     fe.set_mode(F.FENC_MODE_BATCHED)
 
-    # per-kernel time and algorithmic bytes: HIP events around each launch of
-    # one kernel over one batched step, one kernel at a time
-    kernels = {}
-    for name in KERNELS:
-        fe.profile_kernel(name)
-        step()
-        torch.cuda.synchronize()
-        kms, klaunch, kbytes = fe.profile_result()
-        if klaunch:
-            avg_s = kms / 1e3 / klaunch
-            gbs = kbytes / klaunch / avg_s / 1e9
-            kernels[name] = {"launches": klaunch, "ms_per_step": round(kms, 4), "avg_launch_us": round(avg_s * 1e6, 2),
-                             "bytes_per_launch": round(kbytes / klaunch), "achieved_GBs": round(gbs, 1),
-                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
-    fe.profile_kernel(None)
-    log("kernels: " + json.dumps(kernels))
+    kernels = kernel_table(fe, step)
     dom = args.profile_kernel
     if dom == "auto":
         dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
@@ -195,6 +186,94 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(x, w, params, lay, ks_per_step, imgs)
     print(json.dumps(res), flush=True)
+
+
+def kernel_table(fe, step):
+    """Per-kernel time and algorithmic bytes: HIP events around each launch of
+    one kernel over one batched step, one kernel at a time."""
+    import torch
+    kernels = {}
+    for name in KERNELS:
+        fe.profile_kernel(name)
+        step()
+        torch.cuda.synchronize()
+        kms, klaunch, kbytes = fe.profile_result()
+        if klaunch:
+            avg_s = kms / 1e3 / klaunch
+            gbs = kbytes / klaunch / avg_s / 1e9
+            kernels[name] = {"launches": klaunch, "ms_per_step": round(kms, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+                             "bytes_per_launch": round(kbytes / klaunch), "achieved_GBs": round(gbs, 1),
+                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    fe.profile_kernel(None)
+    log("kernels: " + json.dumps(kernels))
+    return kernels
+
+
+def other_workload(args):
+    """Secondary full-size measurements, batched eager form, one JSON line:
+    cifar: the CIFAR-shaped stack, 256 images 16x32x32, N = 2^16 (five 3x3
+    convs, a cubic after each); mobilenet: the three MobileNet-V1-shaped blocks
+    at 224x224, 16 images, each block from its own encryption.  The headline
+    benchmark is the LeNet-shaped network (the default workload)."""
+    import torch
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["cifar"])
+    if args.workload == "cifar":
+        imgs = 256
+        x, w = W.cifar_inputs(imgs)
+        lay = fe.plan_layout(imgs, 16, 32, 32, 3, 16)
+        cts = [fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)]
+
+        def step():
+            return [W.cifar_forward(fe, cts[0], w)]
+        desc = "CIFAR-shaped stack, 256 images 16x32x32, RNS-CKKS N=2^16, 24x50-bit limbs, dnum 4, scale 2^40"
+    else:
+        imgs = 16
+        ws = W.mobilenet_weights()
+        cts = []
+        for b, (blk, ((c, h, wd), S)) in enumerate(zip(W.MOBILENET_BLOCKS, W.MOBILENET_INPUTS)):
+            lay = fe.plan_layout(imgs, c, h, wd, blk[0]["w"][2], blk[0]["w"][0], S)
+            cts.append(fe.encrypt(fe.encode_fragment(W.images((imgs, c, h, wd), seed=1 + b), lay), lay,
+                                  W.SEED_ENC + b))
+
+        def step():
+            return [W.mobilenet_block(fe, ct, blk, wb) for ct, blk, wb in zip(cts, W.MOBILENET_BLOCKS, ws)]
+        desc = ("MobileNet-V1-shaped blocks at 224x224 (conv 3->32 s2; dw 32 + pw 32->64; dw 64 s2 + pw 64->128), "
+                "16 images, RNS-CKKS N=2^16, 24x50-bit limbs, dnum 4, scale 2^40")
+    torch.cuda.synchronize()
+    for i in range(max(1, args.warmup)):
+        t0 = time.time()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i} {time.time() - t0:.2f}s")
+    fe.stats_reset()
+    step()
+    torch.cuda.synchronize()
+    st = fe.stats()
+    steps = max(1, min(args.steps, 5))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    kernels = kernel_table(fe, step)
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    print(json.dumps({
+        "metric": "encrypted images/sec (batched, bit-exact)", "value": round(imgs / t, 3), "unit": "images/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic",
+        "data": "synthetic (uniform [0,1) images, N(0,0.1) weights, seeded)",
+        "config": {"workload": desc, "batch_images": imgs},
+        "keyswitches_per_s": round(st["keyswitch"] / t, 1), "keyswitches_per_step": st["keyswitch"],
+        "launches_per_step": st["launches"], "step_counters": st, "ntt_config": fe.ntt_config(),
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],
+                     "bytes_per_launch": kd["bytes_per_launch"]},
+        "kernels": kernels}), flush=True)
 
 
 def cpu_baseline(x, w, params, lay, ks_per_step, imgs):

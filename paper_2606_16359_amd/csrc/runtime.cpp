@@ -616,7 +616,7 @@ void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
     fk::LiftArgs la{last + (long long)b0 * 2 * N, nl, C.logn, (double)C.primes[level], C.pq};
     fk::RescaleTailArgs ra{in + b0 * in_cs, l0, out + b0 * out_cs, nl, C.logn, T.qlinv, C.pq};
     ntt(C, false, l0, l0, (long long)nl * N, (long long)nl * N, nb * 2 * nl, nl, identity_map(nl), s, nullptr,
-        6.0 * nb * nl * N * 8, &ra, &la, (2.0 * nb + 8.0 * nb * nl) * N * 8);
+        6.0 * nb * nl * N * 8, &ra, &la, (2.0 * nb + 2.0 * nb * nl) * N * 8);
     C.cnt.rescale += nb;
   }
 }
