@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 1320086570, "gmac_diag": 351818622, "ntt_fwd_rows_md": 385106384, "ntt_fwd_cols": 236292587, "gmac_pt_fast": 1520082010, "ntt_fwd_rows": 272869353, "ntt_fwd_rows_rs": 298019991, "ntt_inv_rows": 70466984, "modup_fbc": 256656348, "gmac_fast": 623969798, "moddown_fbc": 151104785, "tensor_square": 477121801, "lift_pq": 187013576, "ntt_fwd_cols_lift": 102167640}
+TRAFFIC = {"kip": 1320106589, "gmac_diag": 352273857, "ntt_fwd_rows_md": 385233250, "ntt_fwd_cols": 236292587, "gmac_pt_fast": 1520205860, "ntt_fwd_rows": 271935519, "ntt_fwd_rows_rs": 298301555, "ntt_inv_rows": 70706336, "modup_fbc": 256667735, "gmac_fast": 623973296, "moddown_fbc": 151134511, "tensor_square": 477123817, "lift_pq": 187025808, "ntt_fwd_cols_lift": 102167640, "ntt_inv_cols": 68019147}
 
 
 def log(*a):
@@ -53,8 +53,8 @@ def main():
                          "(calibration of the byte counters), one batched step; no timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the path shards by independent ciphertext "
-                                   "batches (see DESIGN.md), multi-GPU runs are not implemented"}))
+        print(json.dumps({"error": "one GPU only: the library runs on a single device; the path would "
+                                   "shard by independent ciphertext batches, which is not implemented"}))
         sys.exit(2)
 
     if args.workload != "lenet":

@@ -55,7 +55,7 @@ typedef enum {
   FENC_ESCALE = -5,        /* scale mismatch */
   FENC_ELAYOUT = -6,       /* layout not accepted by the operation */
   FENC_EHIP = -7,          /* HIP runtime error */
-  FENC_EUNSUPPORTED = -8   /* valid request outside what this build implements */
+  FENC_EUNSUPPORTED = -8   /* valid request outside what the library implements */
 } fenc_status;
 
 typedef struct fenc_ctx fenc_ctx;

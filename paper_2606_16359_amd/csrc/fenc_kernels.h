@@ -387,10 +387,9 @@ struct ModUpArgs {
   u64* ext;               // [B][beta][le][N]
   int b0;                 // first ct of the launch
   int beta, alpha, nl, le, logn;
-  const unsigned char* eprime;   // [le] prime index of extended limb
-  const d2* tab;
+  const d2* epq;          // [le] (q, 1/q) of the prime of extended limb l
+  const d2* tab;          // per digit: alpha entries, then le rows of alpha (zero past the digit's limbs)
   int tstride;
-  const d2* pq;
 };
 
 template <int A, class X>
@@ -403,28 +402,32 @@ FENC_HD void modup_fbc_a(X& x, const ModUpArgs& a) {
     const long long N = 1LL << a.logn;
     u64* out = a.ext + ((long long)b * a.beta + j) * a.le * N;
     double y[A];
+    u64 own[A];   // the digit's own limbs: copied from the NTT form
 #pragma unroll
     for (int i = 0; i < A; i++) {
       y[i] = 0;
       if (i < ds) {
-        const int p = a.eprime[lo + i];
-        const double q = a.pq[p].x;
+        const double q = a.epq[lo + i].x;
         const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
+        own[i] = a.ntt[b * a.ntt_cs + (lo + i) * N + c];
         y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);
       }
     }
+#pragma unroll
+    for (int i = 0; i < A; i++)
+      if (i < ds) out[(lo + i) * N + c] = own[i];
+    // the other limbs: no loads in this loop, so its stores need no wait
     for (int l = 0; l < a.le; l++) {
-      if (l >= lo && l < hi) {
-        out[l * N + c] = a.ntt[b * a.ntt_cs + l * N + c];
-        continue;
-      }
-      const int p = a.eprime[l];
-      const double q = a.pq[p].x, qi = a.pq[p].y;
+      if (l >= lo && l < hi) continue;
+      const d2 pl = a.epq[l];
+      const double q = pl.x, qi = pl.y;
       const d2* h = tab + a.alpha + (long long)l * a.alpha;
       double acc = 0;
+      // A == alpha up to 8: every h[i] lies in the row and is zero, like
+      // y[i], past the digit's limbs, so the products need no guard
 #pragma unroll
       for (int i = 0; i < A; i++) {
-        if (i < ds) acc += mulmod_c(y[i], h[i].x, h[i].y, q);
+        if (A <= 8 || i < ds) acc += mulmod_c(y[i], h[i].x, h[i].y, q);
         if ((i & 3) == 3) acc = red(acc, q, qi);
       }
       out[l * N + c] = d2u(norm(red(acc, q, qi), q));
@@ -576,9 +579,8 @@ struct ModDownArgs {
   u64* conv;             // [nout][2][nl][N]
   int o0;                // first output of the launch
   int nl, le, K, logn;
-  const unsigned char* eprime;
+  const d2* epq;         // [le] (q, 1/q) of the prime of extended limb l
   const d2* tab;
-  const d2* pq;
 };
 
 template <int KP, class X>
@@ -592,21 +594,20 @@ FENC_HD void moddown_fbc_k(X& x, const ModDownArgs& a) {
 #pragma unroll
     for (int k = 0; k < KP; k++) {
       y[k] = 0;
-      if (k < a.K) {
-        const int p = a.eprime[a.nl + k];
-        const double q = a.pq[p].x;
+      if (KP <= 8 || k < a.K) {
+        const double q = a.epq[a.nl + k].x;
         y[k] = centre(mulmod_c(u2d(in[(long long)(a.nl + k) * N]), a.tab[k].x, a.tab[k].y, q), q);
       }
     }
     u64* out = a.conv + op * a.nl * N + c;
     for (int i = 0; i < a.nl; i++) {
-      const int p = a.eprime[i];
-      const double q = a.pq[p].x, qi = a.pq[p].y;
+      const d2 pl = a.epq[i];
+      const double q = pl.x, qi = pl.y;
       const d2* h = a.tab + a.K + (long long)i * a.K;
       double s = 0;
 #pragma unroll
-      for (int k = 0; k < KP; k++) {
-        if (k < a.K) s += mulmod_c(y[k], h[k].x, h[k].y, q);
+      for (int k = 0; k < KP; k++) {   // KP == K up to 8
+        if (KP <= 8 || k < a.K) s += mulmod_c(y[k], h[k].x, h[k].y, q);
         if ((k & 3) == 3) s = red(s, q, qi);
       }
       out[(long long)i * N] = d2u(norm(red(s, q, qi), q));

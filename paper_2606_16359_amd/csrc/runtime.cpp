@@ -166,6 +166,12 @@ const LevelTabs& level_tabs(Ctx& C, int level) {
   T.h_eprime.resize(le);
   for (int l = 0; l < le; l++) T.h_eprime[l] = (unsigned char)(l < nl ? l : C.L + 1 + (l - nl));
   T.eprime = upload(C, T.h_eprime, C.owned);
+  std::vector<d2> epq(le);
+  for (int l = 0; l < le; l++) {
+    const uint64_t q = C.primes[T.h_eprime[l]];
+    epq[l] = {(double)q, 1.0 / (double)q};
+  }
+  T.epq = upload(C, epq, C.owned);
   T.tstride = alpha + le * alpha;
   std::vector<d2> tab((size_t)beta * T.tstride, d2{0, 0});
   for (int j = 0; j < beta; j++) {
@@ -438,10 +444,9 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
   a.nl = nl;
   a.le = le;
   a.logn = C.logn;
-  a.eprime = T.eprime;
+  a.epq = T.epq;
   a.tab = T.modup;
   a.tstride = T.tstride;
-  a.pq = C.pq;
   const bool per_op = C.mode == FENC_MODE_PER_OP;
   for (int b0 = 0; b0 < B; b0 += per_op ? 1 : B) {
     const int nb = per_op ? 1 : B;
@@ -471,7 +476,7 @@ static void moddown_part(Ctx& C, int level, u64* acc, u64* conv, const KsStage& 
   for (int l = 0; l < le; l++) pmP.p[l] = l < nl ? fk::kSkip : T.h_eprime[l];
   u64* acc0 = acc + (long long)o0 * 2 * le * N;
   ntt(C, true, acc0, acc0, (long long)le * N, (long long)le * N, no * 2 * le, le, pmP, s);
-  fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.eprime, C.md_tab, C.pq};
+  fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.epq, C.md_tab};
   timed(C, "moddown_fbc", 2.0 * no * (C.K + nl) * N * 8, s, [&] {
     fb::moddown_fbc({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, m);
   });

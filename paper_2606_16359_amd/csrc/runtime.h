@@ -150,6 +150,7 @@ struct LevelTabs {
   d2* qlinv = nullptr;   // [level]
   unsigned char* eprime = nullptr;
   std::vector<unsigned char> h_eprime;
+  d2* epq = nullptr;     // [le] (q, 1/q) of the prime of extended limb l
   d2* pmod = nullptr;    // [level+1] P mod q_i
   std::vector<uint64_t> h_pmod;
 };
