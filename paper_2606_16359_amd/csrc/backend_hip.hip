@@ -93,7 +93,7 @@ FENC_KERNEL_LDS(ntt_fwd_cols16_lift, NttLiftArgs)
 FENC_KERNEL_LDS(ntt_inv_rows16, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_cols16, NttArgs)
 FENC_KERNEL(modup_fbc, ModUpArgs)
-FENC_KERNEL(kip, KipArgs)
+FENC_KERNEL_XCD(kip, KipArgs)
 FENC_KERNEL(moddown_fbc, ModDownArgs)
 FENC_KERNEL_XCD(gmac, GmacArgs)
 FENC_KERNEL_XCD(gmac_pt, GmacArgs)

@@ -76,7 +76,7 @@ EMU_LDS(ntt_fwd_cols16_lift, NttLiftArgs)
 EMU_LDS(ntt_inv_rows16, NttArgs)
 EMU_LDS(ntt_inv_cols16, NttArgs)
 EMU(modup_fbc, ModUpArgs)
-EMU(kip, KipArgs)
+EMU_XCD(kip, KipArgs)
 EMU(moddown_fbc, ModDownArgs)
 EMU_XCD(gmac, GmacArgs)
 EMU_XCD(gmac_pt, GmacArgs)
