@@ -29,7 +29,7 @@ KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv
 # HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
 # a copy kernel of known size), per kernel; only kernels unchanged since the
 # counters were taken are listed
-TRAFFIC = {"kip": 856629441, "gmac_diag": 351983885, "ntt_fwd_rows_md": 388344662, "ntt_fwd_cols": 236305473, "gmac_pt_fast": 1520063054, "ntt_fwd_rows": 278982347, "ntt_fwd_rows_rs": 300290219, "ntt_inv_rows": 70454841, "modup_fbc": 256673856, "gmac_fast": 623962647, "moddown_fbc": 151128463, "tensor_square": 477124144, "lift_pq": 187027103, "ntt_fwd_cols_lift": 102150723, "ntt_inv_cols": 68019147}
+TRAFFIC = {"kip": 856641821, "gmac_diag": 351891405, "ntt_fwd_rows_md": 387996651, "ntt_fwd_cols": 236305473, "gmac_pt_fast": 1520051062, "ntt_fwd_rows": 271866994, "ntt_fwd_rows_rs": 298941831, "ntt_inv_rows": 70454841, "modup_fbc": 256676267, "gmac_fast": 623971824, "moddown_fbc": 151133327, "tensor_square": 477123177, "lift_pq": 187025851, "ntt_fwd_cols_lift": 102150723, "ntt_inv_cols": 68019147}
 
 
 def log(*a):

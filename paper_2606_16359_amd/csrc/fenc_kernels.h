@@ -285,8 +285,11 @@ FENC_HD void ntt_cols_pass(X& x, const NttArgs& a, int p, const PRO* pro = nullp
 // go to HBM in a separate coalesced phase.  (Staging the strided first round
 // of the inverse pass the same way was measured slower.)  With an epilogue
 // (EPI other than NoEpi) that phase hands each value (row, element, v in
-// [-q/2, q/2]) to epi_store instead of writing dst.
+// [-q/2, q/2]) to the epilogue instead of writing dst: epi_load fetches the
+// epilogue's own input words for an element, epi_finish computes and stores
+// its output.
 struct NoEpi {};
+constexpr int kEpiBatch = 4;   // elements whose epilogue loads are issued together
 
 template <bool INV, int P, int RB, class EPI = NoEpi, class X>
 FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p, const EPI* epi = nullptr) {
@@ -332,9 +335,26 @@ FENC_HD void ntt_rows_pass(X& x, const NttArgs& a, int p, const EPI* epi = nullp
   });
   if constexpr (stage_out) {
     x.phase([&](int t) {
-      for (int g = t; g < (1 << (P + cb)); g += T) {
-        if constexpr (plain) dst[g] = d2u(norm(sm[g], q));
-        else epi_store(*epi, row, e0 + g, sm[g], q, qi);
+      const int n = 1 << (P + cb);
+      if constexpr (plain) {
+        for (int g = t; g < n; g += T) dst[g] = d2u(norm(sm[g], q));
+      } else {
+        // the epilogue's loads of kEpiBatch words are issued before any of
+        // their stores (a store may alias them as far as the compiler knows);
+        // slots past the tile reload word g0, which exists, and store nothing
+        for (int g0 = t; g0 < n; g0 += kEpiBatch * T) {
+          decltype(epi_load(*epi, row, e0, q, qi)) pre[kEpiBatch];
+#pragma unroll
+          for (int j = 0; j < kEpiBatch; j++) {
+            const int g = g0 + j * T;
+            pre[j] = epi_load(*epi, row, e0 + (g < n ? g : g0), q, qi);
+          }
+#pragma unroll
+          for (int j = 0; j < kEpiBatch; j++) {
+            const int g = g0 + j * T;
+            if (g < n) epi_finish(*epi, row, e0 + g, pre[j], sm[g], q, qi);
+          }
+        }
       }
     });
   }
@@ -647,13 +667,28 @@ struct TailArgs {
 };
 
 // Output word (o, poly, limb i, coefficient c) from the converted value cv
-// (|cv| < q; |acc - cv| < 2q).
-FENC_HD inline void tail_value(const TailArgs& a, int o, int poly, int i, long long c, double cv, double q, double qi) {
+// (|cv| < q; |acc - cv| < 2q).  Two steps: the words of acc and base are
+// loaded first (tail_load), the rest follows (tail_value).
+// Both words are loaded unconditionally (without a base, word c of acc, which
+// exists) and kept raw until tail_value, so the loads stay in flight together.
+struct TailPre {
+  u64 aw, bw;   // acc word; base word (unused without a base)
+};
+FENC_HD FENC_AI TailPre tail_load(const TailArgs& a, int o, int poly, int i, long long c) {
   const long long N = 1LL << a.logn;
-  const double av = u2d(a.acc[((long long)o * 2 + poly) * a.le * N + i * N + c]);
-  double r = mulmod_c(av - cv, a.pinv[i].x, a.pinv[i].y, q);
   const TailItem I = a.items[o];
-  if (I.base >= 0) r += u2d(a.base[I.base * a.base_cs + poly * a.base_ps + i * N + c]);
+  const u64* ap = a.acc + ((long long)o * 2 + poly) * a.le * N + i * N + c;
+  TailPre P;
+  P.aw = ldg(ap);
+  P.bw = ldg(I.base >= 0 ? a.base + I.base * a.base_cs + poly * a.base_ps + i * N + c : a.acc + c);
+  return P;
+}
+FENC_HD FENC_AI void tail_value(const TailArgs& a, int o, int poly, int i, long long c, const TailPre& P, double cv,
+                                double q, double qi) {
+  const long long N = 1LL << a.logn;
+  double r = mulmod_c(u2d(P.aw) - cv, a.pinv[i].x, a.pinv[i].y, q);
+  const TailItem I = a.items[o];
+  if (I.base >= 0) r += u2d(P.bw);
   if (poly == 0)
     for (int k = 0; k < I.add_n; k++) {
       const AddTerm T = a.terms[I.add_off + k];
@@ -667,9 +702,14 @@ FENC_HD inline void tail_value(const TailArgs& a, int o, int poly, int i, long l
 // The tail is the epilogue of the forward row pass that finishes the NTT of
 // the converted values (rows: [output][poly][limb], limb = prime index), so
 // the converted values never return to memory.
-FENC_HD inline void epi_store(const TailArgs& a, int row, long long c, double v, double q, double qi) {
+FENC_HD FENC_AI TailPre epi_load(const TailArgs& a, int row, long long c, double, double) {
   const int i = row % a.nl, grp = row / a.nl;
-  tail_value(a, a.o0 + (grp >> 1), grp & 1, i, c, v, q, qi);
+  return tail_load(a, a.o0 + (grp >> 1), grp & 1, i, c);
+}
+FENC_HD FENC_AI void epi_finish(const TailArgs& a, int row, long long c, const TailPre& P, double v, double q,
+                                double qi) {
+  const int i = row % a.nl, grp = row / a.nl;
+  tail_value(a, a.o0 + (grp >> 1), grp & 1, i, c, P, v, q, qi);
 }
 
 struct NttMdArgs {
@@ -728,11 +768,15 @@ struct RescaleTailArgs {
 
 // The rescale tail as the epilogue of the forward row pass that finishes the
 // NTT of the lifted last limb (rows: [ct * 2 + poly][limb]); w in [-q/2, q/2].
-FENC_HD inline void epi_store(const RescaleTailArgs& a, int row, long long c, double w, double q, double) {
+FENC_HD FENC_AI u64 epi_load(const RescaleTailArgs& a, int row, long long c, double, double) {
   const long long N = 1LL << a.logn;
   const int i = row % a.nl, r = row / a.nl;   // r = ct*2 + poly
-  const double v = u2d(a.in[((long long)r * (a.nl + 1) + i) * N + c]);
-  a.out[((long long)r * a.nl + i) * N + c] = d2u(norm(mulmod_c(v - w, a.qlinv[i].x, a.qlinv[i].y, q), q));
+  return ldg(a.in + ((long long)r * (a.nl + 1) + i) * N + c);
+}
+FENC_HD FENC_AI void epi_finish(const RescaleTailArgs& a, int row, long long c, u64 vw, double w, double q, double) {
+  const long long N = 1LL << a.logn;
+  const int i = row % a.nl, r = row / a.nl;
+  a.out[((long long)r * a.nl + i) * N + c] = d2u(norm(mulmod_c(u2d(vw) - w, a.qlinv[i].x, a.qlinv[i].y, q), q));
 }
 
 struct NttRsArgs {
