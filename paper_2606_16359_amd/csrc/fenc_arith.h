@@ -3,13 +3,28 @@
 // CDNA4 issues binary64 FMA at full rate but 32-bit integer multiplies at a
 // quarter rate, so residues modulo primes q < 2^50 are handled as exact
 // integers held in doubles:
-//   * the product a*b (|a|,|b| < 3q) is split exactly into h + l with
-//     h = fl(a*b), l = fma(a, b, -h)  (Dekker's two-product via FMA);
-//   * the quotient estimate e = round(h * (1/q)) is formed in one FMA against
-//     the constant 1.5*2^52, which rounds to an integer;
-//   * r = fma(-e, q, h) + l is exact and lies in (-q, q).
-// With |a| < 3q, |b| < q and q < 2^50 the quotient error is below 0.875, so
-// |r| < q and every intermediate is an integer below 2^53 in magnitude.
+//   * the product a*b is split exactly into h + l with h = fl(a*b),
+//     l = fma(a, b, -h)  (Dekker's two-product via FMA);
+//   * the quotient estimate e is formed in one FMA against the constant
+//     1.5*2^52: fl(h*(1/q) + 1.5*2^52) - 1.5*2^52;
+//   * r = fma(-e, q, h) + l = a*b - e*q, exact whenever e is an integer.
+//
+// Contract (checked against 128-bit integers by tests/test_arith.py):
+//   The estimate is an integer exactly when the quotient a*b/q lies above
+//   -2^51: on [-2^51, 2^51) the FMA result lies in [2^52, 2^53), where
+//   doubles are the integers, and e is the nearest integer to fl(h/q) (off
+//   by at most 1/2 + |a*b/q| 2^-52 from a*b/q); on [2^51, 2^52) it lies in
+//   [2^53, 2^54) and e is the nearest even integer (off by at most 1 +
+//   |a*b/q| 2^-52).  Below -2^51 the FMA result falls under 2^52, e can be a
+//   half-integer and r is then not a residue at all.  So:
+//     mulmod(a, b):      exact and |r| < q for |a*b/q| < 2^51;
+//     mulmod_c(a, w):    w in [0, q), wq = fl(w/q) or fl(w * fl(1/q)); exact
+//                        for a*w/q > -2^51 and |a| < 2^52, with
+//                        |r| <= (1/2 + |a|/(4q)) q for a*w/q < 2^51 and
+//                        |r| <= (1 + |a|/(4q)) q above;
+//     red(x):            exact, |r| <= q/2 + 1, for |x| < 2^52.
+//   With |b| < q, |a| < 2^51 is enough for mulmod (for q near 2^50 that is
+//   |a| < 2q, not 3q).  Every call site states the operand range it relies on.
 // Residues are stored in HBM as uint64 in [0, q) and converted with the
 // 2^52 exponent trick (exact for values below 2^52).
 #pragma once
@@ -34,7 +49,7 @@ FENC_HD inline u64 d2u(double d) { return __builtin_bit_cast(u64, d + kTwo52) & 
 // integer nearest to x (|x| < 2^51)
 FENC_HD inline double rint52(double x) { return (x + kRound) - kRound; }
 
-// a*b mod q in (-q, q); |a| < 3q, |b| < q
+// a*b mod q in (-q, q) for |a*b/q| < 2^51 (|a| < 2^51 with |b| < q)
 FENC_HD inline double mulmod(double a, double b, double q, double qinv) {
   double h = a * b;
   double l = fma(a, b, -h);
@@ -42,7 +57,8 @@ FENC_HD inline double mulmod(double a, double b, double q, double qinv) {
   return fma(-e, q, h) + l;
 }
 
-// a*w mod q in (-q, q) for a constant w in [0, q) with wq = fl(w/q); |a| < 3q
+// a*w - e*q for a constant w in [0, q) with wq = fl(w/q); exact for
+// a*w/q > -2^51, |a| < 2^52; magnitude bounds in the header comment
 FENC_HD inline double mulmod_c(double a, double w, double wq, double q) {
   double h = a * w;
   double l = fma(a, w, -h);
@@ -50,7 +66,7 @@ FENC_HD inline double mulmod_c(double a, double w, double wq, double q) {
   return fma(-e, q, h) + l;
 }
 
-// x mod q in [-q/2, q/2] (up to one unit); |x| < 2^52
+// x mod q in [-q/2, q/2] (up to one unit); exact for |x| < 2^52
 FENC_HD inline double red(double x, double q, double qinv) {
   double e = fma(x, qinv, kRound) - kRound;
   return fma(-e, q, x);

@@ -88,9 +88,9 @@ struct NttArgs {
 
 // Twiddle pair (w, w/q) for mulmod_c from w alone; the twiddle table holds 8
 // bytes per entry.  The estimate fl(w * fl(1/q)) has relative error below
-// 2^-52, so for q < 2^50 the rounded quotient of a*w/q is off by at most
-// 1/2 + |a|/(4q) and mulmod_c returns the exact a*w - e*q with magnitude at
-// most (1/2 + |a|/(4q)) q.
+// 2^-52, so for q < 2^50 mulmod_c keeps its contract (fenc_arith.h): the
+// exact a*w - e*q for a*w/q > -2^51, of magnitude at most (1/2 + |a|/(4q)) q
+// while a*w/q < 2^51 and (1 + |a|/(4q)) q above.
 FENC_HD inline d2 twiddle(double w, double qi) { return d2{w, w * qi}; }
 
 // Stage index of member f (< 2^k) of the butterfly group whose other stage
@@ -102,10 +102,17 @@ FENC_HD inline int member(int rest, int f, int lo, int k) {
 // One register round of forward (Cooley-Tukey) stages s0..s0+K-1 of a pass
 // with P stage bits: local stage s pairs stage-index bit P-1-s.  tw_of(s, a)
 // is the twiddle of the butterfly whose upper element has stage index a.
-// Inputs have magnitude < q; outputs are reduced to [-q/2, q/2].  With the
-// product bound of twiddle(), three stages keep the sums below 1.75q, 2.69q
-// and 3.86q (< 2^52, exact); a fourth stage (K = 4) follows a reduction.  K
-// is a compile-time constant so the group lives in registers.
+// Inputs come from HBM in [0, q) or from LDS reduced to [-q/2 - 1, q/2 + 1];
+// outputs are reduced to [-q/2, q/2] (up to one unit).  Operand ranges of
+// the products (the multiplicand a of mulmod_c, w < q):
+//   HBM inputs:  stage 1 a in [0, q), sums in [-0.75q, 1.75q); stage 2 a in
+//                that range, sums in [-1.69q, 2.69q]; stage 3 a in that range:
+//                a*w/q >= -1.69 * 2^50 > -2^51 (exact), above 2^51 the
+//                estimate rounds to even, |t| <= 1.68q, sums within 4.37q;
+//   LDS inputs:  sums within 1.13q and 1.91q; stage 3 a*w/q >= -1.91 * 2^50.
+// Every sum stays below 2^53 and exact.  A fourth stage (K = 4) follows a
+// reduction, so its inputs are LDS-like.  K is a compile-time constant so the
+// group lives in registers.
 template <int K, class LD, class ST, class TW>
 FENC_HD inline void fwd_round(int rest, int s0, int P, double q, double qi, LD ld, ST st, TW tw_of) {
   double v[1 << K];
@@ -133,7 +140,9 @@ FENC_HD inline void fwd_round(int rest, int s0, int P, double q, double qi, LD l
 }
 
 // One register round of inverse (Gentleman-Sande) stages s0..s0+K-1: local
-// stage s pairs stage-index bit s.  Inputs and outputs have magnitude < q.
+// stage s pairs stage-index bit s.  Inputs and outputs have magnitude < q:
+// the difference x - y lies within 2q, so |a*w/q| < 2^51 and the product is
+// at most (1/2 + 2q/(4q)) q < q; the sum is reduced.
 template <int K, class LD, class ST, class TW>
 FENC_HD inline void inv_round(int rest, int s0, double q, double qi, LD ld, ST st, TW tw_of) {
   double v[1 << K];
@@ -430,7 +439,7 @@ FENC_HD void modup_fbc_a(X& x, const ModUpArgs& a) {
         const double q = a.epq[lo + i].x;
         const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
         own[i] = a.ntt[b * a.ntt_cs + (lo + i) * N + c];
-        y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);
+        y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);   // v in [0, q): |v*w/q| < q
       }
     }
 #pragma unroll
@@ -447,6 +456,7 @@ FENC_HD void modup_fbc_a(X& x, const ModUpArgs& a) {
       // y[i], past the digit's limbs, so the products need no guard
 #pragma unroll
       for (int i = 0; i < A; i++) {
+        // |y| <= q_src/2 < 2^49: quotient below 2^49, product within 0.63q
         if (A <= 8 || i < ds) acc += mulmod_c(y[i], h[i].x, h[i].y, q);
         if ((i & 3) == 3) acc = red(acc, q, qi);
       }
@@ -542,6 +552,7 @@ FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
 #pragma unroll
         for (int o = 0; o < W; o++) {
           const double e0 = u2d(sw ? v[o][1] : v[o][0]), e1 = u2d(sw ? v[o][0] : v[o][1]);
+          // digit and key words in [0, q): |e*k/q| < q, sums within 1.5q
           a0[o][0] = red(a0[o][0] + mulmod(e0, k00, q, qi), q, qi);
           a0[o][1] = red(a0[o][1] + mulmod(e1, k01, q, qi), q, qi);
           a1[o][0] = red(a1[o][0] + mulmod(e0, k10, q, qi), q, qi);
@@ -616,6 +627,7 @@ FENC_HD void moddown_fbc_k(X& x, const ModDownArgs& a) {
       y[k] = 0;
       if (KP <= 8 || k < a.K) {
         const double q = a.epq[a.nl + k].x;
+        // word in [0, q): |a*w/q| < q
         y[k] = centre(mulmod_c(u2d(in[(long long)(a.nl + k) * N]), a.tab[k].x, a.tab[k].y, q), q);
       }
     }
@@ -627,7 +639,7 @@ FENC_HD void moddown_fbc_k(X& x, const ModDownArgs& a) {
       double s = 0;
 #pragma unroll
       for (int k = 0; k < KP; k++) {   // KP == K up to 8
-        if (KP <= 8 || k < a.K) s += mulmod_c(y[k], h[k].x, h[k].y, q);
+        if (KP <= 8 || k < a.K) s += mulmod_c(y[k], h[k].x, h[k].y, q);   // |y| <= p/2 < 2^49
         if ((k & 3) == 3) s = red(s, q, qi);
       }
       out[(long long)i * N] = d2u(norm(red(s, q, qi), q));
@@ -686,7 +698,7 @@ FENC_HD FENC_AI TailPre tail_load(const TailArgs& a, int o, int poly, int i, lon
 FENC_HD FENC_AI void tail_value(const TailArgs& a, int o, int poly, int i, long long c, const TailPre& P, double cv,
                                 double q, double qi) {
   const long long N = 1LL << a.logn;
-  double r = mulmod_c(u2d(P.aw) - cv, a.pinv[i].x, a.pinv[i].y, q);
+  double r = mulmod_c(u2d(P.aw) - cv, a.pinv[i].x, a.pinv[i].y, q);   // |aw - cv| < 2q: quotient < 2^51
   const TailItem I = a.items[o];
   if (I.base >= 0) r += u2d(P.bw);
   if (poly == 0)
@@ -776,6 +788,7 @@ FENC_HD FENC_AI u64 epi_load(const RescaleTailArgs& a, int row, long long c, dou
 FENC_HD FENC_AI void epi_finish(const RescaleTailArgs& a, int row, long long c, u64 vw, double w, double q, double) {
   const long long N = 1LL << a.logn;
   const int i = row % a.nl, r = row / a.nl;
+  // vw - w in (-q/2 - 1, 1.5q + 1): quotient within (-q/2, 1.5q), product < q
   a.out[((long long)r * a.nl + i) * N + c] = d2u(norm(mulmod_c(u2d(vw) - w, a.qlinv[i].x, a.qlinv[i].y, q), q));
 }
 
@@ -932,7 +945,7 @@ FENC_HD FENC_AI void mac_terms(const u64 (&v)[CH], int cnt, const d2* w, const d
       const d2* wj = w + j * W;
       const double vv = u2d(v[j]);
 #pragma unroll
-      for (int o = 0; o < W; o++) acc[o] += mulmod_c(vv, wj[o].x, wj[o].y, q);
+      for (int o = 0; o < W; o++) acc[o] += mulmod_c(vv, wj[o].x, wj[o].y, q);   // vv in [0, q)
       if (++n == 5) {
 #pragma unroll
         for (int o = 0; o < W; o++) acc[o] = red(acc[o], q, qi);
@@ -963,6 +976,7 @@ FENC_HD FENC_AI void mac_end_group(const u64* const* mg, double q, double qi, co
 #pragma unroll
   for (int o = 0; o < W; o++) {
     double sv;
+    // reduced sums within q/2 + 1 times 2^25 or a word in [0, q): quotients below 2^50
     if constexpr (FAST) sv = red(mulmod_c(red(acc[o], q, qi), t25, t25q, q) + red(acc2[o], q, qi), q, qi);
     else sv = red(acc[o], q, qi);
     if constexpr (PTM == kPtShared) {
@@ -1137,7 +1151,7 @@ FENC_HD FENC_AI bool diag_step(const GmacArgs& a, const MacThread& T, const u64*
   diag_fetch(a, T, mk, more ? g + 1 : T.K.g0, nxt);
   const double vv = u2d(cur.v[0]);
 #pragma unroll
-  for (int o = 0; o < W; o++) r[o] += mulmod(vv, u2d(cur.m[o]), T.q, T.qi);
+  for (int o = 0; o < W; o++) r[o] += mulmod(vv, u2d(cur.m[o]), T.q, T.qi);   // both words in [0, q)
   if (++n == 4) {
 #pragma unroll
     for (int o = 0; o < W; o++) r[o] = red(r[o], T.q, T.qi);
@@ -1244,7 +1258,7 @@ FENC_HD void tensor_square(X& x, const SquareArgs& a) {
     const double b0 = u2d(pb[0]), b1 = u2d(pb[a.nl * N]);
     u64* out = a.out + b * a.ct_stride + i * N + c;
     const d2 k = a.k[i];
-    const double m01 = mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);
+    const double m01 = mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);   // words in [0, q)
     out[0] = d2u(norm(mulmod_c(mulmod(a0, b0, q, qi), k.x, k.y, q), q));
     out[a.nl * N] = d2u(norm(mulmod_c(m01, k.x, k.y, q), q));
     a.d2buf[(long long)b * a.nl * N + i * N + c] = d2u(norm(mulmod_c(mulmod(a1, b1, q, qi), k.x, k.y, q), q));
@@ -1301,7 +1315,7 @@ FENC_HD void key_combine(X& x, const KeyArgs& A) {
     const double av = u2d(A.a[o]), ev = u2d(A.e[o]);
     const double s = u2d(A.s[(long long)p * N + c]), sp = u2d(A.sp[(long long)p * N + c]);
     const d2 g = A.gadget[(long long)j * A.np + p];
-    double b = ev - mulmod(av, s, q, qi);
+    double b = ev - mulmod(av, s, q, qi);   // key, encryption and decryption operands are words in [0, q)
     b += mulmod_c(sp, g.x, g.y, q);
     u64* k = A.key + ((long long)j * 2 * A.np + p) * N + c;
     k[0] = d2u(norm(red(b, q, qi), q));
@@ -1400,7 +1414,7 @@ FENC_HD void perm_rows(X& x, const PermArgs& A) {
       const int p = A.prime[r];
       const double q = A.pq[p].x, qi = A.pq[p].y;
       const double v = u2d(A.in[r * N + c]);
-      A.out[r * N + c] = d2u(norm(mulmod(v, v, q, qi), q));
+      A.out[r * N + c] = d2u(norm(mulmod(v, v, q, qi), q));   // v in [0, q)
     } else {
       A.out[r * N + c] = A.in[r * N + auto_src((unsigned)c, A.g, A.logn)];
     }

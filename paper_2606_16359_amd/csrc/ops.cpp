@@ -1117,7 +1117,7 @@ int fenc_key_export(fenc_ctx* ctx, int32_t shift, uint64_t* out) {
   ntt(*ctx, true, key, t, (long long)np * N, (long long)np * N, nd * 2 * np, np, identity_map(np), nullptr);
   fb::sync(nullptr);
   fb::d2h(out, t, (size_t)nd * 2 * np * N * 8);
-  for (void* p : tmp) fb::dev_free(p);
+  dfree_all(*ctx, tmp);
   API_END
 }
 
@@ -1266,7 +1266,7 @@ int fenc_encrypt(fenc_ctx* ctx, const uint64_t* pt, const fenc_layout* lay, uint
   fk::EncArgs ea{da, dE, dm, C.s_ntt, out->data, nl, C.logn, C.pq};
   fb::enc_combine({(unsigned)std::max(1, N / 256), (unsigned)(n * nl), 1}, std::min(256, N), nullptr, ea);
   fb::sync(nullptr);
-  for (void* p : tmp) fb::dev_free(p);
+  dfree_all(C, tmp);
   API_END
 }
 
@@ -1285,7 +1285,7 @@ static void decrypt_limbs(fenc_ctx& C, const fenc_ctbatch* in, std::vector<uint6
   fb::sync(nullptr);
   m.resize((size_t)n * nl * N);
   fb::d2h(m.data(), dm, m.size() * 8);
-  for (void* p : tmp) fb::dev_free(p);
+  dfree_all(C, tmp);
 }
 
 int fenc_decrypt_raw(fenc_ctx* ctx, const fenc_ctbatch* in, uint64_t* m, void* stream) {
@@ -1340,7 +1340,7 @@ int fenc_ct_export(fenc_ctx* ctx, const fenc_ctbatch* in, uint64_t* host, void* 
   ntt(C, true, in->data, t, (long long)nl * N, (long long)nl * N, n * 2 * nl, nl, identity_map(nl), nullptr);
   fb::sync(nullptr);
   fb::d2h(host, t, (size_t)n * 2 * nl * N * 8);
-  for (void* p : tmp) fb::dev_free(p);
+  dfree_all(C, tmp);
   API_END
 }
 
@@ -1647,7 +1647,7 @@ int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t 
   ntt(C, inverse != 0, d, d, C.N, C.N, (int)n, 1, pm, nullptr);
   fb::sync(nullptr);
   fb::d2h(rows, d, (size_t)n * C.N * 8);
-  for (void* p : tmp) fb::dev_free(p);
+  dfree_all(C, tmp);
   API_END
 }
 

@@ -79,7 +79,20 @@ void* dalloc(Ctx& C, size_t bytes, std::vector<void*>& owner) {
   void* p = fb::dev_alloc(bytes);
   owner.push_back(p);
   C.dev_bytes += (int64_t)bytes;
+  C.dev_sizes[p] = bytes;
   return p;
+}
+
+void dfree_all(Ctx& C, std::vector<void*>& owner) {
+  for (void* p : owner) {
+    auto it = C.dev_sizes.find(p);
+    if (it != C.dev_sizes.end()) {
+      C.dev_bytes -= (int64_t)it->second;
+      C.dev_sizes.erase(it);
+    }
+    fb::dev_free(p);
+  }
+  owner.clear();
 }
 
 fk::PrimeMap identity_map(int n) {
@@ -357,7 +370,7 @@ void autotune_ntt(Ctx& C) {
   fb::sync(nullptr);
   fb::event_destroy(e0);
   fb::event_destroy(e1);
-  for (void* p : tmp) fb::dev_free(p);
+  dfree_all(C, tmp);
 }
 
 // ---------------------------------------------------------------- keys
@@ -411,9 +424,7 @@ const uint64_t* get_key(Ctx& C, uint64_t g) {
   fk::KeyArgs ka{da, dE, C.s_ntt, dS, key, dg, np, C.logn, C.pq};
   fb::key_combine({grid_x(C), (unsigned)(nd * np), 1}, block_threads(C), nullptr, ka);
   fb::sync(nullptr);
-  for (void* p : tmp) {
-    fb::dev_free(p);
-  }
+  dfree_all(C, tmp);
   C.keys[g] = key;
   return key;
 }

@@ -182,6 +182,7 @@ struct fenc_ctx {
   std::vector<void*> owned;
   fr::Arena arena;
   int64_t dev_bytes = 0;
+  std::map<void*, size_t> dev_sizes;          // size of every live allocation made by dalloc
   // NTT pass shapes: [fwd cols, fwd rows, inv rows, inv cols] = {radix bits (3 or 4),
   // log2 of columns (cols pass) or chunks (rows pass) per block}; results do not depend on them
   int ntt_cfg[4][2] = {{3, -1}, {3, -1}, {3, -1}, {3, -1}};
@@ -208,6 +209,8 @@ void ensure_device(Ctx& C);
 // times the candidate NTT pass shapes on this device and keeps the fastest
 void autotune_ntt(Ctx& C);
 void* dalloc(Ctx& C, size_t bytes, std::vector<void*>& owner);
+// frees every allocation in owner (made by dalloc) and takes it off dev_bytes
+void dfree_all(Ctx& C, std::vector<void*>& owner);
 template <class T>
 T* upload(Ctx& C, const std::vector<T>& v, std::vector<void*>& owner) {
   T* p = (T*)dalloc(C, v.size() * sizeof(T) + 8, owner);

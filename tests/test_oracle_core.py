@@ -346,3 +346,52 @@ def test_extended_basis_rotation_moves_down_to_the_rotation():
     shifts = [1, 5, 200]
     assert np.array_equal(o.pq_roundtrip(ct, shifts), o.rotate(ct, shifts))
     assert np.array_equal(o.pq_roundtrip(ct, lift=True), ct)
+
+
+def _mix(z):
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def _rng(seed, tag, i):
+    key = _mix(seed ^ ((tag * 0xD1B54A32D192ED03) & M64))
+    return _mix((key + (i + 1) * 0x9E3779B97F4A7C15) & M64)
+
+
+def test_sampler_words_are_the_stated_functions_of_the_stream():
+    """Bit for bit: uniform mod q = (word 2i << 64 | word 2i+1) mod q (the first
+    word is the high half), ternary = floor(3 r / 2^64) - 1, Gaussian = sign bit
+    63 and the count of table entries <= the low 63 bits."""
+    lib = P.lib()
+    cdt = np.zeros(19, np.uint64)
+    lib.orc_gauss_cdt(cdt)
+    for seed, tag in [(0, 0), (9, 4 << 56), (3, (2 << 56) | (7 << 24) | (1 << 16) | 5)]:
+        for q in [(1 << 50) - 27, 1125899904679937, 268369921]:
+            for i in [0, 1, 2, 17, 1000, 65535]:
+                hi, lo = _rng(seed, tag, 2 * i), _rng(seed, tag, 2 * i + 1)
+                assert lib.orc_uniform(seed, tag, i, q) == ((hi << 64) | lo) % q
+                assert lib.orc_uniform(seed, tag, i, q) != ((lo << 64) | hi) % q or hi == lo
+        for i in range(200):
+            r = _rng(seed, tag, i)
+            assert lib.orc_ternary(seed, tag, i) == ((3 * r) >> 64) - 1
+            mag = sum(1 for t in cdt if (r & ((1 << 63) - 1)) >= int(t))
+            assert lib.orc_gauss(seed, tag, i) == (-mag if r >> 63 else mag)
+
+
+def test_full_size_product_against_schoolbook_coefficients():
+    """N = 2^16 with a 50-bit prime: sampled coefficients of the NTT product
+    equal the negacyclic schoolbook sum computed with Python integers."""
+    o = P.Oracle(16, 2, 50, 1, 50, 2, 40, 1)
+    q = o.primes()[0]
+    N = o.N
+    rng = np.random.default_rng(16)
+    a = rng.integers(0, q, N, dtype=np.uint64)
+    b = rng.integers(0, q, N, dtype=np.uint64)
+    c = o.polymul(0, a, b)
+    al, bl = [int(v) for v in a], [int(v) for v in b]
+    for k in [0, 1, 2, N // 2, N - 2, N - 1] + [int(v) for v in rng.integers(0, N, 26)]:
+        # c_k = sum_{i<=k} a_i b_{k-i} - sum_{i>k} a_i b_{N+k-i}
+        pos = sum(x * y for x, y in zip(al[:k + 1], reversed(bl[:k + 1])))
+        neg = sum(x * y for x, y in zip(al[k + 1:], reversed(bl[k + 1:])))
+        assert int(c[k]) == (pos - neg) % q, k

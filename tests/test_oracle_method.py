@@ -257,3 +257,52 @@ def test_avgpool_rotation_sum_in_the_extended_basis():
     for y in (y0, y1):
         assert np.max(np.abs(o.decrypt_tensor(y) - want)) < 1e-6
     assert (c0["moddown"], c1["moddown"]) == (3 * len(b.data()), len(b.data()))
+
+
+def _border_rotations(L, h, w, k, stride, pad, n_groups):
+    """Pixel-level count of the inner rotations a K <= S convolution needs: the
+    distinct (input fragment, nonzero block offset) pairs that carry at least
+    one valid input pixel to a valid output pixel, times the ciphertexts that
+    share a fragment position (channel and batch groups)."""
+    S, So = L["S"], L["S"] // stride
+    ho, wo = (h + 2 * pad - k) // stride + 1, (w + 2 * pad - k) // stride + 1
+    need = set()
+    for y in range(ho):
+        for x in range(wo):
+            for di in range(k):
+                for dj in range(k):
+                    iy, ix = y * stride + di - pad, x * stride + dj - pad
+                    if not (0 <= iy < h and 0 <= ix < w):
+                        continue
+                    off = (iy // S - y // So, ix // S - x // So)
+                    if off != (0, 0):
+                        need.add((iy % S, ix % S, off))
+    return len(need) * n_groups
+
+
+@pytest.mark.parametrize("case", [
+    dict(x=(2, 2, 8, 8), k=3, S=4, stride=1, pad=1),     # same padding, borders on both sides
+    dict(x=(2, 2, 8, 8), k=3, S=4, stride=2, pad=1),     # stride 2 keeps 4 of 16 fragments
+    dict(x=(1, 3, 12, 12), k=3, S=4, stride=1, pad=0),   # valid conv, one-sided borders
+    dict(x=(2, 1, 8, 8), k=2, S=2, stride=1, pad=0),     # K = S
+    dict(x=(4, 2, 8, 8), k=1, S=2, stride=1, pad=0),     # 1x1: no rotation at all
+])
+def test_conv2d_border_rotations_match_brute_force_when_block_covers_kernel(case):
+    """K <= S: eq. (total-rot) counts no inner rotation (the optimal-S table's
+    convention); the convolution performs exactly the border rotations found
+    by enumerating pixels."""
+    o = small_oracle(nq=3, logN=10)
+    bs, cin, h, w = case["x"]
+    k, S = case["k"], case["S"]
+    L = o.fragment_layout(bs, cin, h, w, S)
+    b = o.encrypt_tensor(L, rand_x(case["x"], 3), seed=1)
+    wt = rand_w((2, cin, k, k), 4)
+    y, cnt = o.conv2d(b, wt, case["stride"], case["pad"], 1)
+    want = _border_rotations(L, h, w, k, case["stride"], case["pad"], L["nbg"] * L["ncg"])
+    assert cnt["inner_rot"] == want
+    alpha = o.ns / L["M"] ** 2
+    outer_only = bs / alpha * max(alpha * S * S / bs - 1, 0) * 2
+    assert P.rot_total_formula(bs, cin, 2, k, S, alpha) == outer_only      # the formula has no inner term
+    got = o.decrypt_tensor(y)
+    ref = cnn_ref.conv2d(rand_x(case["x"], 3), wt, case["stride"], case["pad"], 1)
+    assert np.max(np.abs(got - ref)) < 1e-4
