@@ -130,12 +130,20 @@ int fenc_ctx_primes(const fenc_ctx* ctx, uint64_t* out);
 int fenc_set_mode(fenc_ctx* ctx, int mode);
 /* Convolution plaintext form (Arch-aware Ct Compression, scale split): when
  * per-position weights are needed, the layer's weight diagonals are encoded as
- * full-scale plaintexts if they fit `bytes` of device memory (default 1 GiB);
+ * full-scale plaintexts if those of one batch group (they repeat in every
+ * group) fit `bytes` of device memory (default 1 GiB);
  * otherwise 0/1 position masks at scale Delta_m are combined with integer
  * weight codes at scale Delta_w, Delta_w * Delta_m = q_l * Delta / scale_in,
  * so one rescale follows either way.  The choice changes the ciphertext bits,
  * not the decrypted values beyond rounding. */
 int fenc_set_plaintext_budget(fenc_ctx* ctx, int64_t bytes);
+/* Workspace limit (default 32 GiB, 0: none): an operation whose workspace
+ * would exceed it runs over tiles of whole batch groups, one after the other,
+ * each with the plan of the smaller batch.  Batch groups never share a
+ * ciphertext, so tiles change neither results nor the arithmetic.  The limit
+ * bounds the context's arena for batches of more than one group; a single
+ * batch group is never split.  Errors: EINVAL for a negative limit. */
+int fenc_set_workspace_limit(fenc_ctx* ctx, int64_t bytes);
 /* Kernel profiling: every later launch of the named kernel (e.g. "kip",
  * "ntt_fwd_cols", "gmac") outside graph capture is bracketed by HIP events on
  * its stream; fenc_profile_result returns the summed event time, the number

@@ -280,7 +280,10 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
   // hoisted inner rotations: one ModUp per input ciphertext.  hoist = 1 keeps
   // the rotated copies in the extended basis Q_l U P, takes the linear
   // combination there (unrotated inputs enter as P x) and moves each combined
-  // ciphertext down once; hoist = 0 moves every copy down.
+  // ciphertext down once; hoist = 0 moves every copy down.  Without any
+  // rotated copy the combination would be P y and ModDown(P y) = y exactly,
+  // so such a layer stays in Q_l either way.
+  hoist = hoist && !need.empty();
   const std::vector<int> basis = hoist ? qp_basis(C, lvl) : q_basis(lvl);
   std::map<std::pair<int, long>, Ct> copies;
   for (auto& kv : need) {
@@ -303,8 +306,10 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
   // Plaintext form: with masks, either one full-scale plaintext per (output,
   // diagonal, term) holding the weight of every position ("materialised"),
   // or a mask per (term class, position) times scalar weight codes.
+  // The diagonals are the same in every batch group; the budget is charged
+  // for the distinct ones, those of batch group 0.
   long long n_pt = 0;
-  for (int oct = 0; oct < (int)terms.size(); oct++) {
+  for (int oct = 0; oct < ncg_out * So * So; oct++) {
     const int go = (oct / (So * So)) % ncg_out;
     for (const Term& t : terms[oct])
       for (int r = 0; r < nd; r++) {

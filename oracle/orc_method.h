@@ -43,7 +43,8 @@ std::vector<Ct> encrypt_batch(Context& C, const Layout& L, const std::vector<RPo
 void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, double* x);
 
 // pt_budget: plaintext bytes under which per-position weights are materialised
-// as full-scale plaintext diagonals instead of mask-basis scalar codes
+// as full-scale plaintext diagonals instead of mask-basis scalar codes (the
+// distinct diagonals: those of one batch group)
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
                        long long pt_budget = 1LL << 30, int hoist = 0);

@@ -14,6 +14,7 @@
 #include <set>
 #include <sstream>
 #include <thread>
+#include <tuple>
 
 #include "runtime.h"
 
@@ -358,13 +359,20 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
       copies.push_back({kv.second, kv.first});
     }
   }
+  // without rotated copies the extended basis buys nothing: the combination of
+  // lifted inputs is P y and ModDown(P y) = y word for word, so the plain form
+  // gives the same residues
+  if (copies.empty()) P->pq = false;
   P->rot = make_rot_stage(C, copies, P->owned, P->pq);
 
   // Plaintext form: with masks, either one full-scale plaintext per (output,
   // diagonal, term) holding the weight of every position ("materialised"),
   // or a mask per (term class, position) times scalar weight codes.
+  // The diagonals repeat in every batch group, so the budget is charged for
+  // the distinct ones: those of batch group 0.
+  const int out_per_bg = ncg_out * So * So;
   long long n_pt = 0;
-  for (int oct = 0; oct < P->n_out; oct++) {
+  for (int oct = 0; oct < out_per_bg; oct++) {
     const int go = (oct / (So * So)) % ncg_out;
     for (const Term& t : terms[oct])
       for (int r = 0; r < nd; r++) {
@@ -419,14 +427,23 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   std::vector<std::vector<Groups>> G(P->n_out, std::vector<Groups>(nd));
   std::vector<std::vector<char>> act(P->n_out, std::vector<char>(nd, 0));
   std::vector<std::vector<double>> diag_slots;
+  std::map<std::tuple<int, int, int>, int> diag_id;   // (output of group 0, term, diagonal) -> plaintext
   for (int oct = 0; oct < P->n_out; oct++) {
     const int go = (oct / (So * So)) % ncg_out;
-    for (const Term& t : terms[oct]) {
+    for (size_t ti = 0; ti < terms[oct].size(); ti++) {
+      const Term& t = terms[oct][ti];
       // pq: unrotated inputs enter lifted (P x) after the copies in the B buffer
       const int in_id = t.shift ? P->n_in + copy_id[{t.idx, t.shift}]
                                 : (P->pq ? P->n_in + (int)copies.size() + t.idx : t.idx);
       if (materialise) {
         for (int r = 0; r < nd; r++) {
+          auto known = diag_id.find(std::make_tuple(oct % out_per_bg, (int)ti, r));
+          if (known != diag_id.end()) {
+            act[oct][r] = 1;
+            G[oct][r][known->second].push_back({in_id, -1});
+            P->n_terms++;
+            continue;
+          }
           std::vector<double> z;
           for (int q = 0; q < npos; q++) {
             const int ch = in_channel(t.gi, q), o = go * cpc + posmod(q - r, cpc);
@@ -441,6 +458,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
           }
           if (z.empty()) continue;
           act[oct][r] = 1;
+          diag_id[std::make_tuple(oct % out_per_bg, (int)ti, r)] = (int)diag_slots.size();
           G[oct][r][(int)diag_slots.size()].push_back({in_id, -1});
           diag_slots.push_back(std::move(z));
           P->n_terms++;
@@ -963,6 +981,34 @@ static void run_fc(Ctx& C, const FcPlan& P, const u64* in, u64* out, fb::Stream 
   C.cnt.cts_out += P.n_out;
 }
 
+// ---------------------------------------------------------------- batch-group tiles
+// Batch groups share no ciphertext, so an operation on cnt of them is the
+// same operation on a smaller batch: its plan is the one of that batch.
+static Layout sub_layout(const Layout& L, int cnt) {
+  Layout T = L;
+  T.nbg = cnt;
+  T.bs = cnt * L.bsg;
+  return T;
+}
+static int cts_per_group(const Layout& L) { return L.kind == FENC_LAYOUT_FRAGMENT ? L.ncg * L.S * L.S : 1; }
+
+// batch groups per tile for `per_group` bytes of workspace per group
+static int tile_groups(const Ctx& C, int nbg, double per_group) {
+  if (nbg <= 1 || C.ws_limit <= 0 || per_group * nbg <= (double)C.ws_limit) return nbg;
+  return std::max(1, std::min(nbg, (int)((double)C.ws_limit / per_group)));
+}
+
+// workspace of one run of a key-switch-free or key-switching linear layer:
+// outputs and outer diagonals, rotated copies, the larger ModUp output
+static double conv_ws_bytes(const Ctx& C, int level, bool pq, int n_src, int n_copies, int n_in, int n_out, int n_zr) {
+  const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
+  const double w = (double)C.N * 8, ce = 2.0 * nl * w, ee = 2.0 * le * w, ext = (double)beta * le * w;
+  double b = (n_out + n_zr) * ce + n_out * ce;   // y and z_r, and the rescale's lift
+  if (pq) b += (n_copies + n_in) * ee + (n_out + n_zr) * ee;
+  else b += std::max(1, n_copies) * ce;
+  return b + std::max((double)n_src, (double)n_zr) * ext;
+}
+
 // ---------------------------------------------------------------- plan cache
 template <class T, class F>
 static T& cached(Ctx& C, const std::string& key, F build) {
@@ -1049,6 +1095,13 @@ int fenc_set_plaintext_budget(fenc_ctx* ctx, int64_t bytes) {
   API_BEGIN
   if (!ctx || bytes < 0) fail(FENC_EINVAL, "bad budget");
   ctx->pt_budget = bytes;
+  API_END
+}
+
+int fenc_set_workspace_limit(fenc_ctx* ctx, int64_t bytes) {
+  API_BEGIN
+  if (!ctx || bytes < 0) fail(FENC_EINVAL, "bad workspace limit");
+  ctx->ws_limit = bytes;
   API_END
 }
 
@@ -1372,11 +1425,29 @@ int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t
   check_batch(C, in, true);
   ensure_device(C);
   const size_t nw = (size_t)cout * (Lin.c / groups) * k * k;
-  std::ostringstream key;
-  key << "conv|" << layout_key(Lin) << '|' << cout << ',' << k << ',' << stride << ',' << pad << ',' << groups << ','
-      << fnv(w, nw * sizeof(double)) << ',' << C.pt_budget << ',' << C.hoist;
-  ConvPlan& P = cached<ConvPlan>(C, key.str(), [&] { return build_conv(C, Lin, w, cout, k, stride, pad, groups, false, Lout); });
-  run_conv(C, P, in->data, out->data, (fb::Stream)stream);
+  const uint64_t wh = fnv(w, nw * sizeof(double));
+  auto plan_of = [&](int cnt) -> ConvPlan& {
+    const Layout Ls = sub_layout(Lin, cnt);
+    std::ostringstream key;
+    key << "conv|" << layout_key(Ls) << '|' << cout << ',' << k << ',' << stride << ',' << pad << ',' << groups << ','
+        << wh << ',' << C.pt_budget << ',' << C.hoist;
+    return cached<ConvPlan>(C, key.str(), [&] {
+      Layout lo;
+      return build_conv(C, Ls, w, cout, k, stride, pad, groups, false, lo);
+    });
+  };
+  int tile = Lin.nbg;
+  if (Lin.nbg > 1 && C.ws_limit > 0) {
+    const ConvPlan& P1 = plan_of(1);
+    tile = tile_groups(C, Lin.nbg, conv_ws_bytes(C, P1.level, P1.pq, (int)P1.rot.src.size(), P1.rot.n, P1.n_in,
+                                                 P1.n_out, P1.n_zr));
+  }
+  const long long in_step = (long long)cts_per_group(Lin) * ct_elems(C, Lin.level);
+  const long long out_step = (long long)cts_per_group(Lout) * ct_elems(C, Lout.level);
+  for (int b0 = 0; b0 < Lin.nbg; b0 += tile) {
+    const ConvPlan& P = plan_of(std::min(tile, Lin.nbg - b0));
+    run_conv(C, P, in->data + b0 * in_step, out->data + b0 * out_step, (fb::Stream)stream);
+  }
   API_END
 }
 
@@ -1391,9 +1462,25 @@ int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
-  PoolPlan& P = cached<PoolPlan>(C, "pool|" + layout_key(Lin) + (C.hoist ? "|h" : ""),
-                                 [&] { return build_pool(C, Lin, false, Lout); });
-  run_pool(C, P, in->data, out->data, (fb::Stream)stream);
+  auto plan_of = [&](int cnt) -> PoolPlan& {
+    const Layout Ls = sub_layout(Lin, cnt);
+    return cached<PoolPlan>(C, "pool|" + layout_key(Ls) + (C.hoist ? "|h" : ""), [&] {
+      Layout lo;
+      return build_pool(C, Ls, false, lo);
+    });
+  };
+  int tile = Lin.nbg;
+  if (Lin.nbg > 1 && C.ws_limit > 0 && Lin.S == 1) {
+    const PoolPlan& P1 = plan_of(1);
+    tile = tile_groups(C, Lin.nbg, conv_ws_bytes(C, P1.level, P1.pq, (int)P1.rot.src.size(), P1.rot.n, P1.n_in,
+                                                 P1.n_out, 0));
+  }
+  const long long in_step = (long long)cts_per_group(Lin) * ct_elems(C, Lin.level);
+  const long long out_step = (long long)cts_per_group(Lout) * ct_elems(C, Lout.level);
+  for (int b0 = 0; b0 < Lin.nbg; b0 += tile) {
+    const PoolPlan& P = plan_of(std::min(tile, Lin.nbg - b0));
+    run_pool(C, P, in->data + b0 * in_step, out->data + b0 * out_step, (fb::Stream)stream);
+  }
   API_END
 }
 
@@ -1443,13 +1530,22 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
+  // workspace per ciphertext: the product, its third part, the ModUp output
+  // and, for degree 3, x^2 and u one level down
+  const int l = Lin.level, nl1 = l + 1, beta = (nl1 + C.alpha - 1) / C.alpha;
+  const double per_ct = (double)C.N * 8 * (2.0 * nl1 + nl1 + (double)beta * (nl1 + C.K) + (d == 3 ? 4.0 * l : 0.0));
+  const int tile = tile_groups(C, Lin.nbg, per_ct * cts_per_group(Lin));
+  const long long in_step = (long long)cts_per_group(Lin) * ct_elems(C, Lin.level);
+  const long long out_step = (long long)cts_per_group(Lout) * ct_elems(C, Lout.level);
+  for (int b0 = 0; b0 < Lin.nbg; b0 += tile) {
+  const Layout Ls = sub_layout(Lin, std::min(tile, Lin.nbg - b0));
   std::ostringstream key;
-  key << "poly|" << layout_key(Lin) << '|' << fnv(c, sizeof(c));
+  key << "poly|" << layout_key(Ls) << '|' << fnv(c, sizeof(c));
   PolyPlan& P = cached<PolyPlan>(C, key.str(), [&] {
     auto p = new PolyPlan;
     p->out = Lout;
     p->level = Lin.level;
-    p->n = Lin.n_ct();
+    p->n = Ls.n_ct();
     p->d = d;
     p->lin = d <= 1 || c[0] != 0.0 || c[1] != 0.0;   // adding zero codes changes nothing
     const int l = Lin.level;
@@ -1478,7 +1574,8 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
     }
     return p;
   });
-  run_poly(C, P, in->data, out->data, (fb::Stream)stream);
+  run_poly(C, P, in->data + b0 * in_step, out->data + b0 * out_step, (fb::Stream)stream);
+  }
   API_END
 }
 

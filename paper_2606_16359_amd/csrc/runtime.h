@@ -165,7 +165,8 @@ struct fenc_ctx {
   std::vector<int64_t> s;            // secret key coefficients
   int mode = FENC_MODE_BATCHED;
   bool strict = false;
-  int64_t pt_budget = 1LL << 30;     // bytes of materialised conv plaintexts
+  int64_t pt_budget = 1LL << 30;     // bytes of materialised conv plaintexts (one batch group)
+  int64_t ws_limit = 32LL << 30;     // workspace per operation; larger batches run in tiles of batch groups
   fenc_counters cnt{};
 
   // device state (built on first use)

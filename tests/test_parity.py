@@ -131,6 +131,34 @@ def test_device_bytes_return_after_encrypt_and_decrypt(backend, orc):
     assert f.device_bytes() == before
 
 
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_batch_group_tiles_give_identical_residues(backend, orc):
+    """A workspace limit that forces one batch group per tile: convolution
+    (hoisted rotations, masks, outer rotations), S = 1 pooling and the
+    quadratic run tile by tile and give the untiled residues, which equal the
+    oracle's."""
+    o, f = orc, make(backend, *SMALL)
+    x = rng(11).uniform(0, 1, (16, 2, 8, 8))     # 512 slots, 64-slot fragments: 8 images per ct
+    w = rng(12).normal(0, 0.1, (3, 2, 3, 3))
+    lay = f.plan_layout(16, 2, 8, 8, 3, 3, 1)
+    assert lay.n_bg == 2
+    ct = f.encrypt(f.encode_fragment(x, lay), lay, 5)
+
+    def net():
+        y = f.conv2d(ct, w, pad=1)
+        return f.avgpool2(f.poly_act(y, (0.1, 0.5, 0.25)))
+    ref = f.export(net())
+    f.set_workspace_limit(1)
+    assert np.array_equal(f.export(net()), ref)
+    f.set_workspace_limit(0)
+    Lo = o.fragment_layout(16, 2, 8, 8, 1)
+    ob = o.encrypt_tensor(Lo, x, 5)
+    yo, _ = o.conv2d(ob, w, pad=1, hoist=f.hoist)
+    yo, _ = o.poly_act(yo, (0.1, 0.5, 0.25))
+    yo, _ = o.avgpool2(yo, hoist=f.hoist)
+    assert np.array_equal(ref, yo.data())
+
+
 WIDE = (10, 10, 40, 10, 40, 1, 30, 19)   # one digit of 10 limbs, 10 special primes
 
 
