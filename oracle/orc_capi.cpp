@@ -378,12 +378,15 @@ int orc_decrypt_tensor(void* c, void* bp, double* x) {
 }
 
 void* orc_conv2d(void* c, void* bp, const double* w, int cout, int k, int stride, int pad, int groups,
-                 long long pt_budget, int hoist, long* counts) {
+                 long long pt_budget, int hoist, const OrcLayout* target, const double* bias, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
-  out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt, pt_budget, hoist);
+  Layout T;
+  if (target) T = from_c(target);
+  out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt, pt_budget, hoist,
+                    target ? &T : nullptr, bias);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)
@@ -422,23 +425,24 @@ void* orc_poly_act(void* c, void* bp, const double* coeffs, int n, long* counts)
   GUARD_END(nullptr)
 }
 
-void* orc_compress(void* c, void* bp, long* counts) {
+void* orc_compress(void* c, void* bp, const OrcLayout* target, int hoist, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
-  out->cts = compress(*(Context*)c, in->L, in->cts, out->L, cnt);
+  if (target) out->cts = compress_to(*(Context*)c, in->L, in->cts, from_c(target), out->L, cnt, hoist);
+  else out->cts = compress(*(Context*)c, in->L, in->cts, out->L, cnt, hoist);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)
 }
 
-void* orc_fc(void* c, void* bp, const double* w, int dout, long* counts) {
+void* orc_fc(void* c, void* bp, const double* w, int dout, const double* bias, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
-  out->cts = fc(*(Context*)c, in->L, in->cts, w, dout, out->L, cnt);
+  out->cts = fc(*(Context*)c, in->L, in->cts, w, dout, out->L, cnt, bias);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)

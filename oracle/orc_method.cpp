@@ -33,6 +33,7 @@
 #include <cmath>
 #include <map>
 #include <set>
+#include <tuple>
 #include <stdexcept>
 
 namespace orc {
@@ -207,9 +208,158 @@ static void add_inplace(const Context& C, Ct& a, const Ct& b) {
   poly_add_inplace(C, a.c1, b.c1);
 }
 
+struct Term { int idx; long shift; int u, v, dbi, dbj, di, dj, gi; };
+
+// bias[o] added to every valid slot of output channel o, encoded at the
+// output scale (exactly Delta) and added to c0 after the rescale
+void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const double* bias) {
+  std::vector<std::vector<double>> z(out.size(), std::vector<double>(C.ns, 0.0));
+  std::vector<std::pair<int, int>> sl;
+  for (int b = 0; b < L.bs; b++)
+    for (int ch = 0; ch < L.c; ch++)
+      for (int hh = 0; hh < L.h; hh++)
+        for (int ww = 0; ww < L.w; ww++) {
+          element_slots(L, b, ch, hh, ww, sl);
+          for (auto& p : sl) z[p.first][p.second] = bias[L.kind == KIND_VECTOR ? (ch * L.h + hh) * L.w + ww : ch];
+        }
+  for (size_t t = 0; t < out.size(); t++)
+    poly_add_inplace(C, out[t].c0, encode(C, z[t], {}, out[t].scale, q_basis(out[t].level)));
+}
+
+// Convolution written straight into a target layout (Arch-aware Ct
+// Compression fused with the layer before it).  The natural output ct o is
+// y_o = sum_r Rot(z_{o,r}, s_r) with z_{o,r} = sum_t copy_t (.) P_{o,r,t};
+// the repack adds Rot(A_g (.) y_o, delta_g) into target ct d_g for every move
+// group g of o.  A 0/1 mask commutes with the sum: A (.) Rot(z, s) =
+// Rot(Rot(A, -s) (.) z, s), so the mask multiplies the plaintexts P (both are
+// 0/1 masks or weights at the split scales Delta_w Delta_m = q_l Delta / s_in)
+// and the two rotations merge into one by sigma = s_r + delta_g.  Target ct d
+// is then sum_sigma Rot(Z_{d,sigma}, sigma) with one ModDown and one rescale:
+// the repack adds no level and no product.  A term enters Z_{d,sigma} when its
+// mask pattern meets the moved slots (zero weights included).
+template <class SRC, class INCH, class PAIR>
+std::vector<Ct> conv_into_target(Context& C, const Layout& Lin, const Layout& Lnat, const Layout& target,
+                                 const std::vector<std::vector<Term>>& terms, int nd, int npos, bool need_mask,
+                                 bool materialise, double T, double dw, double dm, SRC& source, INCH in_channel,
+                                 PAIR pair_ok, const double* w, int gin, int gout, int k,
+                                 const std::vector<int>& basis, int hoist, Counts& cnt) {
+  const Layout Tg = check_target(C, target, Lnat.bs, Lnat.c, Lnat.h, Lnat.w);
+  const std::vector<MoveGroup> mg = repack_groups(C, Lnat, Tg);
+  const int S = Lin.S, m = Lin.m, bsg = Lin.bsg, cpc = Lin.cpc, lvl = Lin.level;
+  const int So = Lnat.S, ncg_out = Lnat.ncg;
+  // valid source pixels of a term, at channel position q (the conv's own mask)
+  auto src_mask = [&](const Term& t, int q) {
+    std::vector<double> z(C.ns, 0.0);
+    for (int bi = 0; bi < m; bi++)
+      for (int bj = 0; bj < m; bj++) {
+        int gh = (bi + t.dbi) * S + t.u, gw = (bj + t.dbj) * S + t.v;
+        if (gh < 0 || gh >= Lin.h || gw < 0 || gw >= Lin.w) continue;
+        for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = 1.0;
+      }
+    return z;
+  };
+  auto wval = [&](int o, int ch, const Term& t) {
+    const int grp = o / gout;
+    return w[(((long long)o * gin + (ch - grp * gin)) * k + t.di) * k + t.dj];
+  };
+  std::map<std::pair<int, long>, Ct> Z;   // (target ct, rotation) -> diagonal sum
+  auto acc_of = [&](int d, long sigma) -> Ct& {
+    auto it = Z.find({d, sigma});
+    if (it == Z.end()) {
+      Ct z;
+      z.c0 = poly_zero(C, basis);
+      z.c1 = poly_zero(C, basis);
+      z.level = lvl;
+      z.scale = Lin.scale * T;
+      it = Z.emplace(std::make_pair(d, sigma), z).first;
+    }
+    return it->second;
+  };
+  for (const MoveGroup& g : mg) {
+    const int oct = g.src, go = (oct / (So * So)) % ncg_out;
+    for (int r = 0; r < nd; r++) {
+      const long sr = (long)r * m * m * bsg, sigma = posmod(sr + g.delta, C.ns);
+      std::vector<double> ra(C.ns, 0.0);   // Rot(A_g, -s_r): the moved slots seen from z_{o,r}
+      for (int sl : g.src_slots) ra[posmod((long)sl + sr, C.ns)] = 1.0;
+      for (const Term& t : terms[oct]) {
+        const Ct& copy = source(t.idx, t.shift);
+        if (materialise) {
+          std::vector<double> dz(C.ns, 0.0);
+          bool any = false;
+          for (int q = 0; q < npos; q++) {
+            const int ch = in_channel(t.gi, q), o = go * cpc + posmod(q - r, cpc);
+            if (!pair_ok(ch, o)) continue;
+            const double wv = wval(o, ch, t);
+            const std::vector<double> mq = src_mask(t, q);
+            for (int i = 0; i < C.ns; i++)
+              if (mq[i] != 0.0 && ra[i] != 0.0) {
+                dz[i] = wv;
+                any = true;
+              }
+          }
+          if (!any) continue;
+          add_inplace(C, acc_of(g.dst, sigma), mul_plain(C, copy, encode(C, dz, {}, T, basis), T));
+          cnt.pmult++;
+          continue;
+        }
+        for (int q = 0; q < npos; q++) {
+          const int ch = in_channel(t.gi, q), o = go * cpc + posmod(q - r, cpc);
+          if (!pair_ok(ch, o)) continue;
+          std::vector<double> mq = need_mask ? src_mask(t, q) : std::vector<double>(C.ns, 1.0);
+          bool any = false;
+          for (int i = 0; i < C.ns; i++) {
+            mq[i] = (mq[i] != 0.0 && ra[i] != 0.0) ? 1.0 : 0.0;
+            any = any || mq[i] != 0.0;
+          }
+          if (!any) continue;
+          Ct& acc = acc_of(g.dst, sigma);
+          const i64 code = weight_code(wval(o, ch, t), dw);
+          if (code == 0) continue;
+          add_inplace(C, acc, mul_scalar(C, mul_plain(C, copy, encode(C, mq, {}, dm, basis), dm), code, dw));
+          cnt.pmult++;
+          cnt.smult++;
+        }
+      }
+    }
+  }
+  std::vector<Ct> out;
+  for (int d = 0; d < Tg.n_ct(); d++) {
+    const Ct* z0 = nullptr;
+    std::vector<const Ct*> zs;
+    std::vector<i64> sh;
+    for (auto& kv : Z) {
+      if (kv.first.first != d) continue;
+      if (hoist) {
+        kv.second = mod_down_ct(C, kv.second);
+        cnt.moddown++;
+      }
+      if (kv.first.second == 0) z0 = &kv.second;
+      else {
+        zs.push_back(&kv.second);
+        sh.push_back(kv.first.second);
+      }
+    }
+    Ct y;
+    if (zs.empty()) {
+      if (z0) y = *z0;
+      else y = zero_ct(C, lvl, Lin.scale * T);
+    } else {
+      y = rotate_sum_lazy(C, z0, zs, sh);
+      cnt.outer_rot += zs.size();
+      cnt.ks += zs.size();
+      cnt.modup += zs.size();
+      cnt.moddown += 1;
+    }
+    y = rescale(C, y);
+    cnt.rescale++;
+    out.push_back(y);
+  }
+  return out;
+}
+
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
-                       long long pt_budget, int hoist) {
+                       long long pt_budget, int hoist, const Layout* target, const double* bias) {
   if (Lin.kind != KIND_FRAGMENT || Lin.dil != 1) throw std::runtime_error("conv2d: needs a dense fragment layout");
   if (stride < 1 || Lin.S % stride) throw std::runtime_error("conv2d: stride must divide S");
   const int cin = Lin.c;
@@ -252,7 +402,6 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
     return false;
   };
 
-  struct Term { int idx; long shift; int u, v, dbi, dbj, di, dj, gi; };
   const int So = Lout.S, ncg_out = Lout.ncg;
   std::vector<std::vector<Term>> terms(Lin.nbg * ncg_out * So * So);
   std::map<int, std::set<long>> need;
@@ -345,6 +494,16 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
     return ones_c = m[0];
   };
 
+  if (target) {
+    const Layout Lnat = Lout;
+    std::vector<Ct> out = conv_into_target(C, Lin, Lnat, *target, terms, nd, npos, need_mask, materialise, T, dw, dm,
+                                           source, in_channel, pair_ok, w, gin, gout, k, basis, hoist, cnt);
+    Lout = check_target(C, *target, Lnat.bs, Lnat.c, Lnat.h, Lnat.w);
+    Lout.level = lvl - 1;
+    Lout.scale = Delta;
+    if (bias) add_bias(C, Lout, out, bias);
+    return out;
+  }
   std::vector<Ct> out(terms.size());
   for (int bg = 0; bg < Lin.nbg; bg++)
     for (int go = 0; go < ncg_out; go++)
@@ -436,6 +595,7 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
           y.scale = Delta;
           out[oct] = y;
         }
+  if (bias) add_bias(C, Lout, out, bias);
   return out;
 }
 
@@ -587,12 +747,126 @@ std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>&
   return out;
 }
 
-std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
-                         Counts& cnt) {
+std::vector<MoveGroup> repack_groups(const Context& C, const Layout& Ls, const Layout& Ld) {
+  if (Ls.bs != Ld.bs || Ls.c != Ld.c || Ls.h != Ld.h || Ls.w != Ld.w)
+    throw std::runtime_error("repack: layouts of different tensors");
+  std::map<std::tuple<int, int, long>, std::vector<int>> g;
+  std::vector<std::pair<int, int>> src, dst;
+  for (int b = 0; b < Ls.bs; b++)
+    for (int ch = 0; ch < Ls.c; ch++)
+      for (int hh = 0; hh < Ls.h; hh++)
+        for (int ww = 0; ww < Ls.w; ww++) {
+          element_slots(Ls, b, ch, hh, ww, src);
+          element_slots(Ld, b, ch, hh, ww, dst);
+          for (auto& d : dst)   // Rot(z, delta)[slot_d] = z[slot_d + delta] = z[slot_s]
+            g[std::make_tuple(src[0].first, d.first, (long)posmod((long)src[0].second - d.second, C.ns))]
+                .push_back(src[0].second);
+        }
+  std::vector<MoveGroup> out;
+  for (auto& kv : g) {
+    MoveGroup m;
+    m.src = std::get<0>(kv.first);
+    m.dst = std::get<1>(kv.first);
+    m.delta = std::get<2>(kv.first);
+    m.src_slots = kv.second;
+    std::sort(m.src_slots.begin(), m.src_slots.end());
+    out.push_back(m);
+  }
+  return out;
+}
+
+Layout check_target(const Context& C, const Layout& T, int bs, int c, int h, int w) {
+  if (T.bs != bs || T.c != c || T.h != h || T.w != w) throw std::runtime_error("target: different tensor shape");
+  if (T.kind == KIND_FRAGMENT) {
+    if (T.dil != 1) throw std::runtime_error("target: dilated fragment layout");
+    Layout R = fragment_layout(C, bs, c, h, w, T.S);
+    if (R.M != T.M || R.m != T.m || R.bsg != T.bsg || R.cpc != T.cpc || R.nbg != T.nbg || R.ncg != T.ncg ||
+        R.rep != T.rep)
+      throw std::runtime_error("target: not the fragment layout of its block size");
+    return R;
+  }
+  if (T.kind != KIND_VECTOR) throw std::runtime_error("target: unknown layout kind");
+  if (T.bsg < 1 || T.d * T.bsg != C.ns || T.nbg != (bs + T.bsg - 1) / T.bsg || T.nfeat != c * h * w ||
+      (int)T.pos.size() != T.nfeat)
+    throw std::runtime_error("target: bad vector layout");
+  std::set<int> seen(T.pos.begin(), T.pos.end());
+  if ((int)seen.size() != T.nfeat || *seen.begin() < 0 || *seen.rbegin() >= T.d)
+    throw std::runtime_error("target: feature positions must be distinct and below d");
+  Layout R = T;
+  R.cpc = 1; R.ncg = 1; R.S = 1; R.m = 1; R.M = 1; R.rep = 0; R.dil = 1;
+  return R;
+}
+
+// Rot-mask-add repack into a target layout (Arch-aware Ct Compression): each
+// source ciphertext is rotated once per shift it needs (hoisted: one ModUp per
+// source), every rotated copy is masked to the slots that move with that
+// shift, and the masked copies of one target ciphertext are summed (hoist =
+// 1: in Q_l U P with one ModDown per target).  Masks are encoded at
+// q_l Delta / s_in, so one rescale restores Delta.
+std::vector<Ct> compress_to(Context& C, const Layout& Lin, const std::vector<Ct>& in, const Layout& target,
+                            Layout& Lout, Counts& cnt, int hoist) {
+  const Layout T = check_target(C, target, Lin.bs, Lin.c, Lin.h, Lin.w);
+  const int lvl = Lin.level;
+  if (lvl < 1) throw std::runtime_error("compress: no level left");
+  const std::vector<MoveGroup> mg = repack_groups(C, Lin, T);
+  std::map<int, std::set<long>> need;
+  for (const MoveGroup& g : mg)
+    if (g.delta) need[g.src].insert(g.delta);
+  hoist = hoist && !need.empty();
+  const std::vector<int> basis = hoist ? qp_basis(C, lvl) : q_basis(lvl);
+  std::map<std::pair<int, long>, Ct> copies;
+  for (auto& kv : need) {
+    std::vector<i64> sh(kv.second.begin(), kv.second.end());
+    std::vector<Ct> r = hoist ? rotate_hoisted_pq(C, in[kv.first], sh) : rotate_hoisted(C, in[kv.first], sh);
+    for (size_t i = 0; i < sh.size(); i++) copies[{kv.first, sh[i]}] = r[i];
+    cnt.other_rot += sh.size();
+    cnt.ks += sh.size();
+    cnt.modup += 1;
+    if (!hoist) cnt.moddown += sh.size();
+  }
+  std::map<int, Ct> lifted;
+  auto source = [&](int idx, long delta) -> const Ct& {
+    if (delta) return copies.at({idx, delta});
+    if (!hoist) return in[idx];
+    auto it = lifted.find(idx);
+    if (it == lifted.end()) it = lifted.emplace(idx, lift_pq(C, in[idx])).first;
+    return it->second;
+  };
+  const double dm = ((double)C.primes[lvl] * delta_of(C)) / Lin.scale;
+  Lout = T;
+  Lout.level = lvl - 1;
+  Lout.scale = delta_of(C);
+  std::vector<Ct> out;
+  for (int d = 0; d < T.n_ct(); d++) {
+    Ct acc = zero_ct(C, lvl, Lin.scale * dm);
+    acc.c0 = poly_zero(C, basis);
+    acc.c1 = poly_zero(C, basis);
+    for (const MoveGroup& g : mg) {
+      if (g.dst != d) continue;
+      std::vector<double> z(C.ns, 0.0);   // the moved slots after the rotation
+      for (int sl : g.src_slots) z[posmod((long)sl - g.delta, C.ns)] = 1.0;
+      add_inplace(C, acc, mul_plain(C, source(g.src, g.delta), encode(C, z, {}, dm, basis), dm));
+      cnt.pmult++;
+    }
+    if (hoist) {
+      acc = mod_down_ct(C, acc);
+      cnt.moddown++;
+    }
+    Ct y = rescale(C, acc);
+    cnt.rescale++;
+    y.scale = Lout.scale;
+    out.push_back(y);
+  }
+  return out;
+}
+
+// The library's own target when none is given: one VECTOR ciphertext per
+// batch group, each source ciphertext's valid positions placed at the first
+// offset where they fit (greedy first fit in ciphertext order).
+Layout vector_target(const Context& C, const Layout& Lin) {
   if (Lin.kind != KIND_FRAGMENT) throw std::runtime_error("compress: needs a fragment layout");
-  const int bsg = Lin.bsg, d = C.ns / bsg, lvl = Lin.level;
+  const int bsg = Lin.bsg, d = C.ns / bsg;
   const int per_bg = Lin.ncg * Lin.S * Lin.S;
-  // positions (in units of bsg) holding valid elements, per ciphertext of batch group 0
   std::vector<std::set<int>> P(per_bg);
   std::vector<std::pair<int, int>> sl;
   for (int ch = 0; ch < Lin.c; ch++)
@@ -601,7 +875,6 @@ std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& i
         element_slots(Lin, 0, ch, hh, ww, sl);
         P[sl[0].first].insert(sl[0].second / bsg);
       }
-  // greedy first-fit placement of each ciphertext's positions at an offset phi
   std::vector<char> occ(d, 0);
   std::vector<int> phi(per_bg, 0);
   for (int t = 0; t < per_bg; t++) {
@@ -616,68 +889,31 @@ std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& i
     phi[t] = f;
     for (int p : P[t]) occ[p + f] = 1;
   }
-  Lout = Layout();
-  Lout.kind = KIND_VECTOR;
-  Lout.bs = Lin.bs; Lout.c = Lin.c; Lout.h = Lin.h; Lout.w = Lin.w;
-  Lout.bsg = bsg; Lout.nbg = Lin.nbg; Lout.cpc = 1; Lout.ncg = 1; Lout.S = 1; Lout.m = 1; Lout.M = 1;
-  Lout.d = d;
-  Lout.nfeat = Lin.c * Lin.h * Lin.w;
-  Lout.pos.resize(Lout.nfeat);
+  Layout T;
+  T.kind = KIND_VECTOR;
+  T.bs = Lin.bs; T.c = Lin.c; T.h = Lin.h; T.w = Lin.w;
+  T.bsg = bsg; T.nbg = Lin.nbg; T.cpc = 1; T.ncg = 1; T.S = 1; T.m = 1; T.M = 1;
+  T.d = d;
+  T.nfeat = Lin.c * Lin.h * Lin.w;
+  T.pos.resize(T.nfeat);
   for (int ch = 0; ch < Lin.c; ch++)
     for (int hh = 0; hh < Lin.h; hh++)
       for (int ww = 0; ww < Lin.w; ww++) {
         element_slots(Lin, 0, ch, hh, ww, sl);
-        Lout.pos[(ch * Lin.h + hh) * Lin.w + ww] = sl[0].second / bsg + phi[sl[0].first];
+        T.pos[(ch * Lin.h + hh) * Lin.w + ww] = sl[0].second / bsg + phi[sl[0].first];
       }
-  Lout.level = lvl - 1;
-  Lout.scale = delta_of(C);
-  const double dm = ((double)C.primes[lvl] * delta_of(C)) / Lin.scale;
-  std::vector<RPoly> mk(per_bg);
-  for (int t = 0; t < per_bg; t++) {
-    if (P[t].empty()) continue;
-    std::vector<double> z(C.ns, 0.0);
-    for (int p : P[t])
-      for (int jb = 0; jb < bsg; jb++) z[p * bsg + jb] = 1.0;
-    mk[t] = encode(C, z, {}, dm, q_basis(lvl));
-  }
-  std::vector<Ct> out;
-  for (int bg = 0; bg < Lin.nbg; bg++) {
-    Ct z0 = zero_ct(C, lvl, Lin.scale * dm);
-    bool have0 = false;
-    std::vector<Ct> ms;
-    std::vector<i64> sh;
-    for (int t = 0; t < per_bg; t++) {
-      if (P[t].empty()) continue;
-      Ct mc = mul_plain(C, in[bg * per_bg + t], mk[t], dm);
-      cnt.pmult++;
-      if (phi[t] == 0) {
-        add_inplace(C, z0, mc);
-        have0 = true;
-      } else {
-        ms.push_back(mc);
-        sh.push_back(posmod(-(long)phi[t] * bsg, C.ns));
-      }
-    }
-    Ct y;
-    if (ms.empty()) {
-      y = z0;
-    } else {
-      std::vector<const Ct*> zs;
-      for (const Ct& c : ms) zs.push_back(&c);
-      y = rotate_sum_lazy(C, have0 ? &z0 : nullptr, zs, sh);
-      y.scale = Lin.scale * dm;
-      cnt.other_rot += zs.size(); cnt.ks += zs.size(); cnt.modup += zs.size(); cnt.moddown += 1;
-    }
-    y = rescale(C, y);
-    cnt.rescale++;
-    y.scale = Lout.scale;
-    out.push_back(y);
-  }
-  return out;
+  T.level = Lin.level;
+  T.scale = Lin.scale;
+  return T;
+}
+
+std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
+                         Counts& cnt, int hoist) {
+  return compress_to(C, Lin, in, vector_target(C, Lin), Lout, cnt, hoist);
 }
 
 std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
-                   int dout, Layout& Lout, Counts& cnt) {
+                   int dout, Layout& Lout, Counts& cnt, const double* bias) {
   if (Lin.kind != KIND_VECTOR) throw std::runtime_error("fc: needs a vector layout");
   const int d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level;
   if (dout > d) throw std::runtime_error("fc: output larger than the vector");
@@ -758,6 +994,7 @@ std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, con
     y.scale = Lout.scale;
     out.push_back(y);
   }
+  if (bias) add_bias(C, Lout, out, bias);
   return out;
 }
 

@@ -45,9 +45,14 @@ void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, dou
 // pt_budget: plaintext bytes under which per-position weights are materialised
 // as full-scale plaintext diagonals instead of mask-basis scalar codes (the
 // distinct diagonals: those of one batch group)
+// target: write the output straight into that layout of the output tensor
+// (Arch-aware Ct Compression fused with the convolution: the repack masks
+// multiply the convolution's plaintexts, its rotations merge with the outer
+// rotations, one rescale); bias: bias[cout] added after the rescale
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
-                       long long pt_budget = 1LL << 30, int hoist = 0);
+                       long long pt_budget = 1LL << 30, int hoist = 0, const Layout* target = nullptr,
+                       const double* bias = nullptr);
 // hoist = 1: rotated copies stay in the extended basis and each combined
 // ciphertext is moved down once (see conv2d)
 std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
@@ -60,10 +65,28 @@ std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& i
                          const std::vector<double>& coeffs, Layout& Lout, Counts& cnt);
 // integer nearest to v (half away from zero) for |v| < 2^120, as a 128-bit integer
 i128 big_code(double v);
+// Repack (rot-mask-add) moves: the valid slots of source ct `src` that
+// Rot(., delta) carries to target ct `dst` (Rot(z, r)[i] = z[i + r])
+struct MoveGroup {
+  int src = 0, dst = 0;
+  long delta = 0;
+  std::vector<int> src_slots;
+};
+std::vector<MoveGroup> repack_groups(const Context& C, const Layout& Ls, const Layout& Ld);
+// a target layout of the tensor (bs, c, h, w), checked and completed
+Layout check_target(const Context& C, const Layout& T, int bs, int c, int h, int w);
+// the default compression target: one VECTOR ct per batch group, first fit
+Layout vector_target(const Context& C, const Layout& Lin);
+// Arch-aware Ct Compression into `target` (hoisted rotations per source, masks
+// at q_l Delta / s_in, one ModDown per target under hoist = 1, one rescale)
+std::vector<Ct> compress_to(Context& C, const Layout& Lin, const std::vector<Ct>& in, const Layout& target,
+                            Layout& Lout, Counts& cnt, int hoist = 0);
 std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
-                         Counts& cnt);
+                         Counts& cnt, int hoist = 0);
 std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
-                   int dout, Layout& Lout, Counts& cnt);
+                   int dout, Layout& Lout, Counts& cnt, const double* bias = nullptr);
+// bias[o] (channel o, or feature o of a VECTOR layout) added to every valid slot
+void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const double* bias);
 
 // scalar weight code: round half away from zero of w * scale in binary64
 i64 weight_code(double w, double scale);

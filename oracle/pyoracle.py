@@ -84,13 +84,14 @@ def _declare(L):
         "orc_batch_layout": (None, [vp, C.POINTER(OrcLayout)]),
         "orc_batch_data": (i, [vp, vp, u64p]),
         "orc_decrypt_tensor": (i, [vp, vp, f64p]),
-        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, i, C.POINTER(C.c_long)]),
+        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, i, C.POINTER(OrcLayout), vp,
+                            C.POINTER(C.c_long)]),
         "orc_avgpool2": (vp, [vp, vp, i, C.POINTER(C.c_long)]),
         "orc_pq_roundtrip": (i, [vp, u64p, i, vp, i, i, u64p]),
         "orc_square": (vp, [vp, vp, C.POINTER(C.c_long)]),
         "orc_poly_act": (vp, [vp, vp, f64p, i, C.POINTER(C.c_long)]),
-        "orc_compress": (vp, [vp, vp, C.POINTER(C.c_long)]),
-        "orc_fc": (vp, [vp, vp, f64p, i, C.POINTER(C.c_long)]),
+        "orc_compress": (vp, [vp, vp, C.POINTER(OrcLayout), i, C.POINTER(C.c_long)]),
+        "orc_fc": (vp, [vp, vp, f64p, i, vp, C.POINTER(C.c_long)]),
         "orc_weight_code": (C.c_int64, [d, d]),
         "orc_split_scale": (None, [d, C.POINTER(d), C.POINTER(d)]),
     }
@@ -334,6 +335,11 @@ class Oracle:
         h = lib().orc_batch_from(self.h, C.byref(lay), np.ascontiguousarray(data, np.uint64))
         return Batch(self, _check(h))
 
+    def decrypt_slots(self, batch):
+        """Real parts of the decoded slots of every ciphertext of a batch."""
+        scale = batch.layout()["scale"]
+        return [self.decode(self.decrypt(ct)[0], scale).real for ct in batch.data()]
+
     def decrypt_tensor(self, batch):
         L = batch.layout()
         x = np.zeros((L["bs"], L["c"], L["h"], L["w"]))
@@ -347,12 +353,16 @@ class Oracle:
             raise OracleError(lib().orc_last_error().decode())
         return Batch(self, h), dict(zip(COUNT_FIELDS, list(cnt)))
 
-    def conv2d(self, batch, w, stride=1, pad=0, groups=1, pt_budget=1 << 30, hoist=0):
+    def conv2d(self, batch, w, stride=1, pad=0, groups=1, pt_budget=1 << 30, hoist=0, target=None, bias=None):
         """hoist=1: the linear combination is taken in the extended basis Q_l U P
-        and each combined ciphertext is moved down once."""
+        and each combined ciphertext is moved down once.  target: a layout dict
+        of the output tensor the result is written into (the repack fused with
+        the convolution); bias: cout values added after the rescale."""
         w = np.ascontiguousarray(w, np.float64)
+        t, keep = (None, None) if target is None else dict_to_layout(target)
+        b = None if bias is None else np.ascontiguousarray(bias, np.float64)
         return self._op(lib().orc_conv2d, batch.h, w, w.shape[0], w.shape[2], stride, pad, groups, pt_budget,
-                        hoist)
+                        hoist, None if t is None else C.byref(t), None if b is None else b.ctypes.data)
 
     def avgpool2(self, batch, hoist=0):
         return self._op(lib().orc_avgpool2, batch.h, hoist)
@@ -364,12 +374,16 @@ class Oracle:
         c = np.ascontiguousarray(coeffs, np.float64)
         return self._op(lib().orc_poly_act, batch.h, c, len(c))
 
-    def compress(self, batch):
-        return self._op(lib().orc_compress, batch.h)
+    def compress(self, batch, target=None, hoist=0):
+        """target: a layout dict of the same tensor (None: one VECTOR ciphertext
+        per batch group, placed by first fit)."""
+        t, keep = (None, None) if target is None else dict_to_layout(target)
+        return self._op(lib().orc_compress, batch.h, None if t is None else C.byref(t), hoist)
 
-    def fc(self, batch, w):
+    def fc(self, batch, w, bias=None):
         w = np.ascontiguousarray(w, np.float64)
-        return self._op(lib().orc_fc, batch.h, w, w.shape[0])
+        b = None if bias is None else np.ascontiguousarray(bias, np.float64)
+        return self._op(lib().orc_fc, batch.h, w, w.shape[0], None if b is None else b.ctypes.data)
 
 
 def rot_total_formula(BS, Nin, Nout, K, S, alpha):

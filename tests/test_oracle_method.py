@@ -306,3 +306,103 @@ def test_conv2d_border_rotations_match_brute_force_when_block_covers_kernel(case
     got = o.decrypt_tensor(y)
     ref = cnn_ref.conv2d(rand_x(case["x"], 3), wt, case["stride"], case["pad"], 1)
     assert np.max(np.abs(got - ref)) < 1e-4
+
+
+# ---------------------------------------------------------------- Arch-aware Ct Compression
+
+def test_fused_compression_bottleneck_adds_no_level_and_packs_densely():
+    """Bottleneck 8 -> 2 -> 8 (Arch-aware Ct Compression, Fig. compression):
+    the 1x1 reduction writes its two channels straight into the dense layout
+    of the reduced tensor (the two channels repeated in every group of two of
+    the eight channel positions), at the level the reduction alone would
+    leave (no additional multiplicative depth: the masks multiply the weights'
+    plaintexts and share their rescale), with no rotation beyond the
+    reduction's own outer rotations.  The expansion layer then needs one outer
+    rotation per output ciphertext instead of seven."""
+    o = small_oracle(nq=6)                       # N = 2^10: 512 slots
+    x = rand_x((4, 8, 4, 4), 21)                 # 8 channels x 16 pixels x 4 images: one full ciphertext
+    w1, w2 = rand_w((2, 8, 1, 1), 22), rand_w((8, 2, 1, 1), 23)
+    L = o.fragment_layout(4, 8, 4, 4, 1)
+    assert (L["cpc"], L["ncg"], L["nbg"]) == (8, 1, 1)
+    b = o.encrypt_tensor(L, x, seed=2)
+    nat, cn = o.conv2d(b, w1, hoist=1)           # natural output: 2 of 8 positions used
+    dense_layout = o.fragment_layout(4, 2, 4, 4, 1)
+    assert dense_layout["rep"] == 1 and dense_layout["cpc"] == 8
+    fused, cf = o.conv2d(b, w1, hoist=1, target=dense_layout)
+    assert fused.layout()["level"] == nat.layout()["level"] == L["level"] - 1
+    assert fused.layout()["rep"] == 1 and len(fused.data()) == 1
+    assert cf["outer_rot"] == cn["outer_rot"] == 7 and cf["rescale"] == 1
+    ref = cnn_ref.conv2d(x, w1)
+    assert np.max(np.abs(o.decrypt_tensor(fused) - ref)) < 1e-4
+    # every replica holds the value: decrypt the raw slots of the ciphertext
+    o2 = o.decrypt_slots(fused)[0]
+    for rep in range(4):
+        for ch in range(2):
+            for img in range(4):
+                base = ((rep * 2 + ch) * 16) * 4 + img   # pixel (0, 0)
+                assert abs(o2[base] - ref[img, ch, 0, 0]) < 1e-4
+    y_nat, c_nat = o.conv2d(nat, w2, hoist=1)
+    y_den, c_den = o.conv2d(fused, w2, hoist=1)
+    assert (c_nat["outer_rot"], c_den["outer_rot"]) == (7, 1)
+    ref2 = cnn_ref.conv2d(ref, w2)
+    assert np.max(np.abs(o.decrypt_tensor(y_den) - ref2)) < 1e-4
+    assert np.max(np.abs(o.decrypt_tensor(y_nat) - ref2)) < 1e-4
+
+
+@pytest.mark.parametrize("hoist", [0, 1])
+def test_compression_into_fragment_and_vector_targets(hoist):
+    """Standalone rot-mask-add into an explicit target: decode(compress(x)) is
+    x in the target layout; the masks take one level (no preceding product to
+    share a scale with)."""
+    o = small_oracle(nq=6)
+    x = rand_x((4, 2, 4, 4), 31)
+    L = o.fragment_layout(4, 2, 4, 4, 2)         # S = 2: 4 fragment cts, 2 of 32 positions per block used
+    b = o.encrypt_tensor(L, x, seed=3)
+    for S_t in (1, 2, 4):
+        T = o.fragment_layout(4, 2, 4, 4, S_t)
+        c, cnt = o.compress(b, target=T, hoist=hoist)
+        Lc = c.layout()
+        assert (Lc["S"], Lc["rep"], Lc["level"]) == (S_t, T["rep"], L["level"] - 1)
+        assert np.max(np.abs(o.decrypt_tensor(c) - x)) < 1e-6
+    v, _ = o.compress(b, hoist=hoist)            # default: the first-fit vector
+    assert v.layout()["kind"] == 1 and np.max(np.abs(o.decrypt_tensor(v).reshape(x.shape) - x)) < 1e-6
+
+
+def test_fused_convolution_into_other_block_size_and_vector_layouts():
+    """The fused repack also changes the block size (S = 2 -> 1) and writes a
+    flattened FC vector, each at the convolution's own level.  A block-size
+    change moves every pixel row by its own shift, so it costs many rotations
+    (here 114 against the layer's 4 outer rotations)."""
+    o = small_oracle(nq=4)
+    x = rand_x((8, 2, 8, 8), 41)
+    w = rand_w((2, 2, 3, 3), 42)
+    ref = cnn_ref.conv2d(x, w, 1, 1)
+    L = o.fragment_layout(8, 2, 8, 8, 2)
+    b = o.encrypt_tensor(L, x, seed=4)
+    y, c = o.conv2d(b, w, 1, 1, 1, hoist=1, target=o.fragment_layout(8, 2, 8, 8, 1))
+    assert (y.layout()["S"], y.layout()["level"]) == (1, L["level"] - 1)
+    assert np.max(np.abs(o.decrypt_tensor(y) - ref)) < 1e-4
+    # S = 1 (one channel per ciphertext, 8 images) into a vector whose feature
+    # positions are rotated by five: the moves share a single shift
+    L = o.fragment_layout(8, 2, 8, 8, 1)
+    b = o.encrypt_tensor(L, x, seed=4)
+    w1 = rand_w((1, 2, 3, 3), 43)
+    vt = dict(o.fragment_layout(8, 1, 8, 8, 1), kind=1, d=o.ns // 8, nfeat=64, pos=[(f + 5) % 64 for f in range(64)])
+    y, c = o.conv2d(b, w1, 1, 1, 1, hoist=1, target=vt)
+    assert y.layout()["kind"] == 1 and y.layout()["pos"] == vt["pos"] and c["outer_rot"] == 1
+    assert np.max(np.abs(o.decrypt_tensor(y).reshape(8, 1, 8, 8) - cnn_ref.conv2d(x, w1, 1, 1))) < 1e-4
+
+
+def test_bias_is_added_at_the_output_scale():
+    o = small_oracle(nq=6)
+    x = rand_x((2, 3, 8, 8), 51)
+    w, bias = rand_w((4, 3, 3, 3), 52), np.array([0.5, -0.25, 0.125, 1.0])
+    L = o.fragment_layout(2, 3, 8, 8, 2)
+    b = o.encrypt_tensor(L, x, seed=5)
+    y, _ = o.conv2d(b, w, 1, 1, 1, hoist=1, bias=bias)
+    ref = cnn_ref.conv2d(x, w, 1, 1) + bias[None, :, None, None]
+    assert np.max(np.abs(o.decrypt_tensor(y) - ref)) < 1e-4
+    v, _ = o.compress(y)
+    fw, fb = rand_w((5, 256), 53), np.linspace(-1, 1, 5)
+    z, _ = o.fc(v, fw, bias=fb)
+    assert np.max(np.abs(o.decrypt_tensor(z).reshape(2, 5) - (ref.reshape(2, -1) @ fw.T + fb))) < 1e-4
