@@ -214,10 +214,24 @@ int fenc_ct_import(fenc_ctx* ctx, const uint64_t* host, fenc_ctbatch* out, void*
  * zero padding pad, groups | c and | cout.  Hoisted inner rotations (one
  * ModUp per input ciphertext), masked scalar multiply-accumulate, diagonal
  * outer rotations summed with one ModDown per output ciphertext, one rescale.
- * Output: same m, bs_g, C'; S and M divided by the stride; level - 1;
- * scale exactly Delta. */
-int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t cout, uint32_t k,
-                uint32_t stride, uint32_t pad, uint32_t groups, fenc_ctbatch* out, void* stream);
+ * bias: NULL or cout host doubles added to every valid output slot of their
+ * channel, encoded at the output scale after the rescale (no level).
+ * s_out == 0: output in the convolution's own layout (same m, bs_g, C'; S and
+ *   M divided by the stride; channels at positions 0.. of each ciphertext).
+ * s_out > 0: output written straight into the Alg. fragment-packing layout of
+ *   the output tensor with block size s_out (M from the output's size,
+ *   channels repeated in every group of positions when cout divides C'): the
+ *   Arch-aware Ct Compression repack fused with the convolution.  Its 0/1
+ *   masks multiply the convolution's own plaintexts (weights at Delta_w and
+ *   masks at Delta_m, Delta_w Delta_m = q_l Delta / scale_in) and its shifts
+ *   merge with the outer rotations, so it adds no product and no level; a
+ *   change of block size moves pixel rows by many shifts and costs rotations.
+ * Output level - 1, scale exactly Delta.  Errors: EINVAL (shapes, negative
+ * s_out, non-finite bias), EUNSUPPORTED (stride not dividing S), ELAYOUT
+ * (s_out not a power of two dividing the output's padded side), ELEVEL. */
+int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const double* bias, uint32_t cout,
+                uint32_t k, uint32_t stride, uint32_t pad, uint32_t groups, int32_t s_out, fenc_ctbatch* out,
+                void* stream);
 /* 2x2 average pooling, stride 2 (Evaluation methodology, implementation):
  * S >= 2 sums the four fragments of each block (no rotation); S == 1 sums
  * three hoisted rotations and doubles dil.  The factor 1/4 is carried in the
@@ -237,17 +251,28 @@ int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void
  * non-finite coefficients, ESCALE when a code exceeds 2^120. */
 int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, uint32_t degree,
                   fenc_ctbatch* out, void* stream);
-/* Arch-aware Ct Compression (rot-mask-add): packs a sparse FRAGMENT batch
- * into one VECTOR ciphertext per batch group; every source ciphertext is
- * masked and moved by one rotation, all rotations into an output share one
- * ModDown, and the mask scale is chosen so one rescale restores Delta.
- * target must be NULL (the library places the fragments). */
+/* Arch-aware Ct Compression (rot-mask-add) of a batch into a target layout
+ * of the same tensor: FRAGMENT (the Alg. fragment-packing layout of any block
+ * size, e.g. from fenc_plan_layout with s_override, or the dense repeated-
+ * channel layout) or VECTOR (an FC input; map_id 0 or a map the library
+ * returned); target == NULL: one VECTOR ciphertext per batch group with each
+ * source ciphertext's valid positions placed at the first free offset.  The
+ * target's level and scale are ignored.  Each source ciphertext is rotated
+ * once per shift it needs (one ModUp per source), the rotated copies are
+ * masked to the slots that move and summed per target (one ModDown per
+ * target); the masks are encoded at q_l Delta / scale_in and one rescale
+ * restores Delta, so the standalone repack costs one level (fused with a
+ * convolution it costs none: fenc_conv2d's s_out).  Errors: ELAYOUT for a
+ * target of another tensor or an invalid one, EUNSUPPORTED when the default
+ * vector does not fit one ciphertext, ELEVEL. */
 int fenc_compress(fenc_ctx* ctx, const fenc_ctbatch* in, const fenc_layout* target,
                   fenc_ctbatch* out, void* stream);
-/* Fully connected layer y = W x, w[dout][n_feat] (host) on a VECTOR layout:
- * diagonal method with baby-step giant-step (hoisted baby steps, giant steps
- * summed with one ModDown), one rescale; output features at positions 0..dout-1. */
-int fenc_fc(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t dout,
+/* Fully connected layer y = W x + bias, w[dout][n_feat] (host), bias NULL or
+ * dout host doubles, on a VECTOR layout: diagonal method with baby-step
+ * giant-step (hoisted baby steps, giant steps summed with one ModDown), one
+ * rescale, the bias added at the output scale; output features at positions
+ * 0..dout-1. */
+int fenc_fc(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const double* bias, uint32_t dout,
             fenc_ctbatch* out, void* stream);
 
 /* ---- building blocks exposed for testing --------------------------------

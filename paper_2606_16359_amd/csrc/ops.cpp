@@ -175,6 +175,128 @@ static void check_batch(const Ctx& C, const fenc_ctbatch* b, bool need_data) {
   if (need_data && !b->data) fail(FENC_EINVAL, "null ciphertext data");
 }
 
+// ---------------------------------------------------------------- repacking (Arch-aware Ct Compression)
+// The valid slots of source ct `src` that a left rotation by `delta` carries to
+// target ct `dst` (Rot(z, r)[i] = z[i + r]): the slot map between two layouts
+// of one tensor, grouped by (src, dst, delta).
+struct Move {
+  int src = 0, dst = 0;
+  long long delta = 0;
+  std::vector<int> slots;
+};
+
+static std::vector<Move> repack_moves(const Ctx& C, const Layout& Ls, const Layout& Ld) {
+  if (Ls.bs != Ld.bs || Ls.c != Ld.c || Ls.h != Ld.h || Ls.w != Ld.w) fail(FENC_ELAYOUT, "repack between different tensors");
+  std::map<std::tuple<int, int, long long>, std::vector<int>> g;
+  std::vector<std::pair<int, int>> a, b;
+  for (int n = 0; n < Ls.bs; n++)
+    for (int ch = 0; ch < Ls.c; ch++)
+      for (int y = 0; y < Ls.h; y++)
+        for (int x = 0; x < Ls.w; x++) {
+          layout_slots(Ls, n, ch, y, x, a);
+          layout_slots(Ld, n, ch, y, x, b);
+          for (auto& d : b) g[std::make_tuple(a[0].first, d.first, (long long)posmod((long long)a[0].second - d.second, C.ns))].push_back(a[0].second);
+        }
+  std::vector<Move> out;
+  for (auto& kv : g) {
+    Move m;
+    m.src = std::get<0>(kv.first);
+    m.dst = std::get<1>(kv.first);
+    m.delta = std::get<2>(kv.first);
+    m.slots = kv.second;
+    std::sort(m.slots.begin(), m.slots.end());
+    out.push_back(std::move(m));
+  }
+  return out;
+}
+
+// A caller's target layout of tensor (bs, c, h, w): FRAGMENT layouts must be
+// the Alg. fragment-packing layout of their block size, VECTOR layouts need
+// distinct feature positions below d = (N/2)/bs_g.
+static Layout target_layout(const Ctx& C, const Layout& T, int bs, int c, int h, int w) {
+  if (T.bs != bs || T.c != c || T.h != h || T.w != w) fail(FENC_ELAYOUT, "target describes another tensor");
+  if (T.kind == FENC_LAYOUT_FRAGMENT) {
+    Layout R = make_fragment(C.ns, T.level, T.scale, bs, c, h, w, T.S);
+    if (T.dil != 1 || R.M != T.M || R.m != T.m || R.bsg != T.bsg || R.cpc != T.cpc || R.nbg != T.nbg ||
+        R.ncg != T.ncg || R.rep != T.rep)
+      fail(FENC_ELAYOUT, "target is not the fragment layout of its block size");
+    return R;
+  }
+  if (T.kind != FENC_LAYOUT_VECTOR) fail(FENC_ELAYOUT, "unknown target kind");
+  if (T.bsg < 1 || T.d * T.bsg != C.ns || T.nbg != (bs + T.bsg - 1) / T.bsg || T.nfeat != c * h * w ||
+      (int)T.pos.size() != T.nfeat)
+    fail(FENC_ELAYOUT, "bad vector target");
+  std::set<int> seen(T.pos.begin(), T.pos.end());
+  if ((int)seen.size() != T.nfeat || *seen.begin() < 0 || *seen.rbegin() >= T.d)
+    fail(FENC_ELAYOUT, "vector target positions must be distinct and below d");
+  Layout R = T;
+  R.cpc = 1; R.ncg = 1; R.S = 1; R.m = 1; R.M = 1; R.rep = 0; R.dil = 1;
+  return R;
+}
+
+// Slot vectors of plaintexts, each distinct vector kept once.
+struct PtSet {
+  std::vector<std::vector<double>> slots;
+  std::map<uint64_t, std::vector<int>> by_hash;
+  int id(std::vector<double>&& z) {
+    const uint64_t h = fnv(z.data(), z.size() * sizeof(double));
+    auto& ids = by_hash[h];
+    for (int i : ids)
+      if (slots[i] == z) return i;
+    ids.push_back((int)slots.size());
+    slots.push_back(std::move(z));
+    return (int)slots.size() - 1;
+  }
+};
+
+// bias[ch] (bias[f] for VECTOR layouts) on every valid slot: out = in + B, B a
+// ciphertext-shaped buffer (c1 = 0) of the encoded bias plaintexts at the
+// output scale, one per distinct vector
+struct BiasStage {
+  GmacStage g;
+  u64* B = nullptr;
+  int nb = 0;
+};
+
+static BiasStage make_bias(Ctx& C, const Layout& L, const double* bias, std::vector<void*>& owner) {
+  BiasStage st;
+  const int n = L.n_ct(), nl = L.level + 1;
+  std::vector<std::vector<double>> z(n, std::vector<double>(C.ns, 0.0));
+  std::vector<std::pair<int, int>> sl;
+  for (int b = 0; b < L.bs; b++)
+    for (int ch = 0; ch < L.c; ch++)
+      for (int y = 0; y < L.h; y++)
+        for (int x = 0; x < L.w; x++) {
+          layout_slots(L, b, ch, y, x, sl);
+          for (auto& p : sl) z[p.first][p.second] = bias[L.kind == FENC_LAYOUT_VECTOR ? (ch * L.h + y) * L.w + x : ch];
+        }
+  PtSet ps;
+  std::vector<int> id(n);
+  for (int t = 0; t < n; t++) id[t] = ps.id(std::move(z[t]));
+  st.nb = (int)ps.slots.size();
+  const u64* pts = encode_plaintexts(C, ps.slots, L.scale, L.level, owner);
+  std::vector<uint64_t> zero((size_t)st.nb * 2 * nl * C.N, 0);
+  st.B = upload(C, zero, owner);
+  for (int i = 0; i < st.nb; i++)
+    fb::d2d_async(st.B + (size_t)i * 2 * nl * C.N, pts + (size_t)i * nl * C.N, (size_t)nl * C.N * 8, nullptr);
+  fb::sync(nullptr);
+  GmacBuild gb;
+  for (int t = 0; t < n; t++) {
+    gb.add_group(nullptr);
+    gb.add_term(t, -1);
+    gb.add_term(n + id[t], -1);
+    gb.end_group();
+    gb.end_output();
+  }
+  st.g = make_gmac(C, gb, {}, L.level, owner);
+  return st;
+}
+
+static void run_bias(Ctx& C, const BiasStage& st, int level, const u64* in, u64* out, int n, fb::Stream s) {
+  const long long ce = ct_elems(C, level), ps = (long long)(level + 1) * C.N;
+  run_gmac(C, level + 1, st.g, in, ce, ps, n, st.B, ce, ps, out, ce, ps, s);
+}
+
 // ---------------------------------------------------------------- hoisted rotation stage
 // copies[c] = Rot(in[src_c], shift_c); ModUp of each source once
 struct RotStage {
@@ -274,10 +396,15 @@ struct ConvPlan : Plan {
   KsStage md;        // pq: ModDown of the n_out + n_zr combined ciphertexts
   SumStage sum;
   long long n_terms = 0, n_masked = 0;
+  bool has_bias = false;
+  BiasStage bias;
 };
 
+// s_out > 0: the output is written in the fragment layout of the output
+// tensor with block size s_out (Arch-aware Ct Compression fused with the
+// convolution, see below); bias: cout values added at the output scale.
 static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout, int k, int stride, int pad,
-                            int groups, bool shape_only, Layout& Lout) {
+                            int groups, int s_out, const double* bias, bool shape_only, Layout& Lout) {
   if (Lin.kind != FENC_LAYOUT_FRAGMENT || Lin.dil != 1) fail(FENC_ELAYOUT, "conv2d needs a dense fragment layout");
   if (k < 1 || stride < 1 || pad < 0 || cout < 1) fail(FENC_EINVAL, "bad convolution shape");
   if (Lin.S % stride) fail(FENC_EUNSUPPORTED, "stride must divide the block size");
@@ -297,6 +424,9 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   Lout.ncg = (cout + cpc - 1) / cpc;
   Lout.level = lvl - 1;
   Lout.scale = C.Delta;
+  const Layout Lnat = Lout;   // the convolution's own output layout
+  const bool fused = s_out > 0;
+  if (fused) Lout = make_fragment(C.ns, lvl - 1, C.Delta, Lin.bs, cout, Lnat.h, Lnat.w, s_out);
   if (shape_only) return nullptr;
 
   auto P = new ConvPlan;
@@ -323,9 +453,9 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
     return false;
   };
   struct Term { int idx; long long shift; int u, v, dbi, dbj, di, dj, gi; };
-  const int So = Lout.S, ncg_out = Lout.ncg;
+  const int So = Lnat.S, ncg_out = Lnat.ncg;
   P->n_out = Lout.n_ct();
-  std::vector<std::vector<Term>> terms(P->n_out);
+  std::vector<std::vector<Term>> terms(Lnat.n_ct());
   std::map<std::pair<int, long long>, int> copy_id;
   for (int bg = 0; bg < Lin.nbg; bg++)
     for (int go = 0; go < ncg_out; go++)
@@ -424,11 +554,11 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   // groups[o][r]: plaintext id -> terms (input id, weight id); plaintext ids index
   // mask_slots (mask-basis) or diag_slots (materialised, one term per group)
   typedef std::map<int, std::vector<std::pair<int, int>>> Groups;
-  std::vector<std::vector<Groups>> G(P->n_out, std::vector<Groups>(nd));
-  std::vector<std::vector<char>> act(P->n_out, std::vector<char>(nd, 0));
+  std::vector<std::vector<Groups>> G(fused ? 0 : P->n_out, std::vector<Groups>(nd));
+  std::vector<std::vector<char>> act(fused ? 0 : P->n_out, std::vector<char>(nd, 0));
   std::vector<std::vector<double>> diag_slots;
   std::map<std::tuple<int, int, int>, int> diag_id;   // (output of group 0, term, diagonal) -> plaintext
-  for (int oct = 0; oct < P->n_out; oct++) {
+  for (int oct = 0; oct < (fused ? 0 : P->n_out); oct++) {
     const int go = (oct / (So * So)) % ncg_out;
     for (size_t ti = 0; ti < terms[oct].size(); ti++) {
       const Term& t = terms[oct][ti];
@@ -479,9 +609,91 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
       }
     }
   }
+  // Fused repack (Arch-aware Ct Compression, one rescale for both products):
+  // natural output o is y_o = sum_r Rot(z_{o,r}, s_r); the repack adds
+  // Rot(A_g (.) y_o, delta_g) into target ct d_g for each move g of o.  A 0/1
+  // mask commutes with the rotation sum, A (.) Rot(z, s) = Rot(Rot(A, -s) (.) z, s),
+  // so A multiplies the plaintexts of z_{o,r} (masks or materialised
+  // diagonals, at the convolution's own scales) and the two rotations merge:
+  // target d = sum_sigma Rot(Z_{d,sigma}, sigma), sigma = s_r + delta_g, with
+  // one ModDown and the layer's single rescale.  A term enters Z_{d,sigma}
+  // when its mask pattern meets the moved slots (zero weights included).
+  PtSet fset;
+  std::map<std::pair<int, long long>, Groups> GT;
+  if (fused) {
+    const std::vector<Move> mv = repack_moves(C, Lnat, Lout);
+    std::vector<char> ra(C.ns);
+    for (const Move& g : mv) {
+      const int oct = g.src, go = (oct / (So * So)) % ncg_out;
+      for (int r = 0; r < nd; r++) {
+        const long long sr = (long long)r * m * m * bsg, sigma = posmod(sr + g.delta, C.ns);
+        std::fill(ra.begin(), ra.end(), 0);
+        for (int sl : g.slots) ra[posmod(sl + sr, C.ns)] = 1;
+        for (const Term& t : terms[oct]) {
+          const int in_id = t.shift ? P->n_in + copy_id[{t.idx, t.shift}]
+                                    : (P->pq ? P->n_in + (int)copies.size() + t.idx : t.idx);
+          if (materialise) {
+            std::vector<double> z(C.ns, 0.0);
+            bool any = false;
+            for (int q = 0; q < npos; q++) {
+              const int ch = in_channel(t.gi, q), o = go * cpc + posmod(q - r, cpc);
+              if (!pair_ok(ch, o)) continue;
+              const double wv = wval(o, ch, t);
+              for (int bi = 0; bi < m; bi++)
+                for (int bj = 0; bj < m; bj++) {
+                  if (!valid_src(t, bi, bj)) continue;
+                  for (int jb = 0; jb < bsg; jb++) {
+                    const int slot = ((q * m + bi) * m + bj) * bsg + jb;
+                    if (ra[slot]) {
+                      z[slot] = wv;
+                      any = true;
+                    }
+                  }
+                }
+            }
+            if (!any) continue;
+            GT[{g.dst, sigma}][fset.id(std::move(z))].push_back({in_id, -1});
+            P->n_terms++;
+            continue;
+          }
+          for (int q = 0; q < npos; q++) {
+            const int ch = in_channel(t.gi, q), o = go * cpc + posmod(q - r, cpc);
+            if (!pair_ok(ch, o)) continue;
+            std::vector<double> z(C.ns, 0.0);
+            bool any = false;
+            if (need_mask) {
+              for (int bi = 0; bi < m; bi++)
+                for (int bj = 0; bj < m; bj++) {
+                  if (!valid_src(t, bi, bj)) continue;
+                  for (int jb = 0; jb < bsg; jb++) {
+                    const int slot = ((q * m + bi) * m + bj) * bsg + jb;
+                    if (ra[slot]) {
+                      z[slot] = 1.0;
+                      any = true;
+                    }
+                  }
+                }
+            } else {
+              for (int i = 0; i < C.ns; i++)
+                if (ra[i]) {
+                  z[i] = 1.0;
+                  any = true;
+                }
+            }
+            if (!any) continue;
+            const int64_t code = weight_code(wval(o, ch, t), dw);
+            GT[{g.dst, sigma}][fset.id(std::move(z))].push_back({in_id, weight_id(code)});
+            P->n_terms++;
+          }
+        }
+      }
+    }
+  }
   const u64* masks =
-      materialise ? (diag_slots.empty() ? nullptr : encode_plaintexts(C, diag_slots, T, lvl, P->owned, P->pq))
-                  : (mask_slots.empty() ? nullptr : encode_plaintexts(C, mask_slots, dm, lvl, P->owned, P->pq));
+      fused ? (fset.slots.empty() ? nullptr
+                                  : encode_plaintexts(C, fset.slots, materialise ? T : dm, lvl, P->owned, P->pq))
+      : materialise ? (diag_slots.empty() ? nullptr : encode_plaintexts(C, diag_slots, T, lvl, P->owned, P->pq))
+                    : (mask_slots.empty() ? nullptr : encode_plaintexts(C, mask_slots, dm, lvl, P->owned, P->pq));
   const long long pe = (long long)(lvl + 1 + (P->pq ? C.K : 0)) * C.N;
   GmacBuild b0, br;
   std::vector<int> sum_out, sum_base;
@@ -495,7 +707,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
     }
     gb.end_output();
   };
-  for (int o = 0; o < P->n_out; o++) {
+  for (int o = 0; o < (fused ? 0 : P->n_out); o++) {
     emit(b0, G[o][0]);
     std::vector<std::pair<int, long long>> tl;
     for (int r = 1; r < nd; r++)
@@ -509,10 +721,35 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
       sum_terms.push_back(tl);
     }
   }
+  for (int d = 0; d < (fused ? P->n_out : 0); d++) {
+    auto z0 = GT.find({d, 0LL});
+    if (z0 != GT.end()) {
+      emit(b0, z0->second);
+    } else {   // no unrotated part: an exact zero (one term of weight 0)
+      b0.add_group(nullptr);
+      b0.add_term(0, weight_id(0));
+      b0.end_group();
+      b0.end_output();
+    }
+    std::vector<std::pair<int, long long>> tl;
+    for (auto it = GT.lower_bound({d, 1LL}); it != GT.end() && it->first.first == d; ++it) {
+      emit(br, it->second);
+      tl.push_back({P->n_zr++, it->first.second});
+    }
+    if (!tl.empty()) {
+      sum_out.push_back(d);
+      sum_base.push_back(d);
+      sum_terms.push_back(tl);
+    }
+  }
   P->g0 = make_gmac(C, b0, codes, lvl, P->owned, P->pq, P->n_in);
   P->gr = make_gmac(C, br, codes, lvl, P->owned, P->pq, P->n_in);
   if (P->pq) P->md = make_md(C, P->n_out + P->n_zr, P->owned);
   P->sum = make_sum_stage(C, sum_out, sum_base, sum_terms, P->owned, P->n_zr);
+  if (bias) {
+    P->has_bias = true;
+    P->bias = make_bias(C, Lout, bias, P->owned);
+  }
   return P;
 }
 
@@ -540,7 +777,13 @@ static void run_conv(Ctx& C, const ConvPlan& P, const u64* in, u64* out, fb::Str
     run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, copies, ce, ps, zr, ce, ps, s);
   }
   run_sum_stage(C, lvl, P.sum, zr, y, y, s);
-  rescale(C, lvl, y, P.n_out, out, s);
+  if (P.has_bias) {
+    u64* t = (u64*)C.arena.get((size_t)P.n_out * ct_elems(C, lvl - 1) * 8, s);
+    rescale(C, lvl, y, P.n_out, t, s);
+    run_bias(C, P.bias, lvl - 1, t, out, P.n_out, s);
+  } else {
+    rescale(C, lvl, y, P.n_out, out, s);
+  }
   C.cnt.rot_inner += P.rot.n;
   C.cnt.rot_outer += P.n_zr;
   C.cnt.keyswitch += P.rot.n + P.n_zr;
@@ -748,14 +991,18 @@ static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Str
 
 // ---------------------------------------------------------------- compress (AAC)
 struct CompressPlan : Plan {
-  int level = 0, n_in = 0, n_out = 0, n_zr = 0;
-  GmacStage g0, gr;
-  SumStage sum;
+  int level = 0, n_in = 0, n_out = 0;
+  bool pq = false;   // masked copies summed in the extended basis, one ModDown per target
+  RotStage rot;
+  GmacStage g;
+  KsStage md;
 };
 
-static CompressPlan* build_compress(Ctx& C, const Layout& Lin, bool shape_only, Layout& Lout) {
+// The library's own target when the caller gives none: one VECTOR ciphertext
+// per batch group; the valid positions of each source ciphertext go to the
+// first offset where they fit (greedy first fit in ciphertext order).
+static Layout vector_target(const Ctx& C, const Layout& Lin) {
   if (Lin.kind != FENC_LAYOUT_FRAGMENT) fail(FENC_ELAYOUT, "compress packs fragment layouts");
-  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the compression mask");
   const int bsg = Lin.bsg, d = C.ns / bsg, per_bg = Lin.ncg * Lin.S * Lin.S;
   std::vector<std::set<int>> Pset(per_bg);
   std::vector<std::pair<int, int>> sl;
@@ -779,19 +1026,33 @@ static CompressPlan* build_compress(Ctx& C, const Layout& Lin, bool shape_only, 
     phi[t] = f;
     for (int p : Pset[t]) occ[p + f] = 1;
   }
-  Lout = Layout();
-  Lout.kind = FENC_LAYOUT_VECTOR;
-  Lout.bs = Lin.bs; Lout.c = Lin.c; Lout.h = Lin.h; Lout.w = Lin.w;
-  Lout.bsg = bsg; Lout.nbg = Lin.nbg; Lout.cpc = 1; Lout.ncg = 1; Lout.S = 1; Lout.m = 1; Lout.M = 1;
-  Lout.d = d;
-  Lout.nfeat = Lin.c * Lin.h * Lin.w;
-  Lout.pos.resize(Lout.nfeat);
+  Layout T;
+  T.kind = FENC_LAYOUT_VECTOR;
+  T.bs = Lin.bs; T.c = Lin.c; T.h = Lin.h; T.w = Lin.w;
+  T.bsg = bsg; T.nbg = Lin.nbg; T.cpc = 1; T.ncg = 1; T.S = 1; T.m = 1; T.M = 1;
+  T.d = d;
+  T.nfeat = Lin.c * Lin.h * Lin.w;
+  T.pos.resize(T.nfeat);
   for (int ch = 0; ch < Lin.c; ch++)
     for (int y = 0; y < Lin.h; y++)
       for (int x = 0; x < Lin.w; x++) {
         layout_slots(Lin, 0, ch, y, x, sl);
-        Lout.pos[(ch * Lin.h + y) * Lin.w + x] = sl[0].second / bsg + phi[sl[0].first];
+        T.pos[(ch * Lin.h + y) * Lin.w + x] = sl[0].second / bsg + phi[sl[0].first];
       }
+  T.level = Lin.level;
+  T.scale = Lin.scale;
+  return T;
+}
+
+// Rot-mask-add into a target layout (Arch-aware Ct Compression without a
+// preceding product to share a scale with): each source ciphertext is rotated
+// once per shift it needs (hoisted: one ModUp per source), each rotated copy
+// is masked to the slots that move with that shift, and the masked copies of
+// a target ciphertext are summed (in Q_l U P with one ModDown per target
+// under hoisting schedule 1).  Masks at q_l Delta / s_in: one rescale, one level.
+static CompressPlan* build_compress(Ctx& C, const Layout& Lin, const Layout* target, bool shape_only, Layout& Lout) {
+  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the compression mask");
+  Lout = target ? target_layout(C, *target, Lin.bs, Lin.c, Lin.h, Lin.w) : vector_target(C, Lin);
   Lout.level = Lin.level - 1;
   Lout.scale = C.Delta;
   if (shape_only) return nullptr;
@@ -800,64 +1061,76 @@ static CompressPlan* build_compress(Ctx& C, const Layout& Lin, bool shape_only, 
   P->level = Lin.level;
   P->n_in = Lin.n_ct();
   P->n_out = Lout.n_ct();
+  const std::vector<Move> mv = repack_moves(C, Lin, Lout);
+  std::map<std::pair<int, long long>, int> copy_id;
+  for (const Move& g : mv)
+    if (g.delta) copy_id[{g.src, g.delta}] = 0;
+  std::vector<std::pair<int, long long>> copies;
+  {   // copies ordered by shift, so rotations that share a key are adjacent
+    std::vector<std::pair<long long, int>> bykey;
+    for (auto& kv : copy_id) bykey.push_back({kv.first.second, kv.first.first});
+    std::sort(bykey.begin(), bykey.end());
+    for (auto& kv : bykey) {
+      copy_id[{kv.second, kv.first}] = (int)copies.size();
+      copies.push_back({kv.second, kv.first});
+    }
+  }
+  P->pq = C.hoist != 0 && !copies.empty();
+  P->rot = make_rot_stage(C, copies, P->owned, P->pq);
   const double dm = ((double)C.primes[Lin.level] * C.Delta) / Lin.scale;
-  std::vector<std::vector<double>> ms;
-  std::vector<int> mid(per_bg, -1);
-  for (int t = 0; t < per_bg; t++) {
-    if (Pset[t].empty()) continue;
-    std::vector<double> z(C.ns, 0.0);
-    for (int p : Pset[t])
-      for (int jb = 0; jb < bsg; jb++) z[p * bsg + jb] = 1.0;
-    mid[t] = (int)ms.size();
-    ms.push_back(z);
+  PtSet ps;
+  std::vector<std::vector<std::pair<int, int>>> groups(P->n_out);   // per target: (plaintext, input)
+  for (const Move& g : mv) {
+    std::vector<double> z(C.ns, 0.0);   // the moved slots after the rotation
+    for (int sl : g.slots) z[posmod((long long)sl - g.delta, C.ns)] = 1.0;
+    const int in_id = g.delta ? P->n_in + copy_id[{g.src, g.delta}]
+                              : (P->pq ? P->n_in + (int)copies.size() + g.src : g.src);
+    groups[g.dst].push_back({ps.id(std::move(z)), in_id});
   }
-  const u64* masks = encode_plaintexts(C, ms, dm, Lin.level, P->owned);
-  const long long pe = (long long)(Lin.level + 1) * C.N;
-  GmacBuild b0, br;
-  std::vector<int> so, sb;
-  std::vector<std::vector<std::pair<int, long long>>> st;
-  for (int bg = 0; bg < Lin.nbg; bg++) {
-    std::vector<std::pair<int, long long>> tl;
-    for (int t = 0; t < per_bg; t++) {
-      if (mid[t] < 0 || phi[t] != 0) continue;
-      b0.add_group(masks + mid[t] * pe);
-      b0.add_term(bg * per_bg + t, -1);
-      b0.end_group();
+  const u64* masks = ps.slots.empty() ? nullptr : encode_plaintexts(C, ps.slots, dm, Lin.level, P->owned, P->pq);
+  const long long pe = (long long)(Lin.level + 1 + (P->pq ? C.K : 0)) * C.N;
+  GmacBuild gb;
+  std::vector<int64_t> codes = {0};
+  for (int d = 0; d < P->n_out; d++) {
+    if (groups[d].empty()) {   // nothing moves here: an exact zero (one term of weight 0)
+      gb.add_group(nullptr);
+      gb.add_term(0, 0);
+      gb.end_group();
     }
-    b0.end_output();
-    for (int t = 0; t < per_bg; t++) {
-      if (mid[t] < 0 || phi[t] == 0) continue;
-      br.add_group(masks + mid[t] * pe);
-      br.add_term(bg * per_bg + t, -1);
-      br.end_group();
-      br.end_output();
-      tl.push_back({P->n_zr++, posmod(-(long long)phi[t] * bsg, C.ns)});
+    for (auto& gt : groups[d]) {
+      gb.add_group(masks + gt.first * pe);
+      gb.add_term(gt.second, -1);
+      gb.end_group();
     }
-    if (!tl.empty()) {
-      so.push_back(bg);
-      sb.push_back(bg);
-      st.push_back(tl);
-    }
+    gb.end_output();
   }
-  P->g0 = make_gmac(C, b0, {}, Lin.level, P->owned);
-  P->gr = make_gmac(C, br, {}, Lin.level, P->owned);
-  P->sum = make_sum_stage(C, so, sb, st, P->owned, P->n_zr);
+  P->g = make_gmac(C, gb, codes, Lin.level, P->owned, P->pq, P->n_in);
+  if (P->pq) P->md = make_md(C, P->n_out, P->owned);
   return P;
 }
 
 static void run_compress(Ctx& C, const CompressPlan& P, const u64* in, u64* out, fb::Stream s) {
-  const int lvl = P.level, nl = lvl + 1;
+  const int lvl = P.level, nl = lvl + 1, le = nl + C.K;
   const long long ce = ct_elems(C, lvl), ps = (long long)nl * C.N;
   Scope sc(C.arena);
   u64* y = (u64*)C.arena.get((size_t)P.n_out * ce * 8, s);
-  u64* zr = (u64*)C.arena.get((size_t)std::max(1, P.n_zr) * ce * 8, s);
-  run_gmac(C, nl, P.g0, in, ce, ps, P.n_in, nullptr, 0, ps, y, ce, ps, s);
-  run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, nullptr, 0, ps, zr, ce, ps, s);
-  run_sum_stage(C, lvl, P.sum, zr, y, y, s);
+  if (P.pq) {
+    const long long ee = 2LL * le * C.N, pe = (long long)le * C.N;
+    u64* copies = (u64*)C.arena.get((size_t)(P.rot.n + P.n_in) * ee * 8, s);   // copies, then lifted inputs
+    u64* yp = (u64*)C.arena.get((size_t)P.n_out * ee * 8, s);
+    run_rot_stage(C, lvl, P.rot, in, copies, s, true);
+    lift_to_pq(C, lvl, in, P.n_in, copies + (long long)P.rot.n * ee, s);
+    run_gmac(C, nl, P.g, in, ce, ps, P.n_in, copies, ee, pe, yp, ee, pe, s);
+    moddown_only(C, lvl, yp, P.md, y, ce, s);
+  } else {
+    u64* copies = (u64*)C.arena.get((size_t)std::max(1, P.rot.n) * ce * 8, s);
+    run_rot_stage(C, lvl, P.rot, in, copies, s);
+    run_gmac(C, nl, P.g, in, ce, ps, P.n_in, copies, ce, ps, y, ce, ps, s);
+  }
   rescale(C, lvl, y, P.n_out, out, s);
-  C.cnt.rot_other += P.n_zr;
-  C.cnt.keyswitch += P.n_zr;
-  C.cnt.pmult += P.n_in;
+  C.cnt.rot_other += P.rot.n;
+  C.cnt.keyswitch += P.rot.n;
+  C.cnt.pmult += P.g.n_masked;
   C.cnt.cts_out += P.n_out;
 }
 
@@ -867,9 +1140,12 @@ struct FcPlan : Plan {
   RotStage rot;
   GmacStage g0, gr;
   SumStage sum;
+  bool has_bias = false;
+  BiasStage bias;
 };
 
-static FcPlan* build_fc(Ctx& C, const Layout& Lin, const double* W, int dout, bool shape_only, Layout& Lout) {
+static FcPlan* build_fc(Ctx& C, const Layout& Lin, const double* W, int dout, const double* bias, bool shape_only,
+                        Layout& Lout) {
   if (Lin.kind != FENC_LAYOUT_VECTOR) fail(FENC_ELAYOUT, "fc needs a vector layout");
   if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the fc layer");
   const int d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level;
@@ -961,6 +1237,10 @@ static FcPlan* build_fc(Ctx& C, const Layout& Lin, const double* W, int dout, bo
   P->g0 = make_gmac(C, b0, {}, lvl, P->owned);
   P->gr = make_gmac(C, br, {}, lvl, P->owned);
   P->sum = make_sum_stage(C, so, sb, st, P->owned, P->n_zr);
+  if (bias) {
+    P->has_bias = true;
+    P->bias = make_bias(C, Lout, bias, P->owned);
+  }
   return P;
 }
 
@@ -975,7 +1255,13 @@ static void run_fc(Ctx& C, const FcPlan& P, const u64* in, u64* out, fb::Stream 
   run_gmac(C, nl, P.g0, in, ce, ps, P.n_in, copies, ce, ps, y, ce, ps, s);
   run_gmac(C, nl, P.gr, in, ce, ps, P.n_in, copies, ce, ps, zr, ce, ps, s);
   run_sum_stage(C, lvl, P.sum, zr, y, y, s);
-  rescale(C, lvl, y, P.n_out, out, s);
+  if (P.has_bias) {
+    u64* t = (u64*)C.arena.get((size_t)P.n_out * ct_elems(C, lvl - 1) * 8, s);
+    rescale(C, lvl, y, P.n_out, t, s);
+    run_bias(C, P.bias, lvl - 1, t, out, P.n_out, s);
+  } else {
+    rescale(C, lvl, y, P.n_out, out, s);
+  }
   C.cnt.rot_other += P.rot.n + P.n_zr;
   C.cnt.keyswitch += P.rot.n + P.n_zr;
   C.cnt.cts_out += P.n_out;
@@ -1412,32 +1698,38 @@ int fenc_ct_import(fenc_ctx* ctx, const uint64_t* host, fenc_ctbatch* out, void*
   API_END
 }
 
-int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t cout, uint32_t k, uint32_t stride,
-                uint32_t pad, uint32_t groups, fenc_ctbatch* out, void* stream) {
+int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const double* bias, uint32_t cout, uint32_t k,
+                uint32_t stride, uint32_t pad, uint32_t groups, int32_t s_out, fenc_ctbatch* out, void* stream) {
   API_BEGIN
   if (!ctx || !w || !out) fail(FENC_EINVAL, "null argument");
+  if (s_out < 0) fail(FENC_EINVAL, "s_out must be 0 (natural layout) or a block size");
   check_batch(*ctx, in, false);
   fenc_ctx& C = *ctx;
   Layout Lin = from_pub(C, &in->lay), Lout;
-  build_conv(C, Lin, w, cout, k, stride, pad, groups, true, Lout);
+  if (bias)
+    for (uint32_t o = 0; o < cout; o++)
+      if (!std::isfinite(bias[o])) fail(FENC_EINVAL, "non-finite bias");
+  build_conv(C, Lin, w, cout, k, stride, pad, groups, s_out, bias, true, Lout);
   out->lay = to_pub(C, Lout);
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
   const size_t nw = (size_t)cout * (Lin.c / groups) * k * k;
-  const uint64_t wh = fnv(w, nw * sizeof(double));
+  const uint64_t wh = fnv(w, nw * sizeof(double)), bh = bias ? fnv(bias, cout * sizeof(double)) : 0;
   auto plan_of = [&](int cnt) -> ConvPlan& {
     const Layout Ls = sub_layout(Lin, cnt);
     std::ostringstream key;
     key << "conv|" << layout_key(Ls) << '|' << cout << ',' << k << ',' << stride << ',' << pad << ',' << groups << ','
-        << wh << ',' << C.pt_budget << ',' << C.hoist;
+        << wh << ',' << bh << ',' << s_out << ',' << C.pt_budget << ',' << C.hoist;
     return cached<ConvPlan>(C, key.str(), [&] {
       Layout lo;
-      return build_conv(C, Ls, w, cout, k, stride, pad, groups, false, lo);
+      return build_conv(C, Ls, w, cout, k, stride, pad, groups, s_out, bias, false, lo);
     });
   };
+  // a fused repack into another batch grouping cannot be split by groups
+  const bool tileable = s_out == 0 || (Lout.bsg == Lin.bsg && Lout.nbg == Lin.nbg);
   int tile = Lin.nbg;
-  if (Lin.nbg > 1 && C.ws_limit > 0) {
+  if (Lin.nbg > 1 && C.ws_limit > 0 && tileable) {
     const ConvPlan& P1 = plan_of(1);
     tile = tile_groups(C, Lin.nbg, conv_ws_bytes(C, P1.level, P1.pq, (int)P1.rot.src.size(), P1.rot.n, P1.n_in,
                                                  P1.n_out, P1.n_zr));
@@ -1582,34 +1874,44 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
 int fenc_compress(fenc_ctx* ctx, const fenc_ctbatch* in, const fenc_layout* target, fenc_ctbatch* out, void* stream) {
   API_BEGIN
   if (!ctx || !out) fail(FENC_EINVAL, "null argument");
-  if (target) fail(FENC_EUNSUPPORTED, "explicit compression targets are not supported");
   check_batch(*ctx, in, false);
   fenc_ctx& C = *ctx;
-  Layout Lin = from_pub(C, &in->lay), Lout;
-  build_compress(C, Lin, true, Lout);
+  Layout Lin = from_pub(C, &in->lay), Lout, Lt;
+  if (target) {
+    Lt = from_pub(C, target);
+    Lt.level = Lin.level;   // the target's level and scale are outputs
+  }
+  build_compress(C, Lin, target ? &Lt : nullptr, true, Lout);
   out->lay = to_pub(C, Lout);
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
-  CompressPlan& P = cached<CompressPlan>(C, "aac|" + layout_key(Lin), [&] { return build_compress(C, Lin, false, Lout); });
+  CompressPlan& P = cached<CompressPlan>(C, "aac|" + layout_key(Lin) + "|" + (target ? layout_key(Lt) : "") +
+                                                (C.hoist ? "|h" : ""),
+                                         [&] { return build_compress(C, Lin, target ? &Lt : nullptr, false, Lout); });
   run_compress(C, P, in->data, out->data, (fb::Stream)stream);
   API_END
 }
 
-int fenc_fc(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, uint32_t dout, fenc_ctbatch* out, void* stream) {
+int fenc_fc(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const double* bias, uint32_t dout,
+            fenc_ctbatch* out, void* stream) {
   API_BEGIN
   if (!ctx || !w || !out) fail(FENC_EINVAL, "null argument");
   check_batch(*ctx, in, false);
   fenc_ctx& C = *ctx;
   Layout Lin = from_pub(C, &in->lay), Lout;
-  build_fc(C, Lin, w, dout, true, Lout);
+  if (bias)
+    for (uint32_t o = 0; o < dout; o++)
+      if (!std::isfinite(bias[o])) fail(FENC_EINVAL, "non-finite bias");
+  build_fc(C, Lin, w, dout, bias, true, Lout);
   out->lay = to_pub(C, Lout);
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
   std::ostringstream key;
-  key << "fc|" << layout_key(Lin) << '|' << dout << ',' << fnv(w, (size_t)dout * Lin.nfeat * sizeof(double));
-  FcPlan& P = cached<FcPlan>(C, key.str(), [&] { return build_fc(C, Lin, w, dout, false, Lout); });
+  key << "fc|" << layout_key(Lin) << '|' << dout << ',' << fnv(w, (size_t)dout * Lin.nfeat * sizeof(double)) << ','
+      << (bias ? fnv(bias, dout * sizeof(double)) : 0);
+  FcPlan& P = cached<FcPlan>(C, key.str(), [&] { return build_fc(C, Lin, w, dout, bias, false, Lout); });
   run_fc(C, P, in->data, out->data, (fb::Stream)stream);
   API_END
 }

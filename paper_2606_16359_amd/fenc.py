@@ -13,6 +13,7 @@ from . import build as _build
 
 FENC_LAYOUT_FRAGMENT, FENC_LAYOUT_VECTOR = 0, 1
 FENC_MODE_BATCHED, FENC_MODE_PER_OP = 0, 1
+FENC_ENOMEM = -2
 RELIN = -(1 << 31)
 
 STATUS = {0: "FENC_OK", -1: "FENC_EINVAL", -2: "FENC_ENOMEM", -3: "FENC_ENOKEY", -4: "FENC_ELEVEL",
@@ -104,11 +105,11 @@ def load(path=None):
         "fenc_decrypt_raw": (C.c_int, [vp, B, vp, vp]),
         "fenc_ct_export": (C.c_int, [vp, B, vp, vp]),
         "fenc_ct_import": (C.c_int, [vp, vp, B, vp]),
-        "fenc_conv2d": (C.c_int, [vp, B, vp, u32, u32, u32, u32, u32, B, vp]),
+        "fenc_conv2d": (C.c_int, [vp, B, vp, vp, u32, u32, u32, u32, u32, C.c_int32, B, vp]),
         "fenc_avgpool2": (C.c_int, [vp, B, B, vp]),
         "fenc_poly_act": (C.c_int, [vp, B, vp, u32, B, vp]),
         "fenc_compress": (C.c_int, [vp, B, L, B, vp]),
-        "fenc_fc": (C.c_int, [vp, B, vp, u32, B, vp]),
+        "fenc_fc": (C.c_int, [vp, B, vp, vp, u32, B, vp]),
         "fenc_rotate": (C.c_int, [vp, B, vp, u32, B, vp]),
         "fenc_rotate_sum": (C.c_int, [vp, B, B, vp, u32, B, vp]),
         "fenc_rescale": (C.c_int, [vp, B, B, vp]),
@@ -317,21 +318,35 @@ class Fenc:
         return ct
 
     # ------------------------------------------------------------ server side
-    def _op(self, fn, *args, inp=None):
-        """Two-call convention: size the output, allocate it, run."""
+    def _op(self, fn, *args, keep=None):
+        """Two-call convention: size the output, allocate it, run.  When the
+        library's workspace allocation fails, the cached blocks PyTorch holds
+        are returned to the device and the call is made once more (an
+        operation reads only its input and writes only its output, so running
+        it again is safe)."""
         out = CtBatch()
         out.data = None
         self._check(fn(*args, C.byref(out), self._stream()))
         res = self.alloc_cts(out.lay.copy())
         ob = res.struct()
-        self._check(fn(*args, C.byref(ob), self._stream()))
+        rc = fn(*args, C.byref(ob), self._stream())
+        if rc == FENC_ENOMEM and not self.emulated:
+            import torch
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            rc = fn(*args, C.byref(ob), self._stream())
+        self._check(rc)
         return res
 
-    def conv2d(self, ct, w, stride=1, pad=0, groups=1):
+    def conv2d(self, ct, w, stride=1, pad=0, groups=1, bias=None, s_out=0):
+        """s_out > 0: the output goes straight into the fragment layout of block
+        size s_out (the compression repack fused with the convolution)."""
         w = np.ascontiguousarray(w, np.float64)
+        bv = None if bias is None else np.ascontiguousarray(bias, np.float64)
         b = ct.struct()
-        return self._op(self.lib.fenc_conv2d, self.h, C.byref(b), w.ctypes.data, w.shape[0], w.shape[2], stride,
-                        pad, groups)
+        return self._op(self.lib.fenc_conv2d, self.h, C.byref(b), w.ctypes.data,
+                        None if bv is None else bv.ctypes.data, w.shape[0], w.shape[2], stride, pad, groups, s_out,
+                        keep=bv)
 
     def avgpool2(self, ct):
         b = ct.struct()
@@ -342,14 +357,18 @@ class Fenc:
         b = ct.struct()
         return self._op(self.lib.fenc_poly_act, self.h, C.byref(b), c.ctypes.data, len(c) - 1)
 
-    def compress(self, ct):
+    def compress(self, ct, target=None):
+        """target: a Layout of the same tensor (None: the library's vector)."""
         b = ct.struct()
-        return self._op(self.lib.fenc_compress, self.h, C.byref(b), None)
+        t = None if target is None else target.copy()
+        return self._op(self.lib.fenc_compress, self.h, C.byref(b), None if t is None else C.byref(t))
 
-    def fc(self, ct, w):
+    def fc(self, ct, w, bias=None):
         w = np.ascontiguousarray(w, np.float64)
+        bv = None if bias is None else np.ascontiguousarray(bias, np.float64)
         b = ct.struct()
-        return self._op(self.lib.fenc_fc, self.h, C.byref(b), w.ctypes.data, w.shape[0])
+        return self._op(self.lib.fenc_fc, self.h, C.byref(b), w.ctypes.data, None if bv is None else bv.ctypes.data,
+                        w.shape[0], keep=bv)
 
     def rescale(self, ct):
         b = ct.struct()

@@ -159,6 +159,77 @@ def test_batch_group_tiles_give_identical_residues(backend, orc):
     assert np.array_equal(ref, yo.data())
 
 
+def _layout_dict(o, lay):
+    d = o.fragment_layout(lay.bs, lay.c, lay.h, lay.w, lay.S)
+    assert (d["bsg"], d["cpc"], d["rep"], d["M"]) == (lay.bs_g, lay.chan_per_ct, lay.replicate, lay.M)
+    return d
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("budget,hoist", [(1 << 30, 1), (0, 1), (1 << 30, 0), (0, 0)])
+def test_fused_compression_bottleneck_bit_exact(backend, budget, hoist, orc):
+    """8 -> 2 -> 8 bottleneck: the reduction writes its output straight into
+    the dense repeated-channel layout (the repack fused with the convolution,
+    same level), then the expansion runs with a bias; both bit-exact against
+    the oracle, with the oracle's rotation counts."""
+    o, f = orc, make(backend, *SMALL)
+    f.set_plaintext_budget(budget)
+    f.set_hoisting(hoist)
+    r = rng(21)
+    x, w1, w2 = r.uniform(0, 1, (4, 8, 4, 4)), r.normal(0, 0.1, (2, 8, 1, 1)), r.normal(0, 0.1, (8, 2, 1, 1))
+    bias = np.linspace(-0.5, 0.5, 8)
+    lay = f.plan_layout(4, 8, 4, 4, 1, 2, 1)
+    Lo = o.fragment_layout(4, 8, 4, 4, 1)
+    fb, ob = f.encrypt(f.encode_fragment(x, lay), lay, 3), o.encrypt_tensor(Lo, x, 3)
+    f.stats_reset()
+    y = f.conv2d(fb, w1, s_out=1)
+    assert (y.lay.replicate, y.n_ct, y.lay.level) == (1, 1, lay.level - 1)
+    yo, cnt = o.conv2d(ob, w1, pt_budget=budget, hoist=hoist, target=o.fragment_layout(4, 2, 4, 4, 1))
+    cmp(y, yo, f)
+    st = f.stats()
+    assert (st["rot_inner"], st["rot_outer"]) == (cnt["inner_rot"], cnt["outer_rot"])
+    z = f.conv2d(y, w2, bias=bias)
+    zo, _ = o.conv2d(yo, w2, pt_budget=budget, hoist=hoist, bias=bias)
+    cmp(z, zo, f)
+    ref = cnn_ref.conv2d(cnn_ref.conv2d(x, w1), w2) + bias[None, :, None, None]
+    assert np.max(np.abs(f.decrypt(z) - ref)) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_compression_targets_and_fused_block_size_change_bit_exact(backend, orc):
+    """Standalone compression into fragment targets of three block sizes and
+    into the library's vector; a convolution fused with a block-size change
+    (S = 2 -> 1); an FC layer with a bias."""
+    o, f = orc, make(backend, *SMALL)
+    r = rng(31)
+    x = r.uniform(0, 1, (4, 2, 4, 4))
+    lay = f.plan_layout(4, 2, 4, 4, 3, 2, 2)
+    Lo = o.fragment_layout(4, 2, 4, 4, 2)
+    fb, ob = f.encrypt(f.encode_fragment(x, lay), lay, 5), o.encrypt_tensor(Lo, x, 5)
+    for S_t in (1, 2, 4):
+        T = f.plan_layout(4, 2, 4, 4, 3, 2, S_t)
+        c = f.compress(fb, T)
+        co, _ = o.compress(ob, target=_layout_dict(o, T), hoist=f.hoist)
+        assert (c.lay.S, c.lay.level) == (S_t, lay.level - 1)
+        cmp(c, co, f)
+        assert np.max(np.abs(f.decrypt(c) - x)) < 1e-6
+    v = f.compress(fb)
+    vo, _ = o.compress(ob, hoist=f.hoist)
+    cmp(v, vo, f)
+    fw, fbias = r.normal(0, 0.1, (5, 32)), np.linspace(-1, 1, 5)
+    cmp(f.fc(v, fw, bias=fbias), o.fc(vo, fw, bias=fbias)[0], f)
+    # fused S = 2 -> 1 (8 images, 2 channels of 8 x 8)
+    x8 = r.uniform(0, 1, (8, 2, 8, 8))
+    w = r.normal(0, 0.1, (2, 2, 3, 3))
+    lay8 = f.plan_layout(8, 2, 8, 8, 3, 2, 2)
+    L8 = o.fragment_layout(8, 2, 8, 8, 2)
+    y = f.conv2d(f.encrypt(f.encode_fragment(x8, lay8), lay8, 6), w, pad=1, s_out=1)
+    yo, _ = o.conv2d(o.encrypt_tensor(L8, x8, 6), w, 1, 1, 1, hoist=f.hoist, target=o.fragment_layout(8, 2, 8, 8, 1))
+    assert y.lay.S == 1
+    cmp(y, yo, f)
+    assert np.max(np.abs(f.decrypt(y) - cnn_ref.conv2d(x8, w, 1, 1))) < 1e-4
+
+
 WIDE = (10, 10, 40, 10, 40, 1, 30, 19)   # one digit of 10 limbs, 10 special primes
 
 
@@ -209,7 +280,7 @@ def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
              ("conv", lambda c: f.conv2d(c, w2), lambda b: o.conv2d(b, w2, pt_budget=budget, hoist=hoist)[0]),
              ("square", f.poly_act, lambda b: o.square(b)[0]),
              ("pool-rotations", f.avgpool2, lambda b: o.avgpool2(b, hoist)[0]),
-             ("compress", f.compress, lambda b: o.compress(b)[0]),
+             ("compress", f.compress, lambda b: o.compress(b, hoist=f.hoist)[0]),
              ("fc", lambda c: f.fc(c, f1), lambda b: o.fc(b, f1)[0]),
              ("fc", lambda c: f.fc(c, f2), lambda b: o.fc(b, f2)[0])]
     for name, fl, ol in steps:
