@@ -1,17 +1,25 @@
-"""Benchmark: encrypted LeNet-5-shaped inference on one MI355X.
+"""Benchmark: encrypted CNN inference on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): 64 synthetic
-28x28 images, conv 1->6 5x5, x^2, avgpool, conv 6->16 5x5, x^2, avgpool,
-compression into one ciphertext, FC 256->120->84->10; RNS-CKKS N=2^15, 20 x
-50-bit primes, dnum 3, scale 2^40.  Inputs are encrypted and resident in HBM
-before timing; a step is the whole server-side circuit for the batch.
+Headline (`value`): the largest configuration that fits one GPU, the three
+MobileNet-V1-shaped early blocks at ImageNet shape (224x224x3 input; conv 3->32
+stride 2; depthwise 3x3 32 + pointwise 32->64; depthwise 3x3 stride 2 64 +
+pointwise 64->128; a quadratic after each conv), each block from a fresh
+encryption, with the largest batch that fits HBM (64 images); RNS-CKKS
+N=2^16, 24 x 50-bit primes + 6 special, dnum 4, scale 2^40.  Inputs are
+encrypted and resident in HBM before timing; a step is the whole server-side
+circuit of the batch, captured once as a hipGraph and replayed.
 
-Reported: images/s and key switches/s of the batched form replayed as one
-hipGraph (value), beside the per-op form (every homomorphic operation of every
-ciphertext launched separately), the roofline of the dominant kernel measured
-with HIP events, and the CPU oracle on a bounded sample.
+Beside it: the same step in the per-op form (every homomorphic operation of
+every ciphertext launched separately) and the batch/per-op ratio; every
+kernel's time and algorithmic bytes from HIP events on its launch stream, the
+roofline of the dominant one; the smaller configurations (the single 28x28
+conv layer at N=2^13, the LeNet-5-shaped network of 64 images at N=2^15, the
+CIFAR-shaped stack of 256 images at N=2^16), each graph-replayed beside its
+per-op form; and the CPU oracle, per-operation times on the host cores scaled
+by the step's operation counts (extrapolated).
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -24,16 +32,247 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
-KERNELS = ["gmac", "gmac_pt", "gmac_ptv", "gmac_fast", "gmac_pt_fast", "gmac_ptv_fast", "gmac_diag", "ntt_fwd_rows", "ntt_fwd_cols", "kip", "ntt_inv_rows", "ntt_inv_cols", "ntt_fwd_rows_md", "ntt_fwd_rows_rs",
-           "moddown_fbc", "modup_fbc", "ntt_fwd_cols_lift", "tensor_square", "lin_comb", "lift_pq"]
-# HBM bytes per launch measured with FETCH_SIZE + WRITE_SIZE counters (scaled by
-# a copy kernel of known size), per kernel; only kernels unchanged since the
-# counters were taken are listed
-TRAFFIC = {"kip": 856641821, "gmac_diag": 351891405, "ntt_fwd_rows_md": 387996651, "ntt_fwd_cols": 236305473, "gmac_pt_fast": 1520051062, "ntt_fwd_rows": 271866994, "ntt_fwd_rows_rs": 298941831, "ntt_inv_rows": 70454841, "modup_fbc": 256676267, "gmac_fast": 623971824, "moddown_fbc": 151133327, "tensor_square": 477123177, "lift_pq": 187025851, "ntt_fwd_cols_lift": 102150723, "ntt_inv_cols": 68019147}
+MOBILENET_BATCH = 64
+WORKSPACE_LIMIT = 24 << 30
+METRIC = "encrypted images/sec (batched hipGraph, bit-exact)"
+DTYPE = "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic"
+# HBM bytes per launch from FETCH_SIZE + WRITE_SIZE counters (scaled by a copy
+# of known size), per (workload, kernel); an entry is kept only while its
+# kernel is unchanged since the counters were taken
+TRAFFIC = {}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def fingerprint(outs):
+    """Checksum of a step's output ciphertexts: the wrapped int64 sum of every
+    word and every 7919th word, computed on the device."""
+    import torch
+    fp = []
+    for ct in outs:
+        t = ct.buf
+        fp.append((int(t.sum().item()), int(t[::7919].sum().item()), int(t.numel())))
+    return fp
+
+
+def measure(fe, step, imgs, steps, warmup, per_op_steps, tag, graph=True):
+    """Warm-up, counters, eager and per-op timings, the per-kernel table, then
+    the hipGraph capture and its timed replays."""
+    import torch
+    from paper_2606_16359_amd import fenc as F
+    out = None
+    for i in range(max(1, warmup)):
+        t0 = time.time()
+        out = None           # the previous step's outputs go before the next step allocates its own
+        out = step()
+        torch.cuda.synchronize()
+        log(f"[{tag}] warmup {i} {time.time() - t0:.2f}s")
+    ref_fp = fingerprint(out)
+    out = None
+    fe.stats_reset()
+    step()
+    torch.cuda.synchronize()
+    st = fe.stats()
+    n_eager = max(1, min(3, steps // 4))
+    t0 = time.perf_counter()
+    for _ in range(n_eager):
+        step()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / n_eager
+    fe.set_mode(F.FENC_MODE_PER_OP)
+    out = step()
+    torch.cuda.synchronize()
+    per_op_identical = fingerprint(out) == ref_fp
+    del out
+    t0 = time.perf_counter()
+    for _ in range(per_op_steps):
+        step()
+    torch.cuda.synchronize()
+    t_perop = (time.perf_counter() - t0) / per_op_steps
+    fe.set_mode(F.FENC_MODE_BATCHED)
+    kernels = kernel_table(fe, step)
+    gc.collect()
+    torch.cuda.empty_cache()
+    res = {"images": imgs, "step_counters": st, "keyswitches_per_step": st["keyswitch"],
+           "launches_per_step": st["launches"],
+           "batched_eager": {"images_per_s": round(imgs / t_eager, 3), "ms_per_step": round(t_eager * 1e3, 3)},
+           "per_op": {"images_per_s": round(imgs / t_perop, 3), "ms_per_step": round(t_perop * 1e3, 3),
+                      "keyswitches_per_s": round(st["keyswitch"] / t_perop, 1)},
+           "kernels": kernels}
+    t_best, graph_identical = t_eager, None
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            out_graph = step()
+        for _ in range(2):     # replays interleaved with eager device work
+            g.replay()
+            torch.cuda.synchronize()
+        graph_identical = fingerprint(out_graph) == ref_fp
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        t_best = (time.perf_counter() - t0) / steps
+        res["graph"] = {"images_per_s": round(imgs / t_best, 3), "ms_per_step": round(t_best * 1e3, 3)}
+        del g, out_graph
+        gc.collect()
+        torch.cuda.empty_cache()
+    res["images_per_s"] = round(imgs / t_best, 3)
+    res["ms_per_step"] = round(t_best * 1e3, 3)
+    res["keyswitches_per_s"] = round(st["keyswitch"] / t_best, 1)
+    res["batched_vs_per_op"] = round(t_perop / t_best, 3)
+    res["bit_identical"] = {"per_op_vs_batched": per_op_identical, "graph_vs_eager": graph_identical}
+    log(f"[{tag}] {json.dumps({k: v for k, v in res.items() if k != 'kernels'})}")
+    return res
+
+
+def kernel_table(fe, step):
+    """Per-kernel time and algorithmic bytes of one batched step: HIP events
+    around every launch, on the launch stream."""
+    import torch
+    fe.profile_kernel("*")
+    step()
+    torch.cuda.synchronize()
+    summ = fe.profile_summary()
+    fe.profile_kernel(None)
+    kernels = {}
+    for name, (kms, klaunch, kbytes) in sorted(summ.items(), key=lambda kv: -kv[1][0]):
+        avg_s = kms / 1e3 / klaunch
+        gbs = kbytes / klaunch / avg_s / 1e9
+        kernels[name] = {"launches": klaunch, "ms_per_step": round(kms, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+                         "bytes_per_launch": round(kbytes / klaunch), "achieved_GBs": round(gbs, 1),
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    return kernels
+
+
+def roofline(kernels, workload):
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    return {"kernel": dom, "bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((workload, dom)),
+            "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],
+            "bytes_per_launch": kd["bytes_per_launch"]}
+
+
+# ---------------------------------------------------------------- workloads
+def run_conv1(args):
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["conv1_small"])
+    x, w = W.conv1_inputs()
+    lay = fe.plan_layout(1, 1, 28, 28, 5, 6)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    r = measure(fe, lambda: [fe.conv2d(ct, w)], 1, max(10, args.steps), 2, 5, "conv1")
+    r["workload"] = "single conv 1->6 5x5 on one 28x28 image, N=2^13, 4 x 40-bit + 1 special, scale 2^30"
+    return r
+
+
+def run_lenet(args):
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["lenet"])
+    x, w = W.lenet_inputs(64)
+    lay = fe.plan_layout(64, 1, 28, 28, 5, 6)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    r = measure(fe, lambda: [W.lenet_forward(fe, ct, w)], 64, max(10, args.steps), 2, 2, "lenet")
+    r["workload"] = ("LeNet-5-shaped network, 64 images 28x28, N=2^15, 20 x 50-bit + 7 special, dnum 3, "
+                     "scale 2^40, fragment S=%d" % lay.S)
+    r["roofline"] = roofline(r["kernels"], "lenet")
+    return r
+
+
+def run_cifar(args):
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["cifar"])
+    x, w = W.cifar_inputs(256)
+    lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    r = measure(fe, lambda: [W.cifar_forward(fe, ct, w)], 256, max(3, args.steps // 4), 2, 1, "cifar")
+    r["workload"] = ("CIFAR-shaped stack, 256 images 16x32x32 (3 x conv 16->16, conv 16->32 s2, conv 32->32, "
+                     "a cubic after each), N=2^16, 24 x 50-bit + 6 special, dnum 4, scale 2^40")
+    r["roofline"] = roofline(r["kernels"], "cifar")
+    return r
+
+
+def mobilenet_context(batch):
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["cifar"])
+    fe.set_workspace_limit(WORKSPACE_LIMIT)
+    t0 = time.time()
+    cts = W.mobilenet_encrypt(fe, batch)
+    log(f"[mobilenet] encode+encrypt of {batch} images: {time.time() - t0:.1f}s")
+    return fe, cts, W.mobilenet_weights()
+
+
+def cpu_baseline(counters, imgs, level):
+    """The oracle (plain C++ with 128-bit integers) on the host cores: its
+    per-operation times at the headline's parameters (ModUp with a hoisted
+    rotation, further hoisted rotations, plaintext and scalar products,
+    rescale, square with relinearisation), single-threaded and with one thread
+    per core over independent ciphertexts, scaled by the operation counts of
+    one step (extrapolated; the ops are timed at the top level)."""
+    from oracle import pyoracle as P
+    from paper_2606_16359_amd import workloads as W
+    t0 = time.time()
+    o = P.Oracle(*W.PARAMS["cifar"])
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t1 = P.time_ops(o, level, 1, 1)
+    tn = P.time_ops(o, level, cores, 1)
+    rot = counters["rot_inner"] + counters["rot_outer"] + counters["rot_other"]
+
+    def step_s(t):
+        return (counters["modup"] * t["modup_rot"] + max(0, rot - counters["modup"]) * t["rot"]
+                + counters["pmult"] * t["pmult"] + counters["smult"] * t["smult"]
+                + counters["rescale"] * t["rescale"] + counters["relin"] * t["square_relin"])
+    s1, sn = step_s(t1), step_s(tn)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    log(f"oracle per-op seconds (1 thread) {t1}; ({cores} threads) {tn}; {time.time() - t0:.1f}s in all")
+    return {"value": round(imgs / sn, 6), "unit": "images/s", "cores": cores, "kind": "oracle",
+            "single_thread_images_per_s": round(imgs / s1, 6), "cpu": model,
+            "sample": (f"oracle per-operation times at N=2^16, 24 limbs (one op per thread, {cores} threads and 1), "
+                       f"times the step's counts (modup {counters['modup']}, rotations {rot}, "
+                       f"pmult {counters['pmult']}, smult {counters['smult']}, rescale {counters['rescale']}, "
+                       f"relin {counters['relin']}); extrapolated")}
+
+
+def counters_run(args):
+    """Short run for hardware-counter passes: one warm-up step, a 256 MiB
+    device copy (calibrates the byte counters), one batched step; no timing."""
+    import torch
+    from paper_2606_16359_amd import workloads as W
+    if args.workload == "mobilenet":
+        fe, cts, ws = mobilenet_context(args.batch)
+
+        def step():
+            return W.mobilenet_forward(fe, cts, ws)
+    else:
+        from paper_2606_16359_amd import fenc as F
+        fe = F.Fenc(*W.PARAMS["lenet"])
+        x, w = W.lenet_inputs(64)
+        lay = fe.plan_layout(64, 1, 28, 28, 5, 6)
+        ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+
+        def step():
+            return W.lenet_forward(fe, ct, w)
+    step()
+    torch.cuda.synchronize()
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.int64, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    step()
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": True, "workload": args.workload, "copy_bytes": COPY_BYTES}), flush=True)
 
 
 def main():
@@ -41,263 +280,79 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--per-op-steps", type=int, default=2)
-    ap.add_argument("--profile-kernel", default="auto",
-                    help="kernel for the roofline object; auto = the one with the most time per step")
+    ap.add_argument("--per-op-steps", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=MOBILENET_BATCH, help="MobileNet images per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--workload", choices=["lenet", "cifar", "mobilenet"], default="lenet",
-                    help="lenet: the headline benchmark; cifar / mobilenet: secondary full-size measurements")
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--workload", choices=["mobilenet", "lenet"], default="mobilenet",
+                    help="workload of the --counters run")
     ap.add_argument("--counters", action="store_true",
-                    help="short run for hardware-counter passes: one warm-up step, a 256 MiB device copy "
-                         "(calibration of the byte counters), one batched step; no timing")
+                    help="short run for hardware-counter passes (one warm-up step, a 256 MiB copy, one step)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "one GPU only: the library runs on a single device; the path would "
-                                   "shard by independent ciphertext batches, which is not implemented"}))
+        print(json.dumps({"error": "one GPU only: this build runs every configuration on a single MI355X; the "
+                                   "path would shard by independent batch groups, which is not implemented"}))
         sys.exit(2)
-
-    if args.workload != "lenet":
-        other_workload(args)
-        return
-
     import torch
-    from paper_2606_16359_amd import fenc as F
-    from paper_2606_16359_amd import workloads as W
-
-    params = W.PARAMS["lenet"]
-    fe = F.Fenc(*params)
-    x, w = W.lenet_inputs(args.batch)
-    lay = fe.plan_layout(args.batch, 1, 28, 28, 5, 6)
-    log(f"layout S={lay.S} bs_g={lay.bs_g} C'={lay.chan_per_ct} n_ct={lay.n_ct()}")
-    t0 = time.time()
-    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
-    torch.cuda.synchronize()
-    log(f"encode+encrypt {time.time() - t0:.2f}s")
-
-    def step():
-        return W.lenet_forward(fe, ct, w)
-
+    torch.cuda.set_device(0)
     if args.counters:
-        step()
-        torch.cuda.synchronize()
-        src = torch.empty(COPY_BYTES // 8, dtype=torch.int64, device="cuda").fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)          # the calibration copy: COPY_BYTES read, COPY_BYTES written
-        torch.cuda.synchronize()
-        step()
-        torch.cuda.synchronize()
-        print(json.dumps({"counters_run": True, "copy_bytes": COPY_BYTES}), flush=True)
+        counters_run(args)
         return
 
-    # warm-up: builds plans, keys and workspace
-    for i in range(max(1, args.warmup)):
-        t0 = time.time()
-        out_eager = step()
-        torch.cuda.synchronize()
-        log(f"warmup {i} {time.time() - t0:.2f}s")
-    fe.stats_reset()
-    step()
-    torch.cuda.synchronize()
-    st = fe.stats()
-    ks_per_step = st["keyswitch"]
-    log(f"per step: {st}")
+    extras = {}
+    if not args.no_extras:
+        for name, fn in [("single_conv_n2p13", run_conv1), ("lenet64_n2p15", run_lenet),
+                         ("cifar256_n2p16", run_cifar)]:
+            t0 = time.time()
+            extras[name] = fn(args)
+            gc.collect()
+            torch.cuda.empty_cache()
+            log(f"[{name}] done in {time.time() - t0:.1f}s")
 
-    # batched form captured once into a hipGraph, then replayed
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        out_graph = step()
-    torch.cuda.synchronize()
-    g.replay()
-    torch.cuda.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        g.replay()
-    torch.cuda.synchronize()
-    t_graph = (time.perf_counter() - t0) / args.steps
-    graph_bits = fe.export(out_graph)
-    eager_bits = fe.export(step())
-    identical_graph = bool(np.array_equal(graph_bits, eager_bits))
-
-    # batched eager (no graph)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(max(1, args.steps // 2)):
-        step()
-    torch.cuda.synchronize()
-    t_eager = (time.perf_counter() - t0) / max(1, args.steps // 2)
-
-    # per-op form
-    fe.set_mode(F.FENC_MODE_PER_OP)
-    out_pop = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.per_op_steps):
-        out_pop = step()
-    torch.cuda.synchronize()
-    t_perop = (time.perf_counter() - t0) / args.per_op_steps
-    identical_perop = bool(np.array_equal(fe.export(out_pop), eager_bits))
-    fe.set_mode(F.FENC_MODE_BATCHED)
-
-    kernels = kernel_table(fe, step)
-    dom = args.profile_kernel
-    if dom == "auto":
-        dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    kd = kernels[dom]
-    achieved = kd["achieved_GBs"]
-
-    imgs = args.batch
-    value = imgs / t_graph
+    from paper_2606_16359_amd import workloads as W
+    fe, cts, ws = mobilenet_context(args.batch)
+    r = measure(fe, lambda: W.mobilenet_forward(fe, cts, ws), args.batch, args.steps, args.warmup,
+                args.per_op_steps, "mobilenet")
     res = {
-        "metric": "encrypted images/sec (batched hipGraph, bit-exact)",
-        "value": round(value, 3),
+        "metric": METRIC,
+        "value": r["images_per_s"],
         "unit": "images/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_graph * 1e3, 3),
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic",
-        "data": "synthetic (uniform [0,1) 28x28 images, N(0,0.1) weights, seeded)",
-        "config": {"workload": "LeNet-5-shaped encrypted CNN, 64 images, RNS-CKKS N=2^15, "
-                               "20x50-bit limbs, dnum 3, scale 2^40",
-                   "batch_images": imgs, "log_n": params[0], "limbs": params[1], "dnum": params[5],
-                   "fragment_S": lay.S},
-        "keyswitches_per_s": round(ks_per_step / t_graph, 1),
-        "keyswitches_per_step": ks_per_step,
-        "per_op": {"images_per_s": round(imgs / t_perop, 3), "ms_per_step": round(t_perop * 1e3, 3),
-                   "keyswitches_per_s": round(ks_per_step / t_perop, 1)},
-        "batched_eager": {"images_per_s": round(imgs / t_eager, 3), "ms_per_step": round(t_eager * 1e3, 3)},
-        "graph_vs_per_op": round(t_perop / t_graph, 3),
-        "bit_identical": {"graph_vs_eager": identical_graph, "per_op_vs_batched": identical_perop},
-        "launches_per_step": st["launches"],
-        "step_counters": st,
+        "dtype": DTYPE,
+        "data": "synthetic (uniform [0,1) images of the ImageNet/CIFAR/MNIST shapes, N(0,0.1) weights, seeded)",
+        "config": {"workload": ("MobileNet-V1-shaped early blocks at ImageNet shape 224x224x3 (conv 3->32 s2; "
+                                "dw 3x3 32 + pw 32->64; dw 3x3 s2 64 + pw 64->128; a quadratic after each conv), "
+                                f"{args.batch} images (the largest batch that fits HBM), each block from a fresh "
+                                "encryption, RNS-CKKS N=2^16, 24x50-bit limbs + 6 special, dnum 4, scale 2^40"),
+                   "batch_images": args.batch, "log_n": 16, "limbs": 24, "dnum": 4,
+                   "workspace_limit_bytes": WORKSPACE_LIMIT},
+        "keyswitches_per_s": r["keyswitches_per_s"],
+        "keyswitches_per_step": r["keyswitches_per_step"],
+        "per_op": r["per_op"],
+        "batched_eager": r["batched_eager"],
+        "graph_vs_per_op": r["batched_vs_per_op"],
+        "bit_identical": r["bit_identical"],
+        "launches_per_step": r["launches_per_step"],
+        "step_counters": r["step_counters"],
         "ntt_config": fe.ntt_config(),
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC.get(dom), "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],
-                     "bytes_per_launch": kd["bytes_per_launch"]},
-        "kernels": kernels,
+        "device_bytes_context": fe.device_bytes(),
+        "roofline": roofline(r["kernels"], "mobilenet"),
+        "kernels": r["kernels"],
+        "other_configs": {k: {kk: vv for kk, vv in v.items() if kk != "kernels"} for k, v in extras.items()},
     }
+    level = cts[0].lay.level
+    del cts, fe
+    gc.collect()
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(x, w, params, lay, ks_per_step, imgs)
+        res["cpu_baseline"] = cpu_baseline(r["step_counters"], args.batch, level)
     print(json.dumps(res), flush=True)
-
-
-def kernel_table(fe, step):
-    """Per-kernel time and algorithmic bytes: HIP events around each launch of
-    one kernel over one batched step, one kernel at a time."""
-    import torch
-    kernels = {}
-    for name in KERNELS:
-        fe.profile_kernel(name)
-        step()
-        torch.cuda.synchronize()
-        kms, klaunch, kbytes = fe.profile_result()
-        if klaunch:
-            avg_s = kms / 1e3 / klaunch
-            gbs = kbytes / klaunch / avg_s / 1e9
-            kernels[name] = {"launches": klaunch, "ms_per_step": round(kms, 4), "avg_launch_us": round(avg_s * 1e6, 2),
-                             "bytes_per_launch": round(kbytes / klaunch), "achieved_GBs": round(gbs, 1),
-                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
-    fe.profile_kernel(None)
-    log("kernels: " + json.dumps(kernels))
-    return kernels
-
-
-def other_workload(args):
-    """Secondary full-size measurements, batched eager form, one JSON line:
-    cifar: the CIFAR-shaped stack, 256 images 16x32x32, N = 2^16 (five 3x3
-    convs, a cubic after each); mobilenet: the three MobileNet-V1-shaped blocks
-    at 224x224, 16 images, each block from its own encryption.  The headline
-    benchmark is the LeNet-shaped network (the default workload)."""
-    import torch
-    from paper_2606_16359_amd import fenc as F
-    from paper_2606_16359_amd import workloads as W
-    fe = F.Fenc(*W.PARAMS["cifar"])
-    if args.workload == "cifar":
-        imgs = 256
-        x, w = W.cifar_inputs(imgs)
-        lay = fe.plan_layout(imgs, 16, 32, 32, 3, 16)
-        cts = [fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)]
-
-        def step():
-            return [W.cifar_forward(fe, cts[0], w)]
-        desc = "CIFAR-shaped stack, 256 images 16x32x32, RNS-CKKS N=2^16, 24x50-bit limbs, dnum 4, scale 2^40"
-    else:
-        imgs = 16
-        ws = W.mobilenet_weights()
-        cts = []
-        for b, (blk, ((c, h, wd), S)) in enumerate(zip(W.MOBILENET_BLOCKS, W.MOBILENET_INPUTS)):
-            lay = fe.plan_layout(imgs, c, h, wd, blk[0]["w"][2], blk[0]["w"][0], S)
-            cts.append(fe.encrypt(fe.encode_fragment(W.images((imgs, c, h, wd), seed=1 + b), lay), lay,
-                                  W.SEED_ENC + b))
-
-        def step():
-            return [W.mobilenet_block(fe, ct, blk, wb) for ct, blk, wb in zip(cts, W.MOBILENET_BLOCKS, ws)]
-        desc = ("MobileNet-V1-shaped blocks at 224x224 (conv 3->32 s2; dw 32 + pw 32->64; dw 64 s2 + pw 64->128), "
-                "16 images, RNS-CKKS N=2^16, 24x50-bit limbs, dnum 4, scale 2^40")
-    torch.cuda.synchronize()
-    for i in range(max(1, args.warmup)):
-        t0 = time.time()
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup {i} {time.time() - t0:.2f}s")
-    fe.stats_reset()
-    step()
-    torch.cuda.synchronize()
-    st = fe.stats()
-    steps = max(1, min(args.steps, 5))
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / steps
-    kernels = kernel_table(fe, step)
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    kd = kernels[dom]
-    print(json.dumps({
-        "metric": "encrypted images/sec (batched, bit-exact)", "value": round(imgs / t, 3), "unit": "images/s",
-        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic",
-        "data": "synthetic (uniform [0,1) images, N(0,0.1) weights, seeded)",
-        "config": {"workload": desc, "batch_images": imgs},
-        "keyswitches_per_s": round(st["keyswitch"] / t, 1), "keyswitches_per_step": st["keyswitch"],
-        "launches_per_step": st["launches"], "step_counters": st, "ntt_config": fe.ntt_config(),
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],
-                     "bytes_per_launch": kd["bytes_per_launch"]},
-        "kernels": kernels}), flush=True)
-
-
-def cpu_baseline(x, w, params, lay, ks_per_step, imgs):
-    """The oracle (single-threaded C++ with 128-bit integers) on a bounded
-    sample: the hoisted inner rotations of one input ciphertext of the first
-    convolution (one ModUp, 8 key switches), with the rotation keys generated
-    beforehand, scaled to the network by its key-switch count."""
-    from oracle import pyoracle as P
-    t0 = time.time()
-    o = P.Oracle(*params)
-    L = o.plan_layout(lay.bs, 1, 28, 28, 5, 6)
-    ct0 = o.encrypt_tensor(L, x, 4).data()[0]
-    m, bsg, S = L["m"], L["bsg"], L["S"]
-    reach = -(-5 // S)   # block offsets 0..ceil(K/S)-1 in each direction
-    shifts = [(di * m + dj) * bsg for di in range(reach) for dj in range(reach) if (di, dj) != (0, 0)]
-    o.rotate(ct0, shifts)   # generates the keys (not timed)
-    t1 = time.time()
-    o.rotate(ct0, shifts)
-    t_rot = time.time() - t1
-    t_net = t_rot * ks_per_step / len(shifts)
-    log(f"oracle: setup+keys {t1 - t0:.1f}s, {len(shifts)} hoisted rotations {t_rot:.1f}s")
-    return {"value": round(imgs / t_net, 6), "unit": "images/s", "cores": 1, "kind": "oracle",
-            "sample": f"hoisted inner rotations of one input ciphertext of conv1 ({len(shifts)} of {ks_per_step} "
-                      f"key switches per step, {t_rot:.1f}s, keys pre-generated), scaled by key-switch count"}
 
 
 if __name__ == "__main__":

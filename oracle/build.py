@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "_build", "liborc.so")
 
 def build(verbose=False):
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
-    cmd = ["g++", "-O2", "-std=gnu++17", "-fPIC", "-shared", "-Wall", "-Wno-sign-compare",
+    cmd = ["g++", "-O2", "-std=gnu++17", "-fPIC", "-shared", "-pthread", "-Wall", "-Wno-sign-compare",
            "-o", OUT] + [os.path.join(HERE, s) for s in SOURCES] + ["-lquadmath"]
     if verbose:
         print(" ".join(cmd))

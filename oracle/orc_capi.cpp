@@ -1,7 +1,10 @@
 // C entry points of the oracle for the Python test harness.  TEST INFRASTRUCTURE.
 // Data crosses this boundary as plain arrays: ciphertext batches are
 // [n_ct][2][level+1][N] uint64 residues in coefficient form.
+#include <chrono>
+#include <cmath>
 #include <cstring>
+#include <thread>
 #include <stdexcept>
 #include <string>
 #include "orc_method.h"
@@ -446,6 +449,49 @@ void* orc_fc(void* c, void* bp, const double* w, int dout, const double* bias, l
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)
+}
+
+// Wall time per operation of the oracle's primitives at `level`, each thread
+// working on its own ciphertext (keys generated before the clock starts):
+// out = [ModUp + one rotation (hoisted form, one shift), each further hoisted
+// rotation, plaintext product, scalar product, rescale, square with
+// relinearisation]; per-op time = wall time / (threads * reps).
+int orc_time_ops(void* c, int level, int threads, int reps, double* out) {
+  GUARD_BEGIN
+  Context& C = *(Context*)c;
+  if (level < 1 || level > C.L || threads < 1 || reps < 1) throw std::runtime_error("orc_time_ops: bad argument");
+  gauss_cdt();
+  C.key(C.galois(1));
+  C.key(C.galois(2));
+  C.key(0);
+  const double scale = std::ldexp(1.0, (int)C.prm.log2scale);
+  std::vector<Ct> cts;
+  std::vector<double> z(C.ns);
+  for (int t = 0; t < threads; t++) {
+    for (int i = 0; i < C.ns; i++) z[i] = std::sin(0.1 * (i + t));
+    cts.push_back(encrypt(C, encode(C, z, {}, scale, q_basis(level)), level, scale, 77, t));
+  }
+  const RPoly pt = encode(C, z, {}, scale, q_basis(level));
+  auto wall = [&](auto op) {
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<std::thread> th;
+    for (int t = 0; t < threads; t++)
+      th.emplace_back([&, t] {
+        for (int r = 0; r < reps; r++) op(cts[t]);
+      });
+    for (auto& x : th) x.join();
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / ((double)threads * reps);
+  };
+  const double r1 = wall([&](const Ct& x) { rotate_hoisted(C, x, {1}); });
+  const double r2 = wall([&](const Ct& x) { rotate_hoisted(C, x, {1, 2}); });
+  out[0] = r1;
+  out[1] = r2 - r1;
+  out[2] = wall([&](const Ct& x) { mul_plain(C, x, pt, scale); });
+  out[3] = wall([&](const Ct& x) { mul_scalar(C, x, 12345, 1.0); });
+  out[4] = wall([&](const Ct& x) { rescale(C, x); });
+  out[5] = wall([&](const Ct& x) { square_relin(C, x, 1); });
+  return 0;
+  GUARD_END(-1)
 }
 
 int64_t orc_weight_code(double w, double scale) { return weight_code(w, scale); }

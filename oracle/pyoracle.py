@@ -93,6 +93,7 @@ def _declare(L):
         "orc_compress": (vp, [vp, vp, C.POINTER(OrcLayout), i, C.POINTER(C.c_long)]),
         "orc_fc": (vp, [vp, vp, f64p, i, vp, C.POINTER(C.c_long)]),
         "orc_weight_code": (C.c_int64, [d, d]),
+        "orc_time_ops": (i, [vp, i, i, i, f64p]),
         "orc_split_scale": (None, [d, C.POINTER(d), C.POINTER(d)]),
     }
     for name, (res, args) in sig.items():
@@ -384,6 +385,16 @@ class Oracle:
         w = np.ascontiguousarray(w, np.float64)
         b = None if bias is None else np.ascontiguousarray(bias, np.float64)
         return self._op(lib().orc_fc, batch.h, w, w.shape[0], None if b is None else b.ctypes.data)
+
+
+def time_ops(orc, level, threads=1, reps=1):
+    """Seconds per operation of the oracle's primitives at `level` with
+    `threads` threads (each on its own ciphertext): modup_rot (ModUp and one
+    hoisted rotation), rot (each further hoisted rotation), pmult, smult,
+    rescale, square_relin."""
+    out = np.zeros(6)
+    _check(lib().orc_time_ops(orc.h, level, threads, reps, out))
+    return dict(zip(["modup_rot", "rot", "pmult", "smult", "rescale", "square_relin"], out.tolist()))
 
 
 def rot_total_formula(BS, Nin, Nout, K, S, alpha):

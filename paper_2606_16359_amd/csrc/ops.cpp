@@ -1417,6 +1417,27 @@ int fenc_profile_result(fenc_ctx* ctx, double* total_ms, int64_t* launches, doub
   API_END
 }
 
+int fenc_profile_summary(fenc_ctx* ctx, char* buf, int64_t len) {
+  API_BEGIN
+  if (!ctx || !buf || len < 1) fail(FENC_EINVAL, "null argument");
+  std::map<std::string, std::tuple<double, int64_t, double>> agg;
+  for (auto& r : ctx->prof) {
+    auto& e = agg[r.name];
+    std::get<0>(e) += fb::event_elapsed_ms(r.a, r.b);
+    std::get<1>(e) += 1;
+    std::get<2>(e) += r.bytes;
+  }
+  std::ostringstream o;
+  o.precision(17);
+  for (auto& kv : agg)
+    o << kv.first << ' ' << std::get<0>(kv.second) << ' ' << std::get<1>(kv.second) << ' ' << std::get<2>(kv.second)
+      << '\n';
+  const std::string t = o.str();
+  if ((int64_t)t.size() + 1 > len) fail(FENC_EINVAL, "summary buffer too small");
+  std::memcpy(buf, t.c_str(), t.size() + 1);
+  API_END
+}
+
 int fenc_stats(const fenc_ctx* ctx, fenc_counters* out) {
   API_BEGIN
   if (!ctx || !out) fail(FENC_EINVAL, "null argument");

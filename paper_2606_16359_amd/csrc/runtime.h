@@ -197,6 +197,7 @@ struct fenc_ctx {
   struct ProfRec {
     void *a, *b;
     double bytes;
+    const char* name;   // kernel name (a string literal)
   };
   std::vector<ProfRec> prof;
   ~fenc_ctx();
@@ -275,9 +276,10 @@ inline long long ct_elems(const Ctx& C, int level) { return 2LL * (level + 1) * 
 
 // Times the launch(es) issued by `launch` when `name` is the profiled kernel;
 // `bytes` is the algorithmic HBM traffic of those launches.
+// With the profiled name "*" every kernel's launches are timed.
 template <class F>
 void timed(Ctx& C, const char* name, double bytes, fb::Stream s, F launch) {
-  if (C.prof_kernel.empty() || C.prof_kernel != name || fb::capturing(s)) {
+  if (C.prof_kernel.empty() || (C.prof_kernel != "*" && C.prof_kernel != name) || fb::capturing(s)) {
     launch();
     return;
   }
@@ -286,7 +288,7 @@ void timed(Ctx& C, const char* name, double bytes, fb::Stream s, F launch) {
   fb::event_record(a, s);
   launch();
   fb::event_record(b, s);
-  C.prof.push_back({a, b, bytes});
+  C.prof.push_back({a, b, bytes, name});
 }
 
 }  // namespace fr

@@ -89,6 +89,7 @@ def load(path=None):
         "fenc_stats": (C.c_int, [vp, C.POINTER(Counters)]),
         "fenc_profile_kernel": (C.c_int, [vp, C.c_char_p]),
         "fenc_profile_result": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+        "fenc_profile_summary": (C.c_int, [vp, C.c_char_p, C.c_int64]),
         "fenc_stats_reset": (None, [vp]),
         "fenc_device_bytes": (C.c_int64, [vp]),
         "fenc_keygen": (C.c_int, [vp, vp, u32, C.c_int, C.c_int]),
@@ -233,6 +234,16 @@ class Fenc:
     def profile_kernel(self, name):
         self._check(self.lib.fenc_profile_kernel(self.h, name.encode() if name else None))
 
+    def profile_summary(self):
+        """Per-kernel {name: (total_ms, launches, bytes)} after profile_kernel("*")."""
+        buf = C.create_string_buffer(1 << 16)
+        self._check(self.lib.fenc_profile_summary(self.h, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, ms, n, b = line.split()
+            out[name] = (float(ms), int(n), float(b))
+        return out
+
     def profile_result(self):
         ms, n, b = C.c_double(), C.c_int64(), C.c_double()
         self._check(self.lib.fenc_profile_result(self.h, C.byref(ms), C.byref(n), C.byref(b)))
@@ -332,6 +343,8 @@ class Fenc:
         rc = fn(*args, C.byref(ob), self._stream())
         if rc == FENC_ENOMEM and not self.emulated:
             import torch
+            if torch.cuda.is_current_stream_capturing():
+                self._check(rc)
             torch.cuda.synchronize()
             torch.cuda.empty_cache()
             rc = fn(*args, C.byref(ob), self._stream())

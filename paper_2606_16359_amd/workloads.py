@@ -86,6 +86,28 @@ def mobilenet_weights(seed=SEED_WEIGHTS):
     return [weights([layer["w"] for layer in blk], seed=seed + i) for i, blk in enumerate(MOBILENET_BLOCKS)]
 
 
+def mobilenet_encrypt(fenc, batch, seed_enc=SEED_ENC):
+    """The three blocks' fresh encryptions of batch images each (the block
+    inputs at 224x224x3, 112x112x32 and 112x112x64, uniform [0,1))."""
+    cts = []
+    for b, (blk, ((c, h, w), S)) in enumerate(zip(MOBILENET_BLOCKS, MOBILENET_INPUTS)):
+        lay = fenc.plan_layout(batch, c, h, w, blk[0]["w"][2], blk[0]["w"][0], S)
+        cts.append(fenc.encrypt(fenc.encode_fragment(images((batch, c, h, w), seed=1 + b), lay), lay, seed_enc + b))
+    return cts
+
+
+def mobilenet_forward(fenc, cts, ws, coeffs=QUADRATIC):
+    return [mobilenet_block(fenc, ct, blk, wb, coeffs) for ct, blk, wb in zip(cts, MOBILENET_BLOCKS, ws)]
+
+
+# the single-layer configuration: one 28x28 image, conv 1->6 5x5 (valid)
+CONV1_SHAPE = (6, 1, 5, 5)
+
+
+def conv1_inputs(seed=SEED_INPUT):
+    return images((1, 1, 28, 28), seed), weights([CONV1_SHAPE])[0]
+
+
 def mobilenet_block(fenc, ct, blk, w, coeffs=QUADRATIC):
     """One block on an encrypted batch: each conv followed by the quadratic."""
     y = ct
