@@ -39,7 +39,7 @@ DTYPE = "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic"
 # HBM bytes per launch from FETCH_SIZE + WRITE_SIZE counters (scaled by a copy
 # of known size), per (workload, kernel); an entry is kept only while its
 # kernel is unchanged since the counters were taken
-TRAFFIC = {}
+TRAFFIC = {("mobilenet", "gmac_pt_fast"): 11579000000}
 
 
 def log(*a):
@@ -263,8 +263,9 @@ def counters_run(args):
 
         def step():
             return W.lenet_forward(fe, ct, w)
-    step()
+    out = step()
     torch.cuda.synchronize()
+    out = None
     src = torch.empty(COPY_BYTES // 8, dtype=torch.int64, device="cuda").fill_(1)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -288,6 +289,9 @@ def main():
                     help="workload of the --counters run")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes (one warm-up step, a 256 MiB copy, one step)")
+    ap.add_argument("--trace", action="store_true",
+                    help="run for a kernel trace: one warm-up step, then --steps batched eager steps of the "
+                         "headline workload and nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: this build runs every configuration on a single MI355X; the "
@@ -297,6 +301,16 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_run(args)
+        return
+    if args.trace:
+        from paper_2606_16359_amd import workloads as W
+        fe, cts, ws = mobilenet_context(args.batch)
+        out = None
+        for i in range(1 + args.steps):
+            out = None
+            out = W.mobilenet_forward(fe, cts, ws)
+            torch.cuda.synchronize()
+        print(json.dumps({"trace_run": True, "batched_steps": args.steps, "warmup_steps": 1}), flush=True)
         return
 
     extras = {}

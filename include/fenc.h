@@ -251,6 +251,9 @@ int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void
  *                c1 x + c0 added, one rescale (one level);
  *   degree 3:    x^2 as above and rescaled, times u = c3 x + c2, relinearised,
  *                c1 x + c0 added, rescaled (two levels).
+ * out->data may equal in->data: the output then overwrites the input (every
+ * batch group's input is read before its output is written, and outputs are
+ * no larger than inputs), which saves one activation-sized buffer.
  * Errors: EUNSUPPORTED for degree > 3, ELEVEL without the levels, EINVAL for
  * non-finite coefficients, ESCALE when a code exceeds 2^120. */
 int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, uint32_t degree,

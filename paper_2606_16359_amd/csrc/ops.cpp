@@ -958,6 +958,8 @@ static void relin(Ctx& C, int lvl, int n, const KsStage& ks, u64* t, const u64* 
   C.cnt.keyswitch += n;
 }
 
+// The output may overwrite the input: every path reads `in` only before the
+// final rescale, which reads the arena and writes `out`.
 static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Stream s) {
   const int l = P.level, n = P.n;
   const long long ce = ct_elems(C, l);

@@ -365,10 +365,22 @@ class Fenc:
         b = ct.struct()
         return self._op(self.lib.fenc_avgpool2, self.h, C.byref(b))
 
-    def poly_act(self, ct, coeffs=(0.0, 0.0, 1.0)):
+    def poly_act(self, ct, coeffs=(0.0, 0.0, 1.0), inplace=False):
+        """inplace: the output overwrites the input's buffer (the input batch
+        must not be used afterwards)."""
         c = np.ascontiguousarray(coeffs, np.float64)
         b = ct.struct()
-        return self._op(self.lib.fenc_poly_act, self.h, C.byref(b), c.ctypes.data, len(c) - 1)
+        if not inplace:
+            return self._op(self.lib.fenc_poly_act, self.h, C.byref(b), c.ctypes.data, len(c) - 1)
+        out = CtBatch()
+        out.data = None
+        self._check(self.lib.fenc_poly_act(self.h, C.byref(b), c.ctypes.data, len(c) - 1, C.byref(out),
+                                           self._stream()))
+        res = Ciphertexts(self, out.lay.copy(), ct.buf)
+        ob = res.struct()
+        self._check(self.lib.fenc_poly_act(self.h, C.byref(b), c.ctypes.data, len(c) - 1, C.byref(ob),
+                                           self._stream()))
+        return res
 
     def compress(self, ct, target=None):
         """target: a Layout of the same tensor (None: the library's vector)."""

@@ -65,7 +65,7 @@ def cifar_inputs(batch=256, channels=16, side=32, shapes=None):
 def cifar_forward(fenc, ct, w, strides=None, coeffs=CUBIC):
     y = ct
     for wi, s in zip(w, strides or CIFAR_STRIDES):
-        y = fenc.poly_act(fenc.conv2d(y, wi, stride=s, pad=wi.shape[2] // 2), coeffs)
+        y = fenc.poly_act(fenc.conv2d(y, wi, stride=s, pad=wi.shape[2] // 2), coeffs, inplace=True)
     return y
 
 
@@ -112,6 +112,7 @@ def mobilenet_block(fenc, ct, blk, w, coeffs=QUADRATIC):
     """One block on an encrypted batch: each conv followed by the quadratic."""
     y = ct
     for layer, wi in zip(blk, w):
+        # the activation overwrites the convolution's output buffer
         y = fenc.poly_act(fenc.conv2d(y, wi, stride=layer["stride"], pad=layer["pad"], groups=layer["groups"]),
-                          coeffs)
+                          coeffs, inplace=True)
     return y

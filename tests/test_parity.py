@@ -150,7 +150,16 @@ def test_batch_group_tiles_give_identical_residues(backend, orc):
     ref = f.export(net())
     f.set_workspace_limit(1)
     assert np.array_equal(f.export(net()), ref)
+
+    def net_inplace():    # the activation overwrites the convolution's output
+        y = f.conv2d(ct, w, pad=1)
+        return f.avgpool2(f.poly_act(y, (0.1, 0.5, 0.25), inplace=True))
+    assert np.array_equal(f.export(net_inplace()), ref)
     f.set_workspace_limit(0)
+    assert np.array_equal(f.export(net_inplace()), ref)
+    cub = f.poly_act(f.conv2d(ct, w, pad=1), (0.1, 0.5, 0.25, -0.02))
+    assert np.array_equal(f.export(f.poly_act(f.conv2d(ct, w, pad=1), (0.1, 0.5, 0.25, -0.02), inplace=True)),
+                          f.export(cub))
     Lo = o.fragment_layout(16, 2, 8, 8, 1)
     ob = o.encrypt_tensor(Lo, x, 5)
     yo, _ = o.conv2d(ob, w, pad=1, hoist=f.hoist)
