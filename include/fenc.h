@@ -292,6 +292,21 @@ int fenc_rotate(fenc_ctx* ctx, const fenc_ctbatch* in, const int32_t* shifts, ui
 int fenc_rotate_sum(fenc_ctx* ctx, const fenc_ctbatch* z0, const fenc_ctbatch* zs,
                     const int32_t* shifts, uint32_t n, fenc_ctbatch* out, void* stream);
 int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream);
+/* Rescale that allocates nothing, for callers that cannot allocate device
+ * memory (code under hipGraph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same operation and residues as fenc_rescale; its workspace
+ * ([n_ct][2][N] words for the last limb and [n_ct][2][level][N] for its lift
+ * to the other limbs, every word written before it is read, nothing needs
+ * clearing) lives in the library's static device array of 64 MiB instead of
+ * the context's arena: at most 64 MiB / ((1 + level) * 16 * N) ciphertexts
+ * per call (6 at N = 2^15 and level 19, 2 at N = 2^16 and level 23).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams, other threads, other contexts) race and must be
+ * serialised by the caller.  The output is the caller's.  Errors: EINVAL
+ * when the batch needs more scratch than the array holds, when the context
+ * has no device tables on the current device yet or none for this level (any
+ * earlier fenc_rescale at this level builds them), ELEVEL at level 0. */
+int fenc_rescale_noalloc(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream);
 /* Forward (inverse != 0: inverse) NTT of rows[n][N] (host) modulo prime index
  * prime[i] of row i, through the device kernels. */
 int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t n, int inverse);

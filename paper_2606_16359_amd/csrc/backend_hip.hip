@@ -1,5 +1,6 @@
 // HIP backend: kernels for gfx950 and their launchers.
 #include <hip/hip_runtime.h>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 
@@ -168,3 +169,28 @@ int device_id() {
 }
 
 }  // namespace fb
+
+// Static device scratch of the no-allocation entry point: every GPU the
+// library runs on holds one copy until the process ends.  Host code never
+// uses the array's name as an address (on the host it is a stand-in): the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[fb::kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void* fb::scratch_base() {
+  const int d = device_id();
+  if (d < 0 || d >= kMaxDevices) throw std::runtime_error("scratch: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[d]) {
+    void* ptr = nullptr;
+    check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[d] = ptr;
+  }
+  return g_scratch_ptr[d];
+}

@@ -14,6 +14,11 @@ struct Grid {
 };
 
 void* dev_alloc(size_t bytes);                       // throws std::runtime_error
+// Device address of the library's static scratch array on the current device
+// (kScratchBytes, 256-byte aligned, shared by every call on that device); the
+// first call on a device looks the address up, later calls return it.
+constexpr size_t kScratchBytes = 64ull << 20;
+void* scratch_base();
 void dev_free(void* p);
 void device_sync();                                  // waits for all work on the device
 void h2d(void* dst, const void* src, size_t bytes);  // synchronous

@@ -2017,6 +2017,33 @@ int fenc_rescale(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void*
   API_END
 }
 
+int fenc_rescale_noalloc(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void* stream) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  check_batch(*ctx, in, false);
+  fenc_ctx& C = *ctx;
+  Layout L = from_pub(C, &in->lay);
+  if (L.level < 1) fail(FENC_ELEVEL, "no level left to rescale");
+  Layout Lo = L;
+  Lo.level = L.level - 1;
+  Lo.scale = L.scale / (double)C.primes[L.level];
+  out->lay = to_pub(C, Lo);
+  if (!out->data) return FENC_OK;
+  check_batch(C, in, true);
+  if (!C.dev) fail(FENC_EINVAL, "no device tables yet: run an operation of this context on this device first");
+  if (fb::device_id() != C.device) fail(FENC_EINVAL, "the context's tables live on another device");
+  if (!C.lvl.count(L.level)) fail(FENC_EINVAL, "no tables for this level yet: run fenc_rescale at this level once");
+  const int n = L.n_ct();
+  const size_t need = rescale_ws_bytes(C, L.level, n);
+  if (need > fb::kScratchBytes)
+    fail(FENC_EINVAL, "rescale workspace of " + std::to_string(need) + " bytes exceeds the static scratch of " +
+                          std::to_string(fb::kScratchBytes) + " bytes: split the batch");
+  u64* last = (u64*)fb::scratch_base();
+  u64* lift = last + (size_t)n * 2 * C.N;
+  rescale_ws(C, L.level, in->data, n, out->data, (fb::Stream)stream, last, lift);
+  API_END
+}
+
 int fenc_set_hoisting(fenc_ctx* ctx, int mode) {
   API_BEGIN
   if (!ctx || (mode != 0 && mode != 1)) fail(FENC_EINVAL, "hoisting mode must be 0 or 1");

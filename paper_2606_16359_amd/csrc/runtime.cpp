@@ -611,11 +611,17 @@ KsStage make_md(Ctx& C, int n, std::vector<void*>& owner) {
 void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s) {
   if (B <= 0) return;
   if (level < 1) fail(FENC_ELEVEL, "no level left to rescale");
+  Scope sc(C.arena);
+  u64* last = (u64*)C.arena.get((size_t)B * 2 * C.N * 8, s);
+  u64* lift = (u64*)C.arena.get((size_t)B * 2 * level * C.N * 8, s);
+  rescale_ws(C, level, in, B, out, s, last, lift);
+}
+
+size_t rescale_ws_bytes(const Ctx& C, int level, int B) { return (size_t)B * 2 * (1 + level) * C.N * 8; }
+
+void rescale_ws(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s, u64* last, u64* lift) {
   const LevelTabs& T = level_tabs(C, level);
   const int nl = level, N = C.N;   // output limbs
-  Scope sc(C.arena);
-  u64* last = (u64*)C.arena.get((size_t)B * 2 * N * 8, s);
-  u64* lift = (u64*)C.arena.get((size_t)B * 2 * nl * N * 8, s);
   fk::PrimeMap pl;
   pl.n = 1;
   pl.p[0] = (unsigned char)level;

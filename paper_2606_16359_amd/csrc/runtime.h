@@ -239,6 +239,10 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
 void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
                  const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s);
 void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s);
+// the rescale with caller-given workspace: last [B][2][N], lift [B][2][level][N]
+// (every word is written before it is read)
+void rescale_ws(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s, u64* last, u64* lift);
+size_t rescale_ws_bytes(const Ctx& C, int level, int B);
 void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_cs, long long a_ps, int na,
               const u64* in_b, long long b_cs, long long b_ps, u64* out, long long out_cs, long long out_ps,
               fb::Stream s);

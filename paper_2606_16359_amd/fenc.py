@@ -114,6 +114,7 @@ def load(path=None):
         "fenc_rotate": (C.c_int, [vp, B, vp, u32, B, vp]),
         "fenc_rotate_sum": (C.c_int, [vp, B, B, vp, u32, B, vp]),
         "fenc_rescale": (C.c_int, [vp, B, B, vp]),
+        "fenc_rescale_noalloc": (C.c_int, [vp, B, B, vp]),
         "fenc_ntt_rows": (C.c_int, [vp, vp, vp, u32, C.c_int]),
         "fenc_ntt_config": (C.c_int, [vp, vp]),
         "fenc_set_hoisting": (C.c_int, [vp, C.c_int]),
@@ -398,6 +399,19 @@ class Fenc:
     def rescale(self, ct):
         b = ct.struct()
         return self._op(self.lib.fenc_rescale, self.h, C.byref(b))
+
+    def rescale_noalloc(self, ct, out=None):
+        """The rescale through the library's static scratch (no device
+        allocation by the library); out: a preallocated output batch."""
+        b = ct.struct()
+        if out is None:
+            o = CtBatch()
+            o.data = None
+            self._check(self.lib.fenc_rescale_noalloc(self.h, C.byref(b), C.byref(o), self._stream()))
+            out = self.alloc_cts(o.lay.copy())
+        ob = out.struct()
+        self._check(self.lib.fenc_rescale_noalloc(self.h, C.byref(b), C.byref(ob), self._stream()))
+        return out
 
     def rotate(self, ct, shifts):
         sh = np.array(shifts, np.int32)

@@ -114,4 +114,12 @@ void event_record(void*, Stream) {}
 float event_elapsed_ms(void*, void*) { return 0.f; }
 void event_destroy(void*) {}
 int device_id() { return 0; }
+void* scratch_base() {
+  static unsigned char* buf = [] {
+    unsigned char* b = (unsigned char*)std::aligned_alloc(256, kScratchBytes);
+    std::memset(b, 0xA5, kScratchBytes);
+    return b;
+  }();
+  return buf;
+}
 }  // namespace fb
