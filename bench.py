@@ -39,7 +39,7 @@ DTYPE = "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic"
 # HBM bytes per launch from FETCH_SIZE + WRITE_SIZE counters (scaled by a copy
 # of known size), per (workload, kernel); an entry is kept only while its
 # kernel is unchanged since the counters were taken
-TRAFFIC = {("mobilenet", "gmac_pt_fast"): 11579000000}
+TRAFFIC = {}
 
 
 def log(*a):

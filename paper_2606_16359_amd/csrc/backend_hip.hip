@@ -103,6 +103,7 @@ FENC_KERNEL_XCD(gmac_pt_fast, GmacArgs)
 FENC_KERNEL_XCD(gmac_ptv, GmacArgs)
 FENC_KERNEL_XCD(gmac_ptv_fast, GmacArgs)
 FENC_KERNEL_XCD(gmac_diag, GmacArgs)
+FENC_KERNEL_XCD(gmac_one, GmacArgs)
 FENC_KERNEL(tensor_square, SquareArgs)
 FENC_KERNEL(lift_pq, LiftPqArgs)
 FENC_KERNEL(lin_comb, LinArgs)

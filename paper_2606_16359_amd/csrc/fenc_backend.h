@@ -60,6 +60,7 @@ void gmac_pt_fast(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_ptv(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_ptv_fast(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_diag(Grid g, int threads, Stream s, const fk::GmacArgs& a);
+void gmac_one(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void tensor_square(Grid g, int threads, Stream s, const fk::SquareArgs& a);
 void lift_pq(Grid g, int threads, Stream s, const fk::LiftPqArgs& a);
 void lin_comb(Grid g, int threads, Stream s, const fk::LinArgs& a);

@@ -1184,6 +1184,73 @@ FENC_HD FENC_AI void gmac_diag_body(X& x, const GmacArgs& a) {
   });
 }
 
+// Single-term form: every group is one weighted term with the class's shared
+// plaintext (or none), as in depthwise convolutions where each position mask
+// multiplies one rotated copy:
+//   out_o = sum_g pt_g (.) (w_{g,o} * in_g)
+// Each term is two modular products (weight, then plaintext word) instead of
+// the split-and-accumulate of the general form, whose exact sums pay off only
+// when a group holds many terms.  Groups alternate between two buffers (the
+// next group's words are requested first); sums are reduced every 4 groups.
+struct OneBuf {
+  u64 v[1];
+  u64 m[1];
+};
+
+FENC_HD FENC_AI void one_fetch(const GmacArgs& a, const MacThread& T, const u64* const* mk, int W, int g,
+                               OneBuf& b) {
+  mac_fetch(a, a.toff[g], 1, T.ts, T.off_a, T.off_b, b.v);
+  const u64* p = mk[(long long)(g - T.K.g0) * W];
+  b.m[0] = ldg(p ? p + T.off_pt : T.safe);
+}
+
+template <int W>
+FENC_HD FENC_AI bool one_step(const GmacArgs& a, const MacThread& T, const d2* ew, const u64* const* mk, int& g,
+                              int& n, const OneBuf& cur, OneBuf& nxt, double (&r)[W]) {
+  const bool more = g + 1 < T.gend;
+  one_fetch(a, T, mk, W, more ? g + 1 : T.K.g0, nxt);
+  const double vv = u2d(cur.v[0]), ms = u2d(cur.m[0]);
+  const bool has_pt = mk[(long long)(g - T.K.g0) * W] != nullptr;
+  const d2* w = ew + (long long)(g - T.K.g0) * W;   // one term per group: term rank = group rank
+#pragma unroll
+  for (int o = 0; o < W; o++) {
+    double t = mulmod_c(vv, w[o].x, w[o].y, T.q);    // vv in [0, q): |t| <= 0.75q
+    if (has_pt) t = mulmod(t, ms, T.q, T.qi);        // |t * ms / q| < q
+    r[o] += t;
+  }
+  if (++n == 4) {
+#pragma unroll
+    for (int o = 0; o < W; o++) r[o] = red(r[o], T.q, T.qi);
+    n = 0;
+  }
+  g++;
+  return more;
+}
+
+template <int W, class X>
+FENC_HD FENC_AI void gmac_one_body(X& x, const GmacArgs& a) {
+  x.phase([&](int t) __attribute__((always_inline)) {
+    const MacThread T = mac_thread(x, t, a);
+    const u64* const* mk = a.mask + T.K.m0;
+    const d2* ew = a.ew + (long long)T.i * a.ews + T.K.w0;
+    double r[W];
+#pragma unroll
+    for (int o = 0; o < W; o++) r[o] = 0;
+    if (T.nterm > 0) {
+      OneBuf A, B;
+      int g = T.K.g0, n = 0;
+      one_fetch(a, T, mk, W, g, A);
+      for (;;) {
+        if (!one_step<W>(a, T, ew, mk, g, n, A, B, r)) break;
+        if (!one_step<W>(a, T, ew, mk, g, n, B, A, r)) break;
+      }
+#pragma unroll
+      for (int o = 0; o < W; o++) r[o] = red(r[o], T.q, T.qi);
+    }
+    mac_store<W, X>(a, T, r);
+  });
+}
+
 // Classes with one plaintext per (group, output) hold at most kMacOutEach
 // outputs (their plaintext words take registers per output).
 constexpr int kMacOutEach = 4;
@@ -1219,6 +1286,16 @@ template <class X>
 FENC_HD void gmac_pt_fast(X& x, const GmacArgs& a) { gmac_any<kPtShared, true>(x, a); }
 template <class X>
 FENC_HD void gmac_ptv_fast(X& x, const GmacArgs& a) { gmac_any<kPtEach, true>(x, a); }
+// single-term classes
+template <class X>
+FENC_HD void gmac_one(X& x, const GmacArgs& a) {
+  switch (a.width) {
+    case 1: gmac_one_body<1>(x, a); break;
+    case 2: gmac_one_body<2>(x, a); break;
+    case 4: gmac_one_body<4>(x, a); break;
+    default: gmac_one_body<kMacOut>(x, a); break;   // width 8 (kMacOut)
+  }
+}
 // diagonal classes
 template <class X>
 FENC_HD void gmac_diag(X& x, const GmacArgs& a) {

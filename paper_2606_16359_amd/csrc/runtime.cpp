@@ -691,8 +691,8 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
       typedef void (*Launch)(fb::Grid, int, fb::Stream, const fk::GmacArgs&);
       static const Launch launch[2][3] = {{fb::gmac, fb::gmac_pt, fb::gmac_ptv},
                                           {fb::gmac_fast, fb::gmac_pt_fast, fb::gmac_ptv_fast}};
-      const char* name = sg.diag ? "gmac_diag" : names[sg.fast][sg.ptm];
-      const Launch fn = sg.diag ? fb::gmac_diag : launch[sg.fast][sg.ptm];
+      const char* name = sg.diag ? "gmac_diag" : sg.one ? "gmac_one" : names[sg.fast][sg.ptm];
+      const Launch fn = sg.diag ? fb::gmac_diag : sg.one ? fb::gmac_one : launch[sg.fast][sg.ptm];
       timed(C, name, gb, s, [&] { fn(grid, block_threads(C), s, a); });
       C.cnt.launches += 1;
     }
@@ -829,10 +829,20 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
     const int nt = b.toff[b.goff[m[0] + 1]] - b.toff[b.goff[m[0]]];
     return nt >= 6 * ng ? fk::kMacChunk : 4;
   };
+  // single-term class: every group one term, one plaintext per group shared
+  // by the class (or none) -- two modular products per term beat the exact
+  // split-and-accumulate of the general form
+  auto is_one = [&](const std::vector<int>& mem) {
+    if (is_diag(mem) || ptm_of(mem) != fk::kPtShared) return false;
+    for (int o : mem)
+      for (int g = b.goff[o]; g < b.goff[o + 1]; g++)
+        if (b.toff[g + 1] - b.toff[g] != 1) return false;
+    return true;
+  };
   auto seg_key = [&](const std::vector<int>& m) {
-    const bool dg = is_diag(m);
-    return std::make_tuple(width_of((int)m.size()), dg ? (int)fk::kPtEach : ptm_of(m), (int)dg,
-                           (int)(!dg && is_fast(m)), chunk_of(m));
+    const bool dg = is_diag(m), one = is_one(m);
+    return std::make_tuple(width_of((int)m.size()), dg ? (int)fk::kPtEach : ptm_of(m), (int)dg, (int)one,
+                           (int)(!dg && !one && is_fast(m)), chunk_of(m));
   };
   {   // classes with a plaintext per (group, output) hold at most kMacOutEach outputs
     std::vector<std::vector<int>> split;
@@ -859,11 +869,11 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
   int ngroups = 0;
   for (auto& mem : members) {
     const int rep = mem[0], no = (int)mem.size(), W = width_of(no);
-    const bool diag = is_diag(mem), fast = !diag && is_fast(mem);
+    const bool diag = is_diag(mem), one = is_one(mem), fast = !diag && !one && is_fast(mem);
     const int ptm = diag ? (int)fk::kPtEach : ptm_of(mem), chunk = chunk_of(mem);
     if (T.seg.empty() || T.seg.back().width != W || T.seg.back().ptm != ptm || T.seg.back().diag != diag ||
-        T.seg.back().fast != fast || T.seg.back().chunk != chunk)
-      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, ptm, diag, fast, chunk, 0.0});
+        T.seg.back().one != one || T.seg.back().fast != fast || T.seg.back().chunk != chunk)
+      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, ptm, diag, one, fast, chunk, 0.0});
     for (int r = 0; r < b.toff[b.goff[rep + 1]] - b.toff[b.goff[rep]]; r++)
       for (int o = 0; o < W; o++) wfast.push_back(fast);
     MacSeg& sg = T.seg.back();

@@ -110,6 +110,7 @@ struct MacSeg {
   int c0, n, width;
   int ptm;                         // plaintext products: none, one per group, one per (group, output)
   bool diag;                       // every group one term of weight 1 with its own plaintexts
+  bool one;                        // every group one weighted term and the class's shared plaintext
   bool fast;                       // every weight code below 2^23 in magnitude
   int chunk;                       // terms per chunk: 8, or 4 for groups of under 6 terms on average
   double words;                    // words per (coefficient, limb) moved by the segment's classes

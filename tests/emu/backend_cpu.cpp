@@ -85,6 +85,7 @@ EMU_XCD(gmac_pt_fast, GmacArgs)
 EMU_XCD(gmac_ptv, GmacArgs)
 EMU_XCD(gmac_ptv_fast, GmacArgs)
 EMU_XCD(gmac_diag, GmacArgs)
+EMU_XCD(gmac_one, GmacArgs)
 EMU(tensor_square, SquareArgs)
 EMU(lift_pq, LiftPqArgs)
 EMU(lin_comb, LinArgs)
