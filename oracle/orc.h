@@ -17,6 +17,13 @@
 #include <string>
 #include <vector>
 #include <map>
+#include <memory>
+#include <mutex>
+#include <algorithm>
+#include <thread>
+#include <exception>
+#include <cstdlib>
+#include <atomic>
 
 namespace orc {
 
@@ -94,7 +101,12 @@ struct Context {
   std::vector<Ring> ring;
   std::vector<i64> s;                           // ternary secret coefficients
   // key cache: keyid -> [digit][2][prime][N] in NTT (evaluation) form
-  std::map<u64, std::vector<std::vector<std::vector<Vec>>>> keys;
+  struct KeySlot {
+    std::once_flag once;
+    std::vector<std::vector<std::vector<Vec>>> key;
+  };
+  std::map<u64, std::shared_ptr<KeySlot>> keys;
+  std::shared_ptr<std::mutex> key_mu = std::make_shared<std::mutex>();   // guards the map `keys`
   explicit Context(const Params& p);
   int np_total() const { return L + 1 + K; }
   const std::vector<std::vector<std::vector<Vec>>>& key(u64 keyid);
@@ -105,6 +117,44 @@ struct Context {
 // skipping those already in `taken`
 Vec find_primes(int bits, int logN, int count, const Vec& taken);
 u64 find_psi(u64 q, int N);
+
+// Threads for work over independent ciphertexts (ORC_THREADS, else the
+// hardware's count, at most 16); the arithmetic of each item is unchanged.
+inline int orc_threads() {
+  const char* e = std::getenv("ORC_THREADS");
+  int t = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
+  return std::max(1, std::min(16, t));
+}
+
+// fn(i) for every i in [0, n), items spread over the threads
+template <class F>
+void par_for(int n, F fn) {
+  const int T = std::min(n, orc_threads());
+  if (T <= 1) {
+    for (int i = 0; i < n; i++) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex em;
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; t++)
+    th.emplace_back([&] {
+      for (;;) {
+        const int i = next++;
+        if (i >= n) break;
+        try {
+          fn(i);
+        } catch (...) {
+          std::lock_guard<std::mutex> lock(em);
+          if (!err) err = std::current_exception();
+        }
+      }
+    });
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
+
 
 // ---------------------------------------------------------------- polys
 // A polynomial in RNS form: limb l holds residues modulo primes[pidx[l]],

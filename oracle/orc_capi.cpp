@@ -380,16 +380,20 @@ int orc_decrypt_tensor(void* c, void* bp, double* x) {
   GUARD_END(-1)
 }
 
+// outs/n_outs: compute only those output ciphertexts (n_outs = 0: all); the
+// batch then holds them in that order (its layout is the full output's)
 void* orc_conv2d(void* c, void* bp, const double* w, int cout, int k, int stride, int pad, int groups,
-                 long long pt_budget, int hoist, const OrcLayout* target, const double* bias, long* counts) {
+                 long long pt_budget, int hoist, const OrcLayout* target, const double* bias, const int* outs,
+                 int n_outs, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
   Layout T;
   if (target) T = from_c(target);
+  std::vector<int> only(outs, outs + (n_outs > 0 ? n_outs : 0));
   out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt, pt_budget, hoist,
-                    target ? &T : nullptr, bias);
+                    target ? &T : nullptr, bias, n_outs > 0 ? &only : nullptr);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)

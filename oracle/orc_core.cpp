@@ -90,19 +90,21 @@ u64 sample_uniform(u64 seed, u64 tag, u64 i, u64 q) {
 // Cumulative table of the discrete Gaussian folded onto |e| (sigma = 3.2,
 // support |e| <= 19): T[k-1] = floor(2^63 * P(|e| <= k-1)), k = 1..19.
 const std::vector<u64>& gauss_cdt() {
-  static std::vector<u64> T;
-  if (!T.empty()) return T;
-  const __float128 sigma = 3.2Q;
-  __float128 rho[20];
-  for (int k = 0; k < 20; k++) rho[k] = expq(-(__float128)(k * k) / (2 * sigma * sigma));
-  __float128 Z = rho[0];
-  for (int k = 1; k < 20; k++) Z += 2 * rho[k];
-  __float128 cdf = rho[0] / Z;
-  const __float128 two63 = ldexpq(1.0Q, 63);
-  for (int k = 1; k < 20; k++) {
-    T.push_back((u64)floorq(cdf * two63));
-    cdf += 2 * rho[k] / Z;
-  }
+  static const std::vector<u64> T = [] {   // built once (thread-safe static initialisation)
+    std::vector<u64> t;
+    const __float128 sigma = 3.2Q;
+    __float128 rho[20];
+    for (int k = 0; k < 20; k++) rho[k] = expq(-(__float128)(k * k) / (2 * sigma * sigma));
+    __float128 Z = rho[0];
+    for (int k = 1; k < 20; k++) Z += 2 * rho[k];
+    __float128 cdf = rho[0] / Z;
+    const __float128 two63 = ldexpq(1.0Q, 63);
+    for (int k = 1; k < 20; k++) {
+      t.push_back((u64)floorq(cdf * two63));
+      cdf += 2 * rho[k] / Z;
+    }
+    return t;
+  }();
   return T;
 }
 
@@ -352,23 +354,34 @@ std::vector<std::vector<RPoly>> gen_switch_key(Context& C, u64 keyid) {
 }
 
 const std::vector<std::vector<std::vector<Vec>>>& Context::key(u64 keyid) {
-  auto it = keys.find(keyid);
-  if (it != keys.end()) return it->second;
-  std::vector<std::vector<RPoly>> k = gen_switch_key(*this, keyid);
-  std::vector<std::vector<std::vector<Vec>>> kn(k.size());
-  for (size_t j = 0; j < k.size(); j++) {
-    kn[j].resize(2);
-    for (int t = 0; t < 2; t++) {
-      kn[j][t].resize(primes.size());
-      const RPoly& P = k[j][t];
-      for (size_t l = 0; l < P.pidx.size(); l++) {
-        Vec v = P.c[l];
-        ring[P.pidx[l]].ntt(v);
-        kn[j][t][P.pidx[l]] = v;
+  // The map lock covers only finding or adding the key's slot; each key is
+  // generated once (its own once-flag), distinct keys concurrently.  Slots
+  // are never removed, so the reference stays valid.
+  KeySlot* slot;
+  {
+    std::lock_guard<std::mutex> lock(*key_mu);
+    auto& p = keys[keyid];
+    if (!p) p = std::make_shared<KeySlot>();
+    slot = p.get();
+  }
+  std::call_once(slot->once, [&] {
+    std::vector<std::vector<RPoly>> k = gen_switch_key(*this, keyid);
+    std::vector<std::vector<std::vector<Vec>>> kn(k.size());
+    for (size_t j = 0; j < k.size(); j++) {
+      kn[j].resize(2);
+      for (int t = 0; t < 2; t++) {
+        kn[j][t].resize(primes.size());
+        const RPoly& P = k[j][t];
+        for (size_t l = 0; l < P.pidx.size(); l++) {
+          Vec v = P.c[l];
+          ring[P.pidx[l]].ntt(v);
+          kn[j][t][P.pidx[l]] = v;
+        }
       }
     }
-  }
-  return keys[keyid] = kn;
+    slot->key = std::move(kn);
+  });
+  return slot->key;
 }
 
 // ---------------------------------------------------------------- encryption
@@ -500,9 +513,9 @@ void key_inner_product(Context& C, const std::vector<RPoly>& ext, u64 keyid, int
 
 std::vector<Ct> rotate_hoisted(Context& C, const Ct& x, const std::vector<i64>& shifts) {
   std::vector<RPoly> ext = mod_up(C, x.c1, x.level);
-  std::vector<Ct> out;
-  for (i64 r : shifts) {
-    u64 g = C.galois(r);
+  std::vector<Ct> out(shifts.size());
+  par_for((int)shifts.size(), [&](int k) {   // the shifts share the ModUp and nothing else
+    u64 g = C.galois(shifts[k]);
     if (g == 1) throw std::runtime_error("rotate_hoisted: zero shift");
     std::vector<RPoly> eg;
     for (const RPoly& e : ext) eg.push_back(automorph(C, e, g));
@@ -514,8 +527,8 @@ std::vector<Ct> rotate_hoisted(Context& C, const Ct& x, const std::vector<i64>& 
     y.c1 = mod_down(C, a1, x.level);
     y.level = x.level;
     y.scale = x.scale;
-    out.push_back(y);
-  }
+    out[k] = y;
+  });
   return out;
 }
 
@@ -535,9 +548,9 @@ std::vector<Ct> rotate_hoisted_pq(Context& C, const Ct& x, const std::vector<i64
   std::vector<RPoly> ext = mod_up(C, x.c1, x.level);
   const std::vector<int> qp = qp_basis(C, x.level);
   const std::vector<u64> pm = p_mod(C, qp);
-  std::vector<Ct> out;
-  for (i64 r : shifts) {
-    u64 g = C.galois(r);
+  std::vector<Ct> out(shifts.size());
+  par_for((int)shifts.size(), [&](int k) {   // the shifts share the ModUp and nothing else
+    u64 g = C.galois(shifts[k]);
     if (g == 1) throw std::runtime_error("rotate_hoisted_pq: zero shift");
     std::vector<RPoly> eg;
     for (const RPoly& e : ext) eg.push_back(automorph(C, e, g));
@@ -553,8 +566,8 @@ std::vector<Ct> rotate_hoisted_pq(Context& C, const Ct& x, const std::vector<i64
     y.c1 = a1;
     y.level = x.level;
     y.scale = x.scale;
-    out.push_back(y);
-  }
+    out[k] = y;
+  });
   return out;
 }
 
@@ -594,16 +607,19 @@ Ct rotate_sum_lazy(Context& C, const Ct* z0, const std::vector<const Ct*>& zs,
   Ct y;
   y.c0 = z0 ? z0->c0 : poly_zero(C, qb);
   y.c1 = z0 ? z0->c1 : poly_zero(C, qb);
-  for (size_t r = 0; r < zs.size(); r++) {
+  // every term's ModUp and inner product are independent; the sums follow in term order
+  std::vector<RPoly> k0(zs.size()), k1(zs.size());
+  par_for((int)zs.size(), [&](int r) {
     u64 g = C.galois(shifts[r]);
     if (g == 1) throw std::runtime_error("rotate_sum_lazy: zero shift");
     std::vector<RPoly> up = mod_up(C, zs[r]->c1, level);
     for (RPoly& e : up) e = automorph(C, e, g);
-    RPoly a0, a1;
-    key_inner_product(C, up, g, level, a0, a1);
-    poly_add_inplace(C, acc0, a0);
-    poly_add_inplace(C, acc1, a1);
-    poly_add_inplace(C, y.c0, automorph(C, zs[r]->c0, g));
+    key_inner_product(C, up, g, level, k0[r], k1[r]);
+  });
+  for (size_t r = 0; r < zs.size(); r++) {
+    poly_add_inplace(C, acc0, k0[r]);
+    poly_add_inplace(C, acc1, k1[r]);
+    poly_add_inplace(C, y.c0, automorph(C, zs[r]->c0, C.galois(shifts[r])));
   }
   poly_add_inplace(C, y.c0, mod_down(C, acc0, level));
   poly_add_inplace(C, y.c1, mod_down(C, acc1, level));

@@ -30,6 +30,11 @@
 // S=M pixel-wise, decrypted layers against a float64 numpy CNN).
 #include "orc_method.h"
 #include <algorithm>
+#include <exception>
+#include <mutex>
+#include <thread>
+#include <cstdlib>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <set>
@@ -41,6 +46,12 @@ namespace orc {
 static int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 static int posmod(long a, long b) { long r = a % b; return (int)(r < 0 ? r + b : r); }
 static double delta_of(const Context& C) { return std::ldexp(1.0, (int)C.prm.log2scale); }
+
+static void add_counts(Counts& a, const Counts& b) {
+  a.inner_rot += b.inner_rot; a.outer_rot += b.outer_rot; a.other_rot += b.other_rot; a.ks += b.ks;
+  a.modup += b.modup; a.moddown += b.moddown; a.pmult += b.pmult; a.smult += b.smult;
+  a.rescale += b.rescale; a.relin += b.relin;
+}
 
 double rot_total_formula(double BS, double Nin, double Nout, double K, double S, double alpha) {
   double inner = (K > S) ? (std::pow(std::ceil(K / S), 2) - 1) * Nin : 0.0;
@@ -212,7 +223,10 @@ struct Term { int idx; long shift; int u, v, dbi, dbj, di, dj, gi; };
 
 // bias[o] added to every valid slot of output channel o, encoded at the
 // output scale (exactly Delta) and added to c0 after the rescale
-void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const double* bias) {
+void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const double* bias,
+              const std::vector<int>* idx) {
+  std::map<int, int> where;   // ciphertext index -> position in out
+  for (size_t k = 0; k < out.size(); k++) where[idx ? (*idx)[k] : (int)k] = (int)k;
   std::vector<std::vector<double>> z(out.size(), std::vector<double>(C.ns, 0.0));
   std::vector<std::pair<int, int>> sl;
   for (int b = 0; b < L.bs; b++)
@@ -220,7 +234,11 @@ void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const dou
       for (int hh = 0; hh < L.h; hh++)
         for (int ww = 0; ww < L.w; ww++) {
           element_slots(L, b, ch, hh, ww, sl);
-          for (auto& p : sl) z[p.first][p.second] = bias[L.kind == KIND_VECTOR ? (ch * L.h + hh) * L.w + ww : ch];
+          for (auto& p : sl) {
+            auto it = where.find(p.first);
+            if (it != where.end())
+              z[it->second][p.second] = bias[L.kind == KIND_VECTOR ? (ch * L.h + hh) * L.w + ww : ch];
+          }
         }
   for (size_t t = 0; t < out.size(); t++)
     poly_add_inplace(C, out[t].c0, encode(C, z[t], {}, out[t].scale, q_basis(out[t].level)));
@@ -359,7 +377,8 @@ std::vector<Ct> conv_into_target(Context& C, const Layout& Lin, const Layout& Ln
 
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
-                       long long pt_budget, int hoist, const Layout* target, const double* bias) {
+                       long long pt_budget, int hoist, const Layout* target, const double* bias,
+                       const std::vector<int>* only) {
   if (Lin.kind != KIND_FRAGMENT || Lin.dil != 1) throw std::runtime_error("conv2d: needs a dense fragment layout");
   if (stride < 1 || Lin.S % stride) throw std::runtime_error("conv2d: stride must divide S");
   const int cin = Lin.c;
@@ -404,6 +423,12 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
 
   const int So = Lout.S, ncg_out = Lout.ncg;
   std::vector<std::vector<Term>> terms(Lin.nbg * ncg_out * So * So);
+  // the outputs computed (all, or the listed ones with only their input cone)
+  std::vector<char> sel(terms.size(), only ? 0 : 1);
+  if (only) {
+    if (target) throw std::runtime_error("conv2d: an output subset cannot take a target layout");
+    for (int o : *only) sel.at(o) = 1;
+  }
   std::map<int, std::set<long>> need;
   for (int bg = 0; bg < Lin.nbg; bg++)
     for (int go = 0; go < ncg_out; go++)
@@ -422,7 +447,7 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
                 t.idx = ((bg * Lin.ncg + gi) * S + t.u) * S + t.v;
                 t.shift = posmod(((long)t.dbi * m + t.dbj) * bsg, C.ns);
                 terms[oct].push_back(t);
-                if (t.shift) need[t.idx].insert(t.shift);
+                if (t.shift && sel[oct]) need[t.idx].insert(t.shift);
               }
           }
         }
@@ -435,22 +460,39 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
   hoist = hoist && !need.empty();
   const std::vector<int> basis = hoist ? qp_basis(C, lvl) : q_basis(lvl);
   std::map<std::pair<int, long>, Ct> copies;
-  for (auto& kv : need) {
-    std::vector<i64> sh(kv.second.begin(), kv.second.end());
-    std::vector<Ct> r = hoist ? rotate_hoisted_pq(C, in[kv.first], sh) : rotate_hoisted(C, in[kv.first], sh);
-    for (size_t i = 0; i < sh.size(); i++) copies[{kv.first, sh[i]}] = r[i];
-    cnt.inner_rot += sh.size();
-    cnt.ks += sh.size();
-    cnt.modup += 1;
-    if (!hoist) cnt.moddown += sh.size();
+  {
+    std::vector<std::pair<int, std::vector<i64>>> jobs;
+    for (auto& kv : need) jobs.push_back({kv.first, std::vector<i64>(kv.second.begin(), kv.second.end())});
+    std::vector<std::vector<Ct>> rot(jobs.size());
+    par_for((int)jobs.size(), [&](int j) {
+      rot[j] = hoist ? rotate_hoisted_pq(C, in[jobs[j].first], jobs[j].second)
+                     : rotate_hoisted(C, in[jobs[j].first], jobs[j].second);
+    });
+    for (size_t j = 0; j < jobs.size(); j++) {
+      const std::vector<i64>& sh = jobs[j].second;
+      for (size_t i = 0; i < sh.size(); i++) copies[{jobs[j].first, sh[i]}] = rot[j][i];
+      cnt.inner_rot += sh.size();
+      cnt.ks += sh.size();
+      cnt.modup += 1;
+      if (!hoist) cnt.moddown += sh.size();
+    }
   }
-  std::map<int, Ct> lifted;   // P x of the unrotated inputs (hoist = 1)
+  std::map<int, Ct> lifted;   // P x of the unrotated inputs (hoist = 1), made before the outputs
+  if (hoist) {
+    std::set<int> un;
+    for (size_t oct = 0; oct < terms.size(); oct++)
+      if (sel[oct])
+        for (const Term& t : terms[oct])
+          if (!t.shift) un.insert(t.idx);
+    std::vector<int> ul(un.begin(), un.end());
+    std::vector<Ct> lv(ul.size());
+    par_for((int)ul.size(), [&](int j) { lv[j] = lift_pq(C, in[ul[j]]); });
+    for (size_t j = 0; j < ul.size(); j++) lifted.emplace(ul[j], lv[j]);
+  }
   auto source = [&](int idx, long shift) -> const Ct& {
     if (shift) return copies.at({idx, shift});
     if (!hoist) return in[idx];
-    auto it = lifted.find(idx);
-    if (it == lifted.end()) it = lifted.emplace(idx, lift_pq(C, in[idx])).first;
-    return it->second;
+    return lifted.at(idx);
   };
   // Plaintext form: with masks, either one full-scale plaintext per (output,
   // diagonal, term) holding the weight of every position ("materialised"),
@@ -470,8 +512,10 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
   const bool materialise = need_mask && n_pt * (lvl + 1) * (long long)C.N * 8 <= pt_budget;
   // masks: source pixel inside the logical input, restricted to position q
   std::map<std::vector<int>, RPoly> masks;
+  std::mutex mask_mu;   // the cache is shared by the output threads (map nodes stay put)
   auto mask = [&](const Term& t, int q) -> const RPoly& {
     std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q};
+    std::lock_guard<std::mutex> lock(mask_mu);
     auto it = masks.find(key);
     if (it != masks.end()) return it->second;
     std::vector<double> z(C.ns, 0.0);
@@ -504,12 +548,16 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
     if (bias) add_bias(C, Lout, out, bias);
     return out;
   }
+  if (!materialise && !need_mask) ones_const();   // made once, before the output threads
+  int n_sel = 0;
+  for (char c : sel) n_sel += c;
+  const bool inner = n_sel < orc_threads();   // few outputs: parallel products within each
   std::vector<Ct> out(terms.size());
-  for (int bg = 0; bg < Lin.nbg; bg++)
-    for (int go = 0; go < ncg_out; go++)
-      for (int uo = 0; uo < So; uo++)
-        for (int vo = 0; vo < So; vo++) {
-          const int oct = ((bg * ncg_out + go) * So + uo) * So + vo;
+  std::mutex cnt_mu;
+  par_for((int)terms.size(), [&](int oct) {
+          if (!sel[oct]) return;
+          const int go = (oct / (So * So)) % ncg_out;
+          Counts lc;
           std::vector<Ct> z(nd, zero_ct(C, lvl, Lin.scale * dw * dm));
           if (hoist)
             for (Ct& zr : z) {
@@ -517,9 +565,23 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
               zr.c1 = poly_zero(C, basis);
             }
           std::vector<bool> act(nd, false);
+          // The plaintext products of one output are independent: with fewer
+          // outputs than threads they are made a chunk at a time in parallel
+          // and added in a fixed order (sums mod q are exact either way).
+          auto products = [&](int n, auto make, auto use) {
+            const int chunk = inner ? orc_threads() : 1;
+            std::vector<Ct> buf(chunk);
+            for (int j0 = 0; j0 < n; j0 += chunk) {
+              const int cn = std::min(chunk, n - j0);
+              if (inner) par_for(cn, [&](int j) { buf[j] = make(j0 + j); });
+              else buf[0] = make(j0);
+              for (int j = 0; j < cn; j++) use(j0 + j, buf[j]);
+            }
+          };
           if (materialise) {
-            for (const Term& t : terms[oct]) {
-              const Ct& copy = source(t.idx, t.shift);
+            std::vector<std::pair<const Term*, int>> tr;   // (term, diagonal) pairs with a plaintext
+            std::vector<std::vector<double>> dzs;
+            for (const Term& t : terms[oct])
               for (int r = 0; r < nd; r++) {
                 std::vector<double> dz(C.ns, 0.0);
                 bool any = false;
@@ -537,41 +599,61 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
                     }
                 }
                 if (!any) continue;
-                act[r] = true;
-                add_inplace(C, z[r], mul_plain(C, copy, encode(C, dz, {}, T, basis), T));
-                cnt.pmult++;
+                tr.push_back({&t, r});
+                dzs.push_back(std::move(dz));
               }
-            }
-          }
-          for (const Term& t : materialise ? std::vector<Term>() : terms[oct]) {
-            const Ct& copy = source(t.idx, t.shift);
-            for (int q = 0; q < npos; q++) {
-              const int ch = in_channel(t.gi, q);
-              bool any = false;
-              for (int r = 0; r < nd; r++) any |= pair_ok(ch, go * cpc + posmod(q - r, cpc));
-              if (!any) continue;
-              // the all-ones vector encodes to the constant polynomial round(dm):
-              // multiplying by it is multiplying by that integer
-              Ct mc = need_mask ? mul_plain(C, copy, mask(t, q), dm) : mul_scalar(C, copy, ones_const(), dm);
-              cnt.pmult++;
-              for (int r = 0; r < nd; r++) {
-                const int o = go * cpc + posmod(q - r, cpc);
-                if (!pair_ok(ch, o)) continue;
-                const int grp = o / gout;
-                double wv = w[(((long)o * gin + (ch - grp * gin)) * k + t.di) * k + t.dj];
-                i64 code = weight_code(wv, dw);
-                act[r] = true;
-                if (code == 0) continue;
-                add_inplace(C, z[r], mul_scalar(C, mc, code, dw));
-                cnt.smult++;
+            products(
+                (int)tr.size(),
+                [&](int j) {
+                  const Term& t = *tr[j].first;
+                  return mul_plain(C, source(t.idx, t.shift), encode(C, dzs[j], {}, T, basis), T);
+                },
+                [&](int j, const Ct& p) {
+                  act[tr[j].second] = true;
+                  add_inplace(C, z[tr[j].second], p);
+                  lc.pmult++;
+                });
+          } else {
+            std::vector<std::pair<const Term*, int>> tq;   // (term, position) pairs feeding some diagonal
+            for (const Term& t : terms[oct])
+              for (int q = 0; q < npos; q++) {
+                const int ch = in_channel(t.gi, q);
+                bool any = false;
+                for (int r = 0; r < nd; r++) any |= pair_ok(ch, go * cpc + posmod(q - r, cpc));
+                if (any) tq.push_back({&t, q});
               }
-            }
+            products(
+                (int)tq.size(),
+                [&](int j) {
+                  const Term& t = *tq[j].first;
+                  const Ct& copy = source(t.idx, t.shift);
+                  // the all-ones vector encodes to the constant polynomial round(dm):
+                  // multiplying by it is multiplying by that integer
+                  return need_mask ? mul_plain(C, copy, mask(t, tq[j].second), dm)
+                                   : mul_scalar(C, copy, ones_const(), dm);
+                },
+                [&](int j, const Ct& mc) {
+                  const Term& t = *tq[j].first;
+                  const int q = tq[j].second, ch = in_channel(t.gi, q);
+                  lc.pmult++;
+                  for (int r = 0; r < nd; r++) {
+                    const int o = go * cpc + posmod(q - r, cpc);
+                    if (!pair_ok(ch, o)) continue;
+                    const int grp = o / gout;
+                    double wv = w[(((long)o * gin + (ch - grp * gin)) * k + t.di) * k + t.dj];
+                    i64 code = weight_code(wv, dw);
+                    act[r] = true;
+                    if (code == 0) continue;
+                    add_inplace(C, z[r], mul_scalar(C, mc, code, dw));
+                    lc.smult++;
+                  }
+                });
           }
           if (hoist)
             for (int r = 0; r < nd; r++)
               if (act[r]) {
                 z[r] = mod_down_ct(C, z[r]);
-                cnt.moddown++;
+                lc.moddown++;
               }
           std::vector<const Ct*> zs;
           std::vector<i64> sh;
@@ -585,16 +667,24 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
             y = z[0];
           } else {
             y = rotate_sum_lazy(C, act[0] ? &z[0] : nullptr, zs, sh);
-            cnt.outer_rot += zs.size();
-            cnt.ks += zs.size();
-            cnt.modup += zs.size();
-            cnt.moddown += 1;
+            lc.outer_rot += zs.size();
+            lc.ks += zs.size();
+            lc.modup += zs.size();
+            lc.moddown += 1;
           }
           y = rescale(C, y);
-          cnt.rescale++;
+          lc.rescale++;
           y.scale = Delta;
           out[oct] = y;
-        }
+          std::lock_guard<std::mutex> lock(cnt_mu);
+          add_counts(cnt, lc);
+        });
+  if (only) {   // the listed outputs, in the listed order
+    std::vector<Ct> sub;
+    for (int o : *only) sub.push_back(out[o]);
+    if (bias) add_bias(C, Lout, sub, bias, only);
+    return sub;
+  }
   if (bias) add_bias(C, Lout, out, bias);
   return out;
 }
@@ -624,24 +714,26 @@ std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& i
   } else {
     const long d = Lin.dil, m = Lin.m, bsg = Lin.bsg;
     std::vector<i64> sh = {d * bsg, d * m * bsg, (d * m + d) * bsg};
-    for (const Ct& x : in) {
+    out.resize(in.size());
+    par_for((int)in.size(), [&](int i) {
+      const Ct& x = in[i];
       Ct y;
       if (hoist) {   // sum in the extended basis, one ModDown
         std::vector<Ct> r = rotate_hoisted_pq(C, x, sh);
         y = lift_pq(C, x);
         for (const Ct& t : r) add_inplace(C, y, t);
         y = mod_down_ct(C, y);
-        cnt.moddown += 1;
       } else {
         std::vector<Ct> r = rotate_hoisted(C, x, sh);
         y = x;
         for (const Ct& t : r) add_inplace(C, y, t);
-        cnt.moddown += 3;
       }
-      cnt.other_rot += 3; cnt.ks += 3; cnt.modup += 1;
       y.scale = Lout.scale;
-      out.push_back(y);
-    }
+      out[i] = y;
+    });
+    const long n = (long)in.size();
+    cnt.moddown += hoist ? n : 3 * n;
+    cnt.other_rot += 3 * n; cnt.ks += 3 * n; cnt.modup += n;
     Lout.dil = Lin.dil * 2;
   }
   return out;
@@ -683,19 +775,21 @@ std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& i
       S = (((double)k2 * s) * s) / c2;
     }
     const i128 k1 = big_code(c1 * S / s), k0 = big_code(c0 * S);
-    for (const Ct& x : in) {
+    out.resize(in.size());
+    par_for((int)in.size(), [&](int i) {
+      const Ct& x = in[i];
       Ct y;
       if (d == 2) {
         Ct t = square_relin(C, x, k2);
-        cnt.relin++; cnt.ks++; cnt.modup++; cnt.moddown++;
         y = lin_comb(C, &t, x, k1, k0);
       } else {
         y = lin_comb(C, nullptr, x, k1, k0);
       }
-      y = rescale(C, y);
-      cnt.rescale++;
-      out.push_back(y);
-    }
+      out[i] = rescale(C, y);
+    });
+    const long n = (long)in.size();
+    if (d == 2) { cnt.relin += n; cnt.ks += n; cnt.modup += n; cnt.moddown += n; }
+    cnt.rescale += n;
     Lout.level = Lin.level - 1;
     Lout.scale = S / ql;
   } else {
@@ -708,16 +802,17 @@ std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& i
     if (k3 == 0) k3 = c3 > 0 ? 1 : -1;
     const double Su = ((double)k3 * s) / c3, S = s2 * Su;
     const i128 k2c = big_code(c2 * Su), k1 = big_code(c1 * S / s), k0 = big_code(c0 * S);
-    for (const Ct& x : in) {
+    out.resize(in.size());
+    par_for((int)in.size(), [&](int i) {
+      const Ct& x = in[i];
       Ct X2 = rescale(C, square_relin(C, x, k));
       const Ct xd = drop_last_limb(x);
       const Ct u = lin_comb(C, nullptr, xd, k3, k2c);
       Ct P = mul_relin(C, X2, u);
-      cnt.relin += 2; cnt.ks += 2; cnt.modup += 2; cnt.moddown += 2;
-      Ct y = rescale(C, lin_comb(C, &P, xd, k1, k0));
-      cnt.rescale += 2;
-      out.push_back(y);
-    }
+      out[i] = rescale(C, lin_comb(C, &P, xd, k1, k0));
+    });
+    const long n = (long)in.size();
+    cnt.relin += 2 * n; cnt.ks += 2 * n; cnt.modup += 2 * n; cnt.moddown += 2 * n; cnt.rescale += 2 * n;
     Lout.level = Lin.level - 2;
     Lout.scale = S / q1;
   }
@@ -732,14 +827,10 @@ std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>&
   const double s = Lin.scale, ql = (double)C.primes[Lin.level];
   i64 k = (i64)std::round((delta_of(C) * ql) / (s * s));
   if (k < 1) k = 1;
-  std::vector<Ct> out;
-  for (const Ct& x : in) {
-    Ct y = square_relin(C, x, k);
-    cnt.relin++; cnt.ks++; cnt.modup++; cnt.moddown++;
-    y = rescale(C, y);
-    cnt.rescale++;
-    out.push_back(y);
-  }
+  std::vector<Ct> out(in.size());
+  par_for((int)in.size(), [&](int i) { out[i] = rescale(C, square_relin(C, in[i], k)); });
+  const long n = (long)in.size();
+  cnt.relin += n; cnt.ks += n; cnt.modup += n; cnt.moddown += n; cnt.rescale += n;
   Lout = Lin;
   Lout.level = Lin.level - 1;
   Lout.scale = (((double)k * s) * s) / ql;
@@ -815,48 +906,63 @@ std::vector<Ct> compress_to(Context& C, const Layout& Lin, const std::vector<Ct>
   hoist = hoist && !need.empty();
   const std::vector<int> basis = hoist ? qp_basis(C, lvl) : q_basis(lvl);
   std::map<std::pair<int, long>, Ct> copies;
-  for (auto& kv : need) {
-    std::vector<i64> sh(kv.second.begin(), kv.second.end());
-    std::vector<Ct> r = hoist ? rotate_hoisted_pq(C, in[kv.first], sh) : rotate_hoisted(C, in[kv.first], sh);
-    for (size_t i = 0; i < sh.size(); i++) copies[{kv.first, sh[i]}] = r[i];
-    cnt.other_rot += sh.size();
-    cnt.ks += sh.size();
-    cnt.modup += 1;
-    if (!hoist) cnt.moddown += sh.size();
+  {
+    std::vector<std::pair<int, std::vector<i64>>> jobs;
+    for (auto& kv : need) jobs.push_back({kv.first, std::vector<i64>(kv.second.begin(), kv.second.end())});
+    std::vector<std::vector<Ct>> rot(jobs.size());
+    par_for((int)jobs.size(), [&](int j) {
+      rot[j] = hoist ? rotate_hoisted_pq(C, in[jobs[j].first], jobs[j].second)
+                     : rotate_hoisted(C, in[jobs[j].first], jobs[j].second);
+    });
+    for (size_t j = 0; j < jobs.size(); j++) {
+      const std::vector<i64>& sh = jobs[j].second;
+      for (size_t i = 0; i < sh.size(); i++) copies[{jobs[j].first, sh[i]}] = rot[j][i];
+      cnt.other_rot += sh.size();
+      cnt.ks += sh.size();
+      cnt.modup += 1;
+      if (!hoist) cnt.moddown += sh.size();
+    }
   }
   std::map<int, Ct> lifted;
+  if (hoist)
+    for (const MoveGroup& g : mg)
+      if (!g.delta && !lifted.count(g.src)) lifted.emplace(g.src, lift_pq(C, in[g.src]));
   auto source = [&](int idx, long delta) -> const Ct& {
     if (delta) return copies.at({idx, delta});
     if (!hoist) return in[idx];
-    auto it = lifted.find(idx);
-    if (it == lifted.end()) it = lifted.emplace(idx, lift_pq(C, in[idx])).first;
-    return it->second;
+    return lifted.at(idx);
   };
   const double dm = ((double)C.primes[lvl] * delta_of(C)) / Lin.scale;
   Lout = T;
   Lout.level = lvl - 1;
   Lout.scale = delta_of(C);
-  std::vector<Ct> out;
-  for (int d = 0; d < T.n_ct(); d++) {
+  std::vector<Ct> out(T.n_ct());
+  const bool inner = T.n_ct() < orc_threads();   // few targets: their masked copies in parallel
+  par_for(T.n_ct(), [&](int d) {
     Ct acc = zero_ct(C, lvl, Lin.scale * dm);
     acc.c0 = poly_zero(C, basis);
     acc.c1 = poly_zero(C, basis);
-    for (const MoveGroup& g : mg) {
-      if (g.dst != d) continue;
+    std::vector<const MoveGroup*> gs;
+    for (const MoveGroup& g : mg)
+      if (g.dst == d) gs.push_back(&g);
+    std::vector<Ct> part(gs.size());
+    auto masked = [&](int j) {
+      const MoveGroup& g = *gs[j];
       std::vector<double> z(C.ns, 0.0);   // the moved slots after the rotation
       for (int sl : g.src_slots) z[posmod((long)sl - g.delta, C.ns)] = 1.0;
-      add_inplace(C, acc, mul_plain(C, source(g.src, g.delta), encode(C, z, {}, dm, basis), dm));
-      cnt.pmult++;
-    }
-    if (hoist) {
-      acc = mod_down_ct(C, acc);
-      cnt.moddown++;
-    }
+      part[j] = mul_plain(C, source(g.src, g.delta), encode(C, z, {}, dm, basis), dm);
+    };
+    if (inner) par_for((int)gs.size(), masked);
+    else for (int j = 0; j < (int)gs.size(); j++) masked(j);
+    for (const Ct& p : part) add_inplace(C, acc, p);
+    if (hoist) acc = mod_down_ct(C, acc);
     Ct y = rescale(C, acc);
-    cnt.rescale++;
     y.scale = Lout.scale;
-    out.push_back(y);
-  }
+    out[d] = y;
+  });
+  cnt.pmult += (long)mg.size();
+  if (hoist) cnt.moddown += T.n_ct();
+  cnt.rescale += T.n_ct();
   return out;
 }
 
@@ -938,18 +1044,17 @@ std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, con
       if (diag_active(g * n1 + b)) { baby[b] = true; giant[g] = true; }
   // plaintext for (g, b): diag_{g n1 + b} rotated right by g*n1 slots-of-features
   std::vector<std::vector<RPoly>> pt(n2, std::vector<RPoly>(n1));
-  for (int g = 0; g < n2; g++)
-    for (int b = 0; b < n1; b++) {
-      int kd = g * n1 + b;
-      if (!diag_active(kd)) continue;
-      std::vector<double> z(C.ns, 0.0);
-      for (int l = 0; l < C.ns; l++) {
-        int src = posmod((long)l - (long)g * n1 * bsg, C.ns);
-        int i = src / bsg;
-        z[l] = Wp[(size_t)i * d + (i + kd) % d];
-      }
-      pt[g][b] = encode(C, z, {}, dp, q_basis(lvl));
+  par_for(n2 * n1, [&](int kd) {   // the diagonals are encoded independently
+    const int g = kd / n1;
+    if (!diag_active(kd)) return;
+    std::vector<double> z(C.ns, 0.0);
+    for (int l = 0; l < C.ns; l++) {
+      int src = posmod((long)l - (long)g * n1 * bsg, C.ns);
+      int i = src / bsg;
+      z[l] = Wp[(size_t)i * d + (i + kd) % d];
     }
+    pt[g][kd % n1] = encode(C, z, {}, dp, q_basis(lvl));
+  });
   Lout = Layout();
   Lout.kind = KIND_VECTOR;
   Lout.bs = Lin.bs; Lout.c = dout; Lout.h = 1; Lout.w = 1;
@@ -974,12 +1079,11 @@ std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, con
     xb[0] = &x;
     for (size_t i = 0; i < bsh.size(); i++) xb[bsh[i] / bsg] = &xr[i];
     std::vector<Ct> u(n2, zero_ct(C, lvl, Lin.scale * dp));
-    for (int g = 0; g < n2; g++)
-      for (int b = 0; b < n1; b++) {
-        if (!diag_active(g * n1 + b)) continue;
-        add_inplace(C, u[g], mul_plain(C, *xb[b], pt[g][b], dp));
-        cnt.pmult++;
-      }
+    par_for(n2, [&](int g) {   // giant-step sums are independent
+      for (int b = 0; b < n1; b++)
+        if (diag_active(g * n1 + b)) add_inplace(C, u[g], mul_plain(C, *xb[b], pt[g][b], dp));
+    });
+    for (int kd = 0; kd < n1 * n2; kd++) cnt.pmult += diag_active(kd);
     std::vector<const Ct*> zs;
     std::vector<i64> sh;
     for (int g = 1; g < n2; g++)

@@ -45,6 +45,8 @@ void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, dou
 // pt_budget: plaintext bytes under which per-position weights are materialised
 // as full-scale plaintext diagonals instead of mask-basis scalar codes (the
 // distinct diagonals: those of one batch group)
+// only: compute just the listed output ciphertexts (and only the rotations
+// their terms read), returned in the listed order.
 // target: write the output straight into that layout of the output tensor
 // (Arch-aware Ct Compression fused with the convolution: the repack masks
 // multiply the convolution's plaintexts, its rotations merge with the outer
@@ -52,7 +54,7 @@ void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, dou
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
                        long long pt_budget = 1LL << 30, int hoist = 0, const Layout* target = nullptr,
-                       const double* bias = nullptr);
+                       const double* bias = nullptr, const std::vector<int>* only = nullptr);
 // hoist = 1: rotated copies stay in the extended basis and each combined
 // ciphertext is moved down once (see conv2d)
 std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
@@ -85,8 +87,10 @@ std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& i
                          Counts& cnt, int hoist = 0);
 std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                    int dout, Layout& Lout, Counts& cnt, const double* bias = nullptr);
-// bias[o] (channel o, or feature o of a VECTOR layout) added to every valid slot
-void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const double* bias);
+// bias[o] (channel o, or feature o of a VECTOR layout) added to every valid
+// slot; out[k] is ciphertext idx[k] of L (idx null: ciphertext k)
+void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const double* bias,
+              const std::vector<int>* idx = nullptr);
 
 // scalar weight code: round half away from zero of w * scale in binary64
 i64 weight_code(double w, double scale);

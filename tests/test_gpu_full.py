@@ -77,20 +77,113 @@ def test_graph_replay_survives_workspace_growth():
     assert fe.export(y).shape[0] == y.n_ct
 
 
-def test_lenet_first_layer_matches_oracle_at_full_size(lenet):
-    """Encryption and the whole first convolution (4 -> 24 ciphertexts, 32
-    hoisted key switches) at N = 2^15, 20 limbs, element by element."""
+def test_lenet_every_layer_matches_oracle_at_full_size(lenet):
+    """The whole LeNet-shaped network at N = 2^15, 20 limbs, 64 images, element
+    by element after every layer: encryption, conv1 (32 hoisted key switches),
+    x^2, the fragment-sum pool, conv2 (144), x^2, the rotation pool (48),
+    compression (15) and the three FC layers.  The oracle runs its own chain
+    from its own encryption (a thread per independent ciphertext)."""
+    import time
     from oracle import pyoracle as P
     from paper_2606_16359_amd import workloads as W
     fe, x, w, lay, ct = lenet
     o = P.Oracle(*W.PARAMS["lenet"])
-    Lo = o.plan_layout(64, 1, 28, 28, 5, 6)
-    ob = o.encrypt_tensor(Lo, x, W.SEED_ENC)
+    h = fe.hoist
+    ob = o.encrypt_tensor(o.plan_layout(64, 1, 28, 28, 5, 6), x, W.SEED_ENC)
     assert np.array_equal(fe.export(ct), ob.data())
-    yo, cnt = o.conv2d(ob, w[0], hoist=fe.hoist)
-    y = fe.conv2d(ct, w[0])
-    assert cnt["ks"] == 32
-    assert np.array_equal(fe.export(y), yo.data())
+    steps = [("conv1", lambda c: fe.conv2d(c, w[0]), lambda b: o.conv2d(b, w[0], hoist=h)),
+             ("x^2", lambda c: fe.poly_act(c), lambda b: o.poly_act(b, [0.0, 0.0, 1.0])),
+             ("pool1", fe.avgpool2, lambda b: o.avgpool2(b, hoist=h)),
+             ("conv2", lambda c: fe.conv2d(c, w[1]), lambda b: o.conv2d(b, w[1], hoist=h)),
+             ("x^2", lambda c: fe.poly_act(c), lambda b: o.poly_act(b, [0.0, 0.0, 1.0])),
+             ("pool2", fe.avgpool2, lambda b: o.avgpool2(b, hoist=h)),
+             ("compress", fe.compress, lambda b: o.compress(b, hoist=h)),
+             ("fc1", lambda c: fe.fc(c, w[2]), lambda b: o.fc(b, w[2])),
+             ("fc2", lambda c: fe.fc(c, w[3]), lambda b: o.fc(b, w[3])),
+             ("fc3", lambda c: fe.fc(c, w[4]), lambda b: o.fc(b, w[4]))]
+    y, yo = ct, ob
+    for name, lib_op, orc_op in steps:
+        t0 = time.time()
+        y = lib_op(y)
+        yo, cnt = orc_op(yo)
+        got, want = fe.export(y), yo.data()
+        print(f"{name}: {want.shape[0]} cts, oracle {time.time() - t0:.1f}s, {cnt['ks']} key switches", flush=True)
+        assert got.shape == want.shape, name
+        assert np.array_equal(got, want), name
+
+
+def _container(layout, n, level):
+    """An oracle layout dict holding n ciphertexts of `layout` at `level` (for
+    per-ciphertext operations on sampled outputs)."""
+    d = dict(layout)
+    d.update(nbg=n, ncg=1, S=1, level=level)
+    return d
+
+
+def test_cifar_first_layer_and_cubic_sampled_cones_match_oracle():
+    """CIFAR-shaped stack at its real parameters (256 images, N = 2^16, 24 limbs,
+    dnum 4): the first layer (S = 4, C' = 2: masks, hoisted inner rotations,
+    one outer rotation per output) and its cubic activation, compared element
+    by element on seeded sampled output ciphertexts whose input cones the
+    oracle recomputes; sampled input ciphertexts equal the oracle's own
+    encryption."""
+    import time
+    from oracle import pyoracle as P
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["cifar"])
+    o = P.Oracle(*W.PARAMS["cifar"])
+    x, w = W.cifar_inputs(256)
+    lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
+    Lo = o.plan_layout(256, 16, 32, 32, 3, 16)
+    assert (lay.S, lay.chan_per_ct, lay.n_ct()) == (Lo["S"], Lo["cpc"], 128) == (4, 2, 128)
+    pt = fe.encode_fragment(x, lay)
+    ct = fe.encrypt(pt, lay, W.SEED_ENC)
+    xin = fe.export(ct)
+    for t in (0, 77, 127):
+        assert np.array_equal(xin[t], o.encrypt(pt[t], Lo["level"], Lo["scale"], W.SEED_ENC, t))
+    outs = sorted(np.random.default_rng(2026).choice(128, 2, replace=False).tolist())
+    t0 = time.time()
+    yo, cnt = o.conv2d(o.batch(Lo, xin), w[0], 1, 1, 1, hoist=fe.hoist, outputs=outs)
+    print(f"oracle cone of outputs {outs}: {cnt}, {time.time() - t0:.1f}s", flush=True)
+    del xin
+    y = fe.conv2d(ct, w[0], pad=1)
+    assert np.array_equal(fe.export(y)[outs], yo)
+    z = fe.export(fe.poly_act(y, W.CUBIC))[outs]
+    t0 = time.time()
+    zo, _ = o.poly_act(o.batch(_container(Lo, len(outs), y.lay.level), yo), W.CUBIC)
+    print(f"oracle cubic on the sampled outputs: {time.time() - t0:.1f}s", flush=True)
+    assert np.array_equal(z, zo.data())
+
+
+def test_mobilenet_block_a_sampled_cones_match_oracle():
+    """MobileNet-V1 block A at ImageNet shape (224x224x3, conv 3->32 stride 2,
+    S = 2, 16 images, N = 2^16, 24 limbs) and its quadratic, compared element
+    by element on seeded sampled output ciphertexts."""
+    import time
+    from oracle import pyoracle as P
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["cifar"])
+    o = P.Oracle(*W.PARAMS["cifar"])
+    blk = W.MOBILENET_BLOCKS[0][0]
+    wa = W.mobilenet_weights()[0][0]
+    x = W.images((16, 3, 224, 224))
+    lay = fe.plan_layout(16, 3, 224, 224, 3, 32, 2)
+    Lo = o.fragment_layout(16, 3, 224, 224, 2)
+    assert (lay.bs_g, lay.chan_per_ct, lay.n_ct()) == (Lo["bsg"], Lo["cpc"], 96) == (2, 1, 96)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    xin = fe.export(ct)
+    y = fe.conv2d(ct, wa, stride=blk["stride"], pad=blk["pad"])
+    outs = sorted(np.random.default_rng(2027).choice(y.n_ct, 2, replace=False).tolist())
+    t0 = time.time()
+    yo, cnt = o.conv2d(o.batch(Lo, xin), wa, blk["stride"], blk["pad"], 1, hoist=fe.hoist, outputs=outs)
+    print(f"oracle cone of outputs {outs}: {cnt}, {time.time() - t0:.1f}s", flush=True)
+    del xin
+    assert np.array_equal(fe.export(y)[outs], yo)
+    z = fe.export(fe.poly_act(y, W.QUADRATIC))[outs]
+    zo, _ = o.poly_act(o.batch(_container(Lo, len(outs), y.lay.level), yo), W.QUADRATIC)
+    assert np.array_equal(z, zo.data())
 
 
 def test_cifar_stack_full_size_decrypts_to_float64():

@@ -406,3 +406,16 @@ def test_bias_is_added_at_the_output_scale():
     fw, fb = rand_w((5, 256), 53), np.linspace(-1, 1, 5)
     z, _ = o.fc(v, fw, bias=fb)
     assert np.max(np.abs(o.decrypt_tensor(z).reshape(2, 5) - (ref.reshape(2, -1) @ fw.T + fb))) < 1e-4
+
+
+def test_conv2d_output_subset_equals_the_full_output():
+    """Sampled outputs (their input cone only) are the full layer's outputs,
+    with and without a bias, under both plaintext forms."""
+    o = small_oracle(nq=6)
+    x, w = rand_x((4, 4, 8, 8), 61), rand_w((4, 4, 3, 3), 62)
+    b = o.encrypt_tensor(o.fragment_layout(4, 4, 8, 8, 2), x, seed=6)
+    for budget, bias in [(1 << 30, None), (0, np.arange(4.0))]:
+        full, c = o.conv2d(b, w, 1, 1, 1, pt_budget=budget, hoist=1, bias=bias)
+        sub, cs = o.conv2d(b, w, 1, 1, 1, pt_budget=budget, hoist=1, bias=bias, outputs=[3, 0])
+        assert np.array_equal(sub, full.data()[[3, 0]])
+        assert cs["inner_rot"] < c["inner_rot"]
