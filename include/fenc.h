@@ -33,9 +33,14 @@
  *    a given shape builds and caches its plan (encoded plaintexts, index
  *    tables) and may allocate.  A repeated call with the same shapes and
  *    weights allocates nothing and can be captured into a hipGraph.
- *  - Secret material: the context holds the secret key (client role) and the
- *    evaluation keys (server role) at once; this library is the hot path, not
- *    a key-management system.
+ *  - Secret material (Design Overview: the client holds the secret key, the
+ *    server only evaluation keys): fenc_ctx_create makes a client context
+ *    (secret key drawn from params.seed; it can also evaluate, generating
+ *    missing switching keys on demand); fenc_ctx_create_server makes a server
+ *    context that never holds a secret key: it evaluates with switching keys
+ *    imported from a client (fenc_key_export_galois / fenc_key_import) and
+ *    ciphertexts imported in coefficient form (fenc_ct_import); encryption,
+ *    decryption and key generation there fail with FENC_ENOKEY.
  */
 #ifndef FENC_H
 #define FENC_H
@@ -121,6 +126,8 @@ enum { FENC_MODE_BATCHED = 0, FENC_MODE_PER_OP = 1 };
  * Creates a context (host tables only; device tables are built on first use
  * on the current HIP device).  Errors: EINVAL for unsupported parameters. */
 int fenc_ctx_create(const fenc_params* p, fenc_ctx** out);
+/* A server context: the same parameters and tables, no secret key. */
+int fenc_ctx_create_server(const fenc_params* p, fenc_ctx** out);
 void fenc_ctx_destroy(fenc_ctx* ctx);
 /* n_q + n_p primes of the context (host array). */
 int fenc_ctx_primes(const fenc_ctx* ctx, uint64_t* out);
@@ -170,6 +177,18 @@ int fenc_keygen(fenc_ctx* ctx, const int32_t* rot_steps, uint32_t n_steps, int r
 /* Host copy of a switching key in coefficient form [dnum'][2][n_q+n_p][N]
  * (shift = slot rotation, or INT32_MIN for the relinearisation key). */
 int fenc_key_export(fenc_ctx* ctx, int32_t shift, uint64_t* out);
+/* Galois elements of the switching keys the context holds (0: the
+ * relinearisation key), at most cap written to galois; returns how many the
+ * context holds (or a negative fenc_status). */
+int fenc_key_list(const fenc_ctx* ctx, uint64_t* galois, int32_t cap);
+/* fenc_key_export by Galois element g (0: relinearisation key). */
+int fenc_key_export_galois(fenc_ctx* ctx, uint64_t g, uint64_t* out);
+/* Adds the switching key of Galois element g (0: relinearisation), host
+ * coefficient form [dnum'][2][n_q+n_p][N] as fenc_key_export writes it, to a
+ * context (typically a server context).  Errors: EINVAL for an element that
+ * is not an odd g < 2N other than 1, a key the context already holds, or a
+ * residue not below its prime. */
+int fenc_key_import(fenc_ctx* ctx, uint64_t g, const uint64_t* in);
 
 /* ---- planning (Conv-aware Encoding: Alg. fragment-packing, eq. total-rot,
  * eq. opt, Theorem 1) --------------------------------------------------------

@@ -1325,7 +1325,12 @@ extern "C" {
 
 const char* fenc_last_error(void) { return g_err.c_str(); }
 
-int fenc_ctx_create(const fenc_params* p, fenc_ctx** out) {
+static int ctx_create(const fenc_params* p, fenc_ctx** out, bool with_sk);
+
+int fenc_ctx_create(const fenc_params* p, fenc_ctx** out) { return ctx_create(p, out, true); }
+int fenc_ctx_create_server(const fenc_params* p, fenc_ctx** out) { return ctx_create(p, out, false); }
+
+static int ctx_create(const fenc_params* p, fenc_ctx** out, bool with_sk) {
   API_BEGIN
   if (!p || !out) fail(FENC_EINVAL, "null argument");
   *out = nullptr;
@@ -1352,8 +1357,11 @@ int fenc_ctx_create(const fenc_params* p, fenc_ctx** out) {
   auto ps = fh::ntt_primes(p->p_bits, p->log_n, p->n_p, C->primes);
   C->primes.insert(C->primes.end(), ps.begin(), ps.end());
   for (uint64_t q : C->primes) C->psi.push_back(fh::root_2n(q, p->log_n));
-  C->s.resize(C->N);
-  for (int i = 0; i < C->N; i++) C->s[i] = fh::draw_ternary(p->seed, fh::tag::secret, i);
+  C->has_sk = with_sk;
+  if (with_sk) {
+    C->s.resize(C->N);
+    for (int i = 0; i < C->N; i++) C->s[i] = fh::draw_ternary(p->seed, fh::tag::secret, i);
+  }
   *out = C.release();
   API_END
 }
@@ -1483,6 +1491,57 @@ int fenc_key_export(fenc_ctx* ctx, int32_t shift, uint64_t* out) {
   API_END
 }
 
+int fenc_key_list(const fenc_ctx* ctx, uint64_t* galois, int32_t cap) {
+  if (!ctx || cap < 0 || (cap > 0 && !galois)) {
+    g_err = "bad argument";
+    return FENC_EINVAL;
+  }
+  int n = 0;
+  for (auto& kv : ctx->keys) {
+    if (n < cap) galois[n] = kv.first;
+    n++;
+  }
+  return n;
+}
+
+static void check_galois(const Ctx& C, uint64_t g) {
+  if (g != 0 && (g % 2 == 0 || g >= 2ull * C.N || g == 1)) fail(FENC_EINVAL, "not a Galois element of a rotation");
+}
+
+int fenc_key_export_galois(fenc_ctx* ctx, uint64_t g, uint64_t* out) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  check_galois(*ctx, g);
+  ensure_device(*ctx);
+  const uint64_t* key = get_key(*ctx, g);
+  const int np = ctx->np, nd = ctx->ndig, N = ctx->N;
+  std::vector<void*> tmp;
+  uint64_t* t = (uint64_t*)dalloc(*ctx, (size_t)nd * 2 * np * N * 8, tmp);
+  ntt(*ctx, true, key, t, (long long)np * N, (long long)np * N, nd * 2 * np, np, identity_map(np), nullptr);
+  fb::sync(nullptr);
+  fb::d2h(out, t, (size_t)nd * 2 * np * N * 8);
+  dfree_all(*ctx, tmp);
+  API_END
+}
+
+int fenc_key_import(fenc_ctx* ctx, uint64_t g, const uint64_t* in) {
+  API_BEGIN
+  if (!ctx || !in) fail(FENC_EINVAL, "null argument");
+  fenc_ctx& C = *ctx;
+  check_galois(C, g);
+  if (C.keys.count(g)) fail(FENC_EINVAL, "the context already holds this key");
+  ensure_device(C);
+  const int np = C.np, nd = C.ndig, N = C.N;
+  for (size_t i = 0; i < (size_t)nd * 2 * np * N; i++)
+    if (in[i] >= C.primes[(i / N) % np]) fail(FENC_EINVAL, "key residue out of range");
+  std::vector<uint64_t> h(in, in + (size_t)nd * 2 * np * N);
+  uint64_t* key = upload(C, h, C.owned);
+  ntt(C, false, key, key, (long long)np * N, (long long)np * N, nd * 2 * np, np, identity_map(np), nullptr);
+  fb::sync(nullptr);
+  C.keys[g] = key;
+  API_END
+}
+
 int fenc_plan_layout(const fenc_ctx* ctx, uint32_t bs, uint32_t c, uint32_t h, uint32_t w, uint32_t k_next,
                      uint32_t cout_next, int32_t s_override, fenc_layout* out) {
   API_BEGIN
@@ -1589,6 +1648,7 @@ int fenc_encrypt(fenc_ctx* ctx, const uint64_t* pt, const fenc_layout* lay, uint
                  void* stream) {
   API_BEGIN
   if (!ctx || !pt || !out) fail(FENC_EINVAL, "null argument");
+  if (!ctx->has_sk) fail(FENC_ENOKEY, "server context holds no secret key: encryption is the client's");
   Layout L = from_pub(*ctx, lay);
   out->lay = *lay;
   if (!out->data) return FENC_OK;
@@ -1633,6 +1693,7 @@ int fenc_encrypt(fenc_ctx* ctx, const uint64_t* pt, const fenc_layout* lay, uint
 }
 
 static void decrypt_limbs(fenc_ctx& C, const fenc_ctbatch* in, std::vector<uint64_t>& m, int limbs, fb::Stream s) {
+  if (!C.has_sk) fail(FENC_ENOKEY, "server context holds no secret key: decryption is the client's");
   Layout L = from_pub(C, &in->lay);
   ensure_device(C);
   const int n = L.n_ct(), nl = L.level + 1, N = C.N;

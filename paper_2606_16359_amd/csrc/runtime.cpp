@@ -157,6 +157,10 @@ void ensure_device(Ctx& C) {
   C.md_tab = upload(C, md, C.owned);
   C.pinv = upload(C, pinv, C.owned);
   C.dev = true;
+  if (!C.has_sk) {   // a server context: no secret key on the device
+    autotune_ntt(C);
+    return;
+  }
   // secret key in NTT form over every prime
   std::vector<long long> sv(C.s.begin(), C.s.end());
   long long* ds = upload(C, sv, C.owned);
@@ -378,6 +382,9 @@ const uint64_t* get_key(Ctx& C, uint64_t g) {
   auto it = C.keys.find(g);
   if (it != C.keys.end()) return it->second;
   if (C.strict) fail(FENC_ENOKEY, "missing switching key for Galois element " + std::to_string(g));
+  if (!C.has_sk)
+    fail(FENC_ENOKEY, "server context holds no secret key: import the switching key for Galois element " +
+                          std::to_string(g));
   ensure_device(C);
   const int N = C.N, np = C.np, nd = C.ndig, L1 = C.L + 1;
   const uint64_t seed = C.prm.seed;

@@ -163,7 +163,8 @@ struct fenc_ctx {
   int logn = 0, N = 0, ns = 0, L = 0, K = 0, alpha = 0, ndig = 0, np = 0;
   double Delta = 1.0;
   std::vector<uint64_t> primes, psi;
-  std::vector<int64_t> s;            // secret key coefficients
+  std::vector<int64_t> s;            // secret key coefficients (client role)
+  bool has_sk = true;                // false: server context (evaluation keys only)
   int mode = FENC_MODE_BATCHED;
   bool strict = false;
   int64_t pt_budget = 1LL << 30;     // bytes of materialised conv plaintexts (one batch group)

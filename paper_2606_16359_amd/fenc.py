@@ -81,6 +81,7 @@ def load(path=None):
     sig = {
         "fenc_last_error": (C.c_char_p, []),
         "fenc_ctx_create": (C.c_int, [P, C.POINTER(vp)]),
+        "fenc_ctx_create_server": (C.c_int, [P, C.POINTER(vp)]),
         "fenc_ctx_destroy": (None, [vp]),
         "fenc_ctx_primes": (C.c_int, [vp, vp]),
         "fenc_set_mode": (C.c_int, [vp, C.c_int]),
@@ -94,6 +95,9 @@ def load(path=None):
         "fenc_device_bytes": (C.c_int64, [vp]),
         "fenc_keygen": (C.c_int, [vp, vp, u32, C.c_int, C.c_int]),
         "fenc_key_export": (C.c_int, [vp, i32, vp]),
+        "fenc_key_list": (C.c_int, [vp, vp, C.c_int32]),
+        "fenc_key_export_galois": (C.c_int, [vp, C.c_uint64, vp]),
+        "fenc_key_import": (C.c_int, [vp, C.c_uint64, vp]),
         "fenc_plan_layout": (C.c_int, [vp, u32, u32, u32, u32, u32, u32, i32, L]),
         "fenc_layout_n_ct": (C.c_int, [L]),
         "fenc_ct_bytes": (C.c_int64, [vp, L]),
@@ -158,12 +162,15 @@ class Fenc:
     """One library context.  `lib_path` selects another build of the same ABI
     (the CPU test suite uses the kernel emulator); the default is the HIP library."""
 
-    def __init__(self, log_n, n_q, q_bits, n_p, p_bits, dnum, log2_scale, seed, lib_path=None):
+    def __init__(self, log_n, n_q, q_bits, n_p, p_bits, dnum, log2_scale, seed, lib_path=None, server=False):
+        """server=True: a context without a secret key (evaluation keys are
+        imported with key_import)."""
         self.lib = load(lib_path)
         self.emulated = lib_path is not None and "emu" in os.path.basename(lib_path)
         p = Params(log_n, n_q, q_bits, n_p, p_bits, dnum, log2_scale, seed)
         h = C.c_void_p()
-        self._check(self.lib.fenc_ctx_create(C.byref(p), C.byref(h)))
+        create = self.lib.fenc_ctx_create_server if server else self.lib.fenc_ctx_create
+        self._check(create(C.byref(p), C.byref(h)))
         self.h = h
         self.params = p
         self.N, self.ns, self.L = 1 << log_n, 1 << (log_n - 1), n_q - 1
@@ -260,6 +267,28 @@ class Fenc:
         arr = np.array(list(rot_steps), np.int32)
         self._check(self.lib.fenc_keygen(self.h, arr.ctypes.data if len(arr) else None, len(arr), int(relin),
                                          int(strict)))
+
+    def key_list(self):
+        n = self.lib.fenc_key_list(self.h, None, 0)
+        if n < 0:
+            self._check(n)
+        out = np.zeros(max(1, n), np.uint64)
+        self.lib.fenc_key_list(self.h, out.ctypes.data, n)
+        return [int(g) for g in out[:n]]
+
+    def _key_shape(self):
+        ndig = (self.n_q + self.alpha - 1) // self.alpha
+        return (ndig, 2, self.n_q + self.n_p, self.N)
+
+    def key_export_galois(self, g):
+        out = np.zeros(self._key_shape(), np.uint64)
+        self._check(self.lib.fenc_key_export_galois(self.h, g, out.ctypes.data))
+        return out
+
+    def key_import(self, g, key):
+        key = np.ascontiguousarray(key, np.uint64)
+        assert key.shape == self._key_shape()
+        self._check(self.lib.fenc_key_import(self.h, g, key.ctypes.data))
 
     def key_export(self, shift):
         ndig = (self.n_q + self.alpha - 1) // self.alpha

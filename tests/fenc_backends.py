@@ -28,8 +28,8 @@ def lib_path(backend):
     return None
 
 
-def make(backend, *params):
-    return F.Fenc(*params, lib_path=lib_path(backend))
+def make(backend, *params, server=False):
+    return F.Fenc(*params, lib_path=lib_path(backend), server=server)
 
 
 def rng(seed):

@@ -239,6 +239,45 @@ def test_compression_targets_and_fused_block_size_change_bit_exact(backend, orc)
     assert np.max(np.abs(f.decrypt(y) - cnn_ref.conv2d(x8, w, 1, 1))) < 1e-4
 
 
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_server_context_evaluates_with_imported_keys_and_holds_no_secret(backend):
+    """Client/server protocol (Design Overview): the client encrypts and
+    generates the evaluation keys; a server context without a secret key
+    imports them and the ciphertexts, evaluates a convolution, an activation,
+    pooling, compression and an FC layer, and returns ciphertexts identical
+    to the client's own evaluation; it cannot encrypt, decrypt or make keys."""
+    client, server = make(backend, *SMALL), make(backend, *SMALL, server=True)
+    r = rng(41)
+    x, w, fw = r.uniform(0, 1, (4, 2, 8, 8)), r.normal(0, 0.1, (2, 2, 3, 3)), r.normal(0, 0.1, (3, 32))
+    lay = client.plan_layout(4, 2, 8, 8, 3, 2, 2)
+    ct = client.encrypt(client.encode_fragment(x, lay), lay, 9)
+
+    def net(f, c):
+        y = f.avgpool2(f.poly_act(f.conv2d(c, w, pad=1)))
+        return f.fc(f.compress(y), fw)
+    ref = client.export(net(client, ct))
+    keys = client.key_list()
+    assert 0 in keys and len(keys) > 2
+    for g in keys:
+        server.key_import(g, client.key_export_galois(g))
+    assert sorted(server.key_list()) == sorted(keys)
+    sct = server.import_cts(client.export(ct), ct.lay.copy())
+    out = net(server, sct)
+    assert np.array_equal(server.export(out), ref)
+    back = client.import_cts(server.export(out), out.lay.copy())
+    want = cnn_ref.fc(cnn_ref.avgpool2(cnn_ref.square(cnn_ref.conv2d(x, w, 1, 1))), fw)
+    assert np.max(np.abs(client.decrypt(back).reshape(4, 3) - want.reshape(4, 3))) < 1e-4
+    for call in (lambda: server.decrypt(out), lambda: server.decrypt_raw(out),
+                 lambda: server.encrypt(client.encode_fragment(x, lay), lay, 9),
+                 lambda: server.rotate(sct, [5])):            # no key for this shift, and none can be made
+        with pytest.raises(F.FencError) as e:
+            call()
+        assert e.value.code == -3
+    with pytest.raises(F.FencError) as e:
+        server.key_import(keys[0], client.key_export_galois(keys[0]))   # already held
+    assert e.value.code == -1
+
+
 WIDE = (10, 10, 40, 10, 40, 1, 30, 19)   # one digit of 10 limbs, 10 special primes
 
 
