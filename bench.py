@@ -31,7 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# measured on this device by `bench.py --peaks` (profiles/gfx950_peaks.md): a
+# 4 GiB device-to-device copy and the library's binary64 modular multiply
+COPY_CEILING_GBS = 5202.0
+MODMUL_PEAK = 6.223e12
 COPY_BYTES = 256 << 20
+PEAKS_BYTES = 4 << 30          # buffer size of the --peaks HBM ceilings
 MOBILENET_BATCH = 64
 WORKSPACE_LIMIT = 24 << 30
 METRIC = "encrypted images/sec (batched hipGraph, bit-exact)"
@@ -138,22 +143,32 @@ def kernel_table(fe, step):
     summ = fe.profile_summary()
     fe.profile_kernel(None)
     kernels = {}
-    for name, (kms, klaunch, kbytes) in sorted(summ.items(), key=lambda kv: -kv[1][0]):
+    for name, (kms, klaunch, kbytes, kops) in sorted(summ.items(), key=lambda kv: -kv[1][0]):
         avg_s = kms / 1e3 / klaunch
         gbs = kbytes / klaunch / avg_s / 1e9
         kernels[name] = {"launches": klaunch, "ms_per_step": round(kms, 4), "avg_launch_us": round(avg_s * 1e6, 2),
                          "bytes_per_launch": round(kbytes / klaunch), "achieved_GBs": round(gbs, 1),
-                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                         "frac_copy_ceiling": round(gbs / COPY_CEILING_GBS, 4)}
+        if kops > 0:
+            rate = kops / klaunch / avg_s
+            kernels[name].update({"modmul_per_launch": round(kops / klaunch), "modmul_per_s": round(rate, -6),
+                                  "frac_modmul_peak": round(rate / MODMUL_PEAK, 4)})
     return kernels
 
 
 def roofline(kernels, workload):
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     kd = kernels[dom]
-    return {"kernel": dom, "bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((workload, dom)),
-            "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],
-            "bytes_per_launch": kd["bytes_per_launch"]}
+    r = {"kernel": dom, "bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((workload, dom)),
+         "avg_launch_us": kd["avg_launch_us"], "launches": kd["launches"],
+         "bytes_per_launch": kd["bytes_per_launch"],
+         "measured_copy_ceiling_GBs": COPY_CEILING_GBS, "frac_of_measured_ceiling": kd["frac_copy_ceiling"]}
+    if "modmul_per_s" in kd:
+        r["alu"] = {"achieved": kd["modmul_per_s"], "peak": MODMUL_PEAK, "unit": "modmul/s",
+                    "frac": kd["frac_modmul_peak"], "peak_source": "measured binary64 mulmod rate"}
+    return r
 
 
 # ---------------------------------------------------------------- workloads
@@ -276,6 +291,36 @@ def counters_run(args):
     print(json.dumps({"counters_run": True, "workload": args.workload, "copy_bytes": COPY_BYTES}), flush=True)
 
 
+def peaks_run(args):
+    """Measured gfx950 peaks: instruction issue rates, modular-multiply rates
+    of the binary64 and the 64-bit integer designs, and HBM ceilings."""
+    import ctypes
+    from paper_2606_16359_amd import build as B
+    if not os.path.exists(B.PEAKS_LIB):
+        raise RuntimeError(f"{B.PEAKS_LIB} is not built")
+    L = ctypes.CDLL(B.PEAKS_LIB)
+    L.fenc_peaks_name.restype = ctypes.c_char_p
+    L.fenc_peaks_run.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    rows = []
+    for i in range(L.fenc_peaks_count()):
+        name, unit = L.fenc_peaks_name(i).decode().split("|")
+        arg = float(PEAKS_BYTES) if unit == "byte" else 0.02
+        sec, work, exact = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        if L.fenc_peaks_run(i, arg, ctypes.byref(sec), ctypes.byref(work), ctypes.byref(exact)) != 0:
+            raise RuntimeError(f"peaks test {name} failed")
+        rate = work.value / sec.value
+        rows.append({"test": name, "unit": unit + "/s", "rate": rate, "seconds": sec.value,
+                     "work": work.value, "exact": {1: True, 0: False}.get(exact.value)})
+        log(f"{name:55s} {rate / 1e12:9.3f} T{unit}/s  ({sec.value * 1e3:.3f} ms, exact={rows[-1]['exact']})")
+    print(json.dumps({"peaks": rows, "buffer_bytes": PEAKS_BYTES, "device": torch_device_name()}), flush=True)
+
+
+def torch_device_name():
+    import torch
+    return torch.cuda.get_device_properties(0).name
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +334,8 @@ def main():
                     help="workload of the --counters run")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes (one warm-up step, a 256 MiB copy, one step)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure instruction, modular-multiply and HBM peaks of the device and exit")
     ap.add_argument("--trace", action="store_true",
                     help="run for a kernel trace: one warm-up step, then --steps batched eager steps of the "
                          "headline workload and nothing else")
@@ -301,6 +348,9 @@ def main():
     torch.cuda.set_device(0)
     if args.counters:
         counters_run(args)
+        return
+    if args.peaks:
+        peaks_run(args)
         return
     if args.trace:
         from paper_2606_16359_amd import workloads as W

@@ -159,8 +159,9 @@ int fenc_set_workspace_limit(fenc_ctx* ctx, int64_t bytes);
 int fenc_profile_kernel(fenc_ctx* ctx, const char* name);
 int fenc_profile_result(fenc_ctx* ctx, double* total_ms, int64_t* launches, double* bytes);
 /* With the name "*" every kernel is profiled; this writes one line per kernel
- * ("name total_ms launches bytes\n", a NUL-terminated host string of at most
- * len bytes, EINVAL when it does not fit).  Synchronises on the events. */
+ * ("name total_ms launches bytes modmuls\n": algorithmic HBM bytes and modular
+ * products, 0 where not counted; a NUL-terminated host string of at most len
+ * bytes, EINVAL when it does not fit).  Synchronises on the events. */
 int fenc_profile_summary(fenc_ctx* ctx, char* buf, int64_t len);
 int fenc_stats(const fenc_ctx* ctx, fenc_counters* out);
 void fenc_stats_reset(fenc_ctx* ctx);

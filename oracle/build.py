@@ -9,17 +9,30 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["orc_core.cpp", "orc_encode.cpp", "orc_method.cpp", "orc_capi.cpp"]
 OUT = os.path.join(HERE, "_build", "liborc.so")
+SAN_OUT = os.path.join(HERE, "_build", "liborc_san.so")
 
 
-def build(verbose=False):
-    os.makedirs(os.path.dirname(OUT), exist_ok=True)
-    cmd = ["g++", "-O2", "-std=gnu++17", "-fPIC", "-shared", "-pthread", "-Wall", "-Wno-sign-compare",
-           "-o", OUT] + [os.path.join(HERE, s) for s in SOURCES] + ["-lquadmath"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
-    return OUT
+def build(verbose=False, sanitize=False):
+    """liborc.so; with sanitize, liborc_san.so under AddressSanitizer and
+    UndefinedBehaviorSanitizer."""
+    out = SAN_OUT if sanitize else OUT
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+    base = ["g++"] + opt + ["-std=gnu++17", "-fPIC", "-pthread", "-Wall", "-Wno-sign-compare"]
+    objs, procs = [], []
+    for src in SOURCES:   # one compiler per source, then the link
+        obj = out + "." + src + ".o"
+        objs.append(obj)
+        cmd = base + ["-c", os.path.join(HERE, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd))
+        procs.append(subprocess.Popen(cmd))
+    if any(p.wait() != 0 for p in procs):
+        raise RuntimeError("oracle build failed")
+    subprocess.check_call(base + ["-shared", "-o", out] + objs + ["-lquadmath"])
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--san" in sys.argv))

@@ -16,9 +16,12 @@ _LIB = None
 def lib():
     global _LIB
     if _LIB is None:
-        if not os.path.exists(_build.OUT):
-            _build.build()
-        _LIB = C.CDLL(_build.OUT)
+        path = os.environ.get("ORC_LIB")   # a prebuilt oracle (the sanitizer build)
+        if not path:
+            if not os.path.exists(_build.OUT):
+                _build.build()
+            path = _build.OUT
+        _LIB = C.CDLL(path)
         _declare(_LIB)
     return _LIB
 

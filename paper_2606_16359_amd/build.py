@@ -1,7 +1,8 @@
 """Build the HIP library for gfx950 (and, for the CPU test suite, the emulator).
 
-    python -m paper_2606_16359_amd.build            # libfenc.so (HIP, gfx950)
+    python -m paper_2606_16359_amd.build            # libfenc.so + libfenc_peaks.so (HIP, gfx950)
     python -m paper_2606_16359_amd.build --emu      # tests/emu/_build/libfenc_emu.so
+    python -m paper_2606_16359_amd.build --emu-san  # the same under ASan + UBSan
 """
 import os
 import subprocess
@@ -11,6 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "_build", "libfenc.so")
+PEAKS_LIB = os.path.join(PKG, "_build", "libfenc_peaks.so")
 EMU_LIB = os.path.join(ROOT, "tests", "emu", "_build", "libfenc_emu.so")
 HOST_SOURCES = ["runtime.cpp", "ops.cpp", "host_math.cpp"]
 ARCH = os.environ.get("FENC_OFFLOAD_ARCH", "gfx950")
@@ -45,17 +47,42 @@ def build_hip(verbose=False, jobs=8):
     if any(p.wait() != 0 for p in procs):
         raise RuntimeError("hipcc failed")
     _run([hipcc, "-shared", "--offload-arch=" + ARCH, "-o", LIB] + objs + ["-lpthread"], verbose)
+    # peak-rate microbenchmarks: a separate library, not part of libfenc
+    _run([hipcc] + COMMON + ["-x", "hip", "--offload-arch=" + ARCH, "-Wno-unused-result",
+                             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-shared",
+                             os.path.join(CSRC, "peaks.hip"), "-o", PEAKS_LIB], verbose)
     return LIB
 
 
-def build_emu(verbose=False):
-    """Sequential CPU emulator of the kernels (test infrastructure)."""
-    os.makedirs(os.path.dirname(EMU_LIB), exist_ok=True)
+EMU_SAN_LIB = os.path.join(ROOT, "tests", "emu", "_build", "libfenc_emu_san.so")
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+
+
+def build_emu(verbose=False, sanitize=False):
+    """CPU emulator of the kernels (test infrastructure); with sanitize, an
+    AddressSanitizer + UndefinedBehaviorSanitizer build (host code only)."""
+    out = EMU_SAN_LIB if sanitize else EMU_LIB
+    os.makedirs(os.path.dirname(out), exist_ok=True)
     srcs = [os.path.join(ROOT, "tests", "emu", "backend_cpu.cpp")] + [os.path.join(CSRC, s) for s in HOST_SOURCES]
-    _run(["g++"] + COMMON + ["-fopenmp", "-shared", "-I", CSRC, "-o", EMU_LIB] + srcs + ["-lpthread"], verbose)
-    return EMU_LIB
+    flags = ["g++"] + ([f for f in COMMON if f != "-O3"] + SANITIZE if sanitize else COMMON) + \
+        ["-Wno-unknown-pragmas", "-fopenmp", "-I", CSRC]
+    objs, procs = [], []
+    for src in srcs:   # one compiler per source, then the link
+        obj = out + "." + os.path.basename(src) + ".o"
+        objs.append(obj)
+        cmd = flags + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+    if any(p.wait() != 0 for p in procs):
+        raise RuntimeError("emulator build failed")
+    _run(flags + ["-shared", "-o", out] + objs + ["-lpthread"], verbose)
+    return out
 
 
 if __name__ == "__main__":
     v = "-v" in sys.argv
-    print(build_emu(v) if "--emu" in sys.argv else build_hip(v))
+    if "--emu-san" in sys.argv:
+        print(build_emu(v, sanitize=True))
+    else:
+        print(build_emu(v) if "--emu" in sys.argv else build_hip(v))

@@ -925,7 +925,7 @@ static void run_tensor(Ctx& C, int lvl, int n, const u64* a, const u64* b, const
     fk::SquareArgs sa{a + b0 * ce, b + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, k, C.pq};
     timed(C, "tensor_square", (a == b ? 5.0 : 7.0) * nb * nl * C.N * 8, s, [&] {
       fb::tensor_square({(unsigned)std::max(1, C.N / 256), (unsigned)nl, (unsigned)nb}, std::min(256, C.N), s, sa);
-    });
+    }, (a == b ? 3.0 : 4.0) * nb * nl * C.N);
     C.cnt.launches++;
   }
 }
@@ -941,7 +941,7 @@ static void run_lin(Ctx& C, int nl, int n, const u64* x, long long x_cs, long lo
                    nl, C.logn, k1, k0, C.pq};
     timed(C, "lin_comb", (base ? 6.0 : 4.0) * nb * nl * C.N * 8, s, [&] {
       fb::lin_comb({(unsigned)std::max(1, C.N / 256), (unsigned)(2 * nl), (unsigned)nb}, std::min(256, C.N), s, la);
-    });
+    }, 2.0 * nb * nl * C.N);
     C.cnt.launches++;
   }
 }
@@ -1430,18 +1430,19 @@ int fenc_profile_result(fenc_ctx* ctx, double* total_ms, int64_t* launches, doub
 int fenc_profile_summary(fenc_ctx* ctx, char* buf, int64_t len) {
   API_BEGIN
   if (!ctx || !buf || len < 1) fail(FENC_EINVAL, "null argument");
-  std::map<std::string, std::tuple<double, int64_t, double>> agg;
+  std::map<std::string, std::tuple<double, int64_t, double, double>> agg;
   for (auto& r : ctx->prof) {
     auto& e = agg[r.name];
     std::get<0>(e) += fb::event_elapsed_ms(r.a, r.b);
     std::get<1>(e) += 1;
     std::get<2>(e) += r.bytes;
+    std::get<3>(e) += r.ops;
   }
   std::ostringstream o;
   o.precision(17);
   for (auto& kv : agg)
     o << kv.first << ' ' << std::get<0>(kv.second) << ' ' << std::get<1>(kv.second) << ' ' << std::get<2>(kv.second)
-      << '\n';
+      << ' ' << std::get<3>(kv.second) << '\n';
   const std::string t = o.str();
   if ((int64_t)t.size() + 1 > len) fail(FENC_EINVAL, "summary buffer too small");
   std::memcpy(buf, t.c_str(), t.size() + 1);

@@ -267,6 +267,10 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
   for (int r = 0; r < std::min(nrows, pm.n); r++) active += (pm.p[r] != fk::kSkip);
   active = (int)((long long)active * nrows / std::max(1, std::min(nrows, pm.n)));
   const double pass_bytes = 16.0 * active * C.N;   // read + write of every active row
+  // modular products: one per butterfly (N/2 per stage and row); the inverse
+  // column pass also scales by 1/N, the ModDown and rescale tails multiply
+  // every output word by P^-1 or q_l^-1
+  const double ops_c = 0.5 * active * C.N * a.n1, ops_r = 0.5 * active * C.N * a.n2;
   const fb::Grid gc{colblocks, (unsigned)nrows, 1}, gr{rowblocks, (unsigned)nrows, 1};
   if (!inverse) {
     if (lift) {   // the column pass starts from the rescale lift
@@ -274,12 +278,12 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
       timed(C, "ntt_fwd_cols_lift", lift_bytes, s, [&] {
         if (fc[0] == 4) fb::ntt_fwd_cols16_lift(gc, fc[2], lds_c, s, m);
         else fb::ntt_fwd_cols_lift(gc, fc[2], lds_c, s, m);
-      });
+      }, ops_c);
     } else {
       timed(C, "ntt_fwd_cols", pass_bytes, s, [&] {
         if (fc[0] == 4) fb::ntt_fwd_cols16(gc, fc[2], lds_c, s, a);
         else fb::ntt_fwd_cols(gc, fc[2], lds_c, s, a);
-      });
+      }, ops_c);
     }
     a.src = dst;
     a.src_gs = dst_gs;
@@ -288,31 +292,31 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
       timed(C, "ntt_fwd_rows_md", md_bytes, s, [&] {
         if (fr[0] == 4) fb::ntt_fwd_rows16_md(gr, fr[2], lds_r, s, m);
         else fb::ntt_fwd_rows_md(gr, fr[2], lds_r, s, m);
-      });
+      }, ops_r + (double)active * C.N);
     } else if (rs) {   // the row pass ends in the rescale tail
       const fk::NttRsArgs m{a, *rs};
       timed(C, "ntt_fwd_rows_rs", md_bytes, s, [&] {
         if (fr[0] == 4) fb::ntt_fwd_rows16_rs(gr, fr[2], lds_r, s, m);
         else fb::ntt_fwd_rows_rs(gr, fr[2], lds_r, s, m);
-      });
+      }, ops_r + (double)active * C.N);
     } else {
       timed(C, "ntt_fwd_rows", pass_bytes, s, [&] {
         if (fr[0] == 4) fb::ntt_fwd_rows16(gr, fr[2], lds_r, s, a);
         else fb::ntt_fwd_rows(gr, fr[2], lds_r, s, a);
-      });
+      }, ops_r);
     }
     C.cnt.ntt_limbs += active;
   } else {
     timed(C, "ntt_inv_rows", pass_bytes, s, [&] {
       if (fr[0] == 4) fb::ntt_inv_rows16(gr, fr[2], lds_r, s, a);
       else fb::ntt_inv_rows(gr, fr[2], lds_r, s, a);
-    });
+    }, ops_r);
     a.src = dst;
     a.src_gs = dst_gs;
     timed(C, "ntt_inv_cols", pass_bytes, s, [&] {
       if (fc[0] == 4) fb::ntt_inv_cols16(gc, fc[2], lds_c, s, a);
       else fb::ntt_inv_cols(gc, fc[2], lds_c, s, a);
-    });
+    }, ops_c + (double)active * C.N);
     C.cnt.intt_limbs += active;
   }
   C.cnt.launches += 2;
@@ -471,10 +475,15 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
     ntt(C, true, in + ps + b0 * cs, coef + (long long)b0 * nl * N, cs, (long long)nl * N, nb * nl, nl,
         identity_map(nl), s);
     a.b0 = b0;
-    double mb = 0;
-    for (int j = 0; j < beta; j++) mb += (2.0 * (std::min((j + 1) * C.alpha, nl) - j * C.alpha) + le) * N * 8.0;
+    double mb = 0, mo = 0;
+    for (int j = 0; j < beta; j++) {
+      const int aj = std::min((j + 1) * C.alpha, nl) - j * C.alpha;
+      mb += (2.0 * aj + le) * N * 8.0;
+      mo += (double)aj * (1 + (le - aj)) * N;   // y_i, then one product per (source, target) limb
+    }
     timed(C, "modup_fbc", mb * nb, s,
-          [&] { fb::modup_fbc({(unsigned)(N / block_threads(C)), (unsigned)(nb * beta), 1}, block_threads(C), s, a); });
+          [&] { fb::modup_fbc({(unsigned)(N / block_threads(C)), (unsigned)(nb * beta), 1}, block_threads(C), s, a); },
+          mo * nb);
     ntt(C, false, ext + (long long)b0 * beta * le * N, ext + (long long)b0 * beta * le * N, (long long)le * N,
         (long long)le * N, nb * beta * le, le, pmd, s);
     C.cnt.launches += 1;
@@ -497,7 +506,7 @@ static void moddown_part(Ctx& C, int level, u64* acc, u64* conv, const KsStage& 
   fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.epq, C.md_tab};
   timed(C, "moddown_fbc", 2.0 * no * (C.K + nl) * N * 8, s, [&] {
     fb::moddown_fbc({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, m);
-  });
+  }, 2.0 * no * C.K * (1.0 + nl) * N);
   u64* conv0 = conv + (long long)o0 * 2 * nl * N;
   fk::TailArgs t;
   t.acc = acc;
@@ -542,14 +551,17 @@ static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int
     k.c0_cs = c0_cs;
     k.pmod = T.pmod;
   }
-  double kb = 0;
-  for (int g = g0; g < g0 + ng; g++) kb += KT.rd[g] * beta + KT.wr[g];
+  double kb = 0, ko = 0;
+  for (int g = g0; g < g0 + ng; g++) {
+    kb += KT.rd[g] * beta + KT.wr[g];
+    ko += KT.wr[g] * beta;   // each output word: one product per digit
+  }
   kb *= (double)le * N * 8;
   timed(C, "kip", kb, s,
         [&] {   // a thread per coefficient pair
           const int kt = std::min(256, N / 2);
           fb::kip({(unsigned)(N / 2 / kt), (unsigned)le, (unsigned)ng}, kt, s, k);
-        });
+        }, ko * le * N);
   C.cnt.launches += 1;
 }
 
@@ -691,7 +703,7 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
       a.width = sg.width;
       a.chunk = sg.chunk;
       const int nc = per_op ? 1 : sg.n;
-      const double gb = sg.words / sg.n * nc * nl * C.N * 8;
+      const double gb = sg.words / sg.n * nc * nl * C.N * 8, go = sg.mm / sg.n * nc * nl * C.N;
       const fb::Grid grid{(unsigned)(C.N / block_threads(C)), (unsigned)nl, (unsigned)(2 * nc)};
       static const char* const names[2][3] = {{"gmac", "gmac_pt", "gmac_ptv"},
                                                 {"gmac_fast", "gmac_pt_fast", "gmac_ptv_fast"}};
@@ -700,7 +712,7 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
                                           {fb::gmac_fast, fb::gmac_pt_fast, fb::gmac_ptv_fast}};
       const char* name = sg.diag ? "gmac_diag" : sg.one ? "gmac_one" : names[sg.fast][sg.ptm];
       const Launch fn = sg.diag ? fb::gmac_diag : sg.one ? fb::gmac_one : launch[sg.fast][sg.ptm];
-      timed(C, name, gb, s, [&] { fn(grid, block_threads(C), s, a); });
+      timed(C, name, gb, s, [&] { fn(grid, block_threads(C), s, a); }, go);
       C.cnt.launches += 1;
     }
   }
@@ -880,7 +892,7 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
     const int ptm = diag ? (int)fk::kPtEach : ptm_of(mem), chunk = chunk_of(mem);
     if (T.seg.empty() || T.seg.back().width != W || T.seg.back().ptm != ptm || T.seg.back().diag != diag ||
         T.seg.back().one != one || T.seg.back().fast != fast || T.seg.back().chunk != chunk)
-      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, ptm, diag, one, fast, chunk, 0.0});
+      T.seg.push_back(MacSeg{(int)cls.size(), 0, W, ptm, diag, one, fast, chunk, 0.0, 0.0});
     for (int r = 0; r < b.toff[b.goff[rep + 1]] - b.toff[b.goff[rep]]; r++)
       for (int o = 0; o < W; o++) wfast.push_back(fast);
     MacSeg& sg = T.seg.back();
@@ -900,6 +912,7 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
         tin.push_back(b.tin[k]);
         sg.words += 2.0;   // input read (both polys)
       }
+      if (!diag) sg.mm += 2.0 * no * (b.toff[g + 1] - b.toff[g]);   // a weight product per term and output
       toff.push_back((int)tin.size());
       ngroups++;
       const uint64_t* prev = nullptr;
@@ -907,6 +920,7 @@ static MacTables make_mac_tables(Ctx& C, const GmacBuild& b, const std::vector<i
         const uint64_t* m = o < no ? b.mask[b.goff[mem[o]] + gr] : nullptr;
         mask.push_back(m);
         if (m && m != prev) sg.words += 1.0;   // plaintext read (one poly)
+        if (m) sg.mm += 2.0;                    // a plaintext product per (group, output)
         if (m) prev = m;
       }
     }

@@ -114,6 +114,7 @@ struct MacSeg {
   bool fast;                       // every weight code below 2^23 in magnitude
   int chunk;                       // terms per chunk: 8, or 4 for groups of under 6 terms on average
   double words;                    // words per (coefficient, limb) moved by the segment's classes
+  double mm;                       // modular products per (coefficient, limb) of the segment's classes
 };
 struct MacTables {
   int n = 0;                       // classes
@@ -199,6 +200,7 @@ struct fenc_ctx {
   struct ProfRec {
     void *a, *b;
     double bytes;
+    double ops;         // algorithmic modular products of the launch(es)
     const char* name;   // kernel name (a string literal)
   };
   std::vector<ProfRec> prof;
@@ -281,10 +283,11 @@ void split_scale(double T, double& dw, double& dm);
 inline long long ct_elems(const Ctx& C, int level) { return 2LL * (level + 1) * C.N; }
 
 // Times the launch(es) issued by `launch` when `name` is the profiled kernel;
-// `bytes` is the algorithmic HBM traffic of those launches.
+// `bytes` is the algorithmic HBM traffic of those launches and `ops` their
+// algorithmic modular products (0 where not counted).
 // With the profiled name "*" every kernel's launches are timed.
 template <class F>
-void timed(Ctx& C, const char* name, double bytes, fb::Stream s, F launch) {
+void timed(Ctx& C, const char* name, double bytes, fb::Stream s, F launch, double ops = 0) {
   if (C.prof_kernel.empty() || (C.prof_kernel != "*" && C.prof_kernel != name) || fb::capturing(s)) {
     launch();
     return;
@@ -294,7 +297,7 @@ void timed(Ctx& C, const char* name, double bytes, fb::Stream s, F launch) {
   fb::event_record(a, s);
   launch();
   fb::event_record(b, s);
-  C.prof.push_back({a, b, bytes, name});
+  C.prof.push_back({a, b, bytes, ops, name});
 }
 
 }  // namespace fr

@@ -243,13 +243,13 @@ class Fenc:
         self._check(self.lib.fenc_profile_kernel(self.h, name.encode() if name else None))
 
     def profile_summary(self):
-        """Per-kernel {name: (total_ms, launches, bytes)} after profile_kernel("*")."""
+        """Per-kernel {name: (total_ms, launches, bytes, modmuls)} after profile_kernel("*")."""
         buf = C.create_string_buffer(1 << 16)
         self._check(self.lib.fenc_profile_summary(self.h, buf, len(buf)))
         out = {}
         for line in buf.value.decode().splitlines():
-            name, ms, n, b = line.split()
-            out[name] = (float(ms), int(n), float(b))
+            name, ms, n, b, o = line.split()
+            out[name] = (float(ms), int(n), float(b), float(o))
         return out
 
     def profile_result(self):

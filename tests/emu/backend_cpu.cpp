@@ -96,9 +96,11 @@ EMU(small_to_rns, SmallArgs)
 EMU(perm_rows, PermArgs)
 
 namespace fb {
+// exact-size allocations, so that an address-sanitizer build of the emulator
+// reports any read or write past the end of a buffer
 void* dev_alloc(size_t bytes) {
-  void* p = std::aligned_alloc(256, ((bytes ? bytes : 256) + 255) / 256 * 256);
-  if (!p) throw std::runtime_error("emulator: out of memory");
+  void* p = nullptr;
+  if (posix_memalign(&p, 256, bytes ? bytes : 1) != 0 || !p) throw std::runtime_error("emulator: out of memory");
   std::memset(p, 0xA5, bytes);   // poison: kernels must not read unwritten memory
   return p;
 }

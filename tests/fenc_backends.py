@@ -19,6 +19,8 @@ _built_emu = False
 def lib_path(backend):
     global _built_emu
     if backend == "emu":
+        if os.environ.get("FENC_EMU_LIB"):   # a prebuilt emulator (the sanitizer build)
+            return os.environ["FENC_EMU_LIB"]
         if not _built_emu and not os.environ.get("FENC_SKIP_EMU_BUILD"):
             B.build_emu()
             _built_emu = True
