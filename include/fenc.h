@@ -339,8 +339,18 @@ int fenc_ntt_rows(fenc_ctx* ctx, uint64_t* rows, const int32_t* prime, uint32_t 
  * enter as P x, and each combined ciphertext is moved down once.  Mode 0:
  * every rotated copy is moved down.  The two modes round differently, so the
  * residues differ; each matches the oracle's schedule of the same number.
- * Errors: EINVAL for other modes. */
+ * Mode 2: each layer's plan takes the schedule whose modelled HBM traffic is
+ * smaller (schedule 0 pays a ModDown per rotated copy over nl limbs; schedule
+ * 1 combines over nl + K limbs, lifts the unrotated inputs and pays a ModDown
+ * per combined ciphertext); the choice is a function of the layer's shape
+ * and weights' sparsity pattern, kept in its cached plan, the same on every
+ * device.  Errors: EINVAL for other modes. */
 int fenc_set_hoisting(fenc_ctx* ctx, int mode);
+/* The schedule (0 or 1) the most recent fenc_conv2d, fenc_avgpool2 or
+ * fenc_compress on this context ran with (0 where the layer has no rotated
+ * copies), -1 before any; with mode 2 this is how a caller learns, and can
+ * reproduce elsewhere, the schedule a layer's plan chose. */
+int fenc_last_hoisting(const fenc_ctx* ctx);
 /* NTT pass shapes, 8 ints: for [forward columns, forward rows, inverse rows,
  * inverse columns] the radix bits of a register round (3: radix 8, 4: radix
  * 16) and the log2 of the columns (column pass) or chunks (row pass) a block

@@ -12,10 +12,10 @@ OUT = os.path.join(HERE, "_build", "liborc.so")
 SAN_OUT = os.path.join(HERE, "_build", "liborc_san.so")
 
 
-def build(verbose=False, sanitize=False):
+def build(verbose=False, sanitize=False, out=None):
     """liborc.so; with sanitize, liborc_san.so under AddressSanitizer and
     UndefinedBehaviorSanitizer."""
-    out = SAN_OUT if sanitize else OUT
+    out = out or (SAN_OUT if sanitize else OUT)
     os.makedirs(os.path.dirname(out), exist_ok=True)
     opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]

@@ -58,10 +58,10 @@ EMU_SAN_LIB = os.path.join(ROOT, "tests", "emu", "_build", "libfenc_emu_san.so")
 SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 
-def build_emu(verbose=False, sanitize=False):
+def build_emu(verbose=False, sanitize=False, out=None):
     """CPU emulator of the kernels (test infrastructure); with sanitize, an
     AddressSanitizer + UndefinedBehaviorSanitizer build (host code only)."""
-    out = EMU_SAN_LIB if sanitize else EMU_LIB
+    out = out or (EMU_SAN_LIB if sanitize else EMU_LIB)
     os.makedirs(os.path.dirname(out), exist_ok=True)
     srcs = [os.path.join(ROOT, "tests", "emu", "backend_cpu.cpp")] + [os.path.join(CSRC, s) for s in HOST_SOURCES]
     flags = ["g++"] + ([f for f in COMMON if f != "-O3"] + SANITIZE if sanitize else COMMON) + \

@@ -404,7 +404,8 @@ struct ConvPlan : Plan {
 // tensor with block size s_out (Arch-aware Ct Compression fused with the
 // convolution, see below); bias: cout values added at the output scale.
 static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout, int k, int stride, int pad,
-                            int groups, int s_out, const double* bias, bool shape_only, Layout& Lout) {
+                            int groups, int s_out, const double* bias, bool shape_only, Layout& Lout,
+                            bool pq = false) {
   if (Lin.kind != FENC_LAYOUT_FRAGMENT || Lin.dil != 1) fail(FENC_ELAYOUT, "conv2d needs a dense fragment layout");
   if (k < 1 || stride < 1 || pad < 0 || cout < 1) fail(FENC_EINVAL, "bad convolution shape");
   if (Lin.S % stride) fail(FENC_EUNSUPPORTED, "stride must divide the block size");
@@ -433,7 +434,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   P->out = Lout;
   P->level = lvl;
   P->n_in = Lin.n_ct();
-  P->pq = C.hoist != 0;
+  P->pq = pq;
   const int nd = Lin.rep ? cin : cpc;
   // masks per channel position when a ciphertext holds several positions or the
   // kernel reads padding; T is always split into a weight scale dw and a
@@ -801,7 +802,7 @@ struct PoolPlan : Plan {
   KsStage md;
 };
 
-static PoolPlan* build_pool(Ctx& C, const Layout& Lin, bool shape_only, Layout& Lout) {
+static PoolPlan* build_pool(Ctx& C, const Layout& Lin, bool shape_only, Layout& Lout, bool pq = false) {
   if (Lin.kind != FENC_LAYOUT_FRAGMENT) fail(FENC_ELAYOUT, "avgpool needs a fragment layout");
   Lout = Lin;
   Lout.h = Lin.h / 2;
@@ -840,7 +841,7 @@ static PoolPlan* build_pool(Ctx& C, const Layout& Lin, bool shape_only, Layout& 
     std::vector<std::pair<int, long long>> copies;
     for (int i = 0; i < 3; i++)
       for (int t = 0; t < P->n_in; t++) copies.push_back({t, sh[i] % C.ns});
-    P->pq = C.hoist != 0;
+    P->pq = pq;
     P->rot = make_rot_stage(C, copies, P->owned, P->pq);
     for (int t = 0; t < P->n_in; t++) {
       gb.add_group(nullptr);
@@ -1052,7 +1053,8 @@ static Layout vector_target(const Ctx& C, const Layout& Lin) {
 // is masked to the slots that move with that shift, and the masked copies of
 // a target ciphertext are summed (in Q_l U P with one ModDown per target
 // under hoisting schedule 1).  Masks at q_l Delta / s_in: one rescale, one level.
-static CompressPlan* build_compress(Ctx& C, const Layout& Lin, const Layout* target, bool shape_only, Layout& Lout) {
+static CompressPlan* build_compress(Ctx& C, const Layout& Lin, const Layout* target, bool shape_only, Layout& Lout,
+                                    bool pq = false) {
   if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the compression mask");
   Lout = target ? target_layout(C, *target, Lin.bs, Lin.c, Lin.h, Lin.w) : vector_target(C, Lin);
   Lout.level = Lin.level - 1;
@@ -1077,7 +1079,7 @@ static CompressPlan* build_compress(Ctx& C, const Layout& Lin, const Layout* tar
       copies.push_back({kv.second, kv.first});
     }
   }
-  P->pq = C.hoist != 0 && !copies.empty();
+  P->pq = pq && !copies.empty();
   P->rot = make_rot_stage(C, copies, P->owned, P->pq);
   const double dm = ((double)C.primes[Lin.level] * C.Delta) / Lin.scale;
   PtSet ps;
@@ -1298,6 +1300,42 @@ static double conv_ws_bytes(const Ctx& C, int level, bool pq, int n_src, int n_c
 }
 
 // ---------------------------------------------------------------- plan cache
+// Modelled HBM traffic, in units of N words, of what the two hoisting
+// schedules do differently in a layer with n_rot hoisted rotations.
+// Schedule 0 moves every rotated copy down (inverse NTT of the 2K special
+// limbs, base conversion, NTT of 2 nl limbs with the tail: about 10K + 14 nl)
+// and combines over the nl limbs of Q_l.  Schedule 1 keeps the copies in
+// Q_l U P, lifts the n_lift unrotated inputs, combines over nl + K limbs and
+// moves the n_md combined ciphertexts down.  mac_words: words per
+// (coefficient, limb) the combination moves.  Everything the schedules share
+// (ModUp, key reads, outer rotations, rescale) is left out.
+static double hoist_traffic(const Ctx& C, int level, bool pq, int n_rot, int n_md, int n_lift, double mac_words) {
+  const double nl = level + 1, K = C.K, le = nl + K, md = 10 * K + 14 * nl;
+  if (!pq) return n_rot * (2 * le + md) + mac_words * nl;
+  return n_rot * 2 * le + n_lift * 2 * (nl + le) + mac_words * le + n_md * md;
+}
+
+static double mac_words(const GmacStage& g) {
+  double w = 0;
+  for (const MacSeg& sg : g.batched.seg) w += sg.words;
+  return w;
+}
+
+// A hoisted layer's plan under the context's mode: 0 or 1 as set; 2 builds
+// the schedule-0 plan, models both schedules on it (cost returns their
+// traffic) and rebuilds under schedule 1 when that moves fewer words.  The
+// schedule is kept in the plan (it changes residues).
+template <class T, class B, class Cost>
+static T* build_hoisted(Ctx& C, B build, Cost cost) {
+  if (C.hoist != 2) return build(C.hoist == 1);
+  T* p0 = build(false);
+  const std::pair<double, double> c = cost(*p0);
+  if (!(c.second < c.first)) return p0;
+  dfree_all(C, p0->owned);
+  delete p0;
+  return build(true);
+}
+
 template <class T, class F>
 static T& cached(Ctx& C, const std::string& key, F build) {
   auto it = C.plans.find(key);
@@ -1807,8 +1845,17 @@ int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const do
     key << "conv|" << layout_key(Ls) << '|' << cout << ',' << k << ',' << stride << ',' << pad << ',' << groups << ','
         << wh << ',' << bh << ',' << s_out << ',' << C.pt_budget << ',' << C.hoist;
     return cached<ConvPlan>(C, key.str(), [&] {
-      Layout lo;
-      return build_conv(C, Ls, w, cout, k, stride, pad, groups, s_out, bias, false, lo);
+      return build_hoisted<ConvPlan>(
+          C,
+          [&](bool pq) {
+            Layout lo;
+            return build_conv(C, Ls, w, cout, k, stride, pad, groups, s_out, bias, false, lo, pq);
+          },
+          [&](const ConvPlan& P) {
+            const double mw = mac_words(P.g0) + mac_words(P.gr);
+            return std::make_pair(hoist_traffic(C, P.level, false, P.rot.n, 0, 0, mw),
+                                  hoist_traffic(C, P.level, true, P.rot.n, P.n_out + P.n_zr, P.n_in, mw));
+          });
     });
   };
   // a fused repack into another batch grouping cannot be split by groups
@@ -1824,6 +1871,7 @@ int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const do
   for (int b0 = 0; b0 < Lin.nbg; b0 += tile) {
     const ConvPlan& P = plan_of(std::min(tile, Lin.nbg - b0));
     run_conv(C, P, in->data + b0 * in_step, out->data + b0 * out_step, (fb::Stream)stream);
+    C.last_hoist = P.pq;
   }
   API_END
 }
@@ -1841,9 +1889,18 @@ int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void
   ensure_device(C);
   auto plan_of = [&](int cnt) -> PoolPlan& {
     const Layout Ls = sub_layout(Lin, cnt);
-    return cached<PoolPlan>(C, "pool|" + layout_key(Ls) + (C.hoist ? "|h" : ""), [&] {
-      Layout lo;
-      return build_pool(C, Ls, false, lo);
+    return cached<PoolPlan>(C, "pool|" + layout_key(Ls) + "|h" + std::to_string(C.hoist), [&] {
+      return build_hoisted<PoolPlan>(
+          C,
+          [&](bool pq) {
+            Layout lo;
+            return build_pool(C, Ls, false, lo, pq);
+          },
+          [&](const PoolPlan& P) {
+            const double mw = mac_words(P.g);
+            return std::make_pair(hoist_traffic(C, P.level, false, P.rot.n, 0, 0, mw),
+                                  hoist_traffic(C, P.level, true, P.rot.n, P.n_out, P.n_in, mw));
+          });
     });
   };
   int tile = Lin.nbg;
@@ -1857,6 +1914,7 @@ int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void
   for (int b0 = 0; b0 < Lin.nbg; b0 += tile) {
     const PoolPlan& P = plan_of(std::min(tile, Lin.nbg - b0));
     run_pool(C, P, in->data + b0 * in_step, out->data + b0 * out_step, (fb::Stream)stream);
+    C.last_hoist = P.pq;
   }
   API_END
 }
@@ -1971,10 +2029,18 @@ int fenc_compress(fenc_ctx* ctx, const fenc_ctbatch* in, const fenc_layout* targ
   if (!out->data) return FENC_OK;
   check_batch(C, in, true);
   ensure_device(C);
-  CompressPlan& P = cached<CompressPlan>(C, "aac|" + layout_key(Lin) + "|" + (target ? layout_key(Lt) : "") +
-                                                (C.hoist ? "|h" : ""),
-                                         [&] { return build_compress(C, Lin, target ? &Lt : nullptr, false, Lout); });
+  CompressPlan& P = cached<CompressPlan>(
+      C, "aac|" + layout_key(Lin) + "|" + (target ? layout_key(Lt) : "") + "|h" + std::to_string(C.hoist), [&] {
+        return build_hoisted<CompressPlan>(
+            C, [&](bool pq) { return build_compress(C, Lin, target ? &Lt : nullptr, false, Lout, pq); },
+            [&](const CompressPlan& P) {
+              const double mw = mac_words(P.g);
+              return std::make_pair(hoist_traffic(C, P.level, false, P.rot.n, 0, 0, mw),
+                                    hoist_traffic(C, P.level, true, P.rot.n, P.n_out, P.n_in, mw));
+            });
+      });
   run_compress(C, P, in->data, out->data, (fb::Stream)stream);
+  C.last_hoist = P.pq;
   API_END
 }
 
@@ -2108,10 +2174,12 @@ int fenc_rescale_noalloc(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* ou
 
 int fenc_set_hoisting(fenc_ctx* ctx, int mode) {
   API_BEGIN
-  if (!ctx || (mode != 0 && mode != 1)) fail(FENC_EINVAL, "hoisting mode must be 0 or 1");
+  if (!ctx || mode < 0 || mode > 2) fail(FENC_EINVAL, "hoisting mode must be 0, 1 or 2");
   ctx->hoist = mode;
   API_END
 }
+
+int fenc_last_hoisting(const fenc_ctx* ctx) { return ctx ? ctx->last_hoist : -1; }
 
 int fenc_ntt_config(fenc_ctx* ctx, int32_t* out) {
   API_BEGIN

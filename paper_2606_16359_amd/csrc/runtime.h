@@ -194,7 +194,8 @@ struct fenc_ctx {
   // hoisting schedule of convolutions and S = 1 pooling: 1 = linear
   // combinations of rotated copies in the extended basis with one ModDown per
   // combined ciphertext, 0 = one ModDown per rotated copy
-  int hoist = 1;
+  int hoist = 1;        // hoisting schedule: 0, 1, or 2 (per layer, the smaller modelled traffic)
+  int last_hoist = -1;  // schedule of the most recent convolution, pooling or compression
   // single-kernel profiling: events around every launch of `prof_kernel`
   std::string prof_kernel;
   struct ProfRec {

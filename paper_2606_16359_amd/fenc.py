@@ -122,6 +122,7 @@ def load(path=None):
         "fenc_ntt_rows": (C.c_int, [vp, vp, vp, u32, C.c_int]),
         "fenc_ntt_config": (C.c_int, [vp, vp]),
         "fenc_set_hoisting": (C.c_int, [vp, C.c_int]),
+        "fenc_last_hoisting": (C.c_int, [vp]),
         "fenc_set_ntt_config": (C.c_int, [vp, vp]),
         "fenc_sample_word": (u64, [u64, u64, u64]),
         "fenc_sample_gauss": (C.c_int, [u64, u64, u64]),
@@ -215,9 +216,15 @@ class Fenc:
 
     def set_hoisting(self, mode):
         """1: linear combinations of rotated copies in the extended basis (one
-        ModDown per combined ciphertext); 0: one ModDown per rotated copy."""
+        ModDown per combined ciphertext); 0: one ModDown per rotated copy;
+        2: per layer, the schedule with the smaller modelled HBM traffic
+        (last_hoisting() tells which one a layer ran with)."""
         self._check(self.lib.fenc_set_hoisting(self.h, mode))
         self.hoist = mode
+
+    def last_hoisting(self):
+        """Schedule (0/1) of the most recent conv2d / avgpool2 / compress."""
+        return self.lib.fenc_last_hoisting(self.h)
 
     def ntt_config(self):
         out = np.zeros(8, np.int32)

@@ -19,6 +19,10 @@ PARAMS = {
 
 SEED_INPUT, SEED_WEIGHTS, SEED_ENC = 1, 2, 4
 
+# hoisting mode of the benchmark configurations: 2, each layer's plan takes
+# the schedule with the smaller modelled HBM traffic
+BENCH_HOISTING = 2
+
 
 def images(shape, seed=SEED_INPUT):
     return np.random.default_rng(seed).uniform(0.0, 1.0, shape)

@@ -304,10 +304,11 @@ def test_keyswitch_with_digits_and_special_primes_above_eight(backend):
 @pytest.mark.parametrize("backend", BACKENDS)
 @pytest.mark.parametrize("mode,budget,hoist", [(F.FENC_MODE_BATCHED, 1 << 30, 1), (F.FENC_MODE_PER_OP, 1 << 30, 1),
                                                (F.FENC_MODE_BATCHED, 0, 1), (F.FENC_MODE_BATCHED, 1 << 30, 0),
-                                               (F.FENC_MODE_PER_OP, 0, 0)])
+                                               (F.FENC_MODE_PER_OP, 0, 0), (F.FENC_MODE_BATCHED, 1 << 30, 2)])
 def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
     """Two conv/x^2/pool blocks, compression and two FC layers at N = 2^10, in
-    both hoisting schedules."""
+    both hoisting schedules and in the per-layer choice (mode 2: the oracle
+    runs each layer in the schedule the library reports it chose)."""
     o, f = orc, make(backend, *SMALL)
     f.set_mode(mode)
     f.set_plaintext_budget(budget)
@@ -322,18 +323,25 @@ def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
     assert np.array_equal(pt, o.encode_tensor(Lo, x))
     ob, fb = o.encrypt_tensor(Lo, x, 3), f.encrypt(pt, lay, 3)
     cmp(fb, ob, f)
-    steps = [("conv", lambda c: f.conv2d(c, w1), lambda b: o.conv2d(b, w1, pt_budget=budget, hoist=hoist)[0]),
-             ("square", f.poly_act, lambda b: o.square(b)[0]),
-             ("pool-fragments", f.avgpool2, lambda b: o.avgpool2(b, hoist)[0]),
-             ("conv", lambda c: f.conv2d(c, w2), lambda b: o.conv2d(b, w2, pt_budget=budget, hoist=hoist)[0]),
-             ("square", f.poly_act, lambda b: o.square(b)[0]),
-             ("pool-rotations", f.avgpool2, lambda b: o.avgpool2(b, hoist)[0]),
-             ("compress", f.compress, lambda b: o.compress(b, hoist=f.hoist)[0]),
-             ("fc", lambda c: f.fc(c, f1), lambda b: o.fc(b, f1)[0]),
-             ("fc", lambda c: f.fc(c, f2), lambda b: o.fc(b, f2)[0])]
+    # h: the schedule the library's layer ran with
+    steps = [("conv", lambda c: f.conv2d(c, w1), lambda b, h: o.conv2d(b, w1, pt_budget=budget, hoist=h)[0]),
+             ("square", f.poly_act, lambda b, h: o.square(b)[0]),
+             ("pool-fragments", f.avgpool2, lambda b, h: o.avgpool2(b, h)[0]),
+             ("conv", lambda c: f.conv2d(c, w2), lambda b, h: o.conv2d(b, w2, pt_budget=budget, hoist=h)[0]),
+             ("square", f.poly_act, lambda b, h: o.square(b)[0]),
+             ("pool-rotations", f.avgpool2, lambda b, h: o.avgpool2(b, h)[0]),
+             ("compress", f.compress, lambda b, h: o.compress(b, hoist=h)[0]),
+             ("fc", lambda c: f.fc(c, f1), lambda b, h: o.fc(b, f1)[0]),
+             ("fc", lambda c: f.fc(c, f2), lambda b, h: o.fc(b, f2)[0])]
+    chosen = []
     for name, fl, ol in steps:
-        fb, ob = fl(fb), ol(ob)
+        fb = fl(fb)
+        h = f.last_hoisting() if hoist == 2 else hoist
+        chosen.append(h)
+        ob = ol(ob, h)
         cmp(fb, ob, f)
+    if hoist != 2:
+        assert f.last_hoisting() == hoist   # the compression has rotated copies
     ref = cnn_ref.fc(cnn_ref.fc(cnn_ref.avgpool2(cnn_ref.square(cnn_ref.conv2d(
         cnn_ref.avgpool2(cnn_ref.square(cnn_ref.conv2d(x, w1))), w2))), f1), f2)
     assert np.max(np.abs(f.decrypt(fb) - ref)) < 1e-4
@@ -350,7 +358,7 @@ def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
     dict(x=(2, 4, 8, 8), w=(6, 4, 1, 1), stride=1, pad=0, groups=1, S=1),    # pointwise: outer rotations only
     dict(x=(2, 4, 8, 8), w=(4, 1, 3, 3), stride=2, pad=1, groups=4, S=2),    # depthwise with stride
 ])
-@pytest.mark.parametrize("hoist", [1, 0])
+@pytest.mark.parametrize("hoist", [1, 0, 2])
 def test_conv_variants_bit_exact(backend, budget, case, hoist, orc):
     o, f = orc, make(backend, *SMALL)
     f.set_plaintext_budget(budget)
@@ -360,9 +368,11 @@ def test_conv_variants_bit_exact(backend, budget, case, hoist, orc):
     Lo = o.fragment_layout(*case["x"], case["S"])
     lay = f.plan_layout(*case["x"], case["w"][2], case["w"][0], case["S"])
     ob, fb = o.encrypt_tensor(Lo, x, 5), f.encrypt(f.encode_fragment(x, lay), lay, 5)
-    yo, cnt = o.conv2d(ob, w, case["stride"], case["pad"], case["groups"], pt_budget=budget, hoist=hoist)
     f.stats_reset()
     yf = f.conv2d(fb, w, case["stride"], case["pad"], case["groups"])
+    h = f.last_hoisting()
+    assert h in (0, 1) and (hoist == 2 or h == hoist or (h == 0 and f.stats()["rot_inner"] == 0))
+    yo, cnt = o.conv2d(ob, w, case["stride"], case["pad"], case["groups"], pt_budget=budget, hoist=h)
     cmp(yf, yo, f)
     st = f.stats()
     assert (st["rot_inner"], st["rot_outer"], st["moddown"]) == (cnt["inner_rot"], cnt["outer_rot"], cnt["moddown"])

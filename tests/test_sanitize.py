@@ -51,8 +51,11 @@ def test_parity_subset_under_address_and_undefined_behaviour_sanitizers(tmp_path
         except Exception as e:   # reported below
             errs.append(f"{key}: {e}")
 
-    ts = [threading.Thread(target=job, args=("emu", lambda: B.build_emu(sanitize=True))),
-          threading.Thread(target=job, args=("orc", lambda: OB.build(sanitize=True)))]
+    # built outside the tree: nothing else loads them
+    ts = [threading.Thread(target=job, args=("emu", lambda: B.build_emu(sanitize=True,
+                                                                         out=str(tmp_path / "libfenc_emu_san.so")))),
+          threading.Thread(target=job, args=("orc", lambda: OB.build(sanitize=True,
+                                                                     out=str(tmp_path / "liborc_san.so"))))]
     for t in ts:
         t.start()
     for t in ts:
@@ -72,6 +75,7 @@ def test_parity_subset_under_address_and_undefined_behaviour_sanitizers(tmp_path
                         "-m", "not gpu", "-x", "-q", "-p", "no:cacheprovider", "-k", SUBSET],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=1500)
     print(r.stdout[-2000:])
-    reports = "".join(open(tmp_path / f).read()[:6000] for f in sorted(os.listdir(tmp_path)) if f.startswith("san"))
+    reports = "".join(open(tmp_path / f).read()[:6000] for f in sorted(os.listdir(tmp_path))
+                      if f.startswith("san."))
     assert r.returncode == 0 and not reports, (r.stdout[-3000:] + "\n" + r.stderr[-4000:] + "\n" + reports)
     assert " passed" in r.stdout and " failed" not in r.stdout
