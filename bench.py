@@ -191,7 +191,7 @@ def run_lenet(args):
     fe = F.Fenc(*W.PARAMS["lenet"])
     fe.set_hoisting(W.BENCH_HOISTING)
     x, w = W.lenet_inputs(64)
-    lay = fe.plan_layout(64, 1, 28, 28, 5, 6)
+    lay = W.lenet_layout(fe, 64)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
     r = measure(fe, lambda: [W.lenet_forward(fe, ct, w)], 64, max(10, args.steps), 2, 2, "lenet")
     r["workload"] = ("LeNet-5-shaped network, 64 images 28x28, N=2^15, 20 x 50-bit + 7 special, dnum 3, "
@@ -276,8 +276,9 @@ def counters_run(args):
     else:
         from paper_2606_16359_amd import fenc as F
         fe = F.Fenc(*W.PARAMS["lenet"])
+        fe.set_hoisting(W.BENCH_HOISTING)
         x, w = W.lenet_inputs(64)
-        lay = fe.plan_layout(64, 1, 28, 28, 5, 6)
+        lay = W.lenet_layout(fe, 64)
         ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
 
         def step():
@@ -329,7 +330,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3,
+                    help="untimed steps (the first builds plans and keys; the workspace settles by the third)")
     ap.add_argument("--per-op-steps", type=int, default=1)
     ap.add_argument("--batch", type=int, default=MOBILENET_BATCH, help="MobileNet images per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -341,7 +343,7 @@ def main():
     ap.add_argument("--peaks", action="store_true",
                     help="measure instruction, modular-multiply and HBM peaks of the device and exit")
     ap.add_argument("--trace", action="store_true",
-                    help="run for a kernel trace: one warm-up step, then --steps batched eager steps of the "
+                    help="run for a kernel trace: three warm-up steps, then --steps batched eager steps of the "
                          "headline workload and nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -360,11 +362,11 @@ def main():
         from paper_2606_16359_amd import workloads as W
         fe, cts, ws = mobilenet_context(args.batch)
         out = None
-        for i in range(1 + args.steps):
+        for i in range(3 + args.steps):
             out = None
             out = W.mobilenet_forward(fe, cts, ws)
             torch.cuda.synchronize()
-        print(json.dumps({"trace_run": True, "batched_steps": args.steps, "warmup_steps": 1}), flush=True)
+        print(json.dumps({"trace_run": True, "batched_steps": args.steps, "warmup_steps": 3}), flush=True)
         return
 
     extras = {}

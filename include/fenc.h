@@ -199,6 +199,50 @@ int fenc_key_import(fenc_ctx* ctx, uint64_t g, const uint64_t* in);
  * S.  Host only. */
 int fenc_plan_layout(const fenc_ctx* ctx, uint32_t bs, uint32_t c, uint32_t h, uint32_t w,
                      uint32_t k_next, uint32_t cout_next, int32_t s_override, fenc_layout* out);
+/* Block size per layer of a layer chain (the paper adapts S between layers
+ * with HEAR-style rot-mask-add, Evaluation Methodology; eq. total-rot prices
+ * one layer).  layers[i].kind: FENC_LAYER_CONV (cout, k, stride, pad, groups),
+ * FENC_LAYER_POOL (2x2 average), FENC_LAYER_ACT (polynomial, no layout
+ * change) or FENC_LAYER_COMPRESS (into the FC vector layout).  A dynamic
+ * program over the layout after each layer chooses the input block size and,
+ * before up to max_repacks convolutions whose input has at most 2^22
+ * elements, a repack into a fragment layout of another block size
+ * (fenc_compress with that target, one level each),
+ * minimising key switches + MAC terms / 16: each convolution's exact key
+ * switches and scalar MAC terms (as fenc_conv2d_keyswitches), each repack's
+ * key switches (as fenc_compress_keyswitches), three rotations per
+ * ciphertext for a pool at S = 1 (pools at S >= 2 sum fragments), one
+ * relinearisation per ciphertext for an activation (two when its k field,
+ * the degree, is 3) and the final compression.  The paper's objective is the
+ * rotation count; the MAC term weight (a term moves about a ciphertext, a key
+ * switch 10-20) keeps a block size whose replicated channels multiply the
+ * scalar MACs from winning on rotations alone.  Ties: fewer repacks, then
+ * smaller block sizes.  block_size[i] (n_layers entries, caller-owned): the
+ * block size layer i runs at; block_size[0] is the input's encoding when
+ * layer 0 is a convolution, and a convolution whose entry differs from the
+ * block size its input arrives in is preceded by that repack.  keyswitches,
+ * mac_terms (each may be NULL): the chosen chain's totals.  Host only.
+ * Errors: EINVAL for a bad argument or layer kind, EUNSUPPORTED when no
+ * block size admits some layer. */
+enum { FENC_LAYER_CONV = 0, FENC_LAYER_POOL = 1, FENC_LAYER_ACT = 2, FENC_LAYER_COMPRESS = 3 };
+typedef struct {
+  int32_t kind, cout, k, stride, pad, groups;
+} fenc_layer;
+int fenc_plan_network(const fenc_ctx* ctx, uint32_t bs, uint32_t c, uint32_t h, uint32_t w,
+                      const fenc_layer* layers, uint32_t n_layers, int32_t max_repacks, int32_t* block_size,
+                      int64_t* keyswitches, int64_t* mac_terms);
+/* Key switches fenc_conv2d performs on input layout `in` (inner: distinct
+ * hoisted rotated copies; outer: one per output ciphertext and nonzero
+ * diagonal; Conv-aware Encoding, eq. inner / eq. outer-rot give their
+ * worst cases) and its scalar MAC terms in the mask-basis form (mac_terms,
+ * may be NULL), and the key switches of fenc_compress from `in` to `target`
+ * (NULL: the library's vector target), without building anything.  Host
+ * only. */
+int fenc_conv2d_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, uint32_t cout, uint32_t k,
+                            uint32_t stride, uint32_t pad, uint32_t groups, int64_t* inner, int64_t* outer,
+                            int64_t* mac_terms);
+int fenc_compress_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, const fenc_layout* target,
+                              int64_t* keyswitches);
 int fenc_layout_n_ct(const fenc_layout* lay);
 int64_t fenc_ct_bytes(const fenc_ctx* ctx, const fenc_layout* lay);
 /* First (ciphertext, slot) of element (b, ch, y, x).  Host only. */

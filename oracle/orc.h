@@ -120,7 +120,15 @@ u64 find_psi(u64 q, int N);
 
 // Threads for work over independent ciphertexts (ORC_THREADS, else the
 // hardware's count, at most 16); the arithmetic of each item is unchanged.
+// Set on a thread that must run par_for loops inline (the per-operation
+// timings run one operation per thread).
+inline bool& orc_serial() {
+  static thread_local bool serial = false;
+  return serial;
+}
+
 inline int orc_threads() {
+  if (orc_serial()) return 1;
   const char* e = std::getenv("ORC_THREADS");
   int t = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
   return std::max(1, std::min(16, t));

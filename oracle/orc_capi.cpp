@@ -481,6 +481,7 @@ int orc_time_ops(void* c, int level, int threads, int reps, double* out) {
     std::vector<std::thread> th;
     for (int t = 0; t < threads; t++)
       th.emplace_back([&, t] {
+        orc_serial() = true;   // one operation per thread, none split further
         for (int r = 0; r < reps; r++) op(cts[t]);
       });
     for (auto& x : th) x.join();

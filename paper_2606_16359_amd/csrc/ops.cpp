@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <set>
+#include <unordered_set>
 #include <sstream>
 #include <thread>
 #include <tuple>
@@ -517,9 +518,11 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
     const int gy = (bi + t.dbi) * S + t.u, gx = (bj + t.dbj) * S + t.v;
     return gy >= 0 && gy < Lin.h && gx >= 0 && gx < Lin.w;
   };
-  // masks: source pixel inside the logical input, at channel position q
+  // masks: source pixel inside the logical input, at channel position q; one
+  // plaintext per distinct mask (away from the borders most (u, v, dbi, dbj)
+  // give the same one, and their terms then share a group)
   std::map<std::vector<int>, int> mask_id;
-  std::vector<std::vector<double>> mask_slots;
+  PtSet mset;
   auto mask_of = [&](const Term& t, int q) {
     std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q};
     auto it = mask_id.find(key);
@@ -530,15 +533,13 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
         if (!valid_src(t, bi, bj)) continue;
         for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = 1.0;
       }
-    mask_slots.push_back(z);
-    return mask_id[key] = (int)mask_slots.size() - 1;
+    return mask_id[key] = mset.id(std::move(z));
   };
   auto ones_id = [&]() {
     const std::vector<int> key = {-1};
     auto it = mask_id.find(key);
     if (it != mask_id.end()) return it->second;
-    mask_slots.push_back(std::vector<double>(C.ns, 1.0));
-    return mask_id[key] = (int)mask_slots.size() - 1;
+    return mask_id[key] = mset.id(std::vector<double>(C.ns, 1.0));
   };
   std::map<int64_t, int> wid;
   std::vector<int64_t> codes;
@@ -694,7 +695,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
       fused ? (fset.slots.empty() ? nullptr
                                   : encode_plaintexts(C, fset.slots, materialise ? T : dm, lvl, P->owned, P->pq))
       : materialise ? (diag_slots.empty() ? nullptr : encode_plaintexts(C, diag_slots, T, lvl, P->owned, P->pq))
-                    : (mask_slots.empty() ? nullptr : encode_plaintexts(C, mask_slots, dm, lvl, P->owned, P->pq));
+                    : (mset.slots.empty() ? nullptr : encode_plaintexts(C, mset.slots, dm, lvl, P->owned, P->pq));
   const long long pe = (long long)(lvl + 1 + (P->pq ? C.K : 0)) * C.N;
   GmacBuild b0, br;
   std::vector<int> sum_out, sum_base;
@@ -1345,6 +1346,213 @@ static T& cached(Ctx& C, const std::string& key, F build) {
   return *p;
 }
 
+// ================================================================ network planning
+// Key switches of a convolution on input layout Lin, without building it:
+// the same term enumeration as build_conv (distinct rotated copies (source
+// ciphertext, shift != 0): inner rotations; outputs with a nonzero diagonal r:
+// outer rotations, one per (output, r >= 1)), and its scalar MAC terms in the
+// mask-basis form (one per output, tap and (channel position, diagonal) pair
+// that connects an input channel to an output channel).  Shapes only.
+static void conv_keyswitches(const Ctx& C, const Layout& Lin, int cout, int k, int stride, int pad, int groups,
+                             long long& inner, long long& outer, long long& terms) {
+  const int cin = Lin.c, S = Lin.S, m = Lin.m, bsg = Lin.bsg, cpc = Lin.cpc;
+  const int gin = cin / groups, gout = cout / groups, So = S / stride, ncg_out = (cout + cpc - 1) / cpc;
+  const int nd = Lin.rep ? cin : cpc, npos = ((cpc > 1) || (pad > 0)) ? cpc : 1;
+  auto in_channel = [&](int gi, int q) { return Lin.rep ? q % cin : gi * cpc + q; };
+  auto pair_ok = [&](int ch, int o) { return ch < cin && o < cout && ch / gin == o / gout; };
+  std::set<std::pair<int, long long>> copies;
+  inner = outer = terms = 0;
+  for (int bg = 0; bg < Lin.nbg; bg++)
+    for (int go = 0; go < ncg_out; go++) {
+      std::vector<char> act(nd, 0);   // diagonals with a term, the same for every (uo, vo)
+      std::vector<int> gis;
+      long long pairs = 0;            // (q, r) pairs of the active input groups
+      for (int gi = 0; gi < Lin.ncg; gi++) {
+        bool any = false;
+        for (int q = 0; q < npos; q++)
+          for (int r = 0; r < nd; r++)
+            if (pair_ok(in_channel(gi, q), go * cpc + posmod(q - r, cpc))) {
+              act[r] = 1;
+              any = true;
+              pairs++;
+            }
+        if (any) gis.push_back(gi);
+      }
+      for (int uo = 0; uo < So; uo++)
+        for (int vo = 0; vo < So; vo++) {
+          terms += pairs * k * k;
+          if (!gis.empty())
+            for (int r = 1; r < nd; r++) outer += act[r];
+          for (int gi : gis)
+            for (int di = 0; di < k; di++)
+              for (int dj = 0; dj < k; dj++) {
+                const int a = uo * stride + di - pad, b = vo * stride + dj - pad;
+                const int u = posmod(a, S), dbi = floordiv(a, S), v = posmod(b, S), dbj = floordiv(b, S);
+                const long long shift = posmod(((long long)dbi * m + dbj) * bsg, C.ns);
+                if (shift) copies.insert({((bg * Lin.ncg + gi) * S + u) * S + v, shift});
+              }
+        }
+    }
+  inner = (long long)copies.size();
+}
+
+// Key switches of a rot-mask-add repack from Ls to Ld: one hoisted rotation
+// per distinct (source ciphertext, shift != 0) among the moves (the pairs
+// repack_moves groups by).  When both layouts put the same images in a batch
+// group, every image of a group gives its group's pairs, so the first image
+// of each group is enough.
+static long long repack_keyswitches(const Ctx& C, const Layout& Ls, const Layout& Ld) {
+  if (Ls.bs != Ld.bs || Ls.c != Ld.c || Ls.h != Ld.h || Ls.w != Ld.w) fail(FENC_ELAYOUT, "repack between different tensors");
+  const int step = (Ls.kind == Ld.kind || Ld.kind == FENC_LAYOUT_VECTOR) && Ls.bsg == Ld.bsg ? Ls.bsg : 1;
+  std::unordered_set<unsigned long long> seen;
+  std::vector<std::pair<int, int>> a, b;
+  for (int n = 0; n < Ls.bs; n += step)
+    for (int ch = 0; ch < Ls.c; ch++)
+      for (int y = 0; y < Ls.h; y++)
+        for (int x = 0; x < Ls.w; x++) {
+          layout_slots(Ls, n, ch, y, x, a);
+          layout_slots(Ld, n, ch, y, x, b);
+          for (auto& d : b) {
+            const long long delta = posmod((long long)a[0].second - d.second, C.ns);
+            if (delta) seen.insert((unsigned long long)a[0].first * (unsigned long long)C.ns + (unsigned long long)delta);
+          }
+        }
+  return (long long)seen.size();
+}
+
+// Block sizes of every layer of a chain, chosen by dynamic programming over
+// the layout after each layer: the input may be encoded at any admissible S;
+// before a convolution the tensor may be repacked (rot-mask-add into a
+// fragment layout of another block size, one level each, at most max_repacks)
+// so that each convolution runs at the block size that is cheapest for the
+// whole chain (the paper adapts S between layers with HEAR-style rot-mask-add,
+// Evaluation Methodology).  Cost: key switches of convolutions, repacks,
+// S = 1 poolings (three rotations per ciphertext; S >= 2 pools sum fragments)
+// and the final compression into the FC vector layout.
+constexpr long long kRepackElems = 1LL << 22;
+// a scalar MAC term moves at most about one ciphertext of HBM traffic, a key
+// switch (ModUp, key inner product, ModDown) about 10-20
+constexpr double kTermsPerKeyswitch = 16.0;
+
+struct NetPlan {
+  std::vector<int> S;   // per layer: the block size it runs at
+  long long ks = 0;     // key switches: rotations, repacks, relinearisations
+  long long terms = 0;  // scalar MAC terms of the convolutions
+  int repacks = 0;
+  double cost() const { return (double)ks + (double)terms / kTermsPerKeyswitch; }
+};
+
+static NetPlan plan_network(const Ctx& C, int bs, int c, int h, int w, const fenc_layer* layers, int n,
+                            int max_repacks) {
+  struct St {
+    Layout L;
+    NetPlan p;
+  };
+  auto admissible = [&](const Layout& L) {
+    std::vector<int> out;
+    const int M = next_pow2(std::max(L.h, L.w));
+    for (int S = 1; S <= M; S <<= 1)
+      if ((long long)(M / S) * (M / S) <= C.ns) out.push_back(S);
+    return out;
+  };
+  auto better = [](const NetPlan& a, const NetPlan& b) {
+    if (a.cost() != b.cost()) return a.cost() < b.cost();
+    return a.repacks != b.repacks ? a.repacks < b.repacks : a.S < b.S;
+  };
+  auto key = [](const Layout& L, int reps) {
+    return std::make_tuple(L.S, L.M, L.dil, L.c, L.h, reps);
+  };
+  std::vector<St> cur;
+  {
+    Layout L0;
+    L0.h = h;
+    L0.w = w;
+    for (int S : admissible(L0)) cur.push_back({make_fragment(C.ns, C.L, C.Delta, bs, c, h, w, S), NetPlan{}});
+  }
+  for (int li = 0; li < n; li++) {
+    const fenc_layer& ly = layers[li];
+    std::map<decltype(key(Layout(), 0)), St> next;
+    auto offer = [&](St s) {
+      auto kk = key(s.L, s.p.repacks);
+      auto it = next.find(kk);
+      if (it == next.end() || better(s.p, it->second.p)) next[kk] = std::move(s);
+    };
+    for (const St& st : cur) {
+      switch (ly.kind) {
+        case FENC_LAYER_CONV: {
+          std::vector<std::pair<Layout, long long>> starts;   // (layout the conv runs on, repack cost)
+          if (st.L.dil == 1) starts.push_back({st.L, 0});
+          // repacks are offered for tensors up to kRepackElems elements (their
+          // count walks every element)
+          const bool small = (long long)bs * st.L.c * st.L.h * st.L.w <= kRepackElems;
+          if (li > 0 && st.p.repacks < max_repacks && small)
+            for (int S2 : admissible(st.L)) {
+              if (S2 == st.L.S && st.L.dil == 1) continue;
+              Layout R = make_fragment(C.ns, st.L.level, st.L.scale, bs, st.L.c, st.L.h, st.L.w, S2);
+              starts.push_back({R, repack_keyswitches(C, st.L, R)});
+            }
+          for (auto& sv : starts) {
+            const Layout& Lc = sv.first;
+            if (ly.stride < 1 || Lc.S % ly.stride || ly.groups < 1 || Lc.c % ly.groups || ly.cout % ly.groups)
+              continue;
+            Layout Lo;
+            try {
+              build_conv(*(Ctx*)&C, Lc, nullptr, ly.cout, ly.k, ly.stride, ly.pad, ly.groups, 0, nullptr, true, Lo);
+            } catch (const Error&) {
+              continue;
+            }
+            long long in = 0, out = 0, tm = 0;
+            conv_keyswitches(C, Lc, ly.cout, ly.k, ly.stride, ly.pad, ly.groups, in, out, tm);
+            St ns{Lo, st.p};
+            ns.p.S.push_back(Lc.S);
+            ns.p.ks += sv.second + in + out;
+            ns.p.terms += tm;
+            ns.p.repacks += sv.second > 0 || Lc.S != st.L.S || Lc.dil != st.L.dil;
+            offer(std::move(ns));
+          }
+          break;
+        }
+        case FENC_LAYER_POOL: {
+          Layout Lo;
+          try {
+            build_pool(*(Ctx*)&C, st.L, true, Lo);
+          } catch (const Error&) {
+            break;
+          }
+          St ns{Lo, st.p};
+          ns.p.S.push_back(st.L.S);
+          if (st.L.S == 1) ns.p.ks += 3LL * st.L.n_ct();
+          offer(std::move(ns));
+          break;
+        }
+        case FENC_LAYER_ACT: {   // relinearisations: one per ciphertext, two for degree 3
+          St ns = st;
+          ns.p.S.push_back(st.L.S);
+          ns.p.ks += (long long)st.L.n_ct() * (ly.k >= 3 ? 2 : 1);
+          offer(std::move(ns));
+          break;
+        }
+        case FENC_LAYER_COMPRESS: {
+          St ns = st;
+          ns.p.S.push_back(st.L.S);
+          ns.p.ks += repack_keyswitches(C, st.L, vector_target(C, st.L));
+          offer(std::move(ns));
+          break;
+        }
+        default:
+          fail(FENC_EINVAL, "unknown layer kind");
+      }
+    }
+    cur.clear();
+    for (auto& kv : next) cur.push_back(std::move(kv.second));
+    if (cur.empty()) fail(FENC_EUNSUPPORTED, "no block size admits layer " + std::to_string(li));
+  }
+  const St* best = &cur[0];
+  for (const St& s : cur)
+    if (better(s.p, best->p)) best = &s;
+  return best->p;
+}
+
 // ================================================================ C ABI
 #define API_BEGIN try {
 #define API_END                                                  \
@@ -1587,6 +1795,47 @@ int fenc_plan_layout(const fenc_ctx* ctx, uint32_t bs, uint32_t c, uint32_t h, u
   if (!ctx || !out) fail(FENC_EINVAL, "null argument");
   Layout L = plan_fragment(ctx->ns, ctx->L, ctx->Delta, bs, c, h, w, k_next, cout_next, s_override);
   *out = to_pub(*(fenc_ctx*)ctx, L);
+  API_END
+}
+
+int fenc_plan_network(const fenc_ctx* ctx, uint32_t bs, uint32_t c, uint32_t h, uint32_t w, const fenc_layer* layers,
+                      uint32_t n_layers, int32_t max_repacks, int32_t* block_size, int64_t* keyswitches,
+                      int64_t* mac_terms) {
+  API_BEGIN
+  if (!ctx || !layers || !block_size || n_layers < 1 || max_repacks < 0) fail(FENC_EINVAL, "bad argument");
+  const NetPlan p = plan_network(*ctx, (int)bs, (int)c, (int)h, (int)w, layers, (int)n_layers, max_repacks);
+  for (uint32_t i = 0; i < n_layers; i++) block_size[i] = p.S[i];
+  if (keyswitches) *keyswitches = p.ks;
+  if (mac_terms) *mac_terms = p.terms;
+  API_END
+}
+
+int fenc_conv2d_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, uint32_t cout, uint32_t k, uint32_t stride,
+                            uint32_t pad, uint32_t groups, int64_t* inner, int64_t* outer, int64_t* mac_terms) {
+  API_BEGIN
+  if (!ctx || !in || !inner || !outer) fail(FENC_EINVAL, "null argument");
+  Layout Lin = from_pub(*ctx, in), Lo;
+  build_conv(*(Ctx*)ctx, Lin, nullptr, cout, k, stride, pad, groups, 0, nullptr, true, Lo);   // shape checks
+  long long a = 0, b = 0, t = 0;
+  conv_keyswitches(*ctx, Lin, cout, k, stride, pad, groups, a, b, t);
+  *inner = a;
+  *outer = b;
+  if (mac_terms) *mac_terms = t;
+  API_END
+}
+
+int fenc_compress_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, const fenc_layout* target, int64_t* ks) {
+  API_BEGIN
+  if (!ctx || !in || !ks) fail(FENC_EINVAL, "null argument");
+  const Layout Lin = from_pub(*ctx, in);
+  Layout Lt;
+  if (target) {
+    Lt = from_pub(*ctx, target);
+    Lt.level = Lin.level;
+  }
+  Layout Lout;
+  build_compress(*(Ctx*)ctx, Lin, target ? &Lt : nullptr, true, Lout);   // the layout compress would produce
+  *ks = repack_keyswitches(*ctx, Lin, Lout);
   API_END
 }
 
@@ -1968,19 +2217,20 @@ int fenc_poly_act(fenc_ctx* ctx, const fenc_ctbatch* in, const double* coeffs, u
   // workspace per ciphertext: the product, its third part, the ModUp output
   // and, for degree 3, x^2 and u one level down
   const int l = Lin.level, nl1 = l + 1, beta = (nl1 + C.alpha - 1) / C.alpha;
+  // ciphertexts are independent here, so tiles are runs of ciphertexts
   const double per_ct = (double)C.N * 8 * (2.0 * nl1 + nl1 + (double)beta * (nl1 + C.K) + (d == 3 ? 4.0 * l : 0.0));
-  const int tile = tile_groups(C, Lin.nbg, per_ct * cts_per_group(Lin));
-  const long long in_step = (long long)cts_per_group(Lin) * ct_elems(C, Lin.level);
-  const long long out_step = (long long)cts_per_group(Lout) * ct_elems(C, Lout.level);
-  for (int b0 = 0; b0 < Lin.nbg; b0 += tile) {
-  const Layout Ls = sub_layout(Lin, std::min(tile, Lin.nbg - b0));
+  const int n_all = Lin.n_ct();
+  const int tile = tile_groups(C, n_all, per_ct);
+  const long long in_step = ct_elems(C, Lin.level), out_step = ct_elems(C, Lout.level);
+  for (int b0 = 0; b0 < n_all; b0 += tile) {
+  const int n_tile = std::min(tile, n_all - b0);
   std::ostringstream key;
-  key << "poly|" << layout_key(Ls) << '|' << fnv(c, sizeof(c));
+  key << "poly|" << layout_key(Lin) << '|' << n_tile << '|' << fnv(c, sizeof(c));
   PolyPlan& P = cached<PolyPlan>(C, key.str(), [&] {
     auto p = new PolyPlan;
     p->out = Lout;
     p->level = Lin.level;
-    p->n = Ls.n_ct();
+    p->n = n_tile;
     p->d = d;
     p->lin = d <= 1 || c[0] != 0.0 || c[1] != 0.0;   // adding zero codes changes nothing
     const int l = Lin.level;

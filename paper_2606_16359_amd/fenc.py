@@ -99,6 +99,11 @@ def load(path=None):
         "fenc_key_export_galois": (C.c_int, [vp, C.c_uint64, vp]),
         "fenc_key_import": (C.c_int, [vp, C.c_uint64, vp]),
         "fenc_plan_layout": (C.c_int, [vp, u32, u32, u32, u32, u32, u32, i32, L]),
+        "fenc_plan_network": (C.c_int, [vp, u32, u32, u32, u32, vp, u32, i32, vp, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_int64)]),
+        "fenc_conv2d_keyswitches": (C.c_int, [vp, L, u32, u32, u32, u32, u32, C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+        "fenc_compress_keyswitches": (C.c_int, [vp, L, vp, C.POINTER(C.c_int64)]),
         "fenc_layout_n_ct": (C.c_int, [L]),
         "fenc_ct_bytes": (C.c_int64, [vp, L]),
         "fenc_layout_slot": (C.c_int, [vp, L, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(i32), C.POINTER(i32)]),
@@ -308,6 +313,53 @@ class Fenc:
         lay = Layout()
         self._check(self.lib.fenc_plan_layout(self.h, bs, c, h, w, k_next, cout_next, s_override, C.byref(lay)))
         return lay
+
+    LAYER_KINDS = {"conv": 0, "pool": 1, "act": 2, "compress": 3}
+
+    def plan_network(self, bs, shape, layers, max_repacks=1):
+        """Block size per layer of a chain (dicts with kind "conv" (cout, k,
+        stride=1, pad=0, groups=1), "pool", "act" (k: degree, default 2) or
+        "compress"); returns (block sizes, key switches, MAC terms)."""
+        arr = np.zeros((len(layers), 6), np.int32)
+        for i, ly in enumerate(layers):
+            arr[i] = [self.LAYER_KINDS[ly["kind"]], ly.get("cout", 0), ly.get("k", 0), ly.get("stride", 1),
+                      ly.get("pad", 0), ly.get("groups", 1)]
+        out = np.zeros(len(layers), np.int32)
+        ks, tm = C.c_int64(), C.c_int64()
+        c, h, w = shape
+        self._check(self.lib.fenc_plan_network(self.h, bs, c, h, w, arr.ctypes.data, len(layers), max_repacks,
+                                               out.ctypes.data, C.byref(ks), C.byref(tm)))
+        return [int(v) for v in out], ks.value, tm.value
+
+    def conv2d_keyswitches(self, lay, cout, k, stride=1, pad=0, groups=1):
+        """(inner, outer) key switches and scalar MAC terms conv2d performs on
+        layout lay."""
+        a, b, t = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(self.lib.fenc_conv2d_keyswitches(self.h, C.byref(lay), cout, k, stride, pad, groups, C.byref(a),
+                                                     C.byref(b), C.byref(t)))
+        return a.value, b.value, t.value
+
+    def conv2d_layout(self, lay, cout, k, stride=1, pad=0, groups=1):
+        """Output layout of conv2d on layout lay (the sizing call; nothing is
+        built or run)."""
+        b, out = CtBatch(), CtBatch()
+        b.data, b.lay, out.data = None, lay, None
+        w = np.zeros(cout * (lay.c // groups) * k * k)
+        self._check(self.lib.fenc_conv2d(self.h, C.byref(b), w.ctypes.data, None, cout, k, stride, pad, groups, 0,
+                                         C.byref(out), None))
+        return out.lay.copy()
+
+    def avgpool2_layout(self, lay):
+        b, out = CtBatch(), CtBatch()
+        b.data, b.lay, out.data = None, lay, None
+        self._check(self.lib.fenc_avgpool2(self.h, C.byref(b), C.byref(out), None))
+        return out.lay.copy()
+
+    def compress_keyswitches(self, lay, target=None):
+        ks = C.c_int64()
+        self._check(self.lib.fenc_compress_keyswitches(self.h, C.byref(lay), C.byref(target) if target else None,
+                                                       C.byref(ks)))
+        return ks.value
 
     def layout_slot(self, lay, b, ch, y, x):
         ct, slot = C.c_int32(), C.c_int32()

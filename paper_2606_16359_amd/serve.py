@@ -48,7 +48,8 @@ class Tenant:
     NETS = {
         "lenet": dict(params="lenet", in_shape=(1, 28, 28), block_size=0),
         "cifar": dict(params="cifar", in_shape=(16, 32, 32), block_size=0),
-        "mobilenet": dict(params="cifar", in_shape=W.MOBILENET_INPUTS[0][0], block_size=W.MOBILENET_INPUTS[0][1]),
+        # S = 2: two images per batch group, the request granularity
+        "mobilenet": dict(params="cifar", in_shape=W.MOBILENET_INPUTS[0], block_size=2),
     }
 
     def __init__(self, name, net, seed, capacity, max_batch=4, lib_path=None, params=None, shapes=None,

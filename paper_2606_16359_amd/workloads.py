@@ -34,11 +34,27 @@ def weights(shapes, seed=SEED_WEIGHTS):
 
 
 LENET_SHAPES = [(6, 1, 5, 5), (16, 6, 5, 5), (120, 256), (84, 120), (10, 84)]
+# the layer chain the block-size planner prices (the FC layers do not depend
+# on the layout of their input and are left out)
+LENET_LAYERS = [dict(kind="conv", cout=6, k=5), dict(kind="act"), dict(kind="pool"),
+                dict(kind="conv", cout=16, k=5), dict(kind="act"), dict(kind="pool"), dict(kind="compress")]
 
 
 def lenet_inputs(batch=64):
     """x[batch][1][28][28] and the five weight tensors of the LeNet-5-shaped network."""
     return images((batch, 1, 28, 28)), weights(LENET_SHAPES)
+
+
+def planned_layout(fenc, batch, shape, layers):
+    """Input layout at the block size the library's chain planner picks for
+    `layers` (no repacks)."""
+    S = fenc.plan_network(batch, shape, layers, 0)[0][0]
+    c, h, w = shape
+    return fenc.plan_layout(batch, c, h, w, layers[0]["k"], layers[0]["cout"], S)
+
+
+def lenet_layout(fenc, batch=64):
+    return planned_layout(fenc, batch, (1, 28, 28), LENET_LAYERS)
 
 
 def lenet_forward(fenc, ct, w):
@@ -81,8 +97,9 @@ MOBILENET_BLOCKS = [
     [dict(w=(32, 1, 3, 3), stride=1, pad=1, groups=32), dict(w=(64, 32, 1, 1), stride=1, pad=0, groups=1)],
     [dict(w=(64, 1, 3, 3), stride=2, pad=1, groups=64), dict(w=(128, 64, 1, 1), stride=1, pad=0, groups=1)],
 ]
-# the input shape and the block size each block's fresh encryption uses
-MOBILENET_INPUTS = [((3, 224, 224), 2), ((32, 112, 112), 1), ((64, 112, 112), 2)]
+# the input shape of each block's fresh encryption; its block size comes from
+# the chain planner (mobilenet_layout)
+MOBILENET_INPUTS = [(3, 224, 224), (32, 112, 112), (64, 112, 112)]
 QUADRATIC = (0.1471, 0.5, 0.1196)   # a x^2 + b x + c of the ReLU-approximation kind
 
 
@@ -90,12 +107,26 @@ def mobilenet_weights(seed=SEED_WEIGHTS):
     return [weights([layer["w"] for layer in blk], seed=seed + i) for i, blk in enumerate(MOBILENET_BLOCKS)]
 
 
+def mobilenet_layers(b):
+    """Layer chain of block b for the planner."""
+    out = []
+    for ly in MOBILENET_BLOCKS[b]:
+        out += [dict(kind="conv", cout=ly["w"][0], k=ly["w"][2], stride=ly["stride"], pad=ly["pad"],
+                     groups=ly["groups"]), dict(kind="act")]
+    return out
+
+
+def mobilenet_layout(fenc, b, batch):
+    return planned_layout(fenc, batch, MOBILENET_INPUTS[b], mobilenet_layers(b))
+
+
 def mobilenet_encrypt(fenc, batch, seed_enc=SEED_ENC):
     """The three blocks' fresh encryptions of batch images each (the block
-    inputs at 224x224x3, 112x112x32 and 112x112x64, uniform [0,1))."""
+    inputs at 224x224x3, 112x112x32 and 112x112x64, uniform [0,1)), each at
+    its planned block size."""
     cts = []
-    for b, (blk, ((c, h, w), S)) in enumerate(zip(MOBILENET_BLOCKS, MOBILENET_INPUTS)):
-        lay = fenc.plan_layout(batch, c, h, w, blk[0]["w"][2], blk[0]["w"][0], S)
+    for b, (c, h, w) in enumerate(MOBILENET_INPUTS):
+        lay = mobilenet_layout(fenc, b, batch)
         cts.append(fenc.encrypt(fenc.encode_fragment(images((batch, c, h, w), seed=1 + b), lay), lay, seed_enc + b))
     return cts
 

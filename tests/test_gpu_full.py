@@ -13,7 +13,7 @@ def lenet():
     fe = F.Fenc(*W.PARAMS["lenet"])
     fe.set_hoisting(W.BENCH_HOISTING)   # the benchmark's per-layer schedule choice
     x, w = W.lenet_inputs(64)
-    lay = fe.plan_layout(64, 1, 28, 28, 5, 6)
+    lay = W.lenet_layout(fe, 64)          # the benchmark's block size (chain planner)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
     torch.cuda.synchronize()
     return fe, x, w, lay, ct
@@ -23,7 +23,9 @@ def test_lenet_decrypts_to_float64_cnn(lenet):
     from oracle import cnn_ref
     from paper_2606_16359_amd import workloads as W
     fe, x, w, lay, ct = lenet
-    assert lay.S == 2 and lay.n_ct() == 4          # planner: S = 2 fills the slots (eq. opt)
+    # chain planner: S = 2 (S = 4 would save key switches but replicate the
+    # single input channel four times per ciphertext and quadruple the MAC terms)
+    assert lay.S == 2 and lay.n_ct() == 4
     out = W.lenet_forward(fe, ct, w)
     got = fe.decrypt(out).reshape(64, 10)
     want = cnn_ref.lenet(x, *w).reshape(64, 10)
@@ -90,7 +92,7 @@ def test_lenet_every_layer_matches_oracle_at_full_size(lenet):
     from paper_2606_16359_amd import workloads as W
     fe, x, w, lay, ct = lenet
     o = P.Oracle(*W.PARAMS["lenet"])
-    ob = o.encrypt_tensor(o.plan_layout(64, 1, 28, 28, 5, 6), x, W.SEED_ENC)
+    ob = o.encrypt_tensor(o.fragment_layout(64, 1, 28, 28, lay.S), x, W.SEED_ENC)
     assert np.array_equal(fe.export(ct), ob.data())
     # h: the schedule the library's layer ran with
     steps = [("conv1", lambda c: fe.conv2d(c, w[0]), lambda b, h: o.conv2d(b, w[0], hoist=h)),
@@ -161,9 +163,10 @@ def test_cifar_first_layer_and_cubic_sampled_cones_match_oracle():
 
 
 def test_mobilenet_block_a_sampled_cones_match_oracle():
-    """MobileNet-V1 block A at ImageNet shape (224x224x3, conv 3->32 stride 2,
-    S = 2, 16 images, N = 2^16, 24 limbs) and its quadratic, compared element
-    by element on seeded sampled output ciphertexts."""
+    """MobileNet-V1 block A at ImageNet shape as the benchmark runs it
+    (224x224x3, conv 3->32 stride 2, 64 images at the planned block size,
+    N = 2^16, 24 limbs) and its quadratic, compared element by element on
+    seeded sampled output ciphertexts."""
     import time
     from oracle import pyoracle as P
     from paper_2606_16359_amd import fenc as F
@@ -173,10 +176,10 @@ def test_mobilenet_block_a_sampled_cones_match_oracle():
     o = P.Oracle(*W.PARAMS["cifar"])
     blk = W.MOBILENET_BLOCKS[0][0]
     wa = W.mobilenet_weights()[0][0]
-    x = W.images((16, 3, 224, 224))
-    lay = fe.plan_layout(16, 3, 224, 224, 3, 32, 2)
-    Lo = o.fragment_layout(16, 3, 224, 224, 2)
-    assert (lay.bs_g, lay.chan_per_ct, lay.n_ct()) == (Lo["bsg"], Lo["cpc"], 96) == (2, 1, 96)
+    x = W.images((64, 3, 224, 224))
+    lay = W.mobilenet_layout(fe, 0, 64)
+    Lo = o.fragment_layout(64, 3, 224, 224, lay.S)
+    assert (lay.bs_g, lay.chan_per_ct, lay.n_ct()) == (Lo["bsg"], Lo["cpc"], Lo["nbg"] * Lo["ncg"] * lay.S ** 2)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
     xin = fe.export(ct)
     y = fe.conv2d(ct, wa, stride=blk["stride"], pad=blk["pad"])
@@ -234,9 +237,9 @@ def test_mobilenet_blocks_at_imagenet_shape_decrypt_to_float64():
     fe = F.Fenc(*W.PARAMS["cifar"])
     ws = W.mobilenet_weights()
     x = W.images((2, 3, 224, 224))
-    for b, (blk, w, ((c, h, wd), S)) in enumerate(zip(W.MOBILENET_BLOCKS, ws, W.MOBILENET_INPUTS)):
+    for b, (blk, w, (c, h, wd)) in enumerate(zip(W.MOBILENET_BLOCKS, ws, W.MOBILENET_INPUTS)):
         assert x.shape[1:] == (c, h, wd)
-        lay = fe.plan_layout(2, c, h, wd, blk[0]["w"][2], blk[0]["w"][0], S)
+        lay = W.mobilenet_layout(fe, b, 2)
         ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC + b)
         t0 = time.time()
         y = W.mobilenet_block(fe, ct, blk, w)
