@@ -41,10 +41,14 @@ MOBILENET_BATCH = 64
 WORKSPACE_LIMIT = 24 << 30
 METRIC = "encrypted images/sec (batched hipGraph, bit-exact)"
 DTYPE = "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic"
-# HBM bytes per launch from FETCH_SIZE + WRITE_SIZE counters (scaled by a copy
-# of known size), per (workload, kernel); an entry is kept only while its
-# kernel is unchanged since the counters were taken
-TRAFFIC = {}
+# HBM bytes per launch of each workload's dominant kernel, from FETCH_SIZE +
+# WRITE_SIZE counters scaled by a copy of known size (profiles/*_hbm_traffic.md);
+# an entry is kept only while its kernel is unchanged since the counters were taken
+TRAFFIC = {
+    ("mobilenet", "ntt_fwd_cols"): 1.8092e9,
+    ("cifar", "gmac_pt"): 11.4665e9,
+    ("lenet", "kip"): 0.8760e9,
+}
 
 
 def log(*a):
@@ -263,26 +267,33 @@ def cpu_baseline(counters, imgs, level):
                        f"relin {counters['relin']}); extrapolated")}
 
 
+def workload_step(workload, batch):
+    """(context, step) of a benchmark workload in its benchmark configuration."""
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    if workload == "mobilenet":
+        fe, cts, ws = mobilenet_context(batch)
+        return fe, lambda: W.mobilenet_forward(fe, cts, ws)
+    if workload == "cifar":
+        fe = F.Fenc(*W.PARAMS["cifar"])
+        fe.set_hoisting(W.BENCH_HOISTING)
+        x, w = W.cifar_inputs(256)
+        lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
+        ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+        return fe, lambda: W.cifar_forward(fe, ct, w)
+    fe = F.Fenc(*W.PARAMS["lenet"])
+    fe.set_hoisting(W.BENCH_HOISTING)
+    x, w = W.lenet_inputs(64)
+    lay = W.lenet_layout(fe, 64)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    return fe, lambda: W.lenet_forward(fe, ct, w)
+
+
 def counters_run(args):
     """Short run for hardware-counter passes: one warm-up step, a 256 MiB
     device copy (calibrates the byte counters), one batched step; no timing."""
     import torch
-    from paper_2606_16359_amd import workloads as W
-    if args.workload == "mobilenet":
-        fe, cts, ws = mobilenet_context(args.batch)
-
-        def step():
-            return W.mobilenet_forward(fe, cts, ws)
-    else:
-        from paper_2606_16359_amd import fenc as F
-        fe = F.Fenc(*W.PARAMS["lenet"])
-        fe.set_hoisting(W.BENCH_HOISTING)
-        x, w = W.lenet_inputs(64)
-        lay = W.lenet_layout(fe, 64)
-        ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
-
-        def step():
-            return W.lenet_forward(fe, ct, w)
+    fe, step = workload_step(args.workload, args.batch)
     out = step()
     torch.cuda.synchronize()
     out = None
@@ -294,6 +305,55 @@ def counters_run(args):
     step()
     torch.cuda.synchronize()
     print(json.dumps({"counters_run": True, "workload": args.workload, "copy_bytes": COPY_BYTES}), flush=True)
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """HBM bytes per dispatch of every kernel of the measured step of a
+    --counters run, from a FETCH_SIZE and a WRITE_SIZE pass (rocprofv3
+    counter_collection CSVs, KiB per dispatch).  Each counter is calibrated by
+    the run's COPY_BYTES device copy (the largest runtime copy dispatch), and
+    only the dispatches after that copy (the step that follows it) count.
+    Radix variants of an NTT pass are merged under the pass's name."""
+    import csv
+    import re
+
+    def load(path):
+        rows = list(csv.DictReader(open(path)))
+        keys = rows[0].keys()
+        kcol = next(k for k in keys if k.lower().replace("-", "_") in ("kernel_name", "kernelname"))
+        vcol = next(k for k in keys if k.lower() in ("counter_value", "value"))
+        icol = next(k for k in keys if "dispatch" in k.lower() and "id" in k.lower())
+        out = {}
+        for r in rows:   # one row per dispatch (and counter instance): sum the instances
+            d = int(r[icol])
+            name = r[kcol].split("(")[0].split("<")[0].strip()
+            out.setdefault(d, [name, 0.0])[1] += float(r[vcol])
+        copy = max((d for d, (n, v) in out.items() if "copyBuffer" in n), key=lambda d: out[d][1])
+        factor = COPY_BYTES / 1024.0 / out[copy][1]
+        return {d: (n, v) for d, (n, v) in out.items() if d > copy}, factor, out[copy][1]
+
+    def norm(name):
+        name = re.sub(r"^k_", "", name)
+        return name.replace("16", "") if name.startswith("ntt_") else name
+
+    fetch, ff, fc = load(fetch_csv)
+    write, fw, wc = load(write_csv)
+    agg = {}
+    for d, (n, v) in fetch.items():
+        a = agg.setdefault(norm(n), [0, 0.0, 0.0])
+        a[0] += 1
+        a[1] += v
+        a[2] += write.get(d, (n, 0.0))[1]
+    print(f"calibration copy of {COPY_BYTES >> 10} KiB: FETCH_SIZE {fc:.0f} KiB (factor {ff:.3f}), "
+          f"WRITE_SIZE {wc:.0f} KiB (factor {fw:.3f})")
+    print("| Kernel | Dispatches | FETCH KiB (mean) | WRITE KiB (mean) | HBM GB per dispatch (calibrated) |")
+    print("|---|---|---|---|---|")
+    res = {}
+    for name, (n, fs, ws) in sorted(agg.items(), key=lambda kv: -(kv[1][1] * ff + kv[1][2] * fw)):
+        gb = (fs * ff + ws * fw) / n * 1024 / 1e9
+        res[name] = round(gb, 4)
+        print(f"| {name} | {n} | {fs / n:.4g} | {ws / n:.4g} | {gb:.4f} |")
+    print(json.dumps({"hbm_GB_per_dispatch": res}))
 
 
 def peaks_run(args):
@@ -336,16 +396,21 @@ def main():
     ap.add_argument("--batch", type=int, default=MOBILENET_BATCH, help="MobileNet images per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
-    ap.add_argument("--workload", choices=["mobilenet", "lenet"], default="mobilenet",
-                    help="workload of the --counters run")
+    ap.add_argument("--workload", choices=["mobilenet", "cifar", "lenet"], default="mobilenet",
+                    help="workload of the --counters and --trace runs")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="reduce the two counter passes of a --counters run to HBM bytes per dispatch and exit")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes (one warm-up step, a 256 MiB copy, one step)")
     ap.add_argument("--peaks", action="store_true",
                     help="measure instruction, modular-multiply and HBM peaks of the device and exit")
     ap.add_argument("--trace", action="store_true",
                     help="run for a kernel trace: three warm-up steps, then --steps batched eager steps of the "
-                         "headline workload and nothing else")
+                         "workload (--workload) and nothing else")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: this build runs every configuration on a single MI355X; the "
                                    "path would shard by independent batch groups, which is not implemented"}))
@@ -359,14 +424,14 @@ def main():
         peaks_run(args)
         return
     if args.trace:
-        from paper_2606_16359_amd import workloads as W
-        fe, cts, ws = mobilenet_context(args.batch)
+        fe, step = workload_step(args.workload, args.batch)
         out = None
         for i in range(3 + args.steps):
             out = None
-            out = W.mobilenet_forward(fe, cts, ws)
+            out = step()
             torch.cuda.synchronize()
-        print(json.dumps({"trace_run": True, "batched_steps": args.steps, "warmup_steps": 3}), flush=True)
+        print(json.dumps({"trace_run": True, "workload": args.workload, "batched_steps": args.steps,
+                          "warmup_steps": 3}), flush=True)
         return
 
     extras = {}
