@@ -5,13 +5,20 @@ launches.
 Each tenant owns a context (its own keys, resident in HBM), a network and a
 serving layout whose batch group holds `capacity` images.  A request is one
 client's batch of images, encrypted by the client into up to `max_groups`
-whole batch groups.  A tenant's executor takes every request queued when it becomes idle
-(up to its batch-size limit and the memory budget), concatenates their batch
-groups into one ciphertext batch and runs the network once for all of them:
-every stage launch covers the requests together.  Batch groups never mix
-inside a ciphertext, so each request's output ciphertexts are bit-identical to
-a run of that request alone.  Tenants run on their own HIP streams, so their
-batches overlap on the device.
+whole batch groups.  Requests queued together (up to a batch-size limit and
+the memory budget) are concatenated into one ciphertext batch and the network
+runs once for all of them: every stage launch covers the requests together.
+Batch groups never mix inside a ciphertext, so each request's output
+ciphertexts are bit-identical to a run of that request alone.
+
+On the GPU a tenant has several lanes: contexts of their own with the
+tenant's parameters and key seed (so the same keys and the same residues),
+each with its own HIP stream and workspace, and the network's stages
+(layers) captured as hipGraphs for every batch-group count.  The tenant's
+executor replays each running batch stage by stage and, at every stage
+boundary, admits the requests that arrived meanwhile into a free lane: a new
+batch starts while earlier ones are at later layers, and the batches of all
+lanes and all tenants overlap on the device.
 
 This module holds scheduling and bookkeeping only; all arithmetic runs in the
 library.  Arrival traces are seeded and synthetic.
@@ -53,13 +60,17 @@ class Tenant:
     }
 
     def __init__(self, name, net, seed, capacity, max_batch=4, lib_path=None, params=None, shapes=None,
-                 strides=None, in_shape=None, block_size=None, max_groups=1):
+                 strides=None, in_shape=None, block_size=None, max_groups=1, ws_limit=None):
+        """ws_limit: the workspace limit of each of the tenant's contexts (bytes;
+        None: the library's default); operations tile by batch groups within it."""
         spec = self.NETS[net]
         self.name, self.net, self.capacity, self.max_batch = name, net, capacity, max_batch
         self.max_groups = max_groups
         prm = list(params or W.PARAMS[spec["params"]])
         prm[-1] = seed
-        self.fe = F.Fenc(*prm, lib_path=lib_path)
+        self.prm, self.lib_path, self.ws_limit = prm, lib_path, ws_limit
+        self.fe = self._context()
+        self.lanes = []
         c, h, w = in_shape or spec["in_shape"]
         self.in_shape = (c, h, w)
         if net == "mobilenet":
@@ -117,12 +128,41 @@ class Tenant:
         return y.reshape(y.shape[0], -1)[:req.n_images]
 
     # ---- server side
-    def forward(self, ct):
+    def stages(self, fe):
+        """The network as a list of stages (one layer each) on context fe; the
+        same calls as workloads' lenet_forward / cifar_forward / mobilenet_block."""
+        w = self.w
         if self.net == "lenet":
-            return W.lenet_forward(self.fe, ct, self.w)
+            return [lambda c: fe.conv2d(c, w[0]), fe.poly_act, fe.avgpool2,
+                    lambda c: fe.conv2d(c, w[1]), fe.poly_act, fe.avgpool2, fe.compress,
+                    lambda c: fe.fc(c, w[2]), lambda c: fe.fc(c, w[3]), lambda c: fe.fc(c, w[4])]
         if self.net == "mobilenet":
-            return W.mobilenet_block(self.fe, ct, W.MOBILENET_BLOCKS[0], self.w)
-        return W.cifar_forward(self.fe, ct, self.w, self.strides)
+            ly = W.MOBILENET_BLOCKS[0][0]
+            return [lambda c: fe.conv2d(c, w[0], stride=ly["stride"], pad=ly["pad"], groups=ly["groups"]),
+                    lambda c: fe.poly_act(c, W.QUADRATIC, inplace=True)]
+        out = []
+        for wi, st in zip(w, self.strides):
+            out += [lambda c, wi=wi, st=st: fe.conv2d(c, wi, stride=st, pad=wi.shape[2] // 2),
+                    lambda c: fe.poly_act(c, W.CUBIC, inplace=True)]
+        return out
+
+    def forward(self, ct):
+        y = ct
+        for st in self.stages(self.fe):
+            y = st(y)
+        return y
+
+    def _context(self):
+        fe = F.Fenc(*self.prm, lib_path=self.lib_path)
+        if self.ws_limit is not None:
+            fe.set_workspace_limit(self.ws_limit)
+        return fe
+
+    def make_lanes(self, n):
+        """n lanes (GPU): the first on the tenant's own context, the others on
+        new contexts with the same parameters and key seed."""
+        self.lanes = [Lane(self, self.fe if i == 0 else self._context()) for i in range(n)]
+        return self.lanes
 
     # HBM held while a request runs, in units of its input ciphertext bytes
     # (rotated copies, extended digits and outputs).  The MobileNet-shaped
@@ -163,6 +203,68 @@ class Tenant:
         return out
 
 
+class Lane:
+    """One pipeline slot of a tenant on the GPU: a context, a HIP stream (default
+    priority) and, per batch-group count G, the network's stages captured as
+    hipGraphs on that stream, reading a fixed input buffer of G groups."""
+
+    def __init__(self, tenant, fe):
+        import torch
+        self.t, self.fe = tenant, fe
+        self.stream = torch.cuda.Stream()
+        self.graphs = {}         # G -> (input Ciphertexts, [CUDAGraph per stage], output Ciphertexts)
+        self.reqs = None         # the running batch
+        self.G = 0
+        self.next = 0            # next stage to launch
+        self.events = deque()    # one per launched, unfinished stage
+        self.t_admit = 0.0
+
+    def capture(self, G):
+        """An eager run of G groups (plans, keys, workspace), then one graph per
+        stage.  The stages' buffers come from one private pool and stay
+        referenced, so replays find them where the capture left them."""
+        import torch
+        lay = self.t.layout(1).copy()   # G groups side by side, as a merged batch is laid out
+        lay.n_bg, lay.bs = G, G * self.t.capacity
+        x = self.fe.alloc_cts(lay)
+        x.buf.zero_()
+        stages = self.t.stages(self.fe)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        # eager passes until the workspace stops changing: an operation may
+        # replace the unpinned chunks an earlier one used, and a capture
+        # cannot grow the workspace
+        size = -1
+        for _ in range(4):
+            with torch.cuda.stream(self.stream):
+                y = x
+                for st in stages:
+                    y = st(y)
+            self.stream.synchronize()
+            del y
+            if self.fe.device_bytes() == size:
+                break
+            size = self.fe.device_bytes()
+        graphs, cur, pool = [], x, None
+        for st in stages:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, pool=pool, stream=self.stream):
+                cur = st(cur)
+            pool = g.pool()
+            graphs.append(g)
+        self.graphs[G] = (x, graphs, cur)
+
+    def launch(self):
+        """Replay the next stage on the lane's stream; an event marks its end."""
+        import torch
+        g = self.graphs[self.G][1][self.next]
+        with torch.cuda.stream(self.stream):
+            g.replay()
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self.events.append(ev)
+        self.next += 1
+
+
 class Server:
     """Continuous batching over tenants with HBM-footprint admission."""
 
@@ -177,15 +279,31 @@ class Server:
         self.done = []
         self.done_lock = threading.Lock()
         self.batches = []
+        self.admissions = []   # lanes: (tenant, time, stages the tenant's other running batches are at)
 
-    def warmup(self, seed=1, group_counts=None, progress=None):
+    def warmup(self, seed=1, group_counts=None, progress=None, lanes=0):
         """Build a tenant's plans for the batch-group counts it may run (all
-        counts up to max_batch * max_groups unless given; not timed).
-        progress(tenant name, group count) is called after each run."""
+        counts up to max_batch * max_groups unless given; not timed).  With
+        lanes > 0 (GPU), each tenant gets that many lanes and every lane
+        captures its stage graphs for those counts.  progress(tenant name,
+        group count) is called after each count."""
         for t in self.tenants.values():
+            counts = list((group_counts or {}).get(t.name, range(1, t.max_batch * t.max_groups + 1)))
+            if lanes and t.stream is not None:
+                t.make_lanes(lanes)
+                # graphs for powers of two (and the largest count): a batch runs
+                # in the smallest captured count that holds it
+                counts = sorted({1 << i for i in range(max(counts).bit_length()) if (1 << i) <= max(counts)}
+                                | {max(counts)})
+                for G in counts:
+                    for ln in t.lanes:
+                        ln.capture(G)
+                    if progress:
+                        progress(t.name, G)
+                continue
             x = np.zeros((t.capacity,) + t.in_shape)
             ct = t.encrypt_request(x, seed)
-            for G in (group_counts or {}).get(t.name, range(1, t.max_batch * t.max_groups + 1)):
+            for G in counts:
                 reqs = [Request(-1, t.name, t.capacity, ct) for _ in range(G)]
                 self._run(t, reqs)
                 if progress:
@@ -245,6 +363,80 @@ class Server:
             self.batches.append((t.name, len(reqs), sum(r.n_images for r in reqs), t0, t1))
         return len(reqs)
 
+    # ---- lanes (GPU): stage-by-stage replay, admission at stage boundaries
+    def _admit(self, t, ln, reqs, clock):
+        """Copy the batch's input groups into the lane's buffer (after the work
+        that wrote them) and launch its first stages."""
+        import torch
+        need = sum(r.ct.lay.n_bg for r in reqs)
+        G = min(g for g in ln.graphs if g >= need)   # groups past `need` hold stale data; their outputs are dropped
+        x = ln.graphs[G][0]
+        ln.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(ln.stream):
+            off = 0
+            for r in reqs:
+                n = r.ct.buf.numel()
+                x.buf[off:off + n].copy_(r.ct.buf)
+                off += n
+        ln.reqs, ln.G, ln.next, ln.t_admit = reqs, G, 0, clock()
+        for r in reqs:
+            r.t_start = ln.t_admit
+        # the stage each other running batch of this tenant is executing
+        others = [o.next - len(o.events) for o in t.lanes if o is not ln and o.reqs is not None]
+        self.admissions.append((t.name, ln.t_admit, others))
+        self._advance(t, ln, clock)
+
+    def _advance(self, t, ln, clock, ahead=2):
+        """Retire finished stages, keep up to `ahead` stages queued; when the
+        last stage is done, hand out the outputs and free the lane."""
+        while ln.events and ln.events[0].query():
+            ln.events.popleft()
+        n_st = len(ln.graphs[ln.G][1])
+        while len(ln.events) < ahead and ln.next < n_st:
+            ln.launch()
+        if ln.next < n_st or ln.events:
+            return
+        import torch
+        reqs, out, G = ln.reqs, ln.graphs[ln.G][2], ln.G
+        if self.keep_outputs:   # the next replay overwrites the output buffer
+            per = out.n_ct // G * 2 * (out.lay.level + 1) * t.fe.N
+            g0 = 0
+            with torch.cuda.stream(ln.stream):
+                for r in reqs:
+                    g = r.ct.lay.n_bg
+                    lay = out.lay.copy()
+                    lay.n_bg, lay.bs = g, out.lay.bs // G * g
+                    r.out = F.Ciphertexts(t.fe, lay, out.buf[g0 * per:(g0 + g) * per].clone())
+                    g0 += g
+            ln.stream.synchronize()
+        t1 = clock()
+        ln.reqs = None
+        with self.mem:
+            self.in_flight -= sum(r.footprint for r in reqs)
+        with self.done_lock:
+            for r in reqs:
+                r.t_done = t1
+                self.done.append(r)
+            self.batches.append((t.name, len(reqs), sum(r.n_images for r in reqs), ln.t_admit, t1))
+
+    def lane_step(self, t, clock):
+        """One pass of tenant t's lane executor: advance every running batch,
+        then admit queued requests into a free lane.  Returns True if any lane
+        is busy."""
+        busy = False
+        for ln in t.lanes:
+            if ln.reqs is not None:
+                self._advance(t, ln, clock)
+                busy = busy or ln.reqs is not None
+        for ln in t.lanes:
+            if ln.reqs is None:
+                reqs = self._take(t)
+                if not reqs:
+                    break
+                self._admit(t, ln, reqs, clock)
+                busy = True
+        return busy
+
     def serve(self, arrivals, clock=time.perf_counter):
         """arrivals: list of (t_offset_seconds, Request) sorted by time.  One
         executor thread per tenant; the calling thread releases requests at
@@ -258,7 +450,10 @@ class Server:
         def worker(ts):
             try:
                 while not stop.is_set():
-                    if not sum(self.step(t, clock) for t in ts):
+                    if all(t.lanes for t in ts):
+                        if not any([self.lane_step(t, clock) for t in ts]):
+                            time.sleep(0.0002)
+                    elif not sum(self.step(t, clock) for t in ts):
                         time.sleep(0.0005)
             except Exception as e:   # reported by serve(); the other executors stop
                 errors.append(e)
@@ -318,12 +513,14 @@ def latency_summary(done):
 
 def main():
     """Serving benchmark: Poisson arrivals over LeNet-shaped, CIFAR-shaped and
-    MobileNet-block tenants; prints one JSON line with latency percentiles and
-    throughput."""
+    MobileNet-block tenants at one or more offered rates (the same warmed
+    server); prints one JSON line with latency percentiles and throughput per
+    rate."""
     import argparse
     import json
     ap = argparse.ArgumentParser()
-    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--rates", type=float, nargs="+", default=[200.0],
+                    help="offered request rates (requests/s), each a run of --duration seconds")
     ap.add_argument("--duration", type=float, default=5.0)
     ap.add_argument("--lenet-tenants", type=int, default=2)
     ap.add_argument("--cifar-tenants", type=int, default=1)
@@ -332,29 +529,35 @@ def main():
                     help="largest MobileNet request (two 224x224 images per batch group)")
     ap.add_argument("--max-batch", type=int, default=4)
     ap.add_argument("--cifar-capacity", type=int, default=64)
+    ap.add_argument("--lanes", type=int, default=2, help="pipeline lanes per tenant (0: eager runs, one per tenant)")
     ap.add_argument("--pool", type=int, default=4, help="distinct pre-encrypted requests per tenant")
     ap.add_argument("--seed", type=int, default=7)
     args = ap.parse_args()
     import torch
-    tenants = [Tenant(f"lenet{i}", "lenet", 11 + i, 64, args.max_batch) for i in range(args.lenet_tenants)]
-    tenants += [Tenant(f"cifar{i}", "cifar", 31 + i, args.cifar_capacity, 2) for i in range(args.cifar_tenants)]
-    tenants += [Tenant(f"mobilenet{i}", "mobilenet", 41 + i, 2, 1, max_groups=-(-args.mobilenet_max_images // 2))
-                for i in range(args.mobilenet_tenants)]
+    # every lane is a context with its own workspace: bound them so that all
+    # tenants' lanes, keys, plans and stage graphs fit in HBM together
+    ws = {"lenet": 6 << 30, "cifar": 12 << 30, "mobilenet": 8 << 30}
+    tenants = [Tenant(f"lenet{i}", "lenet", 11 + i, 64, args.max_batch, ws_limit=ws["lenet"])
+               for i in range(args.lenet_tenants)]
+    tenants += [Tenant(f"cifar{i}", "cifar", 31 + i, args.cifar_capacity, 2, ws_limit=ws["cifar"])
+                for i in range(args.cifar_tenants)]
+    tenants += [Tenant(f"mobilenet{i}", "mobilenet", 41 + i, 2, 1, max_groups=-(-args.mobilenet_max_images // 2),
+                       ws_limit=ws["mobilenet"]) for i in range(args.mobilenet_tenants)]
     srv = Server(tenants, keep_outputs=False)
     share = {"lenet": 0.6, "cifar": 0.3, "mobilenet": 0.1}
     count = {net: sum(t.net == net for t in tenants) for net in share}
     mix = {t.name: share[t.net] / count[t.net] for t in tenants}
     sizes = {t.name: (1, min(64, t.capacity * t.max_groups)) for t in tenants}
-    trace = poisson_trace(args.rate, args.duration, mix, sizes, args.seed)
-    # plans for every batch-group count a run can reach
+    # plans (and, with lanes, the stage graphs) for every batch-group count a run can reach
     t0 = time.perf_counter()
-    srv.warmup(progress=lambda n, G: print(
+    srv.warmup(lanes=args.lanes, progress=lambda n, G: print(
         f"warm-up {n}: {G} batch groups, {time.perf_counter() - t0:.1f}s, library GiB "
         f"{srv.tenants[n].fe.device_bytes() / 2**30:.1f}, torch GiB {torch.cuda.memory_reserved() / 2**30:.1f}",
         file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
-    held = {t.name: round(t.fe.device_bytes() / 2**30, 2) for t in tenants}
+    held = {t.name: round(sum(ln.fe.device_bytes() for ln in t.lanes) / 2**30 if t.lanes
+                          else t.fe.device_bytes() / 2**30, 2) for t in tenants}
     print(f"warm-up {t_warm:.1f}s; device GiB held per tenant {held}", file=sys.stderr, flush=True)
     # clients encrypt before sending (outside the served latency); each tenant
     # has a pool of distinct encrypted requests of its largest size, and an
@@ -362,31 +565,39 @@ def main():
     # the network never writes its input)
     pool = {t.name: [t.encrypt_request(W.images((t.capacity * t.max_groups,) + t.in_shape, seed=1000 + j),
                                        5000 + j) for j in range(args.pool)] for t in tenants}
-    arrivals = []
-    for i, (off, name, n) in enumerate(trace):
-        t = srv.tenants[name]
-        ct = t.leading_groups(pool[name][i % args.pool], t.groups_of(n))
-        arrivals.append((off, Request(i, name, n, ct)))
-    # the tenants' workspaces were sized in the warm-up; admission budgets what
+    # the workspaces and graphs were sized in the warm-up; admission budgets what
     # is left for the ciphertexts that runs allocate between layers
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     srv.budget = int(0.8 * torch.cuda.mem_get_info()[0])
-    torch.cuda.synchronize()
-    wall = srv.serve(arrivals)
-    res = latency_summary(srv.done)
-    res.update({"metric": "served encrypted images/s (continuous batching, per-tenant keys resident)",
-                "images_per_s": round(res["images"] / wall, 2), "wall_s": round(wall, 3),
-                "rate_req_per_s": args.rate, "batches": len(srv.batches),
-                "mean_batch": round(float(np.mean([b[1] for b in srv.batches])), 2),
-                "tenants": {t.name: t.net for t in tenants}, "warmup_s": round(t_warm, 1),
-                "device_GiB_after_warmup": held, "admission_budget_GiB": round(srv.budget / 2**30, 1),
-                "per_net": {}})
-    for net in ("lenet", "cifar", "mobilenet"):
-        d = [r for r in srv.done if srv.tenants[r.tenant].net == net]
-        if d:
-            res["per_net"][net] = latency_summary(d)
-    print(json.dumps(res), flush=True)
+    runs = []
+    for k, rate in enumerate(args.rates):
+        trace = poisson_trace(rate, args.duration, mix, sizes, args.seed + k)
+        arrivals = []
+        for i, (off, name, n) in enumerate(trace):
+            t = srv.tenants[name]
+            ct = t.leading_groups(pool[name][i % args.pool], t.groups_of(n))
+            arrivals.append((off, Request(i, name, n, ct)))
+        srv.done, srv.batches = [], []
+        torch.cuda.synchronize()
+        wall = srv.serve(arrivals)
+        res = latency_summary(srv.done)
+        offered = sum(n for _, _, n in trace) / args.duration
+        res.update({"rate_req_per_s": rate, "offered_images_per_s": round(offered, 1),
+                    "images_per_s": round(res["images"] / wall, 2), "wall_s": round(wall, 3),
+                    "batches": len(srv.batches), "mean_batch": round(float(np.mean([b[1] for b in srv.batches])), 2),
+                    "per_net": {}})
+        for net in ("lenet", "cifar", "mobilenet"):
+            d = [r for r in srv.done if srv.tenants[r.tenant].net == net]
+            if d:
+                res["per_net"][net] = latency_summary(d)
+        runs.append(res)
+        print(f"rate {rate}: {json.dumps(res)}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "served encrypted images/s (continuous batching, per-tenant keys resident)",
+                      "lanes_per_tenant": args.lanes, "tenants": {t.name: t.net for t in tenants},
+                      "warmup_s": round(t_warm, 1), "device_GiB_after_warmup": held,
+                      "admission_budget_GiB": round(srv.budget / 2**30, 1), "duration_s": args.duration,
+                      "runs": runs}), flush=True)
 
 
 if __name__ == "__main__":

@@ -56,6 +56,31 @@ def test_requests_batched_across_arrivals_match_each_alone(backend):
 
 
 @pytest.mark.parametrize("backend", BACKENDS)
+def test_served_request_equals_the_oracle(backend):
+    """A request served in a merged batch (on the GPU: replayed from a lane's
+    stage graphs) equals, word for word, the oracle's run of the same
+    encryption through the same network."""
+    from oracle import pyoracle as P
+    t = small_tenant("a", 25, backend)
+    srv = S.Server([t])
+    if backend == "hip":
+        srv.warmup(lanes=2)
+    xs = [W.images((n,) + t.in_shape, seed=330 + i) for i, n in enumerate((2, 1))]
+    reqs = [(0.0, S.Request(i, "a", len(x), t.encrypt_request(x, 930 + i))) for i, x in enumerate(xs)]
+    srv.serve(reqs)
+    assert len(srv.done) == 2
+    o = P.Oracle(*t.prm)
+    for (_, r), x, seed in zip(reqs, xs, (930, 931)):
+        full = np.zeros((t.capacity,) + t.in_shape)
+        full[:len(x)] = x
+        ob = o.encrypt_tensor(o.fragment_layout(t.capacity, *t.in_shape, t.block_size), full, seed)
+        for wi, st in zip(t.w, t.strides):
+            ob, _ = o.conv2d(ob, wi, st, wi.shape[2] // 2, 1, hoist=t.fe.hoist)
+            ob, _ = o.poly_act(ob, list(W.CUBIC))
+        assert np.array_equal(t.fe.export(r.out), ob.data())
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
 def test_admission_respects_the_memory_budget(backend):
     t = small_tenant("a", 23, backend, max_batch=4)
     x = W.images((1,) + t.in_shape, seed=5)
@@ -169,3 +194,40 @@ def test_mobilenet_tenant_requests_of_several_groups_at_full_size():
         want = np.polynomial.polynomial.polyval(
             cnn_ref.conv2d(x, t.w[0], layer["stride"], layer["pad"], layer["groups"]), W.QUADRATIC)
         assert np.max(np.abs(t.decrypt_request(r) - want.reshape(x.shape[0], -1))) < 1e-4
+
+
+@pytest.mark.gpu
+def test_lanes_admit_a_batch_while_another_is_at_a_later_layer():
+    """A LeNet-shaped tenant with two lanes (stage graphs, N = 2^15): a request
+    arriving while another batch of the same tenant is mid-network is admitted
+    at the next stage boundary into the free lane and runs concurrently; both
+    outputs equal their runs alone and the float64 network."""
+    import torch
+    t = S.Tenant("l", "lenet", 13, 64, 1)
+    srv = S.Server([t])
+    srv.warmup(lanes=2, group_counts={"l": [1]})
+    xs = [W.images((n, 1, 28, 28), seed=540 + i) for i, n in enumerate((64, 40))]
+    cts = [t.encrypt_request(x, 740 + i) for i, x in enumerate(xs)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a = S.Request(0, "l", 64, cts[0])
+    srv.submit(a)
+    srv.lane_step(t, time.perf_counter)                    # a: lane 0, first stages queued
+    ln0 = t.lanes[0]
+    while ln0.reqs is not None and ln0.next - len(ln0.events) < 3:
+        srv.lane_step(t, time.perf_counter)                # until a is executing its fourth stage or later
+    assert ln0.reqs is not None, "the first batch finished before the second could arrive"
+    b = S.Request(1, "l", 40, cts[1])
+    srv.submit(b)
+    srv.lane_step(t, time.perf_counter)
+    assert t.lanes[1].reqs == [b]                          # admitted into the free lane
+    assert srv.admissions[-1][2] and srv.admissions[-1][2][0] >= 3   # while a was at a later layer
+    while any(ln.reqs is not None for ln in t.lanes):
+        srv.lane_step(t, time.perf_counter)
+    assert len(srv.done) == 2 and time.perf_counter() > t0
+    for r, x in zip((a, b), xs):
+        alone = S.Request(r.rid, r.tenant, r.n_images, r.ct)
+        srv._run(t, [alone])
+        assert np.array_equal(t.fe.export(alone.out), t.fe.export(r.out))
+        want = cnn_ref.lenet(x, *t.w).reshape(r.n_images, -1)
+        assert np.max(np.abs(t.decrypt_request(r)[:, :want.shape[1]] - want)) < 1e-4
