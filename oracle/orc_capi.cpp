@@ -384,7 +384,7 @@ int orc_decrypt_tensor(void* c, void* bp, double* x) {
 // batch then holds them in that order (its layout is the full output's)
 void* orc_conv2d(void* c, void* bp, const double* w, int cout, int k, int stride, int pad, int groups,
                  long long pt_budget, int hoist, const OrcLayout* target, const double* bias, const int* outs,
-                 int n_outs, long* counts) {
+                 int n_outs, int baby, long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
@@ -393,7 +393,7 @@ void* orc_conv2d(void* c, void* bp, const double* w, int cout, int k, int stride
   if (target) T = from_c(target);
   std::vector<int> only(outs, outs + (n_outs > 0 ? n_outs : 0));
   out->cts = conv2d(*(Context*)c, in->L, in->cts, w, cout, k, stride, pad, groups, out->L, cnt, pt_budget, hoist,
-                    target ? &T : nullptr, bias, n_outs > 0 ? &only : nullptr);
+                    target ? &T : nullptr, bias, n_outs > 0 ? &only : nullptr, baby);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)

@@ -11,9 +11,10 @@
 //   conv2d            : eq. (multi-channel-conv) evaluated over fragment
 //                       ciphertexts: inner rotations (hoisted per input ct),
 //                       per-position masks and scalar weight codes, diagonal
-//                       outer rotations summed with a single ModDown, one
-//                       rescale; stride by discarding fragments (Evaluation
-//                       methodology, implementation paragraph).
+//                       outer rotations (plain or baby-step giant-step) summed
+//                       with a single ModDown, one rescale; stride by
+//                       discarding fragments (Evaluation methodology,
+//                       implementation paragraph).
 //   avgpool2          : average pooling as a fragment sum (S >= 2) or a
 //                       hoisted rotation sum (S = 1); the 1/4 is carried in
 //                       the scale.
@@ -378,7 +379,7 @@ std::vector<Ct> conv_into_target(Context& C, const Layout& Lin, const Layout& Ln
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
                        long long pt_budget, int hoist, const Layout* target, const double* bias,
-                       const std::vector<int>* only) {
+                       const std::vector<int>* only, int baby) {
   if (Lin.kind != KIND_FRAGMENT || Lin.dil != 1) throw std::runtime_error("conv2d: needs a dense fragment layout");
   if (stride < 1 || Lin.S % stride) throw std::runtime_error("conv2d: stride must divide S");
   const int cin = Lin.c;
@@ -421,6 +422,25 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
     return false;
   };
 
+  // Outer rotations by baby-step giant-step (Motivation, HE multi-channel
+  // convolution, which assumes BSGS): with baby step n1 the diagonal r =
+  // i + n1 j contributes Rot(z_r, r s) = Rot(Rot(z_r, i s), n1 j s), and
+  // Rot(c (.) P, i s) = Rot(c, i s) (.) Rot(P, i s).  So each term's copy is
+  // also rotated by i s (extra hoisted rotations of the same source), its
+  // plaintext is encoded rotated by i s, the products are summed into the
+  // giant-step accumulator Z_j, and y = sum_j Rot(Z_j, n1 j s) takes n2 - 1
+  // rotations per output instead of C' - 1.  n1 = 1 is the plain form.
+  if (baby < 1) throw std::runtime_error("conv2d: baby step must be at least 1");
+  if (target && baby != 1) throw std::runtime_error("conv2d: a target layout takes the plain outer rotations");
+  const int n1 = std::min(baby, nd), n2 = (nd + n1 - 1) / n1;
+  const long s_outer = (long)m * m * bsg;   // the slot shift between consecutive diagonals
+  auto rot_vec = [&](const std::vector<double>& z, int i) {   // Rot(z, i s_outer)
+    if (i == 0) return z;
+    std::vector<double> r(C.ns);
+    for (int x = 0; x < C.ns; x++) r[x] = z[posmod((long)x + (long)i * s_outer, C.ns)];
+    return r;
+  };
+
   const int So = Lout.S, ncg_out = Lout.ncg;
   std::vector<std::vector<Term>> terms(Lin.nbg * ncg_out * So * So);
   // the outputs computed (all, or the listed ones with only their input cone)
@@ -447,7 +467,16 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
                 t.idx = ((bg * Lin.ncg + gi) * S + t.u) * S + t.v;
                 t.shift = posmod(((long)t.dbi * m + t.dbj) * bsg, C.ns);
                 terms[oct].push_back(t);
-                if (t.shift && sel[oct]) need[t.idx].insert(t.shift);
+                if (!sel[oct]) continue;
+                // baby steps i this term feeds: r = i (mod n1) for a connected (q, r)
+                for (int i = 0; i < n1; i++) {
+                  bool used = false;
+                  for (int q = 0; q < npos && !used; q++)
+                    for (int r = i; r < nd && !used; r += n1)
+                      used = pair_ok(in_channel(gi, q), go * cpc + posmod(q - r, cpc));
+                  const long sh = posmod(t.shift + (long)i * s_outer, C.ns);
+                  if (used && sh) need[t.idx].insert(sh);
+                }
               }
           }
         }
@@ -483,7 +512,8 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
     for (size_t oct = 0; oct < terms.size(); oct++)
       if (sel[oct])
         for (const Term& t : terms[oct])
-          if (!t.shift) un.insert(t.idx);
+          for (int i = 0; i < n1; i++)
+            if (!posmod(t.shift + (long)i * s_outer, C.ns)) un.insert(t.idx);
     std::vector<int> ul(un.begin(), un.end());
     std::vector<Ct> lv(ul.size());
     par_for((int)ul.size(), [&](int j) { lv[j] = lift_pq(C, in[ul[j]]); });
@@ -513,8 +543,8 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
   // masks: source pixel inside the logical input, restricted to position q
   std::map<std::vector<int>, RPoly> masks;
   std::mutex mask_mu;   // the cache is shared by the output threads (map nodes stay put)
-  auto mask = [&](const Term& t, int q) -> const RPoly& {
-    std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q};
+  auto mask = [&](const Term& t, int q, int i) -> const RPoly& {   // rotated by i baby steps
+    std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q, i};
     std::lock_guard<std::mutex> lock(mask_mu);
     auto it = masks.find(key);
     if (it != masks.end()) return it->second;
@@ -525,7 +555,7 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
         if (gh < 0 || gh >= Lin.h || gw < 0 || gw >= Lin.w) continue;
         for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = 1.0;
       }
-    return masks[key] = encode(C, z, {}, dm, basis);
+    return masks[key] = encode(C, rot_vec(z, i), {}, dm, basis);
   };
   // the all-ones plaintext at dm: its integer polynomial is checked to be the
   // constant round(dm) (every other coefficient zero) and that constant is used
@@ -558,13 +588,13 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
           if (!sel[oct]) return;
           const int go = (oct / (So * So)) % ncg_out;
           Counts lc;
-          std::vector<Ct> z(nd, zero_ct(C, lvl, Lin.scale * dw * dm));
+          std::vector<Ct> z(n2, zero_ct(C, lvl, Lin.scale * dw * dm));   // giant-step accumulators
           if (hoist)
             for (Ct& zr : z) {
               zr.c0 = poly_zero(C, basis);
               zr.c1 = poly_zero(C, basis);
             }
-          std::vector<bool> act(nd, false);
+          std::vector<bool> act(n2, false);
           // The plaintext products of one output are independent: with fewer
           // outputs than threads they are made a chunk at a time in parallel
           // and added in a fixed order (sums mod q are exact either way).
@@ -580,7 +610,7 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
           };
           if (materialise) {
             std::vector<std::pair<const Term*, int>> tr;   // (term, diagonal) pairs with a plaintext
-            std::vector<std::vector<double>> dzs;
+            std::vector<std::vector<double>> dzs;          // their diagonals, rotated by r mod n1 baby steps
             for (const Term& t : terms[oct])
               for (int r = 0; r < nd; r++) {
                 std::vector<double> dz(C.ns, 0.0);
@@ -600,67 +630,71 @@ std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in,
                 }
                 if (!any) continue;
                 tr.push_back({&t, r});
-                dzs.push_back(std::move(dz));
+                dzs.push_back(rot_vec(dz, r % n1));
               }
             products(
                 (int)tr.size(),
                 [&](int j) {
                   const Term& t = *tr[j].first;
-                  return mul_plain(C, source(t.idx, t.shift), encode(C, dzs[j], {}, T, basis), T);
+                  const long sh = posmod(t.shift + (long)(tr[j].second % n1) * s_outer, C.ns);
+                  return mul_plain(C, source(t.idx, sh), encode(C, dzs[j], {}, T, basis), T);
                 },
                 [&](int j, const Ct& p) {
-                  act[tr[j].second] = true;
-                  add_inplace(C, z[tr[j].second], p);
+                  act[tr[j].second / n1] = true;
+                  add_inplace(C, z[tr[j].second / n1], p);
                   lc.pmult++;
                 });
           } else {
-            std::vector<std::pair<const Term*, int>> tq;   // (term, position) pairs feeding some diagonal
+            struct TQ { const Term* t; int q, i; };   // (term, position, baby step) feeding some diagonal
+            std::vector<TQ> tq;
             for (const Term& t : terms[oct])
               for (int q = 0; q < npos; q++) {
                 const int ch = in_channel(t.gi, q);
-                bool any = false;
-                for (int r = 0; r < nd; r++) any |= pair_ok(ch, go * cpc + posmod(q - r, cpc));
-                if (any) tq.push_back({&t, q});
+                for (int i = 0; i < n1; i++) {
+                  bool any = false;
+                  for (int r = i; r < nd; r += n1) any |= pair_ok(ch, go * cpc + posmod(q - r, cpc));
+                  if (any) tq.push_back({&t, q, i});
+                }
               }
             products(
                 (int)tq.size(),
                 [&](int j) {
-                  const Term& t = *tq[j].first;
-                  const Ct& copy = source(t.idx, t.shift);
-                  // the all-ones vector encodes to the constant polynomial round(dm):
-                  // multiplying by it is multiplying by that integer
-                  return need_mask ? mul_plain(C, copy, mask(t, tq[j].second), dm)
+                  const Term& t = *tq[j].t;
+                  const Ct& copy = source(t.idx, posmod(t.shift + (long)tq[j].i * s_outer, C.ns));
+                  // the all-ones vector encodes to the constant polynomial round(dm)
+                  // (also rotated): multiplying by it is multiplying by that integer
+                  return need_mask ? mul_plain(C, copy, mask(t, tq[j].q, tq[j].i), dm)
                                    : mul_scalar(C, copy, ones_const(), dm);
                 },
                 [&](int j, const Ct& mc) {
-                  const Term& t = *tq[j].first;
-                  const int q = tq[j].second, ch = in_channel(t.gi, q);
+                  const Term& t = *tq[j].t;
+                  const int q = tq[j].q, ch = in_channel(t.gi, q);
                   lc.pmult++;
-                  for (int r = 0; r < nd; r++) {
+                  for (int r = tq[j].i; r < nd; r += n1) {
                     const int o = go * cpc + posmod(q - r, cpc);
                     if (!pair_ok(ch, o)) continue;
                     const int grp = o / gout;
                     double wv = w[(((long)o * gin + (ch - grp * gin)) * k + t.di) * k + t.dj];
                     i64 code = weight_code(wv, dw);
-                    act[r] = true;
+                    act[r / n1] = true;
                     if (code == 0) continue;
-                    add_inplace(C, z[r], mul_scalar(C, mc, code, dw));
+                    add_inplace(C, z[r / n1], mul_scalar(C, mc, code, dw));
                     lc.smult++;
                   }
                 });
           }
           if (hoist)
-            for (int r = 0; r < nd; r++)
-              if (act[r]) {
-                z[r] = mod_down_ct(C, z[r]);
+            for (int j = 0; j < n2; j++)
+              if (act[j]) {
+                z[j] = mod_down_ct(C, z[j]);
                 lc.moddown++;
               }
           std::vector<const Ct*> zs;
           std::vector<i64> sh;
-          for (int r = 1; r < nd; r++)
-            if (act[r]) {
-              zs.push_back(&z[r]);
-              sh.push_back((i64)r * m * m * bsg);
+          for (int j = 1; j < n2; j++)
+            if (act[j]) {
+              zs.push_back(&z[j]);
+              sh.push_back((i64)j * n1 * s_outer);
             }
           Ct y;
           if (zs.empty()) {

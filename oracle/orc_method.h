@@ -54,7 +54,7 @@ void decrypt_decode(Context& C, const Layout& L, const std::vector<Ct>& cts, dou
 std::vector<Ct> conv2d(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                        int cout, int k, int stride, int pad, int groups, Layout& Lout, Counts& cnt,
                        long long pt_budget = 1LL << 30, int hoist = 0, const Layout* target = nullptr,
-                       const double* bias = nullptr, const std::vector<int>* only = nullptr);
+                       const double* bias = nullptr, const std::vector<int>* only = nullptr, int baby = 1);
 // hoist = 1: rotated copies stay in the extended basis and each combined
 // ciphertext is moved down once (see conv2d)
 std::vector<Ct> avgpool2(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,

@@ -87,7 +87,7 @@ def _declare(L):
         "orc_batch_layout": (None, [vp, C.POINTER(OrcLayout)]),
         "orc_batch_data": (i, [vp, vp, u64p]),
         "orc_decrypt_tensor": (i, [vp, vp, f64p]),
-        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, i, C.POINTER(OrcLayout), vp, vp, i,
+        "orc_conv2d": (vp, [vp, vp, f64p, i, i, i, i, i, C.c_longlong, i, C.POINTER(OrcLayout), vp, vp, i, i,
                             C.POINTER(C.c_long)]),
         "orc_avgpool2": (vp, [vp, vp, i, C.POINTER(C.c_long)]),
         "orc_pq_roundtrip": (i, [vp, u64p, i, vp, i, i, u64p]),
@@ -358,20 +358,22 @@ class Oracle:
         return Batch(self, h), dict(zip(COUNT_FIELDS, list(cnt)))
 
     def conv2d(self, batch, w, stride=1, pad=0, groups=1, pt_budget=1 << 30, hoist=0, target=None, bias=None,
-               outputs=None):
+               outputs=None, baby=1):
         """hoist=1: the linear combination is taken in the extended basis Q_l U P
         and each combined ciphertext is moved down once.  target: a layout dict
         of the output tensor the result is written into (the repack fused with
         the convolution); bias: cout values added after the rescale; outputs:
         compute only these output ciphertexts (their input cone), returned as
-        an array [len(outputs)][2][level+1][N] instead of a batch."""
+        an array [len(outputs)][2][level+1][N] instead of a batch; baby: the
+        baby step n1 of the outer rotations' baby-step giant-step form (1: the
+        plain form, C' - 1 rotations per output)."""
         w = np.ascontiguousarray(w, np.float64)
         t, keep = (None, None) if target is None else dict_to_layout(target)
         b = None if bias is None else np.ascontiguousarray(bias, np.float64)
         outs = None if outputs is None else np.ascontiguousarray(outputs, np.int32)
         res = self._op(lib().orc_conv2d, batch.h, w, w.shape[0], w.shape[2], stride, pad, groups, pt_budget,
                        hoist, None if t is None else C.byref(t), None if b is None else b.ctypes.data,
-                       None if outs is None else outs.ctypes.data, 0 if outs is None else len(outs))
+                       None if outs is None else outs.ctypes.data, 0 if outs is None else len(outs), baby)
         if outs is None:
             return res
         bat, cnt = res

@@ -419,3 +419,27 @@ def test_conv2d_output_subset_equals_the_full_output():
         sub, cs = o.conv2d(b, w, 1, 1, 1, pt_budget=budget, hoist=1, bias=bias, outputs=[3, 0])
         assert np.array_equal(sub, full.data()[[3, 0]])
         assert cs["inner_rot"] < c["inner_rot"]
+
+
+@pytest.mark.parametrize("n1", [1, 2, 4, 16])
+@pytest.mark.parametrize("k", [1, 3])
+def test_conv2d_bsgs_outer_rotations_counts_and_decryption(k, n1):
+    """Outer rotations by baby-step giant-step (Motivation, HE multi-channel
+    convolution).  16 channels on 4x4 maps at N = 2^10 (S = 1, m = 4, one image)
+    are replicated twice per ciphertext, so C' = 16 diagonals, shifted by
+    s = m^2 = 16 slots each.  With baby step n1 an output takes ceil(16/n1) - 1
+    giant-step rotations; the input takes one hoisted rotation per distinct
+    nonzero shift (kernel shift + i s, i < n1).  Every form decrypts to the
+    float64 convolution."""
+    o = small_oracle(nq=3, logN=10)
+    L = o.fragment_layout(1, 16, 4, 4, 1)
+    assert (L["cpc"], L["rep"], L["m"], L["bsg"]) == (32, 1, 4, 1)
+    x, w = rand_x((1, 16, 4, 4), 31), rand_w((16, 16, k, k), 32)
+    b = o.encrypt_tensor(L, x, seed=3)
+    y, cnt = o.conv2d(b, w, 1, k // 2, 1, baby=n1)
+    assert cnt["outer_rot"] == -(-16 // n1) - 1
+    shifts = {(a * 4 + c + 16 * i) % o.ns for a in range(-(k // 2), k // 2 + 1)
+              for c in range(-(k // 2), k // 2 + 1) for i in range(n1)}
+    assert cnt["inner_rot"] == len(shifts - {0})
+    ref = cnn_ref.conv2d(x, w, 1, k // 2)
+    assert np.max(np.abs(o.decrypt_tensor(y) - ref)) < 1e-4
