@@ -180,7 +180,7 @@ def run_conv1(args):
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["conv1_small"])
-    fe.set_hoisting(W.BENCH_HOISTING)
+    W.bench_config(fe)
     x, w = W.conv1_inputs()
     lay = fe.plan_layout(1, 1, 28, 28, 5, 6)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
@@ -193,7 +193,7 @@ def run_lenet(args):
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["lenet"])
-    fe.set_hoisting(W.BENCH_HOISTING)
+    W.bench_config(fe)
     x, w = W.lenet_inputs(64)
     lay = W.lenet_layout(fe, 64)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
@@ -208,7 +208,7 @@ def run_cifar(args):
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["cifar"])
-    fe.set_hoisting(W.BENCH_HOISTING)
+    W.bench_config(fe)
     x, w = W.cifar_inputs(256)
     lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
@@ -224,7 +224,7 @@ def mobilenet_context(batch):
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["cifar"])
     fe.set_workspace_limit(WORKSPACE_LIMIT)
-    fe.set_hoisting(W.BENCH_HOISTING)
+    W.bench_config(fe)
     t0 = time.time()
     cts = W.mobilenet_encrypt(fe, batch)
     log(f"[mobilenet] encode+encrypt of {batch} images: {time.time() - t0:.1f}s")
@@ -276,13 +276,13 @@ def workload_step(workload, batch):
         return fe, lambda: W.mobilenet_forward(fe, cts, ws)
     if workload == "cifar":
         fe = F.Fenc(*W.PARAMS["cifar"])
-        fe.set_hoisting(W.BENCH_HOISTING)
+        W.bench_config(fe)
         x, w = W.cifar_inputs(256)
         lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
         ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
         return fe, lambda: W.cifar_forward(fe, ct, w)
     fe = F.Fenc(*W.PARAMS["lenet"])
-    fe.set_hoisting(W.BENCH_HOISTING)
+    W.bench_config(fe)
     x, w = W.lenet_inputs(64)
     lay = W.lenet_layout(fe, 64)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)

@@ -395,6 +395,23 @@ int fenc_set_hoisting(fenc_ctx* ctx, int mode);
  * copies), -1 before any; with mode 2 this is how a caller learns, and can
  * reproduce elsewhere, the schedule a layer's plan chose. */
 int fenc_last_hoisting(const fenc_ctx* ctx);
+/* Outer rotations of a convolution by baby-step giant-step (Motivation, HE
+ * multi-channel convolution, eq. multi-channel-conv, which assumes BSGS).
+ * The C' diagonals z_r of an output are rotated by r s (s = m^2 BS_g slots)
+ * and summed.  With baby step n1, diagonal r = i + n1 j is formed from copies
+ * rotated by i s more (extra hoisted rotations of the same inputs, shared by
+ * every output) and from plaintexts encoded rotated by i s, summed into the
+ * giant-step accumulator j, and y = sum_j Rot(Z_j, n1 j s): n2 - 1 = ceil(C'/n1)
+ * - 1 rotations per output instead of C' - 1, against up to n1 - 1 more per
+ * input copy.  n1 >= 1 fixes the baby step (1, the default: the plain form;
+ * larger values are capped at C'); 0 chooses, per layer, the power of two up
+ * to C' with the fewest key switches (ties: the smaller), kept in the cached
+ * plan.  A convolution fused with a repack (s_out > 0) uses the plain form.
+ * The baby step changes the residues; the oracle takes the same parameter.
+ * fenc_last_baby_step: the baby step of the most recent fenc_conv2d, -1
+ * before any.  Errors: EINVAL for n1 < 0. */
+int fenc_set_baby_step(fenc_ctx* ctx, int n1);
+int fenc_last_baby_step(const fenc_ctx* ctx);
 /* NTT pass shapes, 8 ints: for [forward columns, forward rows, inverse rows,
  * inverse columns] the radix bits of a register round (3: radix 8, 4: radix
  * 16) and the log2 of the columns (column pass) or chunks (row pass) a block

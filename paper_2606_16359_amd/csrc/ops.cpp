@@ -391,6 +391,7 @@ static void run_sum_stage(Ctx& C, int level, const SumStage& S, const u64* z, u6
 // ---------------------------------------------------------------- conv2d
 struct ConvPlan : Plan {
   int level = 0, n_in = 0, n_out = 0, n_zr = 0;
+  int n1 = 1;        // baby step of the outer rotations (1: plain, C' - 1 rotations per output)
   bool pq = false;   // linear combinations in the extended basis, one ModDown per combined ciphertext
   RotStage rot;
   GmacStage g0, gr;
@@ -406,7 +407,7 @@ struct ConvPlan : Plan {
 // convolution, see below); bias: cout values added at the output scale.
 static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout, int k, int stride, int pad,
                             int groups, int s_out, const double* bias, bool shape_only, Layout& Lout,
-                            bool pq = false) {
+                            bool pq = false, int baby = 1) {
   if (Lin.kind != FENC_LAYOUT_FRAGMENT || Lin.dil != 1) fail(FENC_ELAYOUT, "conv2d needs a dense fragment layout");
   if (k < 1 || stride < 1 || pad < 0 || cout < 1) fail(FENC_EINVAL, "bad convolution shape");
   if (Lin.S % stride) fail(FENC_EUNSUPPORTED, "stride must divide the block size");
@@ -437,6 +438,18 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   P->n_in = Lin.n_ct();
   P->pq = pq;
   const int nd = Lin.rep ? cin : cpc;
+  // outer rotations in baby-step giant-step form (see run_conv): diagonal
+  // r = i + n1 j sums into the giant-step accumulator j from copies rotated by
+  // i more diagonal shifts, with plaintexts encoded rotated by as much
+  const int n1 = fused ? 1 : std::max(1, std::min(baby, nd)), n2 = (nd + n1 - 1) / n1;
+  const long long s_outer = (long long)m * m * bsg;
+  P->n1 = n1;
+  auto rot_slots = [&](std::vector<double> z, int i) {   // Rot(z, i s_outer)
+    if (i == 0) return z;
+    std::vector<double> r(C.ns);
+    for (int x = 0; x < C.ns; x++) r[x] = z[posmod((long long)x + (long long)i * s_outer, C.ns)];
+    return r;
+  };
   // masks per channel position when a ciphertext holds several positions or the
   // kernel reads padding; T is always split into a weight scale dw and a
   // plaintext scale dm, so weight codes stay small (the all-ones plaintext at
@@ -451,6 +464,12 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   auto term_active = [&](int go, int gi) {
     for (int q = 0; q < npos; q++)
       for (int r = 0; r < nd; r++)
+        if (pair_ok(in_channel(gi, q), go * cpc + posmod(q - r, cpc))) return true;
+    return false;
+  };
+  auto baby_used = [&](int go, int gi, int i) {   // some (q, r = i mod n1) pair connects go and gi
+    for (int q = 0; q < npos; q++)
+      for (int r = i; r < nd; r += n1)
         if (pair_ok(in_channel(gi, q), go * cpc + posmod(q - r, cpc))) return true;
     return false;
   };
@@ -476,7 +495,10 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
                 t.idx = ((bg * Lin.ncg + gi) * S + t.u) * S + t.v;
                 t.shift = posmod(((long long)t.dbi * m + t.dbj) * bsg, C.ns);
                 terms[oct].push_back(t);
-                if (t.shift) copy_id[{t.idx, t.shift}] = 0;
+                for (int i = 0; i < n1; i++) {
+                  const long long sh = posmod(t.shift + (long long)i * s_outer, C.ns);
+                  if (sh && (n1 == 1 || baby_used(go, gi, i))) copy_id[{t.idx, sh}] = 0;
+                }
               }
           }
         }
@@ -523,8 +545,8 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   // give the same one, and their terms then share a group)
   std::map<std::vector<int>, int> mask_id;
   PtSet mset;
-  auto mask_of = [&](const Term& t, int q) {
-    std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q};
+  auto mask_of = [&](const Term& t, int q, int i) {   // rotated by i baby steps
+    std::vector<int> key = {t.u, t.v, t.dbi, t.dbj, q, i};
     auto it = mask_id.find(key);
     if (it != mask_id.end()) return it->second;
     std::vector<double> z(C.ns, 0.0);
@@ -533,7 +555,7 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
         if (!valid_src(t, bi, bj)) continue;
         for (int jb = 0; jb < bsg; jb++) z[((q * m + bi) * m + bj) * bsg + jb] = 1.0;
       }
-    return mask_id[key] = mset.id(std::move(z));
+    return mask_id[key] = mset.id(rot_slots(std::move(z), i));
   };
   auto ones_id = [&]() {
     const std::vector<int> key = {-1};
@@ -556,23 +578,27 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   // groups[o][r]: plaintext id -> terms (input id, weight id); plaintext ids index
   // mask_slots (mask-basis) or diag_slots (materialised, one term per group)
   typedef std::map<int, std::vector<std::pair<int, int>>> Groups;
-  std::vector<std::vector<Groups>> G(fused ? 0 : P->n_out, std::vector<Groups>(nd));
-  std::vector<std::vector<char>> act(fused ? 0 : P->n_out, std::vector<char>(nd, 0));
+  std::vector<std::vector<Groups>> G(fused ? 0 : P->n_out, std::vector<Groups>(n2));   // per giant step
+  std::vector<std::vector<char>> act(fused ? 0 : P->n_out, std::vector<char>(n2, 0));
   std::vector<std::vector<double>> diag_slots;
   std::map<std::tuple<int, int, int>, int> diag_id;   // (output of group 0, term, diagonal) -> plaintext
   for (int oct = 0; oct < (fused ? 0 : P->n_out); oct++) {
     const int go = (oct / (So * So)) % ncg_out;
     for (size_t ti = 0; ti < terms[oct].size(); ti++) {
       const Term& t = terms[oct][ti];
-      // pq: unrotated inputs enter lifted (P x) after the copies in the B buffer
-      const int in_id = t.shift ? P->n_in + copy_id[{t.idx, t.shift}]
-                                : (P->pq ? P->n_in + (int)copies.size() + t.idx : t.idx);
+      // the input of this term for baby step i; pq: unrotated inputs enter
+      // lifted (P x) after the copies in the B buffer
+      auto in_id_of = [&](int i) {
+        const long long sh = posmod(t.shift + (long long)i * s_outer, C.ns);
+        return sh ? P->n_in + copy_id.at({t.idx, sh}) : (P->pq ? P->n_in + (int)copies.size() + t.idx : t.idx);
+      };
       if (materialise) {
         for (int r = 0; r < nd; r++) {
+          const int in_id = in_id_of(r % n1), jg = r / n1;
           auto known = diag_id.find(std::make_tuple(oct % out_per_bg, (int)ti, r));
           if (known != diag_id.end()) {
-            act[oct][r] = 1;
-            G[oct][r][known->second].push_back({in_id, -1});
+            act[oct][jg] = 1;
+            G[oct][jg][known->second].push_back({in_id, -1});
             P->n_terms++;
             continue;
           }
@@ -589,10 +615,10 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
               }
           }
           if (z.empty()) continue;
-          act[oct][r] = 1;
+          act[oct][jg] = 1;
           diag_id[std::make_tuple(oct % out_per_bg, (int)ti, r)] = (int)diag_slots.size();
-          G[oct][r][(int)diag_slots.size()].push_back({in_id, -1});
-          diag_slots.push_back(std::move(z));
+          G[oct][jg][(int)diag_slots.size()].push_back({in_id, -1});
+          diag_slots.push_back(rot_slots(std::move(z), r % n1));
           P->n_terms++;
         }
         continue;
@@ -602,10 +628,10 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
         for (int r = 0; r < nd; r++) {
           const int o = go * cpc + posmod(q - r, cpc);
           if (!pair_ok(ch, o)) continue;
-          act[oct][r] = 1;
+          act[oct][r / n1] = 1;
           const int64_t code = weight_code(wval(o, ch, t), dw);   // zero codes kept: shared structure
-          const int mid = need_mask ? mask_of(t, q) : ones_id();
-          G[oct][r][mid].push_back({in_id, weight_id(code)});
+          const int mid = need_mask ? mask_of(t, q, r % n1) : ones_id();
+          G[oct][r / n1][mid].push_back({in_id_of(r % n1), weight_id(code)});
           P->n_terms++;
         }
       }
@@ -712,10 +738,10 @@ static ConvPlan* build_conv(Ctx& C, const Layout& Lin, const double* w, int cout
   for (int o = 0; o < (fused ? 0 : P->n_out); o++) {
     emit(b0, G[o][0]);
     std::vector<std::pair<int, long long>> tl;
-    for (int r = 1; r < nd; r++)
-      if (act[o][r]) {
-        emit(br, G[o][r]);
-        tl.push_back({P->n_zr++, (long long)r * m * m * bsg});
+    for (int j = 1; j < n2; j++)
+      if (act[o][j]) {
+        emit(br, G[o][j]);
+        tl.push_back({P->n_zr++, (long long)j * n1 * s_outer});
       }
     if (!tl.empty()) {
       sum_out.push_back(o);
@@ -1354,46 +1380,78 @@ static T& cached(Ctx& C, const std::string& key, F build) {
 // mask-basis form (one per output, tap and (channel position, diagonal) pair
 // that connects an input channel to an output channel).  Shapes only.
 static void conv_keyswitches(const Ctx& C, const Layout& Lin, int cout, int k, int stride, int pad, int groups,
-                             long long& inner, long long& outer, long long& terms) {
+                             long long& inner, long long& outer, long long& terms, int n1 = 1) {
   const int cin = Lin.c, S = Lin.S, m = Lin.m, bsg = Lin.bsg, cpc = Lin.cpc;
   const int gin = cin / groups, gout = cout / groups, So = S / stride, ncg_out = (cout + cpc - 1) / cpc;
   const int nd = Lin.rep ? cin : cpc, npos = ((cpc > 1) || (pad > 0)) ? cpc : 1;
+  n1 = std::max(1, std::min(n1, nd));
+  const int n2 = (nd + n1 - 1) / n1;
+  const long long s_outer = (long long)m * m * bsg;
   auto in_channel = [&](int gi, int q) { return Lin.rep ? q % cin : gi * cpc + q; };
   auto pair_ok = [&](int ch, int o) { return ch < cin && o < cout && ch / gin == o / gout; };
   std::set<std::pair<int, long long>> copies;
   inner = outer = terms = 0;
   for (int bg = 0; bg < Lin.nbg; bg++)
     for (int go = 0; go < ncg_out; go++) {
-      std::vector<char> act(nd, 0);   // diagonals with a term, the same for every (uo, vo)
+      std::vector<char> act(n2, 0);   // giant steps with a term, the same for every (uo, vo)
       std::vector<int> gis;
-      long long pairs = 0;            // (q, r) pairs of the active input groups
+      std::vector<std::vector<int>> babies;   // per active input group: the baby steps it feeds
+      long long pairs = 0;                    // (q, r) pairs of the active input groups
       for (int gi = 0; gi < Lin.ncg; gi++) {
-        bool any = false;
+        std::vector<char> used(n1, 0);
         for (int q = 0; q < npos; q++)
           for (int r = 0; r < nd; r++)
             if (pair_ok(in_channel(gi, q), go * cpc + posmod(q - r, cpc))) {
-              act[r] = 1;
-              any = true;
+              act[r / n1] = 1;
+              used[r % n1] = 1;
               pairs++;
             }
-        if (any) gis.push_back(gi);
+        std::vector<int> b;
+        for (int i = 0; i < n1; i++)
+          if (used[i]) b.push_back(i);
+        if (!b.empty()) {
+          gis.push_back(gi);
+          babies.push_back(b);
+        }
       }
       for (int uo = 0; uo < So; uo++)
         for (int vo = 0; vo < So; vo++) {
           terms += pairs * k * k;
           if (!gis.empty())
-            for (int r = 1; r < nd; r++) outer += act[r];
-          for (int gi : gis)
+            for (int j = 1; j < n2; j++) outer += act[j];
+          for (size_t g = 0; g < gis.size(); g++)
             for (int di = 0; di < k; di++)
               for (int dj = 0; dj < k; dj++) {
                 const int a = uo * stride + di - pad, b = vo * stride + dj - pad;
                 const int u = posmod(a, S), dbi = floordiv(a, S), v = posmod(b, S), dbj = floordiv(b, S);
                 const long long shift = posmod(((long long)dbi * m + dbj) * bsg, C.ns);
-                if (shift) copies.insert({((bg * Lin.ncg + gi) * S + u) * S + v, shift});
+                for (int i : babies[g]) {
+                  const long long sh = posmod(shift + (long long)i * s_outer, C.ns);
+                  if (sh) copies.insert({((bg * Lin.ncg + gis[g]) * S + u) * S + v, sh});
+                }
               }
         }
     }
   inner = (long long)copies.size();
+}
+
+// The baby step of a convolution's outer rotations under the context's
+// setting: a fixed one, or (setting 0) the power of two up to C' with the
+// fewest key switches (ties: the smaller).
+static int conv_baby(const Ctx& C, const Layout& Lin, int cout, int k, int stride, int pad, int groups) {
+  const int nd = Lin.rep ? Lin.c : Lin.cpc;
+  if (C.baby > 0) return std::min(C.baby, nd);
+  int best = 1;
+  long long best_ks = -1;
+  for (int n1 = 1; n1 <= nd; n1 *= 2) {
+    long long a = 0, b = 0, t = 0;
+    conv_keyswitches(C, Lin, cout, k, stride, pad, groups, a, b, t, n1);
+    if (best_ks < 0 || a + b < best_ks) {
+      best_ks = a + b;
+      best = n1;
+    }
+  }
+  return best;
 }
 
 // Key switches of a rot-mask-add repack from Ls to Ld: one hoisted rotation
@@ -1502,7 +1560,8 @@ static NetPlan plan_network(const Ctx& C, int bs, int c, int h, int w, const fen
               continue;
             }
             long long in = 0, out = 0, tm = 0;
-            conv_keyswitches(C, Lc, ly.cout, ly.k, ly.stride, ly.pad, ly.groups, in, out, tm);
+            conv_keyswitches(C, Lc, ly.cout, ly.k, ly.stride, ly.pad, ly.groups, in, out, tm,
+                             conv_baby(C, Lc, ly.cout, ly.k, ly.stride, ly.pad, ly.groups));
             St ns{Lo, st.p};
             ns.p.S.push_back(Lc.S);
             ns.p.ks += sv.second + in + out;
@@ -1817,7 +1876,7 @@ int fenc_conv2d_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, uint32_t
   Layout Lin = from_pub(*ctx, in), Lo;
   build_conv(*(Ctx*)ctx, Lin, nullptr, cout, k, stride, pad, groups, 0, nullptr, true, Lo);   // shape checks
   long long a = 0, b = 0, t = 0;
-  conv_keyswitches(*ctx, Lin, cout, k, stride, pad, groups, a, b, t);
+  conv_keyswitches(*ctx, Lin, cout, k, stride, pad, groups, a, b, t, conv_baby(*ctx, Lin, cout, k, stride, pad, groups));
   *inner = a;
   *outer = b;
   if (mac_terms) *mac_terms = t;
@@ -2092,13 +2151,14 @@ int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const do
     const Layout Ls = sub_layout(Lin, cnt);
     std::ostringstream key;
     key << "conv|" << layout_key(Ls) << '|' << cout << ',' << k << ',' << stride << ',' << pad << ',' << groups << ','
-        << wh << ',' << bh << ',' << s_out << ',' << C.pt_budget << ',' << C.hoist;
+        << wh << ',' << bh << ',' << s_out << ',' << C.pt_budget << ',' << C.hoist << ',' << C.baby;
     return cached<ConvPlan>(C, key.str(), [&] {
+      const int n1 = s_out > 0 ? 1 : conv_baby(C, Ls, cout, k, stride, pad, groups);
       return build_hoisted<ConvPlan>(
           C,
           [&](bool pq) {
             Layout lo;
-            return build_conv(C, Ls, w, cout, k, stride, pad, groups, s_out, bias, false, lo, pq);
+            return build_conv(C, Ls, w, cout, k, stride, pad, groups, s_out, bias, false, lo, pq, n1);
           },
           [&](const ConvPlan& P) {
             const double mw = mac_words(P.g0) + mac_words(P.gr);
@@ -2121,6 +2181,7 @@ int fenc_conv2d(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const do
     const ConvPlan& P = plan_of(std::min(tile, Lin.nbg - b0));
     run_conv(C, P, in->data + b0 * in_step, out->data + b0 * out_step, (fb::Stream)stream);
     C.last_hoist = P.pq;
+    C.last_baby = P.n1;
   }
   API_END
 }
@@ -2430,6 +2491,15 @@ int fenc_set_hoisting(fenc_ctx* ctx, int mode) {
 }
 
 int fenc_last_hoisting(const fenc_ctx* ctx) { return ctx ? ctx->last_hoist : -1; }
+
+int fenc_set_baby_step(fenc_ctx* ctx, int n1) {
+  API_BEGIN
+  if (!ctx || n1 < 0) fail(FENC_EINVAL, "baby step must be 0 (chosen per layer) or at least 1");
+  ctx->baby = n1;
+  API_END
+}
+
+int fenc_last_baby_step(const fenc_ctx* ctx) { return ctx ? ctx->last_baby : -1; }
 
 int fenc_ntt_config(fenc_ctx* ctx, int32_t* out) {
   API_BEGIN

@@ -196,6 +196,8 @@ struct fenc_ctx {
   // combined ciphertext, 0 = one ModDown per rotated copy
   int hoist = 1;        // hoisting schedule: 0, 1, or 2 (per layer, the smaller modelled traffic)
   int last_hoist = -1;  // schedule of the most recent convolution, pooling or compression
+  int baby = 1;         // baby step of convolutions' outer rotations: n >= 1 fixed, 0 chosen per layer
+  int last_baby = -1;   // baby step of the most recent convolution
   // single-kernel profiling: events around every launch of `prof_kernel`
   std::string prof_kernel;
   struct ProfRec {

@@ -128,6 +128,8 @@ def load(path=None):
         "fenc_ntt_config": (C.c_int, [vp, vp]),
         "fenc_set_hoisting": (C.c_int, [vp, C.c_int]),
         "fenc_last_hoisting": (C.c_int, [vp]),
+        "fenc_set_baby_step": (C.c_int, [vp, C.c_int]),
+        "fenc_last_baby_step": (C.c_int, [vp]),
         "fenc_set_ntt_config": (C.c_int, [vp, vp]),
         "fenc_sample_word": (u64, [u64, u64, u64]),
         "fenc_sample_gauss": (C.c_int, [u64, u64, u64]),
@@ -226,6 +228,15 @@ class Fenc:
         (last_hoisting() tells which one a layer ran with)."""
         self._check(self.lib.fenc_set_hoisting(self.h, mode))
         self.hoist = mode
+
+    def set_baby_step(self, n1):
+        """Baby step of convolutions' outer rotations: 1 (default) the plain
+        form, n1 > 1 fixed, 0 chosen per layer by key-switch count."""
+        self._check(self.lib.fenc_set_baby_step(self.h, n1))
+
+    def last_baby_step(self):
+        """Baby step the most recent conv2d ran with."""
+        return self.lib.fenc_last_baby_step(self.h)
 
     def last_hoisting(self):
         """Schedule (0/1) of the most recent conv2d / avgpool2 / compress."""

@@ -22,6 +22,16 @@ SEED_INPUT, SEED_WEIGHTS, SEED_ENC = 1, 2, 4
 # hoisting mode of the benchmark configurations: 2, each layer's plan takes
 # the schedule with the smaller modelled HBM traffic
 BENCH_HOISTING = 2
+# baby step of the convolutions' outer rotations: 0, chosen per layer by
+# key-switch count (the plain form wherever C' <= 2, as in these networks)
+BENCH_BABY_STEP = 0
+
+
+def bench_config(fenc):
+    """The benchmark configurations' per-layer schedule choices on a context."""
+    fenc.set_hoisting(BENCH_HOISTING)
+    fenc.set_baby_step(BENCH_BABY_STEP)
+    return fenc
 
 
 def images(shape, seed=SEED_INPUT):

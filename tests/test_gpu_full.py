@@ -11,7 +11,7 @@ def lenet():
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["lenet"])
-    fe.set_hoisting(W.BENCH_HOISTING)   # the benchmark's per-layer schedule choice
+    W.bench_config(fe)   # the benchmark's per-layer schedule choice
     x, w = W.lenet_inputs(64)
     lay = W.lenet_layout(fe, 64)          # the benchmark's block size (chain planner)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
@@ -59,7 +59,7 @@ def test_graph_replay_survives_workspace_growth():
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["lenet"])
-    fe.set_hoisting(W.BENCH_HOISTING)   # the benchmark's per-layer schedule choice
+    W.bench_config(fe)   # the benchmark's per-layer schedule choice
     x, w = W.lenet_inputs(64)
     lay = fe.plan_layout(64, 1, 28, 28, 5, 6)
     ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
@@ -95,10 +95,10 @@ def test_lenet_every_layer_matches_oracle_at_full_size(lenet):
     ob = o.encrypt_tensor(o.fragment_layout(64, 1, 28, 28, lay.S), x, W.SEED_ENC)
     assert np.array_equal(fe.export(ct), ob.data())
     # h: the schedule the library's layer ran with
-    steps = [("conv1", lambda c: fe.conv2d(c, w[0]), lambda b, h: o.conv2d(b, w[0], hoist=h)),
+    steps = [("conv1", lambda c: fe.conv2d(c, w[0]), lambda b, h: o.conv2d(b, w[0], hoist=h, baby=fe.last_baby_step())),
              ("x^2", lambda c: fe.poly_act(c), lambda b, h: o.poly_act(b, [0.0, 0.0, 1.0])),
              ("pool1", fe.avgpool2, lambda b, h: o.avgpool2(b, hoist=h)),
-             ("conv2", lambda c: fe.conv2d(c, w[1]), lambda b, h: o.conv2d(b, w[1], hoist=h)),
+             ("conv2", lambda c: fe.conv2d(c, w[1]), lambda b, h: o.conv2d(b, w[1], hoist=h, baby=fe.last_baby_step())),
              ("x^2", lambda c: fe.poly_act(c), lambda b, h: o.poly_act(b, [0.0, 0.0, 1.0])),
              ("pool2", fe.avgpool2, lambda b, h: o.avgpool2(b, hoist=h)),
              ("compress", fe.compress, lambda b, h: o.compress(b, hoist=h)),
@@ -136,7 +136,7 @@ def test_cifar_first_layer_and_cubic_sampled_cones_match_oracle():
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["cifar"])
-    fe.set_hoisting(W.BENCH_HOISTING)
+    W.bench_config(fe)
     o = P.Oracle(*W.PARAMS["cifar"])
     x, w = W.cifar_inputs(256)
     lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
@@ -150,7 +150,8 @@ def test_cifar_first_layer_and_cubic_sampled_cones_match_oracle():
     outs = sorted(np.random.default_rng(2026).choice(128, 2, replace=False).tolist())
     y = fe.conv2d(ct, w[0], pad=1)
     t0 = time.time()
-    yo, cnt = o.conv2d(o.batch(Lo, xin), w[0], 1, 1, 1, hoist=fe.last_hoisting(), outputs=outs)
+    yo, cnt = o.conv2d(o.batch(Lo, xin), w[0], 1, 1, 1, hoist=fe.last_hoisting(), outputs=outs,
+                       baby=fe.last_baby_step())
     print(f"oracle cone of outputs {outs} (schedule {fe.last_hoisting()}): {cnt}, {time.time() - t0:.1f}s",
           flush=True)
     del xin
@@ -172,7 +173,7 @@ def test_mobilenet_block_a_sampled_cones_match_oracle():
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
     fe = F.Fenc(*W.PARAMS["cifar"])
-    fe.set_hoisting(W.BENCH_HOISTING)
+    W.bench_config(fe)
     o = P.Oracle(*W.PARAMS["cifar"])
     blk = W.MOBILENET_BLOCKS[0][0]
     wa = W.mobilenet_weights()[0][0]
@@ -185,7 +186,8 @@ def test_mobilenet_block_a_sampled_cones_match_oracle():
     y = fe.conv2d(ct, wa, stride=blk["stride"], pad=blk["pad"])
     outs = sorted(np.random.default_rng(2027).choice(y.n_ct, 2, replace=False).tolist())
     t0 = time.time()
-    yo, cnt = o.conv2d(o.batch(Lo, xin), wa, blk["stride"], blk["pad"], 1, hoist=fe.last_hoisting(), outputs=outs)
+    yo, cnt = o.conv2d(o.batch(Lo, xin), wa, blk["stride"], blk["pad"], 1, hoist=fe.last_hoisting(), outputs=outs,
+                       baby=fe.last_baby_step())
     print(f"oracle cone of outputs {outs} (schedule {fe.last_hoisting()}): {cnt}, {time.time() - t0:.1f}s",
           flush=True)
     del xin

@@ -521,3 +521,45 @@ def test_cifar_shaped_stack_small_bit_exact(backend):
     cmp(fb, ob, f)
     assert fb.lay.level == 11 - 9
     assert np.max(np.abs(f.decrypt(fb) - ref)) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("case", [dict(x=(1, 16, 4, 4), w=(16, 16, 1, 1), pad=0),
+                                  dict(x=(1, 16, 4, 4), w=(16, 16, 3, 3), pad=1),
+                                  dict(x=(2, 8, 8, 8), w=(8, 8, 3, 3), pad=1)])
+@pytest.mark.parametrize("n1", [1, 2, 4, 0])
+@pytest.mark.parametrize("budget,hoist", [(1 << 30, 1), (0, 0)])
+def test_conv_bsgs_outer_rotations_bit_exact(backend, case, n1, budget, hoist, orc):
+    """Outer rotations by baby-step giant-step: a fixed baby step or the
+    per-layer choice (0) gives the oracle's words for the same baby step, in
+    both plaintext forms and both hoisting schedules; the key switches equal
+    the oracle's and the no-build count, and the choice is the count's
+    minimum over powers of two."""
+    o, f = orc, make(backend, *SMALL)
+    f.set_baby_step(n1)
+    f.set_plaintext_budget(budget)
+    f.set_hoisting(hoist)
+    r = rng(41)
+    x, w = r.uniform(0, 1, case["x"]), r.normal(0, 0.1, case["w"])
+    lay = f.plan_layout(*case["x"], case["w"][2], case["w"][0], 1)
+    ob, fb = o.encrypt_tensor(o.fragment_layout(*case["x"], 1), x, 5), f.encrypt(f.encode_fragment(x, lay), lay, 5)
+    inner, outer, _ = f.conv2d_keyswitches(lay, case["w"][0], case["w"][2], 1, case["pad"])
+    f.stats_reset()
+    yf = f.conv2d(fb, w, 1, case["pad"])
+    nb = f.last_baby_step()
+    nd = lay.chan_per_ct if not lay.replicate else case["x"][1]
+    assert nb == (min(n1, nd) if n1 else nb)
+    yo, cnt = o.conv2d(ob, w, 1, case["pad"], 1, pt_budget=budget, hoist=f.last_hoisting(), baby=nb)
+    cmp(yf, yo, f)
+    st = f.stats()
+    assert (st["rot_inner"], st["rot_outer"]) == (cnt["inner_rot"], cnt["outer_rot"]) == (inner, outer)
+    if n1 == 0:
+        ks = {}
+        for p in (1, 2, 4, 8, 16, 32):
+            if p <= nd:
+                f.set_baby_step(p)
+                a, b, _ = f.conv2d_keyswitches(lay, case["w"][0], case["w"][2], 1, case["pad"])
+                ks[p] = a + b
+        assert inner + outer == min(ks.values()) and nb == min(p for p in ks if ks[p] == min(ks.values()))
+    ref = cnn_ref.conv2d(x, w, 1, case["pad"])
+    assert np.max(np.abs(f.decrypt(yf) - ref)) < 1e-4
