@@ -316,6 +316,13 @@ int orc_fragment_layout(void* c, int bs, int ch, int h, int w, int S, OrcLayout*
   GUARD_END(-1)
 }
 
+int orc_token_layout(void* c, int n, int E, int S, OrcLayout* out) {
+  GUARD_BEGIN
+  to_c(token_layout(*(Context*)c, n, E, S), out);
+  return 0;
+  GUARD_END(-1)
+}
+
 int orc_element_slots(const OrcLayout* lay, int b, int ch, int hh, int ww, int* out, int cap) {
   GUARD_BEGIN
   Layout L = from_c(lay);

@@ -127,10 +127,48 @@ Layout plan_layout(const Context& C, int bs, int c, int h, int w, int k_next, in
   return fragment_layout(C, bs, c, h, w, best);
 }
 
+// Token embeddings split into S fragments (Discussions, extensibility to
+// Transformers): the n x E input becomes n x (E/S) x S and each fragment goes
+// to its own ciphertexts, so a ciphertext holds E/S features of S times more
+// tokens than full-embedding packing.  Feature e lies in fragment s = e mod S
+// at position p = e div S; a fragment takes ncg = ceil(ceil(E/S)/d)
+// ciphertexts of d positions; slot = (p mod d) bsg + token in its group, with
+// bsg tokens per ciphertext (a power of two, d bsg = N/2).
+Layout token_layout(const Context& C, int n, int E, int S, int group) {
+  if (n < 1 || E < 1 || S < 1 || S > E) throw std::runtime_error("token_layout: bad shape");
+  const int per = (E + S - 1) / S;   // positions of the largest fragment
+  int d0 = 1;
+  while (d0 < per && d0 < C.ns) d0 <<= 1;
+  int bsg = 1;   // tokens per ciphertext: the given grouping (a layer's output keeps its input's), or the most that fit
+  if (group > 0) {
+    if (group & (group - 1) || group > C.ns) throw std::runtime_error("token_layout: bad token grouping");
+    bsg = group;
+  } else {
+    while (bsg * 2 <= n && (long)bsg * 2 * d0 <= C.ns) bsg <<= 1;
+  }
+  Layout L;
+  L.kind = KIND_TOKENS;
+  L.bs = n; L.c = E; L.h = 1; L.w = 1;
+  L.M = 1; L.m = 1; L.S = S; L.cpc = 1; L.rep = 0; L.dil = 1;
+  L.bsg = bsg;
+  L.d = C.ns / bsg;
+  L.ncg = (per + L.d - 1) / L.d;
+  L.nbg = (n + bsg - 1) / bsg;
+  L.nfeat = E;
+  L.level = C.L;
+  L.scale = delta_of(C);
+  return L;
+}
+
 void element_slots(const Layout& L, int b, int ch, int hh, int ww,
                    std::vector<std::pair<int, int>>& out) {
   out.clear();
   const int bg = b / L.bsg, jb = b % L.bsg;
+  if (L.kind == KIND_TOKENS) {
+    const int s = ch % L.S, p = ch / L.S;
+    out.push_back({(bg * L.S + s) * L.ncg + p / L.d, (p % L.d) * L.bsg + jb});
+    return;
+  }
   if (L.kind == KIND_VECTOR) {
     int f = (ch * L.h + hh) * L.w + ww;
     out.push_back({bg, L.pos[f] * L.bsg + jb});
@@ -1052,8 +1090,112 @@ std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& i
   return compress_to(C, Lin, in, vector_target(C, Lin), Lout, cnt, hoist);
 }
 
+// A linear layer on token fragments: every output ciphertext (fragment s',
+// chunk k') is the sum over the input ciphertexts (s, k) of the diagonal
+// product with the weights of the features they hold,
+// W_{(s,k),(s',k')}[i][j] = w[e' = ((k' d + i) S + s')][e = ((k d + j) S + s)],
+// by baby-step giant-step over d: y = sum_g Rot(sum_{(s,k), b}
+// diag'_{g,b} (.) Rot(x_{s,k}, b bsg), g n1 bsg).  Baby steps are hoisted
+// once per input ciphertext and shared by every output; each output sums all
+// inputs before its giant steps, one lazy ModDown.
+static std::vector<Ct> token_fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w, int dout,
+                                Layout& Lout, Counts& cnt, const double* bias) {
+  const int S = Lin.S, d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level, kin = Lin.ncg;
+  Lout = token_layout(C, Lin.bs, dout, S, bsg);
+  Lout.level = lvl - 1;
+  Lout.scale = delta_of(C);
+  const int kout = Lout.ncg;
+  int e = 0;
+  while ((1 << e) < d) e++;
+  const int n1 = 1 << ((e + 1) / 2), n2 = d / n1;
+  const double dp = ((double)C.primes[lvl] * delta_of(C)) / Lin.scale;
+  const int ni = S * kin, no = S * kout;   // ciphertexts per token group
+  // block (input ct a = s k_in + k, output ct o = s' k_out + k'): entry [i][j]
+  auto wv = [&](int a, int o, int i, int j) -> double {
+    const int s = a / kin, k = a % kin, s2 = o / kout, k2 = o % kout;
+    const long ein = ((long)(k * d + j)) * S + s, eout = ((long)(k2 * d + i)) * S + s2;
+    if (ein >= din || eout >= dout) return 0.0;
+    return w[eout * din + ein];
+  };
+  auto diag_active = [&](int a, int o, int kd) {
+    for (int i = 0; i < d; i++)
+      if (wv(a, o, i, (i + kd) % d) != 0.0) return true;
+    return false;
+  };
+  // active (input, output, diagonal) triples; baby steps per input, giant steps per output
+  std::vector<std::vector<std::vector<char>>> act(ni, std::vector<std::vector<char>>(no, std::vector<char>(d, 0)));
+  par_for(ni * no, [&](int ao) {
+    for (int kd = 0; kd < d; kd++) act[ao / no][ao % no][kd] = diag_active(ao / no, ao % no, kd);
+  });
+  std::vector<std::vector<char>> baby(ni, std::vector<char>(n1, 0)), giant(no, std::vector<char>(n2, 0));
+  for (int a = 0; a < ni; a++)
+    for (int o = 0; o < no; o++)
+      for (int kd = 0; kd < d; kd++)
+        if (act[a][o][kd]) {
+          baby[a][kd % n1] = 1;
+          giant[o][kd / n1] = 1;
+        }
+  auto plain = [&](int a, int o, int g, int b) {   // diagonal g n1 + b, rotated right by g n1 positions
+    const int kd = g * n1 + b;
+    std::vector<double> z(C.ns, 0.0);
+    for (int l = 0; l < C.ns; l++) {
+      const int i = posmod((long)l - (long)g * n1 * bsg, C.ns) / bsg;
+      z[l] = wv(a, o, i, (i + kd) % d);
+    }
+    return encode(C, z, {}, dp, q_basis(lvl));
+  };
+  std::vector<Ct> out(Lin.nbg * no);
+  for (int bg = 0; bg < Lin.nbg; bg++) {
+    // baby steps of every input ciphertext, hoisted
+    std::vector<std::vector<Ct>> xr(ni);
+    std::vector<std::vector<const Ct*>> xb(ni, std::vector<const Ct*>(n1, nullptr));
+    par_for(ni, [&](int a) {
+      std::vector<i64> bsh;
+      for (int b = 1; b < n1; b++)
+        if (baby[a][b]) bsh.push_back((i64)b * bsg);
+      if (!bsh.empty()) xr[a] = rotate_hoisted(C, in[bg * ni + a], bsh);
+    });
+    for (int a = 0; a < ni; a++) {
+      xb[a][0] = &in[bg * ni + a];
+      int j = 0;
+      for (int b = 1; b < n1; b++)
+        if (baby[a][b]) {
+          xb[a][b] = &xr[a][j++];
+          cnt.other_rot++; cnt.ks++; cnt.moddown++;
+        }
+      if (j) cnt.modup++;
+    }
+    par_for(no, [&](int o) {
+      std::vector<Ct> u(n2, zero_ct(C, lvl, Lin.scale * dp));
+      for (int g = 0; g < n2; g++)
+        for (int a = 0; a < ni; a++)
+          for (int b = 0; b < n1; b++)
+            if (act[a][o][g * n1 + b]) add_inplace(C, u[g], mul_plain(C, *xb[a][b], plain(a, o, g, b), dp));
+      std::vector<const Ct*> zs;
+      std::vector<i64> sh;
+      for (int g = 1; g < n2; g++)
+        if (giant[o][g]) { zs.push_back(&u[g]); sh.push_back((i64)g * n1 * bsg); }
+      Ct y = zs.empty() ? u[0] : rotate_sum_lazy(C, giant[o][0] ? &u[0] : nullptr, zs, sh);
+      y.scale = Lin.scale * dp;
+      y = rescale(C, y);
+      y.scale = Lout.scale;
+      out[bg * no + o] = y;
+    });
+    for (int o = 0; o < no; o++) {
+      int ng = 0;
+      for (int g = 1; g < n2; g++) ng += giant[o][g];
+      cnt.other_rot += ng; cnt.ks += ng; cnt.modup += ng; cnt.moddown += ng ? 1 : 0; cnt.rescale++;
+      for (int a = 0; a < ni; a++)
+        for (int kd = 0; kd < d; kd++) cnt.pmult += act[a][o][kd];
+    }
+  }
+  if (bias) add_bias(C, Lout, out, bias);
+  return out;
+}
+
 std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
                    int dout, Layout& Lout, Counts& cnt, const double* bias) {
+  if (Lin.kind == KIND_TOKENS) return token_fc(C, Lin, in, w, dout, Lout, cnt, bias);
   if (Lin.kind != KIND_VECTOR) throw std::runtime_error("fc: needs a vector layout");
   const int d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level;
   if (dout > d) throw std::runtime_error("fc: output larger than the vector");

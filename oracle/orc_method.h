@@ -4,7 +4,7 @@
 
 namespace orc {
 
-enum { KIND_FRAGMENT = 0, KIND_VECTOR = 1 };
+enum { KIND_FRAGMENT = 0, KIND_VECTOR = 1, KIND_TOKENS = 2 };
 
 struct Layout {
   int kind = KIND_FRAGMENT;
@@ -18,13 +18,19 @@ struct Layout {
   double scale = 1.0;
   int d = 0, nfeat = 0;              // vector layout: positions, features
   std::vector<int> pos;              // vector layout: feature -> position
-  int n_ct() const { return kind == KIND_FRAGMENT ? nbg * ncg * S * S : nbg; }
+  // KIND_TOKENS (token embeddings split into S fragments): bs tokens, c = E
+  // features, S fragments of ncg ciphertexts each, d positions per token
+  int n_ct() const { return kind == KIND_FRAGMENT ? nbg * ncg * S * S : kind == KIND_TOKENS ? nbg * S * ncg : nbg; }
 };
 
 // eq. (total-rot) with the convention that reproduces the optimal-S table
 double rot_total_formula(double BS, double Nin, double Nout, double K, double S, double alpha);
 double rot_inner_formula_eq(double Nin, double K, double S, double M, double alpha);   // eq. (inner) as printed
 double optimal_S_closed_form(double K, double Nin, double Nout, double alpha, double BS);
+
+// Token-fragment layout (Discussions, extensibility to Transformers): n tokens
+// of E features, feature e in fragment e mod S at position e div S
+Layout token_layout(const Context& C, int n, int E, int S, int group = 0);
 
 Layout plan_layout(const Context& C, int bs, int c, int h, int w, int k_next, int cout_next,
                    int s_override);

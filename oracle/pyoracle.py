@@ -79,6 +79,7 @@ def _declare(L):
         "orc_optimal_S": (d, [d, d, d, d, d]),
         "orc_plan_layout": (i, [vp, i, i, i, i, i, i, i, C.POINTER(OrcLayout)]),
         "orc_fragment_layout": (i, [vp, i, i, i, i, i, C.POINTER(OrcLayout)]),
+        "orc_token_layout": (i, [vp, i, i, i, C.POINTER(OrcLayout)]),
         "orc_element_slots": (i, [C.POINTER(OrcLayout), i, i, i, i, C.POINTER(C.c_int), i]),
         "orc_encrypt_tensor": (vp, [vp, C.POINTER(OrcLayout), f64p, u]),
         "orc_encode_tensor": (i, [vp, C.POINTER(OrcLayout), f64p, u64p]),
@@ -314,6 +315,13 @@ class Oracle:
         lay = OrcLayout()
         lay.pos = C.POINTER(C.c_int)()
         _check(lib().orc_fragment_layout(self.h, bs, c, h, w, S, C.byref(lay)))
+        return layout_to_dict(lay)
+
+    def token_layout(self, n, E, S):
+        """Token embeddings of E features, n tokens, split into S fragments
+        (feature e in fragment e mod S at position e div S)."""
+        lay = OrcLayout()
+        _check(lib().orc_token_layout(self.h, n, E, S, C.byref(lay)))
         return layout_to_dict(lay)
 
     def element_slots(self, layout, b, ch, hh, ww):

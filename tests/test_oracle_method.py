@@ -443,3 +443,76 @@ def test_conv2d_bsgs_outer_rotations_counts_and_decryption(k, n1):
     assert cnt["inner_rot"] == len(shifts - {0})
     ref = cnn_ref.conv2d(x, w, 1, k // 2)
     assert np.max(np.abs(o.decrypt_tensor(y) - ref)) < 1e-4
+
+
+def test_token_fragment_layout_places_features_by_fragment():
+    """Token embeddings split into S fragments (Discussions, extensibility to
+    Transformers): feature e of token t lies in fragment e mod S at position
+    e div S, so a ciphertext holds E/S features of S times more tokens than
+    full-embedding packing."""
+    o = small_oracle(nq=3, logN=10)
+    for n, E, S in [(8, 48, 1), (8, 48, 4), (16, 40, 8), (4, 200, 2)]:
+        L = o.token_layout(n, E, S)
+        per = -(-E // S)
+        d0 = 1 << (per - 1).bit_length()
+        assert L["kind"] == 2 and L["d"] * L["bsg"] == o.ns and L["d"] >= min(d0, o.ns)
+        assert L["ncg"] == -(-per // L["d"]) and L["nbg"] == -(-n // L["bsg"])
+        seen = set()
+        for t in range(n):
+            for e in range(E):
+                (ct, sl), = o.element_slots(L, t, e, 0, 0)
+                p = e // S
+                assert ct == ((t // L["bsg"]) * S + e % S) * L["ncg"] + p // L["d"]
+                assert sl == (p % L["d"]) * L["bsg"] + t % L["bsg"]
+                seen.add((ct, sl))
+        assert len(seen) == n * E
+
+
+def test_token_fc_with_one_fragment_is_the_vector_fc():
+    """With S = 1 the token layout is the FC vector layout (identity positions):
+    the token-fragment linear layer gives the vector FC's words."""
+    o = small_oracle(nq=3, logN=10)
+    x, w = rand_x((8, 24), 41), rand_w((20, 24), 42)
+    Lt = o.token_layout(8, 24, 1)
+    Lv = dict(Lt)
+    Lv.update(kind=1, pos=list(range(24)))
+    yt, ct = o.fc(o.encrypt_tensor(Lt, x.reshape(8, 24, 1, 1), 5), w)
+    yv, cv = o.fc(o.encrypt_tensor(Lv, x.reshape(8, 24, 1, 1), 5), w)
+    assert np.array_equal(yt.data(), yv.data())
+    assert (ct["other_rot"], ct["ks"]) == (cv["other_rot"], cv["ks"])
+
+
+@pytest.mark.parametrize("n,E,E2,S", [(8, 48, 32, 4), (16, 64, 64, 8), (8, 24, 96, 2), (4, 32, 160, 1)])
+def test_token_fc_decrypts_and_counts_rotations(n, E, E2, S):
+    """A linear layer E -> E2 (with bias) on token fragments decrypts to
+    x W^T + b within 1e-4, also where an output fragment spans several
+    ciphertexts; per token group it takes S k_in (n1 - 1) baby-step and
+    S k_out (n2 - 1) giant-step rotations, n1 n2 = d."""
+    o = small_oracle(nq=3, logN=10)
+    x, w, b = rand_x((n, E), 43), rand_w((E2, E), 44), rand_w((E2,), 45)
+    L = o.token_layout(n, E, S)
+    y, cnt = o.fc(o.encrypt_tensor(L, x.reshape(n, E, 1, 1), 6), w, bias=b)
+    Ly = y.layout()
+    assert (Ly["kind"], Ly["S"], Ly["bsg"]) == (2, S, L["bsg"]) and Ly["level"] == L["level"] - 1
+    got = o.decrypt_tensor(y).reshape(n, E2)
+    assert np.max(np.abs(got - (x @ w.T + b))) < 1e-4
+    # brute force over the layout: the live diagonals of block (input ct a,
+    # output ct o) are (j - i) mod d for used positions j of a and i of o; an
+    # input takes a baby rotation per nonzero kd mod n1 it feeds, an output a
+    # giant rotation per nonzero kd div n1 it receives
+    d, kin, kout = L["d"], L["ncg"], Ly["ncg"]
+    e = (d - 1).bit_length()
+    n1 = 1 << ((e + 1) // 2)
+    used = lambda k, s, F: [j for j in range(d) if (k * d + j) * S + s < F]
+    babies, giants = 0, {}
+    for s in range(S):
+        for k in range(kin):
+            b = set()
+            for s2 in range(S):
+                for k2 in range(kout):
+                    kds = {(j - i) % d for j in used(k, s, E) for i in used(k2, s2, E2)}
+                    b |= {kd % n1 for kd in kds}
+                    giants.setdefault((s2, k2), set()).update(kd // n1 for kd in kds)
+            babies += len(b - {0})
+    assert cnt["other_rot"] == L["nbg"] * (babies + sum(len(g - {0}) for g in giants.values()))
+    assert babies <= S * kin * (n1 - 1)
