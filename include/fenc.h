@@ -77,7 +77,7 @@ typedef struct {
   uint64_t seed;
 } fenc_params;
 
-enum { FENC_LAYOUT_FRAGMENT = 0, FENC_LAYOUT_VECTOR = 1 };
+enum { FENC_LAYOUT_FRAGMENT = 0, FENC_LAYOUT_VECTOR = 1, FENC_LAYOUT_TOKENS = 2 };
 
 /* Slot layout of an encrypted tensor [bs][c][h][w].
  * FRAGMENT (Alg. fragment-packing): M = next power of two >= max(h, w),
@@ -89,7 +89,14 @@ enum { FENC_LAYOUT_FRAGMENT = 0, FENC_LAYOUT_VECTOR = 1 };
  *   c < C' channels are repeated in every group of c positions.
  * VECTOR (FC input/output): one ciphertext per batch group, feature f of the
  *   flattened [c][h][w] tensor at slot pos[f]*bs_g + b%bs_g with d = (N/2)/bs_g
- *   positions; pos is the context-owned map map_id (0: identity). */
+ *   positions; pos is the context-owned map map_id (0: identity).
+ * TOKENS (Discussions, extensibility to Transformers): bs tokens of c = E
+ *   features (h = w = 1), each embedding split into S fragments: feature e
+ *   goes to fragment e%S at position p = e/S; a fragment spans n_cg
+ *   ciphertexts of d = (N/2)/bs_g positions; element (t, e) sits in
+ *   ciphertext ((t/bs_g * S + e%S) * n_cg + p/d) at slot (p%d)*bs_g + t%bs_g.
+ *   A ciphertext holds E/S features of S times more tokens than one holding
+ *   whole embeddings. */
 typedef struct {
   int32_t kind;
   int32_t bs, c, h, w;
@@ -243,6 +250,12 @@ int fenc_conv2d_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, uint32_t
                             int64_t* mac_terms);
 int fenc_compress_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, const fenc_layout* target,
                               int64_t* keyswitches);
+/* TOKENS layout of n tokens with E features split into S fragments (S <= E),
+ * at the top level and scale Delta.  group > 0 fixes the tokens per
+ * ciphertext (a power of two; a linear layer's output keeps its input's);
+ * 0 takes the most that fit the largest fragment's next power of two of
+ * positions.  Host only.  Errors: EINVAL for a bad shape or grouping. */
+int fenc_plan_tokens(const fenc_ctx* ctx, uint32_t n, uint32_t E, uint32_t S, uint32_t group, fenc_layout* out);
 int fenc_layout_n_ct(const fenc_layout* lay);
 int64_t fenc_ct_bytes(const fenc_ctx* ctx, const fenc_layout* lay);
 /* First (ciphertext, slot) of element (b, ch, y, x).  Host only. */

@@ -116,6 +116,16 @@ def _check(rc):
     return rc
 
 
+def layout_n_ct(L):
+    """Ciphertexts of a layout: S^2 per (batch group, channel group) for
+    fragments, S per chunk of a token group, one per group for vectors."""
+    if L["kind"] == 0:
+        return L["nbg"] * L["ncg"] * L["S"] ** 2
+    if L["kind"] == 2:
+        return L["nbg"] * L["S"] * L["ncg"]
+    return L["nbg"]
+
+
 def layout_to_dict(lay, pos=None):
     d = {k: getattr(lay, k) for k in LAYOUT_FIELDS}
     d["pos"] = list(pos[:lay.nfeat]) if (pos is not None and lay.kind == 1) else None
@@ -155,8 +165,7 @@ class Batch:
 
     def data(self):
         L = self.layout()
-        n = L["kind"] == 0 and L["nbg"] * L["ncg"] * L["S"] ** 2 or L["nbg"]
-        out = np.zeros((n, 2, L["level"] + 1, self.orc.N), np.uint64)
+        out = np.zeros((layout_n_ct(L), 2, L["level"] + 1, self.orc.N), np.uint64)
         lib().orc_batch_data(self.orc.h, self.h, out)
         return out
 
@@ -332,8 +341,7 @@ class Oracle:
 
     def encode_tensor(self, layout, x):
         lay, keep = dict_to_layout(layout)
-        n = layout["nbg"] * layout["ncg"] * layout["S"] ** 2
-        out = np.zeros((n, layout["level"] + 1, self.N), np.uint64)
+        out = np.zeros((layout_n_ct(layout), layout["level"] + 1, self.N), np.uint64)
         _check(lib().orc_encode_tensor(self.h, C.byref(lay), np.ascontiguousarray(x, np.float64), out))
         return out
 

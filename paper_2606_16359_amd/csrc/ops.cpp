@@ -89,9 +89,43 @@ Layout plan_fragment(int ns, int level, double scale, int bs, int c, int h, int 
   return make_fragment(ns, level, scale, bs, c, h, w, best);
 }
 
+// Token embeddings split into S fragments (Discussions, extensibility to
+// Transformers): feature e in fragment e mod S at position e div S, tokens
+// innermost; group > 0 keeps a given number of tokens per ciphertext.
+Layout make_tokens(int ns, int level, double scale, int n, int E, int S, int group) {
+  if (n < 1 || E < 1 || S < 1 || S > E) fail(FENC_EINVAL, "bad token tensor or fragment count");
+  const int per = (E + S - 1) / S;
+  int d0 = 1;
+  while (d0 < per && d0 < ns) d0 <<= 1;
+  int bsg = 1;
+  if (group > 0) {
+    if ((group & (group - 1)) || group > ns) fail(FENC_EINVAL, "tokens per ciphertext must be a power of two");
+    bsg = group;
+  } else {
+    while (bsg * 2 <= n && (long long)bsg * 2 * d0 <= ns) bsg <<= 1;
+  }
+  Layout L;
+  L.kind = FENC_LAYOUT_TOKENS;
+  L.bs = n; L.c = E; L.h = 1; L.w = 1;
+  L.M = 1; L.m = 1; L.S = S; L.cpc = 1; L.rep = 0; L.dil = 1;
+  L.bsg = bsg;
+  L.d = ns / bsg;
+  L.ncg = (per + L.d - 1) / L.d;
+  L.nbg = (n + bsg - 1) / bsg;
+  L.nfeat = E;
+  L.level = level;
+  L.scale = scale;
+  return L;
+}
+
 void layout_slots(const Layout& L, int b, int ch, int y, int x, std::vector<std::pair<int, int>>& out) {
   out.clear();
   const int bg = b / L.bsg, jb = b % L.bsg;
+  if (L.kind == FENC_LAYOUT_TOKENS) {
+    const int s = ch % L.S, p = ch / L.S;
+    out.push_back({(bg * L.S + s) * L.ncg + p / L.d, (p % L.d) * L.bsg + jb});
+    return;
+  }
   if (L.kind == FENC_LAYOUT_VECTOR) {
     const int f = (ch * L.h + y) * L.w + x;
     out.push_back({bg, L.pos[f] * L.bsg + jb});
@@ -138,6 +172,10 @@ static Layout from_pub(const Ctx& C, const fenc_layout* p) {
     }
   } else if (L.kind == FENC_LAYOUT_FRAGMENT) {
     if (L.S < 1 || L.m < 1 || (long long)L.m * L.m * L.bsg * L.cpc > C.ns || L.ncg < 1) fail(FENC_EINVAL, "bad fragment layout");
+  } else if (L.kind == FENC_LAYOUT_TOKENS) {
+    const Layout R = make_tokens(C.ns, L.level, L.scale, L.bs, L.c, L.S, L.bsg);
+    if (R.d != L.d || R.ncg != L.ncg || R.nbg != L.nbg || L.h != 1 || L.w != 1 || L.nfeat != L.c)
+      fail(FENC_EINVAL, "bad token layout");
   } else {
     fail(FENC_EINVAL, "unknown layout kind");
   }
@@ -1175,8 +1213,117 @@ struct FcPlan : Plan {
   BiasStage bias;
 };
 
+// A linear layer on token fragments (Discussions, extensibility to
+// Transformers).  Each output ciphertext (fragment s', chunk k') sums, over the
+// input ciphertexts (s, k) of its token group, the diagonal products with the
+// weights of the features they hold, W[i][j] = w[e' = (k' d + i) S + s'][e =
+// (k d + j) S + s], by baby-step giant-step over the d positions:
+// y = sum_g Rot(sum_{(s,k), b} diag'_{g,b} (.) Rot(x_{s,k}, b bs_g), g n1 bs_g).
+// Baby steps are hoisted once per input ciphertext and shared by every
+// output; each output sums all its inputs before one lazy giant-step sum.  A
+// diagonal is live when some weight on it is nonzero.
+static FcPlan* build_fc_tokens(Ctx& C, const Layout& Lin, const double* W, int dout, const double* bias,
+                               bool shape_only, Layout& Lout) {
+  if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the fc layer");
+  const int S = Lin.S, d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level, kin = Lin.ncg;
+  if (dout < S) fail(FENC_EINVAL, "fewer output features than fragments");
+  Lout = make_tokens(C.ns, lvl - 1, C.Delta, Lin.bs, dout, S, bsg);
+  if (shape_only) return nullptr;
+  const int kout = Lout.ncg, ni = S * kin, no = S * kout;
+  int e = 0;
+  while ((1 << e) < d) e++;
+  const int n1 = 1 << ((e + 1) / 2), n2 = d / n1;
+  auto wv = [&](int a, int o, int i, int j) -> double {   // block (input ct a, output ct o), entry [i][j]
+    const int s = a / kin, k = a % kin, s2 = o / kout, k2 = o % kout;
+    const long long ein = ((long long)k * d + j) * S + s, eout = ((long long)k2 * d + i) * S + s2;
+    return ein < din && eout < dout ? W[eout * din + ein] : 0.0;
+  };
+  std::vector<char> act((size_t)ni * no * d, 0);
+  auto live = [&](int a, int o, int kd) -> char& { return act[((size_t)a * no + o) * d + kd]; };
+  std::vector<std::vector<char>> baby(ni, std::vector<char>(n1, 0)), giant(no, std::vector<char>(n2, 0));
+  for (int a = 0; a < ni; a++)
+    for (int o = 0; o < no; o++)
+      for (int kd = 0; kd < d; kd++) {
+        for (int i = 0; i < d && !live(a, o, kd); i++) live(a, o, kd) = wv(a, o, i, (i + kd) % d) != 0.0;
+        if (live(a, o, kd)) {
+          baby[a][kd % n1] = 1;
+          giant[o][kd / n1] = 1;
+        }
+      }
+  auto P = new FcPlan;
+  P->out = Lout;
+  P->level = lvl;
+  P->n_in = Lin.n_ct();
+  P->n_out = Lout.n_ct();
+  const double dp = ((double)C.primes[lvl] * C.Delta) / Lin.scale;
+  std::vector<std::vector<double>> slots;
+  std::vector<int> pid((size_t)ni * no * d, -1);
+  for (int a = 0; a < ni; a++)
+    for (int o = 0; o < no; o++)
+      for (int kd = 0; kd < d; kd++) {
+        if (!live(a, o, kd)) continue;
+        const int g = kd / n1;
+        std::vector<double> z(C.ns);
+        for (int l = 0; l < C.ns; l++) {
+          const int i = posmod((long long)l - (long long)g * n1 * bsg, C.ns) / bsg;
+          z[l] = wv(a, o, i, (i + kd) % d);
+        }
+        pid[((size_t)a * no + o) * d + kd] = (int)slots.size();
+        slots.push_back(std::move(z));
+      }
+  const u64* pts = encode_plaintexts(C, slots, dp, lvl, P->owned);
+  const long long pe = (long long)(lvl + 1) * C.N;
+  // baby copies of every input ciphertext, ordered by shift so rotations sharing a key are adjacent
+  std::vector<std::pair<int, long long>> copies;
+  std::map<std::pair<int, int>, int> copy_of;   // (input ct, baby step) -> copy
+  for (int b = 1; b < n1; b++)
+    for (int t = 0; t < P->n_in; t++)
+      if (baby[t % ni][b]) {
+        copy_of[{t, b}] = (int)copies.size();
+        copies.push_back({t, (long long)b * bsg});
+      }
+  P->rot = make_rot_stage(C, copies, P->owned);
+  GmacBuild b0, br;
+  std::vector<int> so, sb;
+  std::vector<std::vector<std::pair<int, long long>>> st;
+  for (int bg = 0; bg < Lin.nbg; bg++)
+    for (int o = 0; o < no; o++) {
+      const int oid = bg * no + o;
+      std::vector<std::pair<int, long long>> tl;
+      for (int g = 0; g < n2; g++) {
+        if (g > 0 && !giant[o][g]) continue;
+        GmacBuild& gb = g == 0 ? b0 : br;
+        for (int a = 0; a < ni; a++)
+          for (int b = 0; b < n1; b++) {
+            const int id = pid[((size_t)a * no + o) * d + g * n1 + b];
+            if (id < 0) continue;
+            const int t = bg * ni + a;
+            gb.add_group(pts + id * pe);
+            gb.add_term(b == 0 ? t : P->n_in + copy_of.at({t, b}), -1);
+            gb.end_group();
+          }
+        gb.end_output();
+        if (g > 0) tl.push_back({P->n_zr++, (long long)g * n1 * bsg});
+      }
+      if (!tl.empty()) {
+        so.push_back(oid);
+        sb.push_back(oid);
+        st.push_back(tl);
+      }
+    }
+  P->g0 = make_gmac(C, b0, {}, lvl, P->owned);
+  P->gr = make_gmac(C, br, {}, lvl, P->owned);
+  P->sum = make_sum_stage(C, so, sb, st, P->owned, P->n_zr);
+  if (bias) {
+    P->has_bias = true;
+    P->bias = make_bias(C, Lout, bias, P->owned);
+  }
+  return P;
+}
+
 static FcPlan* build_fc(Ctx& C, const Layout& Lin, const double* W, int dout, const double* bias, bool shape_only,
                         Layout& Lout) {
+  if (Lin.kind == FENC_LAYOUT_TOKENS) return build_fc_tokens(C, Lin, W, dout, bias, shape_only, Lout);
   if (Lin.kind != FENC_LAYOUT_VECTOR) fail(FENC_ELAYOUT, "fc needs a vector layout");
   if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the fc layer");
   const int d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level;
@@ -1898,8 +2045,16 @@ int fenc_compress_keyswitches(const fenc_ctx* ctx, const fenc_layout* in, const 
   API_END
 }
 
+int fenc_plan_tokens(const fenc_ctx* ctx, uint32_t n, uint32_t E, uint32_t S, uint32_t group, fenc_layout* out) {
+  API_BEGIN
+  if (!ctx || !out) fail(FENC_EINVAL, "null argument");
+  *out = to_pub(*(fenc_ctx*)ctx, make_tokens(ctx->ns, ctx->L, ctx->Delta, (int)n, (int)E, (int)S, (int)group));
+  API_END
+}
+
 int fenc_layout_n_ct(const fenc_layout* lay) {
   if (!lay) return FENC_EINVAL;
+  if (lay->kind == FENC_LAYOUT_TOKENS) return lay->n_bg * lay->S * lay->n_cg;
   return lay->kind == FENC_LAYOUT_FRAGMENT ? lay->n_bg * lay->n_cg * lay->S * lay->S : lay->n_bg;
 }
 

@@ -31,11 +31,14 @@ struct Layout {
   int rep = 0, dil = 1, level = 0, d = 0, nfeat = 0;
   double scale = 1.0;
   std::vector<int> pos;   // VECTOR layouts
-  int n_ct() const { return kind == FENC_LAYOUT_FRAGMENT ? nbg * ncg * S * S : nbg; }
+  int n_ct() const {
+    return kind == FENC_LAYOUT_FRAGMENT ? nbg * ncg * S * S : kind == FENC_LAYOUT_TOKENS ? nbg * S * ncg : nbg;
+  }
 };
 
 Layout make_fragment(int ns, int level, double scale, int bs, int c, int h, int w, int S);
 Layout plan_fragment(int ns, int level, double scale, int bs, int c, int h, int w, int k, int cout, int s_override);
+Layout make_tokens(int ns, int level, double scale, int n, int E, int S, int group);
 // first (ct, slot) of an element, plus every replica when `all`
 void layout_slots(const Layout& L, int b, int ch, int y, int x, std::vector<std::pair<int, int>>& out);
 

@@ -37,6 +37,8 @@ class Layout(C.Structure):
                [("scale", C.c_double), ("map_id", C.c_uint64)]
 
     def n_ct(self):
+        if self.kind == 2:   # token fragments
+            return self.n_bg * self.S * self.n_cg
         return self.n_bg * self.n_cg * self.S * self.S if self.kind == 0 else self.n_bg
 
     def as_dict(self):
@@ -104,6 +106,7 @@ def load(path=None):
         "fenc_conv2d_keyswitches": (C.c_int, [vp, L, u32, u32, u32, u32, u32, C.POINTER(C.c_int64),
                                               C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
         "fenc_compress_keyswitches": (C.c_int, [vp, L, vp, C.POINTER(C.c_int64)]),
+        "fenc_plan_tokens": (C.c_int, [vp, u32, u32, u32, u32, L]),
         "fenc_layout_n_ct": (C.c_int, [L]),
         "fenc_ct_bytes": (C.c_int64, [vp, L]),
         "fenc_layout_slot": (C.c_int, [vp, L, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(i32), C.POINTER(i32)]),
@@ -371,6 +374,12 @@ class Fenc:
         self._check(self.lib.fenc_compress_keyswitches(self.h, C.byref(lay), C.byref(target) if target else None,
                                                        C.byref(ks)))
         return ks.value
+
+    def plan_tokens(self, n, E, S, group=0):
+        """Token-fragment layout: n tokens of E features in S fragments."""
+        lay = Layout()
+        self._check(self.lib.fenc_plan_tokens(self.h, n, E, S, group, C.byref(lay)))
+        return lay
 
     def layout_slot(self, lay, b, ch, y, x):
         ct, slot = C.c_int32(), C.c_int32()
