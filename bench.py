@@ -219,6 +219,72 @@ def run_cifar(args):
     return r
 
 
+def run_ffn(args):
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["ffn"])
+    W.bench_config(fe)
+    x, w = W.ffn_inputs()
+    lay = fe.plan_tokens(W.FFN_TOKENS, W.FFN_E, W.FFN_S)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    r = measure(fe, lambda: [W.ffn_forward(fe, ct, w)], W.FFN_TOKENS, max(10, args.steps), 2, 1, "ffn")
+    r["tokens_per_s"] = r.pop("images_per_s")
+    r["unit"] = "tokens/s (the images fields count tokens)"
+    r["workload"] = ("BERT-base-shaped feed-forward block on token fragments: 128 tokens, FC 768->3072 with bias, "
+                     "x^2, FC 3072->768 with bias; S=4 (%d input ciphertexts), N=2^16, 4 x 50-bit + 2 special, "
+                     "dnum 2, scale 2^40" % lay.n_ct())
+    r["roofline"] = roofline(r["kernels"], "ffn")
+    return r
+
+
+def ffn_sweep(args):
+    """The FFN block at every admissible block size S: key switches, plaintext
+    products and time per step (graph replay), each S on a fresh context."""
+    import torch
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    x, w = W.ffn_inputs()
+    rows = []
+    print("| S | tokens per group | d | input cts | key switches | plaintext products | context GB | "
+          "ms per step (graph) | tokens/s |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for S in (1, 2, 4, 8):
+        fe = F.Fenc(*W.PARAMS["ffn"])
+        W.bench_config(fe)
+        lay = fe.plan_tokens(W.FFN_TOKENS, W.FFN_E, S)
+        ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+        t0 = time.time()
+        W.ffn_forward(fe, ct, w)
+        torch.cuda.synchronize()
+        log(f"[ffn S={S}] plans and keys {time.time() - t0:.1f}s")
+        W.ffn_forward(fe, ct, w)
+        fe.stats_reset()
+        W.ffn_forward(fe, ct, w)
+        torch.cuda.synchronize()
+        st = fe.stats()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            out = W.ffn_forward(fe, ct, w)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        err = float(np.max(np.abs(fe.decrypt(out).reshape(W.FFN_TOKENS, W.FFN_E) - W.ffn_reference(x, w))))
+        r = {"S": S, "bs_g": lay.bs_g, "d": lay.d, "input_cts": lay.n_ct(), "keyswitch": st["keyswitch"],
+             "pmult": st["pmult"], "device_bytes": fe.device_bytes(), "ms_per_step": round(t * 1e3, 3),
+             "tokens_per_s": round(W.FFN_TOKENS / t, 1), "max_abs_err": err}
+        rows.append(r)
+        print(f"| {S} | {lay.bs_g} | {lay.d} | {lay.n_ct()} | {st['keyswitch']} | {st['pmult']} | "
+              f"{fe.device_bytes() / 1e9:.1f} | {r['ms_per_step']} | {r['tokens_per_s']} |", flush=True)
+        del g, out, ct, fe
+        gc.collect()
+        torch.cuda.empty_cache()
+    print(json.dumps({"ffn_sweep": rows}), flush=True)
+
+
 def mobilenet_context(batch):
     from paper_2606_16359_amd import fenc as F
     from paper_2606_16359_amd import workloads as W
@@ -281,6 +347,13 @@ def workload_step(workload, batch):
         lay = fe.plan_layout(256, 16, 32, 32, 3, 16)
         ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
         return fe, lambda: W.cifar_forward(fe, ct, w)
+    if workload == "ffn":
+        fe = F.Fenc(*W.PARAMS["ffn"])
+        W.bench_config(fe)
+        x, w = W.ffn_inputs()
+        lay = fe.plan_tokens(W.FFN_TOKENS, W.FFN_E, W.FFN_S)
+        ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+        return fe, lambda: [W.ffn_forward(fe, ct, w)]
     fe = F.Fenc(*W.PARAMS["lenet"])
     W.bench_config(fe)
     x, w = W.lenet_inputs(64)
@@ -396,12 +469,14 @@ def main():
     ap.add_argument("--batch", type=int, default=MOBILENET_BATCH, help="MobileNet images per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline only")
-    ap.add_argument("--workload", choices=["mobilenet", "cifar", "lenet"], default="mobilenet",
+    ap.add_argument("--workload", choices=["mobilenet", "cifar", "lenet", "ffn"], default="mobilenet",
                     help="workload of the --counters and --trace runs")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="reduce the two counter passes of a --counters run to HBM bytes per dispatch and exit")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter passes (one warm-up step, a 256 MiB copy, one step)")
+    ap.add_argument("--ffn-sweep", action="store_true",
+                    help="the Transformer FFN block at block sizes 1, 2, 4, 8 (key switches, time)")
     ap.add_argument("--peaks", action="store_true",
                     help="measure instruction, modular-multiply and HBM peaks of the device and exit")
     ap.add_argument("--trace", action="store_true",
@@ -423,6 +498,9 @@ def main():
     if args.peaks:
         peaks_run(args)
         return
+    if args.ffn_sweep:
+        ffn_sweep(args)
+        return
     if args.trace:
         fe, step = workload_step(args.workload, args.batch)
         out = None
@@ -437,7 +515,7 @@ def main():
     extras = {}
     if not args.no_extras:
         for name, fn in [("single_conv_n2p13", run_conv1), ("lenet64_n2p15", run_lenet),
-                         ("cifar256_n2p16", run_cifar)]:
+                         ("cifar256_n2p16", run_cifar), ("bert_ffn128_n2p16", run_ffn)]:
             t0 = time.time()
             extras[name] = fn(args)
             gc.collect()

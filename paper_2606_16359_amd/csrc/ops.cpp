@@ -1442,6 +1442,7 @@ static void run_fc(Ctx& C, const FcPlan& P, const u64* in, u64* out, fb::Stream 
   }
   C.cnt.rot_other += P.rot.n + P.n_zr;
   C.cnt.keyswitch += P.rot.n + P.n_zr;
+  C.cnt.pmult += P.g0.n_masked + P.gr.n_masked;
   C.cnt.cts_out += P.n_out;
 }
 

@@ -15,6 +15,8 @@ PARAMS = {
     "lenet": (15, 20, 50, 7, 50, 3, 40, 3),
     # CIFAR-shaped stack: N=2^16, 24 x 50-bit, dnum 4 (6 special), scale 2^40
     "cifar": (16, 24, 50, 6, 50, 4, 40, 3),
+    # Transformer feed-forward block: N=2^16, 4 x 50-bit (FC, square, FC), dnum 2 (2 special), scale 2^40
+    "ffn": (16, 4, 50, 2, 50, 2, 40, 3),
 }
 
 SEED_INPUT, SEED_WEIGHTS, SEED_ENC = 1, 2, 4
@@ -161,3 +163,29 @@ def mobilenet_block(fenc, ct, blk, w, coeffs=QUADRATIC):
         y = fenc.poly_act(fenc.conv2d(y, wi, stride=layer["stride"], pad=layer["pad"], groups=layer["groups"]),
                           coeffs, inplace=True)
     return y
+
+
+# BERT-base-shaped feed-forward block on token fragments (the Transformer
+# extension, Discussions): 128 tokens, E = 768 -> 3072 -> 768 with biases and
+# a square activation between, embeddings split into S = 4 fragments
+FFN_TOKENS, FFN_E, FFN_HIDDEN, FFN_S = 128, 768, 3072, 4
+
+
+def ffn_inputs(n=FFN_TOKENS, E=FFN_E, H=FFN_HIDDEN, seed=SEED_INPUT):
+    """x[n][E][1][1] uniform in [-1, 1) and (W1, b1, W2, b2) with N(0, 0.02)
+    entries (BERT's initialisation scale)."""
+    x = np.random.default_rng(seed).uniform(-1.0, 1.0, (n, E, 1, 1))
+    r = np.random.default_rng(seed + 1)
+    return x, [r.normal(0.0, 0.02, s) for s in ((H, E), (H,), (E, H), (E,))]
+
+
+def ffn_forward(fenc, ct, w):
+    """FC E -> H (+ b1) -> x^2 -> FC H -> E (+ b2), on token fragments."""
+    y = fenc.poly_act(fenc.fc(ct, w[0], bias=w[1]))
+    return fenc.fc(y, w[2], bias=w[3])
+
+
+def ffn_reference(x, w):
+    n = x.shape[0]
+    h = x.reshape(n, -1) @ w[0].T + w[1]
+    return (h * h) @ w[2].T + w[3]

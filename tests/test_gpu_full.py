@@ -255,3 +255,32 @@ def test_mobilenet_blocks_at_imagenet_shape_decrypt_to_float64():
         assert got.shape == ref.shape
         assert np.max(np.abs(got - ref)) < 1e-4, (b, np.max(np.abs(got - ref)))
         x = ref
+
+
+def test_bert_ffn_block_on_token_fragments_decrypts_to_float64():
+    """The BERT-base-shaped feed-forward block of the benchmark (128 tokens,
+    768 -> 3072 -> 768 with biases, x^2 between, S = 4, N = 2^16): the
+    output decrypts to the float64 block; a second pass is bit-identical."""
+    import time
+    import torch
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["ffn"])
+    W.bench_config(fe)
+    x, w = W.ffn_inputs()
+    lay = fe.plan_tokens(W.FFN_TOKENS, W.FFN_E, W.FFN_S)
+    assert (lay.kind, lay.S, lay.bs_g, lay.d, lay.n_ct()) == (2, 4, 128, 256, 4)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    t0 = time.time()
+    out = W.ffn_forward(fe, ct, w)
+    torch.cuda.synchronize()
+    print(f"ffn first pass (plans, keys) {time.time() - t0:.2f}s", flush=True)
+    fe.stats_reset()
+    t0 = time.time()
+    again = W.ffn_forward(fe, ct, w)
+    torch.cuda.synchronize()
+    print(f"ffn {time.time() - t0:.3f}s for 128 tokens, {fe.stats()}", flush=True)
+    assert np.array_equal(fe.export(out), fe.export(again))
+    got = fe.decrypt(out).reshape(W.FFN_TOKENS, W.FFN_E)
+    ref = W.ffn_reference(x, w)
+    assert np.max(np.abs(got - ref)) < 1e-4, np.max(np.abs(got - ref))

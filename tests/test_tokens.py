@@ -62,7 +62,8 @@ def test_token_fc_bit_exact(backend, n, E, E2, S, hoist, orc):
     yo, cnt = orc.fc(ob, w, bias=b)
     _same_layout(f, y.lay, yo.layout())
     cmp(y, yo, f)
-    assert f.stats()["rot_other"] == cnt["other_rot"]
+    st = f.stats()
+    assert (st["rot_other"], st["pmult"]) == (cnt["other_rot"], cnt["pmult"])
     got = f.decrypt(y).reshape(n, E2)
     assert np.max(np.abs(got - (x.reshape(n, E) @ w.T + b))) < 1e-4
 
