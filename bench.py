@@ -48,6 +48,7 @@ TRAFFIC = {
     ("mobilenet", "ntt_fwd_cols"): 1.8092e9,
     ("cifar", "gmac_pt"): 11.4665e9,
     ("lenet", "kip"): 0.8760e9,
+    ("ffn", "gmac_diag"): 6.9600e9,
 }
 
 
