@@ -1311,6 +1311,9 @@ FENC_HD void gmac_diag(X& x, const GmacArgs& a) {
 // Tensor product of ciphertexts a and b (b == a for a square), times the
 // integer k: (d0, d1, d2) = k (a0 b0, a0 b1 + a1 b0, a1 b1); d0, d1 into out
 // (ct [2][nl][N]), d2 into d2buf [nl][N].
+// out = k (a0 b0, a0 b1 + a1 b0) [+ k1 x + k0], d2buf = k a1 b1.  The optional
+// linear term of the activation (x with its own strides, possibly more limbs:
+// limb drop; k0 on poly 0 only) is added here, so it needs no pass of its own.
 struct SquareArgs {
   const u64* in;
   const u64* in_b;
@@ -1320,6 +1323,10 @@ struct SquareArgs {
   long long ct_stride;   // elements per ct (inputs and out)
   const d2* k;           // [nl] (k mod q_i, /q)
   const d2* pq;
+  const u64* lx;         // null: no linear term
+  long long lx_cs, lx_ps;
+  const d2* k1;          // [nl]
+  const d2* k0;          // [nl]
 };
 
 template <class X>
@@ -1336,8 +1343,15 @@ FENC_HD void tensor_square(X& x, const SquareArgs& a) {
     u64* out = a.out + b * a.ct_stride + i * N + c;
     const d2 k = a.k[i];
     const double m01 = mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);   // words in [0, q)
-    out[0] = d2u(norm(mulmod_c(mulmod(a0, b0, q, qi), k.x, k.y, q), q));
-    out[a.nl * N] = d2u(norm(mulmod_c(m01, k.x, k.y, q), q));
+    double o0 = mulmod_c(mulmod(a0, b0, q, qi), k.x, k.y, q), o1 = mulmod_c(m01, k.x, k.y, q);
+    if (a.lx) {   // each term within q: the sums stay within 3q, reduced once
+      const u64* px = a.lx + b * a.lx_cs + i * N + c;
+      const double x0 = px == pa ? a0 : u2d(px[0]), x1 = px == pa ? a1 : u2d(px[a.lx_ps]);
+      o0 = red(o0 + mulmod_c(x0, a.k1[i].x, a.k1[i].y, q) + a.k0[i].x, q, qi);
+      o1 = red(o1 + mulmod_c(x1, a.k1[i].x, a.k1[i].y, q), q, qi);
+    }
+    out[0] = d2u(norm(o0, q));
+    out[a.nl * N] = d2u(norm(o1, q));
     a.d2buf[(long long)b * a.nl * N + i * N + c] = d2u(norm(mulmod_c(mulmod(a1, b1, q, qi), k.x, k.y, q), q));
   });
 }

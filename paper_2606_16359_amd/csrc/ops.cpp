@@ -981,15 +981,20 @@ static std::vector<d2> code_residues(const Ctx& C, double v, int nl) {
   return out;
 }
 
+// t = k (a x b) over (d0, d1), d2b = its d2; with x: plus k1 x + k0, x read
+// with its own strides (the same words as a when x == a)
 static void run_tensor(Ctx& C, int lvl, int n, const u64* a, const u64* b, const d2* k, u64* t, u64* d2b,
-                       fb::Stream s) {
+                       fb::Stream s, const u64* x = nullptr, long long x_cs = 0, long long x_ps = 0,
+                       const d2* k1 = nullptr, const d2* k0 = nullptr) {
   const int nl = lvl + 1;
   const long long ce = ct_elems(C, lvl);
   const bool per_op = C.mode == FENC_MODE_PER_OP;
+  const double xr = x && x != a ? 2.0 : 0.0;   // words of x read beside a and b
   for (int b0 = 0; b0 < n; b0 += per_op ? 1 : n) {
     const int nb = per_op ? 1 : n;
-    fk::SquareArgs sa{a + b0 * ce, b + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, k, C.pq};
-    timed(C, "tensor_square", (a == b ? 5.0 : 7.0) * nb * nl * C.N * 8, s, [&] {
+    fk::SquareArgs sa{a + b0 * ce, b + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, k, C.pq,
+                      x ? x + b0 * x_cs : nullptr, x_cs, x_ps, k1, k0};
+    timed(C, "tensor_square", ((a == b ? 5.0 : 7.0) + xr) * nb * nl * C.N * 8, s, [&] {
       fb::tensor_square({(unsigned)std::max(1, C.N / 256), (unsigned)nl, (unsigned)nb}, std::min(256, C.N), s, sa);
     }, (a == b ? 3.0 : 4.0) * nb * nl * C.N);
     C.cnt.launches++;
@@ -1036,21 +1041,23 @@ static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Str
     rescale(C, l, t, n, out, s);
   } else {
     u64* d2b = (u64*)C.arena.get((size_t)n * (l + 1) * C.N * 8, s);
-    run_tensor(C, l, n, in, in, P.kf, t, d2b, s);
-    relin(C, l, n, P.ks_a, t, d2b, s);
-    if (P.d == 2) {
-      if (P.lin) run_lin(C, l + 1, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
+    const long long xps = (long long)(l + 1) * C.N;
+    if (P.d == 2) {   // k2 x*x + k1 x + k0 in one pass, then the relinearisation adds KS(d2)
+      run_tensor(C, l, n, in, in, P.kf, t, d2b, s, P.lin ? in : nullptr, ce, xps, P.k1, P.k0);
+      relin(C, l, n, P.ks_a, t, d2b, s);
       rescale(C, l, t, n, out, s);
     } else {
+      run_tensor(C, l, n, in, in, P.kf, t, d2b, s);
+      relin(C, l, n, P.ks_a, t, d2b, s);
       const long long c1e = ct_elems(C, l - 1);
       u64* x2 = (u64*)C.arena.get((size_t)n * c1e * 8, s);
       u64* u = (u64*)C.arena.get((size_t)n * c1e * 8, s);
       rescale(C, l, t, n, x2, s);
       // x' = x without its last limb: the same words read with level-l strides
       run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, nullptr, u, P.k3, P.k2c, s);
-      run_tensor(C, l - 1, n, x2, u, P.one, t, d2b, s);
+      // X2 u + k1 x' + k0 in one pass, x' read like u
+      run_tensor(C, l - 1, n, x2, u, P.one, t, d2b, s, P.lin ? in : nullptr, ce, xps, P.k1, P.k0);
       relin(C, l - 1, n, P.ks_b, t, d2b, s);
-      if (P.lin) run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, t, t, P.k1, P.k0, s);
       rescale(C, l - 1, t, n, out, s);
     }
   }
