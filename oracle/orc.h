@@ -226,6 +226,14 @@ Ct mul_scalar(const Context& C, const Ct& a, i64 s, double s_scale);
 Ct square_relin(Context& C, const Ct& a, i64 k = 1);
 // a * b: tensor product of two ciphertexts at one level, relinearised, no rescale
 Ct mul_relin(Context& C, const Ct& a, const Ct& b);
+// ModDown by P q_l of a polynomial over Q_l U P to Q_{l-1}: the special
+// primes and q_l dropped by one fast base conversion
+RPoly mod_down_rescale(const Context& C, const RPoly& a, int level);
+// tensor product k (a x b): d0 = k a0 b0, d1 = k (a0 b1 + a1 b0), d2 = k a1 b1
+void tensor(const Context& C, const Ct& a, const Ct& b, i64 k, RPoly& d0, RPoly& d1, RPoly& d2);
+// (d.c0, d.c1) + KS(d2) relinearised and rescaled together: the key inner
+// product of d2's extended digits plus P (d.c0, d.c1), ModDown by P q_l
+Ct relin_rescale(Context& C, const Ct& d, const RPoly& d2);
 // the same ciphertext at one level less (the last limb dropped)
 Ct drop_last_limb(const Ct& a);
 // base + k1 * x + k0 (k0 added to the constant coefficient of c0); base may be null

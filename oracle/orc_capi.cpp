@@ -223,6 +223,14 @@ int orc_mod_up(void* c, const uint64_t* d, int level, uint64_t* out) {
   GUARD_END(-1)
 }
 
+int orc_mod_down_rescale(void* c, const uint64_t* a, int level, uint64_t* out) {
+  GUARD_BEGIN
+  Context* C = (Context*)c;
+  poly_to(*C, mod_down_rescale(*C, poly_from(*C, a, level + 1 + C->K, qp_basis(*C, level)), level), out);
+  return 0;
+  GUARD_END(-1)
+}
+
 int orc_mod_down(void* c, const uint64_t* a, int level, uint64_t* out) {
   GUARD_BEGIN
   Context* C = (Context*)c;

@@ -714,6 +714,84 @@ Ct mul_relin(Context& C, const Ct& a, const Ct& b) {
   return y;
 }
 
+// ModDown by P q_l (Q_l U P -> Q_{l-1}): the special primes and q_l dropped
+// by one fast base conversion, i.e. the ModDown of a relinearisation and the
+// rescale after it taken together.  With D = P q_l and d_k its primes,
+// y_k = [a_{d_k} (D/d_k)^-1]_{d_k} centred and
+// out_i = (a_i - sum_k y_k [D/d_k]_{q_i}) D^-1 mod q_i, i < l.
+RPoly mod_down_rescale(const Context& C, const RPoly& a, int level) {
+  if (level < 1) throw std::runtime_error("mod_down_rescale: level 0");
+  const int K = C.K;
+  std::vector<u64> dp(K + 1);
+  std::vector<int> row(K + 1);   // rows of the dropped primes in the qp basis of `level`
+  dp[0] = C.primes[level];
+  row[0] = level;
+  for (int k = 0; k < K; k++) {
+    dp[k + 1] = C.primes[C.L + 1 + k];
+    row[k + 1] = level + 1 + k;
+  }
+  std::vector<std::vector<i64>> y(K + 1, std::vector<i64>(C.N));
+  for (int k = 0; k <= K; k++) {
+    const u64 d = dp[k];
+    u64 hat = 1;
+    for (int k2 = 0; k2 <= K; k2++)
+      if (k2 != k) hat = mulm(hat, dp[k2] % d, d);
+    const u64 hinv = invm(hat, d);
+    for (int c = 0; c < C.N; c++) {
+      const u64 v = mulm(a.c[row[k]][c], hinv, d);
+      y[k][c] = v <= (d - 1) / 2 ? (i64)v : (i64)v - (i64)d;
+    }
+  }
+  RPoly r = poly_zero(C, q_basis(level - 1));
+  for (int i = 0; i < level; i++) {
+    const u64 qi = C.primes[i];
+    u64 D = 1;
+    std::vector<u64> hat(K + 1, 1);
+    for (int k = 0; k <= K; k++) {
+      D = mulm(D, dp[k] % qi, qi);
+      for (int k2 = 0; k2 <= K; k2++)
+        if (k2 != k) hat[k] = mulm(hat[k], dp[k2] % qi, qi);
+    }
+    const u64 Dinv = invm(D, qi);
+    for (int c = 0; c < C.N; c++) {
+      u64 conv = 0;
+      for (int k = 0; k <= K; k++) conv = addm(conv, mulm(from_i64(y[k][c], qi), hat[k], qi), qi);
+      r.c[i][c] = mulm(subm(a.c[i][c], conv, qi), Dinv, qi);
+    }
+  }
+  return r;
+}
+
+void tensor(const Context& C, const Ct& a, const Ct& b, i64 k, RPoly& d0, RPoly& d1, RPoly& d2) {
+  if (a.level != b.level) throw std::runtime_error("tensor: level mismatch");
+  d0 = poly_scalar(C, poly_mul(C, a.c0, b.c0), k);
+  d1 = poly_mul(C, a.c0, b.c1);
+  poly_add_inplace(C, d1, poly_mul(C, a.c1, b.c0));
+  d1 = poly_scalar(C, d1, k);
+  d2 = poly_scalar(C, poly_mul(C, a.c1, b.c1), k);
+}
+
+Ct relin_rescale(Context& C, const Ct& d, const RPoly& d2) {
+  const int level = d.level;
+  if (level < 1) throw std::runtime_error("relin_rescale: level 0");
+  std::vector<RPoly> up = mod_up(C, d2, level);
+  RPoly a0, a1;
+  key_inner_product(C, up, 0, level, a0, a1);
+  for (int l = 0; l <= level; l++) {   // + P (d0, d1) on the Q limbs; P is zero on the special primes
+    const u64 q = C.primes[l], Pq = prod_p_mod(C, q);
+    for (int c = 0; c < C.N; c++) {
+      a0.c[l][c] = addm(a0.c[l][c], mulm(d.c0.c[l][c], Pq, q), q);
+      a1.c[l][c] = addm(a1.c[l][c], mulm(d.c1.c[l][c], Pq, q), q);
+    }
+  }
+  Ct y;
+  y.c0 = mod_down_rescale(C, a0, level);
+  y.c1 = mod_down_rescale(C, a1, level);
+  y.level = level - 1;
+  y.scale = d.scale / (double)C.primes[level];
+  return y;
+}
+
 Ct drop_last_limb(const Ct& a) {
   if (a.level < 1) throw std::runtime_error("drop_last_limb: level 0");
   Ct y = a;

@@ -850,14 +850,16 @@ std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& i
     out.resize(in.size());
     par_for((int)in.size(), [&](int i) {
       const Ct& x = in[i];
-      Ct y;
-      if (d == 2) {
-        Ct t = square_relin(C, x, k2);
-        y = lin_comb(C, &t, x, k1, k0);
+      if (d == 2) {   // k2 x*x + k1 x + k0, relinearised and rescaled by one ModDown by P q_l
+        Ct t;
+        RPoly d2;
+        tensor(C, x, x, k2, t.c0, t.c1, d2);
+        t.level = x.level;
+        t.scale = ((double)k2 * s) * s;
+        out[i] = relin_rescale(C, lin_comb(C, &t, x, k1, k0), d2);
       } else {
-        y = lin_comb(C, nullptr, x, k1, k0);
+        out[i] = rescale(C, lin_comb(C, nullptr, x, k1, k0));
       }
-      out[i] = rescale(C, y);
     });
     const long n = (long)in.size();
     if (d == 2) { cnt.relin += n; cnt.ks += n; cnt.modup += n; cnt.moddown += n; }
@@ -877,11 +879,18 @@ std::vector<Ct> poly_act(Context& C, const Layout& Lin, const std::vector<Ct>& i
     out.resize(in.size());
     par_for((int)in.size(), [&](int i) {
       const Ct& x = in[i];
-      Ct X2 = rescale(C, square_relin(C, x, k));
+      Ct t;
+      RPoly d2;
+      tensor(C, x, x, k, t.c0, t.c1, d2);   // X2 = k x*x at level l - 1
+      t.level = x.level;
+      t.scale = ((double)k * s) * s;
+      const Ct X2 = relin_rescale(C, t, d2);
       const Ct xd = drop_last_limb(x);
       const Ct u = lin_comb(C, nullptr, xd, k3, k2c);
-      Ct P = mul_relin(C, X2, u);
-      out[i] = rescale(C, lin_comb(C, &P, xd, k1, k0));
+      tensor(C, X2, u, 1, t.c0, t.c1, d2);  // X2 u + k1 x' + k0 at level l - 2
+      t.level = X2.level;
+      t.scale = X2.scale * u.scale;
+      out[i] = relin_rescale(C, lin_comb(C, &t, xd, k1, k0), d2);
     });
     const long n = (long)in.size();
     cnt.relin += 2 * n; cnt.ks += 2 * n; cnt.modup += 2 * n; cnt.moddown += 2 * n; cnt.rescale += 2 * n;
@@ -900,7 +909,14 @@ std::vector<Ct> square_act(Context& C, const Layout& Lin, const std::vector<Ct>&
   i64 k = (i64)std::round((delta_of(C) * ql) / (s * s));
   if (k < 1) k = 1;
   std::vector<Ct> out(in.size());
-  par_for((int)in.size(), [&](int i) { out[i] = rescale(C, square_relin(C, in[i], k)); });
+  par_for((int)in.size(), [&](int i) {
+    Ct t;
+    RPoly d2;
+    tensor(C, in[i], in[i], k, t.c0, t.c1, d2);
+    t.level = in[i].level;
+    t.scale = ((double)k * s) * s;
+    out[i] = relin_rescale(C, t, d2);
+  });
   const long n = (long)in.size();
   cnt.relin += n; cnt.ks += n; cnt.modup += n; cnt.moddown += n; cnt.rescale += n;
   Lout = Lin;

@@ -70,6 +70,7 @@ def _declare(L):
         "orc_switch_key": (i, [vp, u, u64p]),
         "orc_mod_up": (i, [vp, u64p, i, u64p]),
         "orc_mod_down": (i, [vp, u64p, i, u64p]),
+        "orc_mod_down_rescale": (i, [vp, u64p, i, u64p]),
         "orc_rotate": (i, [vp, u64p, i, i64p, i, u64p]),
         "orc_rotate_sum": (i, [vp, vp, u64p, i64p, i, i, u64p]),
         "orc_rescale": (i, [vp, u64p, i, u64p]),
@@ -274,6 +275,11 @@ class Oracle:
     def mod_down(self, a, level):
         out = np.zeros((level + 1, self.N), np.uint64)
         _check(lib().orc_mod_down(self.h, np.ascontiguousarray(a, np.uint64), level, out))
+        return out
+
+    def mod_down_rescale(self, a, level):
+        out = np.zeros((level, self.N), np.uint64)
+        _check(lib().orc_mod_down_rescale(self.h, np.ascontiguousarray(a, np.uint64), level, out))
         return out
 
     def rotate(self, ct, shifts):

@@ -212,6 +212,36 @@ def crt(residues, primes):
     return x % Q, Q
 
 
+def test_mod_down_rescale_divides_by_P_times_q_l(orc_small):
+    """ModDown by P q_l (the relinearisation's ModDown merged with the rescale):
+    D x + y over Q_l U P gives x - v on Q_{l-1} with |v| <= K + 1 for
+    |y| < D/2 (fast base conversion of K + 1 centred terms), and exactly x
+    for y = 0; checked against the integers themselves."""
+    o = orc_small
+    qs = o.primes()
+    level = 2
+    basis = list(range(level + 1)) + [o.nq + k for k in range(o.np)]
+    D = qs[level]
+    for k in range(o.np):
+        D *= qs[o.nq + k]
+    rng = np.random.default_rng(7)
+    x = [int(v) - (1 << 59) for v in rng.integers(0, 1 << 60, o.N, dtype=np.uint64)]
+    y = [int(v) - (1 << 19) for v in rng.integers(0, 1 << 20, o.N, dtype=np.uint64)]
+    a = np.array([[(D * xi + yi) % qs[t] for xi, yi in zip(x, y)] for t in basis], dtype=np.uint64)
+    got = o.mod_down_rescale(a, level)
+    assert got.shape == (level, o.N)
+    zero_y = np.array([[(D * xi) % qs[t] for xi in x] for t in basis], dtype=np.uint64)
+    assert np.array_equal(o.mod_down_rescale(zero_y, level),
+                          np.array([[xi % qs[i] for xi in x] for i in range(level)], dtype=np.uint64))
+    vs = set()
+    for c in range(o.N):
+        cands = [v for v in range(-o.np - 1, o.np + 2) if all(int(got[i][c]) == (x[c] - v) % qs[i]
+                                                               for i in range(level))]
+        assert cands, c
+        vs.add(cands[0])
+    assert len(vs) > 1   # the conversion's error term is exercised, not always zero
+
+
 def test_mod_up_is_centred_digit_lift_plus_small_multiple(orc_small):
     o = orc_small
     qs = o.primes()
