@@ -53,6 +53,7 @@ void ntt_inv_cols16(Grid g, int threads, size_t smem, Stream s, const fk::NttArg
 void modup_fbc(Grid g, int threads, Stream s, const fk::ModUpArgs& a);
 void kip(Grid g, int threads, Stream s, const fk::KipArgs& a);
 void moddown_fbc(Grid g, int threads, Stream s, const fk::ModDownArgs& a);
+void rs_prep(Grid g, int threads, Stream s, const fk::RsPrepArgs& a);
 void gmac(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_pt(Grid g, int threads, Stream s, const fk::GmacArgs& a);
 void gmac_fast(Grid g, int threads, Stream s, const fk::GmacArgs& a);

@@ -676,6 +676,7 @@ struct TailArgs {
   const u64* add;   long long add_cs;
   const d2* pinv;    // [nl] (P^-1 mod q_i, /q)
   const d2* pq;
+  const d2* bscale;  // [nl] factor of the base word (null: 1)
 };
 
 // Output word (o, poly, limb i, coefficient c) from the converted value cv
@@ -700,7 +701,8 @@ FENC_HD FENC_AI void tail_value(const TailArgs& a, int o, int poly, int i, long 
   const long long N = 1LL << a.logn;
   double r = mulmod_c(u2d(P.aw) - cv, a.pinv[i].x, a.pinv[i].y, q);   // |aw - cv| < 2q: quotient < 2^51
   const TailItem I = a.items[o];
-  if (I.base >= 0) r += u2d(P.bw);
+  // with a factor: within 0.75q, so |r| < 1.75q before the added words
+  if (I.base >= 0) r += a.bscale ? mulmod_c(u2d(P.bw), a.bscale[i].x, a.bscale[i].y, q) : u2d(P.bw);
   if (poly == 0)
     for (int k = 0; k < I.add_n; k++) {
       const AddTerm T = a.terms[I.add_off + k];
@@ -709,6 +711,33 @@ FENC_HD FENC_AI void tail_value(const TailArgs& a, int o, int poly, int i, long 
       if ((k & 3) == 3) r = red(r, q, qi);
     }
   a.out[I.out * a.out_cs + poly * a.out_ps + i * N + c] = d2u(norm(red(r, q, qi), q));
+}
+
+// ModDown by P q_l (a relinearisation and the rescale after it in one base
+// conversion): the q_l limb of the converted sum is acc_l + P base_l, so that
+// limb of acc (NTT form, not read by the tail) takes the base's share before
+// its inverse NTT with the special primes' limbs.  One thread per
+// coefficient; rows: output * 2 + poly.
+struct RsPrepArgs {
+  u64* acc;                 // [nout][2][le][N]
+  const u64* base;  long long base_cs, base_ps;
+  const TailItem* items;
+  int o0, nl, le, logn;
+  d2 pmod, pq;              // (P mod q_l, /q_l), (q_l, 1/q_l)
+};
+template <class X>
+FENC_HD void rs_prep(X& x, const RsPrepArgs& a) {
+  x.phase([&](int t) {
+    const long long N = 1LL << a.logn;
+    const long long c = (long long)x.bx * x.nt + t;
+    const int o = a.o0 + x.by / 2, poly = x.by & 1;
+    const double q = a.pq.x, qi = a.pq.y;
+    u64* ap = a.acc + ((long long)(o * 2 + poly) * a.le + (a.nl - 1)) * N + c;
+    const u64* bp = a.base + a.items[o].base * a.base_cs + poly * a.base_ps + (long long)(a.nl - 1) * N + c;
+    // acc word in [0, q), product within 0.75q
+    const double v = u2d(ldg(ap)) + mulmod_c(u2d(ldg(bp)), a.pmod.x, a.pmod.y, q);
+    *ap = d2u(norm(red(v, q, qi), q));
+  });
 }
 
 // The tail is the epilogue of the forward row pass that finishes the NTT of

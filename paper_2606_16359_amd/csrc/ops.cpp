@@ -1017,14 +1017,15 @@ static void run_lin(Ctx& C, int nl, int n, const u64* x, long long x_cs, long lo
   }
 }
 
-// relinearise in place: t (d0, d1) += KS(d2b) at level lvl
-static void relin(Ctx& C, int lvl, int n, const KsStage& ks, u64* t, const u64* d2b, fb::Stream s) {
+// relinearise and rescale: out (level lvl-1) = (t (d0, d1) + KS(d2b)) / q_lvl,
+// by one ModDown by P q_lvl after the key inner product
+static void relin_rescale(Ctx& C, int lvl, int n, const KsStage& ks, const u64* t, const u64* d2b, u64* out,
+                          fb::Stream s) {
   const int nl = lvl + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
-  const long long ce = ct_elems(C, lvl);
   Scope sc(C.arena);
   u64* ext = (u64*)C.arena.get((size_t)n * beta * le * C.N * 8, s);
   modup(C, lvl, d2b, (long long)nl * C.N, 0, n, ext, s);
-  kip_moddown(C, lvl, ext, ks, t, ce, t, ce, nullptr, 0, s);
+  kip_moddown(C, lvl, ext, ks, out, ct_elems(C, lvl - 1), t, ct_elems(C, lvl), nullptr, 0, s, true);
   C.cnt.relin += n;
   C.cnt.keyswitch += n;
 }
@@ -1042,23 +1043,20 @@ static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Str
   } else {
     u64* d2b = (u64*)C.arena.get((size_t)n * (l + 1) * C.N * 8, s);
     const long long xps = (long long)(l + 1) * C.N;
-    if (P.d == 2) {   // k2 x*x + k1 x + k0 in one pass, then the relinearisation adds KS(d2)
+    if (P.d == 2) {   // k2 x*x + k1 x + k0 in one pass, then relinearised and rescaled together
       run_tensor(C, l, n, in, in, P.kf, t, d2b, s, P.lin ? in : nullptr, ce, xps, P.k1, P.k0);
-      relin(C, l, n, P.ks_a, t, d2b, s);
-      rescale(C, l, t, n, out, s);
+      relin_rescale(C, l, n, P.ks_a, t, d2b, out, s);
     } else {
       run_tensor(C, l, n, in, in, P.kf, t, d2b, s);
-      relin(C, l, n, P.ks_a, t, d2b, s);
       const long long c1e = ct_elems(C, l - 1);
       u64* x2 = (u64*)C.arena.get((size_t)n * c1e * 8, s);
       u64* u = (u64*)C.arena.get((size_t)n * c1e * 8, s);
-      rescale(C, l, t, n, x2, s);
+      relin_rescale(C, l, n, P.ks_a, t, d2b, x2, s);
       // x' = x without its last limb: the same words read with level-l strides
       run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, nullptr, u, P.k3, P.k2c, s);
       // X2 u + k1 x' + k0 in one pass, x' read like u
       run_tensor(C, l - 1, n, x2, u, P.one, t, d2b, s, P.lin ? in : nullptr, ce, xps, P.k1, P.k0);
-      relin(C, l - 1, n, P.ks_b, t, d2b, s);
-      rescale(C, l - 1, t, n, out, s);
+      relin_rescale(C, l - 1, n, P.ks_b, t, d2b, out, s);
     }
   }
   C.cnt.cts_out += n;

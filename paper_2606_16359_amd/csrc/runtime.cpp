@@ -225,6 +225,33 @@ const LevelTabs& level_tabs(Ctx& C, int level) {
     pm[i] = cpair(P, C.primes[i]);
   }
   T.pmod = upload(C, pm, C.owned);
+  if (level >= 1) {   // ModDown by D = P q_l: sources q_l, p_0 .. p_{K-1}
+    const int K1 = C.K + 1;
+    std::vector<uint64_t> dp(K1);
+    dp[0] = C.primes[level];
+    for (int k = 0; k < C.K; k++) dp[k + 1] = C.primes[C.L + 1 + k];
+    std::vector<d2> rs((size_t)K1 + (size_t)level * K1), dinv(level);
+    for (int k = 0; k < K1; k++) {
+      uint64_t hat = 1;
+      for (int k2 = 0; k2 < K1; k2++)
+        if (k2 != k) hat = mulmod(hat, dp[k2] % dp[k], dp[k]);
+      rs[k] = cpair(invmod(hat, dp[k]), dp[k]);
+    }
+    for (int i = 0; i < level; i++) {
+      const uint64_t qi = C.primes[i];
+      uint64_t D = 1;
+      for (int k = 0; k < K1; k++) {
+        uint64_t hat = 1;
+        for (int k2 = 0; k2 < K1; k2++)
+          if (k2 != k) hat = mulmod(hat, dp[k2] % qi, qi);
+        rs[K1 + (size_t)i * K1 + k] = cpair(hat, qi);
+        D = mulmod(D, dp[k] % qi, qi);
+      }
+      dinv[i] = cpair(invmod(D, qi), qi);
+    }
+    T.md_rs = upload(C, rs, C.owned);
+    T.dinv_rs = upload(C, dinv, C.owned);
+  }
   return C.lvl[level] = T;
 }
 
@@ -493,47 +520,62 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
 
 // ModDown of outputs o0 .. o0+no-1 of acc ([n][2][le][N], NTT form; its P
 // limbs are transformed in place), then the tail into out
+// rs: ModDown by P q_l (sources q_l and the special primes, outputs the
+// level-1 limbs); the q_l limb of acc first takes P base (rs_prep)
 static void moddown_part(Ctx& C, int level, u64* acc, u64* conv, const KsStage& st, int o0, int no, u64* out,
                          long long out_cs, const u64* base, long long base_cs, const u64* add, long long add_cs,
-                         fb::Stream s) {
+                         fb::Stream s, bool rs = false) {
   const LevelTabs& T = level_tabs(C, level);
   const int nl = level + 1, le = nl + C.K, N = C.N;
+  const int nk = rs ? C.K + 1 : C.K, no_l = rs ? nl - 1 : nl;   // converted limbs, output limbs
+  if (rs && (level < 1 || !base)) fail(FENC_EINVAL, "ModDown by P q_l needs a level and a base");
   fk::PrimeMap pmP;
   pmP.n = le;
-  for (int l = 0; l < le; l++) pmP.p[l] = l < nl ? fk::kSkip : T.h_eprime[l];
+  for (int l = 0; l < le; l++) pmP.p[l] = l < no_l ? fk::kSkip : T.h_eprime[l];
   u64* acc0 = acc + (long long)o0 * 2 * le * N;
+  if (rs) {
+    const fk::RsPrepArgs r{acc, base, base_cs, (long long)nl * N, st.tails, o0, nl, le, C.logn,
+                           cpair(T.h_pmod[nl - 1], C.primes[nl - 1]),
+                           d2{(double)C.primes[nl - 1], 1.0 / (double)C.primes[nl - 1]}};
+    timed(C, "rs_prep", 3.0 * 2 * no * N * 8, s, [&] {
+      fb::rs_prep({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, r);
+    }, 2.0 * no * N);
+  }
   ntt(C, true, acc0, acc0, (long long)le * N, (long long)le * N, no * 2 * le, le, pmP, s);
-  fk::ModDownArgs m{acc, conv, o0, nl, le, C.K, C.logn, T.epq, C.md_tab};
-  timed(C, "moddown_fbc", 2.0 * no * (C.K + nl) * N * 8, s, [&] {
+  fk::ModDownArgs m{acc, conv, o0, no_l, le, nk, C.logn, T.epq, rs ? T.md_rs : C.md_tab};
+  timed(C, "moddown_fbc", 2.0 * no * (nk + no_l) * N * 8, s, [&] {
     fb::moddown_fbc({(unsigned)(N / block_threads(C)), (unsigned)(2 * no), 1}, block_threads(C), s, m);
-  }, 2.0 * no * C.K * (1.0 + nl) * N);
-  u64* conv0 = conv + (long long)o0 * 2 * nl * N;
+  }, 2.0 * no * nk * (1.0 + no_l) * N);
+  u64* conv0 = conv + (long long)o0 * 2 * no_l * N;
   fk::TailArgs t;
   t.acc = acc;
   t.conv = conv;
   t.items = st.tails;
   t.terms = st.terms;
   t.o0 = o0;
-  t.nl = nl;
+  t.nl = no_l;
   t.le = le;
   t.logn = C.logn;
   t.out = out;
   t.out_cs = out_cs;
-  t.out_ps = (long long)nl * N;
+  t.out_ps = (long long)no_l * N;
   t.base = base;
   t.base_cs = base_cs;
   t.base_ps = (long long)nl * N;
   t.add = add;
   t.add_cs = add_cs;
-  t.pinv = C.pinv;
+  t.pinv = rs ? T.dinv_rs : C.pinv;
   t.pq = C.pq;
+  t.bscale = rs ? T.qlinv : nullptr;   // (P base_i) / (P q_l) = base_i q_l^-1
   // NTT of the converted values; its row pass applies the tail: reads the
   // converted words and acc, writes the output (plus base and added words)
   const double frac = (double)no / st.n_out;
-  const double tb = (6.0 * no + 2.0 * st.n_base * frac + st.n_adds * frac) * nl * N * 8;
-  ntt(C, false, conv0, conv0, (long long)nl * N, (long long)nl * N, no * 2 * nl, nl, identity_map(nl), s, &t, tb);
+  const double tb = (6.0 * no + 2.0 * st.n_base * frac + st.n_adds * frac) * no_l * N * 8;
+  ntt(C, false, conv0, conv0, (long long)no_l * N, (long long)no_l * N, no * 2 * no_l, no_l, identity_map(no_l), s,
+      &t, tb);
   C.cnt.launches += 1;
   C.cnt.moddown += no;
+  if (rs) C.cnt.rescale += no;
 }
 
 static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int it, u64* acc, const u64* c0,
@@ -566,7 +608,7 @@ static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int
 }
 
 void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
-                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s) {
+                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s, bool rs) {
   if (st.n_out <= 0) return;
   const int nl = level + 1, le = nl + C.K, N = C.N;
   Scope sc(C.arena);
@@ -578,7 +620,7 @@ void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out,
   for (int it = 0; it < steps; it++) {
     kip_launch(C, level, ext, st, it, acc, nullptr, 0, s);
     moddown_part(C, level, acc, conv, st, per_op ? it : 0, per_op ? 1 : st.n_out, out, out_cs, base, base_cs, add,
-                 add_cs, s);
+                 add_cs, s, rs);
   }
 }
 

@@ -157,6 +157,10 @@ struct LevelTabs {
   std::vector<unsigned char> h_eprime;
   d2* epq = nullptr;     // [le] (q, 1/q) of the prime of extended limb l
   d2* pmod = nullptr;    // [level+1] P mod q_i
+  // ModDown by P q_l (level >= 1): per source q_l, p_0 .. p_{K-1}: (D/d_k)^-1 mod d_k,
+  // then per limb i < level: (D/d_k) mod q_i; and D^-1 mod q_i
+  d2* md_rs = nullptr;
+  d2* dinv_rs = nullptr;
   std::vector<uint64_t> h_pmod;
 };
 
@@ -246,8 +250,11 @@ fk::PrimeMap identity_map(int n);
 
 // key switching pieces
 void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s);
+// rs: ModDown by P q_l instead of P, so the outputs (level-1, strides out_cs)
+// are (base + KS) / q_l: a relinearisation and its rescale in one conversion
 void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
-                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s);
+                 const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s,
+                 bool rs = false);
 void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s);
 // the rescale with caller-given workspace: last [B][2][N], lift [B][2][level][N]
 // (every word is written before it is read)

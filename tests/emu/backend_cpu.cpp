@@ -78,6 +78,7 @@ EMU_LDS(ntt_inv_cols16, NttArgs)
 EMU(modup_fbc, ModUpArgs)
 EMU_XCD(kip, KipArgs)
 EMU(moddown_fbc, ModDownArgs)
+EMU(rs_prep, RsPrepArgs)
 EMU_XCD(gmac, GmacArgs)
 EMU_XCD(gmac_pt, GmacArgs)
 EMU_XCD(gmac_fast, GmacArgs)
