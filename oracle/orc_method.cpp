@@ -238,8 +238,8 @@ i64 weight_code(double w, double scale) {
 
 void split_scale(double T, double& dw, double& dm) {
   int e = 0;
-  std::frexp(T, &e);   // T = f * 2^e, f in [0.5, 1)
-  int kw = (e - 1) >> 1;
+  std::frexp(T, &e);   // T = f * 2^e, f in [0.5, 1): dw = 2^floor((e-2)/2) <= sqrt(T / 2)
+  int kw = (e - 2) >> 1;
   dw = std::ldexp(1.0, kw);
   dm = T / dw;
 }
