@@ -1068,7 +1068,7 @@ int64_t weight_code(double w, double scale) {
 void split_scale(double T, double& dw, double& dm) {
   int e = 0;
   std::frexp(T, &e);
-  dw = std::ldexp(1.0, (e - 1) >> 1);
+  dw = std::ldexp(1.0, (e - 2) >> 1);   // 2^floor((e-2)/2): codes of |w| < 0.5 below 2^23 for T < 2^52
   dm = T / dw;
 }
 
