@@ -407,12 +407,12 @@ template <class X> FENC_HD void ntt_inv_rows16(X& x, const NttArgs& a) { ntt_inv
 // Fast base conversion of every digit of c1 (coefficient form) to the other
 // limbs of Q_l U P:  y_i = [x_i * (Qj/q_i)^-1]_{q_i} (centred),
 // out_t = sum_i y_i [Qj/q_i]_t.
-// The digit's own limbs are copied from the NTT-form input.
+// The digit's own limbs are not written: the key inner product reads them
+// from the NTT-form input (KipArgs::own).
 // Table per digit j (stride tstride d2 entries): hinv[alpha], hat[le][alpha].
 struct ModUpArgs {
   const u64* coef;        // c1 coefficient form of ct b: coef + b*coef_cs + l*N
-  const u64* ntt;         // c1 NTT form of ct b: ntt + b*ntt_cs + l*N
-  long long coef_cs, ntt_cs;
+  long long coef_cs;
   u64* ext;               // [B][beta][le][N]
   int b0;                 // first ct of the launch
   int beta, alpha, nl, le, logn;
@@ -431,20 +431,15 @@ FENC_HD void modup_fbc_a(X& x, const ModUpArgs& a) {
     const long long N = 1LL << a.logn;
     u64* out = a.ext + ((long long)b * a.beta + j) * a.le * N;
     double y[A];
-    u64 own[A];   // the digit's own limbs: copied from the NTT form
 #pragma unroll
     for (int i = 0; i < A; i++) {
       y[i] = 0;
       if (i < ds) {
         const double q = a.epq[lo + i].x;
         const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
-        own[i] = a.ntt[b * a.ntt_cs + (lo + i) * N + c];
         y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);   // v in [0, q): |v*w/q| < q
       }
     }
-#pragma unroll
-    for (int i = 0; i < A; i++)
-      if (i < ds) out[(lo + i) * N + c] = own[i];
     // the other limbs: no loads in this loop, so its stores need no wait
     for (int l = 0; l < a.le; l++) {
       if (l >= lo && l < hi) continue;
@@ -506,6 +501,13 @@ struct KipArgs {
   const d2* pmod;         // [nl] P mod q_i
   int nl;
   int width;              // outputs per group slot row: 1, 2, 4 or kKipOut (>= every group's nout)
+  // digit j's own limbs l in [j alpha, min((j+1) alpha, nl)) of ext ct e are
+  // the input's NTT-form c1 limbs: own + own_ct[e] * own_cs + l*N (own_ct
+  // null: e); ModUp does not copy them into ext
+  const u64* own;
+  long long own_cs;
+  const int* own_ct;
+  int alpha;
 };
 
 // A thread handles the coefficient pair (c, c+1), c even, with 16-byte
@@ -542,11 +544,17 @@ FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
       }
       for (int j = 0; j < a.beta; j++) {
         const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
-        const u64* ej = a.ext + ((long long)j * a.le + l) * N + m;
         // every output's words for this digit are requested before any is used
         w2 v[W];
+        if (l < a.nl && l >= j * a.alpha && l < (j + 1) * a.alpha) {   // the digit's own limb: the input's
+          const u64* oj = a.own + (long long)l * N + m;
 #pragma unroll
-        for (int o = 0; o < W; o++) v[o] = ldg2(ej + (long long)ct[o] * es);
+          for (int o = 0; o < W; o++) v[o] = ldg2(oj + (long long)(a.own_ct ? a.own_ct[ct[o]] : ct[o]) * a.own_cs);
+        } else {
+          const u64* ej = a.ext + ((long long)j * a.le + l) * N + m;
+#pragma unroll
+          for (int o = 0; o < W; o++) v[o] = ldg2(ej + (long long)ct[o] * es);
+        }
         const w2 k0 = ldg2(kj), k1 = ldg2(kj + (long long)a.nprimes * N);
         const double k00 = u2d(k0[0]), k01 = u2d(k0[1]), k10 = u2d(k1[0]), k11 = u2d(k1[1]);
 #pragma unroll

@@ -484,9 +484,7 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
     }
   fk::ModUpArgs a;
   a.coef = coef;
-  a.ntt = in + ps;
   a.coef_cs = (long long)nl * N;
-  a.ntt_cs = cs;
   a.ext = ext;
   a.beta = beta;
   a.alpha = C.alpha;
@@ -505,7 +503,7 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
     double mb = 0, mo = 0;
     for (int j = 0; j < beta; j++) {
       const int aj = std::min((j + 1) * C.alpha, nl) - j * C.alpha;
-      mb += (2.0 * aj + le) * N * 8.0;
+      mb += (double)le * N * 8.0;   // the digit's limbs read, the others written
       mo += (double)aj * (1 + (le - aj)) * N;   // y_i, then one product per (source, target) limb
     }
     timed(C, "modup_fbc", mb * nb, s,
@@ -578,15 +576,15 @@ static void moddown_part(Ctx& C, int level, u64* acc, u64* conv, const KsStage& 
   if (rs) C.cnt.rescale += no;
 }
 
-static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int it, u64* acc, const u64* c0,
-                       long long c0_cs, fb::Stream s) {
+static void kip_launch(Ctx& C, int level, const u64* ext, const ExtOwn& own, const KsStage& st, int it, u64* acc,
+                       const u64* c0, long long c0_cs, fb::Stream s) {
   const LevelTabs& T = level_tabs(C, level);
   const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha, N = C.N;
   const bool per_op = C.mode == FENC_MODE_PER_OP;
   const KipTables& KT = per_op ? st.single : st.batched;
   const int g0 = per_op ? it : 0, ng = per_op ? 1 : KT.n;
   fk::KipArgs k{ext, acc, KT.groups, KT.keys, KT.items, g0, beta, le, C.logn, C.np, T.eprime, C.pq,
-                nullptr, nullptr, 0, nullptr, nl, per_op ? 1 : KT.width};
+                nullptr, nullptr, 0, nullptr, nl, per_op ? 1 : KT.width, own.p, own.cs, own.ct, C.alpha};
   if (c0 && KT.c0items) {
     k.c0ct = KT.c0items;
     k.c0 = c0;
@@ -607,7 +605,7 @@ static void kip_launch(Ctx& C, int level, const u64* ext, const KsStage& st, int
   C.cnt.launches += 1;
 }
 
-void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
+void kip_moddown(Ctx& C, int level, const u64* ext, const ExtOwn& own, const KsStage& st, u64* out, long long out_cs,
                  const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s, bool rs) {
   if (st.n_out <= 0) return;
   const int nl = level + 1, le = nl + C.K, N = C.N;
@@ -618,17 +616,18 @@ void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out,
   // per-op: one launch sequence per output; batched: every output at once
   const int steps = per_op ? st.n_out : 1;
   for (int it = 0; it < steps; it++) {
-    kip_launch(C, level, ext, st, it, acc, nullptr, 0, s);
+    kip_launch(C, level, ext, own, st, it, acc, nullptr, 0, s);
     moddown_part(C, level, acc, conv, st, per_op ? it : 0, per_op ? 1 : st.n_out, out, out_cs, base, base_cs, add,
                  add_cs, s, rs);
   }
 }
 
-void kip_only(Ctx& C, int level, const u64* ext, const KsStage& st, u64* acc, const u64* c0, long long c0_cs,
+void kip_only(Ctx& C, int level, const u64* ext, const ExtOwn& own, const KsStage& st, u64* acc, const u64* c0,
+              long long c0_cs,
               fb::Stream s) {
   if (st.n_out <= 0) return;
   const int steps = C.mode == FENC_MODE_PER_OP ? st.n_out : 1;
-  for (int it = 0; it < steps; it++) kip_launch(C, level, ext, st, it, acc, c0, c0_cs, s);
+  for (int it = 0; it < steps; it++) kip_launch(C, level, ext, own, st, it, acc, c0, c0_cs, s);
 }
 
 void moddown_only(Ctx& C, int level, const u64* acc, const KsStage& md, u64* out, long long out_cs, fb::Stream s) {

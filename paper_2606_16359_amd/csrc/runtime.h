@@ -250,9 +250,17 @@ fk::PrimeMap identity_map(int n);
 
 // key switching pieces
 void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s);
+// Where the key inner product finds the digits' own limbs (ModUp leaves them
+// out of ext): the NTT-form c1 of ext ct e at p + ct[e] * cs (ct null: e).
+struct ExtOwn {
+  const u64* p;
+  long long cs;
+  const int* ct;
+};
+
 // rs: ModDown by P q_l instead of P, so the outputs (level-1, strides out_cs)
 // are (base + KS) / q_l: a relinearisation and its rescale in one conversion
-void kip_moddown(Ctx& C, int level, const u64* ext, const KsStage& st, u64* out, long long out_cs,
+void kip_moddown(Ctx& C, int level, const u64* ext, const ExtOwn& own, const KsStage& st, u64* out, long long out_cs,
                  const u64* base, long long base_cs, const u64* add, long long add_cs, fb::Stream s,
                  bool rs = false);
 void rescale(Ctx& C, int level, const u64* in, int B, u64* out, fb::Stream s);
@@ -264,7 +272,7 @@ void run_gmac(Ctx& C, int nl, const GmacStage& g, const u64* in_a, long long a_c
               const u64* in_b, long long b_cs, long long b_ps, u64* out, long long out_cs, long long out_ps,
               fb::Stream s);
 // KIP only (no ModDown): acc[o] over Q_l U P in NTT form, with P sigma(c0) folded in
-void kip_only(Ctx& C, int level, const u64* ext, const KsStage& st, u64* acc, const u64* c0, long long c0_cs,
+void kip_only(Ctx& C, int level, const u64* ext, const ExtOwn& own, const KsStage& st, u64* acc, const u64* c0, long long c0_cs,
               fb::Stream s);
 // ModDown only of n extended-basis ciphertexts acc[o] ([2][le][N], NTT form) into out[o]
 void moddown_only(Ctx& C, int level, const u64* acc, const KsStage& md, u64* out, long long out_cs, fb::Stream s);
