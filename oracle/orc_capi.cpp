@@ -459,12 +459,14 @@ void* orc_compress(void* c, void* bp, const OrcLayout* target, int hoist, long* 
   GUARD_END(nullptr)
 }
 
-void* orc_fc(void* c, void* bp, const double* w, int dout, const double* bias, long* counts) {
+void* orc_fc(void* c, void* bp, const double* w, int dout, const double* bias, const int* outs, int n_outs,
+             long* counts) {
   GUARD_BEGIN
   Batch* in = (Batch*)bp;
   Batch* out = new Batch;
   Counts cnt;
-  out->cts = fc(*(Context*)c, in->L, in->cts, w, dout, out->L, cnt, bias);
+  std::vector<int> only(outs, outs + (n_outs > 0 ? n_outs : 0));
+  out->cts = fc(*(Context*)c, in->L, in->cts, w, dout, out->L, cnt, bias, n_outs > 0 ? &only : nullptr);
   counts_to(cnt, counts);
   return out;
   GUARD_END(nullptr)

@@ -1115,7 +1115,7 @@ std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& i
 // once per input ciphertext and shared by every output; each output sums all
 // inputs before its giant steps, one lazy ModDown.
 static std::vector<Ct> token_fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w, int dout,
-                                Layout& Lout, Counts& cnt, const double* bias) {
+                                Layout& Lout, Counts& cnt, const double* bias, const std::vector<int>* only) {
   const int S = Lin.S, d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level, kin = Lin.ncg;
   Lout = token_layout(C, Lin.bs, dout, S, bsg);
   Lout.level = lvl - 1;
@@ -1160,15 +1160,27 @@ static std::vector<Ct> token_fc(Context& C, const Layout& Lin, const std::vector
     }
     return encode(C, z, {}, dp, q_basis(lvl));
   };
+  // outputs computed: all, or the listed ones (with only the baby steps they use)
+  std::vector<char> sel(Lin.nbg * no, only ? 0 : 1);
+  if (only)
+    for (int t : *only) sel.at(t) = 1;
   std::vector<Ct> out(Lin.nbg * no);
   for (int bg = 0; bg < Lin.nbg; bg++) {
+    std::vector<int> os;
+    for (int o = 0; o < no; o++)
+      if (sel[bg * no + o]) os.push_back(o);
+    std::vector<std::vector<char>> need(ni, std::vector<char>(n1, 0));
+    for (int a = 0; a < ni; a++)
+      for (int o : os)
+        for (int kd = 0; kd < d; kd++)
+          if (act[a][o][kd]) need[a][kd % n1] = 1;
     // baby steps of every input ciphertext, hoisted
     std::vector<std::vector<Ct>> xr(ni);
     std::vector<std::vector<const Ct*>> xb(ni, std::vector<const Ct*>(n1, nullptr));
     par_for(ni, [&](int a) {
       std::vector<i64> bsh;
       for (int b = 1; b < n1; b++)
-        if (baby[a][b]) bsh.push_back((i64)b * bsg);
+        if (baby[a][b] && need[a][b]) bsh.push_back((i64)b * bsg);
       if (!bsh.empty()) xr[a] = rotate_hoisted(C, in[bg * ni + a], bsh);
     });
     for (int a = 0; a < ni; a++) {
@@ -1176,22 +1188,26 @@ static std::vector<Ct> token_fc(Context& C, const Layout& Lin, const std::vector
       int j = 0;
       for (int b = 1; b < n1; b++)
         if (baby[a][b]) {
-          xb[a][b] = &xr[a][j++];
+          if (need[a][b]) xb[a][b] = &xr[a][j++];
           cnt.other_rot++; cnt.ks++; cnt.moddown++;
         }
-      if (j) cnt.modup++;
+      if (n1 > 1 && std::count(baby[a].begin() + 1, baby[a].end(), 1)) cnt.modup++;
     }
-    par_for(no, [&](int o) {
-      std::vector<Ct> u(n2, zero_ct(C, lvl, Lin.scale * dp));
-      for (int g = 0; g < n2; g++)
-        for (int a = 0; a < ni; a++)
-          for (int b = 0; b < n1; b++)
-            if (act[a][o][g * n1 + b]) add_inplace(C, u[g], mul_plain(C, *xb[a][b], plain(a, o, g, b), dp));
+    // giant-step partial sums u[o][g], each over every input and baby step
+    std::vector<std::vector<Ct>> u(os.size(), std::vector<Ct>(n2, zero_ct(C, lvl, Lin.scale * dp)));
+    par_for((int)os.size() * n2, [&](int t) {
+      const int o = os[t / n2], g = t % n2;
+      for (int a = 0; a < ni; a++)
+        for (int b = 0; b < n1; b++)
+          if (act[a][o][g * n1 + b]) add_inplace(C, u[t / n2][g], mul_plain(C, *xb[a][b], plain(a, o, g, b), dp));
+    });
+    par_for((int)os.size(), [&](int k) {
+      const int o = os[k];
       std::vector<const Ct*> zs;
       std::vector<i64> sh;
       for (int g = 1; g < n2; g++)
-        if (giant[o][g]) { zs.push_back(&u[g]); sh.push_back((i64)g * n1 * bsg); }
-      Ct y = zs.empty() ? u[0] : rotate_sum_lazy(C, giant[o][0] ? &u[0] : nullptr, zs, sh);
+        if (giant[o][g]) { zs.push_back(&u[k][g]); sh.push_back((i64)g * n1 * bsg); }
+      Ct y = zs.empty() ? u[k][0] : rotate_sum_lazy(C, giant[o][0] ? &u[k][0] : nullptr, zs, sh);
       y.scale = Lin.scale * dp;
       y = rescale(C, y);
       y.scale = Lout.scale;
@@ -1205,13 +1221,20 @@ static std::vector<Ct> token_fc(Context& C, const Layout& Lin, const std::vector
         for (int kd = 0; kd < d; kd++) cnt.pmult += act[a][o][kd];
     }
   }
+  if (only) {   // the listed outputs, in the listed order
+    std::vector<Ct> sub;
+    for (int t : *only) sub.push_back(out[t]);
+    if (bias) add_bias(C, Lout, sub, bias, only);
+    return sub;
+  }
   if (bias) add_bias(C, Lout, out, bias);
   return out;
 }
 
 std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
-                   int dout, Layout& Lout, Counts& cnt, const double* bias) {
-  if (Lin.kind == KIND_TOKENS) return token_fc(C, Lin, in, w, dout, Lout, cnt, bias);
+                   int dout, Layout& Lout, Counts& cnt, const double* bias, const std::vector<int>* only) {
+  if (Lin.kind == KIND_TOKENS) return token_fc(C, Lin, in, w, dout, Lout, cnt, bias, only);
+  if (only) throw std::runtime_error("fc: an output subset needs a token layout");
   if (Lin.kind != KIND_VECTOR) throw std::runtime_error("fc: needs a vector layout");
   const int d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level;
   if (dout > d) throw std::runtime_error("fc: output larger than the vector");

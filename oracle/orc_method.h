@@ -91,8 +91,10 @@ std::vector<Ct> compress_to(Context& C, const Layout& Lin, const std::vector<Ct>
                             Layout& Lout, Counts& cnt, int hoist = 0);
 std::vector<Ct> compress(Context& C, const Layout& Lin, const std::vector<Ct>& in, Layout& Lout,
                          Counts& cnt, int hoist = 0);
+// only (token layouts): compute just these output cts, returned in the listed order
 std::vector<Ct> fc(Context& C, const Layout& Lin, const std::vector<Ct>& in, const double* w,
-                   int dout, Layout& Lout, Counts& cnt, const double* bias = nullptr);
+                   int dout, Layout& Lout, Counts& cnt, const double* bias = nullptr,
+                   const std::vector<int>* only = nullptr);
 // bias[o] (channel o, or feature o of a VECTOR layout) added to every valid
 // slot; out[k] is ciphertext idx[k] of L (idx null: ciphertext k)
 void add_bias(const Context& C, const Layout& L, std::vector<Ct>& out, const double* bias,

@@ -96,7 +96,7 @@ def _declare(L):
         "orc_square": (vp, [vp, vp, C.POINTER(C.c_long)]),
         "orc_poly_act": (vp, [vp, vp, f64p, i, C.POINTER(C.c_long)]),
         "orc_compress": (vp, [vp, vp, C.POINTER(OrcLayout), i, C.POINTER(C.c_long)]),
-        "orc_fc": (vp, [vp, vp, f64p, i, vp, C.POINTER(C.c_long)]),
+        "orc_fc": (vp, [vp, vp, f64p, i, vp, vp, i, C.POINTER(C.c_long)]),
         "orc_weight_code": (C.c_int64, [d, d]),
         "orc_time_ops": (i, [vp, i, i, i, f64p]),
         "orc_split_scale": (None, [d, C.POINTER(d), C.POINTER(d)]),
@@ -420,10 +420,21 @@ class Oracle:
         t, keep = (None, None) if target is None else dict_to_layout(target)
         return self._op(lib().orc_compress, batch.h, None if t is None else C.byref(t), hoist)
 
-    def fc(self, batch, w, bias=None):
+    def fc(self, batch, w, bias=None, outputs=None):
+        """outputs (token layouts): compute only these output ciphertexts,
+        returned as an array [len(outputs)][2][level+1][N] instead of a batch."""
         w = np.ascontiguousarray(w, np.float64)
         b = None if bias is None else np.ascontiguousarray(bias, np.float64)
-        return self._op(lib().orc_fc, batch.h, w, w.shape[0], None if b is None else b.ctypes.data)
+        outs = None if outputs is None else np.ascontiguousarray(outputs, np.int32)
+        res = self._op(lib().orc_fc, batch.h, w, w.shape[0], None if b is None else b.ctypes.data,
+                       None if outs is None else outs.ctypes.data, 0 if outs is None else len(outs))
+        if outs is None:
+            return res
+        bat, cnt = res
+        lvl = bat.layout()["level"]
+        data = np.zeros((len(outs), 2, lvl + 1, self.N), np.uint64)
+        _check(lib().orc_batch_data(self.h, bat.h, data))   # writes the len(outputs) ciphertexts
+        return data, cnt
 
 
 def time_ops(orc, level, threads=1, reps=1):

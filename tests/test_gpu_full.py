@@ -284,3 +284,37 @@ def test_bert_ffn_block_on_token_fragments_decrypts_to_float64():
     got = fe.decrypt(out).reshape(W.FFN_TOKENS, W.FFN_E)
     ref = W.ffn_reference(x, w)
     assert np.max(np.abs(got - ref)) < 1e-4, np.max(np.abs(got - ref))
+
+
+def _orc_layout(lay):
+    """The oracle's layout dict of a library layout (token and vector kinds)."""
+    return {"kind": lay.kind, "bs": lay.bs, "c": lay.c, "h": lay.h, "w": lay.w, "M": lay.M, "S": lay.S, "m": lay.m,
+            "bsg": lay.bs_g, "cpc": lay.chan_per_ct, "nbg": lay.n_bg, "ncg": lay.n_cg, "rep": lay.replicate,
+            "dil": lay.dil, "level": lay.level, "d": lay.d, "nfeat": lay.n_feat, "scale": lay.scale, "pos": None}
+
+
+def test_bert_ffn_sampled_outputs_match_oracle_at_full_size():
+    """Both linear layers of the BERT-base-shaped feed-forward block at their
+    benchmark size (128 tokens, 768 -> 3072 -> 768, S = 4, N = 2^16): the
+    first and last output ciphertexts of each equal, word for word, the
+    oracle computing just those outputs from the library's own input words
+    (every input ciphertext with the baby steps the outputs use)."""
+    import torch
+    from oracle import pyoracle as P
+    from paper_2606_16359_amd import fenc as F
+    from paper_2606_16359_amd import workloads as W
+    fe = F.Fenc(*W.PARAMS["ffn"])
+    W.bench_config(fe)
+    o = P.Oracle(*W.PARAMS["ffn"])
+    x, w = W.ffn_inputs()
+    lay = fe.plan_tokens(W.FFN_TOKENS, W.FFN_E, W.FFN_S)
+    ct = fe.encrypt(fe.encode_fragment(x, lay), lay, W.SEED_ENC)
+    h = fe.fc(ct, w[0], bias=w[1])
+    a = fe.poly_act(h)
+    y = fe.fc(a, w[2], bias=w[3])
+    torch.cuda.synchronize()
+    for src, out, wi, bi in ((ct, h, w[0], w[1]), (a, y, w[2], w[3])):
+        pick = [0, out.lay.n_ct() - 1]
+        print(f"oracle fc {wi.shape}: outputs {pick} of {out.lay.n_ct()}", flush=True)
+        ref, _ = o.fc(o.batch(_orc_layout(src.lay), fe.export(src)), wi, bias=bi, outputs=pick)
+        assert np.array_equal(fe.export(out)[pick], ref)

@@ -516,3 +516,17 @@ def test_token_fc_decrypts_and_counts_rotations(n, E, E2, S):
             babies += len(b - {0})
     assert cnt["other_rot"] == L["nbg"] * (babies + sum(len(g - {0}) for g in giants.values()))
     assert babies <= S * kin * (n1 - 1)
+
+
+def test_token_fc_output_subset_equals_the_full_layer():
+    """The oracle's token linear layer restricted to listed output
+    ciphertexts (only the baby steps they use) gives those ciphertexts of the
+    full layer word for word, bias included, in the listed order."""
+    o = small_oracle(nq=3, logN=10)
+    n, E, E2, S = 8, 48, 160, 2   # 2 fragments of 2 chunks each: 4 output cts
+    x, w, b = rand_x((n, E), 46), rand_w((E2, E), 47), rand_w((E2,), 48)
+    ob = o.encrypt_tensor(o.token_layout(n, E, S), x.reshape(n, E, 1, 1), 6)
+    full, _ = o.fc(ob, w, bias=b)
+    pick = [2, 0, full.layout()["S"] * full.layout()["ncg"] - 1]
+    sub, _ = o.fc(ob, w, bias=b, outputs=pick)
+    assert np.array_equal(sub, full.data()[pick])
