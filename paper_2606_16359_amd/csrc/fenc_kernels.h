@@ -501,9 +501,10 @@ struct KipArgs {
   const d2* pmod;         // [nl] P mod q_i
   int nl;
   int width;              // outputs per group slot row: 1, 2, 4 or kKipOut (>= every group's nout)
-  // digit j's own limbs l in [j alpha, min((j+1) alpha, nl)) of ext ct e are
-  // the input's NTT-form c1 limbs: own + own_ct[e] * own_cs + l*N (own_ct
-  // null: e); ModUp does not copy them into ext
+  // digit j's own limbs l in [j alpha, min((j+1) alpha, nl)) of an item are
+  // the input's NTT-form c1 limbs: own + own_ct[item] * own_cs + l*N, with
+  // own_ct parallel to items (null: the item's ext ct); ModUp does not copy
+  // them into ext
   const u64* own;
   long long own_cs;
   const int* own_ct;
@@ -536,11 +537,12 @@ FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
       const long long m = src & ~1LL;
       const bool sw = (src & 1) != 0;
       // item lists are padded to kKipOut entries; -1 marks no item
-      int ct[W];
+      int ct[W], oc[W];
 #pragma unroll
       for (int o = 0; o < W; o++) {
         ct[o] = a.items[K.item0 + o];
         ct[o] = ct[o] >= 0 ? ct[o] : 0;
+        oc[o] = a.own_ct ? a.own_ct[K.item0 + o] : ct[o];   // loaded beside the item, not after it
       }
       for (int j = 0; j < a.beta; j++) {
         const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
@@ -549,7 +551,7 @@ FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
         if (l < a.nl && l >= j * a.alpha && l < (j + 1) * a.alpha) {   // the digit's own limb: the input's
           const u64* oj = a.own + (long long)l * N + m;
 #pragma unroll
-          for (int o = 0; o < W; o++) v[o] = ldg2(oj + (long long)(a.own_ct ? a.own_ct[ct[o]] : ct[o]) * a.own_cs);
+          for (int o = 0; o < W; o++) v[o] = ldg2(oj + (long long)oc[o] * a.own_cs);
         } else {
           const u64* ej = a.ext + ((long long)j * a.le + l) * N + m;
 #pragma unroll

@@ -340,7 +340,6 @@ static void run_bias(Ctx& C, const BiasStage& st, int level, const u64* in, u64*
 // copies[c] = Rot(in[src_c], shift_c); ModUp of each source once
 struct RotStage {
   std::vector<int> src;   // ModUp'ed input cts (sorted)
-  const int* d_src = nullptr;   // the same on the device: input ct of each ext ct
   KsStage ks;
   int n = 0;
 };
@@ -355,13 +354,12 @@ static RotStage make_rot_stage(Ctx& C, const std::vector<std::pair<int, long lon
     kv.second = (int)R.src.size();
     R.src.push_back(kv.first);
   }
-  if (!R.src.empty()) R.d_src = upload(C, R.src, owner);
   std::vector<std::vector<KsItem>> items;
   std::vector<fk::TailItem> tails;
   std::vector<fk::AddTerm> terms;
   for (int i = 0; i < R.n; i++) {
     const unsigned g = (unsigned)galois(C, copies[i].second);
-    items.push_back({KsItem{pos[copies[i].first], g, get_key(C, g), pq ? copies[i].first : -1}});
+    items.push_back({KsItem{pos[copies[i].first], g, get_key(C, g), pq ? copies[i].first : -1, copies[i].first}});
     tails.push_back(fk::TailItem{i, -1, (int)terms.size(), 1});
     terms.push_back(fk::AddTerm{copies[i].first, g});
   }
@@ -384,7 +382,7 @@ static void run_rot_stage(Ctx& C, int level, const RotStage& R, const u64* in, u
     modup(C, level, in + R.src[i] * ce, ce, (long long)nl * C.N, (int)(j - i + 1), ext + (long long)i * ee, s);
     i = j + 1;
   }
-  const ExtOwn own{in + (long long)nl * C.N, ce, R.d_src};
+  const ExtOwn own{in + (long long)nl * C.N, ce};
   if (pq) kip_only(C, level, ext, own, R.ks, out, in, ce, s);
   else kip_moddown(C, level, ext, own, R.ks, out, ce, nullptr, 0, in, ce, s);
 }
@@ -426,7 +424,7 @@ static void run_sum_stage(Ctx& C, int level, const SumStage& S, const u64* z, u6
   Scope sc(C.arena);
   u64* ext = (u64*)C.arena.get((size_t)S.nz * beta * le * C.N * 8, s);
   modup(C, level, z, ce, (long long)nl * C.N, S.nz, ext, s);
-  kip_moddown(C, level, ext, ExtOwn{z + (long long)nl * C.N, ce, nullptr}, S.ks, out, ce, base, ce, z, ce, s);
+  kip_moddown(C, level, ext, ExtOwn{z + (long long)nl * C.N, ce}, S.ks, out, ce, base, ce, z, ce, s);
 }
 
 // ---------------------------------------------------------------- conv2d
@@ -1028,7 +1026,7 @@ static void relin_rescale(Ctx& C, int lvl, int n, const KsStage& ks, const u64* 
   Scope sc(C.arena);
   u64* ext = (u64*)C.arena.get((size_t)n * beta * le * C.N * 8, s);
   modup(C, lvl, d2b, (long long)nl * C.N, 0, n, ext, s);
-  kip_moddown(C, lvl, ext, ExtOwn{d2b, (long long)nl * C.N, nullptr}, ks, out, ct_elems(C, lvl - 1), t,
+  kip_moddown(C, lvl, ext, ExtOwn{d2b, (long long)nl * C.N}, ks, out, ct_elems(C, lvl - 1), t,
               ct_elems(C, lvl), nullptr, 0, s, true);
   C.cnt.relin += n;
   C.cnt.keyswitch += n;

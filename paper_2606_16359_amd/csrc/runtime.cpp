@@ -584,7 +584,7 @@ static void kip_launch(Ctx& C, int level, const u64* ext, const ExtOwn& own, con
   const KipTables& KT = per_op ? st.single : st.batched;
   const int g0 = per_op ? it : 0, ng = per_op ? 1 : KT.n;
   fk::KipArgs k{ext, acc, KT.groups, KT.keys, KT.items, g0, beta, le, C.logn, C.np, T.eprime, C.pq,
-                nullptr, nullptr, 0, nullptr, nl, per_op ? 1 : KT.width, own.p, own.cs, own.ct, C.alpha};
+                nullptr, nullptr, 0, nullptr, nl, per_op ? 1 : KT.width, own.p, own.cs, KT.ownitems, C.alpha};
   if (c0 && KT.c0items) {
     k.c0ct = KT.c0items;
     k.c0 = c0;
@@ -764,8 +764,8 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
   // batched: consecutive outputs with the same ordered key list share a group
   std::vector<fk::KipGroup> groups;
   std::vector<fk::KipKey> keys;
-  std::vector<int> it, c0it;
-  bool any_c0 = false;
+  std::vector<int> it, c0it, ownit;
+  bool any_c0 = false, any_own = false;
   std::vector<double> bytes, wbytes;
   const int n = (int)items.size();
   int o = 0;
@@ -785,6 +785,9 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
         it.push_back(oo < e ? items[oo][k].ct : -1);
         c0it.push_back(oo < e ? items[oo][k].c0ct : -1);
         any_c0 = any_c0 || (oo < e && items[oo][k].c0ct >= 0);
+        // padded slots: input ct 0, which exists
+        ownit.push_back(oo < e ? (items[oo][k].own >= 0 ? items[oo][k].own : items[oo][k].ct) : 0);
+        any_own = any_own || (oo < e && items[oo][k].own >= 0);
       }
     }
     // words per (limb, coefficient): per digit, nkey keys (2 words) and one ext word per item
@@ -801,6 +804,7 @@ static KipTables make_kip_tables(Ctx& C, const std::vector<std::vector<KsItem>>&
   T.keys = upload(C, keys, owner);
   T.items = upload(C, it, owner);
   if (any_c0) T.c0items = upload(C, c0it, owner);
+  if (any_own) T.ownitems = upload(C, ownit, owner);
   T.rd = bytes;
   T.wr = wbytes;
   return T;

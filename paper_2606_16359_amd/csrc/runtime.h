@@ -84,6 +84,7 @@ struct KsItem {
   unsigned g;
   const uint64_t* key;
   int c0ct = -1;   // input ct whose sigma_g(c0), times P, is folded into the accumulator (-1: none)
+  int own = -1;    // input ct holding the digits' own limbs of ext ct `ct` (-1: ct itself)
 };
 
 // Device tables of a KIP + ModDown stage.  Outputs are grouped twice: in
@@ -95,6 +96,7 @@ struct KipTables {
   fk::KipKey* keys = nullptr;
   int* items = nullptr;
   int* c0items = nullptr;          // parallel to items: folded c0 source, -1 none (null: no folding)
+  int* ownitems = nullptr;         // parallel to items: input ct of the own limbs (null: the item's ct)
   int width = 1;                   // largest group's output count, as a power of two
   std::vector<double> rd, wr;      // host: words per (limb, coefficient) read per digit / written
 };
@@ -251,11 +253,11 @@ fk::PrimeMap identity_map(int n);
 // key switching pieces
 void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s);
 // Where the key inner product finds the digits' own limbs (ModUp leaves them
-// out of ext): the NTT-form c1 of ext ct e at p + ct[e] * cs (ct null: e).
+// out of ext): the NTT-form c1 of input ct t at p + t * cs, t the item's own
+// input ct (KsItem::own, else the ext ct index).
 struct ExtOwn {
   const u64* p;
   long long cs;
-  const int* ct;
 };
 
 // rs: ModDown by P q_l instead of P, so the outputs (level-1, strides out_cs)
