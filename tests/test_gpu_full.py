@@ -296,9 +296,11 @@ def _orc_layout(lay):
 def test_bert_ffn_sampled_outputs_match_oracle_at_full_size():
     """Both linear layers of the BERT-base-shaped feed-forward block at their
     benchmark size (128 tokens, 768 -> 3072 -> 768, S = 4, N = 2^16): the
-    first and last output ciphertexts of each equal, word for word, the
-    oracle computing just those outputs from the library's own input words
-    (every input ciphertext with the baby steps the outputs use)."""
+    last output ciphertext of the first and the first of the second (other
+    fragments and chunks) equal, word for word, the oracle computing just
+    that output from the library's own input words (every input ciphertext
+    with the baby steps the output uses)."""
+    import time
     import torch
     from oracle import pyoracle as P
     from paper_2606_16359_amd import fenc as F
@@ -313,8 +315,8 @@ def test_bert_ffn_sampled_outputs_match_oracle_at_full_size():
     a = fe.poly_act(h)
     y = fe.fc(a, w[2], bias=w[3])
     torch.cuda.synchronize()
-    for src, out, wi, bi in ((ct, h, w[0], w[1]), (a, y, w[2], w[3])):
-        pick = [0, out.lay.n_ct() - 1]
-        print(f"oracle fc {wi.shape}: outputs {pick} of {out.lay.n_ct()}", flush=True)
+    for src, out, wi, bi, pick in ((ct, h, w[0], w[1], [h.lay.n_ct() - 1]), (a, y, w[2], w[3], [0])):
+        t0 = time.time()
         ref, _ = o.fc(o.batch(_orc_layout(src.lay), fe.export(src)), wi, bias=bi, outputs=pick)
+        print(f"oracle fc {wi.shape}: output {pick} of {out.lay.n_ct()} in {time.time() - t0:.1f}s", flush=True)
         assert np.array_equal(fe.export(out)[pick], ref)
