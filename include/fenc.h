@@ -355,7 +355,14 @@ int fenc_compress(fenc_ctx* ctx, const fenc_ctbatch* in, const fenc_layout* targ
  * dout host doubles, on a VECTOR layout: diagonal method with baby-step
  * giant-step (hoisted baby steps, giant steps summed with one ModDown), one
  * rescale, the bias added at the output scale; output features at positions
- * 0..dout-1. */
+ * 0..dout-1.
+ * On a TOKENS layout (Discussions, extensibility to Transformers) it is the
+ * linear layer of every token: the output is the TOKENS layout of dout
+ * features with the input's S and bs_g; each (input ct, output ct) pair of a
+ * token group is a d x d block taken by the same diagonal method, the baby
+ * steps hoisted once per input ct and shared by every output ct, each output
+ * ct summing all its inputs before one giant-step sum.  Only diagonals with a
+ * nonzero weight are multiplied. */
 int fenc_fc(fenc_ctx* ctx, const fenc_ctbatch* in, const double* w, const double* bias, uint32_t dout,
             fenc_ctbatch* out, void* stream);
 

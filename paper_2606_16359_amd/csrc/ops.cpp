@@ -1233,7 +1233,7 @@ static FcPlan* build_fc_tokens(Ctx& C, const Layout& Lin, const double* W, int d
                                bool shape_only, Layout& Lout) {
   if (Lin.level < 1) fail(FENC_ELEVEL, "no level left for the fc layer");
   const int S = Lin.S, d = Lin.d, bsg = Lin.bsg, din = Lin.nfeat, lvl = Lin.level, kin = Lin.ncg;
-  if (dout < S) fail(FENC_EINVAL, "fewer output features than fragments");
+  if (dout < 1) fail(FENC_EINVAL, "fc without outputs");
   Lout = make_tokens(C.ns, lvl - 1, C.Delta, Lin.bs, dout, S, bsg);
   if (shape_only) return nullptr;
   const int kout = Lout.ncg, ni = S * kin, no = S * kout;
