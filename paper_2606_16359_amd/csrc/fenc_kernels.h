@@ -1353,6 +1353,8 @@ FENC_HD void gmac_diag(X& x, const GmacArgs& a) {
 // out = k (a0 b0, a0 b1 + a1 b0) [+ k1 x + k0], d2buf = k a1 b1.  The optional
 // linear term of the activation (x with its own strides, possibly more limbs:
 // limb drop; k0 on poly 0 only) is added here, so it needs no pass of its own.
+// With kb1 set, b is not read but formed from x: b = kb1 x + kb0 (kb0 on poly
+// 0), the cubic's second factor.
 struct SquareArgs {
   const u64* in;
   const u64* in_b;
@@ -1362,10 +1364,12 @@ struct SquareArgs {
   long long ct_stride;   // elements per ct (inputs and out)
   const d2* k;           // [nl] (k mod q_i, /q)
   const d2* pq;
-  const u64* lx;         // null: no linear term
+  const u64* lx;         // x (null: no linear term and no formed b)
   long long lx_cs, lx_ps;
-  const d2* k1;          // [nl]
+  const d2* k1;          // [nl] null: no linear term
   const d2* k0;          // [nl]
+  const d2* kb1;         // [nl] null: b read from in_b
+  const d2* kb0;         // [nl]
 };
 
 template <class X>
@@ -1378,12 +1382,20 @@ FENC_HD void tensor_square(X& x, const SquareArgs& a) {
     const u64* pa = a.in + b * a.ct_stride + i * N + c;
     const u64* pb = a.in_b + b * a.ct_stride + i * N + c;
     const double a0 = u2d(pa[0]), a1 = u2d(pa[a.nl * N]);
-    const double b0 = u2d(pb[0]), b1 = u2d(pb[a.nl * N]);
+    double b0, b1;
+    if (a.kb1) {   // b = kb1 x + kb0, each word in [0, q) like a stored one
+      const u64* px = a.lx + b * a.lx_cs + i * N + c;
+      b0 = norm(red(mulmod_c(u2d(px[0]), a.kb1[i].x, a.kb1[i].y, q) + a.kb0[i].x, q, qi), q);
+      b1 = norm(red(mulmod_c(u2d(px[a.lx_ps]), a.kb1[i].x, a.kb1[i].y, q), q, qi), q);
+    } else {
+      b0 = u2d(pb[0]);
+      b1 = u2d(pb[a.nl * N]);
+    }
     u64* out = a.out + b * a.ct_stride + i * N + c;
     const d2 k = a.k[i];
     const double m01 = mulmod(a0, b1, q, qi) + mulmod(a1, b0, q, qi);   // words in [0, q)
     double o0 = mulmod_c(mulmod(a0, b0, q, qi), k.x, k.y, q), o1 = mulmod_c(m01, k.x, k.y, q);
-    if (a.lx) {   // each term within q: the sums stay within 3q, reduced once
+    if (a.lx && a.k1) {   // each term within q: the sums stay within 3q, reduced once
       const u64* px = a.lx + b * a.lx_cs + i * N + c;
       const double x0 = px == pa ? a0 : u2d(px[0]), x1 = px == pa ? a1 : u2d(px[a.lx_ps]);
       o0 = red(o0 + mulmod_c(x0, a.k1[i].x, a.k1[i].y, q) + a.k0[i].x, q, qi);

@@ -983,19 +983,23 @@ static std::vector<d2> code_residues(const Ctx& C, double v, int nl) {
 }
 
 // t = k (a x b) over (d0, d1), d2b = its d2; with x: plus k1 x + k0, x read
-// with its own strides (the same words as a when x == a)
+// with its own strides (the same words as a when x == a); with kb1 (and x),
+// b is not read but formed as kb1 x + kb0
 static void run_tensor(Ctx& C, int lvl, int n, const u64* a, const u64* b, const d2* k, u64* t, u64* d2b,
                        fb::Stream s, const u64* x = nullptr, long long x_cs = 0, long long x_ps = 0,
-                       const d2* k1 = nullptr, const d2* k0 = nullptr) {
+                       const d2* k1 = nullptr, const d2* k0 = nullptr, const d2* kb1 = nullptr,
+                       const d2* kb0 = nullptr) {
   const int nl = lvl + 1;
   const long long ce = ct_elems(C, lvl);
   const bool per_op = C.mode == FENC_MODE_PER_OP;
-  const double xr = x && x != a ? 2.0 : 0.0;   // words of x read beside a and b
+  if (kb1) b = a;   // b is formed from x; the pointer stays a valid one
+  // words per limb: a (2), b unless formed or equal to a (2), x beside a (2), 3 written
+  const double words = 5.0 + (b != a ? 2.0 : 0.0) + (x && x != a ? 2.0 : 0.0);
   for (int b0 = 0; b0 < n; b0 += per_op ? 1 : n) {
     const int nb = per_op ? 1 : n;
     fk::SquareArgs sa{a + b0 * ce, b + b0 * ce, t + b0 * ce, d2b + (long long)b0 * nl * C.N, nl, C.logn, ce, k, C.pq,
-                      x ? x + b0 * x_cs : nullptr, x_cs, x_ps, k1, k0};
-    timed(C, "tensor_square", ((a == b ? 5.0 : 7.0) + xr) * nb * nl * C.N * 8, s, [&] {
+                      x ? x + b0 * x_cs : nullptr, x_cs, x_ps, k1, k0, kb1, kb0};
+    timed(C, "tensor_square", words * nb * nl * C.N * 8, s, [&] {
       fb::tensor_square({(unsigned)std::max(1, C.N / 256), (unsigned)nl, (unsigned)nb}, std::min(256, C.N), s, sa);
     }, (a == b ? 3.0 : 4.0) * nb * nl * C.N);
     C.cnt.launches++;
@@ -1046,18 +1050,17 @@ static void run_poly(Ctx& C, const PolyPlan& P, const u64* in, u64* out, fb::Str
     u64* d2b = (u64*)C.arena.get((size_t)n * (l + 1) * C.N * 8, s);
     const long long xps = (long long)(l + 1) * C.N;
     if (P.d == 2) {   // k2 x*x + k1 x + k0 in one pass, then relinearised and rescaled together
-      run_tensor(C, l, n, in, in, P.kf, t, d2b, s, P.lin ? in : nullptr, ce, xps, P.k1, P.k0);
+      run_tensor(C, l, n, in, in, P.kf, t, d2b, s, P.lin ? in : nullptr, ce, xps, P.lin ? P.k1 : nullptr, P.k0);
       relin_rescale(C, l, n, P.ks_a, t, d2b, out, s);
     } else {
       run_tensor(C, l, n, in, in, P.kf, t, d2b, s);
       const long long c1e = ct_elems(C, l - 1);
       u64* x2 = (u64*)C.arena.get((size_t)n * c1e * 8, s);
-      u64* u = (u64*)C.arena.get((size_t)n * c1e * 8, s);
       relin_rescale(C, l, n, P.ks_a, t, d2b, x2, s);
-      // x' = x without its last limb: the same words read with level-l strides
-      run_lin(C, l, n, in, ce, (long long)(l + 1) * C.N, nullptr, u, P.k3, P.k2c, s);
-      // X2 u + k1 x' + k0 in one pass, x' read like u
-      run_tensor(C, l - 1, n, x2, u, P.one, t, d2b, s, P.lin ? in : nullptr, ce, xps, P.k1, P.k0);
+      // X2 u + k1 x' + k0 in one pass, with u = k3 x' + k2' formed from x' in
+      // registers; x' = x without its last limb, read with level-l strides
+      run_tensor(C, l - 1, n, x2, nullptr, P.one, t, d2b, s, in, ce, xps, P.lin ? P.k1 : nullptr, P.k0, P.k3,
+                 P.k2c);
       relin_rescale(C, l - 1, n, P.ks_b, t, d2b, out, s);
     }
   }
