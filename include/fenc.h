@@ -324,10 +324,13 @@ int fenc_avgpool2(fenc_ctx* ctx, const fenc_ctbatch* in, fenc_ctbatch* out, void
  * the degree.  All terms of one rescale share one scale reached by integer
  * codes, and the leading coefficient is carried by that scale, so the output
  * scale is within a small factor of Delta (exact value in out->lay.scale):
- *   degree <= 2: one tensor product (x*x times an integer), relinearisation,
- *                c1 x + c0 added, one rescale (one level);
- *   degree 3:    x^2 as above and rescaled, times u = c3 x + c2, relinearised,
- *                c1 x + c0 added, rescaled (two levels).
+ *   degree <= 2: one tensor product (x*x times an integer) with c1 x + c0
+ *                added, relinearised and rescaled together (one level);
+ *   degree 3:    x^2 as above, times u = c3 x + c2 with c1 x + c0 added,
+ *                relinearised and rescaled together (two levels).
+ * "Together": (d0, d1) P + KIP(d2) divided by P q_l in one ModDown whose fast
+ * base conversion takes the special primes and q_l at once (Background:
+ * hybrid key switching and Rescale, taken as one step). 
  * out->data may equal in->data: the output then overwrites the input (every
  * batch group's input is read before its output is written, and outputs are
  * no larger than inputs), which saves one activation-sized buffer.
