@@ -110,3 +110,28 @@ def test_token_ffn_chain_bit_exact(backend, orc):
     h = x.reshape(n, E) @ w1.T + b1
     ref = (h * h) @ w2.T + b2
     assert np.max(np.abs(f.decrypt(y).reshape(n, E) - ref)) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_token_ffn_cubic_per_op_equals_batched_and_oracle(backend, orc):
+    """The feed-forward chain with a cubic activation between (two levels:
+    the second tensor product forms u = k3 x' + k2' itself): the per-op form
+    (every operation of every ciphertext launched separately) and the batched
+    form give the oracle's words at every step."""
+    from paper_2606_16359_amd import fenc as F
+    f = make(backend, 10, 8, 50, 3, 50, 3, 40, 17)
+    o = P.Oracle(10, 8, 50, 3, 50, 3, 40, 17)
+    n, E, S = 8, 16, 2
+    r = rng(65)
+    x = r.uniform(-1, 1, (n, E, 1, 1))
+    w1, w2 = r.normal(0, 0.2, (2 * E, E)), r.normal(0, 0.2, (E, 2 * E))
+    cubic = (0.1, 0.5, 0.25, -0.02)
+    lay, L = f.plan_tokens(n, E, S), o.token_layout(n, E, S)
+    yo = o.encrypt_tensor(L, x, 8)
+    yo, _ = o.fc(yo, w1)
+    yo, _ = o.poly_act(yo, cubic)
+    yo, _ = o.fc(yo, w2)
+    for mode in (F.FENC_MODE_BATCHED, F.FENC_MODE_PER_OP):
+        f.set_mode(mode)
+        y = f.fc(f.poly_act(f.fc(f.encrypt(f.encode_fragment(x, lay), lay, 8), w1), cubic), w2)
+        cmp(y, yo, f)
