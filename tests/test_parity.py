@@ -502,6 +502,25 @@ def test_poly_act_bit_exact(backend, orc, coeffs):
 
 
 @pytest.mark.parametrize("backend", BACKENDS)
+@pytest.mark.parametrize("params", [(10, 8, 50, 8, 50, 1, 40, 17), (10, 9, 50, 7, 50, 2, 40, 17),
+                                    (10, 4, 40, 1, 40, 4, 30, 17)])
+def test_activation_modulus_shapes_bit_exact(backend, params):
+    """The square and the cubic (relinearisation and rescale by one ModDown by
+    P q_l) where the conversion has K + 1 = 9 sources (past the unrolled
+    forms), 8, and 2 (one special prime, one-limb digits)."""
+    o, f = P.Oracle(*params), make(backend, *params)
+    x = 2.0 * rng(24).uniform(0, 1, (2, 2, 8, 8)) - 1.0
+    Lo = o.fragment_layout(2, 2, 8, 8, 2)
+    lay = f.plan_layout(2, 2, 8, 8, 3, 2, 2)
+    ob, fb = o.encrypt_tensor(Lo, x, 5), f.encrypt(f.encode_fragment(x, lay), lay, 5)
+    for coeffs in ((0.0, 0.0, 1.0), (0.1, 0.5, 0.25, -0.02)):
+        yo, _ = o.poly_act(ob, list(coeffs))
+        yf = f.poly_act(fb, coeffs)
+        cmp(yf, yo, f)
+        assert np.max(np.abs(f.decrypt(yf) - np.polynomial.polynomial.polyval(x, coeffs))) < 1e-4
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
 def test_cifar_shaped_stack_small_bit_exact(backend):
     """The CIFAR-shaped stack scaled down: 3x3 convs with padding, a stride-2 conv
     (fragments discarded) and a cubic activation after each conv; N = 2^11."""
