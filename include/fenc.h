@@ -151,6 +151,13 @@ int fenc_set_mode(fenc_ctx* ctx, int mode);
  * so one rescale follows either way.  The choice changes the ciphertext bits,
  * not the decrypted values beyond rounding. */
 int fenc_set_plaintext_budget(fenc_ctx* ctx, int64_t bytes);
+/* Key switching (hybrid, Background): where the key inner product finds each
+ * digit's own limbs of the extended digits.  A stage whose extended digits
+ * (all its ciphertexts) take at most `bytes` (default 1 GiB) has them
+ * copied by ModUp and read with the rest, which is then still in cache; a
+ * larger stage reads them from the input ciphertexts, saving the copy's
+ * traffic.  0: never copied.  Residues do not change. */
+int fenc_set_own_copy_limit(fenc_ctx* ctx, int64_t bytes);
 /* Workspace limit (default 32 GiB, 0: none): an operation whose workspace
  * would exceed it runs over tiles of whole batch groups, one after the other,
  * each with the plan of the smaller batch.  Batch groups never share a

@@ -95,6 +95,7 @@ FENC_KERNEL_LDS(ntt_inv_rows16, NttArgs)
 FENC_KERNEL_LDS(ntt_inv_cols16, NttArgs)
 FENC_KERNEL(modup_fbc, ModUpArgs)
 FENC_KERNEL_XCD(kip, KipArgs)
+FENC_KERNEL_XCD(kip_own, KipArgs)
 FENC_KERNEL(moddown_fbc, ModDownArgs)
 FENC_KERNEL(rs_prep, RsPrepArgs)
 FENC_KERNEL_XCD(gmac, GmacArgs)

@@ -52,6 +52,7 @@ void ntt_inv_rows16(Grid g, int threads, size_t smem, Stream s, const fk::NttArg
 void ntt_inv_cols16(Grid g, int threads, size_t smem, Stream s, const fk::NttArgs& a);
 void modup_fbc(Grid g, int threads, Stream s, const fk::ModUpArgs& a);
 void kip(Grid g, int threads, Stream s, const fk::KipArgs& a);
+void kip_own(Grid g, int threads, Stream s, const fk::KipArgs& a);   // own limbs from the input
 void moddown_fbc(Grid g, int threads, Stream s, const fk::ModDownArgs& a);
 void rs_prep(Grid g, int threads, Stream s, const fk::RsPrepArgs& a);
 void gmac(Grid g, int threads, Stream s, const fk::GmacArgs& a);

@@ -407,12 +407,15 @@ template <class X> FENC_HD void ntt_inv_rows16(X& x, const NttArgs& a) { ntt_inv
 // Fast base conversion of every digit of c1 (coefficient form) to the other
 // limbs of Q_l U P:  y_i = [x_i * (Qj/q_i)^-1]_{q_i} (centred),
 // out_t = sum_i y_i [Qj/q_i]_t.
-// The digit's own limbs are not written: the key inner product reads them
-// from the NTT-form input (KipArgs::own).
+// The digit's own limbs are copied from the NTT-form input when `ntt` is set;
+// otherwise they are not written and the key inner product reads them from
+// the input (KipArgs::own).
 // Table per digit j (stride tstride d2 entries): hinv[alpha], hat[le][alpha].
 struct ModUpArgs {
   const u64* coef;        // c1 coefficient form of ct b: coef + b*coef_cs + l*N
   long long coef_cs;
+  const u64* ntt;         // c1 NTT form of ct b: ntt + b*ntt_cs + l*N (null: own limbs not copied)
+  long long ntt_cs;
   u64* ext;               // [B][beta][le][N]
   int b0;                 // first ct of the launch
   int beta, alpha, nl, le, logn;
@@ -439,6 +442,15 @@ FENC_HD void modup_fbc_a(X& x, const ModUpArgs& a) {
         const double v = u2d(a.coef[b * a.coef_cs + (lo + i) * N + c]);
         y[i] = centre(mulmod_c(v, tab[i].x, tab[i].y, q), q);   // v in [0, q): |v*w/q| < q
       }
+    }
+    if (a.ntt) {   // the digit's own limbs, copied from the NTT form
+      u64 own[A];
+#pragma unroll
+      for (int i = 0; i < A; i++)
+        if (i < ds) own[i] = a.ntt[b * a.ntt_cs + (lo + i) * N + c];
+#pragma unroll
+      for (int i = 0; i < A; i++)
+        if (i < ds) out[(lo + i) * N + c] = own[i];
     }
     // the other limbs: no loads in this loop, so its stores need no wait
     for (int l = 0; l < a.le; l++) {
@@ -501,10 +513,10 @@ struct KipArgs {
   const d2* pmod;         // [nl] P mod q_i
   int nl;
   int width;              // outputs per group slot row: 1, 2, 4 or kKipOut (>= every group's nout)
-  // digit j's own limbs l in [j alpha, min((j+1) alpha, nl)) of an item are
-  // the input's NTT-form c1 limbs: own + own_ct[item] * own_cs + l*N, with
-  // own_ct parallel to items (null: the item's ext ct); ModUp does not copy
-  // them into ext
+  // with own set, digit j's own limbs l in [j alpha, min((j+1) alpha, nl))
+  // of an item are the input's NTT-form c1 limbs: own + own_ct[item] *
+  // own_cs + l*N, with own_ct parallel to items (null: the item's ext ct),
+  // and ModUp did not copy them into ext; with own null they are in ext
   const u64* own;
   long long own_cs;
   const int* own_ct;
@@ -518,7 +530,9 @@ struct KipArgs {
 // padded to a power of two; padded slots read ct 0's words, which exist, and
 // are computed but never stored, so every load is used and the loads in
 // flight are counted exactly.
-template <int W, class X>
+// OWN: the digits' own limbs come from the input (a.own), else all from ext;
+// two kernels, so the plain one keeps its own register allocation.
+template <int W, bool OWN, class X>
 FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
   x.phase([&](int t) __attribute__((always_inline)) {
     const long long N = 1LL << a.logn;
@@ -542,13 +556,13 @@ FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
       for (int o = 0; o < W; o++) {
         ct[o] = a.items[K.item0 + o];
         ct[o] = ct[o] >= 0 ? ct[o] : 0;
-        oc[o] = a.own_ct ? a.own_ct[K.item0 + o] : ct[o];   // loaded beside the item, not after it
+        if constexpr (OWN) oc[o] = a.own_ct ? a.own_ct[K.item0 + o] : ct[o];   // loaded beside the item
       }
       for (int j = 0; j < a.beta; j++) {
         const u64* kj = K.key + ((long long)j * 2 * a.nprimes + p) * N + c;
         // every output's words for this digit are requested before any is used
         w2 v[W];
-        if (l < a.nl && l >= j * a.alpha && l < (j + 1) * a.alpha) {   // the digit's own limb: the input's
+        if (OWN && l < a.nl && l >= j * a.alpha && l < (j + 1) * a.alpha) {   // own limb: the input's
           const u64* oj = a.own + (long long)l * N + m;
 #pragma unroll
           for (int o = 0; o < W; o++) v[o] = ldg2(oj + (long long)oc[o] * a.own_cs);
@@ -601,15 +615,17 @@ FENC_HD FENC_AI void kip_w(X& x, const KipArgs& a) {
   });
 }
 
-template <class X>
-FENC_HD void kip(X& x, const KipArgs& a) {
+template <bool OWN, class X>
+FENC_HD void kip_any(X& x, const KipArgs& a) {
   switch (a.width) {
-    case 1: kip_w<1>(x, a); break;
-    case 2: kip_w<2>(x, a); break;
-    case 4: kip_w<4>(x, a); break;
-    default: kip_w<kKipOut>(x, a); break;
+    case 1: kip_w<1, OWN>(x, a); break;
+    case 2: kip_w<2, OWN>(x, a); break;
+    case 4: kip_w<4, OWN>(x, a); break;
+    default: kip_w<kKipOut, OWN>(x, a); break;
   }
 }
+template <class X> FENC_HD void kip(X& x, const KipArgs& a) { kip_any<false>(x, a); }
+template <class X> FENC_HD void kip_own(X& x, const KipArgs& a) { kip_any<true>(x, a); }
 
 // ------------------------------------------------------------------ ModDown
 // conv_i = sum_k [acc_{p_k} (P/p_k)^-1]_{p_k} [P/p_k]_{q_i}  (coefficient form,

@@ -376,13 +376,14 @@ static void run_rot_stage(Ctx& C, int level, const RotStage& R, const u64* in, u
   const long long ce = ct_elems(C, level), ee = (long long)beta * le * C.N;
   Scope sc(C.arena);
   u64* ext = (u64*)C.arena.get((size_t)R.src.size() * ee * 8, s);
+  const bool copy = (long long)R.src.size() * ee * 8 <= C.own_copy;   // small stage: ext stays in cache
   for (size_t i = 0; i < R.src.size();) {
     size_t j = i;
     while (j + 1 < R.src.size() && R.src[j + 1] == R.src[j] + 1) j++;
-    modup(C, level, in + R.src[i] * ce, ce, (long long)nl * C.N, (int)(j - i + 1), ext + (long long)i * ee, s);
+    modup(C, level, in + R.src[i] * ce, ce, (long long)nl * C.N, (int)(j - i + 1), ext + (long long)i * ee, s, copy);
     i = j + 1;
   }
-  const ExtOwn own{in + (long long)nl * C.N, ce};
+  const ExtOwn own{copy ? nullptr : in + (long long)nl * C.N, ce};
   if (pq) kip_only(C, level, ext, own, R.ks, out, in, ce, s);
   else kip_moddown(C, level, ext, own, R.ks, out, ce, nullptr, 0, in, ce, s);
 }
@@ -423,8 +424,10 @@ static void run_sum_stage(Ctx& C, int level, const SumStage& S, const u64* z, u6
   const long long ce = ct_elems(C, level);
   Scope sc(C.arena);
   u64* ext = (u64*)C.arena.get((size_t)S.nz * beta * le * C.N * 8, s);
-  modup(C, level, z, ce, (long long)nl * C.N, S.nz, ext, s);
-  kip_moddown(C, level, ext, ExtOwn{z + (long long)nl * C.N, ce}, S.ks, out, ce, base, ce, z, ce, s);
+  const bool copy = (long long)S.nz * beta * le * C.N * 8 <= C.own_copy;
+  modup(C, level, z, ce, (long long)nl * C.N, S.nz, ext, s, copy);
+  kip_moddown(C, level, ext, ExtOwn{copy ? nullptr : z + (long long)nl * C.N, ce}, S.ks, out, ce, base, ce, z, ce,
+              s);
 }
 
 // ---------------------------------------------------------------- conv2d
@@ -1029,8 +1032,9 @@ static void relin_rescale(Ctx& C, int lvl, int n, const KsStage& ks, const u64* 
   const int nl = lvl + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha;
   Scope sc(C.arena);
   u64* ext = (u64*)C.arena.get((size_t)n * beta * le * C.N * 8, s);
-  modup(C, lvl, d2b, (long long)nl * C.N, 0, n, ext, s);
-  kip_moddown(C, lvl, ext, ExtOwn{d2b, (long long)nl * C.N}, ks, out, ct_elems(C, lvl - 1), t,
+  const bool copy = (long long)n * beta * le * C.N * 8 <= C.own_copy;
+  modup(C, lvl, d2b, (long long)nl * C.N, 0, n, ext, s, copy);
+  kip_moddown(C, lvl, ext, ExtOwn{copy ? nullptr : d2b, (long long)nl * C.N}, ks, out, ct_elems(C, lvl - 1), t,
               ct_elems(C, lvl), nullptr, 0, s, true);
   C.cnt.relin += n;
   C.cnt.keyswitch += n;
@@ -1854,6 +1858,13 @@ int fenc_set_plaintext_budget(fenc_ctx* ctx, int64_t bytes) {
   API_BEGIN
   if (!ctx || bytes < 0) fail(FENC_EINVAL, "bad budget");
   ctx->pt_budget = bytes;
+  API_END
+}
+
+int fenc_set_own_copy_limit(fenc_ctx* ctx, int64_t bytes) {
+  API_BEGIN
+  if (!ctx || bytes < 0) fail(FENC_EINVAL, "bad own-limb copy limit");
+  ctx->own_copy = bytes;
   API_END
 }
 

@@ -468,7 +468,8 @@ const uint64_t* get_key(Ctx& C, uint64_t g) {
 }
 
 // ---------------------------------------------------------------- key switching
-void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s) {
+void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s,
+           bool copy_own) {
   if (B <= 0) return;
   const LevelTabs& T = level_tabs(C, level);
   const int nl = level + 1, le = nl + C.K, beta = (nl + C.alpha - 1) / C.alpha, N = C.N;
@@ -485,6 +486,8 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
   fk::ModUpArgs a;
   a.coef = coef;
   a.coef_cs = (long long)nl * N;
+  a.ntt = copy_own ? in + ps : nullptr;
+  a.ntt_cs = cs;
   a.ext = ext;
   a.beta = beta;
   a.alpha = C.alpha;
@@ -503,7 +506,7 @@ void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, 
     double mb = 0, mo = 0;
     for (int j = 0; j < beta; j++) {
       const int aj = std::min((j + 1) * C.alpha, nl) - j * C.alpha;
-      mb += (double)le * N * 8.0;   // the digit's limbs read, the others written
+      mb += (copy_own ? 2.0 * aj + le : (double)le) * N * 8.0;   // the digit's limbs read (and copied), the rest written
       mo += (double)aj * (1 + (le - aj)) * N;   // y_i, then one product per (source, target) limb
     }
     timed(C, "modup_fbc", mb * nb, s,
@@ -600,7 +603,8 @@ static void kip_launch(Ctx& C, int level, const u64* ext, const ExtOwn& own, con
   timed(C, "kip", kb, s,
         [&] {   // a thread per coefficient pair
           const int kt = std::min(256, N / 2);
-          fb::kip({(unsigned)(N / 2 / kt), (unsigned)le, (unsigned)ng}, kt, s, k);
+          if (own.p) fb::kip_own({(unsigned)(N / 2 / kt), (unsigned)le, (unsigned)ng}, kt, s, k);
+          else fb::kip({(unsigned)(N / 2 / kt), (unsigned)le, (unsigned)ng}, kt, s, k);
         }, ko * le * N);
   C.cnt.launches += 1;
 }

@@ -178,6 +178,7 @@ struct fenc_ctx {
   int mode = FENC_MODE_BATCHED;
   bool strict = false;
   int64_t pt_budget = 1LL << 30;     // bytes of materialised conv plaintexts (one batch group)
+  int64_t own_copy = 1LL << 30;      // extended digits of a stage up to this size get their own limbs copied
   int64_t ws_limit = 32LL << 30;     // workspace per operation; larger batches run in tiles of batch groups
   fenc_counters cnt{};
 
@@ -251,14 +252,18 @@ void ntt(Ctx& C, bool inverse, const u64* src, u64* dst, long long src_gs, long 
 fk::PrimeMap identity_map(int n);
 
 // key switching pieces
-void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s);
-// Where the key inner product finds the digits' own limbs (ModUp leaves them
-// out of ext): the NTT-form c1 of input ct t at p + t * cs, t the item's own
-// input ct (KsItem::own, else the ext ct index).
+// copy_own: also copy every digit's own limbs into ext (else the KIP reads them from `in`)
+void modup(Ctx& C, int level, const u64* in, long long cs, long long ps, int B, u64* ext, fb::Stream s,
+           bool copy_own = false);
+// Where the key inner product finds the digits' own limbs: with p set, ModUp
+// left them out of ext and they are the NTT-form c1 of input ct t at
+// p + t * cs, t the item's own input ct (KsItem::own, else the ext ct index);
+// with p null they are in ext.
 struct ExtOwn {
   const u64* p;
   long long cs;
 };
+
 
 // rs: ModDown by P q_l instead of P, so the outputs (level-1, strides out_cs)
 // are (base + KS) / q_l: a relinearisation and its rescale in one conversion

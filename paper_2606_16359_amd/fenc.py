@@ -88,6 +88,7 @@ def load(path=None):
         "fenc_ctx_primes": (C.c_int, [vp, vp]),
         "fenc_set_mode": (C.c_int, [vp, C.c_int]),
         "fenc_set_plaintext_budget": (C.c_int, [vp, C.c_int64]),
+        "fenc_set_own_copy_limit": (C.c_int, [vp, C.c_int64]),
         "fenc_set_workspace_limit": (C.c_int, [vp, C.c_int64]),
         "fenc_stats": (C.c_int, [vp, C.POINTER(Counters)]),
         "fenc_profile_kernel": (C.c_int, [vp, C.c_char_p]),
@@ -256,6 +257,9 @@ class Fenc:
 
     def set_plaintext_budget(self, nbytes):
         self._check(self.lib.fenc_set_plaintext_budget(self.h, nbytes))
+
+    def set_own_copy_limit(self, nbytes):
+        self._check(self.lib.fenc_set_own_copy_limit(self.h, nbytes))
 
     def set_workspace_limit(self, nbytes):
         self._check(self.lib.fenc_set_workspace_limit(self.h, nbytes))

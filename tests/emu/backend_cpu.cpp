@@ -77,6 +77,7 @@ EMU_LDS(ntt_inv_rows16, NttArgs)
 EMU_LDS(ntt_inv_cols16, NttArgs)
 EMU(modup_fbc, ModUpArgs)
 EMU_XCD(kip, KipArgs)
+EMU_XCD(kip_own, KipArgs)
 EMU(moddown_fbc, ModDownArgs)
 EMU(rs_prep, RsPrepArgs)
 EMU_XCD(gmac, GmacArgs)

@@ -302,14 +302,20 @@ def test_keyswitch_with_digits_and_special_primes_above_eight(backend):
 
 
 @pytest.mark.parametrize("backend", BACKENDS)
-@pytest.mark.parametrize("mode,budget,hoist", [(F.FENC_MODE_BATCHED, 1 << 30, 1), (F.FENC_MODE_PER_OP, 1 << 30, 1),
-                                               (F.FENC_MODE_BATCHED, 0, 1), (F.FENC_MODE_BATCHED, 1 << 30, 0),
-                                               (F.FENC_MODE_PER_OP, 0, 0), (F.FENC_MODE_BATCHED, 1 << 30, 2)])
-def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
+@pytest.mark.parametrize("mode,budget,hoist,own", [(F.FENC_MODE_BATCHED, 1 << 30, 1, None),
+                                                   (F.FENC_MODE_PER_OP, 1 << 30, 1, 0),
+                                                   (F.FENC_MODE_BATCHED, 0, 1, 0), (F.FENC_MODE_BATCHED, 1 << 30, 0, None),
+                                                   (F.FENC_MODE_PER_OP, 0, 0, None),
+                                                   (F.FENC_MODE_BATCHED, 1 << 30, 2, 0)])
+def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, own, orc):
     """Two conv/x^2/pool blocks, compression and two FC layers at N = 2^10, in
     both hoisting schedules and in the per-layer choice (mode 2: the oracle
-    runs each layer in the schedule the library reports it chose)."""
+    runs each layer in the schedule the library reports it chose); with the
+    digits' own limbs copied into the extended digits (the default at this
+    size) and read from the input ciphertexts (own-copy limit 0)."""
     o, f = orc, make(backend, *SMALL)
+    if own is not None:
+        f.set_own_copy_limit(own)
     f.set_mode(mode)
     f.set_plaintext_budget(budget)
     f.set_hoisting(hoist)
@@ -361,6 +367,7 @@ def test_mini_lenet_layers_bit_exact(backend, mode, budget, hoist, orc):
 @pytest.mark.parametrize("hoist", [1, 0, 2])
 def test_conv_variants_bit_exact(backend, budget, case, hoist, orc):
     o, f = orc, make(backend, *SMALL)
+    f.set_own_copy_limit(0 if hoist != 1 else 1 << 40)   # own limbs read from the input / always copied
     f.set_plaintext_budget(budget)
     f.set_hoisting(hoist)
     r = rng(3)
@@ -492,6 +499,7 @@ def test_poly_act_bit_exact(backend, orc, coeffs):
     yo, cnt = o.poly_act(ob, list(coeffs))
     for mode in (F.FENC_MODE_BATCHED, F.FENC_MODE_PER_OP):
         f.set_mode(mode)
+        f.set_own_copy_limit(0 if mode == F.FENC_MODE_PER_OP else 1 << 40)
         yf = f.poly_act(fb, coeffs)
         Ly = yo.layout()
         assert (yf.lay.level, yf.lay.scale) == (Ly["level"], Ly["scale"])
