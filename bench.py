@@ -47,7 +47,7 @@ DTYPE = "u64 RNS residues (50-bit primes), binary64 FMA modular arithmetic"
 TRAFFIC = {
     ("mobilenet", "ntt_fwd_cols"): 1.7878e9,
     ("cifar", "gmac_pt_fast"): 9.4836e9,
-    ("lenet", "kip"): 0.8762e9,
+    ("lenet", "kip"): 0.8760e9,
     ("ffn", "gmac_diag"): 6.9570e9,
 }
 
