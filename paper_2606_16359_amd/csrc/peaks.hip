@@ -221,24 +221,29 @@ const char* kNames[] = {
 };
 constexpr int kCount = sizeof(kNames) / sizeof(kNames[0]);
 
+// Best of `reps` timed launches in seconds, or -1 when a HIP call fails.
 template <class L>
 double best_seconds(L launch, int reps) {
   hipEvent_t a, b;
-  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1;
+  if (hipEventCreate(&a) != hipSuccess) return -1;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return -1;
+  }
+  bool ok = true;
   launch();   // warm-up
   float best = 1e30f;
-  for (int r = 0; r < reps; ++r) {
-    hipEventRecord(a, 0);
-    launch();
-    hipEventRecord(b, 0);
-    if (hipEventSynchronize(b) != hipSuccess) return -1;
+  for (int r = 0; r < reps && ok; ++r) {
     float ms = 0;
-    hipEventElapsedTime(&ms, a, b);
-    if (ms < best) best = ms;
+    ok = hipEventRecord(a, 0) == hipSuccess;
+    launch();
+    ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(b, 0) == hipSuccess &&
+         hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess;
+    if (ok && ms < best) best = ms;
   }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  return best * 1e-3;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ok ? best * 1e-3 : -1;
 }
 
 // iteration count giving about target seconds per launch
@@ -308,13 +313,16 @@ extern "C" int fenc_peaks_run(int test, double arg, double* seconds, double* wor
       }
     };
     const int iters = calibrate([&](int it) { return best_seconds([&] { launch(it); }, 2); }, arg);
-    if (iters < 0) { hipFree(out); return -1; }
+    if (iters < 0) {
+      (void)hipFree(out);
+      return -1;
+    }
     *seconds = best_seconds([&] { launch(iters); }, 5);
     *work = (double)kLanes * kChains * iters * (test == 0 ? 2.0 : 1.0);
     if (test >= 4) {
       std::vector<u64> h((size_t)kLanes * kChains);
       if (hipMemcpy(h.data(), out, h.size() * sizeof(u64), hipMemcpyDeviceToHost) != hipSuccess) {
-        hipFree(out);
+        (void)hipFree(out);
         return -1;
       }
       int ok = 1;
@@ -323,26 +331,37 @@ extern "C" int fenc_peaks_run(int test, double arg, double* seconds, double* wor
           if (h[(size_t)t * kChains + c] != powmod(chain_start(t, c), ma.w, iters, ma.q)) ok = 0;
       *exact = ok;
     }
-    hipFree(out);
+    (void)hipFree(out);
     return *seconds > 0 ? 0 : -1;
   }
   const size_t bytes = (size_t)arg & ~(size_t)4095;
   const size_t n = bytes / sizeof(uint4);
   void *s = nullptr, *d = nullptr;
+  auto release = [&] {
+    (void)hipFree(s);
+    if (d) (void)hipFree(d);
+  };
   if (hipMalloc(&s, bytes) != hipSuccess) return -1;
-  if (test != 10 && test != 11 && hipMalloc(&d, bytes) != hipSuccess) { hipFree(s); return -1; }
-  if (test == 10 && hipMalloc(&d, (size_t)kLanes * 4 * sizeof(unsigned)) != hipSuccess) { hipFree(s); return -1; }
-  hipMemset(s, 1, bytes);
+  if ((test != 10 && test != 11 && hipMalloc(&d, bytes) != hipSuccess) ||
+      (test == 10 && hipMalloc(&d, (size_t)kLanes * 4 * sizeof(unsigned)) != hipSuccess) ||
+      hipMemset(s, 1, bytes) != hipSuccess) {
+    release();
+    return -1;
+  }
   const dim3 mgrid(kBlocks * 2);
+  bool copy_failed = false;
   auto launch = [&] {
     switch (test) {
       case 9: hipLaunchKernelGGL(k_copy, mgrid, block, 0, 0, (const uint4*)s, (uint4*)d, n); break;
       case 10: hipLaunchKernelGGL(k_read, mgrid, block, 0, 0, (const uint4*)s, (unsigned*)d, n); break;
       case 11: hipLaunchKernelGGL(k_write, mgrid, block, 0, 0, (uint4*)s, n); break;
-      default: hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, 0); break;
+      default:
+        if (hipMemcpyAsync(d, s, bytes, hipMemcpyDeviceToDevice, 0) != hipSuccess) copy_failed = true;
+        break;
     }
   };
   *seconds = best_seconds(launch, 5);
+  if (copy_failed) *seconds = -1;
   *work = (double)bytes * (test == 9 || test == 12 ? 2.0 : 1.0);
   if (test == 9 || test == 12) {   // the copy arrived: compare a few words
     unsigned char a[4096], b[4096];
@@ -352,7 +371,6 @@ extern "C" int fenc_peaks_run(int test, double arg, double* seconds, double* wor
     else
       *exact = memcmp(a, b, 4096) == 0;
   }
-  hipFree(s);
-  if (d) hipFree(d);
+  release();
   return *seconds > 0 ? 0 : -1;
 }
